@@ -1,0 +1,325 @@
+"""Seeded synthetic inputs shared by the tests and the benchmark.
+
+This module only *generates inputs*: the model specifications (a neutral,
+JSON-like dict that both the GPU binding and the oracle translate into their
+own structures), the event columns, parameter points and toy sizes.  It
+computes no likelihood, normalisation or gradient.
+
+Randomness is Philox4x64-10 (counter-based, see ``datagen.cpp``) so every
+value is reproducible independently of threading.  Seeds: master
+2003012875; data seed = master + 1000 * config number; parameter-point seed
+= data seed + 1; toy k of the batched workload uses stream (4 << 32) + k.
+
+The five workloads stand in for the paper's benchmark models (its Fig. 1
+covers 100k-300k events of "various likelihood models" whose definitions
+are not given): a wide Gaussian, a Gaussian-plus-exponential mixture, a
+2-D Crystal Ball / ARGUS mixture times a Chebyshev series, batched toy
+datasets of the Gaussian, and the mixture at 1e8 events.
+"""
+from __future__ import annotations
+
+import copy
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdatagen.so")
+
+MASTER_SEED = 2003012875
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7}
+
+
+def build() -> str:
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall",
+           os.path.join(_HERE, "datagen.cpp"), "-o", LIB_PATH + ".tmp"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class DgNode(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("obs", ctypes.c_int32), ("n_param", ctypes.c_int32),
+                ("p", ctypes.c_double * 8), ("n_child", ctypes.c_int32), ("child", ctypes.c_int32 * 8)]
+
+
+class DgModel(ctypes.Structure):
+    _fields_ = [("n_obs", ctypes.c_int32), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
+                ("n_node", ctypes.c_int32), ("node", DgNode * 16), ("root", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.dg_philox4x64.argtypes = [P(ctypes.c_uint64), P(ctypes.c_uint64), P(ctypes.c_uint64)]
+        L.dg_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P(ctypes.c_double)]
+        L.dg_generate.argtypes = [P(DgModel), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
+                                  P(P(ctypes.c_double)), ctypes.c_int32]
+        L.dg_generate.restype = ctypes.c_int64
+        L.dg_generate_sets.argtypes = [P(DgModel), ctypes.c_int32, P(ctypes.c_int64), ctypes.c_uint64,
+                                       ctypes.c_uint64, P(P(ctypes.c_double)), ctypes.c_int32]
+        L.dg_generate_sets.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def default_threads() -> int:
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:  # pragma: no cover
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+def philox4x64(ctr, key):
+    c = (ctypes.c_uint64 * 4)(*[int(v) for v in ctr])
+    k = (ctypes.c_uint64 * 2)(*[int(v) for v in key])
+    o = (ctypes.c_uint64 * 4)()
+    lib().dg_philox4x64(c, k, o)
+    return [int(v) for v in o]
+
+
+def uniforms(seed: int, stream: int, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    lib().dg_uniforms(seed, stream, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Model specifications (neutral dicts)
+# --------------------------------------------------------------------------
+
+def param(name, value, lo, hi, free=True, jitter=None):
+    """A parameter; `jitter` is the half-width used for seeded parameter
+    points (default 10 % of |value|)."""
+    d = {"name": name, "value": float(value), "lo": float(lo), "hi": float(hi), "free": bool(free)}
+    if jitter is not None:
+        d["jitter"] = float(jitter)
+    return d
+
+
+def gauss_spec(mu=0.3, sigma=1.5, lo=-10.0, hi=10.0, norm="analytic"):
+    """Config 1: one Gaussian on x in [-10, 10]."""
+    return {"obs": [{"name": "x", "lo": lo, "hi": hi}],
+            "params": [param("mu", mu, lo, hi), param("sigma", sigma, 0.05, 10.0)],
+            "nodes": [{"kind": "gauss", "obs": 0, "params": [0, 1], "norm": norm}],
+            "root": 0}
+
+
+def mixture_spec(f=0.2, mu=5.0, sigma=0.4, c=-0.7, lo=0.0, hi=10.0, norm="analytic"):
+    """Config 2 / 5: f * Gauss(mu, sigma) + (1 - f) * Exp(c) on x in [0, 10];
+    parameters (f, mu, sigma, c)."""
+    return {"obs": [{"name": "x", "lo": lo, "hi": hi}],
+            "params": [param("f", f, 0.0, 1.0), param("mu", mu, lo, hi),
+                       param("sigma", sigma, 0.01, 5.0), param("c", c, -5.0, 5.0)],
+            "nodes": [{"kind": "gauss", "obs": 0, "params": [1, 2], "norm": norm},
+                      {"kind": "exp", "obs": 0, "params": [3], "norm": norm},
+                      {"kind": "sum", "params": [0], "children": [0, 1]}],
+            "root": 2}
+
+
+def cheb_coefficients(seed: int, order: int = 4, lo: float = -1.0, hi: float = 1.0,
+                      min_density: float = 0.05, max_tries: int = 1000) -> np.ndarray:
+    """Chebyshev coefficients a_1..a_K ~ U[-0.3, 0.3], redrawn from the next
+    stream until 1 + sum a_k T_k stays >= min_density on a 10001-point grid."""
+    grid = np.linspace(-1.0, 1.0, 10001)
+    for t in range(max_tries):
+        a = -0.3 + 0.6 * uniforms(seed, 1000 + t, order)
+        val = np.polynomial.chebyshev.chebval(grid, np.concatenate([[1.0], a]))
+        if val.min() >= min_density:
+            return a
+    raise RuntimeError("no admissible Chebyshev coefficients")
+
+
+def cb_argus_cheb_spec(cheb=(0.0, 0.0, 0.0, 0.0), f=0.1, m0=5.28, sigma=0.003, alpha=1.5, n=3.0,
+                       am0=5.29, ac=-20.0, norm="gl256"):
+    """Config 3: [f CB(m; m0, sigma, alpha, n) + (1-f) ARGUS(m; am0, ac)] x
+    Cheb_4(y) on m in [5.20, 5.30], y in [-1, 1].  Parameters
+    (f, m0, sigma, alpha, n, am0, ac, a1..a4); n and am0 fixed -> 9 free."""
+    ps = [param("f", f, 0.0, 1.0, jitter=0.1 * f), param("cb_m0", m0, 5.20, 5.30, jitter=0.1 * sigma),
+          param("cb_sigma", sigma, 1e-4, 0.05, jitter=0.1 * sigma),
+          param("cb_alpha", alpha, 0.1, 10.0, jitter=0.1 * alpha), param("cb_n", n, 1.05, 50.0, free=False),
+          param("ar_m0", am0, 5.2001, 6.0, free=False), param("ar_c", ac, -200.0, 0.0, jitter=0.1 * abs(ac))]
+    for k, a in enumerate(cheb):
+        ps.append(param(f"a{k + 1}", a, -1.0, 1.0))
+    return {"obs": [{"name": "m", "lo": 5.20, "hi": 5.30}, {"name": "y", "lo": -1.0, "hi": 1.0}],
+            "params": ps,
+            "nodes": [{"kind": "cb", "obs": 0, "params": [1, 2, 3, 4], "norm": norm},
+                      {"kind": "argus", "obs": 0, "params": [5, 6], "norm": norm},
+                      {"kind": "sum", "params": [0], "children": [0, 1]},
+                      {"kind": "cheb", "obs": 1, "params": [7, 8, 9, 10], "norm": norm},
+                      {"kind": "prod", "children": [2, 3]}],
+            "root": 4}
+
+
+def with_values(spec: dict, theta) -> dict:
+    s = copy.deepcopy(spec)
+    for p, v in zip(s["params"], theta):
+        p["value"] = float(v)
+    return s
+
+
+def theta_of(spec: dict) -> np.ndarray:
+    return np.array([p["value"] for p in spec["params"]], dtype=np.float64)
+
+
+def _dg_model(spec: dict, theta=None) -> DgModel:
+    th = theta_of(spec) if theta is None else np.asarray(theta, dtype=np.float64)
+    m = DgModel()
+    m.n_obs = len(spec["obs"])
+    for k, o in enumerate(spec["obs"]):
+        m.lo[k], m.hi[k] = o["lo"], o["hi"]
+    m.n_node = len(spec["nodes"])
+    for k, nd in enumerate(spec["nodes"]):
+        d = m.node[k]
+        d.kind = KIND[nd["kind"]]
+        d.obs = int(nd.get("obs", -1))
+        ps = nd.get("params", [])
+        d.n_param = len(ps)
+        for j, pi in enumerate(ps):
+            d.p[j] = th[pi]
+        cs = nd.get("children", [])
+        d.n_child = len(cs)
+        for j, c in enumerate(cs):
+            d.child[j] = c
+    m.root = spec["root"]
+    return m
+
+
+def generate(spec: dict, n: int, seed: int, stream: int = 0, theta=None, threads: int | None = None):
+    """n events drawn from the model at `theta` (default: the spec values);
+    returns a list of float64 columns (one per observable)."""
+    m = _dg_model(spec, theta)
+    cols = [np.empty(n, dtype=np.float64) for _ in spec["obs"]]
+    arr = (ctypes.POINTER(ctypes.c_double) * 4)()
+    for k, c in enumerate(cols):
+        arr[k] = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    bad = lib().dg_generate(ctypes.byref(m), seed, stream, n, arr, threads or default_threads())
+    if bad:
+        raise RuntimeError(f"{bad} events could not be sampled")
+    return cols
+
+
+def generate_sets(spec: dict, thetas: np.ndarray, offsets: np.ndarray, seed: int, stream_base: int,
+                  threads: int | None = None, out=None):
+    """Concatenated datasets: set s is drawn at thetas[s] into
+    [offsets[s], offsets[s+1])."""
+    n_sets = len(offsets) - 1
+    models = (DgModel * n_sets)()
+    for s in range(n_sets):
+        models[s] = _dg_model(spec, thetas[s])
+    total = int(offsets[-1])
+    cols = out if out is not None else [np.empty(total, dtype=np.float64) for _ in spec["obs"]]
+    arr = (ctypes.POINTER(ctypes.c_double) * 4)()
+    for k, c in enumerate(cols):
+        arr[k] = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    bad = lib().dg_generate_sets(models, n_sets, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 seed, stream_base, arr, threads or default_threads())
+    if bad:
+        raise RuntimeError(f"{bad} events could not be sampled")
+    return cols
+
+
+def jittered_points(theta_true, n_points: int, seed: int, stream: int = 7, rel: float = 0.1,
+                    free=None, widths=None) -> np.ndarray:
+    """theta_true + w * U(-1, 1) per component with w = rel * |theta_true|
+    unless explicit half-widths are given (fixed components kept)."""
+    th = np.asarray(theta_true, dtype=np.float64)
+    w = rel * np.abs(th) if widths is None else np.asarray(widths, dtype=np.float64)
+    u = uniforms(seed, stream, n_points * len(th)).reshape(n_points, len(th))
+    pts = th[None, :] + w[None, :] * (2.0 * u - 1.0)
+    if free is not None:
+        fixed = ~np.asarray(free, dtype=bool)
+        pts[:, fixed] = th[fixed]
+    return pts
+
+
+def toy_sizes(n_sets: int, seed: int, lo: int = 1000, hi: int = 200000, stream: int = 3) -> np.ndarray:
+    u = uniforms(seed, stream, n_sets)
+    return lo + np.minimum((u * (hi - lo + 1)).astype(np.int64), hi - lo)
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+def data_seed(config: int) -> int:
+    return MASTER_SEED + 1000 * config
+
+
+def free_mask(spec: dict) -> np.ndarray:
+    return np.array([p.get("free", True) for p in spec["params"]], dtype=bool)
+
+
+def jitter_widths(spec: dict, rel: float = 0.1) -> np.ndarray:
+    return np.array([p.get("jitter", rel * abs(p["value"])) for p in spec["params"]], dtype=np.float64)
+
+
+def parameter_points(spec: dict, n_points: int, seed: int) -> np.ndarray:
+    """Seeded points around the spec values; points at which a Chebyshev
+    series would not stay positive (min < 0.02 on a grid) are redrawn from
+    the next stream."""
+    pts = np.empty((n_points, len(spec["params"])))
+    grid = np.linspace(-1.0, 1.0, 2001)
+    cheb_nodes = [nd for nd in spec["nodes"] if nd["kind"] == "cheb"]
+    filled, stream = 0, 7
+    while filled < n_points:
+        cand = jittered_points(theta_of(spec), n_points, seed, stream=stream, free=free_mask(spec),
+                               widths=jitter_widths(spec))
+        for row in cand:
+            ok = all(np.polynomial.chebyshev.chebval(grid, np.concatenate([[1.0], row[nd["params"]]])).min() >= 0.02
+                     for nd in cheb_nodes)
+            if ok and filled < n_points:
+                pts[filled] = row
+                filled += 1
+        stream += 1
+    return pts
+
+
+def workload(config: int, n: int | None = None, threads: int | None = None) -> dict:
+    """Spec, columns and parameter points of workload 1, 2, 3 or 5
+    (optionally with a smaller event count n)."""
+    seed = data_seed(config)
+    if config == 1:
+        spec = gauss_spec()
+        N = 100_000 if n is None else n
+        pts = 64
+    elif config in (2, 5):
+        spec = mixture_spec()
+        N = (10_000_000 if config == 2 else 100_000_000) if n is None else n
+        pts = 8 if config == 2 else 32
+    elif config == 3:
+        spec = cb_argus_cheb_spec(cheb=cheb_coefficients(seed))
+        N = 50_000_000 if n is None else n
+        pts = 8
+    else:
+        raise ValueError("use toys_workload() for the batched configuration")
+    cols = generate(spec, N, seed, threads=threads)
+    theta = theta_of(spec)
+    points = parameter_points(spec, pts, seed + 1)
+    return {"config": config, "spec": spec, "cols": cols, "n": N, "theta": theta, "points": points,
+            "seed": seed}
+
+
+def toys_workload(n_sets: int = 4096, size_lo: int = 1000, size_hi: int = 200000,
+                  threads: int | None = None) -> dict:
+    """Config 4: n_sets Gaussian datasets on [-10, 10] with sizes uniform in
+    [size_lo, size_hi] and truths (0.3, 1.5) jittered by +-10 %."""
+    seed = data_seed(4)
+    spec = gauss_spec()
+    sizes = toy_sizes(n_sets, seed, size_lo, size_hi)
+    offsets = np.zeros(n_sets + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    truths = jittered_points(theta_of(spec), n_sets, seed + 1)
+    cols = generate_sets(spec, truths, offsets, seed, 4 << 32, threads=threads)
+    return {"config": 4, "spec": spec, "cols": cols, "offsets": offsets, "sizes": sizes,
+            "truths": truths, "theta_start": theta_of(spec), "seed": seed}

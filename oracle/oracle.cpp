@@ -1,0 +1,884 @@
+/*
+ * oracle.cpp -- scalar FP64 reference evaluator (test infrastructure only;
+ * the product path never links it).  See oracle.h for the contract.
+ *
+ * Everything here is written to be checked by eye against the paper and
+ * the textbook definitions of the densities:
+ *   - the likelihood is evaluated event by event, the classic single-value
+ *     way of Sec. 5.1: values are written into the leaves, the top node's
+ *     probability is obtained recursively from its daughters and their
+ *     normalisation, and parameter-only quantities (normalisation
+ *     integrals) are computed once per parameter point;
+ *   - densities are composed in the linear domain, p = sum c_j p_j for a
+ *     sum and p = prod p_d for a product, exactly as defined;
+ *   - derivatives are propagated forward through the same recursion;
+ *   - every sum over events is Neumaier-compensated FP64.
+ * Valid while every p(x_i) is a normal double (no underflow to 0).
+ */
+#include "oracle.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr double kInf = std::numeric_limits<double>::infinity();
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+/* Neumaier's improvement of Kahan summation. */
+struct Neumaier {
+  double s = 0.0, c = 0.0;
+  void add(double v) {
+    double t = s + v;
+    if (std::fabs(s) >= std::fabs(v))
+      c += (s - t) + v;
+    else
+      c += (v - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+/* ------------------------------------------------------------------ */
+/* Gauss-Legendre rule: roots of P_n by Newton's method on the three-   */
+/* term recurrence (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}, carried in */
+/* long double; weights w = 2 / ((1 - x^2) P_n'(x)^2).                  */
+/* ------------------------------------------------------------------ */
+struct Rule {
+  std::vector<double> x, w;
+};
+
+Rule make_rule(int n) {
+  Rule r;
+  r.x.assign(n, 0.0);
+  r.w.assign(n, 0.0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    long double z = cosl(pi * (i + 0.75L) / (n + 0.5L));
+    long double dp = 0.0L;
+    for (int it = 0; it < 200; ++it) {
+      long double p0 = 1.0L, p1 = z;
+      for (int k = 1; k < n; ++k) {
+        long double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0L);
+      long double step = p1 / dp;
+      z -= step;
+      if (fabsl(step) < 1e-21L) break;
+    }
+    {
+      long double p0 = 1.0L, p1 = z;
+      for (int k = 1; k < n; ++k) {
+        long double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0L);
+    }
+    long double wt = 2.0L / ((1.0L - z * z) * dp * dp);
+    r.x[n - 1 - i] = (double)z;
+    r.x[i] = (double)(-z);
+    r.w[n - 1 - i] = (double)wt;
+    r.w[i] = (double)wt;
+  }
+  if (n % 2 == 1) r.x[n / 2] = 0.0;
+  return r;
+}
+
+const Rule& rule256() {
+  static const Rule r = make_rule(256);
+  return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* Unnormalised leaf shapes g(x; theta) and dg/dtheta_local.            */
+/* ------------------------------------------------------------------ */
+inline double P(const double* th, const orc_node& nd, int k) { return th[nd.param[k]]; }
+
+/* Gaussian: g = exp(-t^2/2), t = (x - mu)/sigma. */
+double g_gauss(const orc_node& nd, const double* th, double x, double* dg) {
+  double mu = P(th, nd, 0), s = P(th, nd, 1);
+  double t = (x - mu) / s;
+  double g = std::exp(-0.5 * t * t);
+  if (dg) {
+    dg[0] = g * t / s;
+    dg[1] = g * t * t / s;
+  }
+  return g;
+}
+
+/* Exponential: g = exp(c x). */
+double g_exp(const orc_node& nd, const double* th, double x, double* dg) {
+  double c = P(th, nd, 0);
+  double g = std::exp(c * x);
+  if (dg) dg[0] = g * x;
+  return g;
+}
+
+/* Chebyshev series of the first kind on [lo, hi] with the T_0 coefficient
+ * fixed at 1: g = 1 + sum_{k=1..K} a_k T_k(x'), x' = (2x - lo - hi)/(hi - lo). */
+double g_cheb(const orc_node& nd, const double* th, double lo, double hi, double x,
+              double* dg) {
+  double y = (2.0 * x - lo - hi) / (hi - lo);
+  double tkm1 = 1.0, tk = y, g = 1.0;
+  for (int k = 1; k <= nd.n_param; ++k) {
+    g += P(th, nd, k - 1) * tk;
+    if (dg) dg[k - 1] = tk;
+    double tkp1 = 2.0 * y * tk - tkm1;
+    tkm1 = tk;
+    tk = tkp1;
+  }
+  return g;
+}
+
+/* Crystal Ball with a power-law tail on the low side:
+ *   t > -alpha : exp(-t^2/2)
+ *   t <= -alpha: A (B - t)^(-n),  A = (n/alpha)^n exp(-alpha^2/2),
+ *                                 B = n/alpha - alpha.                  */
+double g_cb(const orc_node& nd, const double* th, double x, double* dg) {
+  double m0 = P(th, nd, 0), s = P(th, nd, 1), a = P(th, nd, 2), n = P(th, nd, 3);
+  double t = (x - m0) / s;
+  if (t > -a) {
+    double g = std::exp(-0.5 * t * t);
+    if (dg) {
+      dg[0] = g * t / s;
+      dg[1] = g * t * t / s;
+      dg[2] = 0.0;
+      dg[3] = 0.0;
+    }
+    return g;
+  }
+  double A = std::pow(n / a, n) * std::exp(-0.5 * a * a);
+  double B = n / a - a;
+  double D = B - t;
+  double g = A * std::pow(D, -n);
+  if (dg) {
+    dg[0] = g * (-n / (s * D));
+    dg[1] = g * (-n * t / (s * D));
+    dg[2] = g * (-n / a - a + n * (n / (a * a) + 1.0) / D);
+    dg[3] = g * (std::log(n / a) + 1.0 - std::log(D) - n / (a * D));
+  }
+  return g;
+}
+
+/* ARGUS with power 1/2: g = m sqrt(u) exp(c u), u = 1 - (m/m0)^2, for
+ * m < m0, and 0 otherwise.  u is formed as (m0 - m)(m0 + m)/m0^2.       */
+double g_argus(const orc_node& nd, const double* th, double x, double* dg) {
+  double m0 = P(th, nd, 0), c = P(th, nd, 1);
+  if (x >= m0) {
+    if (dg) dg[0] = dg[1] = 0.0;
+    return 0.0;
+  }
+  double u = (m0 - x) * (m0 + x) / (m0 * m0);
+  double g = x * std::sqrt(u) * std::exp(c * u);
+  if (dg) {
+    dg[0] = g * (0.5 / u + c) * 2.0 * x * x / (m0 * m0 * m0);
+    dg[1] = g * u;
+  }
+  return g;
+}
+
+double leaf_g(const orc_model& m, const orc_node& nd, const double* th, double x, double* dg) {
+  switch (nd.kind) {
+    case ORC_GAUSS: return g_gauss(nd, th, x, dg);
+    case ORC_EXP: return g_exp(nd, th, x, dg);
+    case ORC_CHEB: return g_cheb(nd, th, m.lo[nd.obs], m.hi[nd.obs], x, dg);
+    case ORC_CB: return g_cb(nd, th, x, dg);
+    case ORC_ARGUS: return g_argus(nd, th, x, dg);
+  }
+  return std::nan("");
+}
+
+/* ------------------------------------------------------------------ */
+/* Normalisation integrals.                                             */
+/* ------------------------------------------------------------------ */
+
+/* erf(b/sqrt2) - erf(a/sqrt2) for a <= b, using erfc when both are on the
+ * same side of zero (avoids cancellation in the far tails). */
+double erf_diff(double a, double b) {
+  const double r = 1.0 / std::sqrt(2.0);
+  if (a >= 0.0) return std::erfc(a * r) - std::erfc(b * r);
+  if (b <= 0.0) return std::erfc(-b * r) - std::erfc(-a * r);
+  return std::erf(b * r) - std::erf(a * r);
+}
+
+/* Gaussian over [lo, hi]: Z = sigma sqrt(pi/2) [erf(b/sqrt2) - erf(a/sqrt2)]
+ * with a, b the standardised limits; derivatives by differentiating under
+ * the integral sign:
+ *   dZ/dmu    = e^{-a^2/2} - e^{-b^2/2}
+ *   dZ/dsigma = Z/sigma + a e^{-a^2/2} - b e^{-b^2/2}.                  */
+void norm_gauss_closed(double mu, double s, double lo, double hi, double* Z, double* d) {
+  double a = (lo - mu) / s, b = (hi - mu) / s;
+  double ea = std::exp(-0.5 * a * a), eb = std::exp(-0.5 * b * b);
+  double z = s * std::sqrt(kPi / 2.0) * erf_diff(a, b);
+  *Z = z;
+  d[0] = ea - eb;
+  d[1] = z / s + a * ea - b * eb;
+}
+
+/* Exponential over [lo, hi]: Z = int e^{cx} dx, dZ/dc = int x e^{cx} dx.
+ * Power series in c when |c| max(|lo|,|hi|) is small, else closed form. */
+void norm_exp_closed(double c, double lo, double hi, double* Z, double* d) {
+  double R = std::max(std::fabs(lo), std::fabs(hi));
+  if (std::fabs(c) * R < 0.5) {
+    Neumaier z, dz;
+    double ck = 1.0; /* c^k / k! */
+    double hp = hi, lp = lo;
+    for (int k = 0; k < 60; ++k) {
+      /* hp = hi^{k+1}, lp = lo^{k+1} */
+      z.add(ck * (hp - lp) / (k + 1));
+      dz.add(ck * (hp * hi - lp * lo) / (k + 2));
+      hp *= hi;
+      lp *= lo;
+      ck *= c / (k + 1);
+    }
+    *Z = z.value();
+    d[0] = dz.value();
+    return;
+  }
+  double ehi = std::exp(c * hi), elo = std::exp(c * lo);
+  double z = elo * std::expm1(c * (hi - lo)) / c;
+  *Z = z;
+  d[0] = (ehi * (c * hi - 1.0) - elo * (c * lo - 1.0)) / (c * c);
+}
+
+/* Chebyshev: int_{-1}^{1} T_k = 2/(1-k^2) for even k, 0 for odd k. */
+void norm_cheb_closed(const orc_node& nd, const double* th, double lo, double hi, double* Z,
+                      double* d) {
+  double h = hi - lo;
+  double z = h; /* T_0 term: (hi-lo)/2 * 2 */
+  for (int k = 1; k <= nd.n_param; ++k) {
+    double ik = (k % 2 == 0) ? 2.0 / (1.0 - (double)k * k) : 0.0;
+    z += 0.5 * h * P(th, nd, k - 1) * ik;
+    d[k - 1] = 0.5 * h * ik;
+  }
+  *Z = z;
+}
+
+/* Crystal Ball closed form.  Core piece over t in [ca, cb], tail piece over
+ * t in [ta, tb] (t = (m - m0)/sigma, dm = sigma dt, D = B - t):
+ *   core: sigma sqrt(pi/2) [erf]                       (as the Gaussian)
+ *   tail: sigma A/(n-1) [D^{1-n}]                        since
+ *         int D^{-n} dt = D^{1-n}/(n-1), int D^{-n-1} dt = D^{-n}/n,
+ *         int D^{-n} ln D dt = D^{1-n} (ln D/(n-1) + 1/(n-1)^2).
+ * Derivatives are int dg/dtheta dm over the fixed m-range (g is continuous
+ * at the junction, so the moving split point contributes nothing).      */
+void norm_cb_closed(double m0, double s, double a, double n, double lo, double hi, double* Z,
+                    double* d) {
+  double tlo = (lo - m0) / s, thi = (hi - m0) / s;
+  double z = 0.0;
+  d[0] = d[1] = d[2] = d[3] = 0.0;
+  double ca = std::max(tlo, -a), cb = thi;
+  if (cb > ca) {
+    double ea = std::exp(-0.5 * ca * ca), eb = std::exp(-0.5 * cb * cb);
+    double zc = s * std::sqrt(kPi / 2.0) * erf_diff(ca, cb);
+    z += zc;
+    d[0] += ea - eb;
+    d[1] += zc / s + ca * ea - cb * eb;
+  }
+  double ta = tlo, tb = std::min(thi, -a);
+  if (tb > ta) {
+    double A = std::pow(n / a, n) * std::exp(-0.5 * a * a);
+    double B = n / a - a;
+    double Da = B - ta, Db = B - tb;
+    auto F = [n](double D) {
+      return std::pow(D, 1.0 - n) * (std::log(D) / (n - 1.0) + 1.0 / ((n - 1.0) * (n - 1.0)));
+    };
+    double dDn = std::pow(Db, -n) - std::pow(Da, -n);          /* [D^{-n}]     */
+    double dD1n = std::pow(Db, 1.0 - n) - std::pow(Da, 1.0 - n); /* [D^{1-n}]   */
+    double zt = s * A / (n - 1.0) * dD1n;
+    z += zt;
+    d[0] += -A * dDn;
+    d[1] += -n * A * (B * dDn / n - dD1n / (n - 1.0));
+    d[2] += (-n / a - a) * zt + (n / (a * a) + 1.0) * s * A * dDn;
+    d[3] += (std::log(n / a) + 1.0) * zt - s * A * (F(Db) - F(Da)) - s * A * dDn / a;
+  }
+  *Z = z;
+}
+
+/* J_p(U) = int_0^U u^p e^{c u} du for p > -1, by series with positive
+ * terms only:
+ *   c >= 0: U^{p+1} sum_j (cU)^j / (j! (j + p + 1))
+ *   c <  0: U^{p+1} e^{-kU} sum_j (kU)^j / prod_{i=0..j} (p + 1 + i), k = -c
+ * (the second is the series of the lower incomplete gamma function). */
+double J_series(double p, double c, double U) {
+  if (U <= 0.0) return 0.0;
+  double a = p + 1.0;
+  Neumaier sum;
+  if (c >= 0.0) {
+    double x = c * U, term = 1.0; /* x^j / j! */
+    for (int j = 0; j < 5000; ++j) {
+      double add = term / (j + a);
+      sum.add(add);
+      if (j > 2 && add < 1e-19 * sum.value()) break;
+      term *= x / (j + 1);
+    }
+    return std::pow(U, a) * sum.value();
+  }
+  double x = -c * U, term = 1.0 / a;
+  for (int j = 0; j < 5000; ++j) {
+    sum.add(term);
+    if (j > 2 && term < 1e-19 * sum.value()) break;
+    term *= x / (a + j + 1);
+  }
+  return std::pow(U, a) * std::exp(-x) * sum.value();
+}
+
+/* ARGUS over [lo, min(hi, m0)] in the variable u = 1 - (m/m0)^2
+ * (m dm = -m0^2/2 du):
+ *   Z      = m0^2/2 [J_{1/2}]
+ *   dZ/dc  = m0^2/2 [J_{3/2}]
+ *   dZ/dm0 = m0 [ (J_{-1/2} - J_{1/2})/2 + c (J_{1/2} - J_{3/2}) ]
+ * each bracket taken between u(lo) and u(min(hi, m0)).                 */
+void norm_argus_closed(double m0, double c, double lo, double hi, double* Z, double* d) {
+  double Ua = (m0 - lo) * (m0 + lo) / (m0 * m0);
+  double Ub = (hi >= m0) ? 0.0 : (m0 - hi) * (m0 + hi) / (m0 * m0);
+  auto J = [c, Ua, Ub](double p) { return J_series(p, c, Ua) - J_series(p, c, Ub); };
+  double jm = J(-0.5), j1 = J(0.5), j3 = J(1.5);
+  *Z = 0.5 * m0 * m0 * j1;
+  d[0] = m0 * (0.5 * (jm - j1) + c * (j1 - j3));
+  d[1] = 0.5 * m0 * m0 * j3;
+}
+
+/* 256-point Gauss-Legendre on [a, b] of g and dg (np local derivatives). */
+void gl_panel(const orc_model& m, const orc_node& nd, const double* th, double a, double b,
+              double* Z, double* d) {
+  const Rule& r = rule256();
+  double h = 0.5 * (b - a), c = 0.5 * (a + b);
+  double dg[ORC_NODE_PAR];
+  for (size_t i = 0; i < r.x.size(); ++i) {
+    double x = c + h * r.x[i];
+    double g = leaf_g(m, nd, th, x, dg);
+    *Z += h * r.w[i] * g;
+    for (int k = 0; k < nd.n_param; ++k) d[k] += h * r.w[i] * dg[k];
+  }
+}
+
+/* ARGUS after m = m0 - s^2 (dm = 2 s ds), which makes the integrand
+ * analytic in s; u = s^2 (2 m0 - s^2)/m0^2 is formed from s directly. */
+void gl_argus_subst(const orc_node& nd, const double* th, double lo, double hi, double* Z,
+                    double* d) {
+  double m0 = P(th, nd, 0), c = P(th, nd, 1);
+  double sa = std::sqrt(m0 - std::min(hi, m0)), sb = std::sqrt(m0 - lo);
+  const Rule& r = rule256();
+  double h = 0.5 * (sb - sa), cc = 0.5 * (sa + sb);
+  for (size_t i = 0; i < r.x.size(); ++i) {
+    double sv = cc + h * r.x[i];
+    double mm = m0 - sv * sv;
+    double u = sv * sv * (2.0 * m0 - sv * sv) / (m0 * m0);
+    double g = mm * std::sqrt(u) * std::exp(c * u);
+    double jac = 2.0 * sv * h * r.w[i];
+    *Z += jac * g;
+    d[0] += jac * g * (0.5 / u + c) * 2.0 * mm * mm / (m0 * m0 * m0);
+    d[1] += jac * g * u;
+  }
+}
+
+/* Z and dZ (local parameter order) of one leaf. */
+void leaf_norm_local(const orc_model& m, const orc_node& nd, const double* th, double* Z,
+                     double* d) {
+  double lo = m.lo[nd.obs], hi = m.hi[nd.obs];
+  *Z = 0.0;
+  for (int k = 0; k < ORC_NODE_PAR; ++k) d[k] = 0.0;
+  if (nd.norm == ORC_NORM_CLOSED) {
+    switch (nd.kind) {
+      case ORC_GAUSS: norm_gauss_closed(P(th, nd, 0), P(th, nd, 1), lo, hi, Z, d); return;
+      case ORC_EXP: norm_exp_closed(P(th, nd, 0), lo, hi, Z, d); return;
+      case ORC_CHEB: norm_cheb_closed(nd, th, lo, hi, Z, d); return;
+      case ORC_CB:
+        norm_cb_closed(P(th, nd, 0), P(th, nd, 1), P(th, nd, 2), P(th, nd, 3), lo, hi, Z, d);
+        return;
+      case ORC_ARGUS: norm_argus_closed(P(th, nd, 0), P(th, nd, 1), lo, hi, Z, d); return;
+    }
+    return;
+  }
+  if (nd.norm == ORC_NORM_GL_SINGLE) {
+    gl_panel(m, nd, th, lo, hi, Z, d);
+    return;
+  }
+  /* ORC_NORM_GL_SPLIT */
+  if (nd.kind == ORC_CB) {
+    double mj = P(th, nd, 0) - P(th, nd, 2) * P(th, nd, 1);
+    if (mj <= lo || mj >= hi) {
+      gl_panel(m, nd, th, lo, hi, Z, d);
+    } else {
+      gl_panel(m, nd, th, lo, mj, Z, d);
+      gl_panel(m, nd, th, mj, hi, Z, d);
+    }
+    return;
+  }
+  if (nd.kind == ORC_ARGUS) {
+    gl_argus_subst(nd, th, lo, hi, Z, d);
+    return;
+  }
+  gl_panel(m, nd, th, lo, hi, Z, d);
+}
+
+/* ------------------------------------------------------------------ */
+/* Model checks.                                                        */
+/* ------------------------------------------------------------------ */
+int expected_params(const orc_node& nd) {
+  switch (nd.kind) {
+    case ORC_GAUSS: return 2;
+    case ORC_EXP: return 1;
+    case ORC_CHEB: return (nd.n_param >= 1 && nd.n_param <= ORC_NODE_PAR) ? nd.n_param : -1;
+    case ORC_CB: return 4;
+    case ORC_ARGUS: return 2;
+    case ORC_SUM: return nd.n_child - 1;
+    case ORC_PROD: return 0;
+  }
+  return -1;
+}
+
+/* Bit mask of observables a node depends on. */
+unsigned obs_mask(const orc_model& m, int i) {
+  const orc_node& nd = m.node[i];
+  if (nd.kind <= ORC_ARGUS) return 1u << nd.obs;
+  unsigned r = 0;
+  for (int j = 0; j < nd.n_child; ++j) r |= obs_mask(m, nd.child[j]);
+  return r;
+}
+
+int check_model(const orc_model& m) {
+  if (m.n_obs < 1 || m.n_obs > ORC_MAX_OBS) return ORC_E_ARG;
+  if (m.n_param < 0 || m.n_param > ORC_MAX_PAR) return ORC_E_ARG;
+  if (m.n_node < 1 || m.n_node > ORC_MAX_NODE) return ORC_E_ARG;
+  if (m.root < 0 || m.root >= m.n_node) return ORC_E_ARG;
+  for (int o = 0; o < m.n_obs; ++o)
+    if (!(m.lo[o] < m.hi[o])) return ORC_E_ARG;
+  for (int i = 0; i < m.n_node; ++i) {
+    const orc_node& nd = m.node[i];
+    if (nd.kind < ORC_GAUSS || nd.kind > ORC_PROD) return ORC_E_ARG;
+    if (nd.n_param < 0 || nd.n_param > ORC_NODE_PAR) return ORC_E_ARG;
+    if (expected_params(nd) != nd.n_param) return ORC_E_ARG;
+    for (int k = 0; k < nd.n_param; ++k)
+      if (nd.param[k] < 0 || nd.param[k] >= m.n_param) return ORC_E_ARG;
+    if (nd.kind <= ORC_ARGUS) {
+      if (nd.obs < 0 || nd.obs >= m.n_obs || nd.n_child != 0) return ORC_E_ARG;
+      if (nd.norm < ORC_NORM_CLOSED || nd.norm > ORC_NORM_GL_SINGLE) return ORC_E_ARG;
+      if (nd.kind == ORC_ARGUS && m.lo[nd.obs] < 0.0) return ORC_E_UNSUPPORTED;
+    } else {
+      if (nd.n_child < (nd.kind == ORC_SUM ? 2 : 1) || nd.n_child > ORC_NODE_CHILD)
+        return ORC_E_ARG;
+      for (int j = 0; j < nd.n_child; ++j)
+        if (nd.child[j] < 0 || nd.child[j] >= i) return ORC_E_ARG; /* topological */
+      if (nd.kind == ORC_SUM) {
+        unsigned m0 = obs_mask(m, nd.child[0]);
+        for (int j = 1; j < nd.n_child; ++j)
+          if (obs_mask(m, nd.child[j]) != m0) return ORC_E_UNSUPPORTED;
+      } else {
+        unsigned seen = 0;
+        for (int j = 0; j < nd.n_child; ++j) {
+          unsigned mk = obs_mask(m, nd.child[j]);
+          if (mk & seen) return ORC_E_UNSUPPORTED; /* products over disjoint observables */
+          seen |= mk;
+        }
+      }
+    }
+  }
+  if (obs_mask(m, m.root) != (1u << m.n_obs) - 1u) return ORC_E_UNSUPPORTED;
+  if (m.extended && (m.yield_param < 0 || m.yield_param >= m.n_param)) return ORC_E_ARG;
+  return ORC_OK;
+}
+
+/* Parameter-range checks of Sec. 3: declared [lo, hi] per parameter plus
+ * the constraints of each density. */
+int check_params(const orc_model& m, const double* th) {
+  for (int k = 0; k < m.n_param; ++k) {
+    if (!(th[k] >= m.par_lo[k] && th[k] <= m.par_hi[k])) return ORC_E_PARAM; /* NaN too */
+  }
+  for (int i = 0; i < m.n_node; ++i) {
+    const orc_node& nd = m.node[i];
+    switch (nd.kind) {
+      case ORC_GAUSS:
+        if (!(P(th, nd, 1) > 0.0)) return ORC_E_PARAM;
+        break;
+      case ORC_CB:
+        if (!(P(th, nd, 1) > 0.0) || !(P(th, nd, 2) > 0.0) || !(P(th, nd, 3) > 1.0))
+          return ORC_E_PARAM;
+        break;
+      case ORC_ARGUS:
+        if (!(P(th, nd, 0) > m.lo[nd.obs])) return ORC_E_PARAM;
+        break;
+      case ORC_SUM: {
+        double f = 0.0;
+        for (int k = 0; k < nd.n_param; ++k) {
+          double v = P(th, nd, k);
+          if (!(v >= 0.0 && v <= 1.0)) return ORC_E_PARAM;
+          f += v;
+        }
+        if (!(f <= 1.0)) return ORC_E_PARAM;
+        break;
+      }
+      default: break;
+    }
+  }
+  if (m.extended && !(th[m.yield_param] > 0.0)) return ORC_E_PARAM;
+  return ORC_OK;
+}
+
+/* Per-parameter-point cache: the normalisation of every leaf. */
+struct Prepared {
+  const orc_model* m;
+  const double* th;
+  double Z[ORC_MAX_NODE];
+  double dZ[ORC_MAX_NODE][ORC_NODE_PAR]; /* local order */
+};
+
+int prepare(const orc_model& m, const double* th, Prepared& pr) {
+  pr.m = &m;
+  pr.th = th;
+  int st = check_params(m, th);
+  if (st != ORC_OK) return st;
+  for (int i = 0; i < m.n_node; ++i) {
+    const orc_node& nd = m.node[i];
+    if (nd.kind > ORC_ARGUS) continue;
+    leaf_norm_local(m, nd, th, &pr.Z[i], pr.dZ[i]);
+    if (!(pr.Z[i] > 0.0) || !std::isfinite(pr.Z[i])) return ORC_E_PARAM;
+  }
+  return ORC_OK;
+}
+
+/* Value of node i at event x and, if dv != NULL, d value / d theta over all
+ * n_param parameters. */
+double node_value(const Prepared& pr, int i, const double* x, double* dv) {
+  const orc_model& m = *pr.m;
+  const orc_node& nd = m.node[i];
+  const int np = m.n_param;
+  if (nd.kind <= ORC_ARGUS) {
+    double dg[ORC_NODE_PAR];
+    double g = leaf_g(m, nd, pr.th, x[nd.obs], dv ? dg : nullptr);
+    double Z = pr.Z[i];
+    double v = g / Z;
+    if (dv) {
+      for (int k = 0; k < np; ++k) dv[k] = 0.0;
+      /* d(g/Z) = dg/Z - g dZ / Z^2 */
+      for (int k = 0; k < nd.n_param; ++k) dv[nd.param[k]] += dg[k] / Z - g * pr.dZ[i][k] / (Z * Z);
+    }
+    return v;
+  }
+  double cd[ORC_MAX_PAR];
+  if (nd.kind == ORC_SUM) {
+    double v = 0.0, flast = 1.0;
+    if (dv)
+      for (int k = 0; k < np; ++k) dv[k] = 0.0;
+    for (int k = 0; k < nd.n_param; ++k) flast -= P(pr.th, nd, k);
+    for (int j = 0; j < nd.n_child; ++j) {
+      double cv = node_value(pr, nd.child[j], x, dv ? cd : nullptr);
+      double coef = (j < nd.n_child - 1) ? P(pr.th, nd, j) : flast;
+      v += coef * cv;
+      if (dv) {
+        for (int k = 0; k < np; ++k) dv[k] += coef * cd[k];
+        if (j < nd.n_child - 1) {
+          dv[nd.param[j]] += cv;
+        } else {
+          for (int q = 0; q < nd.n_param; ++q) dv[nd.param[q]] -= cv;
+        }
+      }
+    }
+    return v;
+  }
+  /* ORC_PROD */
+  double v = 1.0;
+  double vals[ORC_NODE_CHILD];
+  double dchild[ORC_NODE_CHILD][ORC_MAX_PAR];
+  for (int j = 0; j < nd.n_child; ++j) {
+    vals[j] = node_value(pr, nd.child[j], x, dv ? dchild[j] : nullptr);
+    v *= vals[j];
+  }
+  if (dv) {
+    for (int k = 0; k < np; ++k) dv[k] = 0.0;
+    for (int j = 0; j < nd.n_child; ++j) {
+      double others = 1.0;
+      for (int q = 0; q < nd.n_child; ++q)
+        if (q != j) others *= vals[q];
+      for (int k = 0; k < np; ++k) dv[k] += others * dchild[j][k];
+    }
+  }
+  return v;
+}
+
+struct Partial {
+  Neumaier nll;
+  Neumaier grad[ORC_MAX_PAR];
+  Neumaier abs_l;
+  Neumaier abs_g[ORC_MAX_PAR];
+  int status = ORC_OK;
+};
+
+void nll_range(const Prepared& pr, const double* const* cols, int64_t b, int64_t e, bool want_grad,
+               Partial& out) {
+  const orc_model& m = *pr.m;
+  const int np = m.n_param;
+  double x[ORC_MAX_OBS];
+  double dv[ORC_MAX_PAR];
+  for (int64_t i = b; i < e; ++i) {
+    for (int o = 0; o < m.n_obs; ++o) {
+      x[o] = cols[o][i];
+      if (!(x[o] >= m.lo[o] && x[o] <= m.hi[o])) {
+        out.status = ORC_E_DOMAIN;
+        return;
+      }
+    }
+    double p = node_value(pr, m.root, x, want_grad ? dv : nullptr);
+    if (!(p > 0.0) || !std::isfinite(p)) {
+      out.status = ORC_E_PDF;
+      return;
+    }
+    double l = std::log(p);
+    out.nll.add(-l);
+    out.abs_l.add(std::fabs(l));
+    if (want_grad) {
+      for (int k = 0; k < np; ++k) {
+        double dl = dv[k] / p; /* d log p = dp / p */
+        out.grad[k].add(-dl);
+        out.abs_g[k].add(std::fabs(dl));
+      }
+    }
+  }
+}
+
+/* One dataset, one parameter point. */
+int nll_one(const orc_model& m, const double* const* cols, int64_t n, const double* th,
+            int threads, double* nll, double* grad, double* stats) {
+  const int np = m.n_param;
+  auto fail = [&](int st) {
+    *nll = kInf;
+    if (grad)
+      for (int k = 0; k < np; ++k) grad[k] = 0.0;
+    return st;
+  };
+  Prepared pr;
+  int st = prepare(m, th, pr);
+  if (st != ORC_OK) return fail(st);
+  int T = std::max(1, threads);
+  if (n < 4096) T = 1;
+  std::vector<Partial> parts(T);
+  const bool want_grad = (grad != nullptr) || (stats != nullptr);
+  if (T == 1) {
+    nll_range(pr, cols, 0, n, want_grad, parts[0]);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 0; t < T; ++t) {
+      int64_t b = n * t / T, e = n * (t + 1) / T;
+      pool.emplace_back([&, b, e, t]() { nll_range(pr, cols, b, e, want_grad, parts[t]); });
+    }
+    for (auto& th_ : pool) th_.join();
+  }
+  /* fixed-order combine of the per-chunk compensated sums */
+  Neumaier tot, g[ORC_MAX_PAR], al, ag[ORC_MAX_PAR];
+  for (int t = 0; t < T; ++t) {
+    if (parts[t].status != ORC_OK) return fail(parts[t].status);
+    tot.add(parts[t].nll.s);
+    tot.add(parts[t].nll.c);
+    al.add(parts[t].abs_l.s);
+    al.add(parts[t].abs_l.c);
+    for (int k = 0; k < np; ++k) {
+      g[k].add(parts[t].grad[k].s);
+      g[k].add(parts[t].grad[k].c);
+      ag[k].add(parts[t].abs_g[k].s);
+      ag[k].add(parts[t].abs_g[k].c);
+    }
+  }
+  double v = tot.value();
+  if (m.extended) {
+    /* Poisson term for the total yield nu: nu - N ln nu */
+    double nu = th[m.yield_param];
+    v += nu - (double)n * std::log(nu);
+    g[m.yield_param].add(1.0 - (double)n / nu);
+  }
+  *nll = v;
+  if (grad)
+    for (int k = 0; k < np; ++k) grad[k] = m.par_free[k] ? g[k].value() : 0.0;
+  if (stats) {
+    stats[0] = al.value();
+    for (int k = 0; k < np; ++k) stats[1 + k] = ag[k].value();
+  }
+  return ORC_OK;
+}
+
+/* Gradient descent with step halving, see oracle.h. */
+int gd_fit_one(const orc_model& m, const double* const* cols, int64_t n, double* theta,
+               int n_steps, double eta, int threads, double* nll_out, double* grad_out,
+               double* eta_out, double* trace) {
+  const int np = m.n_param;
+  std::vector<double> acc(theta, theta + np), prop(theta, theta + np), g_acc(np, 0.0),
+      g(np, 0.0);
+  double f_acc = kInf;
+  double inv_n = 1.0 / (double)std::max<int64_t>(n, 1);
+  int last = ORC_OK;
+  for (int s = 0; s < n_steps; ++s) {
+    double f;
+    int st = nll_one(m, cols, n, prop.data(), threads, &f, g.data(), nullptr);
+    if (trace) {
+      trace[s * (np + 1)] = f;
+      for (int k = 0; k < np; ++k) trace[s * (np + 1) + 1 + k] = prop[k];
+    }
+    bool ok = (st == ORC_OK) && std::isfinite(f) && f <= f_acc;
+    if (st == ORC_E_DOMAIN) return st;
+    if (ok) {
+      acc = prop;
+      f_acc = f;
+      g_acc = g;
+      last = ORC_OK;
+    } else {
+      eta *= 0.5;
+      if (!std::isfinite(f_acc)) last = st;
+    }
+    for (int k = 0; k < np; ++k)
+      prop[k] = m.par_free[k] ? acc[k] - eta * g_acc[k] * inv_n : acc[k];
+  }
+  for (int k = 0; k < np; ++k) theta[k] = acc[k];
+  *nll_out = f_acc;
+  if (grad_out)
+    for (int k = 0; k < np; ++k) grad_out[k] = g_acc[k];
+  if (eta_out) *eta_out = eta;
+  return std::isfinite(f_acc) ? ORC_OK : (last != ORC_OK ? last : ORC_E_PDF);
+}
+
+template <class F>
+void parallel_sets(int n_sets, int threads, F&& fn) {
+  int T = std::max(1, std::min(threads, n_sets));
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (;;) {
+      int s = next.fetch_add(1);
+      if (s >= n_sets) return;
+      fn(s);
+    }
+  };
+  if (T == 1) {
+    work();
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < T; ++t) pool.emplace_back(work);
+  for (auto& t : pool) t.join();
+}
+
+bool data_args_ok(const orc_model* m, const double* const* cols) {
+  if (!m || !cols) return false;
+  for (int o = 0; o < m->n_obs; ++o)
+    if (!cols[o]) return false;
+  return true;
+}
+
+}  // namespace
+
+/* ------------------------------------------------------------------ */
+/* C interface                                                          */
+/* ------------------------------------------------------------------ */
+extern "C" {
+
+int orc_check_model(const orc_model* m) { return m ? check_model(*m) : ORC_E_ARG; }
+
+int orc_leaf_norm(const orc_model* m, int32_t node, const double* theta, double* Z, double* dZ) {
+  if (!m || !theta || !Z || !dZ) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  if (node < 0 || node >= m->n_node || m->node[node].kind > ORC_ARGUS) return ORC_E_ARG;
+  st = check_params(*m, theta);
+  if (st != ORC_OK) return st;
+  double d[ORC_NODE_PAR];
+  const orc_node& nd = m->node[node];
+  leaf_norm_local(*m, nd, theta, Z, d);
+  for (int k = 0; k < m->n_param; ++k) dZ[k] = 0.0;
+  for (int k = 0; k < nd.n_param; ++k) dZ[nd.param[k]] += d[k];
+  return ORC_OK;
+}
+
+int orc_log_density(const orc_model* m, const double* x, const double* theta, double* logp,
+                    double* dlogp) {
+  if (!m || !x || !theta || !logp) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  Prepared pr;
+  st = prepare(*m, theta, pr);
+  if (st != ORC_OK) return st;
+  for (int o = 0; o < m->n_obs; ++o)
+    if (!(x[o] >= m->lo[o] && x[o] <= m->hi[o])) return ORC_E_DOMAIN;
+  double dv[ORC_MAX_PAR];
+  double p = node_value(pr, m->root, x, dlogp ? dv : nullptr);
+  if (!(p > 0.0) || !std::isfinite(p)) {
+    *logp = -kInf;
+    return ORC_E_PDF;
+  }
+  *logp = std::log(p);
+  if (dlogp)
+    for (int k = 0; k < m->n_param; ++k) dlogp[k] = dv[k] / p;
+  return ORC_OK;
+}
+
+int orc_nll(const orc_model* m, const double* const* cols, int64_t n, const double* theta,
+            int32_t threads, double* nll, double* grad, double* stats) {
+  if (!data_args_ok(m, cols) || !theta || !nll || n < 0) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  return nll_one(*m, cols, n, theta, threads, nll, grad, stats);
+}
+
+int orc_nll_batched(const orc_model* m, const double* const* cols, const int64_t* offsets,
+                    int32_t n_sets, const double* theta, int32_t threads, double* nll,
+                    double* grad, int32_t* status) {
+  if (!data_args_ok(m, cols) || !offsets || !theta || !nll || n_sets < 0) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  for (int s = 0; s < n_sets; ++s)
+    if (offsets[s + 1] < offsets[s]) return ORC_E_ARG;
+  const int np = m->n_param;
+  parallel_sets(n_sets, threads, [&](int s) {
+    const double* c[ORC_MAX_OBS];
+    for (int o = 0; o < m->n_obs; ++o) c[o] = cols[o] + offsets[s];
+    int r = nll_one(*m, c, offsets[s + 1] - offsets[s], theta + (size_t)s * np, 1, &nll[s],
+                    grad ? grad + (size_t)s * np : nullptr, nullptr);
+    if (status) status[s] = r;
+  });
+  return ORC_OK;
+}
+
+int orc_gd_fit(const orc_model* m, const double* const* cols, int64_t n, double* theta,
+               int32_t n_steps, double eta, int32_t threads, double* nll, double* grad,
+               double* eta_out, double* trace) {
+  if (!data_args_ok(m, cols) || !theta || !nll || n < 0 || n_steps < 0) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  return gd_fit_one(*m, cols, n, theta, n_steps, eta, threads, nll, grad, eta_out, trace);
+}
+
+int orc_gd_fit_batched(const orc_model* m, const double* const* cols, const int64_t* offsets,
+                       int32_t n_sets, double* theta, int32_t n_steps, double eta,
+                       int32_t threads, double* nll, double* grad, int32_t* status) {
+  if (!data_args_ok(m, cols) || !offsets || !theta || !nll || n_sets < 0 || n_steps < 0)
+    return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  const int np = m->n_param;
+  parallel_sets(n_sets, threads, [&](int s) {
+    const double* c[ORC_MAX_OBS];
+    for (int o = 0; o < m->n_obs; ++o) c[o] = cols[o] + offsets[s];
+    int r = gd_fit_one(*m, c, offsets[s + 1] - offsets[s], theta + (size_t)s * np, n_steps,
+                       eta, 1, &nll[s], grad ? grad + (size_t)s * np : nullptr, nullptr,
+                       nullptr);
+    if (status) status[s] = r;
+  });
+  return ORC_OK;
+}
+
+int orc_gl_rule(int32_t n, double* x, double* w) {
+  if (n < 1 || n > 4096 || !x || !w) return ORC_E_ARG;
+  Rule r = make_rule(n);
+  for (int i = 0; i < n; ++i) {
+    x[i] = r.x[i];
+    w[i] = r.w[i];
+  }
+  return ORC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+/*
+ * oracle.h -- scalar FP64 reference evaluator for unbinned negative
+ * log-likelihoods of composed probability densities.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include,
+ * link or call this code; only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark use it.  It shares no source with
+ * the GPU library (its own types, its own quadrature rule, its own
+ * special-function series).
+ *
+ * What it computes (paper, Sec. 5.1): for every entry of the dataset the
+ * observable values are written into the leaves of the computation graph
+ * and the probability of the top node is obtained by evaluating the
+ * daughters and their normalisation; constant (parameter-only) branches,
+ * i.e. the normalisation integrals, are computed once per parameter point.
+ * The result is NLL(theta) = -sum_i log p(x_i; theta) (natural log),
+ * accumulated with Neumaier-compensated FP64 sums, together with the
+ * analytic gradient dNLL/dtheta obtained by forward-mode differentiation of
+ * the same recursion (normalisation derivatives included).
+ *
+ * Normalisation (paper, Sec. 3, "Analytic Integrals"): closed forms when
+ * requested, otherwise 256-point Gauss-Legendre quadrature, either on one
+ * panel over the whole range or split into panels on which the integrand
+ * is analytic (Crystal Ball junction, ARGUS square-root endpoint).
+ *
+ * Parameter and observable range checks follow Sec. 3 ("Checking
+ * parameters"): a parameter outside its allowed range returns
+ * ORC_E_PARAM with NLL = +inf, an event outside the closed observable
+ * range returns ORC_E_DOMAIN, a non-positive or non-finite probability
+ * returns ORC_E_PDF with NLL = +inf.
+ */
+#ifndef NLL_ORACLE_H
+#define NLL_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum orc_kind {
+  ORC_GAUSS = 1, /* params (mu, sigma)                         */
+  ORC_EXP = 2,   /* params (c)            g = exp(c x)           */
+  ORC_CHEB = 3,  /* params (a_1..a_K)     g = 1 + sum a_k T_k(x') */
+  ORC_CB = 4,    /* params (m0, sigma, alpha, n), low-side tail   */
+  ORC_ARGUS = 5, /* params (m0, c), power 1/2                    */
+  ORC_SUM = 6,   /* params (f_1..f_{k-1}) over k children         */
+  ORC_PROD = 7   /* no params; children on disjoint observables   */
+};
+
+enum orc_norm {
+  ORC_NORM_CLOSED = 0,    /* closed-form integral and derivatives        */
+  ORC_NORM_GL_SPLIT = 1,  /* 256-point Gauss-Legendre per analytic panel */
+  ORC_NORM_GL_SINGLE = 2  /* 256-point Gauss-Legendre on one panel       */
+};
+
+enum orc_status {
+  ORC_OK = 0,
+  ORC_E_ARG = -1,
+  ORC_E_UNSUPPORTED = -2,
+  ORC_E_PARAM = -3,
+  ORC_E_DOMAIN = -4,
+  ORC_E_PDF = -5
+};
+
+#define ORC_MAX_OBS 4
+#define ORC_MAX_PAR 32
+#define ORC_MAX_NODE 16
+#define ORC_NODE_PAR 8
+#define ORC_NODE_CHILD 8
+
+typedef struct orc_node {
+  int32_t kind;
+  int32_t obs; /* observable index for leaves, -1 otherwise */
+  int32_t n_param;
+  int32_t param[ORC_NODE_PAR];
+  int32_t n_child;
+  int32_t child[ORC_NODE_CHILD];
+  int32_t norm; /* orc_norm, leaves only */
+} orc_node;
+
+typedef struct orc_model {
+  int32_t n_obs;
+  double lo[ORC_MAX_OBS], hi[ORC_MAX_OBS];
+  int32_t n_param;
+  double par_lo[ORC_MAX_PAR], par_hi[ORC_MAX_PAR];
+  uint8_t par_free[ORC_MAX_PAR];
+  int32_t n_node;
+  orc_node node[ORC_MAX_NODE];
+  int32_t root;
+  int32_t extended;    /* 1: add nu - N ln nu (Poisson yield term) */
+  int32_t yield_param; /* index of nu when extended               */
+} orc_model;
+
+/* Structural validation (topological order, arities, disjoint products). */
+int orc_check_model(const orc_model* m);
+
+/* Normalisation integral Z of leaf `node` over its observable range and
+ * dZ/dtheta for every model parameter (dZ has n_param entries).        */
+int orc_leaf_norm(const orc_model* m, int32_t node, const double* theta,
+                  double* Z, double* dZ);
+
+/* log p and d log p / d theta (n_param entries, may be NULL) for ONE event
+ * x[0..n_obs-1].                                                        */
+int orc_log_density(const orc_model* m, const double* x, const double* theta,
+                    double* logp, double* dlogp);
+
+/* NLL and gradient (grad may be NULL) over n events held as columns
+ * cols[obs][i].  threads <= 1 runs serially; otherwise contiguous chunks
+ * are combined in fixed order.  stats (may be NULL) receives
+ * [sum |l_i|, then sum_i |d l_i / d theta_k| for every k].              */
+int orc_nll(const orc_model* m, const double* const* cols, int64_t n,
+            const double* theta, int32_t threads, double* nll, double* grad,
+            double* stats);
+
+/* Many datasets: set s holds events [offsets[s], offsets[s+1]) and its own
+ * parameter row theta[s*n_param ...].  Per-set status in status[s].      */
+int orc_nll_batched(const orc_model* m, const double* const* cols,
+                    const int64_t* offsets, int32_t n_sets, const double* theta,
+                    int32_t threads, double* nll, double* grad, int32_t* status);
+
+/* Gradient descent on the mean NLL: proposal theta' = theta_acc -
+ * eta * g_acc / N over free parameters; a proposal is accepted when its NLL
+ * is finite and not larger than the last accepted one, otherwise eta is
+ * halved.  Exactly n_steps evaluations; the first evaluates the start
+ * point.  On return theta/nll/grad hold the last accepted point and
+ * eta_out the final step size.  trace (may be NULL) receives per step
+ * [nll_prop, theta_prop...].                                            */
+int orc_gd_fit(const orc_model* m, const double* const* cols, int64_t n,
+               double* theta, int32_t n_steps, double eta, int32_t threads,
+               double* nll, double* grad, double* eta_out, double* trace);
+
+/* The same minimiser run independently on every set (threads over sets). */
+int orc_gd_fit_batched(const orc_model* m, const double* const* cols,
+                       const int64_t* offsets, int32_t n_sets, double* theta,
+                       int32_t n_steps, double eta, int32_t threads,
+                       double* nll, double* grad, int32_t* status);
+
+/* n-point Gauss-Legendre rule on [-1, 1] (nodes ascending). */
+int orc_gl_rule(int32_t n, double* x, double* w);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLL_ORACLE_H */
