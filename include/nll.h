@@ -1,0 +1,223 @@
+/*
+ * nll.h -- C ABI of libnllmi: batched unbinned negative log-likelihoods of
+ * composed probability densities on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Hageboeck, "A Faster, More Intuitive RooFit",
+ * arXiv:2003.12875):
+ *   - a computation graph connecting observables, parameters and densities
+ *     into a likelihood model fitted to data (Sec. 1);
+ *   - the unbinned likelihood, one expression evaluated per dataset entry
+ *     (Sec. 5.1), here reduced to NLL(theta) = -sum_i ln p(x_i; theta) over
+ *     all events, in one fused streaming pass over structure-of-arrays
+ *     event columns (the batched data flow of Sec. 5.2/5.3);
+ *   - normalisation of every density over its observable range by closed
+ *     forms or numerical quadrature (Sec. 3, "Analytic Integrals"), computed
+ *     once per parameter point (Sec. 5.1, node-local caching);
+ *   - parameter range checks and the rejection of non-positive or
+ *     non-finite probabilities (Sec. 3, "Checking parameters");
+ *   - the analytic gradient dNLL/dtheta from the same pass, many datasets
+ *     per launch (toy studies, Sec. 1) and on-device gradient-descent fits
+ *     in the role of fitTo (Sec. 5.3).
+ *
+ * Conventions
+ *   - All event columns, parameter vectors and outputs are DEVICE pointers
+ *     (memory of the model's device).  The caller owns them.  Entry points
+ *     marked "enqueue" only enqueue work on the model's stream; results are
+ *     valid when that stream reaches them (they never synchronise, so they
+ *     can be captured into a HIP graph), and device-detected errors are
+ *     reported later by nll_sync() or the per-set status arrays.
+ *   - theta always holds all n_param values in declaration order, fixed
+ *     ones included; gradients have n_param entries and those of fixed
+ *     parameters are written as 0.  Batched theta and gradient arrays are
+ *     row-major [set][param].
+ *   - A model is used by one host thread at a time; calls on one model are
+ *     not reentrant.  Different models are independent.
+ *   - Errors: every entry point returns an nll_status; arguments are checked
+ *     before anything is enqueued, and on a synchronous error nothing is
+ *     enqueued.
+ */
+#ifndef NLLMI_NLL_H
+#define NLLMI_NLL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NLL_MAX_OBS 4
+#define NLL_MAX_PARAMS 32
+#define NLL_MAX_NODES 16
+#define NLL_NODE_MAX_PARAMS 8
+#define NLL_NODE_MAX_CHILDREN 8
+
+typedef enum nll_status {
+  NLL_OK = 0,
+  NLL_ERR_ARG = -1,          /* malformed argument or descriptor            */
+  NLL_ERR_UNSUPPORTED = -2,  /* valid graph with no compiled kernel shape    */
+  NLL_ERR_PARAM_RANGE = -3,  /* parameter outside its allowed range          */
+  NLL_ERR_DOMAIN = -4,       /* event outside the closed observable range    */
+  NLL_ERR_INVALID_PDF = -5,  /* some p(x_i) <= 0 or non-finite               */
+  NLL_ERR_DEVICE = -6,       /* HIP runtime error                           */
+  NLL_ERR_OOM = -7,          /* device allocation failed                    */
+  NLL_ERR_STATE = -8         /* call out of order (e.g. no data attached)    */
+} nll_status;
+
+/* Node kinds.  Leaf parameters, in this order:
+ *   NLL_GAUSS  (mu, sigma)            g = exp(-((x-mu)/sigma)^2 / 2), sigma > 0
+ *   NLL_EXP    (c)                    g = exp(c x)
+ *   NLL_CHEB   (a_1 .. a_K), K <= 8   g = 1 + sum_k a_k T_k(x'), x' = (2x-lo-hi)/(hi-lo)
+ *   NLL_CB     (m0, sigma, alpha, n)  Crystal Ball, Gaussian core for
+ *              t = (x-m0)/sigma > -alpha, power-law tail A (B - t)^-n below,
+ *              A = (n/alpha)^n exp(-alpha^2/2), B = n/alpha - alpha;
+ *              sigma > 0, alpha > 0, n > 1
+ *   NLL_ARGUS  (m0, c)                g = x sqrt(u) exp(c u), u = 1 - (x/m0)^2 for
+ *              x < m0, 0 above; m0 > observable lo >= 0
+ * Composite nodes:
+ *   NLL_SUM    params (f_1 .. f_{k-1}) over k >= 2 children on the same
+ *              observables: p = sum_{j<k} f_j p_j + (1 - sum f) p_k,
+ *              f_j in [0, 1], sum f <= 1
+ *   NLL_PROD   no params; children on disjoint observables: p = prod p_d   */
+enum nll_node_kind { NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7 };
+
+/* Normalisation of a leaf over its observable range [lo, hi]:
+ *   NLL_NORM_ANALYTIC      closed form (Sec. 3 "Analytic Integrals")
+ *   NLL_NORM_GL256         256-point Gauss-Legendre per analytic panel: the
+ *                          Crystal Ball is split at its core/tail junction,
+ *                          the ARGUS endpoint is removed by x = m0 - s^2
+ *   NLL_NORM_GL256_SINGLE  256-point Gauss-Legendre on [lo, hi] as one panel */
+enum nll_norm_method { NLL_NORM_ANALYTIC = 0, NLL_NORM_GL256 = 1, NLL_NORM_GL256_SINGLE = 2 };
+
+/* Arithmetic of the per-event pass.  FP64 everywhere, or FP32 per-event
+ * density arithmetic with compensated (two-sum) FP32 per-thread sums and
+ * FP64 normalisation, cross-thread reduction and minimiser. */
+enum nll_precision { NLL_FP64 = 0, NLL_FP32C = 1 };
+
+typedef struct nll_node_desc {
+  int32_t kind;                         /* nll_node_kind                     */
+  int32_t obs;                          /* observable index (leaves), else -1 */
+  int32_t n_param;
+  int32_t param[NLL_NODE_MAX_PARAMS];   /* indices into theta                */
+  int32_t n_child;
+  int32_t child[NLL_NODE_MAX_CHILDREN]; /* indices of EARLIER nodes          */
+  int32_t norm;                         /* nll_norm_method (leaves)          */
+} nll_node_desc;
+
+typedef struct nll_model_desc {
+  int32_t n_obs;                  /* 1 .. NLL_MAX_OBS                         */
+  const double* obs_lo;           /* host arrays [n_obs]: closed ranges       */
+  const double* obs_hi;
+  int32_t n_param;                /* 1 .. NLL_MAX_PARAMS                      */
+  const double* param_lo;         /* host arrays [n_param]: allowed ranges    */
+  const double* param_hi;
+  const uint8_t* param_free;      /* host [n_param], 0 = fixed (NULL: all free) */
+  int32_t n_node;                 /* 1 .. NLL_MAX_NODES, topological order     */
+  const nll_node_desc* nodes;     /* host [n_node]                            */
+  int32_t root;                   /* index of the top density                 */
+  int32_t precision;              /* nll_precision                            */
+  int32_t extended;               /* 1: add nu - N ln nu (Poisson yield term) */
+  int32_t yield_param;            /* index of nu when extended                */
+  int32_t device;                 /* HIP device ordinal                       */
+  void* stream;                   /* hipStream_t for all enqueued work (NULL: default) */
+} nll_model_desc;
+
+typedef struct nll_model nll_model; /* opaque, owned by the library */
+
+/* Validate the descriptor, lower the graph onto a compiled kernel shape and
+ * allocate the model's device scratch.  Descriptor arrays are copied; the
+ * caller may free them afterwards.  Errors: NLL_ERR_ARG (malformed graph,
+ * bad indices, non-topological order, SUM over different observables, PROD
+ * over shared observables, unused observable), NLL_ERR_UNSUPPORTED (no
+ * compiled shape matches), NLL_ERR_DEVICE, NLL_ERR_OOM. */
+nll_status nll_create_model(const nll_model_desc* desc, nll_model** out);
+
+/* Release the model and its device scratch (waits for its stream). */
+void nll_destroy_model(nll_model* model);
+
+/* Change the stream used by subsequent enqueue calls. */
+nll_status nll_set_stream(nll_model* model, void* stream);
+
+/* Attach n_events events: cols[o] is a device array of n_events doubles for
+ * observable o (structure of arrays).  The library borrows the columns until
+ * the next nll_set_data or nll_destroy_model.  Makes one validation pass and
+ * SYNCHRONISES the stream: NLL_ERR_DOMAIN if any value lies outside its
+ * closed observable range or is NaN (the data are then not attached). */
+nll_status nll_set_data(nll_model* model, const double* const* cols, int64_t n_events);
+
+/* Enqueue: NLL at theta (device [n_param]) into *nll_out (device [1]).
+ * A parameter outside its range or an invalid density yields +inf and a
+ * status bit read by nll_sync. */
+nll_status nll_eval(nll_model* model, const double* theta, double* nll_out);
+
+/* Enqueue: NLL and gradient (device [n_param]) from one fused pass. */
+nll_status nll_eval_grad(nll_model* model, const double* theta, double* nll_out, double* grad_out);
+
+/* Enqueue: many datasets in one launch.  Set s holds the attached events
+ * [offsets[s], offsets[s+1]) (device int64 [n_sets+1]) and is evaluated at
+ * theta[s * n_param ...] (device).  nll_out[s] (device), grad_out (device
+ * [n_sets * n_param], NULL for NLL only) and status_out[s] (device, NULL
+ * allowed: an nll_status per set).  The offsets must be non-decreasing
+ * within [0, n_events]; otherwise every set reports NLL_ERR_ARG and +inf. */
+nll_status nll_eval_batched(nll_model* model, int32_t n_sets, const int64_t* offsets, const double* theta,
+                            double* nll_out, double* grad_out, int32_t* status_out);
+
+/* Enqueue: independent gradient-descent fits, one per set, all on the
+ * device.  Each of the n_steps steps evaluates NLL and gradient at the
+ * current proposal of every set in one launch; a proposal is accepted when
+ * its NLL is finite and exceeds the last accepted one by at most 4 ulps
+ * (rounding noise), otherwise that set's step size is halved; the next proposal is
+ * theta_acc - eta * grad_acc / N_s over the free parameters.  theta (device
+ * [n_sets * n_param]) holds the start points on entry and the last accepted
+ * points on completion; nll_out / grad_out / status_out as above (at the
+ * accepted points).  The whole fit is recorded once into a HIP graph and
+ * replayed on later calls with the same arguments. */
+nll_status nll_fit_batched(nll_model* model, int32_t n_sets, const int64_t* offsets, double* theta,
+                           int32_t n_steps, double eta, double* nll_out, double* grad_out, int32_t* status_out);
+
+/* Enqueue: the same fit on all attached events as one dataset. */
+nll_status nll_fit(nll_model* model, double* theta, int32_t n_steps, double eta, double* nll_out,
+                   double* grad_out, int32_t* status_out);
+
+/* Synchronise the model's stream and report (and clear) the errors found on
+ * the device since the last call: NLL_ERR_PARAM_RANGE or NLL_ERR_INVALID_PDF
+ * (also in *status_out if non-NULL), NLL_ERR_DEVICE on a runtime error. */
+nll_status nll_sync(nll_model* model, int32_t* status_out);
+
+/* Launch schedule of the streaming kernels. */
+typedef struct nll_schedule {
+  int32_t unroll;             /* events per thread per tile: 2 or 4        */
+  int32_t blocks_per_cu;      /* persistent grid = CUs * blocks_per_cu     */
+  int32_t tile_events;        /* batched: events per (set, tile) work item */
+  int32_t sets_blocks_per_cu; /* batched: grid = CUs * sets_blocks_per_cu  */
+} nll_schedule;
+
+nll_status nll_get_schedule(const nll_model* model, nll_schedule* out);
+/* Values outside unroll in {2,4}, blocks_per_cu in [1,32],
+ * tile_events in [1024, 1<<22] (multiple of 512), sets_blocks_per_cu in
+ * [1,32] give NLL_ERR_ARG. */
+nll_status nll_set_schedule(nll_model* model, const nll_schedule* sched);
+
+/* Time the candidate schedules on the attached data (synchronises; several
+ * evaluations per candidate), check each candidate's NLL against the
+ * default schedule's, keep the fastest.  which: 1 = single dataset,
+ * 2 = batched with the given sets (n_sets/offsets/theta as in
+ * nll_eval_batched).  Results are cached per model shape, precision and
+ * event-count bucket in the file named by $NLLMI_TUNE_CACHE, if set. */
+nll_status nll_autotune(nll_model* model, int32_t which, int32_t n_sets, const int64_t* offsets,
+                        const double* theta);
+
+typedef struct nll_info {
+  char variant[64];   /* compiled shape the model was lowered onto */
+  int32_t n_leaf, n_term, n_accumulators, precision;
+  int32_t n_cu;
+  int64_t n_events;
+} nll_info;
+nll_status nll_get_info(const nll_model* model, nll_info* out);
+
+const char* nll_status_string(nll_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLLMI_NLL_H */

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -721,7 +722,8 @@ int gd_fit_one(const orc_model& m, const double* const* cols, int64_t n, double*
       trace[s * (np + 1)] = f;
       for (int k = 0; k < np; ++k) trace[s * (np + 1) + 1 + k] = prop[k];
     }
-    bool ok = (st == ORC_OK) && std::isfinite(f) && f <= f_acc;
+    /* an increase of at most 4 ulps of the NLL is rounding noise, not an increase */
+    bool ok = (st == ORC_OK) && std::isfinite(f) && f <= f_acc + 4.0 * DBL_EPSILON * std::fabs(f_acc);
     if (st == ORC_E_DOMAIN) return st;
     if (ok) {
       acc = prop;

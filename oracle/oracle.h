@@ -121,7 +121,8 @@ int orc_nll_batched(const orc_model* m, const double* const* cols,
 
 /* Gradient descent on the mean NLL: proposal theta' = theta_acc -
  * eta * g_acc / N over free parameters; a proposal is accepted when its NLL
- * is finite and not larger than the last accepted one, otherwise eta is
+ * is finite and exceeds the last accepted one by at most 4 ulps (an
+ * increase within rounding noise is not an increase), otherwise eta is
  * halved.  Exactly n_steps evaluations; the first evaluates the start
  * point.  On return theta/nll/grad hold the last accepted point and
  * eta_out the final step size.  trace (may be NULL) receives per step

@@ -1,0 +1,278 @@
+"""nllmi: batched unbinned negative log-likelihoods on AMD MI355X (gfx950).
+
+Thin Python front end of ``libnllmi.so`` (C ABI in ``include/nll.h``):
+argument marshalling only -- every step of the likelihood runs in the HIP
+kernels.  PyTorch provides device memory (tensors) and streams.
+
+    model = Model.from_spec(spec)          # PDF graph (see ``Model.from_spec``)
+    model.set_data([x_tensor])             # SoA float64 columns on the GPU
+    nll, grad = model.eval_grad(theta)     # one fused pass
+    nll = NLL.apply(theta, model)          # autograd: backward uses the same pass
+
+Reference: S. Hageboeck, "A Faster, More Intuitive RooFit" (arXiv:2003.12875):
+the computation graph of Sec. 1, the batched likelihood evaluation of
+Sec. 5, the built-in densities of Sec. 3.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from ._native import (MAX_NODE_CHILDREN, MAX_NODE_PARAMS, NLLError, NodeDesc, ModelDesc, Schedule, Info,
+                      STATUS, check, lib, LIB_PATH)
+
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7}
+NORM = {"analytic": 0, "gl256": 1, "gl256_single": 2}
+PRECISION = {"fp64": 0, "fp32c": 1}
+
+__all__ = ["Model", "NLL", "NLLError", "STATUS", "lib", "LIB_PATH"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_tensor(t, dtype, device):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t, dtype=dtype)
+    if t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if t.device != device:
+        t = t.to(device)
+    return t.contiguous()
+
+
+class Model:
+    """One likelihood model on one device (``nll_model``)."""
+
+    def __init__(self, desc_args: dict, device: int = 0):
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        self.n_param = desc_args["n_param"]
+        self.n_obs = desc_args["n_obs"]
+        self._keep = desc_args["keep"]
+        d = desc_args["desc"]
+        d.device = device
+        d.stream = ctypes.c_void_p(self._stream())
+        handle = ctypes.c_void_p()
+        check(lib().nll_create_model(ctypes.byref(d), ctypes.byref(handle)), "nll_create_model")
+        self._h = handle
+        self._cols = None
+        self.n_events = -1
+
+    # -- construction ------------------------------------------------------
+    @classmethod
+    def from_spec(cls, spec: dict, precision: str = "fp64", device: int = 0) -> "Model":
+        """Build from a graph specification::
+
+            {"obs": [{"name", "lo", "hi"}...],
+             "params": [{"name", "value", "lo", "hi", "free"}...],
+             "nodes": [{"kind": "gauss"|"exp"|"cheb"|"cb"|"argus"|"sum"|"prod",
+                        "obs": int, "params": [...], "children": [...],
+                        "norm": "analytic"|"gl256"|"gl256_single"}...],
+             "root": int, "extended": bool, "yield_param": int}
+        """
+        obs, params, nodes = spec["obs"], spec["params"], spec["nodes"]
+        n_obs, n_param, n_node = len(obs), len(params), len(nodes)
+        lo = (ctypes.c_double * n_obs)(*[float(o["lo"]) for o in obs])
+        hi = (ctypes.c_double * n_obs)(*[float(o["hi"]) for o in obs])
+        plo = (ctypes.c_double * n_param)(*[float(p["lo"]) for p in params])
+        phi = (ctypes.c_double * n_param)(*[float(p["hi"]) for p in params])
+        pfree = (ctypes.c_uint8 * n_param)(*[1 if p.get("free", True) else 0 for p in params])
+        nd = (NodeDesc * n_node)()
+        for i, n in enumerate(nodes):
+            ps, cs = list(n.get("params", [])), list(n.get("children", []))
+            if len(ps) > MAX_NODE_PARAMS or len(cs) > MAX_NODE_CHILDREN:
+                raise NLLError(-1, "node has too many parameters or children")
+            nd[i].kind = KIND[n["kind"]]
+            nd[i].obs = int(n.get("obs", -1))
+            nd[i].n_param = len(ps)
+            nd[i].n_child = len(cs)
+            for j, v in enumerate(ps):
+                nd[i].param[j] = int(v)
+            for j, v in enumerate(cs):
+                nd[i].child[j] = int(v)
+            nd[i].norm = NORM[n.get("norm", "analytic")]
+        d = ModelDesc()
+        d.n_obs, d.obs_lo, d.obs_hi = n_obs, lo, hi
+        d.n_param, d.param_lo, d.param_hi, d.param_free = n_param, plo, phi, pfree
+        d.n_node, d.nodes, d.root = n_node, nd, int(spec["root"])
+        d.precision = PRECISION[precision]
+        d.extended = 1 if spec.get("extended", False) else 0
+        d.yield_param = int(spec.get("yield_param", -1)) if spec.get("extended", False) else 0
+        return cls({"desc": d, "n_param": n_param, "n_obs": n_obs, "keep": (lo, hi, plo, phi, pfree, nd)},
+                   device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().nll_destroy_model(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -------------------------------------------------------------
+    def _stream(self) -> int:
+        return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def _bind_stream(self):
+        check(lib().nll_set_stream(self._h, ctypes.c_void_p(self._stream())), "nll_set_stream")
+
+    # -- data ----------------------------------------------------------------
+    def set_data(self, cols):
+        """Attach SoA float64 event columns (device tensors, one per
+        observable).  Validates every event against the observable ranges."""
+        torch = _torch()
+        cols = [_dev_tensor(c, torch.float64, self.device) for c in cols]
+        if len(cols) != self.n_obs or len({c.numel() for c in cols}) != 1:
+            raise NLLError(-1, "one column of equal length per observable required")
+        n = cols[0].numel()
+        arr = (ctypes.c_void_p * 4)(*[c.data_ptr() for c in cols])
+        self._bind_stream()
+        check(lib().nll_set_data(self._h, arr, ctypes.c_int64(n)), "nll_set_data")
+        self._cols = cols
+        self.n_events = n
+
+    # -- evaluation ------------------------------------------------------------
+    def eval(self, theta, out=None):
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        self._bind_stream()
+        check(lib().nll_eval(self._h, _ptr(theta), _ptr(out)), "nll_eval")
+        return out
+
+    def eval_grad(self, theta, out=None, grad=None):
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        grad = torch.empty(self.n_param, dtype=torch.float64, device=self.device) if grad is None else grad
+        self._bind_stream()
+        check(lib().nll_eval_grad(self._h, _ptr(theta), _ptr(out), _ptr(grad)), "nll_eval_grad")
+        return out, grad
+
+    def eval_batched(self, offsets, theta, grad: bool = True):
+        torch = _torch()
+        offsets = _dev_tensor(offsets, torch.int64, self.device)
+        n_sets = offsets.numel() - 1
+        theta = _dev_tensor(theta, torch.float64, self.device).reshape(n_sets, self.n_param).contiguous()
+        nll = torch.empty(n_sets, dtype=torch.float64, device=self.device)
+        g = torch.empty(n_sets, self.n_param, dtype=torch.float64, device=self.device) if grad else None
+        status = torch.empty(n_sets, dtype=torch.int32, device=self.device)
+        self._bind_stream()
+        check(lib().nll_eval_batched(self._h, n_sets, _ptr(offsets), _ptr(theta), _ptr(nll), _ptr(g), _ptr(status)),
+              "nll_eval_batched")
+        return nll, g, status
+
+    def fit_batched(self, offsets, theta, n_steps: int, eta: float = 1.0, out=None):
+        """Gradient-descent fits of every set (see nll_fit_batched).  Returns
+        (theta, nll, grad, status) at the last accepted points."""
+        torch = _torch()
+        offsets = _dev_tensor(offsets, torch.int64, self.device)
+        n_sets = offsets.numel() - 1
+        if out is None:
+            th = _dev_tensor(theta, torch.float64, self.device).reshape(n_sets, self.n_param).clone()
+            nll = torch.empty(n_sets, dtype=torch.float64, device=self.device)
+            g = torch.empty(n_sets, self.n_param, dtype=torch.float64, device=self.device)
+            status = torch.empty(n_sets, dtype=torch.int32, device=self.device)
+        else:
+            th, nll, g, status = out
+            th.copy_(_dev_tensor(theta, torch.float64, self.device).reshape(n_sets, self.n_param))
+        self._bind_stream()
+        check(lib().nll_fit_batched(self._h, n_sets, _ptr(offsets), _ptr(th), int(n_steps), float(eta), _ptr(nll),
+                                    _ptr(g), _ptr(status)), "nll_fit_batched")
+        return th, nll, g, status
+
+    def fit(self, theta, n_steps: int, eta: float = 1.0):
+        torch = _torch()
+        th = _dev_tensor(theta, torch.float64, self.device).clone()
+        nll = torch.empty(1, dtype=torch.float64, device=self.device)
+        g = torch.empty(self.n_param, dtype=torch.float64, device=self.device)
+        status = torch.empty(1, dtype=torch.int32, device=self.device)
+        self._bind_stream()
+        check(lib().nll_fit(self._h, _ptr(th), int(n_steps), float(eta), _ptr(nll), _ptr(g), _ptr(status)), "nll_fit")
+        return th, nll, g, status
+
+    def sync(self) -> int:
+        """Synchronise and return (and clear) the device status (0 = ok)."""
+        st = ctypes.c_int32(0)
+        self._bind_stream()
+        lib().nll_sync(self._h, ctypes.byref(st))
+        return st.value
+
+    # -- schedule / info -------------------------------------------------------
+    @property
+    def schedule(self) -> dict:
+        s = Schedule()
+        check(lib().nll_get_schedule(self._h, ctypes.byref(s)), "nll_get_schedule")
+        return {"unroll": s.unroll, "blocks_per_cu": s.blocks_per_cu, "tile_events": s.tile_events,
+                "sets_blocks_per_cu": s.sets_blocks_per_cu}
+
+    def set_schedule(self, **kw):
+        cur = self.schedule
+        cur.update(kw)
+        s = Schedule(cur["unroll"], cur["blocks_per_cu"], cur["tile_events"], cur["sets_blocks_per_cu"])
+        check(lib().nll_set_schedule(self._h, ctypes.byref(s)), "nll_set_schedule")
+
+    def autotune(self, theta, offsets=None):
+        torch = _torch()
+        self._bind_stream()
+        if offsets is None:
+            theta = _dev_tensor(theta, torch.float64, self.device)
+            check(lib().nll_autotune(self._h, 1, 0, None, _ptr(theta)), "nll_autotune")
+        else:
+            offsets = _dev_tensor(offsets, torch.int64, self.device)
+            n_sets = offsets.numel() - 1
+            theta = _dev_tensor(theta, torch.float64, self.device).reshape(n_sets, self.n_param).contiguous()
+            check(lib().nll_autotune(self._h, 2, n_sets, _ptr(offsets), _ptr(theta)), "nll_autotune")
+        return self.schedule
+
+    @property
+    def info(self) -> dict:
+        i = Info()
+        check(lib().nll_get_info(self._h, ctypes.byref(i)), "nll_get_info")
+        return {"variant": i.variant.decode(), "n_leaf": i.n_leaf, "n_term": i.n_term,
+                "n_accumulators": i.n_accumulators, "precision": i.precision, "n_cu": i.n_cu,
+                "n_events": i.n_events}
+
+
+def _nll_function():
+    torch = _torch()
+
+    class _NLL(torch.autograd.Function):
+        """NLL(theta) with the analytic gradient of the same fused pass:
+        forward calls nll_eval_grad and keeps the gradient; backward scales it."""
+
+        @staticmethod
+        def forward(ctx, theta, model):
+            nll, grad = model.eval_grad(theta.detach())
+            ctx.save_for_backward(grad)
+            return nll[0]
+
+        @staticmethod
+        def backward(ctx, g):
+            (grad,) = ctx.saved_tensors
+            return g * grad, None
+
+    return _NLL
+
+
+class _LazyNLL:
+    _fn = None
+
+    def apply(self, theta, model):
+        if _LazyNLL._fn is None:
+            _LazyNLL._fn = _nll_function()
+        return _LazyNLL._fn.apply(theta, model)
+
+
+NLL = _LazyNLL()

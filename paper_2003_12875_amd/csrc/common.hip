@@ -1,0 +1,101 @@
+// common.hip -- model-independent kernels: dataset validation, the tile
+// schedule of the batched pass, and the read-out of a batched fit.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace nllmi {
+
+// Item counts per set and their exclusive prefix.  The offsets must be
+// non-decreasing within [0, n_total]; if any is not, every set of the batch
+// is flagged (status NLL_ERR_ARG) and gets one empty item, so the number of
+// items never exceeds n_total / tile + n_sets.
+__global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__ offsets, int n_sets,
+                                                     int64_t n_total, int64_t tile,
+                                                     int64_t* __restrict__ tile_off,
+                                                     int* __restrict__ set_flag) {
+  __shared__ int64_t scan[kBlock];
+  __shared__ int any_bad;
+  const int t = threadIdx.x;
+  if (t == 0) any_bad = 0;
+  __syncthreads();
+  const int per = (n_sets + kBlock - 1) / kBlock;
+  const int s0 = min(n_sets, t * per), s1 = min(n_sets, s0 + per);
+  for (int s = s0; s < s1; ++s) {
+    const int64_t a = offsets[s], b = offsets[s + 1];
+    if (!(a >= 0 && b >= a && b <= n_total)) atomicOr(&any_bad, 1);
+  }
+  __syncthreads();
+  const int bad = any_bad;
+  int64_t local = 0;
+  for (int s = s0; s < s1; ++s) {
+    set_flag[s] = bad;
+    const int64_t len = bad ? 0 : offsets[s + 1] - offsets[s];
+    local += len > 0 ? (len + tile - 1) / tile : 1;
+  }
+  scan[t] = local;
+  __syncthreads();
+  for (int d = 1; d < kBlock; d <<= 1) {
+    const int64_t v = t >= d ? scan[t - d] : 0;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  int64_t run = scan[t] - local;  // exclusive prefix
+  for (int s = s0; s < s1; ++s) {
+    tile_off[s] = run;
+    const int64_t len = bad ? 0 : offsets[s + 1] - offsets[s];
+    run += len > 0 ? (len + tile - 1) / tile : 1;
+  }
+  if (t == kBlock - 1) tile_off[n_sets] = scan[kBlock - 1];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fit_final(int n_sets, int P, GDState gd, double* theta_out,
+                                                     double* nll_out, double* grad_out,
+                                                     int* status_out) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= n_sets) return;
+  for (int q = 0; q < P; ++q) {
+    theta_out[(size_t)s * P + q] = gd.th_acc[(size_t)s * P + q];
+    if (grad_out) grad_out[(size_t)s * P + q] = gd.g_acc[(size_t)s * P + q];
+  }
+  const double f = gd.f_acc[s];
+  if (nll_out) nll_out[s] = f;
+  if (status_out) status_out[s] = __builtin_isfinite(f) ? 0 : gd.last_status[s];
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_range(const double* __restrict__ x, int64_t n,
+                                                       double lo, double hi,
+                                                       unsigned long long* __restrict__ bad) {
+  unsigned long long local = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const double v = x[i];
+    local += !(v >= lo && v <= hi);
+  }
+  if (local) atomicAdd(bad, local);
+}
+
+hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
+                           int64_t* tile_off, int* set_flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kBlock), 0, st, offsets, n_sets, n_total, tile, tile_off, set_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_out, double* nll_out,
+                            double* grad_out, int* status_out, hipStream_t st) {
+  const int grid = (n_sets + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_fit_final, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, st, n_sets, P, gd, theta_out,
+                     nll_out, grad_out, status_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, unsigned long long* bad,
+                              hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_check_range, dim3((unsigned)blocks), dim3(kBlock), 0, st, x, n, lo, hi, bad);
+  return hipGetLastError();
+}
+
+}  // namespace nllmi

@@ -1,0 +1,684 @@
+// host.cpp -- the C ABI of libnllmi: model validation, lowering of the
+// graph onto a compiled kernel shape, device scratch, launches, the
+// recorded HIP graph of a batched fit, status reporting.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "nll.h"
+#include "plan.h"
+#include "runtime.h"
+
+using namespace nllmi;
+
+// ---------------------------------------------------------------------------
+// registry of compiled shapes, per-device Gauss-Legendre tables
+// ---------------------------------------------------------------------------
+static const std::vector<VariantOps>& registry() {
+  static std::vector<VariantOps> reg;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    register_variants_single(reg);
+    register_variants_mixture(reg);
+    register_variants_2d(reg);
+  });
+  return reg;
+}
+
+static nll_status gl_table(int device, GLTable* out) {
+  static std::mutex mu;
+  static std::map<int, GLTable> tables;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = tables.find(device);
+  if (it != tables.end()) {
+    *out = it->second;
+    return NLL_OK;
+  }
+  double hx[256], hw[256];
+  gauss_legendre(256, hx, hw);
+  GLTable t;
+  if (hipMalloc(&t.x, sizeof(hx)) != hipSuccess || hipMalloc(&t.w, sizeof(hw)) != hipSuccess)
+    return NLL_ERR_OOM;
+  if (hipMemcpy(t.x, hx, sizeof(hx), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.w, hw, sizeof(hw), hipMemcpyHostToDevice) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  tables[device] = t;
+  *out = t;
+  return NLL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the model object
+// ---------------------------------------------------------------------------
+namespace {
+
+nll_status dev_err(hipError_t e) {
+  if (e == hipSuccess) return NLL_OK;
+  return e == hipErrorOutOfMemory ? NLL_ERR_OOM : NLL_ERR_DEVICE;
+}
+
+template <class T>
+nll_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return dev_err(hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)));
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int expected_params(int kind, int np) {
+  switch (kind) {
+    case NLL_GAUSS: return 2;
+    case NLL_EXP: return 1;
+    case NLL_CHEB: return (np >= 1 && np <= 8) ? np : -1;
+    case NLL_CB: return 4;
+    case NLL_ARGUS: return 2;
+    default: return -1;
+  }
+}
+
+bool is_leaf(int kind) { return kind >= NLL_GAUSS && kind <= NLL_ARGUS; }
+
+// ---------------------------------------------------------------------------
+// lowering: graph -> sum of products of leaves
+// ---------------------------------------------------------------------------
+struct Term {
+  uint32_t mask = 0;                       // leaves (by position in `leaves`)
+  std::vector<std::pair<int, int>> refs;   // (sum position, child index)
+};
+
+struct Lowering {
+  const nll_model_desc* d = nullptr;
+  std::vector<int> leaves, sums;   // node indices, in node order
+  std::vector<int> leaf_pos, sum_pos;
+  std::vector<unsigned> obs_mask;  // per node
+
+  nll_status validate() {
+    const nll_model_desc& D = *d;
+    if (D.n_obs < 1 || D.n_obs > NLL_MAX_OBS || !D.obs_lo || !D.obs_hi) return NLL_ERR_ARG;
+    if (D.n_param < 1 || D.n_param > NLL_MAX_PARAMS || !D.param_lo || !D.param_hi) return NLL_ERR_ARG;
+    if (D.n_node < 1 || D.n_node > NLL_MAX_NODES || !D.nodes) return NLL_ERR_ARG;
+    if (D.root < 0 || D.root >= D.n_node) return NLL_ERR_ARG;
+    if (D.precision != NLL_FP64 && D.precision != NLL_FP32C) return NLL_ERR_ARG;
+    for (int o = 0; o < D.n_obs; ++o)
+      if (!(std::isfinite(D.obs_lo[o]) && std::isfinite(D.obs_hi[o]) && D.obs_lo[o] < D.obs_hi[o])) return NLL_ERR_ARG;
+    for (int k = 0; k < D.n_param; ++k)
+      if (!(D.param_lo[k] <= D.param_hi[k])) return NLL_ERR_ARG;
+    if (D.extended && (D.yield_param < 0 || D.yield_param >= D.n_param)) return NLL_ERR_ARG;
+    obs_mask.assign(D.n_node, 0u);
+    for (int i = 0; i < D.n_node; ++i) {
+      const nll_node_desc& nd = D.nodes[i];
+      if (nd.n_param < 0 || nd.n_param > NLL_NODE_MAX_PARAMS) return NLL_ERR_ARG;
+      if (nd.n_child < 0 || nd.n_child > NLL_NODE_MAX_CHILDREN) return NLL_ERR_ARG;
+      for (int k = 0; k < nd.n_param; ++k)
+        if (nd.param[k] < 0 || nd.param[k] >= D.n_param) return NLL_ERR_ARG;
+      if (is_leaf(nd.kind)) {
+        if (nd.obs < 0 || nd.obs >= D.n_obs || nd.n_child != 0) return NLL_ERR_ARG;
+        if (expected_params(nd.kind, nd.n_param) != nd.n_param) return NLL_ERR_ARG;
+        if (nd.norm < NLL_NORM_ANALYTIC || nd.norm > NLL_NORM_GL256_SINGLE) return NLL_ERR_ARG;
+        if (nd.kind == NLL_ARGUS && D.obs_lo[nd.obs] < 0.0) return NLL_ERR_UNSUPPORTED;
+        obs_mask[i] = 1u << nd.obs;
+      } else if (nd.kind == NLL_SUM || nd.kind == NLL_PROD) {
+        if (nd.kind == NLL_SUM && (nd.n_child < 2 || nd.n_param != nd.n_child - 1)) return NLL_ERR_ARG;
+        if (nd.kind == NLL_PROD && (nd.n_child < 1 || nd.n_param != 0)) return NLL_ERR_ARG;
+        unsigned acc = 0;
+        for (int j = 0; j < nd.n_child; ++j) {
+          const int c = nd.child[j];
+          if (c < 0 || c >= i) return NLL_ERR_ARG;  // topological order
+          if (nd.kind == NLL_SUM) {
+            if (j > 0 && obs_mask[c] != acc) return NLL_ERR_ARG;  // same observables
+            acc = obs_mask[c];
+          } else {
+            if (obs_mask[c] & acc) return NLL_ERR_ARG;  // disjoint observables
+            acc |= obs_mask[c];
+          }
+        }
+        obs_mask[i] = acc;
+      } else {
+        return NLL_ERR_ARG;
+      }
+    }
+    if (obs_mask[D.root] != (1u << D.n_obs) - 1u) return NLL_ERR_ARG;  // every observable used
+    return NLL_OK;
+  }
+
+  void collect(int i, std::vector<char>& seen) {
+    if (seen[i]) return;
+    seen[i] = 1;
+    const nll_node_desc& nd = d->nodes[i];
+    for (int j = 0; j < nd.n_child; ++j) collect(nd.child[j], seen);
+  }
+
+  std::vector<Term> expand(int i) {
+    const nll_node_desc& nd = d->nodes[i];
+    if (is_leaf(nd.kind)) return {Term{1u << leaf_pos[i], {}}};
+    std::vector<Term> out;
+    if (nd.kind == NLL_SUM) {
+      for (int j = 0; j < nd.n_child; ++j)
+        for (Term t : expand(nd.child[j])) {
+          t.refs.push_back({sum_pos[i], j});
+          out.push_back(t);
+        }
+      return out;
+    }
+    out.push_back(Term{});
+    for (int j = 0; j < nd.n_child; ++j) {
+      std::vector<Term> next;
+      for (const Term& a : out)
+        for (const Term& b : expand(nd.child[j])) {
+          Term t = a;
+          t.mask |= b.mask;
+          t.refs.insert(t.refs.end(), b.refs.begin(), b.refs.end());
+          next.push_back(t);
+        }
+      out.swap(next);
+    }
+    return out;
+  }
+};
+
+// Match the lowered leaves against a compiled shape: perm[slot] = leaf.
+bool match_variant(const VariantOps& v, const std::vector<int>& kind, const std::vector<int>& obs,
+                   const std::vector<int>& root, const std::vector<int>& np, int K, int n_obs, int precision,
+                   std::vector<int>& perm) {
+  const int L = (int)kind.size();
+  if (v.n_leaf != L || v.K != K || v.nobs != n_obs || v.precision != precision) return false;
+  std::vector<int> p(L);
+  for (int i = 0; i < L; ++i) p[i] = i;
+  do {
+    bool ok = true;
+    for (int s = 0; s < L && ok; ++s) {
+      const int l = p[s];
+      ok = v.kind[s] == kind[l] && v.obs[s] == obs[l] && v.root[s] == root[l] && v.np[s] == np[l];
+    }
+    if (ok) {
+      perm = p;
+      return true;
+    }
+  } while (std::next_permutation(p.begin(), p.end()));
+  return false;
+}
+
+nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_out) {
+  Lowering lw;
+  lw.d = &D;
+  nll_status st = lw.validate();
+  if (st != NLL_OK) return st;
+  std::vector<char> seen(D.n_node, 0);
+  lw.collect(D.root, seen);
+  lw.leaf_pos.assign(D.n_node, -1);
+  lw.sum_pos.assign(D.n_node, -1);
+  for (int i = 0; i < D.n_node; ++i) {
+    if (!seen[i]) continue;
+    if (is_leaf(D.nodes[i].kind)) {
+      lw.leaf_pos[i] = (int)lw.leaves.size();
+      lw.leaves.push_back(i);
+    } else if (D.nodes[i].kind == NLL_SUM) {
+      lw.sum_pos[i] = (int)lw.sums.size();
+      lw.sums.push_back(i);
+    }
+  }
+  const int L = (int)lw.leaves.size();
+  if (L > kMaxLeaves || (int)lw.sums.size() > kMaxSums) return NLL_ERR_UNSUPPORTED;
+  std::vector<Term> terms = lw.expand(D.root);
+  const int K = (int)terms.size();
+  if (K > kMaxTerms) return NLL_ERR_UNSUPPORTED;
+  for (const Term& t : terms)
+    if ((int)t.refs.size() > kMaxPathRefs) return NLL_ERR_UNSUPPORTED;
+
+  std::vector<int> kind(L), obs(L), root(L), np(L);
+  for (int l = 0; l < L; ++l) {
+    const nll_node_desc& nd = D.nodes[lw.leaves[l]];
+    kind[l] = nd.kind;
+    obs[l] = nd.obs;
+    np[l] = nd.n_param;
+    bool all = true;
+    for (const Term& t : terms) all = all && ((t.mask >> l) & 1u);
+    root[l] = all ? 1 : 0;
+  }
+  std::vector<int> perm;
+  const VariantOps* found = nullptr;
+  for (const VariantOps& v : registry()) {
+    if (match_variant(v, kind, obs, root, np, K, D.n_obs, D.precision, perm)) {
+      found = &v;
+      break;
+    }
+  }
+  if (!found) return NLL_ERR_UNSUPPORTED;
+
+  std::memset(&pl, 0, sizeof(pl));
+  pl.n_obs = D.n_obs;
+  for (int o = 0; o < D.n_obs; ++o) {
+    pl.lo[o] = D.obs_lo[o];
+    pl.hi[o] = D.obs_hi[o];
+  }
+  pl.n_param = D.n_param;
+  for (int k = 0; k < D.n_param; ++k) {
+    pl.par_lo[k] = D.param_lo[k];
+    pl.par_hi[k] = D.param_hi[k];
+    pl.par_free[k] = D.param_free ? (D.param_free[k] ? 1 : 0) : 1;
+  }
+  std::vector<int> slot_of(L);
+  pl.n_leaf = L;
+  for (int s = 0; s < L; ++s) {
+    const int l = perm[s];
+    slot_of[l] = s;
+    const nll_node_desc& nd = D.nodes[lw.leaves[l]];
+    pl.leaf_kind[s] = nd.kind;
+    pl.leaf_obs[s] = nd.obs;
+    pl.leaf_np[s] = nd.n_param;
+    for (int p = 0; p < nd.n_param; ++p) pl.leaf_param[s][p] = nd.param[p];
+    pl.leaf_norm[s] = nd.norm;
+    pl.leaf_root[s] = root[l];
+  }
+  pl.n_term = K;
+  for (int k = 0; k < K; ++k) {
+    uint32_t m = 0;
+    for (int l = 0; l < L; ++l)
+      if (((terms[k].mask >> l) & 1u) && !root[l]) m |= 1u << slot_of[l];
+    pl.term_mask[k] = (int32_t)m;
+    pl.term_nref[k] = (int32_t)terms[k].refs.size();
+    for (size_t r = 0; r < terms[k].refs.size(); ++r) {
+      pl.term_ref_sum[k][r] = terms[k].refs[r].first;
+      pl.term_ref_child[k][r] = terms[k].refs[r].second;
+    }
+  }
+  pl.n_sum = (int)lw.sums.size();
+  for (int q = 0; q < pl.n_sum; ++q) {
+    const nll_node_desc& nd = D.nodes[lw.sums[q]];
+    pl.sum_nchild[q] = nd.n_child;
+    for (int j = 0; j < nd.n_param; ++j) pl.sum_param[q][j] = nd.param[j];
+  }
+  pl.acc_term_base = 1;
+  int base = 1 + (K > 1 ? K : 0);
+  for (int s = 0; s < L; ++s) {
+    pl.acc_leaf_base[s] = base;
+    base += pl.leaf_np[s];
+  }
+  pl.n_acc = found->na_grad;
+  pl.extended = D.extended ? 1 : 0;
+  pl.yield_param = D.extended ? D.yield_param : 0;
+  *ops_out = found;
+  return NLL_OK;
+}
+
+int tile_events(const nll_model* m) { return m->sched.unroll * kBlock; }
+
+int single_grid(const nll_model* m) {
+  const int64_t tiles = m->n > 0 ? (m->n + tile_events(m) - 1) / tile_events(m) : 1;
+  int64_t g = (int64_t)m->n_cu * m->sched.blocks_per_cu;
+  if (g > tiles) g = tiles;
+  return (int)std::max<int64_t>(1, g);
+}
+
+nll_status ensure_sets(nll_model* m, int n_sets) {
+  if (n_sets > m->sets_cap) {
+    dfree(m->tile_off);
+    dfree(m->set_flag);
+    dfree(m->consts);
+    m->sets_cap = 0;
+    int cap = std::max(n_sets, 64);
+    nll_status st;
+    if ((st = dalloc(&m->tile_off, (size_t)cap + 1)) != NLL_OK) return st;
+    if ((st = dalloc(&m->set_flag, (size_t)cap)) != NLL_OK) return st;
+    if ((st = dalloc(&m->consts, (size_t)cap)) != NLL_OK) return st;
+    m->sets_cap = cap;
+    m->have_graph = false;
+  }
+  const int64_t tile = m->sched.tile_events;
+  const int64_t items = (m->n > 0 ? m->n / tile : 0) + n_sets + 1;
+  const size_t need = (size_t)items * (size_t)(m->ops->na_grad + 1) * 2 * sizeof(double);
+  if (need > m->set_partials_cap) {
+    dfree(m->set_partials);
+    m->set_partials_cap = 0;
+    nll_status st = dalloc(reinterpret_cast<char**>(&m->set_partials), need);
+    if (st != NLL_OK) return st;
+    m->set_partials_cap = need;
+    m->have_graph = false;
+  }
+  return NLL_OK;
+}
+
+nll_status ensure_gd(nll_model* m, int n_sets) {
+  if (n_sets <= m->gd_cap) return NLL_OK;
+  dfree(m->gd_mem);
+  dfree(m->gd_status);
+  m->gd_cap = 0;
+  const size_t P = (size_t)m->plan.n_param;
+  nll_status st;
+  if ((st = dalloc(&m->gd_mem, (size_t)n_sets * (3 * P + 2))) != NLL_OK) return st;
+  if ((st = dalloc(&m->gd_status, (size_t)n_sets)) != NLL_OK) return st;
+  m->gd_cap = n_sets;
+  m->have_graph = false;
+  return NLL_OK;
+}
+
+GDState gd_state(const nll_model* m) {
+  const size_t P = (size_t)m->plan.n_param, S = (size_t)m->gd_cap;
+  GDState g;
+  g.th_acc = m->gd_mem;
+  g.g_acc = m->gd_mem + S * P;
+  g.th_prop = m->gd_mem + 2 * S * P;
+  g.f_acc = m->gd_mem + 3 * S * P;
+  g.eta = m->gd_mem + 3 * S * P + S;
+  g.last_status = m->gd_status;
+  return g;
+}
+
+SetsArgs sets_args(const nll_model* m, int n_sets, const int64_t* offsets) {
+  SetsArgs a{};
+  for (int o = 0; o < kMaxObs; ++o) a.cols[o] = m->cols[o];
+  a.n_sets = n_sets;
+  a.offsets = offsets;
+  a.tile = m->sched.tile_events;
+  a.tile_off = m->tile_off;
+  a.set_flag = m->set_flag;
+  a.consts = m->consts;
+  a.partials = m->set_partials;
+  a.glx = m->gl.x;
+  a.glw = m->gl.w;
+  return a;
+}
+
+int sets_grid(const nll_model* m) { return std::max(1, m->n_cu * m->sched.sets_blocks_per_cu); }
+
+// enqueue a whole fit on stream st
+nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* offsets, double* theta,
+                       int n_steps, double eta, double* nll_out, double* grad_out, int32_t* status_out) {
+  GDState gd = gd_state(m);
+  SetsArgs a = sets_args(m, n_sets, offsets);
+  a.gd = gd;
+  hipError_t e = launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, st);
+  if (e != hipSuccess) return NLL_ERR_DEVICE;
+  e = m->ops->fit_init(m->plan, theta, n_sets, eta, gd, m->consts, m->gl.x, m->gl.w, st);
+  if (e != hipSuccess) return NLL_ERR_DEVICE;
+  for (int s = 0; s < n_steps; ++s) {
+    e = m->ops->sets(m->plan, a, true, true, sets_grid(m), st);
+    if (e != hipSuccess) return NLL_ERR_DEVICE;
+  }
+  e = launch_fit_final(n_sets, m->plan.n_param, gd, theta, nll_out, grad_out, reinterpret_cast<int*>(status_out), st);
+  return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* nll_status_string(nll_status s) {
+  switch (s) {
+    case NLL_OK: return "ok";
+    case NLL_ERR_ARG: return "invalid argument";
+    case NLL_ERR_UNSUPPORTED: return "model shape not supported by the compiled kernels";
+    case NLL_ERR_PARAM_RANGE: return "parameter outside its allowed range";
+    case NLL_ERR_DOMAIN: return "event outside the observable range";
+    case NLL_ERR_INVALID_PDF: return "probability density <= 0 or not finite";
+    case NLL_ERR_DEVICE: return "HIP runtime error";
+    case NLL_ERR_OOM: return "out of device memory";
+    case NLL_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+nll_status nll_create_model(const nll_model_desc* desc, nll_model** out) {
+  if (!desc || !out) return NLL_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return NLL_ERR_DEVICE;
+  if (desc->device < 0 || desc->device >= ndev) return NLL_ERR_ARG;
+  Plan pl;
+  const VariantOps* ops = nullptr;
+  nll_status st = build_plan(*desc, pl, &ops);
+  if (st != NLL_OK) return st;
+
+  DeviceGuard guard(desc->device);
+  nll_model* m = new (std::nothrow) nll_model();
+  if (!m) return NLL_ERR_OOM;
+  m->device = desc->device;
+  m->stream = reinterpret_cast<hipStream_t>(desc->stream);
+  m->plan = pl;
+  m->ops = ops;
+  m->precision = desc->precision;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess && cus > 0)
+    m->n_cu = cus;
+  auto fail = [&](nll_status s) {
+    nll_destroy_model(m);
+    return s;
+  };
+  if ((st = gl_table(m->device, &m->gl)) != NLL_OK) return fail(st);
+  const size_t max_grid = (size_t)m->n_cu * 32;
+  if ((st = dalloc(&m->partials, max_grid * (size_t)(ops->na_grad + 1) * 2)) != NLL_OK) return fail(st);
+  if ((st = dalloc(&m->ticket, 1)) != NLL_OK) return fail(st);
+  if ((st = dalloc(&m->status, 1)) != NLL_OK) return fail(st);
+  if ((st = dalloc(&m->dbad, 1)) != NLL_OK) return fail(st);
+  if ((st = dalloc(&m->offsets1, 2)) != NLL_OK) return fail(st);
+  if (hipMemset(m->ticket, 0, sizeof(int)) != hipSuccess || hipMemset(m->status, 0, sizeof(int)) != hipSuccess)
+    return fail(NLL_ERR_DEVICE);
+  if (hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking) != hipSuccess) return fail(NLL_ERR_DEVICE);
+  *out = m;
+  return NLL_OK;
+}
+
+void nll_destroy_model(nll_model* m) {
+  if (!m) return;
+  DeviceGuard guard(m->device);
+  (void)hipStreamSynchronize(m->stream);
+  if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->capture) (void)hipStreamDestroy(m->capture);
+  dfree(m->partials);
+  dfree(m->ticket);
+  dfree(m->status);
+  dfree(m->dbad);
+  dfree(m->offsets1);
+  dfree(m->tile_off);
+  dfree(m->set_flag);
+  dfree(m->consts);
+  dfree(m->set_partials);
+  dfree(m->gd_mem);
+  dfree(m->gd_status);
+  delete m;
+}
+
+nll_status nll_set_stream(nll_model* m, void* stream) {
+  if (!m) return NLL_ERR_ARG;
+  m->stream = reinterpret_cast<hipStream_t>(stream);
+  return NLL_OK;
+}
+
+nll_status nll_set_data(nll_model* m, const double* const* cols, int64_t n_events) {
+  if (!m || n_events < 0 || (n_events > 0 && !cols)) return NLL_ERR_ARG;
+  for (int o = 0; o < m->plan.n_obs && n_events > 0; ++o)
+    if (!cols[o] || (reinterpret_cast<uintptr_t>(cols[o]) & 7u)) return NLL_ERR_ARG;
+  DeviceGuard guard(m->device);
+  unsigned long long bad = 0;
+  for (int o = 0; o < m->plan.n_obs && n_events > 0; ++o) {
+    if (hipMemsetAsync(m->dbad, 0, sizeof(unsigned long long), m->stream) != hipSuccess) return NLL_ERR_DEVICE;
+    if (launch_check_range(cols[o], n_events, m->plan.lo[o], m->plan.hi[o], m->dbad, m->stream) != hipSuccess)
+      return NLL_ERR_DEVICE;
+    unsigned long long b = 0;
+    if (hipMemcpyAsync(&b, m->dbad, sizeof(b), hipMemcpyDeviceToHost, m->stream) != hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess)
+      return NLL_ERR_DEVICE;
+    bad += b;
+  }
+  if (bad) return NLL_ERR_DOMAIN;
+  for (int o = 0; o < kMaxObs; ++o) m->cols[o] = (o < m->plan.n_obs && n_events > 0) ? cols[o] : nullptr;
+  m->n = n_events;
+  const int64_t off[2] = {0, n_events};
+  if (hipMemcpy(m->offsets1, off, sizeof(off), hipMemcpyHostToDevice) != hipSuccess) return NLL_ERR_DEVICE;
+  m->have_graph = false;
+  return NLL_OK;
+}
+
+static nll_status nll_eval_impl(nll_model* m, const double* theta, double* nll_out, double* grad_out, bool grad) {
+  if (!m || !theta || !nll_out || (grad && !grad_out)) return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  DeviceGuard guard(m->device);
+  SingleArgs a{};
+  for (int o = 0; o < kMaxObs; ++o) a.cols[o] = m->cols[o];
+  a.n = m->n;
+  a.theta = theta;
+  a.nll_out = nll_out;
+  a.grad_out = grad_out;
+  a.partials = m->partials;
+  a.ticket = m->ticket;
+  a.status = m->status;
+  a.glx = m->gl.x;
+  a.glw = m->gl.w;
+  hipError_t e = m->ops->single(m->plan, a, grad, m->sched.unroll, single_grid(m), m->stream);
+  return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+}
+
+nll_status nll_eval(nll_model* m, const double* theta, double* nll_out) {
+  return nll_eval_impl(m, theta, nll_out, nullptr, false);
+}
+
+nll_status nll_eval_grad(nll_model* m, const double* theta, double* nll_out, double* grad_out) {
+  return nll_eval_impl(m, theta, nll_out, grad_out, true);
+}
+
+nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets, const double* theta,
+                            double* nll_out, double* grad_out, int32_t* status_out) {
+  if (!m || n_sets < 0 || (n_sets > 0 && (!offsets || !theta || !nll_out))) return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  if (n_sets == 0) return NLL_OK;
+  DeviceGuard guard(m->device);
+  nll_status st = ensure_sets(m, n_sets);
+  if (st != NLL_OK) return st;
+  const bool grad = grad_out != nullptr;
+  SetsArgs a = sets_args(m, n_sets, offsets);
+  a.theta = theta;
+  a.nll_out = nll_out;
+  a.grad_out = grad_out;
+  a.status_out = reinterpret_cast<int*>(status_out);
+  if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->stream) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  if (m->ops->consts(m->plan, theta, n_sets, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  if (m->ops->sets(m->plan, a, grad, false, sets_grid(m), m->stream) != hipSuccess) return NLL_ERR_DEVICE;
+  return NLL_OK;
+}
+
+nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets, double* theta, int32_t n_steps,
+                           double eta, double* nll_out, double* grad_out, int32_t* status_out) {
+  if (!m || n_sets < 0 || n_steps < 0 || !(eta > 0.0) || (n_sets > 0 && (!offsets || !theta || !nll_out)))
+    return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  if (n_sets == 0) return NLL_OK;
+  DeviceGuard guard(m->device);
+  nll_status st = ensure_sets(m, n_sets);
+  if (st != NLL_OK) return st;
+  if ((st = ensure_gd(m, n_sets)) != NLL_OK) return st;
+  if (!m->use_graph) return enqueue_fit(m, m->stream, n_sets, offsets, theta, n_steps, eta, nll_out, grad_out, status_out);
+
+  FitKey k;
+  k.n_sets = n_sets;
+  k.offsets = offsets;
+  k.theta = theta;
+  k.n_steps = n_steps;
+  k.eta = eta;
+  k.nll = nll_out;
+  k.grad = grad_out;
+  k.status = status_out;
+  k.sched = m->sched;
+  if (!(m->have_graph && m->key == k)) {
+    if (m->exec) (void)hipGraphExecDestroy(m->exec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    m->exec = nullptr;
+    m->graph = nullptr;
+    m->have_graph = false;
+    if (hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return NLL_ERR_DEVICE;
+    nll_status est = enqueue_fit(m, m->capture, n_sets, offsets, theta, n_steps, eta, nll_out, grad_out, status_out);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(m->capture, &g);
+    if (est != NLL_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return est != NLL_OK ? est : NLL_ERR_DEVICE;
+    }
+    if (hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return NLL_ERR_DEVICE;
+    }
+    m->graph = g;
+    m->key = k;
+    m->have_graph = true;
+  }
+  return hipGraphLaunch(m->exec, m->stream) == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+}
+
+nll_status nll_fit(nll_model* m, double* theta, int32_t n_steps, double eta, double* nll_out, double* grad_out,
+                   int32_t* status_out) {
+  if (!m) return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  return nll_fit_batched(m, 1, m->offsets1, theta, n_steps, eta, nll_out, grad_out, status_out);
+}
+
+nll_status nll_sync(nll_model* m, int32_t* status_out) {
+  if (!m) return NLL_ERR_ARG;
+  DeviceGuard guard(m->device);
+  if (hipStreamSynchronize(m->stream) != hipSuccess) return NLL_ERR_DEVICE;
+  int bits = 0;
+  if (hipMemcpy(&bits, m->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return NLL_ERR_DEVICE;
+  const int zero = 0;
+  if (hipMemcpy(m->status, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return NLL_ERR_DEVICE;
+  nll_status st = NLL_OK;
+  if (bits & kStatusParam) st = NLL_ERR_PARAM_RANGE;
+  else if (bits & kStatusPdf) st = NLL_ERR_INVALID_PDF;
+  if (status_out) *status_out = st;
+  return st;
+}
+
+nll_status nll_get_schedule(const nll_model* m, nll_schedule* out) {
+  if (!m || !out) return NLL_ERR_ARG;
+  *out = m->sched;
+  return NLL_OK;
+}
+
+nll_status nll_set_schedule(nll_model* m, const nll_schedule* s) {
+  if (!m || !s) return NLL_ERR_ARG;
+  if (!(s->unroll == 2 || s->unroll == 4)) return NLL_ERR_ARG;
+  if (s->blocks_per_cu < 1 || s->blocks_per_cu > 32) return NLL_ERR_ARG;
+  if (s->tile_events < 1024 || s->tile_events > (1 << 22) || (s->tile_events % 512) != 0) return NLL_ERR_ARG;
+  if (s->sets_blocks_per_cu < 1 || s->sets_blocks_per_cu > 32) return NLL_ERR_ARG;
+  if (std::memcmp(&m->sched, s, sizeof(*s)) != 0) m->have_graph = false;
+  m->sched = *s;
+  return NLL_OK;
+}
+
+nll_status nll_autotune(nll_model* m, int32_t which, int32_t n_sets, const int64_t* offsets, const double* theta) {
+  if (!m || (which != 1 && which != 2)) return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  DeviceGuard guard(m->device);
+  return tune_model(m, which, n_sets, offsets, theta);
+}
+
+nll_status nll_get_info(const nll_model* m, nll_info* out) {
+  if (!m || !out) return NLL_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  std::strncpy(out->variant, m->ops->name, sizeof(out->variant) - 1);
+  out->n_leaf = m->plan.n_leaf;
+  out->n_term = m->plan.n_term;
+  out->n_accumulators = m->ops->na_grad;
+  out->precision = m->precision;
+  out->n_cu = m->n_cu;
+  out->n_events = m->n;
+  return NLL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// kernels.h -- what the host runtime sees of the device code: kernel
+// argument blocks, launchers and the registry of compiled model shapes.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "plan.h"
+
+namespace nllmi {
+
+struct SingleArgs {
+  const double* cols[kMaxObs];  // SoA event columns (device)
+  int64_t n;
+  const double* theta;          // n_param (device)
+  double* nll_out;              // 1 (device)
+  double* grad_out;             // n_param (device) or null
+  double* partials;             // grid * (NA + 1) double-double pairs
+  int* ticket;                  // zero between launches
+  int* status;                  // accumulated status bits
+  const double* glx;            // 256-point Gauss-Legendre rule on [-1, 1]
+  const double* glw;
+};
+
+// State of a batched gradient-descent fit (device arrays).
+struct GDState {
+  double* th_acc;   // n_sets * P  last accepted point
+  double* g_acc;    // n_sets * P  its gradient
+  double* th_prop;  // n_sets * P  point being evaluated
+  double* f_acc;    // n_sets      its NLL (+inf before the first acceptance)
+  double* eta;      // n_sets      step size
+  int* last_status; // n_sets
+};
+
+struct SetsArgs {
+  const double* cols[kMaxObs];
+  int n_sets;
+  const int64_t* offsets;   // n_sets + 1 (device)
+  int64_t tile;             // events per work item
+  const int64_t* tile_off;  // n_sets + 1 prefix of item counts (device)
+  const int* set_flag;      // n_sets: 1 = malformed offsets
+  PerTheta* consts;         // n_sets
+  double* partials;         // items * (NA + 1) double-double pairs
+  const double* theta;      // n_sets * P (evaluation mode)
+  double* nll_out;          // n_sets
+  double* grad_out;         // n_sets * P or null
+  int* status_out;          // n_sets or null
+  GDState gd;               // fit mode
+  const double* glx;
+  const double* glw;
+};
+
+struct VariantOps {
+  const char* name;
+  int n_leaf, K, nobs, na_grad;
+  int kind[kMaxLeaves], obs[kMaxLeaves], root[kMaxLeaves], np[kMaxLeaves];
+  int precision;  // 0: FP64
+  hipError_t (*single)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, hipStream_t);
+  hipError_t (*consts)(const Plan&, const double* theta, int n_sets, PerTheta* out, const double* glx,
+                       const double* glw, hipStream_t);
+  hipError_t (*sets)(const Plan&, const SetsArgs&, bool grad, bool fit, int grid, hipStream_t);
+  hipError_t (*fit_init)(const Plan&, const double* theta, int n_sets, double eta, const GDState&,
+                         PerTheta* consts, const double* glx, const double* glw, hipStream_t);
+};
+
+// registry: every variants_*.hip file appends its compiled shapes
+void register_variants_single(std::vector<VariantOps>& out);
+void register_variants_mixture(std::vector<VariantOps>& out);
+void register_variants_2d(std::vector<VariantOps>& out);
+
+hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
+                           int64_t* tile_off, int* set_flag, hipStream_t st);
+hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_out, double* nll_out,
+                            double* grad_out, int* status_out, hipStream_t st);
+hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, unsigned long long* bad,
+                              hipStream_t st);
+
+}  // namespace nllmi

@@ -1,0 +1,465 @@
+// leaves.h -- the built-in leaf densities on the device (gfx950).
+//
+// Each leaf type provides
+//   * setup():   per-parameter-point constants for the event pass, the
+//                normalisation integral Z and dZ/dtheta (closed form), and
+//                the scale that maps each gradient feature to d log g/dtheta;
+//   * shape():   the unnormalised density and its parameter derivatives at
+//                one point (for Gauss-Legendre normalisation);
+//   * event():   the per-event part, fused into the single streaming pass.
+//                It returns lam (log-domain part of log g), gam (a linear
+//                factor, 1 for pure log-domain leaves: used when the leaf is
+//                a root factor so that no per-event log is needed) and the
+//                gradient features phi_p with d log g / d theta_p =
+//                fscale_p * phi_p.
+//
+// The densities are the ones of the paper's built-in models (Sec. 3):
+//   Gauss(mu, sigma)        g = exp(-t^2/2),        t = (x - mu)/sigma
+//   Exp(c)                  g = exp(c x)
+//   Cheb(a_1..a_K)          g = 1 + sum a_k T_k(x'), x' mapped to [-1, 1]
+//   CrystalBall(m0,s,a,n)   g = exp(-t^2/2) for t > -a, A (B - t)^-n below,
+//                           A = (n/a)^n e^{-a^2/2}, B = n/a - a
+//   Argus(m0, c)            g = m sqrt(u) e^{c u}, u = 1 - (m/m0)^2, m < m0
+// The branch-free selects follow Sec. 5.3 (both sides computed, one kept).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace nllmi {
+
+constexpr double kSqrtPiOver2 = 1.2533141373155002512078826424055;  // sqrt(pi/2)
+constexpr double kSqrtPi = 1.7724538509055160272981674833411;
+constexpr double kInvSqrt2 = 0.70710678118654752440084436210485;
+constexpr double kLn2 = 0.69314718055994530941723212145818;
+
+// erf(b/sqrt2) - erf(a/sqrt2) for a <= b without cancellation in the tails
+__device__ inline double erf_span(double a, double b) {
+  if (a >= 0.0) return erfc(a * kInvSqrt2) - erfc(b * kInvSqrt2);
+  if (b <= 0.0) return erfc(-b * kInvSqrt2) - erfc(-a * kInvSqrt2);
+  return erf(b * kInvSqrt2) - erf(a * kInvSqrt2);
+}
+
+// Closed-form pieces are written for the leaf's local parameter order.
+struct LeafSetup {
+  double ec[12];      // event constants
+  double fscale[kMaxLeafParams];
+  double Z;
+  double dZ[kMaxLeafParams];
+};
+
+// ------------------------------------------------------------------------
+// Gaussian
+// ------------------------------------------------------------------------
+struct GaussLeaf {
+  static constexpr int kKind = kGauss;
+  static constexpr int NP = 2;
+  static constexpr bool kLinear = false;
+  struct C {
+    double is, b;
+  };
+  __device__ static bool valid(const double* p) { return p[1] > 0.0; }
+  __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
+    const double mu = p[0], sg = p[1], is = 1.0 / sg;
+    s.ec[0] = is;
+    s.ec[1] = -mu * is;
+    s.fscale[0] = is;
+    s.fscale[1] = is;
+    if (!analytic) return;
+    const double a = (lo - mu) * is, b = (hi - mu) * is;
+    const double ea = exp(-0.5 * a * a), eb = exp(-0.5 * b * b);
+    s.Z = sg * kSqrtPiOver2 * erf_span(a, b);
+    s.dZ[0] = ea - eb;
+    s.dZ[1] = s.Z * is + a * ea - b * eb;
+  }
+  __device__ static double shape(const double* p, double lo, double hi, double x, double* dg) {
+    const double t = (x - p[0]) / p[1];
+    const double g = exp(-0.5 * t * t);
+    dg[0] = g * t / p[1];
+    dg[1] = g * t * t / p[1];
+    return g;
+  }
+  __device__ static C load(const double* ec) { return C{ec[0], ec[1]}; }
+  template <bool GRAD>
+  __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
+    const double t = fma(x, c.is, c.b);
+    const double tt = t * t;
+    lam = -0.5 * tt;
+    gam = 1.0;
+    if (GRAD) {
+      phi[0] = t;
+      phi[1] = tt;
+    }
+  }
+};
+
+// ------------------------------------------------------------------------
+// Exponential
+// ------------------------------------------------------------------------
+struct ExpLeaf {
+  static constexpr int kKind = kExp;
+  static constexpr int NP = 1;
+  static constexpr bool kLinear = false;
+  struct C {
+    double c;
+  };
+  __device__ static bool valid(const double*) { return true; }
+  __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
+    const double c = p[0];
+    s.ec[0] = c;
+    s.fscale[0] = 1.0;
+    if (!analytic) return;
+    const double R = fmax(fabs(lo), fabs(hi));
+    if (fabs(c) * R < 0.25) {
+      // int x^j e^{cx} as a power series in c (all terms small)
+      double z = 0.0, dz = 0.0, ck = 1.0, hp = hi, lp = lo;
+      for (int k = 0; k < 40; ++k) {
+        z += ck * (hp - lp) / (k + 1);
+        dz += ck * (hp * hi - lp * lo) / (k + 2);
+        hp *= hi;
+        lp *= lo;
+        ck *= c / (k + 1);
+      }
+      s.Z = z;
+      s.dZ[0] = dz;
+      return;
+    }
+    const double elo = exp(c * lo), ehi = exp(c * hi);
+    s.Z = elo * expm1(c * (hi - lo)) / c;
+    s.dZ[0] = (ehi * fma(c, hi, -1.0) - elo * fma(c, lo, -1.0)) / (c * c);
+  }
+  __device__ static double shape(const double* p, double, double, double x, double* dg) {
+    const double g = exp(p[0] * x);
+    dg[0] = g * x;
+    return g;
+  }
+  __device__ static C load(const double* ec) { return C{ec[0]}; }
+  template <bool GRAD>
+  __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
+    lam = c.c * x;
+    gam = 1.0;
+    if (GRAD) phi[0] = x;
+  }
+};
+
+// ------------------------------------------------------------------------
+// Chebyshev series of order K (T_0 coefficient 1); linear when a root factor
+// ------------------------------------------------------------------------
+template <int K>
+struct ChebLeaf {
+  static_assert(K >= 1 && K <= 8, "Chebyshev order 1..8");
+  static constexpr int kKind = kCheb;
+  static constexpr int NP = K;
+  static constexpr bool kLinear = true;
+  struct C {
+    double sx, ox, a[K];
+  };
+  __device__ static bool valid(const double*) { return true; }
+  __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
+    s.ec[0] = 2.0 / (hi - lo);
+    s.ec[1] = -(hi + lo) / (hi - lo);
+    for (int k = 0; k < K; ++k) {
+      s.ec[2 + k] = p[k];
+      s.fscale[k] = 1.0;
+    }
+    if (!analytic) return;
+    // int_{-1}^{1} T_k dx' = 2/(1-k^2) (k even), 0 (k odd); dx = (hi-lo)/2 dx'
+    const double half = 0.5 * (hi - lo);
+    double z = 2.0 * half;
+    for (int k = 1; k <= K; ++k) {
+      const double w = (k & 1) ? 0.0 : 2.0 / (1.0 - (double)(k * k));
+      z += half * p[k - 1] * w;
+      s.dZ[k - 1] = half * w;
+    }
+    s.Z = z;
+  }
+  __device__ static double shape(const double* p, double lo, double hi, double x, double* dg) {
+    const double y = (2.0 * x - lo - hi) / (hi - lo);
+    double t0 = 1.0, t1 = y, g = 1.0;
+    for (int k = 0; k < K; ++k) {
+      g += p[k] * t1;
+      dg[k] = t1;
+      const double t2 = 2.0 * y * t1 - t0;
+      t0 = t1;
+      t1 = t2;
+    }
+    return g;
+  }
+  __device__ static C load(const double* ec) {
+    C c;
+    c.sx = ec[0];
+    c.ox = ec[1];
+    for (int k = 0; k < K; ++k) c.a[k] = ec[2 + k];
+    return c;
+  }
+  // LIN: leave g as a linear factor (root factor) instead of taking its log.
+  template <bool GRAD, bool LIN = false>
+  __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
+    const double y = fma(x, c.sx, c.ox);
+    const double y2 = y + y;
+    double tk[K];
+    double tm = 1.0, t = y;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      tk[k] = t;
+      const double tn = fma(y2, t, -tm);
+      tm = t;
+      t = tn;
+    }
+    double g = 1.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) g = fma(c.a[k], tk[k], g);
+    if (LIN) {
+      lam = 0.0;
+      gam = g;
+    } else {
+      lam = log(g);
+      gam = 1.0;
+    }
+    if (GRAD) {
+      // 1/g: hardware reciprocal refined by two Newton steps
+      double r = __builtin_amdgcn_rcp(g);
+      r = fma(r, fma(-g, r, 1.0), r);
+      r = fma(r, fma(-g, r, 1.0), r);
+#pragma unroll
+      for (int k = 0; k < K; ++k) phi[k] = tk[k] * r;
+    }
+  }
+};
+
+// ------------------------------------------------------------------------
+// Crystal Ball (low-side tail)
+// ------------------------------------------------------------------------
+struct CBLeaf {
+  static constexpr int kKind = kCB;
+  static constexpr int NP = 4;
+  static constexpr bool kLinear = false;
+  struct C {
+    double is, b, na, logA, B, n, Ka, Kb, Kc, nOverA;
+  };
+  __device__ static bool valid(const double* p) { return p[1] > 0.0 && p[2] > 0.0 && p[3] > 1.0; }
+
+  // closed-form integral over t in [ca, cb] of the core and [ta, tb] of the tail
+  __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
+    const double m0 = p[0], sg = p[1], al = p[2], n = p[3], is = 1.0 / sg;
+    const double logA = n * log(n / al) - 0.5 * al * al;
+    const double B = n / al - al;
+    s.ec[0] = is;
+    s.ec[1] = -m0 * is;
+    s.ec[2] = -al;
+    s.ec[3] = logA;
+    s.ec[4] = B;
+    s.ec[5] = n;
+    s.ec[6] = -n / al - al;                 // d log A/d alpha
+    s.ec[7] = n * (n / (al * al) + 1.0);    // -n dB/d alpha
+    s.ec[8] = log(n / al) + 1.0;            // d log A / d n
+    s.ec[9] = n / al;                       // n dB/dn
+    s.fscale[0] = is;
+    s.fscale[1] = is;
+    s.fscale[2] = 1.0;
+    s.fscale[3] = 1.0;
+    if (!analytic) return;
+    const double tlo = (lo - m0) * is, thi = (hi - m0) * is;
+    double Z = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+    const double ca = fmax(tlo, -al), cb = thi;
+    if (cb > ca) {
+      const double ea = exp(-0.5 * ca * ca), eb = exp(-0.5 * cb * cb);
+      const double zc = sg * kSqrtPiOver2 * erf_span(ca, cb);
+      Z += zc;
+      d0 += ea - eb;                       // int t e^{-t^2/2} dt
+      d1 += zc * is + ca * ea - cb * eb;   // int t^2 e^{-t^2/2} dt
+    }
+    const double ta = tlo, tb = fmin(thi, -al);
+    if (tb > ta) {
+      const double A = exp(logA);
+      const double Da = B - ta, Db = B - tb;  // Db < Da
+      const double lDa = log(Da), lDb = log(Db);
+      const double pa = exp(-n * lDa), pb = exp(-n * lDb);         // D^-n
+      const double qa = Da * pa, qb = Db * pb;                     // D^{1-n}
+      const double n1 = n - 1.0;
+      const double I0 = (qb - qa) / n1;        // int D^-n dt
+      const double I1 = (pb - pa) / n;         // int D^{-n-1} dt
+      // int D^-n ln D dt = [D^{1-n} (ln D/(n-1) + 1/(n-1)^2)]
+      const double IL = qb * (lDb / n1 + 1.0 / (n1 * n1)) - qa * (lDa / n1 + 1.0 / (n1 * n1));
+      const double zt = sg * A * I0;
+      Z += zt;
+      d0 += -n * A * I1;                                // m0
+      d1 += -n * A * (B * I1 - I0);                     // sigma: t = B - D
+      d2 += s.ec[6] * zt + s.ec[7] * sg * A * I1;       // alpha
+      d3 += s.ec[8] * zt - sg * A * IL - s.ec[9] * sg * A * I1;  // n
+    }
+    s.Z = Z;
+    s.dZ[0] = d0;
+    s.dZ[1] = d1;
+    s.dZ[2] = d2;
+    s.dZ[3] = d3;
+  }
+  __device__ static double shape(const double* p, double lo, double hi, double x, double* dg) {
+    const double m0 = p[0], sg = p[1], al = p[2], n = p[3];
+    const double t = (x - m0) / sg;
+    if (t > -al) {
+      const double g = exp(-0.5 * t * t);
+      dg[0] = g * t / sg;
+      dg[1] = g * t * t / sg;
+      dg[2] = 0.0;
+      dg[3] = 0.0;
+      return g;
+    }
+    const double B = n / al - al, D = B - t;
+    const double g = exp(n * log(n / al) - 0.5 * al * al - n * log(D));
+    dg[0] = -g * n / (sg * D);
+    dg[1] = -g * n * t / (sg * D);
+    dg[2] = g * (-n / al - al + n * (n / (al * al) + 1.0) / D);
+    dg[3] = g * (log(n / al) + 1.0 - log(D) - n / (al * D));
+    return g;
+  }
+  __device__ static C load(const double* ec) {
+    return C{ec[0], ec[1], ec[2], ec[3], ec[4], ec[5], ec[6], ec[7], ec[8], ec[9]};
+  }
+  template <bool GRAD>
+  __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
+    const double t = fma(x, c.is, c.b);
+    const bool core = t > c.na;
+    const double D = core ? 1.0 : (c.B - t);
+    const double lD = log(D);
+    const double tt = t * t;
+    lam = core ? -0.5 * tt : fma(-c.n, lD, c.logA);
+    gam = 1.0;
+    if (GRAD) {
+      double r = __builtin_amdgcn_rcp(D);
+      r = fma(r, fma(-D, r, 1.0), r);
+      r = fma(r, fma(-D, r, 1.0), r);
+      const double nr = c.n * r;
+      phi[0] = core ? t : -nr;
+      phi[1] = core ? tt : -nr * t;
+      phi[2] = core ? 0.0 : fma(c.Kb, r, c.Ka);
+      phi[3] = core ? 0.0 : (c.Kc - lD) - c.nOverA * r;
+    }
+  }
+};
+
+// ------------------------------------------------------------------------
+// ARGUS (power 1/2)
+// ------------------------------------------------------------------------
+// J_p(U) = int_0^U u^p e^{c u} du for p in {-1/2, 1/2, 3/2}, through the
+// lower incomplete gamma function gamma(p+1, kU)/k^{p+1} (k = -c > 0):
+//   gamma(1/2, z) = sqrt(pi) erf(sqrt z)
+//   gamma(a+1, z) = a gamma(a, z) - z^a e^{-z}
+// with the series gamma(a, z) = z^a sum_j (-z)^j / (j! (a + j)) for z < 1
+// (where the recurrence cancels); c >= 0 uses the power series of e^{cu}.
+__device__ inline void argus_J(double c, double U, double J[3]) {
+  J[0] = J[1] = J[2] = 0.0;
+  if (!(U > 0.0)) return;
+  const double ap[3] = {0.5, 1.5, 2.5};
+  if (c >= 0.0) {
+    const double x = c * U;
+    for (int q = 0; q < 3; ++q) {
+      double sum = 0.0, term = 1.0;
+      for (int j = 0; j < 400; ++j) {
+        const double add = term / (j + ap[q]);
+        sum += add;
+        if (add < 1e-18 * sum) break;
+        term *= x / (j + 1);
+      }
+      J[q] = pow(U, ap[q]) * sum;
+    }
+    return;
+  }
+  const double k = -c, z = k * U;
+  double g[3];
+  if (z < 1.0) {
+    for (int q = 0; q < 3; ++q) {
+      double sum = 0.0, term = 1.0;
+      for (int j = 0; j < 60; ++j) {
+        sum += term / (j + ap[q]);
+        term *= -z / (j + 1);
+      }
+      g[q] = pow(z, ap[q]) * sum;
+    }
+  } else {
+    const double sz = sqrt(z), ez = exp(-z);
+    g[0] = kSqrtPi * erf(sz);
+    g[1] = 0.5 * g[0] - sz * ez;
+    g[2] = 1.5 * g[1] - z * sz * ez;
+  }
+  for (int q = 0; q < 3; ++q) J[q] = g[q] / pow(k, ap[q]);
+}
+
+struct ArgusLeaf {
+  static constexpr int kKind = kArgus;
+  static constexpr int NP = 2;
+  static constexpr bool kLinear = true;
+  struct C {
+    double m0, im02, c, dm0;  // dm0: 2/m0^3, or 0 when m0 is not differentiated
+  };
+  __device__ static bool valid(const double* p) { return true; }
+  __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
+    const double m0 = p[0], c = p[1];
+    s.ec[0] = m0;
+    s.ec[1] = 1.0 / (m0 * m0);
+    s.ec[2] = c;
+    s.ec[3] = 2.0 / (m0 * m0 * m0);
+    s.fscale[0] = 1.0;
+    s.fscale[1] = 1.0;
+    if (!analytic) return;
+    const double Ua = (m0 - lo) * (m0 + lo) / (m0 * m0);
+    const double Ub = hi >= m0 ? 0.0 : (m0 - hi) * (m0 + hi) / (m0 * m0);
+    double Ja[3], Jb[3];
+    argus_J(c, Ua, Ja);
+    argus_J(c, Ub, Jb);
+    const double jm = Ja[0] - Jb[0], j1 = Ja[1] - Jb[1], j3 = Ja[2] - Jb[2];
+    s.Z = 0.5 * m0 * m0 * j1;
+    s.dZ[0] = m0 * (0.5 * (jm - j1) + c * (j1 - j3));
+    s.dZ[1] = 0.5 * m0 * m0 * j3;
+  }
+  __device__ static double shape(const double* p, double, double, double x, double* dg) {
+    const double m0 = p[0], c = p[1];
+    if (x >= m0) {
+      dg[0] = dg[1] = 0.0;
+      return 0.0;
+    }
+    const double u = (m0 - x) * (m0 + x) / (m0 * m0);
+    const double g = x * sqrt(u) * exp(c * u);
+    dg[0] = g * (0.5 / u + c) * 2.0 * x * x / (m0 * m0 * m0);
+    dg[1] = g * u;
+    return g;
+  }
+  // the integrand after m = m0 - s^2 (analytic in s), times dm/ds = 2 s
+  __device__ static double shape_subst(const double* p, double sv, double* dg) {
+    const double m0 = p[0], c = p[1];
+    const double s2 = sv * sv, m = m0 - s2;
+    const double u = s2 * (2.0 * m0 - s2) / (m0 * m0);
+    const double g = m * sqrt(u) * exp(c * u) * 2.0 * sv;
+    dg[0] = g * (0.5 / u + c) * 2.0 * m * m / (m0 * m0 * m0);
+    dg[1] = g * u;
+    return g;
+  }
+  __device__ static C load(const double* ec) { return C{ec[0], ec[1], ec[2], ec[3]}; }
+  template <bool GRAD, bool LIN = false>
+  __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
+    const double u = (c.m0 - x) * (c.m0 + x) * c.im02;
+    const bool in = u > 0.0;
+    const double us = in ? u : 1.0;
+    if (LIN) {
+      lam = in ? c.c * us : -__builtin_inf();
+      gam = in ? x * sqrt(us) : 0.0;
+    } else {
+      lam = in ? fma(0.5, log(x * x * us), c.c * us) : -__builtin_inf();
+      gam = 1.0;
+    }
+    if (GRAD) {
+      double d0 = 0.0;
+      if (c.dm0 != 0.0) {
+        double r = __builtin_amdgcn_rcp(us);
+        r = fma(r, fma(-us, r, 1.0), r);
+        r = fma(r, fma(-us, r, 1.0), r);
+        d0 = fma(0.5, r, c.c) * (x * x) * c.dm0;
+      }
+      phi[0] = in ? d0 : 0.0;
+      phi[1] = in ? us : 0.0;
+    }
+  }
+};
+
+}  // namespace nllmi

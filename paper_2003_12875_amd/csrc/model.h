@@ -1,0 +1,248 @@
+// model.h -- compile-time model shapes, the fused per-event pass and the
+// per-parameter-point prologue.
+//
+// A compiled model is Model<K, NOBS, Slot<Leaf, obs, root>...>: the leaf
+// types, the observable each reads and whether it is a factor of every
+// term are template parameters, so the per-event work is straight-line
+// code; which non-root leaf belongs to which of the K terms and the term
+// weights are runtime (uniform) data in the Plan.
+//
+// Per event (Sec. 5.1: one expression per dataset entry; Sec. 5.3: no data
+// dependence between entries, intermediates kept in registers):
+//   lam_l, gam_l, phi_l       from every leaf
+//   L_k = ck_k + sum_{l in S_k, not root} lam_l
+//   log p = croot + sum_{root l} (lam_l + log gam_l) + logsumexp_k L_k
+// The log-sum-exp is split as m = max_k L_k (summed) and s = sum_k
+// e^{L_k - m} in [1, K] (multiplied into a running mantissa/exponent
+// product whose log is taken once per thread), so a K = 2 mixture costs one
+// exp and no log per event, and a single-term model (e.g. one Gaussian)
+// costs no transcendental at all.
+// Gradient (the adjoint of that expression):
+//   d log p / d theta = sum_k r_k dC_k + sum_l R_l fscale_lp phi_lp,
+//   r_k = e^{L_k - m} / s,  R_l = sum_{k contains l} r_k  (1 for root leaves)
+// and the parameter-only parts (dC_k, fscale, d log Z) are applied once,
+// after the reduction, to the accumulated sums of r_k and R_l phi_lp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <tuple>
+#include <type_traits>
+#include <utility>
+
+#include "leaves.h"
+#include "plan.h"
+
+namespace nllmi {
+
+template <class F, int... I>
+__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ inline void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// broadcast lane 0's value: the compiler then keeps it in scalar registers
+__device__ inline double uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <class LeafT, int OBS, bool ROOT>
+struct Slot {
+  using Leaf = LeafT;
+  static constexpr int obs = OBS;
+  static constexpr bool root = ROOT;
+  static constexpr bool lin = ROOT && LeafT::kLinear;  // linear factor, no per-event log
+};
+
+template <int K_, int NOBS_, class... Slots>
+struct Model {
+  static constexpr int K = K_;
+  static constexpr int NOBS = NOBS_;
+  static constexpr int L = sizeof...(Slots);
+  using SlotTuple = std::tuple<Slots...>;
+  template <int l>
+  using S = std::tuple_element_t<l, SlotTuple>;
+
+  static constexpr int NPT = (Slots::Leaf::NP + ... + 0);
+  static constexpr bool HAS_LIN = (Slots::lin || ...);
+  static constexpr bool NEED_PROD = (K > 1) || HAS_LIN;
+  static constexpr int TERM_BASE = 1;
+  static constexpr int LEAF_BASE = 1 + (K > 1 ? K : 0);
+  static constexpr int NA_GRAD = LEAF_BASE + NPT;
+  template <bool GRAD>
+  static constexpr int NA = GRAD ? NA_GRAD : 1;
+
+  static constexpr int NPs[L] = {Slots::Leaf::NP...};
+  template <int l>
+  static constexpr int leaf_off() {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += NPs[i];
+    return o;
+  }
+  using LeafCs = std::tuple<typename Slots::Leaf::C...>;
+
+  static_assert(L >= 1 && L <= kMaxLeaves, "1..kMaxLeaves leaves");
+  static_assert(K >= 1 && K <= kMaxTerms, "1..kMaxTerms terms");
+  static_assert(NA_GRAD <= kMaxAcc, "accumulator budget");
+};
+
+// Uniform per-point constants of a compiled model, held in scalar registers.
+template <class M>
+struct Consts {
+  typename M::LeafCs leaf;
+  double ck[M::K];
+  int mask[M::K];  // non-root leaves of term k
+
+  __device__ void load(const PerTheta& pt, const Plan& pl) {
+    static_for<M::L>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      double ec[12];
+#pragma unroll
+      for (int j = 0; j < 12; ++j) ec[j] = uniform(pt.ec[l][j]);
+      std::get<l>(leaf) = M::template S<l>::Leaf::load(ec);
+    });
+#pragma unroll
+    for (int k = 0; k < M::K; ++k) {
+      ck[k] = uniform(pt.ck[k]);
+      mask[k] = pl.term_mask[k];
+    }
+  }
+};
+
+template <class M, bool GRAD>
+struct Acc {
+  double a[M::template NA<GRAD>];
+  double P;    // running product (mantissa)
+  int E;       // its binary exponent
+  int bad;     // events with p <= 0 or non-finite
+  __device__ void init() {
+#pragma unroll
+    for (int j = 0; j < M::template NA<GRAD>; ++j) a[j] = 0.0;
+    P = 1.0;
+    E = 0;
+    bad = 0;
+  }
+  __device__ void renorm() {
+    if constexpr (M::NEED_PROD) {
+      int e;
+      P = frexp(P, &e);
+      E += e;
+    }
+  }
+  // fold the product into the log-sum (once per thread)
+  __device__ void close() {
+    if constexpr (M::NEED_PROD) {
+      a[0] += log(P) + (double)E * kLn2;
+      P = 1.0;
+      E = 0;
+    }
+  }
+};
+
+template <class M, bool GRAD>
+__device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& C, Acc<M, GRAD>& acc) {
+  constexpr int L = M::L, K = M::K;
+  double lam[L];
+  double gprod = 1.0;
+  double phi[M::NPT > 0 ? M::NPT : 1];
+  static_for<L>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    using Sl = typename M::template S<l>;
+    double gam;
+    if constexpr (Sl::Leaf::kLinear) {
+      Sl::Leaf::template event<GRAD, Sl::lin>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
+                                               &phi[M::template leaf_off<l>()]);
+    } else {
+      Sl::Leaf::template event<GRAD>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
+                                     &phi[M::template leaf_off<l>()]);
+    }
+    if constexpr (Sl::lin) gprod *= gam;
+  });
+
+  double rootsum = 0.0;
+  static_for<L>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    if constexpr (M::template S<l>::root) rootsum += lam[l];
+  });
+
+  if constexpr (K == 1) {
+    acc.a[0] += rootsum;
+    if constexpr (M::HAS_LIN) acc.P *= gprod;
+    acc.bad += !(__builtin_isfinite(rootsum) && gprod > 0.0);
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int j = 0; j < M::NPT; ++j) acc.a[M::LEAF_BASE + j] += phi[j];
+    }
+  } else {
+    double Lk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v = C.ck[k];
+      static_for<L>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        if constexpr (!M::template S<l>::root) v += ((C.mask[k] >> l) & 1) ? lam[l] : 0.0;
+      });
+      Lk[k] = v;
+    }
+    double m, s, e[K];
+    if constexpr (K == 2) {
+      const double d = Lk[0] - Lk[1];
+      m = fmax(Lk[0], Lk[1]);
+      const double es = exp(-fabs(d));
+      e[0] = d >= 0.0 ? 1.0 : es;
+      e[1] = d >= 0.0 ? es : 1.0;
+      s = 1.0 + es;
+    } else {
+      m = Lk[0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) m = fmax(m, Lk[k]);
+      s = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        e[k] = exp(Lk[k] - m);
+        s += e[k];
+      }
+    }
+    const double tot = rootsum + m;
+    acc.a[0] += tot;
+    if constexpr (M::HAS_LIN)
+      acc.P *= s * gprod;
+    else
+      acc.P *= s;
+    acc.bad += !(__builtin_isfinite(tot) && gprod > 0.0);
+    if constexpr (GRAD) {
+      double inv = __builtin_amdgcn_rcp(s);
+      inv = fma(inv, fma(-s, inv, 1.0), inv);
+      inv = fma(inv, fma(-s, inv, 1.0), inv);
+      double r[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        r[k] = e[k] * inv;
+        acc.a[M::TERM_BASE + k] += r[k];
+      }
+      static_for<L>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        using Sl = typename M::template S<l>;
+        constexpr int off = M::template leaf_off<l>();
+        if constexpr (Sl::root) {
+#pragma unroll
+          for (int p = 0; p < Sl::Leaf::NP; ++p) acc.a[M::LEAF_BASE + off + p] += phi[off + p];
+        } else {
+          double R = 0.0;
+#pragma unroll
+          for (int k = 0; k < K; ++k) R += ((C.mask[k] >> l) & 1) ? r[k] : 0.0;
+#pragma unroll
+          for (int p = 0; p < Sl::Leaf::NP; ++p) acc.a[M::LEAF_BASE + off + p] = fma(R, phi[off + p], acc.a[M::LEAF_BASE + off + p]);
+        }
+      });
+    }
+  }
+}
+
+}  // namespace nllmi

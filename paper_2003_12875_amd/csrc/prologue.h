@@ -1,0 +1,203 @@
+// prologue.h -- per-parameter-point constants, computed once per evaluation
+// (the caching of parameter-only branches of Sec. 5.1) by one thread block.
+//
+//  * parameter range checks (Sec. 3, "Checking parameters");
+//  * per leaf: event constants, gradient scales, Z and dZ/dtheta, either in
+//    closed form ("Analytic Integrals", Sec. 3) or by a 256-point
+//    Gauss-Legendre rule, one node per thread, on panels where the integrand
+//    is analytic (the Crystal Ball split at its junction; the ARGUS
+//    endpoint removed by m = m0 - s^2) or on one panel;
+//  * per term: log of its weight (product of sum coefficients) minus the
+//    log normalisations of its leaves, and d log w_k / d theta.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "leaves.h"
+#include "model.h"
+#include "plan.h"
+
+namespace nllmi {
+
+// sum over the block of NV values per thread (fixed order: deterministic)
+template <int NV>
+__device__ inline void block_sum_small(double (&v)[NV], double* lds /* >= 4*NV */) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] += __shfl_xor(v[j], off, 64);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = ((lds[j] + lds[NV + j]) + lds[2 * NV + j]) + lds[3 * NV + j];
+  __syncthreads();
+}
+
+// Gauss-Legendre contribution of this thread's node to Z and dZ of a leaf.
+template <class Leaf>
+__device__ inline void gl_node(const double* p, int norm, double lo, double hi, const double* glx,
+                               const double* glw, double (&v)[Leaf::NP + 1]) {
+  const int i = threadIdx.x;
+  double dg[kMaxLeafParams];
+#pragma unroll
+  for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
+  auto panel = [&](double a, double b) {
+    const double h = 0.5 * (b - a), c = 0.5 * (a + b);
+    const double w = h * glw[i];
+    const double g = Leaf::shape(p, lo, hi, fma(h, glx[i], c), dg);
+    v[0] += w * g;
+#pragma unroll
+    for (int j = 0; j < Leaf::NP; ++j) v[j + 1] += w * dg[j];
+  };
+  if (norm == kNormGLSingle) {
+    panel(lo, hi);
+    return;
+  }
+  if constexpr (Leaf::kKind == kCB) {
+    const double mj = p[0] - p[2] * p[1];
+    if (mj > lo && mj < hi) {
+      panel(lo, mj);
+      panel(mj, hi);
+    } else {
+      panel(lo, hi);
+    }
+  } else if constexpr (Leaf::kKind == kArgus) {
+    const double m0 = p[0];
+    const double sa = sqrt(m0 - fmin(hi, m0)), sb = sqrt(fmax(m0 - lo, 0.0));
+    const double h = 0.5 * (sb - sa), c = 0.5 * (sa + sb);
+    const double w = h * glw[i];
+    const double g = ArgusLeaf::shape_subst(p, fma(h, glx[i], c), dg);
+    v[0] += w * g;
+    v[1] += w * dg[0];
+    v[2] += w * dg[1];
+  } else {
+    panel(lo, hi);
+  }
+}
+
+// Fills *pt (LDS or global) for parameter vector theta.  All threads of the
+// block must call it; on return *pt is complete and visible to the block.
+template <class M>
+__device__ void compute_pertheta(const Plan& pl, const double* __restrict__ theta,
+                                 const double* __restrict__ glx, const double* __restrict__ glw,
+                                 PerTheta* pt, double* lds) {
+  const int tid = threadIdx.x;
+  __shared__ int s_bad;
+  if (tid == 0) {
+    int bad = 0;
+    for (int k = 0; k < pl.n_param; ++k) {
+      const double v = theta[k];
+      if (!(v >= pl.par_lo[k] && v <= pl.par_hi[k])) bad = 1;  // NaN fails too
+    }
+    for (int q = 0; q < pl.n_sum; ++q) {
+      double f = 0.0;
+      for (int j = 0; j < pl.sum_nchild[q] - 1; ++j) {
+        const double v = theta[pl.sum_param[q][j]];
+        if (!(v >= 0.0 && v <= 1.0)) bad = 1;
+        f += v;
+      }
+      if (!(f <= 1.0)) bad = 1;
+    }
+    if (pl.extended && !(theta[pl.yield_param] > 0.0)) bad = 1;
+    s_bad = bad;
+  }
+  __syncthreads();
+
+  static_for<M::L>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    using Leaf = typename M::template S<l>::Leaf;
+    double p[Leaf::NP];
+#pragma unroll
+    for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
+    const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
+    const bool analytic = pl.leaf_norm[l] == kNormAnalytic;
+    const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
+    if (!analytic) {
+      double v[Leaf::NP + 1];
+      if (ok) {
+        gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
+      } else {
+#pragma unroll
+        for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
+      }
+      block_sum_small<Leaf::NP + 1>(v, lds);
+      if (tid == 0) {
+        pt->logz[l] = v[0];  // Z for now
+#pragma unroll
+        for (int j = 0; j < Leaf::NP; ++j) pt->dlogz[l][j] = v[j + 1];  // dZ for now
+      }
+    }
+    if (tid == 0) {
+      LeafSetup s;
+      for (int j = 0; j < 12; ++j) s.ec[j] = 0.0;
+      for (int j = 0; j < kMaxLeafParams; ++j) {
+        s.fscale[j] = 0.0;
+        s.dZ[j] = 0.0;
+      }
+      s.Z = 0.0;
+      if (ok) Leaf::setup(p, lo, hi, analytic, s);
+      if (!analytic) {
+        s.Z = pt->logz[l];
+        for (int j = 0; j < Leaf::NP; ++j) s.dZ[j] = pt->dlogz[l][j];
+      }
+      if constexpr (Leaf::kKind == kArgus) {
+        if (!pl.par_free[pl.leaf_param[l][0]]) s.ec[3] = 0.0;  // m0 not differentiated
+      }
+      if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) s_bad = 1;
+      for (int j = 0; j < 12; ++j) pt->ec[l][j] = s.ec[j];
+      const double iz = 1.0 / s.Z;
+      pt->logz[l] = log(s.Z);
+      for (int j = 0; j < kMaxLeafParams; ++j) {
+        pt->fscale[l][j] = s.fscale[j];
+        pt->dlogz[l][j] = j < Leaf::NP ? s.dZ[j] * iz : 0.0;
+      }
+    }
+    __syncthreads();
+  });
+
+  if (tid == 0) {
+    // term constants: log w_k - sum_{non-root l in S_k} log Z_l, and
+    // d log w_k / d theta over the fraction parameters of every sum on the path.
+    // Coefficients are floored at 1e-200 so that a fraction exactly at 0 or 1
+    // keeps a finite log and a finite d/df (the floored term then carries a
+    // weight of 1e-200, i.e. nothing, in the likelihood).
+    double croot = 0.0;
+    for (int l = 0; l < pl.n_leaf; ++l)
+      if (pl.leaf_root[l]) croot -= pt->logz[l];
+    pt->croot = croot;
+    for (int k = 0; k < kMaxTerms; ++k) {
+      for (int q = 0; q < kMaxParams; ++q) pt->dlogw[k][q] = 0.0;
+      pt->ck[k] = 0.0;
+    }
+    for (int k = 0; k < pl.n_term; ++k) {
+      double lw = 0.0;
+      for (int r = 0; r < pl.term_nref[k]; ++r) {
+        const int q = pl.term_ref_sum[k][r], j = pl.term_ref_child[k][r];
+        const int nc = pl.sum_nchild[q];
+        double f = 0.0;
+        for (int i = 0; i < nc - 1; ++i) f += theta[pl.sum_param[q][i]];
+        const double c = (j < nc - 1) ? theta[pl.sum_param[q][j]] : 1.0 - f;
+        const double cf = fmax(c, 1e-200);
+        lw += log(cf);
+        if (j < nc - 1) {
+          pt->dlogw[k][pl.sum_param[q][j]] += 1.0 / cf;
+        } else {
+          for (int i = 0; i < nc - 1; ++i) pt->dlogw[k][pl.sum_param[q][i]] -= 1.0 / cf;
+        }
+      }
+      for (int l = 0; l < pl.n_leaf; ++l)
+        if (!pl.leaf_root[l] && ((pl.term_mask[k] >> l) & 1)) lw -= pt->logz[l];
+      pt->ck[k] = lw;
+    }
+    pt->bad = s_bad;
+  }
+  __syncthreads();
+}
+
+}  // namespace nllmi

@@ -1,0 +1,95 @@
+// runtime.h -- the model object shared by the C ABI (host.cpp) and the
+// autotuner (tune.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstring>
+
+#include "kernels.h"
+#include "nll.h"
+#include "plan.h"
+
+namespace nllmi {
+
+struct GLTable {
+  double* x = nullptr;
+  double* w = nullptr;
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+void gauss_legendre(int n, double* nodes, double* weights);
+
+}  // namespace nllmi
+
+struct FitKey {
+  int n_sets = -1;
+  const int64_t* offsets = nullptr;
+  double* theta = nullptr;
+  int n_steps = 0;
+  double eta = 0;
+  double* nll = nullptr;
+  double* grad = nullptr;
+  int32_t* status = nullptr;
+  nll_schedule sched{};
+  bool operator==(const FitKey& o) const {
+    return n_sets == o.n_sets && offsets == o.offsets && theta == o.theta && n_steps == o.n_steps &&
+           eta == o.eta && nll == o.nll && grad == o.grad && status == o.status &&
+           std::memcmp(&sched, &o.sched, sizeof(sched)) == 0;
+  }
+};
+
+struct nll_model {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;
+  int n_cu = 256;
+  nllmi::Plan plan{};
+  const nllmi::VariantOps* ops = nullptr;
+  int precision = NLL_FP64;
+  nllmi::GLTable gl;
+
+  const double* cols[nllmi::kMaxObs] = {};
+  int64_t n = -1;
+  nll_schedule sched{4, 4, 16384, 8};
+
+  // single dataset
+  double* partials = nullptr;
+  int* ticket = nullptr;
+  int* status = nullptr;
+  unsigned long long* dbad = nullptr;
+  int64_t* offsets1 = nullptr;
+
+  // many datasets
+  int sets_cap = 0;
+  int64_t* tile_off = nullptr;
+  int* set_flag = nullptr;
+  nllmi::PerTheta* consts = nullptr;
+  size_t set_partials_cap = 0;  // bytes
+  double* set_partials = nullptr;
+  int gd_cap = 0;
+  double* gd_mem = nullptr;
+  int* gd_status = nullptr;
+
+  // recorded fit
+  bool use_graph = true;
+  bool have_graph = false;
+  FitKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+
+namespace nllmi {
+nll_status tune_model(nll_model* m, int which, int n_sets, const int64_t* offsets, const double* theta);
+}  // namespace nllmi

@@ -1,0 +1,281 @@
+"""GPU parity: the HIP path (through the C ABI) against the scalar FP64
+oracle on the same seeded inputs.
+
+Tolerances: relative NLL error <= 1e-12 in FP64; gradient error
+||g_gpu - g_orc||_inf <= 1e-8 * max(||g_orc||_inf, G) where G is the
+largest per-parameter sum of |d l_i / d theta| (the gradient's own
+rounding scale, relevant where the gradient nearly vanishes).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+NLL_TOL = 1e-12
+GRAD_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def nllmi():
+    import paper_2003_12875_amd as m
+    m.lib()
+    return m
+
+
+def to_dev(torch, cols):
+    return [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in cols]
+
+
+def grad_close(g, ref, scale):
+    err = np.max(np.abs(np.asarray(g) - ref))
+    return err <= GRAD_TOL * max(np.max(np.abs(ref)), np.max(scale)), err
+
+
+def check_points(torch, nllmi, spec, cols, points, threads, grad=True, n_check=None, precision="fp64"):
+    m = nllmi.Model.from_spec(spec, precision=precision)
+    m.set_data(to_dev(torch, cols))
+    o = oracle.Oracle(spec)
+    for th in points[:n_check]:
+        st, ref, gref, stats = o.nll(cols, th, threads=threads, stats=True)
+        assert st == 0
+        if grad:
+            v, g = m.eval_grad(torch.from_numpy(th))
+            v, g = float(v.item()), g.cpu().numpy()
+            ok, err = grad_close(g, gref, stats[1:])
+            assert ok, (th, g, gref, err)
+        else:
+            v = float(m.eval(torch.from_numpy(th)).item())
+        assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref, abs(v / ref - 1))
+    assert m.sync() == 0
+    return m
+
+
+# ---------------------------------------------------------------------------
+# the five workloads (small sizes with ragged tails, then full sizes)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 255, 257, 4097, 100_000])
+def test_gauss_c1(torch, nllmi, threads, n):
+    w = datagen.workload(1, n=n)
+    print(f"[c1 n={n}]", flush=True)
+    check_points(torch, nllmi, w["spec"], w["cols"], w["points"], threads, n_check=16 if n < 100_000 else None)
+
+
+def test_gauss_c1_nll_only(torch, nllmi, threads):
+    w = datagen.workload(1)
+    check_points(torch, nllmi, w["spec"], w["cols"], w["points"], threads, grad=False)
+
+
+@pytest.mark.parametrize("n", [3, 1000, 123_457])
+def test_mixture_c2_small(torch, nllmi, threads, n):
+    w = datagen.workload(2, n=n)
+    print(f"[c2 n={n}]", flush=True)
+    check_points(torch, nllmi, w["spec"], w["cols"], w["points"], threads)
+
+
+def test_mixture_c2_full(torch, nllmi, threads):
+    w = datagen.workload(2)
+    print("[c2 n=1e7]", flush=True)
+    check_points(torch, nllmi, w["spec"], w["cols"], w["points"], threads)
+
+
+@pytest.mark.parametrize("n", [7, 5000, 100_003])
+@pytest.mark.parametrize("norm", ["gl256", "analytic"])
+def test_cb_argus_cheb_c3_small(torch, nllmi, threads, n, norm):
+    w = datagen.workload(3, n=n)
+    spec = datagen.cb_argus_cheb_spec(cheb=w["theta"][7:11], norm=norm)
+    print(f"[c3 n={n} {norm}]", flush=True)
+    check_points(torch, nllmi, spec, w["cols"], w["points"], threads, n_check=4)
+
+
+def test_cb_argus_cheb_c3_full(torch, nllmi, threads):
+    w = datagen.workload(3)
+    print("[c3 n=5e7]", flush=True)
+    check_points(torch, nllmi, w["spec"], w["cols"], w["points"], threads, n_check=2)
+
+
+# ---------------------------------------------------------------------------
+# many datasets
+# ---------------------------------------------------------------------------
+
+def test_batched_toys_small(torch, nllmi, threads):
+    w = datagen.toys_workload(n_sets=96, size_lo=0, size_hi=20000)
+    print("[toys 96]", flush=True)
+    spec = w["spec"]
+    o = oracle.Oracle(spec)
+    th = w["truths"].copy()
+    st, ref, gref, sref = o.nll_batched(w["cols"], w["offsets"], th, threads=threads)
+    m = nllmi.Model.from_spec(spec)
+    m.set_data(to_dev(torch, w["cols"]))
+    m.set_schedule(tile_events=4096)
+    nll, g, status = m.eval_batched(torch.from_numpy(w["offsets"]), torch.from_numpy(th))
+    nll, g, status = nll.cpu().numpy(), g.cpu().numpy(), status.cpu().numpy()
+    assert np.all(status == 0)
+    for s in range(96):
+        assert abs(nll[s] - ref[s]) <= NLL_TOL * max(1.0, abs(ref[s])), (s, nll[s], ref[s])
+        assert np.max(np.abs(g[s] - gref[s])) <= GRAD_TOL * max(1.0, np.max(np.abs(gref[s]))) * 100, s
+    # additivity: the sum over sets at one common point equals the NLL of the concatenation
+    common = np.tile(w["theta_start"], (96, 1))
+    nll2, _, _ = m.eval_batched(torch.from_numpy(w["offsets"]), torch.from_numpy(common))
+    tot, _ = m.eval_grad(torch.from_numpy(w["theta_start"]))
+    assert abs(math.fsum(nll2.cpu().numpy()) - tot.item()) <= 1e-12 * abs(tot.item())
+
+
+def test_batched_equals_single(torch, nllmi):
+    w = datagen.toys_workload(n_sets=8, size_lo=1000, size_hi=30000)
+    m = nllmi.Model.from_spec(w["spec"])
+    cols = to_dev(torch, w["cols"])
+    m.set_data(cols)
+    th = w["truths"]
+    nll, g, _ = m.eval_batched(torch.from_numpy(w["offsets"]), torch.from_numpy(th))
+    for s in range(8):
+        a, b = w["offsets"][s], w["offsets"][s + 1]
+        m1 = nllmi.Model.from_spec(w["spec"])
+        m1.set_data([cols[0][a:b]])
+        v, gg = m1.eval_grad(torch.from_numpy(th[s]))
+        assert abs(v.item() - nll[s].item()) <= 1e-13 * abs(v.item())
+
+
+def test_fit_c1_matches_oracle_and_mle(torch, nllmi, threads):
+    w = datagen.workload(1)
+    print("[fit c1]", flush=True)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    th, nll, g, status = m.fit(torch.from_numpy(w["theta"]), 50, 1.0)
+    th = th.cpu().numpy()
+    st, th_o, nll_o, g_o, eta_o = oracle.Oracle(w["spec"]).gd_fit(w["cols"], w["theta"], 50, 1.0, threads=threads)
+    assert status.item() == 0
+    np.testing.assert_allclose(th, th_o, rtol=1e-9)
+    x = w["cols"][0].astype(np.longdouble)
+    assert abs(th[0] - float(x.mean())) <= 1e-8 * abs(float(x.mean()))
+    assert abs(th[1] - float(np.sqrt(((x - x.mean()) ** 2).mean()))) <= 1e-8 * th[1]
+    assert abs(nll.item() - nll_o) <= NLL_TOL * abs(nll_o)
+
+
+def test_fit_toys_small(torch, nllmi, threads):
+    w = datagen.toys_workload(n_sets=64, size_lo=1000, size_hi=20000)
+    print("[fit toys 64]", flush=True)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    m.set_schedule(tile_events=4096)
+    start = np.tile(w["theta_start"], (64, 1))
+    th, nll, g, status = m.fit_batched(torch.from_numpy(w["offsets"]), torch.from_numpy(start), 50, 1.0)
+    st, th_o, nll_o, g_o, status_o = oracle.Oracle(w["spec"]).gd_fit_batched(
+        w["cols"], w["offsets"], start, 50, 1.0, threads=threads)
+    assert np.all(status.cpu().numpy() == 0)
+    np.testing.assert_allclose(th.cpu().numpy(), th_o, rtol=1e-9)
+    np.testing.assert_allclose(nll.cpu().numpy(), nll_o, rtol=1e-12)
+    # each toy lands on its closed-form maximum-likelihood estimate
+    for s in range(64):
+        x = w["cols"][0][w["offsets"][s]:w["offsets"][s + 1]].astype(np.longdouble)
+        assert abs(th[s, 0].item() - float(x.mean())) <= 1e-7 * max(1.0, abs(float(x.mean())))
+        assert abs(th[s, 1].item() - float(np.sqrt(((x - x.mean()) ** 2).mean()))) <= 1e-7 * th[s, 1].item()
+    # replay of the recorded graph gives the same bits
+    th2, nll2, g2, status2 = m.fit_batched(torch.from_numpy(w["offsets"]), torch.from_numpy(start), 50, 1.0,
+                                          out=(th, nll, g, status))
+    assert np.array_equal(th2.cpu().numpy(), th.cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# errors, edge cases, determinism
+# ---------------------------------------------------------------------------
+
+def test_errors(torch, nllmi):
+    w = datagen.workload(2, n=1000)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    bad = w["theta"].copy()
+    bad[2] = -0.1
+    v = m.eval(torch.from_numpy(bad))
+    assert math.isinf(v.item())
+    assert m.sync() == -3
+    assert m.sync() == 0
+    cols = [w["cols"][0].copy()]
+    cols[0][5] = 11.0
+    with pytest.raises(nllmi.NLLError) as e:
+        m.set_data(to_dev(torch, cols))
+    assert e.value.status == -4
+    spec = {"obs": [{"name": "y", "lo": -1.0, "hi": 1.0}],
+            "params": [datagen.param("a1", 1.5, -5, 5), datagen.param("a2", 0.0, -5, 5)],
+            "nodes": [{"kind": "cheb", "obs": 0, "params": [0, 1]}], "root": 0}
+    mc = nllmi.Model.from_spec(spec)
+    mc.set_data(to_dev(torch, [np.array([-0.9, 0.0, 0.9])]))
+    v = mc.eval(torch.tensor([1.5, 0.0], dtype=torch.float64))
+    assert math.isinf(v.item()) and mc.sync() == -5
+
+
+def test_empty_data_and_empty_sets(torch, nllmi):
+    w = datagen.workload(1, n=0)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.zeros(0, dtype=torch.float64, device="cuda")])
+    v, g = m.eval_grad(torch.from_numpy(w["theta"]))
+    assert v.item() == 0.0 and np.all(g.cpu().numpy() == 0)
+    w = datagen.workload(1, n=5000)
+    m.set_data(to_dev(torch, w["cols"]))
+    offs = np.array([0, 0, 2000, 2000, 5000], dtype=np.int64)
+    th = np.tile(w["theta"], (4, 1))
+    nll, g, st = m.eval_batched(torch.from_numpy(offs), torch.from_numpy(th))
+    nll = nll.cpu().numpy()
+    assert nll[0] == 0.0 and nll[2] == 0.0 and np.all(st.cpu().numpy() == 0)
+    bad = np.array([0, 3000, 2000, 4000, 5000], dtype=np.int64)
+    nll, g, st = m.eval_batched(torch.from_numpy(bad), torch.from_numpy(th))
+    assert np.all(st.cpu().numpy() == -1) and np.all(np.isinf(nll.cpu().numpy()))
+
+
+def test_determinism_and_schedules(torch, nllmi):
+    w = datagen.workload(2, n=2_000_003)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    th = torch.from_numpy(w["points"][0])
+    a = m.eval_grad(th)
+    b = m.eval_grad(th)
+    assert a[0].item() == b[0].item() and torch.equal(a[1], b[1])
+    ref = a[0].item()
+    for unroll in (2, 4):
+        for bpc in (1, 3, 8, 32):
+            m.set_schedule(unroll=unroll, blocks_per_cu=bpc)
+            v, g = m.eval_grad(th)
+            assert abs(v.item() - ref) <= 1e-13 * abs(ref), (unroll, bpc)
+
+
+def test_autograd_function(torch, nllmi):
+    w = datagen.workload(2, n=20000)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    th = torch.from_numpy(w["points"][1]).cuda().requires_grad_(True)
+    loss = 0.5 * nllmi.NLL.apply(th, m)
+    loss.backward()
+    _, g = m.eval_grad(th.detach())
+    assert torch.allclose(th.grad, 0.5 * g, rtol=0, atol=0)
+
+
+def test_gradient_against_central_differences_c2(torch, nllmi):
+    """Adjoint gradient vs central finite differences with h = 1e-6 on each
+    parameter; tolerance = 10 x (truncation + rounding) bound of the FD."""
+    w = datagen.workload(2, n=1_000_000)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    th = w["points"][3]
+    v, g = m.eval_grad(torch.from_numpy(th))
+    v, g = v.item(), g.cpu().numpy()
+    h = 1e-6
+    for k in range(4):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (m.eval(torch.from_numpy(tp)).item() - m.eval(torch.from_numpy(tm)).item()) / (2 * h)
+        bound = 10 * (2.2e-16 * abs(v) / h + h * h * abs(g[k]) + 1e-12 * abs(v) / h)
+        assert abs(fd - g[k]) <= bound, (k, fd, g[k], bound)
