@@ -206,6 +206,20 @@ nll_status nll_set_schedule(nll_model* model, const nll_schedule* sched);
 nll_status nll_autotune(nll_model* model, int32_t which, int32_t n_sets, const int64_t* offsets,
                         const double* theta);
 
+/* Options (nll_set_option):
+ *   NLL_OPT_GRAPH        1 (default): fits are recorded once into a HIP graph
+ *                        and replayed; 0: fits are enqueued eagerly
+ *   NLL_OPT_STEP_TIMING  1: fits are enqueued eagerly with a HIP event before
+ *                        the first and after every step, read by
+ *                        nll_step_times; 0 (default): no events            */
+enum nll_option { NLL_OPT_GRAPH = 1, NLL_OPT_STEP_TIMING = 2 };
+nll_status nll_set_option(nll_model* model, int32_t option, int32_t value);
+
+/* Synchronise and copy the duration in milliseconds of each step of the most
+ * recent fit run with NLL_OPT_STEP_TIMING on (at most cap values; the count is
+ * written to *n).  NLL_ERR_STATE if no timed fit has run. */
+nll_status nll_step_times(nll_model* model, float* ms, int32_t cap, int32_t* n);
+
 typedef struct nll_info {
   char variant[64];   /* compiled shape the model was lowered onto */
   int32_t n_leaf, n_term, n_accumulators, precision;

@@ -192,12 +192,19 @@ class Model:
                                     _ptr(g), _ptr(status)), "nll_fit_batched")
         return th, nll, g, status
 
-    def fit(self, theta, n_steps: int, eta: float = 1.0):
+    def fit(self, theta, n_steps: int, eta: float = 1.0, out=None):
+        """Gradient-descent fit on all attached events (see nll_fit).  Pass
+        out=(theta, nll, grad, status) tensors to reuse buffers (and the
+        recorded graph) across calls."""
         torch = _torch()
-        th = _dev_tensor(theta, torch.float64, self.device).clone()
-        nll = torch.empty(1, dtype=torch.float64, device=self.device)
-        g = torch.empty(self.n_param, dtype=torch.float64, device=self.device)
-        status = torch.empty(1, dtype=torch.int32, device=self.device)
+        if out is None:
+            th = _dev_tensor(theta, torch.float64, self.device).clone()
+            nll = torch.empty(1, dtype=torch.float64, device=self.device)
+            g = torch.empty(self.n_param, dtype=torch.float64, device=self.device)
+            status = torch.empty(1, dtype=torch.int32, device=self.device)
+        else:
+            th, nll, g, status = out
+            th.copy_(_dev_tensor(theta, torch.float64, self.device))
         self._bind_stream()
         check(lib().nll_fit(self._h, _ptr(th), int(n_steps), float(eta), _ptr(nll), _ptr(g), _ptr(status)), "nll_fit")
         return th, nll, g, status
@@ -235,6 +242,18 @@ class Model:
             theta = _dev_tensor(theta, torch.float64, self.device).reshape(n_sets, self.n_param).contiguous()
             check(lib().nll_autotune(self._h, 2, n_sets, _ptr(offsets), _ptr(theta)), "nll_autotune")
         return self.schedule
+
+    def set_option(self, option: str, value: bool):
+        code = {"graph": 1, "step_timing": 2}[option]
+        check(lib().nll_set_option(self._h, code, 1 if value else 0), "nll_set_option")
+
+    def step_times(self, cap: int = 1 << 16):
+        """Per-step durations (ms) of the last fit run with step timing on."""
+        buf = (ctypes.c_float * cap)()
+        n = ctypes.c_int32(0)
+        self._bind_stream()
+        check(lib().nll_step_times(self._h, buf, cap, ctypes.byref(n)), "nll_step_times")
+        return [buf[i] for i in range(n.value)]
 
     @property
     def info(self) -> dict:

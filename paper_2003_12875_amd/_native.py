@@ -16,7 +16,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported model shape", -3: "p
 # every entry point declared in include/nll.h
 EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_data", "nll_eval",
            "nll_eval_grad", "nll_eval_batched", "nll_fit_batched", "nll_fit", "nll_sync", "nll_get_schedule",
-           "nll_set_schedule", "nll_autotune", "nll_get_info", "nll_status_string")
+           "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
+           "nll_status_string")
 
 
 class NLLError(RuntimeError):
@@ -80,6 +81,8 @@ def lib():
         L.nll_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
         L.nll_autotune.argtypes = [vp, i32, i32, vp, vp]
         L.nll_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.nll_set_option.argtypes = [vp, i32, i32]
+        L.nll_step_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         L.nll_status_string.argtypes = [i32]
         L.nll_status_string.restype = ctypes.c_char_p
         for f in EXPORTS:

@@ -283,6 +283,30 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
     pl.leaf_norm[s] = nd.norm;
     pl.leaf_root[s] = root[l];
   }
+  // Flat shapes (as many non-root leaves as terms): term k must be the one
+  // whose only non-root leaf sits in the k-th non-root slot.
+  int n_nonroot = 0;
+  for (int l = 0; l < L; ++l) n_nonroot += root[l] ? 0 : 1;
+  if (K > 1 && n_nonroot == K) {
+    std::vector<Term> ordered;
+    for (int sidx = 0; sidx < L; ++sidx) {
+      const int l = perm[sidx];
+      if (root[l]) continue;
+      int found_k = -1, count = 0;
+      for (int k = 0; k < K; ++k) {
+        int nr = 0;
+        for (int q = 0; q < L; ++q)
+          if (((terms[k].mask >> q) & 1u) && !root[q]) ++nr;
+        if (nr == 1 && ((terms[k].mask >> l) & 1u)) {
+          found_k = k;
+          ++count;
+        }
+      }
+      if (count != 1) return NLL_ERR_UNSUPPORTED;
+      ordered.push_back(terms[found_k]);
+    }
+    terms.swap(ordered);
+  }
   pl.n_term = K;
   for (int k = 0; k < K; ++k) {
     uint32_t m = 0;
@@ -394,6 +418,56 @@ SetsArgs sets_args(const nll_model* m, int n_sets, const int64_t* offsets) {
 
 int sets_grid(const nll_model* m) { return std::max(1, m->n_cu * m->sched.sets_blocks_per_cu); }
 
+SingleArgs single_args(const nll_model* m, const double* theta, double* nll_out, double* grad_out) {
+  SingleArgs a{};
+  for (int o = 0; o < kMaxObs; ++o) a.cols[o] = m->cols[o];
+  a.n = m->n;
+  a.theta = theta;
+  a.nll_out = nll_out;
+  a.grad_out = grad_out;
+  a.partials = m->partials;
+  a.pt_out = m->pt_single;
+  a.status = m->status;
+  a.glx = m->gl.x;
+  a.glw = m->gl.w;
+  return a;
+}
+
+// (re)create the step events of a timed fit
+nll_status ensure_events(nll_model* m, int n_steps) {
+  if (!m->step_timing) return NLL_OK;
+  while ((int)m->events.size() < n_steps + 1) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return NLL_ERR_DEVICE;
+    m->events.push_back(e);
+    m->have_graph = false;
+  }
+  return NLL_OK;
+}
+
+void record_step(nll_model* m, int s, hipStream_t st) {
+  if (m->step_timing) (void)hipEventRecord(m->events[s], st);
+}
+
+// a whole single-dataset fit: one persistent launch per step, the last
+// block of each launch takes the gradient-descent step
+nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n_steps, double eta, double* nll_out,
+                              double* grad_out, int32_t* status_out) {
+  GDState gd = gd_state(m);
+  hipError_t e = m->ops->fit_init(m->plan, theta, 1, eta, gd, m->consts, m->gl.x, m->gl.w, st);
+  if (e != hipSuccess) return NLL_ERR_DEVICE;
+  SingleArgs a = single_args(m, nullptr, nullptr, nullptr);
+  a.gd = gd;
+  record_step(m, 0, st);
+  for (int s = 0; s < n_steps; ++s) {
+    e = m->ops->single_fit(m->plan, a, m->sched.unroll, single_grid(m), st);
+    if (e != hipSuccess) return NLL_ERR_DEVICE;
+    record_step(m, s + 1, st);
+  }
+  e = launch_fit_final(1, m->plan.n_param, gd, theta, nll_out, grad_out, reinterpret_cast<int*>(status_out), st);
+  return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+}
+
 // enqueue a whole fit on stream st
 nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* offsets, double* theta,
                        int n_steps, double eta, double* nll_out, double* grad_out, int32_t* status_out) {
@@ -404,12 +478,46 @@ nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* 
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   e = m->ops->fit_init(m->plan, theta, n_sets, eta, gd, m->consts, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
+  record_step(m, 0, st);
   for (int s = 0; s < n_steps; ++s) {
     e = m->ops->sets(m->plan, a, true, true, sets_grid(m), st);
     if (e != hipSuccess) return NLL_ERR_DEVICE;
+    record_step(m, s + 1, st);
   }
   e = launch_fit_final(n_sets, m->plan.n_param, gd, theta, nll_out, grad_out, reinterpret_cast<int*>(status_out), st);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+}
+
+// Enqueue through the model's recorded graph: capture once per argument
+// set on the library's own stream, replay on the model's stream.
+// Step timing runs eagerly: events recorded as nodes of a captured graph do
+// not yield elapsed times.
+template <class F>
+nll_status run_recorded(nll_model* m, const FitKey& k, F&& enqueue) {
+  if (!m->use_graph || m->step_timing) return enqueue(m->stream);
+  if (!(m->have_graph && m->key == k)) {
+    if (m->exec) (void)hipGraphExecDestroy(m->exec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    m->exec = nullptr;
+    m->graph = nullptr;
+    m->have_graph = false;
+    if (hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return NLL_ERR_DEVICE;
+    nll_status est = enqueue(m->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(m->capture, &g);
+    if (est != NLL_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return est != NLL_OK ? est : NLL_ERR_DEVICE;
+    }
+    if (hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return NLL_ERR_DEVICE;
+    }
+    m->graph = g;
+    m->key = k;
+    m->have_graph = true;
+  }
+  return hipGraphLaunch(m->exec, m->stream) == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
 
 }  // namespace
@@ -463,11 +571,11 @@ nll_status nll_create_model(const nll_model_desc* desc, nll_model** out) {
   if ((st = gl_table(m->device, &m->gl)) != NLL_OK) return fail(st);
   const size_t max_grid = (size_t)m->n_cu * 32;
   if ((st = dalloc(&m->partials, max_grid * (size_t)(ops->na_grad + 1) * 2)) != NLL_OK) return fail(st);
-  if ((st = dalloc(&m->ticket, 1)) != NLL_OK) return fail(st);
+  if ((st = dalloc(&m->pt_single, 1)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->status, 1)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->dbad, 1)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->offsets1, 2)) != NLL_OK) return fail(st);
-  if (hipMemset(m->ticket, 0, sizeof(int)) != hipSuccess || hipMemset(m->status, 0, sizeof(int)) != hipSuccess)
+  if (hipMemset(m->status, 0, sizeof(int)) != hipSuccess)
     return fail(NLL_ERR_DEVICE);
   if (hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking) != hipSuccess) return fail(NLL_ERR_DEVICE);
   *out = m;
@@ -481,8 +589,9 @@ void nll_destroy_model(nll_model* m) {
   if (m->exec) (void)hipGraphExecDestroy(m->exec);
   if (m->graph) (void)hipGraphDestroy(m->graph);
   if (m->capture) (void)hipStreamDestroy(m->capture);
+  for (hipEvent_t e : m->events) (void)hipEventDestroy(e);
   dfree(m->partials);
-  dfree(m->ticket);
+  dfree(m->pt_single);
   dfree(m->status);
   dfree(m->dbad);
   dfree(m->offsets1);
@@ -530,17 +639,7 @@ static nll_status nll_eval_impl(nll_model* m, const double* theta, double* nll_o
   if (!m || !theta || !nll_out || (grad && !grad_out)) return NLL_ERR_ARG;
   if (m->n < 0) return NLL_ERR_STATE;
   DeviceGuard guard(m->device);
-  SingleArgs a{};
-  for (int o = 0; o < kMaxObs; ++o) a.cols[o] = m->cols[o];
-  a.n = m->n;
-  a.theta = theta;
-  a.nll_out = nll_out;
-  a.grad_out = grad_out;
-  a.partials = m->partials;
-  a.ticket = m->ticket;
-  a.status = m->status;
-  a.glx = m->gl.x;
-  a.glw = m->gl.w;
+  SingleArgs a = single_args(m, theta, nll_out, grad_out);
   hipError_t e = m->ops->single(m->plan, a, grad, m->sched.unroll, single_grid(m), m->stream);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
@@ -585,9 +684,11 @@ nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets,
   nll_status st = ensure_sets(m, n_sets);
   if (st != NLL_OK) return st;
   if ((st = ensure_gd(m, n_sets)) != NLL_OK) return st;
-  if (!m->use_graph) return enqueue_fit(m, m->stream, n_sets, offsets, theta, n_steps, eta, nll_out, grad_out, status_out);
-
   FitKey k;
+  k.mode = 2;
+  k.timing = m->step_timing;
+  if ((st = ensure_events(m, n_steps)) != NLL_OK) return st;
+  m->timed_steps = m->step_timing ? n_steps : -1;
   k.n_sets = n_sets;
   k.offsets = offsets;
   k.theta = theta;
@@ -597,36 +698,35 @@ nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets,
   k.grad = grad_out;
   k.status = status_out;
   k.sched = m->sched;
-  if (!(m->have_graph && m->key == k)) {
-    if (m->exec) (void)hipGraphExecDestroy(m->exec);
-    if (m->graph) (void)hipGraphDestroy(m->graph);
-    m->exec = nullptr;
-    m->graph = nullptr;
-    m->have_graph = false;
-    if (hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return NLL_ERR_DEVICE;
-    nll_status est = enqueue_fit(m, m->capture, n_sets, offsets, theta, n_steps, eta, nll_out, grad_out, status_out);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(m->capture, &g);
-    if (est != NLL_OK || e != hipSuccess || !g) {
-      if (g) (void)hipGraphDestroy(g);
-      return est != NLL_OK ? est : NLL_ERR_DEVICE;
-    }
-    if (hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return NLL_ERR_DEVICE;
-    }
-    m->graph = g;
-    m->key = k;
-    m->have_graph = true;
-  }
-  return hipGraphLaunch(m->exec, m->stream) == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+  return run_recorded(m, k, [&](hipStream_t st) {
+    return enqueue_fit(m, st, n_sets, offsets, theta, n_steps, eta, nll_out, grad_out, status_out);
+  });
 }
 
 nll_status nll_fit(nll_model* m, double* theta, int32_t n_steps, double eta, double* nll_out, double* grad_out,
                    int32_t* status_out) {
-  if (!m) return NLL_ERR_ARG;
+  if (!m || !theta || !nll_out || n_steps < 0 || !(eta > 0.0)) return NLL_ERR_ARG;
   if (m->n < 0) return NLL_ERR_STATE;
-  return nll_fit_batched(m, 1, m->offsets1, theta, n_steps, eta, nll_out, grad_out, status_out);
+  DeviceGuard guard(m->device);
+  nll_status st = ensure_sets(m, 1);
+  if (st != NLL_OK) return st;
+  if ((st = ensure_gd(m, 1)) != NLL_OK) return st;
+  FitKey k;
+  k.mode = 1;
+  k.timing = m->step_timing;
+  if ((st = ensure_events(m, n_steps)) != NLL_OK) return st;
+  m->timed_steps = m->step_timing ? n_steps : -1;
+  k.n_sets = 1;
+  k.theta = theta;
+  k.n_steps = n_steps;
+  k.eta = eta;
+  k.nll = nll_out;
+  k.grad = grad_out;
+  k.status = status_out;
+  k.sched = m->sched;
+  return run_recorded(m, k, [&](hipStream_t s) {
+    return enqueue_fit_single(m, s, theta, n_steps, eta, nll_out, grad_out, status_out);
+  });
 }
 
 nll_status nll_sync(nll_model* m, int32_t* status_out) {
@@ -666,6 +766,31 @@ nll_status nll_autotune(nll_model* m, int32_t which, int32_t n_sets, const int64
   if (m->n < 0) return NLL_ERR_STATE;
   DeviceGuard guard(m->device);
   return tune_model(m, which, n_sets, offsets, theta);
+}
+
+nll_status nll_set_option(nll_model* m, int32_t option, int32_t value) {
+  if (!m) return NLL_ERR_ARG;
+  if (option == NLL_OPT_GRAPH) {
+    m->use_graph = value != 0;
+  } else if (option == NLL_OPT_STEP_TIMING) {
+    m->step_timing = value != 0;
+  } else {
+    return NLL_ERR_ARG;
+  }
+  m->have_graph = false;
+  return NLL_OK;
+}
+
+nll_status nll_step_times(nll_model* m, float* ms, int32_t cap, int32_t* n) {
+  if (!m || !n || cap < 0 || (cap > 0 && !ms)) return NLL_ERR_ARG;
+  if (m->timed_steps < 0) return NLL_ERR_STATE;
+  DeviceGuard guard(m->device);
+  if (hipStreamSynchronize(m->stream) != hipSuccess) return NLL_ERR_DEVICE;
+  const int k = std::min(cap, m->timed_steps);
+  for (int s = 0; s < k; ++s)
+    if (hipEventElapsedTime(&ms[s], m->events[s], m->events[s + 1]) != hipSuccess) return NLL_ERR_DEVICE;
+  *n = k;
+  return NLL_OK;
 }
 
 nll_status nll_get_info(const nll_model* m, nll_info* out) {

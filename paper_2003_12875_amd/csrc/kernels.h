@@ -11,20 +11,7 @@
 
 namespace nllmi {
 
-struct SingleArgs {
-  const double* cols[kMaxObs];  // SoA event columns (device)
-  int64_t n;
-  const double* theta;          // n_param (device)
-  double* nll_out;              // 1 (device)
-  double* grad_out;             // n_param (device) or null
-  double* partials;             // grid * (NA + 1) double-double pairs
-  int* ticket;                  // zero between launches
-  int* status;                  // accumulated status bits
-  const double* glx;            // 256-point Gauss-Legendre rule on [-1, 1]
-  const double* glw;
-};
-
-// State of a batched gradient-descent fit (device arrays).
+// State of a gradient-descent fit (device arrays).
 struct GDState {
   double* th_acc;   // n_sets * P  last accepted point
   double* g_acc;    // n_sets * P  its gradient
@@ -32,6 +19,20 @@ struct GDState {
   double* f_acc;    // n_sets      its NLL (+inf before the first acceptance)
   double* eta;      // n_sets      step size
   int* last_status; // n_sets
+};
+
+struct SingleArgs {
+  const double* cols[kMaxObs];  // SoA event columns (device)
+  int64_t n;
+  const double* theta;          // n_param (device)
+  double* nll_out;              // 1 (device)
+  double* grad_out;             // n_param (device) or null
+  double* partials;             // grid * (NA + 1) double-double pairs
+  PerTheta* pt_out;             // per-point constants left by block 0
+  int* status;                  // accumulated status bits
+  const double* glx;            // 256-point Gauss-Legendre rule on [-1, 1]
+  const double* glw;
+  GDState gd;                   // fit mode: theta = gd.th_prop, set 0
 };
 
 struct SetsArgs {
@@ -58,6 +59,7 @@ struct VariantOps {
   int kind[kMaxLeaves], obs[kMaxLeaves], root[kMaxLeaves], np[kMaxLeaves];
   int precision;  // 0: FP64
   hipError_t (*single)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, hipStream_t);
+  hipError_t (*single_fit)(const Plan&, const SingleArgs&, int unroll, int grid, hipStream_t);
   hipError_t (*consts)(const Plan&, const double* theta, int n_sets, PerTheta* out, const double* glx,
                        const double* glw, hipStream_t);
   hipError_t (*sets)(const Plan&, const SetsArgs&, bool grad, bool fit, int grid, hipStream_t);

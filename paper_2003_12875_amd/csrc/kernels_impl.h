@@ -85,20 +85,81 @@ __device__ int finish(const Plan& pl, const PerTheta& pt, const DD* tot, int64_t
   return status;
 }
 
+// Gradient descent on the mean NLL with step halving, by a whole block:
+// thread 0 accepts the evaluated proposal when its NLL is finite and exceeds
+// the last accepted one by at most 4 ulps (rounding noise), else halves the
+// step; then thread q forms the next proposal theta_acc - eta g_acc / N of
+// parameter q (free parameters only).  st/nll/grad are valid in thread 0;
+// grad is in shared memory.
+__device__ inline void gd_update(const Plan& pl, const GDState& gd, int s, int st, double nll,
+                                 const double* grad, int64_t n_s) {
+  __shared__ int s_ok;
+  __shared__ double s_step;
+  const int P = pl.n_param;
+  if (threadIdx.x == 0) {
+    const double fa = gd.f_acc[s];
+    const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
+    if (ok) {
+      gd.f_acc[s] = nll;
+      gd.last_status[s] = 0;
+    } else {
+      gd.eta[s] *= 0.5;
+      if (!__builtin_isfinite(fa)) gd.last_status[s] = st != 0 ? st : -5;
+    }
+    s_ok = ok;
+    s_step = gd.eta[s] / (double)(n_s > 0 ? n_s : 1);
+  }
+  __syncthreads();
+  const int q = threadIdx.x;
+  if (q < P) {
+    double* th_acc = gd.th_acc + (size_t)s * P;
+    double* g_acc = gd.g_acc + (size_t)s * P;
+    double* th_prop = gd.th_prop + (size_t)s * P;
+    double acc = th_acc[q], ga = g_acc[q];
+    if (s_ok) {
+      acc = th_prop[q];
+      ga = grad[q];
+      th_acc[q] = acc;
+      g_acc[q] = ga;
+    }
+    th_prop[q] = pl.par_free[q] ? acc - s_step * ga : acc;
+  }
+}
+
 // ------------------------------------------------------------------------
 // per-tile event loops
 // ------------------------------------------------------------------------
-template <class M, bool GRAD, int U>
-__device__ inline void stream_full_tile(const double* const* cols, int64_t base, const Consts<M>& C,
-                                        Acc<M, GRAD>& acc) {
-  double x[U][M::NOBS];
+template <class M, int U>
+__device__ inline void load_tile(const double* const* cols, int64_t base, double (&x)[U][M::NOBS]) {
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int o = 0; o < M::NOBS; ++o) x[u][o] = cols[o][base + (int64_t)u * kBlock];
+}
+
+template <class M, bool GRAD, int U>
+__device__ inline void compute_tile(const double (&x)[U][M::NOBS], const Consts<M>& C, Acc<M, GRAD>& acc) {
 #pragma unroll
   for (int u = 0; u < U; ++u) model_event<M, GRAD>(x[u], C, acc);
   acc.renorm();
+}
+
+// Full tiles base0, base0 + stride, ... (count of them), software
+// pipelined: the first tile arrives preloaded in xn, and the loads of the
+// next tile are issued before the current one is computed so that two tiles
+// of loads are in flight per wave.
+template <class M, bool GRAD, int U>
+__device__ inline void stream_tiles(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
+                                    double (&xn)[U][M::NOBS], const Consts<M>& C, Acc<M, GRAD>& acc) {
+  for (int64_t k = 0; k < count; ++k) {
+    double xc[U][M::NOBS];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int o = 0; o < M::NOBS; ++o) xc[u][o] = xn[u][o];
+    if (k + 1 < count) load_tile<M, U>(cols, base0 + (k + 1) * stride, xn);
+    compute_tile<M, GRAD, U>(xc, C, acc);
+  }
 }
 
 template <class M, bool GRAD, int U>
@@ -120,7 +181,11 @@ __device__ inline void stream_part_tile(const double* const* cols, int64_t base,
 // ------------------------------------------------------------------------
 // single dataset
 // ------------------------------------------------------------------------
-template <class M, bool GRAD, int U>
+// Streaming pass over one dataset: per-block prologue, the block's tiles,
+// one compensated partial per block (plain stores; the next kernel on the
+// stream reads them).  Block 0 also leaves its per-point constants for the
+// finishing kernel.
+template <class M, bool GRAD, int U, bool FIT = false>
 __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleArgs a) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;  // + invalid-event count
@@ -128,23 +193,26 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   __shared__ DD red[4 * NV];
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
-  __shared__ double s_grad[kMaxParams];
-  __shared__ int s_last;
 
-  compute_pertheta<M>(pl, a.theta, a.glx, a.glw, &pt, small);
+  const double* cols[M::NOBS];
+#pragma unroll
+  for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
+  const int64_t tile = (int64_t)kBlock * U;
+  const int64_t nfull = a.n / tile;
+  const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t base0 = (int64_t)blockIdx.x * tile + threadIdx.x;
+  // the first tile does not depend on theta: its loads overlap the prologue
+  double xn[U][M::NOBS];
+  if (mine > 0) load_tile<M, U>(cols, base0, xn);
+
+  const double* theta = FIT ? a.gd.th_prop : a.theta;
+  compute_pertheta<M>(pl, theta, a.glx, a.glw, &pt, small);
   Consts<M> C;
   C.load(pt, pl);
   Acc<M, GRAD> acc;
   acc.init();
-  const double* cols[M::NOBS];
-#pragma unroll
-  for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
-
   if (uniform(pt.bad) == 0) {
-    const int64_t tile = (int64_t)kBlock * U;
-    const int64_t nfull = a.n / tile;
-    for (int64_t t = blockIdx.x; t < nfull; t += gridDim.x)
-      stream_full_tile<M, GRAD, U>(cols, t * tile + threadIdx.x, C, acc);
+    stream_tiles<M, GRAD, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xn, C, acc);
     const int64_t rest = nfull * tile;
     if (rest < a.n && blockIdx.x == (unsigned)(nfull % gridDim.x))
       stream_part_tile<M, GRAD, U>(cols, rest + threadIdx.x, a.n, C, acc);
@@ -156,33 +224,49 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   for (int j = 0; j < NA; ++j) v[j] = DD{acc.a[j], 0.0};
   v[NA] = DD{(double)acc.bad, 0.0};
   block_sum_dd<NV>(v, red, tot);
-  if (threadIdx.x < NV) store_dd(&reinterpret_cast<DD*>(a.partials)[(size_t)blockIdx.x * NV + threadIdx.x], tot[threadIdx.x]);
-  __syncthreads();
+  if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
+  if (blockIdx.x == 0) {
+    const double* src = reinterpret_cast<const double*>(&pt);
+    double* dst = reinterpret_cast<double*>(a.pt_out);
+    for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kBlock) dst[i] = src[i];
+  }
+}
+
+// Finishing kernel (one block of kFinishBlock threads): the block partials
+// in block order, then NLL and gradient; in fit mode the gradient-descent
+// step of the proposal just evaluated.
+template <class M, bool GRAD, bool FIT = false>
+__global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, const SingleArgs a, int n_blocks) {
+  constexpr int NA = M::template NA<GRAD>;
+  constexpr int NV = NA + 1;
+  __shared__ DD red[kFinishBlock];
+  __shared__ DD tot[NV];
+  __shared__ double s_grad[kMaxParams];
+  __shared__ PerTheta spt;
+  __shared__ double s_theta[kMaxParams];
+  __shared__ double s_nll;
+  __shared__ int s_st;
+  {  // one parallel copy of the per-point constants and theta
+    const double* src = reinterpret_cast<const double*>(a.pt_out);
+    double* dst = reinterpret_cast<double*>(&spt);
+    for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kFinishBlock) dst[i] = src[i];
+    const double* th = FIT ? a.gd.th_prop : a.theta;
+    if (threadIdx.x < pl.n_param) s_theta[threadIdx.x] = th[threadIdx.x];
+  }
+  sum_records<NV, kFinishBlock>(reinterpret_cast<const DD*>(a.partials), n_blocks, red, tot);
   if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(a.ticket, 1) == (int)gridDim.x - 1;
+    s_st = finish<M, GRAD>(pl, spt, tot, (int64_t)(tot[NA].hi + tot[NA].lo), a.n, s_theta, &s_nll, s_grad);
   }
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  DD g[NV];
-#pragma unroll
-  for (int j = 0; j < NV; ++j) g[j] = DD{0.0, 0.0};
-#pragma unroll 1
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
-#pragma unroll
-    for (int j = 0; j < NV; ++j) g[j] = dd_add(g[j], load_dd(&reinterpret_cast<const DD*>(a.partials)[(size_t)b * NV + j]));
-  }
-  block_sum_dd<NV>(g, red, tot);
-  if (threadIdx.x == 0) {
-    double nll;
-    const int st = finish<M, GRAD>(pl, pt, tot, (int64_t)(tot[NA].hi + tot[NA].lo), a.n, a.theta, &nll, s_grad);
-    *a.nll_out = nll;
-    if (GRAD && a.grad_out)
-      for (int q = 0; q < pl.n_param; ++q) a.grad_out[q] = s_grad[q];
-    if (st == -3) atomicOr(a.status, (int)kStatusParam);
-    if (st == -5) atomicOr(a.status, (int)kStatusPdf);
-    __hip_atomic_store(a.ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if constexpr (FIT) {
+    gd_update(pl, a.gd, 0, s_st, s_nll, s_grad, a.n);
+  } else {
+    if (threadIdx.x == 0) {
+      *a.nll_out = s_nll;
+      if (s_st == -3) atomicOr(a.status, (int)kStatusParam);
+      if (s_st == -5) atomicOr(a.status, (int)kStatusPdf);
+    }
+    if (GRAD && a.grad_out && threadIdx.x < pl.n_param) a.grad_out[threadIdx.x] = s_grad[threadIdx.x];
   }
 }
 
@@ -235,8 +319,11 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     acc.init();
     if (uniform(pt.bad) == 0 && flag == 0) {
       const int64_t step = (int64_t)kBlock * U;
-      int64_t base = start;
-      for (; base + step <= end; base += step) stream_full_tile<M, GRAD, U>(cols, base + threadIdx.x, C, acc);
+      const int64_t full = (end - start) / step;
+      double xn[U][M::NOBS];
+      if (full > 0) load_tile<M, U>(cols, start + threadIdx.x, xn);
+      stream_tiles<M, GRAD, U>(cols, start + threadIdx.x, step, full, xn, C, acc);
+      const int64_t base = start + full * step;
       if (base < end) stream_part_tile<M, GRAD, U>(cols, base + threadIdx.x, end, C, acc);
     }
     acc.close();
@@ -256,63 +343,48 @@ template <class M, bool GRAD, bool FIT>
 __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const SetsArgs a) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
-  __shared__ DD red[4 * NV];
+  __shared__ DD red[kBlock];
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
   __shared__ double s_grad[kMaxParams];
+  __shared__ PerTheta spt;
+  __shared__ double s_theta[kMaxParams];
+  __shared__ double s_nll;
+  __shared__ int s_st;
   const int s = blockIdx.x;
   if (s >= a.n_sets) return;
   const int P = pl.n_param;
-  const int64_t first = a.tile_off[s], n_items = a.tile_off[s + 1] - first;
-  DD g[NV];
-#pragma unroll
-  for (int j = 0; j < NV; ++j) g[j] = DD{0.0, 0.0};
-#pragma unroll 1
-  for (int64_t it = threadIdx.x; it < n_items; it += kBlock) {
-    const DD* src = reinterpret_cast<const DD*>(a.partials) + (size_t)(first + it) * NV;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) g[j] = dd_add(g[j], src[j]);
+  {  // one parallel copy of the set's constants and parameters
+    const double* src = reinterpret_cast<const double*>(&a.consts[s]);
+    double* dst = reinterpret_cast<double*>(&spt);
+    for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kBlock) dst[i] = src[i];
+    const double* th = FIT ? a.gd.th_prop + (size_t)s * P : a.theta + (size_t)s * P;
+    if (threadIdx.x < P) s_theta[threadIdx.x] = th[threadIdx.x];
   }
-  block_sum_dd<NV>(g, red, tot);
+  const int64_t first = a.tile_off[s], n_items = a.tile_off[s + 1] - first;
+  sum_records<NV, kBlock>(reinterpret_cast<const DD*>(a.partials) + (size_t)first * NV, n_items, red, tot);
   const int flag = a.set_flag[s];
   const int64_t n_s = flag ? 0 : a.offsets[s + 1] - a.offsets[s];
-  const double* th = FIT ? a.gd.th_prop + (size_t)s * P : a.theta + (size_t)s * P;
   if (threadIdx.x == 0) {
     double nll;
-    int st = finish<M, GRAD>(pl, a.consts[s], tot, (int64_t)(tot[NA].hi + tot[NA].lo), n_s, th, &nll, s_grad);
+    int st = finish<M, GRAD>(pl, spt, tot, (int64_t)(tot[NA].hi + tot[NA].lo), n_s, s_theta, &nll, s_grad);
     if (flag) {
       st = -1;
       nll = __builtin_inf();
     }
-    if constexpr (!FIT) {
-      a.nll_out[s] = nll;
-      if (GRAD && a.grad_out)
-        for (int q = 0; q < P; ++q) a.grad_out[(size_t)s * P + q] = st == 0 ? s_grad[q] : 0.0;
-      if (a.status_out) a.status_out[s] = st;
-    } else {
-      // gradient descent on the mean NLL, halving the step on a rejection
-      double* th_acc = a.gd.th_acc + (size_t)s * P;
-      double* g_acc = a.gd.g_acc + (size_t)s * P;
-      double* th_prop = a.gd.th_prop + (size_t)s * P;
-      // an increase of at most 4 ulps of the NLL is rounding noise, not an increase
-      const double fa = a.gd.f_acc[s];
-      const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
-      if (ok) {
-        for (int q = 0; q < P; ++q) {
-          th_acc[q] = th_prop[q];
-          g_acc[q] = s_grad[q];
-        }
-        a.gd.f_acc[s] = nll;
-        a.gd.last_status[s] = 0;
-      } else {
-        a.gd.eta[s] *= 0.5;
-        if (!__builtin_isfinite(a.gd.f_acc[s])) a.gd.last_status[s] = st != 0 ? st : -5;
-      }
-      const double step = a.gd.eta[s] / (double)(n_s > 0 ? n_s : 1);
-      for (int q = 0; q < P; ++q) th_prop[q] = pl.par_free[q] ? th_acc[q] - step * g_acc[q] : th_acc[q];
-    }
+    s_st = st;
+    s_nll = nll;
   }
-  if constexpr (FIT) {
+  __syncthreads();
+  if constexpr (!FIT) {
+    if (threadIdx.x == 0) {
+      a.nll_out[s] = s_nll;
+      if (a.status_out) a.status_out[s] = s_st;
+    }
+    if (GRAD && a.grad_out && threadIdx.x < P)
+      a.grad_out[(size_t)s * P + threadIdx.x] = s_st == 0 ? s_grad[threadIdx.x] : 0.0;
+  } else {
+    gd_update(pl, a.gd, s, s_st, s_nll, s_grad, n_s);
     __syncthreads();
     compute_pertheta<M>(pl, a.gd.th_prop + (size_t)s * P, a.glx, a.glw, &a.consts[s], small);
   }
@@ -353,10 +425,21 @@ struct Launch {
     hipLaunchKernelGGL((k_single<M, GRAD, U>), dim3(grid), dim3(kBlock), 0, st, pl, a);
     return hipGetLastError();
   }
+  template <bool GRAD, bool FIT>
+  static hipError_t single_t(const Plan& pl, const SingleArgs& a, int unroll, int grid, hipStream_t st) {
+    if (unroll >= 4) hipLaunchKernelGGL((k_single<M, GRAD, 4, FIT>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+    else hipLaunchKernelGGL((k_single<M, GRAD, 2, FIT>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_single_finish<M, GRAD, FIT>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
+    return hipGetLastError();
+  }
+  static hipError_t single_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, hipStream_t st) {
+    return single_t<true, true>(pl, a, unroll, grid, st);
+  }
   static hipError_t single(const Plan& pl, const SingleArgs& a, bool grad, int unroll, int grid,
                            hipStream_t st) {
-    if (grad) return unroll >= 4 ? single_u<true, 4>(pl, a, grid, st) : single_u<true, 2>(pl, a, grid, st);
-    return unroll >= 4 ? single_u<false, 4>(pl, a, grid, st) : single_u<false, 2>(pl, a, grid, st);
+    return grad ? single_t<true, false>(pl, a, unroll, grid, st) : single_t<false, false>(pl, a, unroll, grid, st);
   }
   static hipError_t consts(const Plan& pl, const double* theta, int n_sets, PerTheta* out, const double* glx,
                            const double* glw, hipStream_t st) {
@@ -404,6 +487,7 @@ VariantOps make_ops(const char* name) {
   fill_slots<M>(v);
   v.na_grad = M::NA_GRAD;
   v.single = &Launch<M>::single;
+  v.single_fit = &Launch<M>::single_fit;
   v.consts = &Launch<M>::consts;
   v.sets = &Launch<M>::sets;
   v.fit_init = &Launch<M>::fit_init;

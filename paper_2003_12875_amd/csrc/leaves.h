@@ -43,7 +43,7 @@ __device__ inline double erf_span(double a, double b) {
 
 // Closed-form pieces are written for the leaf's local parameter order.
 struct LeafSetup {
-  double ec[12];      // event constants
+  double ec[kLeafConsts];  // event constants
   double fscale[kMaxLeafParams];
   double Z;
   double dZ[kMaxLeafParams];
@@ -461,5 +461,9 @@ struct ArgusLeaf {
     }
   }
 };
+
+static_assert(sizeof(PerTheta::ec[0]) == sizeof(LeafSetup::ec), "leaf constant rows must match");
+// every leaf's constants fit one row: CB uses 10, Chebyshev 2 + K (K <= 8)
+static_assert(10 <= kLeafConsts && 2 + 8 <= kLeafConsts, "leaf constants");
 
 }  // namespace nllmi

@@ -79,6 +79,18 @@ struct Model {
   static constexpr int NA = GRAD ? NA_GRAD : 1;
 
   static constexpr int NPs[L] = {Slots::Leaf::NP...};
+  static constexpr bool ROOTs[L] = {Slots::root...};
+  static constexpr int NR = ((Slots::root ? 0 : 1) + ... + 0);  // non-root leaves
+  static constexpr bool HAS_ROOT = NR < L;
+  // Flat mixture: term k consists of the k-th non-root leaf (and the root
+  // factors); the host orders the terms accordingly.
+  static constexpr bool FLAT = K > 1 && NR == K;
+  template <int l>
+  static constexpr int term_of() {  // term of non-root leaf l (flat shapes)
+    int k = 0;
+    for (int i = 0; i < l; ++i) k += ROOTs[i] ? 0 : 1;
+    return k;
+  }
   template <int l>
   static constexpr int leaf_off() {
     int o = 0;
@@ -102,9 +114,9 @@ struct Consts {
   __device__ void load(const PerTheta& pt, const Plan& pl) {
     static_for<M::L>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
-      double ec[12];
+      double ec[kLeafConsts];
 #pragma unroll
-      for (int j = 0; j < 12; ++j) ec[j] = uniform(pt.ec[l][j]);
+      for (int j = 0; j < kLeafConsts; ++j) ec[j] = uniform(pt.ec[l][j]);
       std::get<l>(leaf) = M::template S<l>::Leaf::load(ec);
     });
 #pragma unroll
@@ -166,29 +178,46 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
   });
 
   double rootsum = 0.0;
-  static_for<L>([&](auto lc) {
-    constexpr int l = decltype(lc)::value;
-    if constexpr (M::template S<l>::root) rootsum += lam[l];
-  });
+  if constexpr (M::HAS_ROOT) {
+    bool first = true;
+    static_for<L>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      if constexpr (M::template S<l>::root) {
+        rootsum = first ? lam[l] : rootsum + lam[l];
+        first = false;
+      }
+    });
+  }
 
   if constexpr (K == 1) {
     acc.a[0] += rootsum;
-    if constexpr (M::HAS_LIN) acc.P *= gprod;
-    acc.bad += !(__builtin_isfinite(rootsum) && gprod > 0.0);
+    // a non-finite log value propagates into the sum by itself; only the sign
+    // of a linear factor has to be checked (two negative factors would cancel)
+    if constexpr (M::HAS_LIN) {
+      acc.P *= gprod;
+      acc.bad += !(gprod > 0.0);
+    }
     if constexpr (GRAD) {
 #pragma unroll
       for (int j = 0; j < M::NPT; ++j) acc.a[M::LEAF_BASE + j] += phi[j];
     }
   } else {
     double Lk[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double v = C.ck[k];
+    if constexpr (M::FLAT) {
       static_for<L>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
-        if constexpr (!M::template S<l>::root) v += ((C.mask[k] >> l) & 1) ? lam[l] : 0.0;
+        if constexpr (!M::template S<l>::root) Lk[M::template term_of<l>()] = C.ck[M::template term_of<l>()] + lam[l];
       });
-      Lk[k] = v;
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double v = C.ck[k];
+        static_for<L>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          if constexpr (!M::template S<l>::root) v += ((C.mask[k] >> l) & 1) ? lam[l] : 0.0;
+        });
+        Lk[k] = v;
+      }
     }
     double m, s, e[K];
     if constexpr (K == 2) {
@@ -209,13 +238,15 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
         s += e[k];
       }
     }
-    const double tot = rootsum + m;
+    double tot = m;
+    if constexpr (M::HAS_ROOT) tot = rootsum + m;
     acc.a[0] += tot;
-    if constexpr (M::HAS_LIN)
+    if constexpr (M::HAS_LIN) {
       acc.P *= s * gprod;
-    else
+      acc.bad += !(gprod > 0.0);
+    } else {
       acc.P *= s;
-    acc.bad += !(__builtin_isfinite(tot) && gprod > 0.0);
+    }
     if constexpr (GRAD) {
       double inv = __builtin_amdgcn_rcp(s);
       inv = fma(inv, fma(-s, inv, 1.0), inv);
@@ -235,8 +266,12 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
           for (int p = 0; p < Sl::Leaf::NP; ++p) acc.a[M::LEAF_BASE + off + p] += phi[off + p];
         } else {
           double R = 0.0;
+          if constexpr (M::FLAT) {
+            R = r[M::template term_of<l>()];
+          } else {
 #pragma unroll
-          for (int k = 0; k < K; ++k) R += ((C.mask[k] >> l) & 1) ? r[k] : 0.0;
+            for (int k = 0; k < K; ++k) R += ((C.mask[k] >> l) & 1) ? r[k] : 0.0;
+          }
 #pragma unroll
           for (int p = 0; p < Sl::Leaf::NP; ++p) acc.a[M::LEAF_BASE + off + p] = fma(R, phi[off + p], acc.a[M::LEAF_BASE + off + p]);
         }

@@ -25,10 +25,12 @@ constexpr int kMaxParams = 32;
 constexpr int kMaxLeaves = 6;
 constexpr int kMaxTerms = 8;
 constexpr int kMaxLeafParams = 8;
+constexpr int kLeafConsts = 12;     // per-event constants of one leaf
 constexpr int kMaxSums = 4;
 constexpr int kMaxSumChildren = 8;
 constexpr int kMaxPathRefs = 4;     // sum coefficients on the path to a term
 constexpr int kBlock = 256;         // threads per block (4 wave64)
+constexpr int kFinishBlock = 1024;  // threads of the single-dataset finishing kernel
 constexpr int kMaxAcc = 1 + kMaxTerms + kMaxLeaves * kMaxLeafParams;
 
 enum LeafKind : int32_t { kGauss = 1, kExp = 2, kCheb = 3, kCB = 4, kArgus = 5 };
@@ -71,7 +73,7 @@ struct Plan {
 
 // Per-parameter-point constants (device memory / LDS).
 struct PerTheta {
-  double ec[kMaxLeaves][8];               // per-event constants of each leaf
+  double ec[kMaxLeaves][kLeafConsts];     // per-event constants of each leaf
   double fscale[kMaxLeaves][kMaxLeafParams];  // gradient feature -> d/dtheta scale
   double dlogz[kMaxLeaves][kMaxLeafParams];   // d log Z_l / d theta (local order)
   double logz[kMaxLeaves];

@@ -84,41 +84,46 @@ __device__ inline void gl_node(const double* p, int norm, double lo, double hi, 
 // Fills *pt (LDS or global) for parameter vector theta.  All threads of the
 // block must call it; on return *pt is complete and visible to the block.
 template <class M>
-__device__ void compute_pertheta(const Plan& pl, const double* __restrict__ theta,
+__device__ void compute_pertheta(const Plan& pl, const double* __restrict__ theta_g,
                                  const double* __restrict__ glx, const double* __restrict__ glw,
                                  PerTheta* pt, double* lds) {
   const int tid = threadIdx.x;
   __shared__ int s_bad;
-  if (tid == 0) {
-    int bad = 0;
-    for (int k = 0; k < pl.n_param; ++k) {
-      const double v = theta[k];
-      if (!(v >= pl.par_lo[k] && v <= pl.par_hi[k])) bad = 1;  // NaN fails too
-    }
-    for (int q = 0; q < pl.n_sum; ++q) {
-      double f = 0.0;
-      for (int j = 0; j < pl.sum_nchild[q] - 1; ++j) {
-        const double v = theta[pl.sum_param[q][j]];
-        if (!(v >= 0.0 && v <= 1.0)) bad = 1;
-        f += v;
-      }
-      if (!(f <= 1.0)) bad = 1;
-    }
-    if (pl.extended && !(theta[pl.yield_param] > 0.0)) bad = 1;
-    s_bad = bad;
-  }
+  __shared__ double theta[kMaxParams];  // one parallel load instead of dependent ones
+  if (tid == 0) s_bad = 0;
+  if (tid < pl.n_param) theta[tid] = theta_g[tid];
+  // parallel zero fill of the term-weight derivatives
+  for (int i = tid; i < kMaxTerms * kMaxParams; i += kBlock) (&pt->dlogw[0][0])[i] = 0.0;
   __syncthreads();
+  // parameter range checks (Sec. 3): one thread per parameter, per sum
+  if (tid < pl.n_param) {
+    const double v = theta[tid];
+    if (!(v >= pl.par_lo[tid] && v <= pl.par_hi[tid])) atomicOr(&s_bad, 1);  // NaN fails too
+  } else if (tid >= 64 && tid < 64 + pl.n_sum) {
+    const int q = tid - 64;
+    double f = 0.0;
+    bool ok = true;
+    for (int j = 0; j < pl.sum_nchild[q] - 1; ++j) {
+      const double v = theta[pl.sum_param[q][j]];
+      ok = ok && v >= 0.0 && v <= 1.0;
+      f += v;
+    }
+    if (!ok || !(f <= 1.0)) atomicOr(&s_bad, 1);
+  } else if (tid == 128 && pl.extended && !(theta[pl.yield_param] > 0.0)) {
+    atomicOr(&s_bad, 1);
+  }
 
+  // (1) numerically normalised leaves: every thread evaluates one
+  // Gauss-Legendre node, one leaf after the other
   static_for<M::L>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     using Leaf = typename M::template S<l>::Leaf;
-    double p[Leaf::NP];
+    if (pl.leaf_norm[l] != kNormAnalytic) {
+      double p[Leaf::NP];
 #pragma unroll
-    for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
-    const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
-    const bool analytic = pl.leaf_norm[l] == kNormAnalytic;
-    const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
-    if (!analytic) {
+      for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
+      const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
+      const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
       double v[Leaf::NP + 1];
       if (ok) {
         gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
@@ -133,9 +138,22 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
         for (int j = 0; j < Leaf::NP; ++j) pt->dlogz[l][j] = v[j + 1];  // dZ for now
       }
     }
-    if (tid == 0) {
+  });
+  __syncthreads();
+
+  // (2) per-leaf constants and closed-form integrals, leaf l on wave l % 4
+  static_for<M::L>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    using Leaf = typename M::template S<l>::Leaf;
+    if (tid == 64 * (l % 4) + l / 4) {
+      double p[Leaf::NP];
+#pragma unroll
+      for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
+      const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
+      const bool analytic = pl.leaf_norm[l] == kNormAnalytic;
+      const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
       LeafSetup s;
-      for (int j = 0; j < 12; ++j) s.ec[j] = 0.0;
+      for (int j = 0; j < kLeafConsts; ++j) s.ec[j] = 0.0;
       for (int j = 0; j < kMaxLeafParams; ++j) {
         s.fscale[j] = 0.0;
         s.dZ[j] = 0.0;
@@ -149,8 +167,8 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
       if constexpr (Leaf::kKind == kArgus) {
         if (!pl.par_free[pl.leaf_param[l][0]]) s.ec[3] = 0.0;  // m0 not differentiated
       }
-      if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) s_bad = 1;
-      for (int j = 0; j < 12; ++j) pt->ec[l][j] = s.ec[j];
+      if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) atomicOr(&s_bad, 1);
+      for (int j = 0; j < kLeafConsts; ++j) pt->ec[l][j] = s.ec[j];
       const double iz = 1.0 / s.Z;
       pt->logz[l] = log(s.Z);
       for (int j = 0; j < kMaxLeafParams; ++j) {
@@ -158,25 +176,18 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
         pt->dlogz[l][j] = j < Leaf::NP ? s.dZ[j] * iz : 0.0;
       }
     }
-    __syncthreads();
   });
+  __syncthreads();
 
-  if (tid == 0) {
-    // term constants: log w_k - sum_{non-root l in S_k} log Z_l, and
-    // d log w_k / d theta over the fraction parameters of every sum on the path.
-    // Coefficients are floored at 1e-200 so that a fraction exactly at 0 or 1
-    // keeps a finite log and a finite d/df (the floored term then carries a
-    // weight of 1e-200, i.e. nothing, in the likelihood).
-    double croot = 0.0;
-    for (int l = 0; l < pl.n_leaf; ++l)
-      if (pl.leaf_root[l]) croot -= pt->logz[l];
-    pt->croot = croot;
-    for (int k = 0; k < kMaxTerms; ++k) {
-      for (int q = 0; q < kMaxParams; ++q) pt->dlogw[k][q] = 0.0;
-      pt->ck[k] = 0.0;
-    }
-    for (int k = 0; k < pl.n_term; ++k) {
-      double lw = 0.0;
+  // (3) term constants, one lane per term: log w_k - sum_{non-root l in S_k}
+  // log Z_l and d log w_k / d theta over the fraction parameters of every sum
+  // on the path.  Coefficients are floored at 1e-200 so that a fraction at
+  // exactly 0 or 1 keeps a finite log and a finite d/df (the floored term
+  // then carries a weight of 1e-200, i.e. nothing, in the likelihood).
+  const int k = tid;
+  if (k < kMaxTerms) {
+    double lw = 0.0;
+    if (k < pl.n_term) {
       for (int r = 0; r < pl.term_nref[k]; ++r) {
         const int q = pl.term_ref_sum[k][r], j = pl.term_ref_child[k][r];
         const int nc = pl.sum_nchild[q];
@@ -193,10 +204,16 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
       }
       for (int l = 0; l < pl.n_leaf; ++l)
         if (!pl.leaf_root[l] && ((pl.term_mask[k] >> l) & 1)) lw -= pt->logz[l];
-      pt->ck[k] = lw;
     }
-    pt->bad = s_bad;
+    pt->ck[k] = lw;
+  } else if (tid == 64) {
+    double croot = 0.0;
+    for (int l = 0; l < pl.n_leaf; ++l)
+      if (pl.leaf_root[l]) croot -= pt->logz[l];
+    pt->croot = croot;
   }
+  __syncthreads();
+  if (tid == 0) pt->bad = s_bad;
   __syncthreads();
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstring>
+#include <vector>
 
 #include "kernels.h"
 #include "nll.h"
@@ -33,6 +34,7 @@ void gauss_legendre(int n, double* nodes, double* weights);
 }  // namespace nllmi
 
 struct FitKey {
+  int mode = 0;  // 1: single-dataset fit, 2: batched fit
   int n_sets = -1;
   const int64_t* offsets = nullptr;
   double* theta = nullptr;
@@ -42,10 +44,11 @@ struct FitKey {
   double* grad = nullptr;
   int32_t* status = nullptr;
   nll_schedule sched{};
+  bool timing = false;
   bool operator==(const FitKey& o) const {
-    return n_sets == o.n_sets && offsets == o.offsets && theta == o.theta && n_steps == o.n_steps &&
+    return mode == o.mode && n_sets == o.n_sets && offsets == o.offsets && theta == o.theta && n_steps == o.n_steps &&
            eta == o.eta && nll == o.nll && grad == o.grad && status == o.status &&
-           std::memcmp(&sched, &o.sched, sizeof(sched)) == 0;
+           timing == o.timing && std::memcmp(&sched, &o.sched, sizeof(sched)) == 0;
   }
 };
 
@@ -65,7 +68,7 @@ struct nll_model {
 
   // single dataset
   double* partials = nullptr;
-  int* ticket = nullptr;
+  nllmi::PerTheta* pt_single = nullptr;
   int* status = nullptr;
   unsigned long long* dbad = nullptr;
   int64_t* offsets1 = nullptr;
@@ -80,6 +83,11 @@ struct nll_model {
   int gd_cap = 0;
   double* gd_mem = nullptr;
   int* gd_status = nullptr;
+
+  // step timing of fits
+  bool step_timing = false;
+  std::vector<hipEvent_t> events;  // n_steps + 1 while timing
+  int timed_steps = -1;
 
   // recorded fit
   bool use_graph = true;
