@@ -12,20 +12,33 @@ all in the library's HIP kernels, recorded once into a HIP graph.
 Also reported, on the same GPU:
   * fd_baseline -- forward-only FP64 NLL plus a central finite-difference
     gradient (2P+1 passes per step), the per-fit speed-up of the adjoint;
-  * roofline    -- algorithmic bytes per launch of the dominant kernel over
-    its measured duration (HIP events between steps inside the timed
-    graph), against the 8 TB/s HBM peak;
+  * roofline    -- algorithmic bytes per launch of the dominant kernel (the
+    fused streaming kernel) over its average duration, measured in the same
+    run with HIP events recorded on the library's stream right before and
+    after that kernel in every step of an eager K-step fit, against the
+    8 TB/s HBM peak; `traffic` is the HBM byte count per launch from the
+    FETCH_SIZE and WRITE_SIZE counter summary under profiles/ (scaled by the
+    same counters on a plain streaming kernel of known size), reported only
+    while the kernel sources still hash to what was profiled;
   * cpu_baseline -- the scalar FP64 oracle (test infrastructure) on the
     host cores, same events, same minimiser;
   * extra       -- the other workloads: 1-D Gaussian (1e5 events) fit
     steps, the 2-D Crystal Ball/ARGUS x Chebyshev model (5e7 events), and
     4096 batched toy fits (4.1e8 events per step).
 
-    python bench.py [--steps K] [--warmup W] [--quick]
+    python bench.py [--steps K] [--warmup W] [--quick] [--no-cpu-baseline]
+
+Profiling helpers (used to write the summaries under profiles/):
+    python bench.py --probe pmc          # calibration copy + a few eager fit steps
+    python bench.py --summarize-trace DIR [--workload-name NAME]
+    python bench.py --summarize-pmc FETCH_DIR WRITE_DIR
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +49,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NLL+grad events/s per MI355X and % HBM roofline vs plain FP64 NLL+FD grad"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2003_12875_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_single_fit_gauss_exp_1e7_traffic.txt")
+COPY_BYTES = 1 << 30  # calibration kernel: reads and writes 1 GiB
+
+
+def csrc_hash():
+    """sha256 over the device and host sources of the library (sorted)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed counter summary, or None if
+    absent or taken on different kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        if kv.get("csrc_sha256") != csrc_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -58,6 +102,8 @@ def timed_fit(torch, model, theta0, steps, warmup, step_timing=False):
             torch.empty(P, dtype=torch.float64, device=dev), torch.empty(1, dtype=torch.int32, device=dev))
     th0 = torch.as_tensor(theta0, dtype=torch.float64, device=dev)
     model.set_option("step_timing", step_timing)
+    if step_timing:
+        model.set_option("graph", False)
     if warmup > 0:
         model.fit(th0, warmup)
     model.fit(th0, steps, out=bufs)  # records the graph for these buffers
@@ -72,6 +118,8 @@ def timed_fit(torch, model, theta0, steps, warmup, step_timing=False):
     gpu_ms = ev0.elapsed_time(ev1)
     step_ms = model.step_times() if step_timing else [gpu_ms / steps]
     st = int(bufs[3].item())
+    model.set_option("step_timing", False)
+    model.set_option("graph", True)
     return {"wall_s": wall, "gpu_ms": gpu_ms, "step_ms": step_ms, "status": st,
             "theta": bufs[0].cpu().numpy(), "nll": float(bufs[1].item())}
 
@@ -108,9 +156,14 @@ def headline(torch, nllmi, datagen, args):
         raise RuntimeError(f"fit status {r['status']}")
     ms_per_step = 1e3 * r["wall_s"] / args.steps
     value = n * args.steps / r["wall_s"]
-    kern_ms = r["gpu_ms"] / args.steps  # HIP events around the replay, per launch
+    graph_step_ms = r["gpu_ms"] / args.steps  # HIP events around the replay, per step
+    # the dominant kernel alone: events right before and after the streaming
+    # kernel of every step of an eager fit of the same K steps
+    kt = timed_fit(torch, model, theta0, args.steps, 0, step_timing="kernel")
+    kern_ms = sum(kt["step_ms"]) / len(kt["step_ms"])
     bytes_per_launch = 8.0 * n * len(spec["obs"])
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+    traffic = profiled_traffic()
 
     # same-GPU baseline: forward-only FP64 NLL + central finite differences
     th = torch.as_tensor(theta0, dtype=torch.float64, device="cuda")
@@ -131,10 +184,11 @@ def headline(torch, nllmi, datagen, args):
                    "n_events": n, "n_params": model.n_param, "schedule": model.schedule,
                    "variant": model.info["variant"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_single (fit mode): fused NLL+gradient pass + GD update",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_single<gauss+exp, grad, fit>: fused per-point constants + NLL/gradient pass",
                      "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kern_ms,
-                     "note": "80 MB of events fit in the 256 MB last-level cache; see DESIGN.md"},
+                     "graph_step_ms": graph_step_ms, "csrc_sha256": csrc_hash(),
+                     "note": "80 MB of events also fit in the 256 MB last-level cache"},
         "fd_baseline": {"forward_ms": t_fwd, "passes_per_step": fd_passes, "fd_step_ms": fd_step_ms,
                         "eval_grad_ms": t_grad, "speedup_per_fit": fd_step_ms / ms_per_step,
                         "speedup_vs_eval_grad": fd_step_ms / t_grad},
@@ -213,6 +267,98 @@ def extras(torch, nllmi, datagen, args):
     return ex
 
 
+def probe_pmc(torch, nllmi, datagen, steps):
+    """Workload for counter runs: one calibration kernel of known traffic
+    (elementwise negation of 1 GiB: reads and writes COPY_BYTES), then an
+    eager fit of the headline workload."""
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    w = datagen.workload(2)
+    model = nllmi.Model.from_spec(w["spec"])
+    model.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    model.set_option("graph", False)
+    th0 = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    model.fit(th0, steps)
+    torch.cuda.synchronize()
+    log(f"probe: {steps} eager fit steps done")
+
+
+def _csv_rows(d, suffix):
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return rows
+
+
+def _short(name):
+    name = name.replace("nllmi::", "")
+    return name if len(name) < 160 else name[:157] + "..."
+
+
+def summarize_trace(d, workload):
+    """Per-kernel duration summary from a --kernel-trace CSV output folder."""
+    rows = _csv_rows(d, "_kernel_trace.csv")
+    agg = {}
+    for r in rows:
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3  # ns -> us
+        a = agg.setdefault(r["Kernel_Name"], [])
+        a.append(dt)
+    tot = sum(sum(v) for v in agg.values())
+    print(f"# Kernel durations: {workload}\n")
+    print("| kernel | calls | total us | avg us | min us | max us | % |")
+    print("|---|---|---|---|---|---|---|")
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| `{_short(k)}` | {len(v)} | {sum(v):.1f} | {sum(v) / len(v):.2f} | {min(v):.2f} | "
+              f"{max(v):.2f} | {100 * sum(v) / tot:.1f} |")
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """HBM traffic per launch of the streaming fit kernel from two counter
+    runs (FETCH_SIZE, WRITE_SIZE: KiB per dispatch), scaled by what the same
+    counters read for the calibration kernel."""
+    def per_kernel(d, counter):
+        out = {}
+        for r in _csv_rows(d, "_counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return out
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+
+    def pick(tab, pred):
+        ks = [k for k in tab if pred(k)]
+        if len(ks) != 1:
+            raise SystemExit(f"expected one kernel, found {ks}")
+        return ks[0], tab[ks[0]]
+    ck, cf = pick(fetch, lambda k: "neg" in k)
+    _, cw = pick(write, lambda k: "neg" in k)
+    kk, kf = pick(fetch, lambda k: "k_single<" in k and "true, 4, true" in k or
+                  ("k_single<" in k and "true, 2, true" in k))
+    _, kw = pick(write, lambda k: k == kk)
+    f_fac = COPY_BYTES / (sum(cf) / len(cf))
+    w_fac = COPY_BYTES / (sum(cw) / len(cw))
+    fb = f_fac * sum(kf) / len(kf)
+    wb = w_fac * sum(kw) / len(kw)
+    print("# HBM traffic of the streaming fit kernel: gauss+exp mixture, 1e7 FP64 events\n")
+    print("Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own run, scaled by")
+    print(f"the same counter on the calibration kernel (elementwise negation, {COPY_BYTES} bytes read and written).\n")
+    print(f"- kernel: `{_short(kk)}`")
+    print(f"- csrc_sha256: `{csrc_hash()}`")
+    print(f"- dispatches: {len(kf)}")
+    print(f"- calibration_fetch_factor: {f_fac:.4f}")
+    print(f"- calibration_write_factor: {w_fac:.4f}")
+    print(f"- fetch_bytes_per_launch: {fb:.4e}")
+    print(f"- write_bytes_per_launch: {wb:.4e}")
+    print(f"- traffic_bytes_per_launch: {fb + wb:.4e}")
+    print(f"- algorithmic_bytes_per_launch: {8.0e7:.4e}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,7 +366,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", choices=["pmc"], help="run the counter-collection workload only")
+    ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--workload-name", default="")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.workload_name)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {max(args.gpus, world)}); "
@@ -233,6 +389,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     nllmi.lib()
+    if args.probe == "pmc":
+        probe_pmc(torch, nllmi, datagen, 10)
+        return
     res, w, model = headline(torch, nllmi, datagen, args)
     del model
     if not args.quick:

@@ -210,14 +210,19 @@ nll_status nll_autotune(nll_model* model, int32_t which, int32_t n_sets, const i
  *   NLL_OPT_GRAPH        1 (default): fits are recorded once into a HIP graph
  *                        and replayed; 0: fits are enqueued eagerly
  *   NLL_OPT_STEP_TIMING  1: fits are enqueued eagerly with a HIP event before
- *                        the first and after every step, read by
- *                        nll_step_times; 0 (default): no events            */
+ *                        the first and after every step; 2: eagerly, with a
+ *                        HIP event right before and right after the event-
+ *                        streaming kernel of every step (its duration alone,
+ *                        without the finishing kernel); read by
+ *                        nll_step_times; 0 (default): no events.
+ *                        Other values: NLL_ERR_ARG.                        */
 enum nll_option { NLL_OPT_GRAPH = 1, NLL_OPT_STEP_TIMING = 2 };
 nll_status nll_set_option(nll_model* model, int32_t option, int32_t value);
 
-/* Synchronise and copy the duration in milliseconds of each step of the most
- * recent fit run with NLL_OPT_STEP_TIMING on (at most cap values; the count is
- * written to *n).  NLL_ERR_STATE if no timed fit has run. */
+/* Synchronise and copy the duration in milliseconds of each step (or of each
+ * step's streaming kernel, NLL_OPT_STEP_TIMING = 2) of the most recent fit run
+ * with NLL_OPT_STEP_TIMING on (at most cap values; the count is written to
+ * *n).  NLL_ERR_STATE if no timed fit has run. */
 nll_status nll_step_times(nll_model* model, float* ms, int32_t cap, int32_t* n);
 
 typedef struct nll_info {

@@ -243,12 +243,16 @@ class Model:
             check(lib().nll_autotune(self._h, 2, n_sets, _ptr(offsets), _ptr(theta)), "nll_autotune")
         return self.schedule
 
-    def set_option(self, option: str, value: bool):
+    def set_option(self, option: str, value):
+        """"graph": bool; "step_timing": False/0, True/1 (whole steps) or
+        "kernel"/2 (the streaming kernel of each step)."""
         code = {"graph": 1, "step_timing": 2}[option]
-        check(lib().nll_set_option(self._h, code, 1 if value else 0), "nll_set_option")
+        v = 2 if value == "kernel" else int(value)
+        check(lib().nll_set_option(self._h, code, v), "nll_set_option")
 
     def step_times(self, cap: int = 1 << 16):
-        """Per-step durations (ms) of the last fit run with step timing on."""
+        """Per-step (or per-streaming-kernel) durations (ms) of the last fit
+        run with step timing on."""
         buf = (ctypes.c_float * cap)()
         n = ctypes.c_int32(0)
         self._bind_stream()

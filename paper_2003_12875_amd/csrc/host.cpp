@@ -29,6 +29,8 @@ static const std::vector<VariantOps>& registry() {
     register_variants_single(reg);
     register_variants_mixture(reg);
     register_variants_2d(reg);
+    register_variants_fp32c_1d(reg);
+    register_variants_fp32c_2d(reg);
   });
   return reg;
 }
@@ -418,6 +420,15 @@ SetsArgs sets_args(const nll_model* m, int n_sets, const int64_t* offsets) {
 
 int sets_grid(const nll_model* m) { return std::max(1, m->n_cu * m->sched.sets_blocks_per_cu); }
 
+// LDS per block that lets at most bpc blocks of the persistent grid share a
+// CU (the dispatcher would otherwise pack up to the register limit onto
+// some CUs and leave others short); 0 where no cap is needed or possible.
+int lds_cap(const nll_model* m, int bpc) {
+  if (bpc <= 0 || bpc >= 8 || m->lds_per_cu <= 0) return 0;
+  const int cap = m->lds_per_cu / bpc - 256;
+  return std::min(cap, m->lds_per_block);
+}
+
 SingleArgs single_args(const nll_model* m, const double* theta, double* nll_out, double* grad_out) {
   SingleArgs a{};
   for (int o = 0; o < kMaxObs; ++o) a.cols[o] = m->cols[o];
@@ -427,6 +438,7 @@ SingleArgs single_args(const nll_model* m, const double* theta, double* nll_out,
   a.grad_out = grad_out;
   a.partials = m->partials;
   a.pt_out = m->pt_single;
+  a.consts = m->consts;
   a.status = m->status;
   a.glx = m->gl.x;
   a.glw = m->gl.w;
@@ -436,7 +448,8 @@ SingleArgs single_args(const nll_model* m, const double* theta, double* nll_out,
 // (re)create the step events of a timed fit
 nll_status ensure_events(nll_model* m, int n_steps) {
   if (!m->step_timing) return NLL_OK;
-  while ((int)m->events.size() < n_steps + 1) {
+  const int need = m->step_timing == 2 ? 2 * n_steps : n_steps + 1;
+  while ((int)m->events.size() < need) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return NLL_ERR_DEVICE;
     m->events.push_back(e);
@@ -446,7 +459,12 @@ nll_status ensure_events(nll_model* m, int n_steps) {
 }
 
 void record_step(nll_model* m, int s, hipStream_t st) {
-  if (m->step_timing) (void)hipEventRecord(m->events[s], st);
+  if (m->step_timing == 1) (void)hipEventRecord(m->events[s], st);
+}
+
+// events around the streaming kernel of step s (kernel timing only)
+hipEvent_t kernel_event(nll_model* m, int s, int which) {
+  return m->step_timing == 2 ? m->events[2 * s + which] : nullptr;
 }
 
 // a whole single-dataset fit: one persistent launch per step, the last
@@ -460,7 +478,8 @@ nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n
   a.gd = gd;
   record_step(m, 0, st);
   for (int s = 0; s < n_steps; ++s) {
-    e = m->ops->single_fit(m->plan, a, m->sched.unroll, single_grid(m), st);
+    e = m->ops->single_fit(m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), st,
+                           kernel_event(m, s, 0), kernel_event(m, s, 1));
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     record_step(m, s + 1, st);
   }
@@ -480,7 +499,8 @@ nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* 
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   record_step(m, 0, st);
   for (int s = 0; s < n_steps; ++s) {
-    e = m->ops->sets(m->plan, a, true, true, sets_grid(m), st);
+    e = m->ops->sets(m->plan, a, true, true, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu), st,
+                     kernel_event(m, s, 0), kernel_event(m, s, 1));
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     record_step(m, s + 1, st);
   }
@@ -564,6 +584,11 @@ nll_status nll_create_model(const nll_model_desc* desc, nll_model** out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess && cus > 0)
     m->n_cu = cus;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, desc->device) == hipSuccess)
+    m->lds_per_cu = lds;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device) == hipSuccess)
+    m->lds_per_block = lds;
   auto fail = [&](nll_status s) {
     nll_destroy_model(m);
     return s;
@@ -640,7 +665,8 @@ static nll_status nll_eval_impl(nll_model* m, const double* theta, double* nll_o
   if (m->n < 0) return NLL_ERR_STATE;
   DeviceGuard guard(m->device);
   SingleArgs a = single_args(m, theta, nll_out, grad_out);
-  hipError_t e = m->ops->single(m->plan, a, grad, m->sched.unroll, single_grid(m), m->stream);
+  hipError_t e = m->ops->single(m->plan, a, grad, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu),
+                                m->stream);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
 
@@ -670,7 +696,9 @@ nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets
     return NLL_ERR_DEVICE;
   if (m->ops->consts(m->plan, theta, n_sets, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->sets(m->plan, a, grad, false, sets_grid(m), m->stream) != hipSuccess) return NLL_ERR_DEVICE;
+  if (m->ops->sets(m->plan, a, grad, false, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu), m->stream, nullptr,
+                   nullptr) != hipSuccess)
+    return NLL_ERR_DEVICE;
   return NLL_OK;
 }
 
@@ -689,6 +717,7 @@ nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets,
   k.timing = m->step_timing;
   if ((st = ensure_events(m, n_steps)) != NLL_OK) return st;
   m->timed_steps = m->step_timing ? n_steps : -1;
+  m->timed_mode = m->step_timing;
   k.n_sets = n_sets;
   k.offsets = offsets;
   k.theta = theta;
@@ -716,6 +745,7 @@ nll_status nll_fit(nll_model* m, double* theta, int32_t n_steps, double eta, dou
   k.timing = m->step_timing;
   if ((st = ensure_events(m, n_steps)) != NLL_OK) return st;
   m->timed_steps = m->step_timing ? n_steps : -1;
+  m->timed_mode = m->step_timing;
   k.n_sets = 1;
   k.theta = theta;
   k.n_steps = n_steps;
@@ -773,7 +803,8 @@ nll_status nll_set_option(nll_model* m, int32_t option, int32_t value) {
   if (option == NLL_OPT_GRAPH) {
     m->use_graph = value != 0;
   } else if (option == NLL_OPT_STEP_TIMING) {
-    m->step_timing = value != 0;
+    if (value < 0 || value > 2) return NLL_ERR_ARG;
+    m->step_timing = value;
   } else {
     return NLL_ERR_ARG;
   }
@@ -787,8 +818,11 @@ nll_status nll_step_times(nll_model* m, float* ms, int32_t cap, int32_t* n) {
   DeviceGuard guard(m->device);
   if (hipStreamSynchronize(m->stream) != hipSuccess) return NLL_ERR_DEVICE;
   const int k = std::min(cap, m->timed_steps);
-  for (int s = 0; s < k; ++s)
-    if (hipEventElapsedTime(&ms[s], m->events[s], m->events[s + 1]) != hipSuccess) return NLL_ERR_DEVICE;
+  for (int s = 0; s < k; ++s) {
+    const hipEvent_t a = m->timed_mode == 2 ? m->events[2 * s] : m->events[s];
+    const hipEvent_t b = m->timed_mode == 2 ? m->events[2 * s + 1] : m->events[s + 1];
+    if (hipEventElapsedTime(&ms[s], a, b) != hipSuccess) return NLL_ERR_DEVICE;
+  }
   *n = k;
   return NLL_OK;
 }

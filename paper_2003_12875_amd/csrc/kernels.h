@@ -28,7 +28,9 @@ struct SingleArgs {
   double* nll_out;              // 1 (device)
   double* grad_out;             // n_param (device) or null
   double* partials;             // grid * (NA + 1) double-double pairs
-  PerTheta* pt_out;             // per-point constants left by block 0
+  PerTheta* pt_out;             // per-point constants left by block 0 (evaluation)
+  PerTheta* consts;             // fit: constants of the proposal being evaluated,
+                                // written by the previous step's finishing kernel
   int* status;                  // accumulated status bits
   const double* glx;            // 256-point Gauss-Legendre rule on [-1, 1]
   const double* glw;
@@ -57,12 +59,19 @@ struct VariantOps {
   const char* name;
   int n_leaf, K, nobs, na_grad;
   int kind[kMaxLeaves], obs[kMaxLeaves], root[kMaxLeaves], np[kMaxLeaves];
-  int precision;  // 0: FP64
-  hipError_t (*single)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, hipStream_t);
-  hipError_t (*single_fit)(const Plan&, const SingleArgs&, int unroll, int grid, hipStream_t);
+  int precision;  // 0: FP64 event pass, 1: FP32-compensated
+  // lds_cap > 0: LDS reserved per block of the streaming kernel (padded
+  // with dynamic LDS), so that at most the intended number of blocks share
+  // a CU and the persistent grid spreads evenly over the CUs
+  hipError_t (*single)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, int lds_cap, hipStream_t);
+  // fit steps; ev0/ev1 (may be null) are recorded on the stream right before
+  // and right after the streaming kernel of the step
+  hipError_t (*single_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
+                           hipEvent_t ev0, hipEvent_t ev1);
   hipError_t (*consts)(const Plan&, const double* theta, int n_sets, PerTheta* out, const double* glx,
                        const double* glw, hipStream_t);
-  hipError_t (*sets)(const Plan&, const SetsArgs&, bool grad, bool fit, int grid, hipStream_t);
+  hipError_t (*sets)(const Plan&, const SetsArgs&, bool grad, bool fit, int grid, int lds_cap, hipStream_t,
+                     hipEvent_t ev0, hipEvent_t ev1);
   hipError_t (*fit_init)(const Plan&, const double* theta, int n_sets, double eta, const GDState&,
                          PerTheta* consts, const double* glx, const double* glw, hipStream_t);
 };
@@ -71,6 +80,8 @@ struct VariantOps {
 void register_variants_single(std::vector<VariantOps>& out);
 void register_variants_mixture(std::vector<VariantOps>& out);
 void register_variants_2d(std::vector<VariantOps>& out);
+void register_variants_fp32c_1d(std::vector<VariantOps>& out);
+void register_variants_fp32c_2d(std::vector<VariantOps>& out);
 
 hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
                            int64_t* tile_off, int* set_flag, hipStream_t st);

@@ -29,101 +29,152 @@
 namespace nllmi {
 
 // ------------------------------------------------------------------------
-// finisher: totals -> NLL and gradient (thread 0 of one block).  The
-// gradient is assembled in g (LDS, n_param entries) so that the scattered
-// parameter indices never touch private memory.
+// finisher: block totals -> NLL, status and gradient, by a whole block.
+// pl, pt and theta are LDS copies.  Every thread forms NLL and status (the
+// same bits everywhere); thread q < n_param forms d NLL / d theta_q from
+//   sum_k T_k d log w_k/d theta_q
+//     + sum_{l,p: param(l,p) = q} [ fscale_lp F_lp - Rtot_l d log Z_l/d theta_p ]
+// with T_k = sum_i r_k, F_lp = sum_i R_l phi_lp and Rtot_l = sum_{k ∋ l} T_k
+// (N for root leaves); the leaf and term loops are compile-time.
+// Results: *s_nll, *s_st (thread 0 writes) and g[q], visible after the
+// trailing barrier.
 // ------------------------------------------------------------------------
 template <class M, bool GRAD>
-__device__ int finish(const Plan& pl, const PerTheta& pt, const DD* tot, int64_t bad_events, int64_t n,
-                      const double* theta, double* nll_out, double* g) {
-  const int P = pl.n_param;
+__device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt, const DD* tot, int64_t n, const double* theta,
+                             bool flagged, double* s_nll, int* s_st, double* g) {
+  constexpr int NA = M::template NA<GRAD>;
+  const int64_t bad_events = (int64_t)(tot[NA].hi + tot[NA].lo);
   const double sum_l = tot[0].hi + tot[0].lo;
-  double nll = -(sum_l + (double)n * pt.croot);
+  // the FP32 pass sums log-densities without the term constants: croot +
+  // ck_0 for every event, ck_k - ck_0 for every event whose largest term is k
+  double cn = pt.croot;
+  double cterms = 0.0;
+  if constexpr (M::PREC == 1 && M::K > 1) {
+    cn += pt.ck[0];
+#pragma unroll
+    for (int k = 1; k < M::K; ++k) {
+      const DD c = tot[M::template CNT_BASE<GRAD> + k - 1];
+      cterms += (pt.ck[k] - pt.ck[0]) * (c.hi + c.lo);
+    }
+  }
+  double nll = -((sum_l + cterms) + (double)n * cn);
   if (pl.extended) {
     const double nu = theta[pl.yield_param];
     nll += nu - (double)n * log(nu);
   }
   int status = 0;
-  if (pt.bad) status = -3;                                                  // parameter range
+  if (flagged) status = -1;                                                 // malformed offsets
+  else if (pt.bad) status = -3;                                             // parameter range
   else if (bad_events > 0 || !__builtin_isfinite(nll)) status = -5;         // invalid density
   if (status != 0) nll = __builtin_inf();
-  *nll_out = nll;
-  if constexpr (GRAD) {
-    #pragma unroll 1
-    for (int q = 0; q < P; ++q) g[q] = 0.0;
-    if (status != 0) return status;
-    // per-event features: sum_i R_l phi_lp, times their scale; root leaves
-    // carry -d log Z_l for every event
-    #pragma unroll 1
-    for (int l = 0, off = 0; l < pl.n_leaf; ++l) {
-      #pragma unroll 1
-      for (int p = 0; p < pl.leaf_np[l]; ++p, ++off) {
-        const DD v = tot[M::LEAF_BASE + off];
-        const int q = pl.leaf_param[l][p];
-        g[q] += pt.fscale[l][p] * (v.hi + v.lo);
-        if (pl.leaf_root[l]) g[q] -= (double)n * pt.dlogz[l][p];
-      }
-    }
-    if constexpr (M::K > 1) {
-      // sum_i r_k (d log w_k - sum_{non-root l in S_k} d log Z_l)
-      #pragma unroll 1
-      for (int k = 0; k < pl.n_term; ++k) {
-        const double T = tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo;
-        #pragma unroll 1
-        for (int q = 0; q < P; ++q) g[q] += T * pt.dlogw[k][q];
-        #pragma unroll 1
-        for (int l = 0; l < pl.n_leaf; ++l)
-          if (!pl.leaf_root[l] && ((pl.term_mask[k] >> l) & 1))
-            #pragma unroll 1
-            for (int p = 0; p < pl.leaf_np[l]; ++p) g[pl.leaf_param[l][p]] -= T * pt.dlogz[l][p];
-      }
-    }
-    #pragma unroll 1
-    for (int q = 0; q < P; ++q) g[q] = pl.par_free[q] ? -g[q] : 0.0;
-    if (pl.extended && pl.par_free[pl.yield_param]) g[pl.yield_param] += 1.0 - (double)n / theta[pl.yield_param];
+  if (threadIdx.x == 0) {
+    *s_nll = nll;
+    *s_st = status;
   }
-  return status;
+  if constexpr (GRAD) {
+    const int q = threadIdx.x;
+    if (q < pl.n_param) {
+      double acc = 0.0;
+      if (status == 0) {
+        double T[M::K];
+#pragma unroll
+        for (int k = 0; k < M::K; ++k) T[k] = M::K > 1 ? tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo : 0.0;
+        if constexpr (M::K > 1) {
+#pragma unroll
+          for (int k = 0; k < M::K; ++k) acc += T[k] * pt.dlogw[k][q];
+        }
+        static_for<M::L>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          constexpr int off = M::template leaf_off<l>();
+          double R = (double)n;
+          if constexpr (!M::ROOTs[l]) {
+            const int mask_l = 1 << l;
+            R = 0.0;
+#pragma unroll
+            for (int k = 0; k < M::K; ++k) R += (pl.term_mask[k] & mask_l) ? T[k] : 0.0;
+          }
+#pragma unroll
+          for (int p = 0; p < M::NPs[l]; ++p) {
+            if (pl.leaf_param[l][p] == q) {
+              const DD v = tot[M::LEAF_BASE + off + p];
+              double F = v.hi + v.lo;
+              if constexpr (M::PREC == 1) F += pt.phioff[l][p] * R;  // features of x - x0
+              acc += pt.fscale[l][p] * F - R * pt.dlogz[l][p];
+            }
+          }
+        });
+        acc = -acc;
+        if (pl.extended && q == pl.yield_param) acc += 1.0 - (double)n / theta[q];
+      }
+      g[q] = pl.par_free[q] ? acc : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// Gradient-descent state of set s as read at the start of a finishing
+// kernel (thread 0: f_acc, eta; thread q < P: its parameter's entries), so
+// that these loads travel together with the kernel's other loads.
+struct GDPre {
+  double fa, eta;         // thread 0
+  double acc, ga, prop;   // thread q < P
+};
+__device__ inline GDPre gd_preload(const GDState& gd, int s, int P) {
+  GDPre r{0.0, 0.0, 0.0, 0.0, 0.0};
+  const int q = threadIdx.x;
+  if (q == 0) {
+    r.fa = gd.f_acc[s];
+    r.eta = gd.eta[s];
+  }
+  if (q < P) {
+    r.acc = gd.th_acc[(size_t)s * P + q];
+    r.ga = gd.g_acc[(size_t)s * P + q];
+    r.prop = gd.th_prop[(size_t)s * P + q];
+  }
+  return r;
 }
 
 // Gradient descent on the mean NLL with step halving, by a whole block:
 // thread 0 accepts the evaluated proposal when its NLL is finite and exceeds
 // the last accepted one by at most 4 ulps (rounding noise), else halves the
 // step; then thread q forms the next proposal theta_acc - eta g_acc / N of
-// parameter q (free parameters only).  st/nll/grad are valid in thread 0;
-// grad is in shared memory.
-__device__ inline void gd_update(const Plan& pl, const GDState& gd, int s, int st, double nll,
-                                 const double* grad, int64_t n_s) {
+// parameter q (free parameters only), stores it and returns it (threads
+// q >= P return 0).  st/nll are block-uniform LDS values; grad is in LDS.
+__device__ inline double gd_update(const Plan& pl, const GDState& gd, int s, int st, double nll,
+                                   const double* grad, int64_t n_s, const GDPre& pre) {
   __shared__ int s_ok;
   __shared__ double s_step;
   const int P = pl.n_param;
   if (threadIdx.x == 0) {
-    const double fa = gd.f_acc[s];
+    const double fa = pre.fa;
     const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
+    double eta = pre.eta;
     if (ok) {
       gd.f_acc[s] = nll;
       gd.last_status[s] = 0;
     } else {
-      gd.eta[s] *= 0.5;
+      eta *= 0.5;
+      gd.eta[s] = eta;
       if (!__builtin_isfinite(fa)) gd.last_status[s] = st != 0 ? st : -5;
     }
     s_ok = ok;
-    s_step = gd.eta[s] / (double)(n_s > 0 ? n_s : 1);
+    s_step = eta / (double)(n_s > 0 ? n_s : 1);
   }
   __syncthreads();
   const int q = threadIdx.x;
+  double next = 0.0;
   if (q < P) {
-    double* th_acc = gd.th_acc + (size_t)s * P;
-    double* g_acc = gd.g_acc + (size_t)s * P;
-    double* th_prop = gd.th_prop + (size_t)s * P;
-    double acc = th_acc[q], ga = g_acc[q];
+    double acc = pre.acc, ga = pre.ga;
     if (s_ok) {
-      acc = th_prop[q];
+      acc = pre.prop;
       ga = grad[q];
-      th_acc[q] = acc;
-      g_acc[q] = ga;
+      gd.th_acc[(size_t)s * P + q] = acc;
+      gd.g_acc[(size_t)s * P + q] = ga;
     }
-    th_prop[q] = pl.par_free[q] ? acc - s_step * ga : acc;
+    next = pl.par_free[q] ? acc - s_step * ga : acc;
+    gd.th_prop[(size_t)s * P + q] = next;
   }
+  return next;
 }
 
 // ------------------------------------------------------------------------
@@ -137,20 +188,21 @@ __device__ inline void load_tile(const double* const* cols, int64_t base, double
     for (int o = 0; o < M::NOBS; ++o) x[u][o] = cols[o][base + (int64_t)u * kBlock];
 }
 
-template <class M, bool GRAD, int U>
-__device__ inline void compute_tile(const double (&x)[U][M::NOBS], const Consts<M>& C, Acc<M, GRAD>& acc) {
+template <class M, bool GRAD, int U, class CT, class AT>
+__device__ inline void compute_tile(const double (&x)[U][M::NOBS], const CT& C, AT& acc) {
+  acc.begin_tile();
 #pragma unroll
   for (int u = 0; u < U; ++u) model_event<M, GRAD>(x[u], C, acc);
-  acc.renorm();
+  acc.end_tile();
 }
 
 // Full tiles base0, base0 + stride, ... (count of them), software
 // pipelined: the first tile arrives preloaded in xn, and the loads of the
 // next tile are issued before the current one is computed so that two tiles
 // of loads are in flight per wave.
-template <class M, bool GRAD, int U>
+template <class M, bool GRAD, int U, class CT, class AT>
 __device__ inline void stream_tiles(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
-                                    double (&xn)[U][M::NOBS], const Consts<M>& C, Acc<M, GRAD>& acc) {
+                                    double (&xn)[U][M::NOBS], const CT& C, AT& acc) {
   for (int64_t k = 0; k < count; ++k) {
     double xc[U][M::NOBS];
 #pragma unroll
@@ -162,9 +214,10 @@ __device__ inline void stream_tiles(const double* const* cols, int64_t base0, in
   }
 }
 
-template <class M, bool GRAD, int U>
-__device__ inline void stream_part_tile(const double* const* cols, int64_t base, int64_t end,
-                                        const Consts<M>& C, Acc<M, GRAD>& acc) {
+template <class M, bool GRAD, int U, class CT, class AT>
+__device__ inline void stream_part_tile(const double* const* cols, int64_t base, int64_t end, const CT& C,
+                                        AT& acc) {
+  acc.begin_tile();
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int64_t i = base + (int64_t)u * kBlock;
@@ -175,7 +228,7 @@ __device__ inline void stream_part_tile(const double* const* cols, int64_t base,
       model_event<M, GRAD>(x, C, acc);
     }
   }
-  acc.renorm();
+  acc.end_tile();
 }
 
 // ------------------------------------------------------------------------
@@ -189,11 +242,30 @@ template <class M, bool GRAD, int U, bool FIT = false>
 __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleArgs a) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;  // + invalid-event count
+  __shared__ Plan spl;
+  __shared__ double s_theta[kMaxParams];
   __shared__ PerTheta pt;
-  __shared__ DD red[4 * NV];
+  __shared__ double red[NV * (kBlock + 1)];
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
 
+  // Evaluation: plan and parameters first, then the first event tile
+  // (which does not depend on theta), whose loads overlap the prologue.
+  // Fit: the constants of the proposal were prepared by the previous step's
+  // finishing kernel; one parallel copy, then the first tile.
+  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
+  constexpr int PTR = (PT8 + kBlock - 1) / kBlock;
+  double ptv[FIT ? PTR : 1];
+  if constexpr (FIT) {
+#pragma unroll
+    for (int i = 0; i < PTR; ++i) {
+      const int e = threadIdx.x + i * kBlock;
+      ptv[i] = e < PT8 ? reinterpret_cast<const double*>(a.consts)[e] : 0.0;
+    }
+  } else {
+    stage_plan<kBlock>(pl, &spl);
+    stage_theta(a.theta, pl.n_param, s_theta);
+  }
   const double* cols[M::NOBS];
 #pragma unroll
   for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
@@ -201,15 +273,22 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   const int64_t nfull = a.n / tile;
   const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const int64_t base0 = (int64_t)blockIdx.x * tile + threadIdx.x;
-  // the first tile does not depend on theta: its loads overlap the prologue
   double xn[U][M::NOBS];
   if (mine > 0) load_tile<M, U>(cols, base0, xn);
 
-  const double* theta = FIT ? a.gd.th_prop : a.theta;
-  compute_pertheta<M>(pl, theta, a.glx, a.glw, &pt, small);
-  Consts<M> C;
+  if constexpr (FIT) {
+#pragma unroll
+    for (int i = 0; i < PTR; ++i) {
+      const int e = threadIdx.x + i * kBlock;
+      if (e < PT8) reinterpret_cast<double*>(&pt)[e] = ptv[i];
+    }
+    __syncthreads();
+  } else {
+    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
+  }
+  typename Pass<M, GRAD>::C C;
   C.load(pt, pl);
-  Acc<M, GRAD> acc;
+  typename Pass<M, GRAD>::A acc;
   acc.init();
   if (uniform(pt.bad) == 0) {
     stream_tiles<M, GRAD, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xn, C, acc);
@@ -217,15 +296,13 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
     if (rest < a.n && blockIdx.x == (unsigned)(nfull % gridDim.x))
       stream_part_tile<M, GRAD, U>(cols, rest + threadIdx.x, a.n, C, acc);
   }
-  acc.close();
 
-  DD v[NV];
-#pragma unroll
-  for (int j = 0; j < NA; ++j) v[j] = DD{acc.a[j], 0.0};
-  v[NA] = DD{(double)acc.bad, 0.0};
-  block_sum_dd<NV>(v, red, tot);
+  double v[NV];
+  acc.finalize(reinterpret_cast<double(&)[NA]>(v));
+  v[NA] = (double)acc.bad;
+  block_sum_vals<NV, kBlock>(v, red, tot);
   if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
-  if (blockIdx.x == 0) {
+  if (!FIT && blockIdx.x == 0) {
     const double* src = reinterpret_cast<const double*>(&pt);
     double* dst = reinterpret_cast<double*>(a.pt_out);
     for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kBlock) dst[i] = src[i];
@@ -234,39 +311,46 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
 
 // Finishing kernel (one block of kFinishBlock threads): the block partials
 // in block order, then NLL and gradient; in fit mode the gradient-descent
-// step of the proposal just evaluated.
+// step of the proposal just evaluated and the per-point constants of the
+// next proposal (for the next step's streaming kernel).  Every load it
+// needs is issued at once at the start.
 template <class M, bool GRAD, bool FIT = false>
 __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, const SingleArgs a, int n_blocks) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
-  __shared__ DD red[kFinishBlock];
+  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
+  static_assert(PT8 <= kFinishBlock, "one constant per thread");
+  __shared__ Plan spl;
+  __shared__ DD red[kFinishBlock / 64];
   __shared__ DD tot[NV];
   __shared__ double s_grad[kMaxParams];
   __shared__ PerTheta spt;
   __shared__ double s_theta[kMaxParams];
   __shared__ double s_nll;
   __shared__ int s_st;
-  {  // one parallel copy of the per-point constants and theta
-    const double* src = reinterpret_cast<const double*>(a.pt_out);
-    double* dst = reinterpret_cast<double*>(&spt);
-    for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kFinishBlock) dst[i] = src[i];
-    const double* th = FIT ? a.gd.th_prop : a.theta;
-    if (threadIdx.x < pl.n_param) s_theta[threadIdx.x] = th[threadIdx.x];
-  }
-  sum_records<NV, kFinishBlock>(reinterpret_cast<const DD*>(a.partials), n_blocks, red, tot);
-  if (threadIdx.x == 0) {
-    s_st = finish<M, GRAD>(pl, spt, tot, (int64_t)(tot[NA].hi + tot[NA].lo), a.n, s_theta, &s_nll, s_grad);
-  }
-  __syncthreads();
+  __shared__ double small[(kFinishBlock / 64) * (kMaxLeafParams + 1)];
+  const int t = threadIdx.x;
+  stage_plan<kFinishBlock>(pl, &spl);
+  const double ptv = t < PT8 ? reinterpret_cast<const double*>(FIT ? a.consts : a.pt_out)[t] : 0.0;
+  stage_theta(FIT ? a.gd.th_prop : a.theta, pl.n_param, s_theta);
+  GDPre pre{};
+  if constexpr (FIT) pre = gd_preload(a.gd, 0, pl.n_param);
+  RecordSum<NV, kFinishBlock> rs;
+  rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
+  if (t < PT8) reinterpret_cast<double*>(&spt)[t] = ptv;
+  rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, red, tot);  // ends with a barrier
+  finish_block<M, GRAD>(spl, spt, tot, a.n, s_theta, false, &s_nll, &s_st, s_grad);
   if constexpr (FIT) {
-    gd_update(pl, a.gd, 0, s_st, s_nll, s_grad, a.n);
+    const double next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, a.n, pre);
+    if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
+    compute_pertheta<M, kFinishBlock>(spl, s_theta, a.glx, a.glw, a.consts, small);
   } else {
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       *a.nll_out = s_nll;
       if (s_st == -3) atomicOr(a.status, (int)kStatusParam);
       if (s_st == -5) atomicOr(a.status, (int)kStatusPdf);
     }
-    if (GRAD && a.grad_out && threadIdx.x < pl.n_param) a.grad_out[threadIdx.x] = s_grad[threadIdx.x];
+    if (GRAD && a.grad_out && t < spl.n_param) a.grad_out[t] = s_grad[t];
   }
 }
 
@@ -279,16 +363,20 @@ __global__ __launch_bounds__(kBlock) void k_consts(const Plan pl, const double* 
                                                   const double* __restrict__ glx,
                                                   const double* __restrict__ glw) {
   __shared__ double small[4 * (kMaxLeafParams + 1)];
+  __shared__ Plan spl;
+  __shared__ double s_theta[kMaxParams];
   const int s = blockIdx.x;
   if (s >= n_sets) return;
-  compute_pertheta<M>(pl, theta + (size_t)s * pl.n_param, glx, glw, &out[s], small);
+  stage_plan<kBlock>(pl, &spl);
+  stage_theta(theta + (size_t)s * pl.n_param, pl.n_param, s_theta);
+  compute_pertheta<M>(spl, s_theta, glx, glw, &out[s], small);
 }
 
 template <class M, bool GRAD, int U>
 __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
-  __shared__ DD red[4 * NV];
+  __shared__ double red[NV * (kBlock + 1)];
   __shared__ DD tot[NV];
   __shared__ int s_set;
   const int64_t total = a.tile_off[a.n_sets];
@@ -313,9 +401,9 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     const int64_t start = (flag ? 0 : a.offsets[s]) + (item - a.tile_off[s]) * a.tile;
     const int64_t end = flag ? 0 : min(start + a.tile, a.offsets[s + 1]);
 
-    Consts<M> C;
+    typename Pass<M, GRAD>::C C;
     C.load(pt, pl);
-    Acc<M, GRAD> acc;
+    typename Pass<M, GRAD>::A acc;
     acc.init();
     if (uniform(pt.bad) == 0 && flag == 0) {
       const int64_t step = (int64_t)kBlock * U;
@@ -326,12 +414,10 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
       const int64_t base = start + full * step;
       if (base < end) stream_part_tile<M, GRAD, U>(cols, base + threadIdx.x, end, C, acc);
     }
-    acc.close();
-    DD v[NV];
-#pragma unroll
-    for (int j = 0; j < NA; ++j) v[j] = DD{acc.a[j], 0.0};
-    v[NA] = DD{(double)acc.bad, 0.0};
-    block_sum_dd<NV>(v, red, tot);
+    double v[NV];
+    acc.finalize(reinterpret_cast<double(&)[NA]>(v));
+    v[NA] = (double)acc.bad;
+    block_sum_vals<NV, kBlock>(v, red, tot);
     if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)item * NV + threadIdx.x] = tot[threadIdx.x];
   }
 }
@@ -343,7 +429,9 @@ template <class M, bool GRAD, bool FIT>
 __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const SetsArgs a) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
-  __shared__ DD red[kBlock];
+  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
+  __shared__ Plan spl;
+  __shared__ DD red[kBlock / 64];
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
   __shared__ double s_grad[kMaxParams];
@@ -354,39 +442,43 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   const int s = blockIdx.x;
   if (s >= a.n_sets) return;
   const int P = pl.n_param;
-  {  // one parallel copy of the set's constants and parameters
-    const double* src = reinterpret_cast<const double*>(&a.consts[s]);
-    double* dst = reinterpret_cast<double*>(&spt);
-    for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kBlock) dst[i] = src[i];
-    const double* th = FIT ? a.gd.th_prop + (size_t)s * P : a.theta + (size_t)s * P;
-    if (threadIdx.x < P) s_theta[threadIdx.x] = th[threadIdx.x];
+  const int t = threadIdx.x;
+  // every independent load at once: plan, constants, parameters, fit
+  // state, offsets and the first batch of partial records
+  stage_plan<kBlock>(pl, &spl);
+  double ptv[(PT8 + kBlock - 1) / kBlock];
+#pragma unroll
+  for (int i = 0; i < (PT8 + kBlock - 1) / kBlock; ++i) {
+    const int e = t + i * kBlock;
+    ptv[i] = e < PT8 ? reinterpret_cast<const double*>(&a.consts[s])[e] : 0.0;
   }
+  stage_theta(FIT ? a.gd.th_prop + (size_t)s * P : a.theta + (size_t)s * P, P, s_theta);
+  GDPre pre{};
+  if constexpr (FIT) pre = gd_preload(a.gd, s, P);
   const int64_t first = a.tile_off[s], n_items = a.tile_off[s + 1] - first;
-  sum_records<NV, kBlock>(reinterpret_cast<const DD*>(a.partials) + (size_t)first * NV, n_items, red, tot);
   const int flag = a.set_flag[s];
-  const int64_t n_s = flag ? 0 : a.offsets[s + 1] - a.offsets[s];
-  if (threadIdx.x == 0) {
-    double nll;
-    int st = finish<M, GRAD>(pl, spt, tot, (int64_t)(tot[NA].hi + tot[NA].lo), n_s, s_theta, &nll, s_grad);
-    if (flag) {
-      st = -1;
-      nll = __builtin_inf();
-    }
-    s_st = st;
-    s_nll = nll;
+  const int64_t o0 = a.offsets[s], o1 = a.offsets[s + 1];
+  const DD* recs = reinterpret_cast<const DD*>(a.partials) + (size_t)first * NV;
+  RecordSum<NV, kBlock> rs;
+  rs.issue(recs, n_items);
+#pragma unroll
+  for (int i = 0; i < (PT8 + kBlock - 1) / kBlock; ++i) {
+    const int e = t + i * kBlock;
+    if (e < PT8) reinterpret_cast<double*>(&spt)[e] = ptv[i];
   }
-  __syncthreads();
+  rs.reduce(recs, n_items, red, tot);  // ends with a barrier
+  const int64_t n_s = flag ? 0 : o1 - o0;
+  finish_block<M, GRAD>(spl, spt, tot, n_s, s_theta, flag != 0, &s_nll, &s_st, s_grad);
   if constexpr (!FIT) {
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       a.nll_out[s] = s_nll;
       if (a.status_out) a.status_out[s] = s_st;
     }
-    if (GRAD && a.grad_out && threadIdx.x < P)
-      a.grad_out[(size_t)s * P + threadIdx.x] = s_st == 0 ? s_grad[threadIdx.x] : 0.0;
+    if (GRAD && a.grad_out && t < P) a.grad_out[(size_t)s * P + t] = s_st == 0 ? s_grad[t] : 0.0;
   } else {
-    gd_update(pl, a.gd, s, s_st, s_nll, s_grad, n_s);
-    __syncthreads();
-    compute_pertheta<M>(pl, a.gd.th_prop + (size_t)s * P, a.glx, a.glw, &a.consts[s], small);
+    const double next = gd_update(spl, a.gd, s, s_st, s_nll, s_grad, n_s, pre);
+    if (t < P) s_theta[t] = next;  // compute_pertheta starts with a barrier
+    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &a.consts[s], small);
   }
 }
 
@@ -397,11 +489,15 @@ __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double
                                                     const double* __restrict__ glx,
                                                     const double* __restrict__ glw) {
   __shared__ double small[4 * (kMaxLeafParams + 1)];
+  __shared__ Plan spl;
+  __shared__ double s_theta[kMaxParams];
   const int s = blockIdx.x;
   if (s >= n_sets) return;
   const int P = pl.n_param;
+  stage_plan<kBlock>(pl, &spl);
   if (threadIdx.x < P) {
     const double v = theta[(size_t)s * P + threadIdx.x];
+    s_theta[threadIdx.x] = v;
     gd.th_acc[(size_t)s * P + threadIdx.x] = v;
     gd.th_prop[(size_t)s * P + threadIdx.x] = v;
     gd.g_acc[(size_t)s * P + threadIdx.x] = 0.0;
@@ -411,46 +507,66 @@ __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double
     gd.eta[s] = eta;
     gd.last_status[s] = 0;
   }
-  __syncthreads();
-  compute_pertheta<M>(pl, theta + (size_t)s * P, glx, glw, &consts[s], small);
+  compute_pertheta<M>(spl, s_theta, glx, glw, &consts[s], small);
 }
 
 // ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
+// dynamic LDS that pads a block of `kernel` to lds_cap bytes (0: no cap)
+inline size_t pad_lds(const void* kernel, int lds_cap) {
+  if (lds_cap <= 0) return 0;
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) return 0;
+  return (size_t)lds_cap > fa.sharedSizeBytes ? (size_t)lds_cap - fa.sharedSizeBytes : 0;
+}
+
 template <class M>
 struct Launch {
-  template <bool GRAD, int U>
-  static hipError_t single_u(const Plan& pl, const SingleArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_single<M, GRAD, U>), dim3(grid), dim3(kBlock), 0, st, pl, a);
-    return hipGetLastError();
-  }
   template <bool GRAD, bool FIT>
-  static hipError_t single_t(const Plan& pl, const SingleArgs& a, int unroll, int grid, hipStream_t st) {
-    if (unroll >= 4) hipLaunchKernelGGL((k_single<M, GRAD, 4, FIT>), dim3(grid), dim3(kBlock), 0, st, pl, a);
-    else hipLaunchKernelGGL((k_single<M, GRAD, 2, FIT>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  static hipError_t single_t(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+    if (ev0 && hipEventRecord(ev0, st) != hipSuccess) return hipErrorUnknown;
+    if (unroll >= 4) {
+      const void* k = reinterpret_cast<const void*>(&k_single<M, GRAD, 4, FIT>);
+      hipLaunchKernelGGL((k_single<M, GRAD, 4, FIT>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+    } else {
+      const void* k = reinterpret_cast<const void*>(&k_single<M, GRAD, 2, FIT>);
+      hipLaunchKernelGGL((k_single<M, GRAD, 2, FIT>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (ev1 && hipEventRecord(ev1, st) != hipSuccess) return hipErrorUnknown;
     hipLaunchKernelGGL((k_single_finish<M, GRAD, FIT>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
     return hipGetLastError();
   }
-  static hipError_t single_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, hipStream_t st) {
-    return single_t<true, true>(pl, a, unroll, grid, st);
+  static hipError_t single_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
+                               hipEvent_t ev0, hipEvent_t ev1) {
+    return single_t<true, true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
   }
-  static hipError_t single(const Plan& pl, const SingleArgs& a, bool grad, int unroll, int grid,
+  static hipError_t single(const Plan& pl, const SingleArgs& a, bool grad, int unroll, int grid, int lds_cap,
                            hipStream_t st) {
-    return grad ? single_t<true, false>(pl, a, unroll, grid, st) : single_t<false, false>(pl, a, unroll, grid, st);
+    return grad ? single_t<true, false>(pl, a, unroll, grid, lds_cap, st)
+                : single_t<false, false>(pl, a, unroll, grid, lds_cap, st);
   }
   static hipError_t consts(const Plan& pl, const double* theta, int n_sets, PerTheta* out, const double* glx,
                            const double* glw, hipStream_t st) {
     hipLaunchKernelGGL((k_consts<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, out, glx, glw);
     return hipGetLastError();
   }
-  static hipError_t sets(const Plan& pl, const SetsArgs& a, bool grad, bool fit, int grid, hipStream_t st) {
-    if (grad || fit) hipLaunchKernelGGL((k_sets<M, true, 2>), dim3(grid), dim3(kBlock), 0, st, pl, a);
-    else hipLaunchKernelGGL((k_sets<M, false, 2>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  static hipError_t sets(const Plan& pl, const SetsArgs& a, bool grad, bool fit, int grid, int lds_cap, hipStream_t st,
+                         hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0 && hipEventRecord(ev0, st) != hipSuccess) return hipErrorUnknown;
+    if (grad || fit) {
+      const void* k = reinterpret_cast<const void*>(&k_sets<M, true, 2>);
+      hipLaunchKernelGGL((k_sets<M, true, 2>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+    } else {
+      const void* k = reinterpret_cast<const void*>(&k_sets<M, false, 2>);
+      hipLaunchKernelGGL((k_sets<M, false, 2>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (ev1 && hipEventRecord(ev1, st) != hipSuccess) return hipErrorUnknown;
     const dim3 fg(a.n_sets > 0 ? a.n_sets : 1);
     if (fit) hipLaunchKernelGGL((k_sets_finish<M, true, true>), fg, dim3(kBlock), 0, st, pl, a);
     else if (grad) hipLaunchKernelGGL((k_sets_finish<M, true, false>), fg, dim3(kBlock), 0, st, pl, a);
@@ -485,7 +601,8 @@ VariantOps make_ops(const char* name) {
   v.nobs = M::NOBS;
   v.n_leaf = M::L;
   fill_slots<M>(v);
-  v.na_grad = M::NA_GRAD;
+  v.na_grad = M::template NA<true>;  // accumulators per record (counters included)
+  v.precision = M::PREC;
   v.single = &Launch<M>::single;
   v.single_fit = &Launch<M>::single_fit;
   v.consts = &Launch<M>::consts;

@@ -25,6 +25,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "fp32.h"
 #include "plan.h"
 
 namespace nllmi {
@@ -42,11 +43,17 @@ __device__ inline double erf_span(double a, double b) {
 }
 
 // Closed-form pieces are written for the leaf's local parameter order.
+// kappa and phioff serve the FP32 event pass only, where a leaf may work on
+// x - x0 for a location x0: its log-density then differs by the constant
+// kappa (added to the term constants in FP64) and feature p by phioff[p]
+// (restored in FP64 after the reduction).
 struct LeafSetup {
   double ec[kLeafConsts];  // event constants
   double fscale[kMaxLeafParams];
   double Z;
   double dZ[kMaxLeafParams];
+  double kappa;
+  double phioff[kMaxLeafParams];
 };
 
 // ------------------------------------------------------------------------
@@ -64,6 +71,7 @@ struct GaussLeaf {
     const double mu = p[0], sg = p[1], is = 1.0 / sg;
     s.ec[0] = is;
     s.ec[1] = -mu * is;
+    s.ec[2] = mu;
     s.fscale[0] = is;
     s.fscale[1] = is;
     if (!analytic) return;
@@ -92,6 +100,23 @@ struct GaussLeaf {
       phi[1] = tt;
     }
   }
+  // FP32 pass: x - mu in FP64, then single precision
+  struct C32 {
+    double mu;
+    F2 is;
+  };
+  __device__ static C32 load32(const double* ec) { return C32{ec[2], split2(ec[0])}; }
+  template <bool GRAD>
+  __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
+    const float t = mul2((float)(x - c.mu), c.is);
+    const float tt = t * t;
+    lam = -0.5f * tt;
+    gam = 1.0f;
+    if (GRAD) {
+      phi[0] = t;
+      phi[1] = tt;
+    }
+  }
 };
 
 // ------------------------------------------------------------------------
@@ -107,8 +132,12 @@ struct ExpLeaf {
   __device__ static bool valid(const double*) { return true; }
   __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
     const double c = p[0];
+    const double x0 = 0.5 * (lo + hi);  // FP32 pass: location of x
     s.ec[0] = c;
+    s.ec[1] = x0;
     s.fscale[0] = 1.0;
+    s.kappa = c * x0;
+    s.phioff[0] = x0;
     if (!analytic) return;
     const double R = fmax(fabs(lo), fabs(hi));
     if (fabs(c) * R < 0.25) {
@@ -140,6 +169,19 @@ struct ExpLeaf {
     lam = c.c * x;
     gam = 1.0;
     if (GRAD) phi[0] = x;
+  }
+  // FP32 pass on x' = x - x0: c x = c x' + kappa, feature x = x' + phioff
+  struct C32 {
+    double x0;
+    F2 c;
+  };
+  __device__ static C32 load32(const double* ec) { return C32{ec[1], split2(ec[0])}; }
+  template <bool GRAD>
+  __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
+    const float xp = (float)(x - c.x0);
+    lam = mul2(xp, c.c);
+    gam = 1.0f;
+    if (GRAD) phi[0] = xp;
   }
 };
 
@@ -226,6 +268,52 @@ struct ChebLeaf {
       for (int k = 0; k < K; ++k) phi[k] = tk[k] * r;
     }
   }
+  // FP32 pass: the mapped coordinate in FP64, the polynomials T_k in
+  // single precision, their combination with the coefficients in FP64 (a
+  // per-point constant added to a single-precision value would always
+  // lose the same low bits), the logarithm and reciprocal in single
+  // precision.
+  struct C32 {
+    double sx, ox;
+    double a[K];
+  };
+  __device__ static C32 load32(const double* ec) {
+    C32 c;
+    c.sx = ec[0];
+    c.ox = ec[1];
+    for (int k = 0; k < K; ++k) c.a[k] = ec[2 + k];
+    return c;
+  }
+  template <bool GRAD, bool LIN = false>
+  __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
+    const float y = (float)fma(x, c.sx, c.ox);
+    const float y2 = y + y;
+    float tk[K];
+    float tm = 1.0f, t = y;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      tk[k] = t;
+      const float tn = fmaf(y2, t, -tm);
+      tm = t;
+      t = tn;
+    }
+    double g64 = 1.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) g64 = fma(c.a[k], (double)tk[k], g64);
+    const float g = (float)g64;
+    if (LIN) {
+      lam = 0.0f;
+      gam = g;
+    } else {
+      lam = log_f32(g);
+      gam = 1.0f;
+    }
+    if (GRAD) {
+      const float r = rcp_f32(g);
+#pragma unroll
+      for (int k = 0; k < K; ++k) phi[k] = tk[k] * r;
+    }
+  }
 };
 
 // ------------------------------------------------------------------------
@@ -255,6 +343,7 @@ struct CBLeaf {
     s.ec[7] = n * (n / (al * al) + 1.0);    // -n dB/d alpha
     s.ec[8] = log(n / al) + 1.0;            // d log A / d n
     s.ec[9] = n / al;                       // n dB/dn
+    s.ec[10] = m0;                          // FP32 pass: location
     s.fscale[0] = is;
     s.fscale[1] = is;
     s.fscale[2] = 1.0;
@@ -335,6 +424,48 @@ struct CBLeaf {
       phi[1] = core ? tt : -nr * t;
       phi[2] = core ? 0.0 : fma(c.Kb, r, c.Ka);
       phi[3] = core ? 0.0 : (c.Kc - lD) - c.nOverA * r;
+    }
+  }
+  // FP32 pass: x - m0 in FP64, t, the logarithm and reciprocal in single
+  // precision; the steps that add per-point constants (B - t, log A - n log D
+  // and the alpha / n features) in FP64.
+  struct C32 {
+    double m0, logA, B, n, Ka, Kb, Kc, nOverA;
+    F2 is;
+    float na;
+  };
+  __device__ static C32 load32(const double* ec) {
+    C32 c;
+    c.m0 = ec[10];
+    c.is = split2(ec[0]);
+    c.na = (float)ec[2];
+    c.logA = ec[3];
+    c.B = ec[4];
+    c.n = ec[5];
+    c.Ka = ec[6];
+    c.Kb = ec[7];
+    c.Kc = ec[8];
+    c.nOverA = ec[9];
+    return c;
+  }
+  template <bool GRAD>
+  __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
+    const float t = mul2((float)(x - c.m0), c.is);
+    const bool core = t > c.na;
+    const double D64 = core ? 1.0 : c.B - (double)t;
+    const float D = (float)D64;
+    const float r = rcp_f32(D);
+    // log D to first order in the rounding of D
+    const double lD = (double)log_f32(D) + (D64 - (double)D) * (double)r;
+    const float tt = t * t;
+    lam = core ? -0.5f * tt : (float)fma(-c.n, lD, c.logA);
+    gam = 1.0f;
+    if (GRAD) {
+      const float nr = (float)(c.n * (double)r);
+      phi[0] = core ? t : -nr;
+      phi[1] = core ? tt : -nr * t;
+      phi[2] = core ? 0.0f : (float)fma(c.Kb, (double)r, c.Ka);
+      phi[3] = core ? 0.0f : (float)((c.Kc - lD) - c.nOverA * (double)r);
     }
   }
 };
@@ -460,10 +591,37 @@ struct ArgusLeaf {
       phi[1] = in ? us : 0.0;
     }
   }
+  // FP32 pass: u from (m0 - x)(m0 + x) and c u in FP64, the square root,
+  // logarithm and reciprocal in single precision.
+  struct C32 {
+    double m0, im02, c, dm0;
+  };
+  __device__ static C32 load32(const double* ec) { return C32{ec[0], ec[1], ec[2], ec[3]}; }
+  template <bool GRAD, bool LIN = false>
+  __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
+    const double u64 = (c.m0 - x) * (c.m0 + x) * c.im02;
+    const bool in = u64 > 0.0;
+    const float us = in ? (float)u64 : 1.0f;
+    const double cu = c.c * u64;
+    const float xf = (float)x;
+    if (LIN) {
+      lam = in ? (float)cu : -__builtin_inff();
+      gam = in ? xf * sqrt_f32(us) : 0.0f;
+    } else {
+      lam = in ? (float)fma(0.5, (double)log_f32(xf * xf * us), cu) : -__builtin_inff();
+      gam = 1.0f;
+    }
+    if (GRAD) {
+      float d0 = 0.0f;
+      if (c.dm0 != 0.0) d0 = (float)(fma(0.5, (double)rcp_f32(us), c.c) * (x * x) * c.dm0);
+      phi[0] = in ? d0 : 0.0f;
+      phi[1] = in ? us : 0.0f;
+    }
+  }
 };
 
 static_assert(sizeof(PerTheta::ec[0]) == sizeof(LeafSetup::ec), "leaf constant rows must match");
-// every leaf's constants fit one row: CB uses 10, Chebyshev 2 + K (K <= 8)
-static_assert(10 <= kLeafConsts && 2 + 8 <= kLeafConsts, "leaf constants");
+// every leaf's constants fit one row: CB uses 11, Chebyshev 2 + K (K <= 8)
+static_assert(11 <= kLeafConsts && 2 + 8 <= kLeafConsts, "leaf constants");
 
 }  // namespace nllmi

@@ -30,6 +30,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "fp32.h"
 #include "leaves.h"
 #include "plan.h"
 
@@ -98,10 +99,27 @@ struct Model {
     return o;
   }
   using LeafCs = std::tuple<typename Slots::Leaf::C...>;
+  using LeafC32s = std::tuple<typename Slots::Leaf::C32...>;
+  static constexpr int PREC = 0;  // 0: FP64 event pass, 1: FP32-compensated
 
   static_assert(L >= 1 && L <= kMaxLeaves, "1..kMaxLeaves leaves");
   static_assert(K >= 1 && K <= kMaxTerms, "1..kMaxTerms terms");
   static_assert(NA_GRAD <= kMaxAcc, "accumulator budget");
+};
+
+// The same compiled shape with the FP32-compensated event pass.  Its sums
+// gain K - 1 counters: how many events have term k (k >= 1) as the largest
+// one, so that the constant ck_k - ck_0 of that term is added count_k times
+// in FP64 instead of being rounded into every event's FP32 value.
+template <class Base>
+struct FP32C : Base {
+  static constexpr int PREC = 1;
+  static constexpr int NCNT = Base::K > 1 ? Base::K - 1 : 0;
+  template <bool GRAD>
+  static constexpr int CNT_BASE = Base::template NA<GRAD>;
+  template <bool GRAD>
+  static constexpr int NA = Base::template NA<GRAD> + NCNT;
+  static_assert(Base::NA_GRAD + NCNT <= kMaxAcc, "accumulator budget");
 };
 
 // Uniform per-point constants of a compiled model, held in scalar registers.
@@ -122,13 +140,14 @@ struct Consts {
 #pragma unroll
     for (int k = 0; k < M::K; ++k) {
       ck[k] = uniform(pt.ck[k]);
-      mask[k] = pl.term_mask[k];
+      mask[k] = uniform(pl.term_mask[k]);
     }
   }
 };
 
 template <class M, bool GRAD>
 struct Acc {
+  static constexpr int NA = M::template NA<GRAD>;
   double a[M::template NA<GRAD>];
   double P;    // running product (mantissa)
   int E;       // its binary exponent
@@ -147,13 +166,13 @@ struct Acc {
       E += e;
     }
   }
-  // fold the product into the log-sum (once per thread)
-  __device__ void close() {
-    if constexpr (M::NEED_PROD) {
-      a[0] += log(P) + (double)E * kLn2;
-      P = 1.0;
-      E = 0;
-    }
+  __device__ void begin_tile() {}
+  __device__ void end_tile() { renorm(); }
+  // fold the product into the log-sum and hand out the thread's sums
+  __device__ void finalize(double (&v)[NA]) {
+    if constexpr (M::NEED_PROD) a[0] += log(P) + (double)E * kLn2;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) v[j] = a[j];
   }
 };
 
@@ -279,5 +298,238 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
     }
   }
 }
+
+// ------------------------------------------------------------------------
+// FP32-compensated event pass.  Per event, every observable is
+// location-subtracted in FP64 and converted once; the leaves, the
+// transcendental functions and the adjoint run in FP32.  A per-event FP32
+// error only cancels in the sum over events if it is an unbiased rounding,
+// and a per-point constant added to an FP32 value of comparable size always
+// loses the same low bits (a bias that grows with N).  So every step that
+// adds such a constant runs in FP64 (at the same vector rate as FP32 here)
+// and is rounded to FP32 only afterwards, and products with constants use
+// split constants inside an FMA.  The log-sum-exp is taken relative to
+// term 0:
+//   log p = croot + ck_0 + (ck_{k*} - ck_0) + [sum_root lam + L'_{k*}] + log s,
+//   A_k = L'_k + (ck_k - ck_0) (FP64),  k* = argmax_k A_k,
+//   s = sum_k e^{A_k - A_{k*}}
+// (L'_k: the term's log-density without constants); croot + ck_0 are added
+// N times and ck_k - ck_0 count_k times (count_k: events with k* = k) in
+// FP64 after the reduction, so that no FP32 value carries a constant.  The per-event values are summed per tile in FP32
+// and added to a per-thread (hi, lo) pair by TwoSum; the pair is widened to
+// FP64 at the end.
+// ------------------------------------------------------------------------
+__device__ inline float uniformf(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+template <class M>
+struct Consts32 {
+  typename M::LeafC32s leaf;
+  double dck[M::K];  // ck_k - ck_0
+  int mask[M::K];
+
+  __device__ void load(const PerTheta& pt, const Plan& pl) {
+    static_for<M::L>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      double ec[kLeafConsts];
+#pragma unroll
+      for (int j = 0; j < kLeafConsts; ++j) ec[j] = uniform(pt.ec[l][j]);
+      std::get<l>(leaf) = M::template S<l>::Leaf::load32(ec);
+    });
+    const double c0 = uniform(pt.ck[0]);
+#pragma unroll
+    for (int k = 0; k < M::K; ++k) {
+      dck[k] = uniform(pt.ck[k]) - c0;
+      mask[k] = uniform(pl.term_mask[k]);
+    }
+  }
+};
+
+template <class M, bool GRAD>
+struct Acc32 {
+  static constexpr int NA = M::template NA<GRAD>;
+  float t[NA];            // sums of the current tile
+  float hi[NA], lo[NA];   // compensated per-thread sums
+  float P;                // running product (mantissa)
+  int E;
+  int bad;
+  __device__ void init() {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) t[j] = hi[j] = lo[j] = 0.0f;
+    P = 1.0f;
+    E = 0;
+    bad = 0;
+  }
+  __device__ void begin_tile() {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) t[j] = 0.0f;
+  }
+  __device__ void end_tile() {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      float sum, err;
+      two_sum(hi[j], t[j], sum, err);
+      hi[j] = sum;
+      lo[j] += err;
+    }
+    if constexpr (M::NEED_PROD) {
+      E += __builtin_amdgcn_frexp_expf(P);
+      P = __builtin_amdgcn_frexp_mantf(P);
+    }
+  }
+  __device__ void finalize(double (&v)[NA]) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) v[j] = (double)hi[j] + (double)lo[j];
+    if constexpr (M::NEED_PROD) v[0] += log((double)P) + (double)E * kLn2;
+  }
+};
+
+template <class M, bool GRAD>
+__device__ inline void model_event(const double (&x)[M::NOBS], const Consts32<M>& C, Acc32<M, GRAD>& acc) {
+  constexpr int L = M::L, K = M::K;
+  float lam[L];
+  float gprod = 1.0f;
+  float phi[M::NPT > 0 ? M::NPT : 1];
+  static_for<L>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    using Sl = typename M::template S<l>;
+    float gam;
+    if constexpr (Sl::Leaf::kLinear) {
+      Sl::Leaf::template event32<GRAD, Sl::lin>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
+                                                 &phi[M::template leaf_off<l>()]);
+    } else {
+      Sl::Leaf::template event32<GRAD>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
+                                       &phi[M::template leaf_off<l>()]);
+    }
+    if constexpr (Sl::lin) gprod *= gam;
+  });
+
+  float rootsum = 0.0f;
+  if constexpr (M::HAS_ROOT) {
+    bool first = true;
+    static_for<L>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      if constexpr (M::template S<l>::root) {
+        rootsum = first ? lam[l] : rootsum + lam[l];
+        first = false;
+      }
+    });
+  }
+
+  if constexpr (K == 1) {
+    acc.t[0] += rootsum;
+    if constexpr (M::HAS_LIN) {
+      acc.P *= gprod;
+      acc.bad += !(gprod > 0.0f);
+    }
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int j = 0; j < M::NPT; ++j) acc.t[M::LEAF_BASE + j] += phi[j];
+    }
+  } else {
+    float Lk[K];
+    if constexpr (M::FLAT) {
+      static_for<L>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        if constexpr (!M::template S<l>::root) Lk[M::template term_of<l>()] = lam[l];
+      });
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float v = 0.0f;
+        static_for<L>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          if constexpr (!M::template S<l>::root) v += ((C.mask[k] >> l) & 1) ? lam[l] : 0.0f;
+        });
+        Lk[k] = v;
+      }
+    }
+    // term log-densities relative to term 0's constant, in FP64:
+    // A_k = L'_k + (ck_k - ck_0), M = A_{k*} = max_k A_k, e_k = e^{A_k - M};
+    // e^a for an FP64 argument a as e^{float(a)} (1 + (a - float(a)))
+    auto exp_arg = [](double a) {
+      if (a < -104.0) return 0.0f;
+      const float af = (float)a;
+      const float e = exp_f32(af);
+      return fmaf(e, (float)(a - (double)af), e);
+    };
+    constexpr int CB = M::template CNT_BASE<GRAD>;
+    double A[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) A[k] = k == 0 ? (double)Lk[0] : (double)Lk[k] + C.dck[k];
+    float s, e[K], Lmax;
+    if constexpr (K == 2) {
+      const bool one = A[1] > A[0];
+      const float es = exp_arg(-fabs(A[1] - A[0]));
+      e[0] = one ? es : 1.0f;
+      e[1] = one ? 1.0f : es;
+      s = 1.0f + es;
+      Lmax = one ? Lk[1] : Lk[0];
+      acc.t[CB] += one ? 1.0f : 0.0f;
+    } else {
+      int ks = 0;
+      double Mx = A[0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) {
+        ks = A[k] > Mx ? k : ks;
+        Mx = fmax(Mx, A[k]);
+      }
+      s = 0.0f;
+      Lmax = Lk[0];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        e[k] = exp_arg(A[k] - Mx);
+        s += e[k];
+        Lmax = ks == k ? Lk[k] : Lmax;
+        if (k > 0) acc.t[CB + k - 1] += ks == k ? 1.0f : 0.0f;
+      }
+    }
+    // the log-likelihood part without constants: the largest term's L'
+    acc.t[0] += rootsum + Lmax;
+    if constexpr (M::HAS_LIN) {
+      acc.P *= s * gprod;
+      acc.bad += !(gprod > 0.0f);
+    } else {
+      acc.P *= s;
+    }
+    if constexpr (GRAD) {
+      const float inv = rcp_f32(s);
+      float r[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        r[k] = e[k] * inv;
+        acc.t[M::TERM_BASE + k] += r[k];
+      }
+      static_for<L>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        using Sl = typename M::template S<l>;
+        constexpr int off = M::template leaf_off<l>();
+        if constexpr (Sl::root) {
+#pragma unroll
+          for (int p = 0; p < Sl::Leaf::NP; ++p) acc.t[M::LEAF_BASE + off + p] += phi[off + p];
+        } else {
+          float R = 0.0f;
+          if constexpr (M::FLAT) {
+            R = r[M::template term_of<l>()];
+          } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) R += ((C.mask[k] >> l) & 1) ? r[k] : 0.0f;
+          }
+#pragma unroll
+          for (int p = 0; p < Sl::Leaf::NP; ++p)
+            acc.t[M::LEAF_BASE + off + p] = fmaf(R, phi[off + p], acc.t[M::LEAF_BASE + off + p]);
+        }
+      });
+    }
+  }
+}
+
+// event-pass types of a compiled model
+template <class M, bool GRAD>
+struct Pass {
+  using C = std::conditional_t<M::PREC == 1, Consts32<M>, Consts<M>>;
+  using A = std::conditional_t<M::PREC == 1, Acc32<M, GRAD>, Acc<M, GRAD>>;
+};
 
 }  // namespace nllmi

@@ -76,10 +76,11 @@ struct PerTheta {
   double ec[kMaxLeaves][kLeafConsts];     // per-event constants of each leaf
   double fscale[kMaxLeaves][kMaxLeafParams];  // gradient feature -> d/dtheta scale
   double dlogz[kMaxLeaves][kMaxLeafParams];   // d log Z_l / d theta (local order)
-  double logz[kMaxLeaves];
+  double logz[kMaxLeaves];                // log Z_l (FP32 pass: log Z_l - kappa_l)
   double ck[kMaxTerms];                   // log w_k - sum log Z over non-root leaves
   double croot;                           // - sum log Z over root leaves
   double dlogw[kMaxTerms][kMaxParams];    // d log w_k / d theta (fraction params)
+  double phioff[kMaxLeaves][kMaxLeafParams];  // FP32 pass: feature offsets (else 0)
   int32_t bad;                            // parameter outside its allowed range
   int32_t pad;
 };

@@ -19,7 +19,11 @@
 
 namespace nllmi {
 
-// sum over the block of NV values per thread (fixed order: deterministic)
+constexpr int kGLNodes = 256;  // Gauss-Legendre nodes per panel, one per thread
+
+// sum over the first kGLNodes threads (4 waves) of NV values per thread, in
+// a fixed order (deterministic); the other threads of a larger block only
+// take part in the barriers.
 template <int NV>
 __device__ inline void block_sum_small(double (&v)[NV], double* lds /* >= 4*NV */) {
 #pragma unroll
@@ -29,7 +33,7 @@ __device__ inline void block_sum_small(double (&v)[NV], double* lds /* >= 4*NV *
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane == 0) {
+  if (lane == 0 && wave < kGLNodes / 64) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
   }
@@ -81,19 +85,36 @@ __device__ inline void gl_node(const double* p, int norm, double lo, double hi, 
   }
 }
 
-// Fills *pt (LDS or global) for parameter vector theta.  All threads of the
-// block must call it; on return *pt is complete and visible to the block.
-template <class M>
-__device__ void compute_pertheta(const Plan& pl, const double* __restrict__ theta_g,
-                                 const double* __restrict__ glx, const double* __restrict__ glw,
-                                 PerTheta* pt, double* lds) {
+// Copies of the plan and of a parameter vector into LDS, so that the
+// prologue's lane-varying and chained look-ups (parameter ranges, leaf
+// parameter indices, sum coefficients) cost one parallel load instead of a
+// chain of dependent ones.  No barrier: compute_pertheta starts with one.
+// Callers issue these before their first event-tile loads (loads complete
+// in order).
+template <int NT>
+__device__ inline void stage_plan(const Plan& src, Plan* dst) {
+  static_assert(sizeof(Plan) % 8 == 0, "plan copied as 8-byte words");
+  const uint2* s = reinterpret_cast<const uint2*>(&src);
+  uint2* d = reinterpret_cast<uint2*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(Plan) / 8); i += NT) d[i] = s[i];
+}
+__device__ inline void stage_theta(const double* __restrict__ theta_g, int n_param, double* dst) {
+  if ((int)threadIdx.x < n_param) dst[threadIdx.x] = theta_g[threadIdx.x];
+}
+
+// Fills *pt (LDS or global) for the parameter vector theta.  pl and theta
+// are the block's LDS copies (stage_plan, stage_theta, or values written by
+// the calling threads); all threads of the block must call it; on return
+// *pt is complete and visible to the block.
+template <class M, int NT = kBlock>
+__device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* theta, const double* __restrict__ glx,
+                                 const double* __restrict__ glw, PerTheta* pt, double* lds) {
+  static_assert(NT >= kGLNodes && NT % 64 == 0, "at least one thread per quadrature node");
   const int tid = threadIdx.x;
   __shared__ int s_bad;
-  __shared__ double theta[kMaxParams];  // one parallel load instead of dependent ones
   if (tid == 0) s_bad = 0;
-  if (tid < pl.n_param) theta[tid] = theta_g[tid];
   // parallel zero fill of the term-weight derivatives
-  for (int i = tid; i < kMaxTerms * kMaxParams; i += kBlock) (&pt->dlogw[0][0])[i] = 0.0;
+  for (int i = tid; i < kMaxTerms * kMaxParams; i += NT) (&pt->dlogw[0][0])[i] = 0.0;
   __syncthreads();
   // parameter range checks (Sec. 3): one thread per parameter, per sum
   if (tid < pl.n_param) {
@@ -125,7 +146,7 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
       const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
       const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
       double v[Leaf::NP + 1];
-      if (ok) {
+      if (ok && tid < kGLNodes) {
         gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
       } else {
 #pragma unroll
@@ -157,8 +178,10 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
       for (int j = 0; j < kMaxLeafParams; ++j) {
         s.fscale[j] = 0.0;
         s.dZ[j] = 0.0;
+        s.phioff[j] = 0.0;
       }
       s.Z = 0.0;
+      s.kappa = 0.0;
       if (ok) Leaf::setup(p, lo, hi, analytic, s);
       if (!analytic) {
         s.Z = pt->logz[l];
@@ -170,10 +193,13 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
       if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) atomicOr(&s_bad, 1);
       for (int j = 0; j < kLeafConsts; ++j) pt->ec[l][j] = s.ec[j];
       const double iz = 1.0 / s.Z;
-      pt->logz[l] = log(s.Z);
+      // the FP32 pass evaluates the leaf on x - x0: its log-density is off
+      // by the constant kappa, absorbed here into the normalisation
+      pt->logz[l] = M::PREC == 1 ? log(s.Z) - s.kappa : log(s.Z);
       for (int j = 0; j < kMaxLeafParams; ++j) {
         pt->fscale[l][j] = s.fscale[j];
         pt->dlogz[l][j] = j < Leaf::NP ? s.dZ[j] * iz : 0.0;
+        pt->phioff[l][j] = M::PREC == 1 ? s.phioff[j] : 0.0;
       }
     }
   });
@@ -187,7 +213,7 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
   const int k = tid;
   if (k < kMaxTerms) {
     double lw = 0.0;
-    if (k < pl.n_term) {
+    if (k < M::K) {
       for (int r = 0; r < pl.term_nref[k]; ++r) {
         const int q = pl.term_ref_sum[k][r], j = pl.term_ref_child[k][r];
         const int nc = pl.sum_nchild[q];
@@ -202,14 +228,17 @@ __device__ void compute_pertheta(const Plan& pl, const double* __restrict__ thet
           for (int i = 0; i < nc - 1; ++i) pt->dlogw[k][pl.sum_param[q][i]] -= 1.0 / cf;
         }
       }
-      for (int l = 0; l < pl.n_leaf; ++l)
-        if (!pl.leaf_root[l] && ((pl.term_mask[k] >> l) & 1)) lw -= pt->logz[l];
+      const int mask = pl.term_mask[k];
+#pragma unroll
+      for (int l = 0; l < M::L; ++l)
+        if (!M::ROOTs[l] && ((mask >> l) & 1)) lw -= pt->logz[l];
     }
     pt->ck[k] = lw;
   } else if (tid == 64) {
     double croot = 0.0;
-    for (int l = 0; l < pl.n_leaf; ++l)
-      if (pl.leaf_root[l]) croot -= pt->logz[l];
+#pragma unroll
+    for (int l = 0; l < M::L; ++l)
+      if (M::ROOTs[l]) croot -= pt->logz[l];
     pt->croot = croot;
   }
   __syncthreads();

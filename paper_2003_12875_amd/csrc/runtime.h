@@ -44,7 +44,7 @@ struct FitKey {
   double* grad = nullptr;
   int32_t* status = nullptr;
   nll_schedule sched{};
-  bool timing = false;
+  int timing = 0;
   bool operator==(const FitKey& o) const {
     return mode == o.mode && n_sets == o.n_sets && offsets == o.offsets && theta == o.theta && n_steps == o.n_steps &&
            eta == o.eta && nll == o.nll && grad == o.grad && status == o.status &&
@@ -57,6 +57,8 @@ struct nll_model {
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;
   int n_cu = 256;
+  int lds_per_cu = 0;       // bytes (0: unknown, no residency cap)
+  int lds_per_block = 0;    // largest LDS allocation of one block
   nllmi::Plan plan{};
   const nllmi::VariantOps* ops = nullptr;
   int precision = NLL_FP64;
@@ -85,9 +87,10 @@ struct nll_model {
   int* gd_status = nullptr;
 
   // step timing of fits
-  bool step_timing = false;
-  std::vector<hipEvent_t> events;  // n_steps + 1 while timing
+  int step_timing = 0;             // 0 off, 1 whole steps, 2 streaming kernels
+  std::vector<hipEvent_t> events;  // n_steps + 1 (steps) or 2 n_steps (kernels)
   int timed_steps = -1;
+  int timed_mode = 0;
 
   // recorded fit
   bool use_graph = true;
