@@ -22,9 +22,10 @@ Also reported, on the same GPU:
     while the kernel sources still hash to what was profiled;
   * cpu_baseline -- the scalar FP64 oracle (test infrastructure) on the
     host cores, same events, same minimiser;
-  * extra       -- the other workloads: 1-D Gaussian (1e5 events) fit
-    steps, the 2-D Crystal Ball/ARGUS x Chebyshev model (5e7 events), and
-    4096 batched toy fits (4.1e8 events per step).
+  * extra       -- the other workloads: 1-D Gaussian (1e5 events) at 64
+    parameter points and fit steps, the precision study (1e8 events, FP64
+    and FP32-compensated passes), the 2-D Crystal Ball/ARGUS x Chebyshev
+    model (5e7 events), and 4096 batched toy fits (4.1e8 events per step).
 
     python bench.py [--steps K] [--warmup W] [--quick] [--no-cpu-baseline]
 
@@ -214,15 +215,48 @@ def cpu_baseline(datagen, w, budget_s=8.0):
 
 def extras(torch, nllmi, datagen, args):
     ex = {}
-    # 1-D Gaussian, 1e5 events: fit steps are launch-latency bound
+    # 1-D Gaussian, 1e5 events: 64 parameter points, then fit steps (both
+    # launch-latency bound at this size)
     w = datagen.workload(1)
     m = nllmi.Model.from_spec(w["spec"])
     m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    pts = torch.from_numpy(w["points"]).cuda()
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(m.n_param, dtype=torch.float64, device="cuda")
+    t64 = time_launches(torch, lambda: [m.eval(pts[i], out=out) for i in range(64)], 5)
     r = timed_fit(torch, m, w["theta"], 50, 5)
-    ex["gauss_1e5_fit"] = {"steps": 50, "ms_per_step": 1e3 * r["wall_s"] / 50,
-                           "avg_launch_us": 1e3 * r["gpu_ms"] / 50,
-                           "events_per_s": w["n"] * 50 / r["wall_s"]}
+    ex["gauss_1e5"] = {"eval_64_points_ms": t64, "eval_us": 1e3 * t64 / 64, "fit_steps": 50,
+                       "fit_ms_per_step": 1e3 * r["wall_s"] / 50, "fit_avg_step_us": 1e3 * r["gpu_ms"] / 50,
+                       "fit_events_per_s": w["n"] * 50 / r["wall_s"]}
     del m
+    # precision study: 1e8 events of the mixture, FP64 and FP32-compensated
+    # event passes; NLL+gradient timing and fp32c-vs-fp64 differences at the
+    # 32 seeded points (the comparison with the FP64 oracle is a GPU test)
+    log("c5: generating 1e8 events")
+    w = datagen.workload(5)
+    cols = [torch.from_numpy(c).cuda() for c in w["cols"]]
+    pts = torch.from_numpy(w["points"]).cuda()
+    res5 = {}
+    vals = {}
+    out5 = torch.empty(1, dtype=torch.float64, device="cuda")
+    g5 = torch.empty(len(w["spec"]["params"]), dtype=torch.float64, device="cuda")
+    for prec in ("fp64", "fp32c"):
+        m = nllmi.Model.from_spec(w["spec"], precision=prec)
+        m.set_data(cols)
+        tg = time_launches(torch, lambda: m.eval_grad(pts[0], out=out5, grad=g5), 10)
+        vals[prec] = [(float(a.item()), b.cpu().numpy()) for a, b in (m.eval_grad(pts[i]) for i in range(32))]
+        res5[prec] = {"eval_grad_ms": tg, "events_per_s": w["n"] / (tg * 1e-3),
+                      "achieved_GBs": 8.0 * w["n"] / (tg * 1e-3) / 1e9,
+                      "hbm_frac": 8.0 * w["n"] / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS, "variant": m.info["variant"]}
+        del m
+    import numpy as np
+    nerr = [abs(a[0] / b[0] - 1.0) for a, b in zip(vals["fp32c"], vals["fp64"])]
+    gerr = [float(np.max(np.abs(a[1] - b[1])) / max(np.max(np.abs(b[1])), 1e-300))
+            for a, b in zip(vals["fp32c"], vals["fp64"])]
+    res5["fp32c_vs_fp64_gpu"] = {"points": 32, "max_nll_rel_err": max(nerr), "max_grad_rel_err_vs_max_abs": max(gerr)}
+    ex["precision_study_1e8"] = res5
+    del cols
+    torch.cuda.empty_cache()
     # 2-D CB/ARGUS x Chebyshev, 5e7 events, 9 free parameters
     log("c3: generating 5e7 events")
     w = datagen.workload(3)
@@ -236,6 +270,7 @@ def extras(torch, nllmi, datagen, args):
     tf = time_launches(torch, lambda: m.eval(th, out=out), 10)
     ex["cb_argus_cheb_5e7"] = {"eval_grad_ms": tg, "eval_ms": tf, "events_per_s": w["n"] / (tg * 1e-3),
                                "achieved_GBs": 16.0 * w["n"] / (tg * 1e-3) / 1e9,
+                               "hbm_frac": 16.0 * w["n"] / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                "fd_step_ms": 19 * tf, "speedup_vs_fd": 19 * tf / tg}
     del m, cols
     torch.cuda.empty_cache()

@@ -88,9 +88,18 @@ enum nll_node_kind { NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_A
  *   NLL_NORM_GL256_SINGLE  256-point Gauss-Legendre on [lo, hi] as one panel */
 enum nll_norm_method { NLL_NORM_ANALYTIC = 0, NLL_NORM_GL256 = 1, NLL_NORM_GL256_SINGLE = 2 };
 
-/* Arithmetic of the per-event pass.  FP64 everywhere, or FP32 per-event
- * density arithmetic with compensated (two-sum) FP32 per-thread sums and
- * FP64 normalisation, cross-thread reduction and minimiser. */
+/* Arithmetic of the per-event pass.  NLL_FP64: FP64 everywhere, as the
+ * paper's batched computations (Sec. 5.2 and 5.3 keep double precision and
+ * quote their agreement with the scalar path).  NLL_FP32C, an option beyond
+ * the paper: per-event density
+ * arithmetic in FP32 (observables location-subtracted in FP64 first; steps
+ * that add per-point constants in FP64), two-sum-compensated FP32 per-thread
+ * sums widened to FP64, FP64 normalisation, cross-thread reduction and
+ * minimiser.  FP32C results differ from FP64 by unbiased FP32 roundings:
+ * about 1e-6/sqrt(N) relative for N events, and within 1e-9 (NLL) and 1e-8
+ * (gradient, relative to the sum of |d log p_i / d theta|) at N = 1e8.
+ * Parameter points at which a per-event FP32 intermediate overflows (e.g.
+ * (x - mu)/sigma beyond ~1e19) give +inf where FP64 would not. */
 enum nll_precision { NLL_FP64 = 0, NLL_FP32C = 1 };
 
 typedef struct nll_node_desc {

@@ -48,6 +48,17 @@ def _dev_tensor(t, dtype, device):
     return t.contiguous()
 
 
+def _buf(t, dtype, device, numel, name):
+    """A caller-supplied buffer the library reads or writes: checked for
+    type, device, contiguity and size (the C ABI takes bare pointers)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor on {device}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    return t
+
+
 class Model:
     """One likelihood model on one device (``nll_model``)."""
 
@@ -145,17 +156,20 @@ class Model:
     # -- evaluation ------------------------------------------------------------
     def eval(self, theta, out=None):
         torch = _torch()
-        theta = _dev_tensor(theta, torch.float64, self.device)
+        theta = _buf(_dev_tensor(theta, torch.float64, self.device), torch.float64, self.device, self.n_param, "theta")
         out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        _buf(out, torch.float64, self.device, 1, "out")
         self._bind_stream()
         check(lib().nll_eval(self._h, _ptr(theta), _ptr(out)), "nll_eval")
         return out
 
     def eval_grad(self, theta, out=None, grad=None):
         torch = _torch()
-        theta = _dev_tensor(theta, torch.float64, self.device)
+        theta = _buf(_dev_tensor(theta, torch.float64, self.device), torch.float64, self.device, self.n_param, "theta")
         out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
         grad = torch.empty(self.n_param, dtype=torch.float64, device=self.device) if grad is None else grad
+        _buf(out, torch.float64, self.device, 1, "out")
+        _buf(grad, torch.float64, self.device, self.n_param, "grad")
         self._bind_stream()
         check(lib().nll_eval_grad(self._h, _ptr(theta), _ptr(out), _ptr(grad)), "nll_eval_grad")
         return out, grad
@@ -164,7 +178,8 @@ class Model:
         torch = _torch()
         offsets = _dev_tensor(offsets, torch.int64, self.device)
         n_sets = offsets.numel() - 1
-        theta = _dev_tensor(theta, torch.float64, self.device).reshape(n_sets, self.n_param).contiguous()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        _buf(theta, torch.float64, self.device, n_sets * self.n_param, "theta")
         nll = torch.empty(n_sets, dtype=torch.float64, device=self.device)
         g = torch.empty(n_sets, self.n_param, dtype=torch.float64, device=self.device) if grad else None
         status = torch.empty(n_sets, dtype=torch.int32, device=self.device)
@@ -187,6 +202,10 @@ class Model:
         else:
             th, nll, g, status = out
             th.copy_(_dev_tensor(theta, torch.float64, self.device).reshape(n_sets, self.n_param))
+        _buf(th, torch.float64, self.device, n_sets * self.n_param, "theta")
+        _buf(nll, torch.float64, self.device, n_sets, "nll")
+        _buf(g, torch.float64, self.device, n_sets * self.n_param, "grad")
+        _buf(status, torch.int32, self.device, n_sets, "status")
         self._bind_stream()
         check(lib().nll_fit_batched(self._h, n_sets, _ptr(offsets), _ptr(th), int(n_steps), float(eta), _ptr(nll),
                                     _ptr(g), _ptr(status)), "nll_fit_batched")
@@ -205,6 +224,10 @@ class Model:
         else:
             th, nll, g, status = out
             th.copy_(_dev_tensor(theta, torch.float64, self.device))
+        _buf(th, torch.float64, self.device, self.n_param, "theta")
+        _buf(nll, torch.float64, self.device, 1, "nll")
+        _buf(g, torch.float64, self.device, self.n_param, "grad")
+        _buf(status, torch.int32, self.device, 1, "status")
         self._bind_stream()
         check(lib().nll_fit(self._h, _ptr(th), int(n_steps), float(eta), _ptr(nll), _ptr(g), _ptr(status)), "nll_fit")
         return th, nll, g, status
