@@ -20,7 +20,10 @@
 //   CrystalBall(m0,s,a,n)   g = exp(-t^2/2) for t > -a, A (B - t)^-n below,
 //                           A = (n/a)^n e^{-a^2/2}, B = n/a - a
 //   Argus(m0, c)            g = m sqrt(u) e^{c u}, u = 1 - (m/m0)^2, m < m0
-// The branch-free selects follow Sec. 5.3 (both sides computed, one kept).
+// Selects are branch-free (both sides computed, one kept, as in Sec. 5.3)
+// where both sides are cheap; the Crystal Ball's rare power-law tail is a
+// real branch, which a 64-lane wavefront skips when none of its events is
+// in the tail.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -406,24 +409,35 @@ struct CBLeaf {
   __device__ static C load(const double* ec) {
     return C{ec[0], ec[1], ec[2], ec[3], ec[4], ec[5], ec[6], ec[7], ec[8], ec[9]};
   }
+  // The power-law tail holds a few per cent of the events: it is a real
+  // branch (a wavefront skips it unless one of its lanes is in the tail),
+  // the core a straight line.
   template <bool GRAD>
   __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
     const double t = fma(x, c.is, c.b);
-    const bool core = t > c.na;
-    const double D = core ? 1.0 : (c.B - t);
-    const double lD = log(D);
     const double tt = t * t;
-    lam = core ? -0.5 * tt : fma(-c.n, lD, c.logA);
+    lam = -0.5 * tt;
     gam = 1.0;
     if (GRAD) {
-      double r = __builtin_amdgcn_rcp(D);
-      r = fma(r, fma(-D, r, 1.0), r);
-      r = fma(r, fma(-D, r, 1.0), r);
-      const double nr = c.n * r;
-      phi[0] = core ? t : -nr;
-      phi[1] = core ? tt : -nr * t;
-      phi[2] = core ? 0.0 : fma(c.Kb, r, c.Ka);
-      phi[3] = core ? 0.0 : (c.Kc - lD) - c.nOverA * r;
+      phi[0] = t;
+      phi[1] = tt;
+      phi[2] = 0.0;
+      phi[3] = 0.0;
+    }
+    if (!(t > c.na)) {
+      const double D = c.B - t;
+      const double lD = log(D);
+      lam = fma(-c.n, lD, c.logA);
+      if (GRAD) {
+        double r = __builtin_amdgcn_rcp(D);
+        r = fma(r, fma(-D, r, 1.0), r);
+        r = fma(r, fma(-D, r, 1.0), r);
+        const double nr = c.n * r;
+        phi[0] = -nr;
+        phi[1] = -nr * t;
+        phi[2] = fma(c.Kb, r, c.Ka);
+        phi[3] = (c.Kc - lD) - c.nOverA * r;
+      }
     }
   }
   // FP32 pass: x - m0 in FP64, t, the logarithm and reciprocal in single
@@ -451,21 +465,29 @@ struct CBLeaf {
   template <bool GRAD>
   __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
     const float t = mul2((float)(x - c.m0), c.is);
-    const bool core = t > c.na;
-    const double D64 = core ? 1.0 : c.B - (double)t;
-    const float D = (float)D64;
-    const float r = rcp_f32(D);
-    // log D to first order in the rounding of D
-    const double lD = (double)log_f32(D) + (D64 - (double)D) * (double)r;
     const float tt = t * t;
-    lam = core ? -0.5f * tt : (float)fma(-c.n, lD, c.logA);
+    lam = -0.5f * tt;
     gam = 1.0f;
     if (GRAD) {
-      const float nr = (float)(c.n * (double)r);
-      phi[0] = core ? t : -nr;
-      phi[1] = core ? tt : -nr * t;
-      phi[2] = core ? 0.0f : (float)fma(c.Kb, (double)r, c.Ka);
-      phi[3] = core ? 0.0f : (float)((c.Kc - lD) - c.nOverA * (double)r);
+      phi[0] = t;
+      phi[1] = tt;
+      phi[2] = 0.0f;
+      phi[3] = 0.0f;
+    }
+    if (!(t > c.na)) {  // the tail, a real branch as in the FP64 pass
+      const double D64 = c.B - (double)t;
+      const float D = (float)D64;
+      const float r = rcp_f32(D);
+      // log D to first order in the rounding of D
+      const double lD = (double)log_f32(D) + (D64 - (double)D) * (double)r;
+      lam = (float)fma(-c.n, lD, c.logA);
+      if (GRAD) {
+        const float nr = (float)(c.n * (double)r);
+        phi[0] = -nr;
+        phi[1] = -nr * t;
+        phi[2] = (float)fma(c.Kb, (double)r, c.Ka);
+        phi[3] = (float)((c.Kc - lD) - c.nOverA * (double)r);
+      }
     }
   }
 };

@@ -59,6 +59,9 @@ struct Slot {
   static constexpr int obs = OBS;
   static constexpr bool root = ROOT;
   static constexpr bool lin = ROOT && LeafT::kLinear;  // linear factor, no per-event log
+  // linear factor of its term: the term contributes e_k * gamma to the sum
+  // s whose log is taken once per thread, so no per-event log either
+  static constexpr bool tlin = !ROOT && LeafT::kLinear;
 };
 
 template <int K_, int NOBS_, class... Slots>
@@ -72,6 +75,7 @@ struct Model {
 
   static constexpr int NPT = (Slots::Leaf::NP + ... + 0);
   static constexpr bool HAS_LIN = (Slots::lin || ...);
+  static constexpr bool HAS_TLIN = (Slots::tlin || ...);
   static constexpr bool NEED_PROD = (K > 1) || HAS_LIN;
   static constexpr int TERM_BASE = 1;
   static constexpr int LEAF_BASE = 1 + (K > 1 ? K : 0);
@@ -180,6 +184,7 @@ template <class M, bool GRAD>
 __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& C, Acc<M, GRAD>& acc) {
   constexpr int L = M::L, K = M::K;
   double lam[L];
+  double gl[L];  // linear factors of term leaves
   double gprod = 1.0;
   double phi[M::NPT > 0 ? M::NPT : 1];
   static_for<L>([&](auto lc) {
@@ -187,13 +192,19 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
     using Sl = typename M::template S<l>;
     double gam;
     if constexpr (Sl::Leaf::kLinear) {
-      Sl::Leaf::template event<GRAD, Sl::lin>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
-                                               &phi[M::template leaf_off<l>()]);
+      Sl::Leaf::template event<GRAD, Sl::lin || Sl::tlin>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
+                                                           &phi[M::template leaf_off<l>()]);
     } else {
       Sl::Leaf::template event<GRAD>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
                                      &phi[M::template leaf_off<l>()]);
     }
     if constexpr (Sl::lin) gprod *= gam;
+    if constexpr (Sl::tlin) {
+      gl[l] = gam;
+      acc.bad += !(gam >= 0.0);  // a negative linear term is an invalid density
+    } else {
+      gl[l] = 1.0;
+    }
   });
 
   double rootsum = 0.0;
@@ -222,20 +233,29 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
     }
   } else {
     double Lk[K];
+    double Gk[K];  // term linear factors (1 without linear term leaves)
     if constexpr (M::FLAT) {
       static_for<L>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
-        if constexpr (!M::template S<l>::root) Lk[M::template term_of<l>()] = C.ck[M::template term_of<l>()] + lam[l];
+        if constexpr (!M::template S<l>::root) {
+          Lk[M::template term_of<l>()] = C.ck[M::template term_of<l>()] + lam[l];
+          Gk[M::template term_of<l>()] = gl[l];
+        }
       });
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        double v = C.ck[k];
+        double v = C.ck[k], g = 1.0;
         static_for<L>([&](auto lc) {
           constexpr int l = decltype(lc)::value;
-          if constexpr (!M::template S<l>::root) v += ((C.mask[k] >> l) & 1) ? lam[l] : 0.0;
+          if constexpr (!M::template S<l>::root) {
+            const bool in = (C.mask[k] >> l) & 1;
+            v += in ? lam[l] : 0.0;
+            if constexpr (M::template S<l>::tlin) g *= in ? gl[l] : 1.0;
+          }
         });
         Lk[k] = v;
+        Gk[k] = g;
       }
     }
     double m, s, e[K];
@@ -245,7 +265,13 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       const double es = exp(-fabs(d));
       e[0] = d >= 0.0 ? 1.0 : es;
       e[1] = d >= 0.0 ? es : 1.0;
-      s = 1.0 + es;
+      if constexpr (M::HAS_TLIN) {
+        e[0] *= Gk[0];
+        e[1] *= Gk[1];
+        s = e[0] + e[1];
+      } else {
+        s = 1.0 + es;
+      }
     } else {
       m = Lk[0];
 #pragma unroll
@@ -254,6 +280,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         e[k] = exp(Lk[k] - m);
+        if constexpr (M::HAS_TLIN) e[k] *= Gk[k];
         s += e[k];
       }
     }
@@ -391,18 +418,25 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts32<M>
   float lam[L];
   float gprod = 1.0f;
   float phi[M::NPT > 0 ? M::NPT : 1];
+  float gl[L];
   static_for<L>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     using Sl = typename M::template S<l>;
     float gam;
     if constexpr (Sl::Leaf::kLinear) {
-      Sl::Leaf::template event32<GRAD, Sl::lin>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
-                                                 &phi[M::template leaf_off<l>()]);
+      Sl::Leaf::template event32<GRAD, Sl::lin || Sl::tlin>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
+                                                             &phi[M::template leaf_off<l>()]);
     } else {
       Sl::Leaf::template event32<GRAD>(x[Sl::obs], std::get<l>(C.leaf), lam[l], gam,
                                        &phi[M::template leaf_off<l>()]);
     }
     if constexpr (Sl::lin) gprod *= gam;
+    if constexpr (Sl::tlin) {
+      gl[l] = gam;
+      acc.bad += !(gam >= 0.0f);
+    } else {
+      gl[l] = 1.0f;
+    }
   });
 
   float rootsum = 0.0f;
@@ -429,20 +463,29 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts32<M>
     }
   } else {
     float Lk[K];
+    float Gk[K];
     if constexpr (M::FLAT) {
       static_for<L>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
-        if constexpr (!M::template S<l>::root) Lk[M::template term_of<l>()] = lam[l];
+        if constexpr (!M::template S<l>::root) {
+          Lk[M::template term_of<l>()] = lam[l];
+          Gk[M::template term_of<l>()] = gl[l];
+        }
       });
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        float v = 0.0f;
+        float v = 0.0f, g = 1.0f;
         static_for<L>([&](auto lc) {
           constexpr int l = decltype(lc)::value;
-          if constexpr (!M::template S<l>::root) v += ((C.mask[k] >> l) & 1) ? lam[l] : 0.0f;
+          if constexpr (!M::template S<l>::root) {
+            const bool in = (C.mask[k] >> l) & 1;
+            v += in ? lam[l] : 0.0f;
+            if constexpr (M::template S<l>::tlin) g *= in ? gl[l] : 1.0f;
+          }
         });
         Lk[k] = v;
+        Gk[k] = g;
       }
     }
     // term log-densities relative to term 0's constant, in FP64:
@@ -464,7 +507,13 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts32<M>
       const float es = exp_arg(-fabs(A[1] - A[0]));
       e[0] = one ? es : 1.0f;
       e[1] = one ? 1.0f : es;
-      s = 1.0f + es;
+      if constexpr (M::HAS_TLIN) {
+        e[0] *= Gk[0];
+        e[1] *= Gk[1];
+        s = e[0] + e[1];
+      } else {
+        s = 1.0f + es;
+      }
       Lmax = one ? Lk[1] : Lk[0];
       acc.t[CB] += one ? 1.0f : 0.0f;
     } else {
@@ -480,6 +529,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts32<M>
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         e[k] = exp_arg(A[k] - Mx);
+        if constexpr (M::HAS_TLIN) e[k] *= Gk[k];
         s += e[k];
         Lmax = ks == k ? Lk[k] : Lmax;
         if (k > 0) acc.t[CB + k - 1] += ks == k ? 1.0f : 0.0f;

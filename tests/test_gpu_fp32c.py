@@ -8,8 +8,12 @@ largest per-parameter sum of |d l_i / d theta| (as for the FP64 path).
 These hold at the precision-study size (1e8 events).  Each event's value
 carries FP32 rounding errors of a few units of 2^-24 relative; they are
 unbiased (the pass is built so) and their sum grows as sqrt(N), so for
-small N the bound is 1e-6 / sqrt(N) instead (about five standard
+small N the NLL bound is 1e-6 / sqrt(N) instead (about five standard
 deviations of that random walk): e.g. 3e-9 at N = 1e5, 1.7e-7 at N = 30.
+Gradient components see larger per-event errors: a feature such as t^2 of
+the Crystal Ball with |t| ~ 5 carries 2^-24 |t|^2 absolute, and only the
+events of one component (a tenth of them in the 2-D model) carry its
+parameters, so their small-N bound is 1e-5 / sqrt(N).
 """
 import numpy as np
 import pytest
@@ -21,7 +25,8 @@ pytestmark = pytest.mark.gpu
 
 NLL_TOL = 1e-9
 GRAD_TOL = 1e-8
-RANDOM_WALK = 1e-6  # per-event relative FP32 error envelope, divided by sqrt(N)
+RANDOM_WALK = 1e-6       # per-event relative FP32 error envelope of the NLL, divided by sqrt(N)
+RANDOM_WALK_GRAD = 1e-5  # the same for gradient components
 
 
 def nll_tol(n):
@@ -29,7 +34,7 @@ def nll_tol(n):
 
 
 def grad_tol(n):
-    return max(GRAD_TOL, RANDOM_WALK / np.sqrt(max(n, 1)))
+    return max(GRAD_TOL, RANDOM_WALK_GRAD / np.sqrt(max(n, 1)))
 
 
 @pytest.fixture(scope="module")
