@@ -192,16 +192,22 @@ nll_status nll_fit(nll_model* model, double* theta, int32_t n_steps, double eta,
  * (also in *status_out if non-NULL), NLL_ERR_DEVICE on a runtime error. */
 nll_status nll_sync(nll_model* model, int32_t* status_out);
 
-/* Launch schedule of the streaming kernels. */
+/* Launch schedule of the streaming kernels.  A new model starts with
+ * {4, 4, 16384, 16, 2}; persistent grids reserve LDS so that at most the
+ * given number of blocks share a CU. */
 typedef struct nll_schedule {
-  int32_t unroll;             /* events per thread per tile: 2 or 4        */
+  int32_t unroll;             /* events per thread per tile: 2, 4 or 8 (8
+                                 falls back to 4 for shapes with more than 8
+                                 accumulators)                              */
   int32_t blocks_per_cu;      /* persistent grid = CUs * blocks_per_cu     */
   int32_t tile_events;        /* batched: events per (set, tile) work item */
   int32_t sets_blocks_per_cu; /* batched: grid = CUs * sets_blocks_per_cu  */
+  int32_t sets_unroll;        /* batched: events per thread per tile, as
+                                 unroll                                     */
 } nll_schedule;
 
 nll_status nll_get_schedule(const nll_model* model, nll_schedule* out);
-/* Values outside unroll in {2,4}, blocks_per_cu in [1,32],
+/* Values outside unroll and sets_unroll in {2,4,8}, blocks_per_cu in [1,32],
  * tile_events in [1024, 1<<22] (multiple of 512), sets_blocks_per_cu in
  * [1,32] give NLL_ERR_ARG. */
 nll_status nll_set_schedule(nll_model* model, const nll_schedule* sched);

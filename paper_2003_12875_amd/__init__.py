@@ -245,12 +245,13 @@ class Model:
         s = Schedule()
         check(lib().nll_get_schedule(self._h, ctypes.byref(s)), "nll_get_schedule")
         return {"unroll": s.unroll, "blocks_per_cu": s.blocks_per_cu, "tile_events": s.tile_events,
-                "sets_blocks_per_cu": s.sets_blocks_per_cu}
+                "sets_blocks_per_cu": s.sets_blocks_per_cu, "sets_unroll": s.sets_unroll}
 
     def set_schedule(self, **kw):
         cur = self.schedule
         cur.update(kw)
-        s = Schedule(cur["unroll"], cur["blocks_per_cu"], cur["tile_events"], cur["sets_blocks_per_cu"])
+        s = Schedule(cur["unroll"], cur["blocks_per_cu"], cur["tile_events"], cur["sets_blocks_per_cu"],
+                     cur["sets_unroll"])
         check(lib().nll_set_schedule(self._h, ctypes.byref(s)), "nll_set_schedule")
 
     def autotune(self, theta, offsets=None):

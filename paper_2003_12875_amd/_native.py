@@ -44,7 +44,7 @@ class ModelDesc(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("unroll", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("tile_events", ctypes.c_int32),
-                ("sets_blocks_per_cu", ctypes.c_int32)]
+                ("sets_blocks_per_cu", ctypes.c_int32), ("sets_unroll", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -50,6 +50,23 @@ __global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__
   if (t == kBlock - 1) tile_off[n_sets] = scan[kBlock - 1];
 }
 
+// The work items of every set (one thread per set), in tile_off order: the
+// batched kernel then reads an item's set and range with one load instead
+// of searching the prefix.
+__global__ __launch_bounds__(kBlock) void k_items(const int64_t* __restrict__ offsets, int n_sets, int64_t tile,
+                                                  const int64_t* __restrict__ tile_off,
+                                                  const int* __restrict__ set_flag, WorkItem* __restrict__ items) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= n_sets) return;
+  const int flag = set_flag[s];
+  const int64_t a = flag ? 0 : offsets[s], b = flag ? 0 : offsets[s + 1];
+  const int64_t i0 = tile_off[s], i1 = tile_off[s + 1];
+  for (int64_t i = i0; i < i1; ++i) {
+    const int64_t start = a + (i - i0) * tile;
+    items[i] = WorkItem{start, start + tile < b ? start + tile : b, s, flag};
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fit_final(int n_sets, int P, GDState gd, double* theta_out,
                                                      double* nll_out, double* grad_out,
                                                      int* status_out) {
@@ -76,8 +93,12 @@ __global__ __launch_bounds__(kBlock) void k_check_range(const double* __restrict
 }
 
 hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
-                           int64_t* tile_off, int* set_flag, hipStream_t st) {
+                           int64_t* tile_off, int* set_flag, WorkItem* items, hipStream_t st) {
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kBlock), 0, st, offsets, n_sets, n_total, tile, tile_off, set_flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_sets <= 0) return e;
+  hipLaunchKernelGGL(k_items, dim3((n_sets + kBlock - 1) / kBlock), dim3(kBlock), 0, st, offsets, n_sets, tile,
+                     tile_off, set_flag, items);
   return hipGetLastError();
 }
 

@@ -364,7 +364,17 @@ nll_status ensure_sets(nll_model* m, int n_sets) {
     m->have_graph = false;
   }
   const int64_t tile = m->sched.tile_events;
+  // work items: at most ceil(len_s / tile) (at least 1) per set, and the
+  // sets are consecutive ranges of the events
   const int64_t items = (m->n > 0 ? m->n / tile : 0) + n_sets + 1;
+  if ((size_t)items > m->items_cap) {
+    dfree(m->items);
+    m->items_cap = 0;
+    nll_status st = dalloc(&m->items, (size_t)items);
+    if (st != NLL_OK) return st;
+    m->items_cap = (size_t)items;
+    m->have_graph = false;
+  }
   const size_t need = (size_t)items * (size_t)(m->ops->na_grad + 1) * 2 * sizeof(double);
   if (need > m->set_partials_cap) {
     dfree(m->set_partials);
@@ -411,6 +421,7 @@ SetsArgs sets_args(const nll_model* m, int n_sets, const int64_t* offsets) {
   a.tile = m->sched.tile_events;
   a.tile_off = m->tile_off;
   a.set_flag = m->set_flag;
+  a.items = m->items;
   a.consts = m->consts;
   a.partials = m->set_partials;
   a.glx = m->gl.x;
@@ -493,14 +504,14 @@ nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* 
   GDState gd = gd_state(m);
   SetsArgs a = sets_args(m, n_sets, offsets);
   a.gd = gd;
-  hipError_t e = launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, st);
+  hipError_t e = launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->items, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   e = m->ops->fit_init(m->plan, theta, n_sets, eta, gd, m->consts, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   record_step(m, 0, st);
   for (int s = 0; s < n_steps; ++s) {
-    e = m->ops->sets(m->plan, a, true, true, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu), st,
-                     kernel_event(m, s, 0), kernel_event(m, s, 1));
+    e = m->ops->sets(m->plan, a, true, true, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
+                     st, kernel_event(m, s, 0), kernel_event(m, s, 1));
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     record_step(m, s + 1, st);
   }
@@ -622,6 +633,7 @@ void nll_destroy_model(nll_model* m) {
   dfree(m->offsets1);
   dfree(m->tile_off);
   dfree(m->set_flag);
+  dfree(m->items);
   dfree(m->consts);
   dfree(m->set_partials);
   dfree(m->gd_mem);
@@ -692,12 +704,13 @@ nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets
   a.nll_out = nll_out;
   a.grad_out = grad_out;
   a.status_out = reinterpret_cast<int*>(status_out);
-  if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->stream) != hipSuccess)
+  if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->items, m->stream) !=
+      hipSuccess)
     return NLL_ERR_DEVICE;
   if (m->ops->consts(m->plan, theta, n_sets, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->sets(m->plan, a, grad, false, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu), m->stream, nullptr,
-                   nullptr) != hipSuccess)
+  if (m->ops->sets(m->plan, a, grad, false, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
+                   m->stream, nullptr, nullptr) != hipSuccess)
     return NLL_ERR_DEVICE;
   return NLL_OK;
 }
@@ -782,7 +795,8 @@ nll_status nll_get_schedule(const nll_model* m, nll_schedule* out) {
 
 nll_status nll_set_schedule(nll_model* m, const nll_schedule* s) {
   if (!m || !s) return NLL_ERR_ARG;
-  if (!(s->unroll == 2 || s->unroll == 4)) return NLL_ERR_ARG;
+  if (!(s->unroll == 2 || s->unroll == 4 || s->unroll == 8)) return NLL_ERR_ARG;
+  if (!(s->sets_unroll == 2 || s->sets_unroll == 4 || s->sets_unroll == 8)) return NLL_ERR_ARG;
   if (s->blocks_per_cu < 1 || s->blocks_per_cu > 32) return NLL_ERR_ARG;
   if (s->tile_events < 1024 || s->tile_events > (1 << 22) || (s->tile_events % 512) != 0) return NLL_ERR_ARG;
   if (s->sets_blocks_per_cu < 1 || s->sets_blocks_per_cu > 32) return NLL_ERR_ARG;

@@ -37,6 +37,12 @@ struct SingleArgs {
   GDState gd;                   // fit mode: theta = gd.th_prop, set 0
 };
 
+// One work item of the batched pass: events [start, end) of one set.
+struct WorkItem {
+  int64_t start, end;
+  int32_t set, flag;  // flag: the offsets were malformed (no events)
+};
+
 struct SetsArgs {
   const double* cols[kMaxObs];
   int n_sets;
@@ -44,6 +50,7 @@ struct SetsArgs {
   int64_t tile;             // events per work item
   const int64_t* tile_off;  // n_sets + 1 prefix of item counts (device)
   const int* set_flag;      // n_sets: 1 = malformed offsets
+  const WorkItem* items;    // tile_off[n_sets] work items in set order
   PerTheta* consts;         // n_sets
   double* partials;         // items * (NA + 1) double-double pairs
   const double* theta;      // n_sets * P (evaluation mode)
@@ -70,8 +77,8 @@ struct VariantOps {
                            hipEvent_t ev0, hipEvent_t ev1);
   hipError_t (*consts)(const Plan&, const double* theta, int n_sets, PerTheta* out, const double* glx,
                        const double* glw, hipStream_t);
-  hipError_t (*sets)(const Plan&, const SetsArgs&, bool grad, bool fit, int grid, int lds_cap, hipStream_t,
-                     hipEvent_t ev0, hipEvent_t ev1);
+  hipError_t (*sets)(const Plan&, const SetsArgs&, bool grad, bool fit, int unroll, int grid, int lds_cap,
+                     hipStream_t, hipEvent_t ev0, hipEvent_t ev1);
   hipError_t (*fit_init)(const Plan&, const double* theta, int n_sets, double eta, const GDState&,
                          PerTheta* consts, const double* glx, const double* glw, hipStream_t);
 };
@@ -84,7 +91,7 @@ void register_variants_fp32c_1d(std::vector<VariantOps>& out);
 void register_variants_fp32c_2d(std::vector<VariantOps>& out);
 
 hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
-                           int64_t* tile_off, int* set_flag, hipStream_t st);
+                           int64_t* tile_off, int* set_flag, WorkItem* items, hipStream_t st);
 hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_out, double* nll_out,
                             double* grad_out, int* status_out, hipStream_t st);
 hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, unsigned long long* bad,

@@ -378,34 +378,28 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
   constexpr int NV = NA + 1;
   __shared__ double red[NV * (kBlock + 1)];
   __shared__ DD tot[NV];
-  __shared__ int s_set;
   const int64_t total = a.tile_off[a.n_sets];
   const double* cols[M::NOBS];
 #pragma unroll
   for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
 
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    if (threadIdx.x == 0) {
-      int lo = 0, hi = a.n_sets;  // tile_off[lo] <= item < tile_off[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.tile_off[mid] <= item) lo = mid;
-        else hi = mid;
-      }
-      s_set = lo;
-    }
-    __syncthreads();
-    const int s = uniform(s_set);
+  // the next item's descriptor is loaded while the current one streams
+  int64_t item = blockIdx.x;
+  WorkItem cur{0, 0, 0, 0};
+  if (item < total) cur = a.items[item];
+  while (item < total) {
+    const int64_t nxt = item + gridDim.x;
+    WorkItem next = cur;
+    if (nxt < total) next = a.items[nxt];
+    const int s = cur.set;
     const PerTheta& pt = a.consts[s];
-    const int flag = a.set_flag[s];
-    const int64_t start = (flag ? 0 : a.offsets[s]) + (item - a.tile_off[s]) * a.tile;
-    const int64_t end = flag ? 0 : min(start + a.tile, a.offsets[s + 1]);
+    const int64_t start = cur.start, end = cur.end;
 
     typename Pass<M, GRAD>::C C;
     C.load(pt, pl);
     typename Pass<M, GRAD>::A acc;
     acc.init();
-    if (uniform(pt.bad) == 0 && flag == 0) {
+    if (uniform(pt.bad) == 0 && cur.flag == 0) {
       const int64_t step = (int64_t)kBlock * U;
       const int64_t full = (end - start) / step;
       double xn[U][M::NOBS];
@@ -419,6 +413,8 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     v[NA] = (double)acc.bad;
     block_sum_vals<NV, kBlock>(v, red, tot);
     if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)item * NV + threadIdx.x] = tot[threadIdx.x];
+    cur = next;
+    item = nxt;
   }
 }
 
@@ -523,17 +519,26 @@ inline size_t pad_lds(const void* kernel, int lds_cap) {
 
 template <class M>
 struct Launch {
+  // events per thread per tile: 2, 4, or 8 (8 only for shapes with few
+  // accumulators, where the extra registers do not cost occupancy)
+  static constexpr bool kU8 = M::NA_GRAD <= 8;
+  static int pick_u(int unroll) { return unroll >= 8 && kU8 ? 8 : unroll >= 4 ? 4 : 2; }
+
+  template <bool GRAD, bool FIT, int U>
+  static void launch_single(const Plan& pl, const SingleArgs& a, int grid, int lds_cap, hipStream_t st) {
+    const void* k = reinterpret_cast<const void*>(&k_single<M, GRAD, U, FIT>);
+    hipLaunchKernelGGL((k_single<M, GRAD, U, FIT>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+  }
   template <bool GRAD, bool FIT>
   static hipError_t single_t(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     if (ev0 && hipEventRecord(ev0, st) != hipSuccess) return hipErrorUnknown;
-    if (unroll >= 4) {
-      const void* k = reinterpret_cast<const void*>(&k_single<M, GRAD, 4, FIT>);
-      hipLaunchKernelGGL((k_single<M, GRAD, 4, FIT>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
-    } else {
-      const void* k = reinterpret_cast<const void*>(&k_single<M, GRAD, 2, FIT>);
-      hipLaunchKernelGGL((k_single<M, GRAD, 2, FIT>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+    const int u = pick_u(unroll);
+    if constexpr (kU8) {
+      if (u == 8) launch_single<GRAD, FIT, 8>(pl, a, grid, lds_cap, st);
     }
+    if (u == 4) launch_single<GRAD, FIT, 4>(pl, a, grid, lds_cap, st);
+    if (u == 2) launch_single<GRAD, FIT, 2>(pl, a, grid, lds_cap, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1 && hipEventRecord(ev1, st) != hipSuccess) return hipErrorUnknown;
@@ -554,16 +559,25 @@ struct Launch {
     hipLaunchKernelGGL((k_consts<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, out, glx, glw);
     return hipGetLastError();
   }
-  static hipError_t sets(const Plan& pl, const SetsArgs& a, bool grad, bool fit, int grid, int lds_cap, hipStream_t st,
-                         hipEvent_t ev0, hipEvent_t ev1) {
-    if (ev0 && hipEventRecord(ev0, st) != hipSuccess) return hipErrorUnknown;
-    if (grad || fit) {
-      const void* k = reinterpret_cast<const void*>(&k_sets<M, true, 2>);
-      hipLaunchKernelGGL((k_sets<M, true, 2>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
-    } else {
-      const void* k = reinterpret_cast<const void*>(&k_sets<M, false, 2>);
-      hipLaunchKernelGGL((k_sets<M, false, 2>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+  template <bool GRAD, int U>
+  static void launch_sets(const Plan& pl, const SetsArgs& a, int grid, int lds_cap, hipStream_t st) {
+    const void* k = reinterpret_cast<const void*>(&k_sets<M, GRAD, U>);
+    hipLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+  }
+  template <bool GRAD>
+  static void sets_u(const Plan& pl, const SetsArgs& a, int unroll, int grid, int lds_cap, hipStream_t st) {
+    const int u = pick_u(unroll);
+    if constexpr (kU8) {
+      if (u == 8) launch_sets<GRAD, 8>(pl, a, grid, lds_cap, st);
     }
+    if (u == 4) launch_sets<GRAD, 4>(pl, a, grid, lds_cap, st);
+    if (u == 2) launch_sets<GRAD, 2>(pl, a, grid, lds_cap, st);
+  }
+  static hipError_t sets(const Plan& pl, const SetsArgs& a, bool grad, bool fit, int unroll, int grid, int lds_cap,
+                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0 && hipEventRecord(ev0, st) != hipSuccess) return hipErrorUnknown;
+    if (grad || fit) sets_u<true>(pl, a, unroll, grid, lds_cap, st);
+    else sets_u<false>(pl, a, unroll, grid, lds_cap, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1 && hipEventRecord(ev1, st) != hipSuccess) return hipErrorUnknown;

@@ -91,6 +91,7 @@ struct Schedule {
   int32_t blocks_per_cu;   // persistent grid size = CUs * blocks_per_cu
   int32_t tile_events;     // batched mode: events per (set, tile) work item
   int32_t sets_blocks_per_cu;
+  int32_t sets_unroll;
 };
 
 // Device status bits (accumulated, read back by nll_sync).

@@ -66,7 +66,7 @@ struct nll_model {
 
   const double* cols[nllmi::kMaxObs] = {};
   int64_t n = -1;
-  nll_schedule sched{4, 4, 16384, 8};
+  nll_schedule sched{4, 4, 16384, 16, 2};
 
   // single dataset
   double* partials = nullptr;
@@ -79,6 +79,8 @@ struct nll_model {
   int sets_cap = 0;
   int64_t* tile_off = nullptr;
   int* set_flag = nullptr;
+  nllmi::WorkItem* items = nullptr;  // batched work items
+  size_t items_cap = 0;
   nllmi::PerTheta* consts = nullptr;
   size_t set_partials_cap = 0;  // bytes
   double* set_partials = nullptr;

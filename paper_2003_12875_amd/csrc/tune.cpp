@@ -28,7 +28,7 @@ std::string cache_key(const nll_model* m, int which) {
   int bucket = 0;
   for (int64_t n = m->n; n > 1; n >>= 1) ++bucket;
   std::ostringstream os;
-  os << m->ops->name << "|p" << m->precision << "|w" << which << "|b" << bucket;
+  os << "s5|" << m->ops->name << "|p" << m->precision << "|w" << which << "|b" << bucket;  // s5: 5-field schedule
   std::string k = os.str();
   for (char& c : k)
     if (c == ' ') c = '_';
@@ -41,7 +41,7 @@ bool cache_lookup(const std::string& key, nll_schedule* out) {
   std::ifstream f(path);
   std::string k;
   nll_schedule s{};
-  while (f >> k >> s.unroll >> s.blocks_per_cu >> s.tile_events >> s.sets_blocks_per_cu)
+  while (f >> k >> s.unroll >> s.blocks_per_cu >> s.tile_events >> s.sets_blocks_per_cu >> s.sets_unroll)
     if (k == key) {
       *out = s;
       return true;
@@ -54,6 +54,7 @@ void cache_store(const std::string& key, const nll_schedule& s) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
   f << key << ' ' << s.unroll << ' ' << s.blocks_per_cu << ' ' << s.tile_events << ' ' << s.sets_blocks_per_cu
+    << ' ' << s.sets_unroll
     << '\n';
 }
 
@@ -103,11 +104,13 @@ nll_status tune_model(nll_model* m, int which, int n_sets, const int64_t* offset
       hipMemcpy(ref.data(), d_nll, sizeof(double) * S, hipMemcpyDeviceToHost) == hipSuccess) {
     std::vector<nll_schedule> cands;
     if (which == 1) {
-      for (int u : {2, 4})
-        for (int b : {1, 2, 4, 8, 16}) cands.push_back(nll_schedule{u, b, base.tile_events, base.sets_blocks_per_cu});
+      for (int u : {2, 4, 8})
+        for (int b : {1, 2, 4, 8, 16})
+          cands.push_back(nll_schedule{u, b, base.tile_events, base.sets_blocks_per_cu, base.sets_unroll});
     } else {
-      for (int t : {4096, 8192, 16384, 32768, 65536})
-        for (int b : {2, 4, 8, 16}) cands.push_back(nll_schedule{base.unroll, base.blocks_per_cu, t, b});
+      for (int u : {2, 4, 8})
+        for (int t : {8192, 16384, 32768, 65536})
+          for (int b : {2, 4, 8, 16}) cands.push_back(nll_schedule{base.unroll, base.blocks_per_cu, t, b, u});
     }
     Timer tm;
     for (const nll_schedule& c : cands) {
