@@ -343,7 +343,10 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
   if constexpr (FIT) {
     const double next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, a.n, pre);
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
-    compute_pertheta<M, kFinishBlock>(spl, s_theta, a.glx, a.glw, a.consts, small);
+    // the next proposal's constants, built in LDS (its phases read back
+    // what other threads wrote) and stored with one parallel copy
+    compute_pertheta<M, kFinishBlock>(spl, s_theta, a.glx, a.glw, &spt, small);
+    if (t < PT8) reinterpret_cast<double*>(a.consts)[t] = reinterpret_cast<const double*>(&spt)[t];
   } else {
     if (t == 0) {
       *a.nll_out = s_nll;
@@ -365,11 +368,14 @@ __global__ __launch_bounds__(kBlock) void k_consts(const Plan pl, const double* 
   __shared__ double small[4 * (kMaxLeafParams + 1)];
   __shared__ Plan spl;
   __shared__ double s_theta[kMaxParams];
+  __shared__ PerTheta spt;
   const int s = blockIdx.x;
   if (s >= n_sets) return;
   stage_plan<kBlock>(pl, &spl);
   stage_theta(theta + (size_t)s * pl.n_param, pl.n_param, s_theta);
-  compute_pertheta<M>(spl, s_theta, glx, glw, &out[s], small);
+  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
+  for (int e = threadIdx.x; e < (int)(sizeof(PerTheta) / sizeof(double)); e += kBlock)
+    reinterpret_cast<double*>(&out[s])[e] = reinterpret_cast<const double*>(&spt)[e];
 }
 
 template <class M, bool GRAD, int U>
@@ -474,7 +480,9 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   } else {
     const double next = gd_update(spl, a.gd, s, s_st, s_nll, s_grad, n_s, pre);
     if (t < P) s_theta[t] = next;  // compute_pertheta starts with a barrier
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &a.consts[s], small);
+    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &spt, small);
+    for (int e = t; e < PT8; e += kBlock)
+      reinterpret_cast<double*>(&a.consts[s])[e] = reinterpret_cast<const double*>(&spt)[e];
   }
 }
 
@@ -487,6 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double
   __shared__ double small[4 * (kMaxLeafParams + 1)];
   __shared__ Plan spl;
   __shared__ double s_theta[kMaxParams];
+  __shared__ PerTheta spt;
   const int s = blockIdx.x;
   if (s >= n_sets) return;
   const int P = pl.n_param;
@@ -503,7 +512,9 @@ __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double
     gd.eta[s] = eta;
     gd.last_status[s] = 0;
   }
-  compute_pertheta<M>(spl, s_theta, glx, glw, &consts[s], small);
+  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
+  for (int e = threadIdx.x; e < (int)(sizeof(PerTheta) / sizeof(double)); e += kBlock)
+    reinterpret_cast<double*>(&consts[s])[e] = reinterpret_cast<const double*>(&spt)[e];
 }
 
 // ------------------------------------------------------------------------

@@ -66,7 +66,7 @@ struct nll_model {
 
   const double* cols[nllmi::kMaxObs] = {};
   int64_t n = -1;
-  nll_schedule sched{4, 4, 16384, 16, 2};
+  nll_schedule sched{4, 2, 16384, 16, 2};
 
   // single dataset
   double* partials = nullptr;
