@@ -77,8 +77,13 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
       double acc = 0.0;
       if (status == 0) {
         double T[M::K];
+        double Tsum = 0.0;
 #pragma unroll
-        for (int k = 0; k < M::K; ++k) T[k] = M::K > 1 ? tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo : 0.0;
+        for (int k = 0; k < M::K - 1; ++k) {
+          T[k] = tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo;
+          Tsum += T[k];
+        }
+        T[M::K - 1] = M::K > 1 ? (double)n - Tsum : 0.0;  // sum_k r_k = 1 per event
         if constexpr (M::K > 1) {
 #pragma unroll
           for (int k = 0; k < M::K; ++k) acc += T[k] * pt.dlogw[k][q];

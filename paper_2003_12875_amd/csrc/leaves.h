@@ -84,6 +84,38 @@ struct GaussLeaf {
     s.dZ[0] = ea - eb;
     s.dZ[1] = s.Z * is + a * ea - b * eb;
   }
+  // setup() over 4 lanes of one wave (lane 0 = the group's first): the two
+  // error-function values of erf_span and the two boundary exponentials each
+  // on a lane of their own, gathered by shuffles; the same operations as
+  // setup(), so the same bits.  The result is complete on lane 0.
+  static constexpr int kSetupLanes = 4;
+  __device__ static void setup_coop(const double* p, double lo, double hi, bool analytic, LeafSetup& s, int lane) {
+    const double mu = p[0], sg = p[1], is = 1.0 / sg;
+    s.ec[0] = is;
+    s.ec[1] = -mu * is;
+    s.ec[2] = mu;
+    s.fscale[0] = is;
+    s.fscale[1] = is;
+    if (!analytic) return;
+    const double a = (lo - mu) * is, b = (hi - mu) * is;
+    double v;
+    if (lane >= 2) {
+      const double t = lane == 2 ? a : b;
+      v = exp(-0.5 * t * t);
+    } else if (a >= 0.0) {  // erf_span = v(lane 0) - v(lane 1)
+      v = erfc((lane ? b : a) * kInvSqrt2);
+    } else if (b <= 0.0) {
+      v = erfc((lane ? -a : -b) * kInvSqrt2);
+    } else {
+      v = erf((lane ? a : b) * kInvSqrt2);
+    }
+    const int base = (int)(threadIdx.x & 63) - lane;
+    const double u0 = __shfl(v, base, 64), u1 = __shfl(v, base + 1, 64);
+    const double ea = __shfl(v, base + 2, 64), eb = __shfl(v, base + 3, 64);
+    s.Z = sg * kSqrtPiOver2 * (u0 - u1);
+    s.dZ[0] = ea - eb;
+    s.dZ[1] = s.Z * is + a * ea - b * eb;
+  }
   __device__ static double shape(const double* p, double lo, double hi, double x, double* dg) {
     const double t = (x - p[0]) / p[1];
     const double g = exp(-0.5 * t * t);
@@ -161,6 +193,33 @@ struct ExpLeaf {
     s.Z = elo * expm1(c * (hi - lo)) / c;
     s.dZ[0] = (ehi * fma(c, hi, -1.0) - elo * fma(c, lo, -1.0)) / (c * c);
   }
+  // setup() over 3 lanes: exp(c lo), exp(c hi) and expm1(c (hi - lo)) each
+  // on a lane of their own (same operations, same bits); complete on lane 0.
+  static constexpr int kSetupLanes = 3;
+  __device__ static void setup_coop(const double* p, double lo, double hi, bool analytic, LeafSetup& s, int lane) {
+    const double c = p[0];
+    const double R = fmax(fabs(lo), fabs(hi));
+    if (!analytic || fabs(c) * R < 0.25) {  // no transcendental functions to spread
+      setup(p, lo, hi, analytic, s);
+      return;
+    }
+    const double x0 = 0.5 * (lo + hi);
+    s.ec[0] = c;
+    s.ec[1] = x0;
+    s.fscale[0] = 1.0;
+    s.kappa = c * x0;
+    s.phioff[0] = x0;
+    double v;
+    if (lane == 0) {
+      v = expm1(c * (hi - lo));
+    } else {
+      v = exp(c * (lane == 1 ? lo : hi));
+    }
+    const int base = (int)(threadIdx.x & 63) - lane;
+    const double em = __shfl(v, base, 64), elo = __shfl(v, base + 1, 64), ehi = __shfl(v, base + 2, 64);
+    s.Z = elo * em / c;
+    s.dZ[0] = (ehi * fma(c, hi, -1.0) - elo * fma(c, lo, -1.0)) / (c * c);
+  }
   __device__ static double shape(const double* p, double, double, double x, double* dg) {
     const double g = exp(p[0] * x);
     dg[0] = g * x;
@@ -197,6 +256,7 @@ struct ChebLeaf {
   static constexpr int kKind = kCheb;
   static constexpr int NP = K;
   static constexpr bool kLinear = true;
+  static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double sx, ox, a[K];
   };
@@ -326,6 +386,7 @@ struct CBLeaf {
   static constexpr int kKind = kCB;
   static constexpr int NP = 4;
   static constexpr bool kLinear = false;
+  static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double is, b, na, logA, B, n, Ka, Kb, Kc, nOverA;
   };
@@ -543,6 +604,7 @@ struct ArgusLeaf {
   static constexpr int kKind = kArgus;
   static constexpr int NP = 2;
   static constexpr bool kLinear = true;
+  static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double m0, im02, c, dm0;  // dm0: 2/m0^3, or 0 when m0 is not differentiated
   };

@@ -21,7 +21,8 @@
 //   d log p / d theta = sum_k r_k dC_k + sum_l R_l fscale_lp phi_lp,
 //   r_k = e^{L_k - m} / s,  R_l = sum_{k contains l} r_k  (1 for root leaves)
 // and the parameter-only parts (dC_k, fscale, d log Z) are applied once,
-// after the reduction, to the accumulated sums of r_k and R_l phi_lp.
+// after the reduction, to the accumulated sums of r_k and R_l phi_lp
+// (the sum of r_{K-1} is N minus the others: sum_k r_k = 1 per event).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -259,10 +260,13 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       }
     }
     double m, s, e[K];
+    double d2 = 0.0, es2 = 0.0;  // two terms: their difference and e^-|d|
     if constexpr (K == 2) {
       const double d = Lk[0] - Lk[1];
       m = fmax(Lk[0], Lk[1]);
       const double es = exp(-fabs(d));
+      d2 = d;
+      es2 = es;
       e[0] = d >= 0.0 ? 1.0 : es;
       e[1] = d >= 0.0 ? es : 1.0;
       if constexpr (M::HAS_TLIN) {
@@ -298,11 +302,18 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       inv = fma(inv, fma(-s, inv, 1.0), inv);
       inv = fma(inv, fma(-s, inv, 1.0), inv);
       double r[K];
+      if constexpr (K == 2 && !M::HAS_TLIN) {
+        const double rs = es2 * inv;  // the smaller term's responsibility
+        r[0] = d2 >= 0.0 ? inv : rs;
+        r[1] = d2 >= 0.0 ? rs : inv;
+      } else {
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        r[k] = e[k] * inv;
-        acc.a[M::TERM_BASE + k] += r[k];
+        for (int k = 0; k < K; ++k) r[k] = e[k] * inv;
       }
+      // the responsibilities of an event sum to 1: the last term's total is
+      // N minus the others (formed after the reduction)
+#pragma unroll
+      for (int k = 0; k < K - 1; ++k) acc.a[M::TERM_BASE + k] += r[k];
       static_for<L>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
         using Sl = typename M::template S<l>;
@@ -547,10 +558,9 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts32<M>
       const float inv = rcp_f32(s);
       float r[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        r[k] = e[k] * inv;
-        acc.t[M::TERM_BASE + k] += r[k];
-      }
+      for (int k = 0; k < K; ++k) r[k] = e[k] * inv;
+#pragma unroll
+      for (int k = 0; k < K - 1; ++k) acc.t[M::TERM_BASE + k] += r[k];  // the last: N minus the others
       static_for<L>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
         using Sl = typename M::template S<l>;

@@ -102,71 +102,71 @@ __device__ inline void stage_theta(const double* __restrict__ theta_g, int n_par
   if ((int)threadIdx.x < n_param) dst[threadIdx.x] = theta_g[threadIdx.x];
 }
 
-// Fills *pt (LDS or global) for the parameter vector theta.  pl and theta
-// are the block's LDS copies (stage_plan, stage_theta, or values written by
-// the calling threads); all threads of the block must call it; on return
-// *pt is complete and visible to the block.
+// Fills *pt for the parameter vector theta.  pl and theta are the block's
+// LDS copies (stage_plan, stage_theta, or values written by the calling
+// threads); *pt should be LDS (its phases read back what other threads
+// wrote).  All threads of the block must call it; on return *pt is
+// complete and visible to the block.  Phases:
+//   (1) leaves normalised numerically: one Gauss-Legendre node per thread
+//       (skipped, with its barrier, when every leaf has a closed form);
+//   (2) in parallel: leaf l's constants and closed-form integrals on wave
+//       l % 4 (lanes cooperating where the leaf provides it), the parameter
+//       range checks (Sec. 3) and the term weights log w_k, d log w_k on
+//       lanes that hold no leaf;
+//   (3) term constants log w_k - sum log Z over the term's non-root leaves.
 template <class M, int NT = kBlock>
 __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* theta, const double* __restrict__ glx,
                                  const double* __restrict__ glw, PerTheta* pt, double* lds) {
   static_assert(NT >= kGLNodes && NT % 64 == 0, "at least one thread per quadrature node");
+  static_assert(M::L <= 6 && NT >= 256, "leaf lane groups at lanes 0 and 32 of waves 0..3, checks on 16..31, 48..63");
+  static_assert(kMaxParams <= 32 && kMaxSums + 1 <= 16 && kMaxTerms <= 16, "check and weight lanes");
   const int tid = threadIdx.x;
   __shared__ int s_bad;
+  __shared__ double s_lw[kMaxTerms];
   if (tid == 0) s_bad = 0;
-  // parallel zero fill of the term-weight derivatives
   for (int i = tid; i < kMaxTerms * kMaxParams; i += NT) (&pt->dlogw[0][0])[i] = 0.0;
   __syncthreads();
-  // parameter range checks (Sec. 3): one thread per parameter, per sum
-  if (tid < pl.n_param) {
-    const double v = theta[tid];
-    if (!(v >= pl.par_lo[tid] && v <= pl.par_hi[tid])) atomicOr(&s_bad, 1);  // NaN fails too
-  } else if (tid >= 64 && tid < 64 + pl.n_sum) {
-    const int q = tid - 64;
-    double f = 0.0;
-    bool ok = true;
-    for (int j = 0; j < pl.sum_nchild[q] - 1; ++j) {
-      const double v = theta[pl.sum_param[q][j]];
-      ok = ok && v >= 0.0 && v <= 1.0;
-      f += v;
-    }
-    if (!ok || !(f <= 1.0)) atomicOr(&s_bad, 1);
-  } else if (tid == 128 && pl.extended && !(theta[pl.yield_param] > 0.0)) {
-    atomicOr(&s_bad, 1);
+
+  // (1)
+  bool any_gl = false;
+#pragma unroll
+  for (int l = 0; l < M::L; ++l) any_gl = any_gl || pl.leaf_norm[l] != kNormAnalytic;
+  if (any_gl) {
+    static_for<M::L>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      using Leaf = typename M::template S<l>::Leaf;
+      if (pl.leaf_norm[l] != kNormAnalytic) {
+        double p[Leaf::NP];
+#pragma unroll
+        for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
+        const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
+        const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
+        double v[Leaf::NP + 1];
+        if (ok && tid < kGLNodes) {
+          gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
+        } else {
+#pragma unroll
+          for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
+        }
+        block_sum_small<Leaf::NP + 1>(v, lds);
+        if (tid == 0) {
+          pt->logz[l] = v[0];  // Z for now
+#pragma unroll
+          for (int j = 0; j < Leaf::NP; ++j) pt->dlogz[l][j] = v[j + 1];  // dZ for now
+        }
+      }
+    });
+    __syncthreads();
   }
 
-  // (1) numerically normalised leaves: every thread evaluates one
-  // Gauss-Legendre node, one leaf after the other
+  // (2a) leaf l: lanes [32 (l / 4), 32 (l / 4) + Leaf::kSetupLanes) of wave l % 4
   static_for<M::L>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     using Leaf = typename M::template S<l>::Leaf;
-    if (pl.leaf_norm[l] != kNormAnalytic) {
-      double p[Leaf::NP];
-#pragma unroll
-      for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
-      const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
-      const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
-      double v[Leaf::NP + 1];
-      if (ok && tid < kGLNodes) {
-        gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
-      } else {
-#pragma unroll
-        for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
-      }
-      block_sum_small<Leaf::NP + 1>(v, lds);
-      if (tid == 0) {
-        pt->logz[l] = v[0];  // Z for now
-#pragma unroll
-        for (int j = 0; j < Leaf::NP; ++j) pt->dlogz[l][j] = v[j + 1];  // dZ for now
-      }
-    }
-  });
-  __syncthreads();
-
-  // (2) per-leaf constants and closed-form integrals, leaf l on wave l % 4
-  static_for<M::L>([&](auto lc) {
-    constexpr int l = decltype(lc)::value;
-    using Leaf = typename M::template S<l>::Leaf;
-    if (tid == 64 * (l % 4) + l / 4) {
+    constexpr int owner = 64 * (l % 4) + 32 * (l / 4);
+    static_assert(Leaf::kSetupLanes >= 1 && Leaf::kSetupLanes <= 16, "setup lanes");
+    if (tid >= owner && tid < owner + Leaf::kSetupLanes) {
+      const int lane = tid - owner;
       double p[Leaf::NP];
 #pragma unroll
       for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
@@ -182,58 +182,100 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
       }
       s.Z = 0.0;
       s.kappa = 0.0;
-      if (ok) Leaf::setup(p, lo, hi, analytic, s);
-      if (!analytic) {
-        s.Z = pt->logz[l];
-        for (int j = 0; j < Leaf::NP; ++j) s.dZ[j] = pt->dlogz[l][j];
+      if (ok) {
+        if constexpr (Leaf::kSetupLanes > 1) {
+          Leaf::setup_coop(p, lo, hi, analytic, s, lane);
+        } else {
+          Leaf::setup(p, lo, hi, analytic, s);
+        }
       }
-      if constexpr (Leaf::kKind == kArgus) {
-        if (!pl.par_free[pl.leaf_param[l][0]]) s.ec[3] = 0.0;  // m0 not differentiated
-      }
-      if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) atomicOr(&s_bad, 1);
-      for (int j = 0; j < kLeafConsts; ++j) pt->ec[l][j] = s.ec[j];
-      const double iz = 1.0 / s.Z;
-      // the FP32 pass evaluates the leaf on x - x0: its log-density is off
-      // by the constant kappa, absorbed here into the normalisation
-      pt->logz[l] = M::PREC == 1 ? log(s.Z) - s.kappa : log(s.Z);
-      for (int j = 0; j < kMaxLeafParams; ++j) {
-        pt->fscale[l][j] = s.fscale[j];
-        pt->dlogz[l][j] = j < Leaf::NP ? s.dZ[j] * iz : 0.0;
-        pt->phioff[l][j] = M::PREC == 1 ? s.phioff[j] : 0.0;
+      if (lane == 0) {
+        if (!analytic) {
+          s.Z = pt->logz[l];
+          for (int j = 0; j < Leaf::NP; ++j) s.dZ[j] = pt->dlogz[l][j];
+        }
+        if constexpr (Leaf::kKind == kArgus) {
+          if (!pl.par_free[pl.leaf_param[l][0]]) s.ec[3] = 0.0;  // m0 not differentiated
+        }
+        if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) atomicOr(&s_bad, 1);
+        for (int j = 0; j < kLeafConsts; ++j) pt->ec[l][j] = s.ec[j];
+        const double iz = 1.0 / s.Z;
+        // the FP32 pass evaluates the leaf on x - x0: its log-density is off
+        // by the constant kappa, absorbed here into the normalisation
+        pt->logz[l] = M::PREC == 1 ? log(s.Z) - s.kappa : log(s.Z);
+        for (int j = 0; j < kMaxLeafParams; ++j) {
+          pt->fscale[l][j] = s.fscale[j];
+          pt->dlogz[l][j] = j < Leaf::NP ? s.dZ[j] * iz : 0.0;
+          pt->phioff[l][j] = M::PREC == 1 ? s.phioff[j] : 0.0;
+        }
       }
     }
   });
+
+  // (2b) checks (Sec. 3) on lanes no leaf uses (leaf groups start at lanes 0
+  // and 32 of each wave): parameter ranges, one lane per parameter, on
+  // lanes 16..31 and 48..63 of wave 2; sum fractions in [0, 1] with a sum
+  // <= 1, one lane per sum node, and a positive yield, on lanes 16..20 of wave 1
+  if ((tid >= 144 && tid < 160) || (tid >= 176 && tid < 192)) {
+    const int q = tid < 160 ? tid - 144 : tid - 176 + 16;
+    if (q < pl.n_param) {
+      const double v = theta[q];
+      if (!(v >= pl.par_lo[q] && v <= pl.par_hi[q])) atomicOr(&s_bad, 1);  // NaN fails too
+    }
+  } else if (tid >= 80 && tid < 80 + kMaxSums) {
+    const int qs = tid - 80;
+    if (qs < pl.n_sum) {
+      double f = 0.0;
+      bool ok = true;
+      for (int j = 0; j < pl.sum_nchild[qs] - 1; ++j) {
+        const double v = theta[pl.sum_param[qs][j]];
+        ok = ok && v >= 0.0 && v <= 1.0;
+        f += v;
+      }
+      if (!ok || !(f <= 1.0)) atomicOr(&s_bad, 1);
+    }
+  } else if (tid == 80 + kMaxSums) {
+    if (pl.extended && !(theta[pl.yield_param] > 0.0)) atomicOr(&s_bad, 1);
+  }
+
+  // (2c) term weights, one lane per term on wave 3 lanes 16..23: log w_k and
+  // d log w_k / d theta over the fraction parameters of every sum on the
+  // path.  Coefficients are floored at 1e-200 so that a fraction at exactly
+  // 0 or 1 keeps a finite log and a finite d/df (the floored term then
+  // carries a weight of 1e-200, i.e. nothing, in the likelihood).
+  if (tid >= 208 && tid < 208 + M::K) {
+    const int k = tid - 208;
+    double lw = 0.0;
+    for (int r = 0; r < pl.term_nref[k]; ++r) {
+      const int q = pl.term_ref_sum[k][r], j = pl.term_ref_child[k][r];
+      const int nc = pl.sum_nchild[q];
+      double f = 0.0;
+      for (int i = 0; i < nc - 1; ++i) f += theta[pl.sum_param[q][i]];
+      const double c = (j < nc - 1) ? theta[pl.sum_param[q][j]] : 1.0 - f;
+      const double cf = fmax(c, 1e-200);
+      lw += log(cf);
+      if (j < nc - 1) {
+        pt->dlogw[k][pl.sum_param[q][j]] += 1.0 / cf;
+      } else {
+        for (int i = 0; i < nc - 1; ++i) pt->dlogw[k][pl.sum_param[q][i]] -= 1.0 / cf;
+      }
+    }
+    s_lw[k] = lw;
+  }
   __syncthreads();
 
-  // (3) term constants, one lane per term: log w_k - sum_{non-root l in S_k}
-  // log Z_l and d log w_k / d theta over the fraction parameters of every sum
-  // on the path.  Coefficients are floored at 1e-200 so that a fraction at
-  // exactly 0 or 1 keeps a finite log and a finite d/df (the floored term
-  // then carries a weight of 1e-200, i.e. nothing, in the likelihood).
-  const int k = tid;
-  if (k < kMaxTerms) {
-    double lw = 0.0;
+  // (3) term constants: log w_k - sum_{non-root l in S_k} log Z_l
+  if (tid < kMaxTerms) {
+    const int k = tid;
+    double ck = 0.0;
     if (k < M::K) {
-      for (int r = 0; r < pl.term_nref[k]; ++r) {
-        const int q = pl.term_ref_sum[k][r], j = pl.term_ref_child[k][r];
-        const int nc = pl.sum_nchild[q];
-        double f = 0.0;
-        for (int i = 0; i < nc - 1; ++i) f += theta[pl.sum_param[q][i]];
-        const double c = (j < nc - 1) ? theta[pl.sum_param[q][j]] : 1.0 - f;
-        const double cf = fmax(c, 1e-200);
-        lw += log(cf);
-        if (j < nc - 1) {
-          pt->dlogw[k][pl.sum_param[q][j]] += 1.0 / cf;
-        } else {
-          for (int i = 0; i < nc - 1; ++i) pt->dlogw[k][pl.sum_param[q][i]] -= 1.0 / cf;
-        }
-      }
+      ck = s_lw[k];
       const int mask = pl.term_mask[k];
 #pragma unroll
       for (int l = 0; l < M::L; ++l)
-        if (!M::ROOTs[l] && ((mask >> l) & 1)) lw -= pt->logz[l];
+        if (!M::ROOTs[l] && ((mask >> l) & 1)) ck -= pt->logz[l];
     }
-    pt->ck[k] = lw;
+    pt->ck[k] = ck;
   } else if (tid == 64) {
     double croot = 0.0;
 #pragma unroll
