@@ -202,21 +202,42 @@ __device__ inline void compute_tile(const double (&x)[U][M::NOBS], const CT& C, 
 }
 
 // Full tiles base0, base0 + stride, ... (count of them), software
-// pipelined: the first tile arrives preloaded in xn, and the loads of the
-// next tile are issued before the current one is computed so that two tiles
-// of loads are in flight per wave.
+// pipelined through a ring of kRing register buffers: the first kRing - 1
+// tiles arrive preloaded in xb[0 .. kRing-2], and before tile k is computed
+// the loads of tile k + kRing - 1 are issued into the buffer that tile k - 1
+// used, so each load has kRing - 1 tiles of compute to arrive.  The ring is
+// unrolled (buffers rotate without copies) and its loads are unconditional:
+// past the last tile they re-read the last one (a cache hit, never used),
+// so the loop body has no branches and the compiler's load-counter waits
+// see every load of the ring in flight.
+constexpr int kRing = 3;
+
+template <class M, int U>
+__device__ inline void preload_ring(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
+                                    double (&xb)[kRing][U][M::NOBS]) {
+#pragma unroll
+  for (int j = 0; j < kRing - 1; ++j)
+    if (j < count) load_tile<M, U>(cols, base0 + j * stride, xb[j]);
+}
+
 template <class M, bool GRAD, int U, class CT, class AT>
 __device__ inline void stream_tiles(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
-                                    double (&xn)[U][M::NOBS], const CT& C, AT& acc) {
-  for (int64_t k = 0; k < count; ++k) {
-    double xc[U][M::NOBS];
+                                    double (&xb)[kRing][U][M::NOBS], const CT& C, AT& acc) {
+  const int64_t groups = count / kRing;
+  for (int64_t g = 0; g < groups; ++g) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int o = 0; o < M::NOBS; ++o) xc[u][o] = xn[u][o];
-    if (k + 1 < count) load_tile<M, U>(cols, base0 + (k + 1) * stride, xn);
-    compute_tile<M, GRAD, U>(xc, C, acc);
+    for (int j = 0; j < kRing; ++j) {
+      const int64_t k = g * kRing + j;
+      const int64_t kl = k + kRing - 1 < count ? k + kRing - 1 : count - 1;
+      load_tile<M, U>(cols, base0 + kl * stride, xb[(j + kRing - 1) % kRing]);
+      compute_tile<M, GRAD, U>(xb[j], C, acc);
+    }
   }
+  // tiles groups * kRing + j, j < count % kRing, are in xb[j]
+  const int64_t rem = count - groups * kRing;
+#pragma unroll
+  for (int j = 0; j < kRing - 1; ++j)
+    if (j < rem) compute_tile<M, GRAD, U>(xb[j], C, acc);
 }
 
 template <class M, bool GRAD, int U, class CT, class AT>
@@ -278,8 +299,8 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   const int64_t nfull = a.n / tile;
   const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const int64_t base0 = (int64_t)blockIdx.x * tile + threadIdx.x;
-  double xn[U][M::NOBS];
-  if (mine > 0) load_tile<M, U>(cols, base0, xn);
+  double xb[kRing][U][M::NOBS];
+  preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
 
   if constexpr (FIT) {
 #pragma unroll
@@ -296,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   typename Pass<M, GRAD>::A acc;
   acc.init();
   if (uniform(pt.bad) == 0) {
-    stream_tiles<M, GRAD, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xn, C, acc);
+    stream_tiles<M, GRAD, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb, C, acc);
     const int64_t rest = nfull * tile;
     if (rest < a.n && blockIdx.x == (unsigned)(nfull % gridDim.x))
       stream_part_tile<M, GRAD, U>(cols, rest + threadIdx.x, a.n, C, acc);
@@ -413,9 +434,9 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     if (uniform(pt.bad) == 0 && cur.flag == 0) {
       const int64_t step = (int64_t)kBlock * U;
       const int64_t full = (end - start) / step;
-      double xn[U][M::NOBS];
-      if (full > 0) load_tile<M, U>(cols, start + threadIdx.x, xn);
-      stream_tiles<M, GRAD, U>(cols, start + threadIdx.x, step, full, xn, C, acc);
+      double xb[kRing][U][M::NOBS];
+      preload_ring<M, U>(cols, start + threadIdx.x, step, full, xb);
+      stream_tiles<M, GRAD, U>(cols, start + threadIdx.x, step, full, xb, C, acc);
       const int64_t base = start + full * step;
       if (base < end) stream_part_tile<M, GRAD, U>(cols, base + threadIdx.x, end, C, acc);
     }

