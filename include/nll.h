@@ -193,8 +193,9 @@ nll_status nll_fit(nll_model* model, double* theta, int32_t n_steps, double eta,
 nll_status nll_sync(nll_model* model, int32_t* status_out);
 
 /* Launch schedule of the streaming kernels.  A new model starts with
- * {4, 2, 16384, 16, 2}; persistent grids reserve LDS so that at most the
- * given number of blocks share a CU. */
+ * {4, 2, 16384, 16, 2}, or {2, 2, 16384, 16, 2} for shapes with more than 8
+ * gradient accumulators (n_accumulators in nll_model_info); persistent
+ * grids reserve LDS so that at most the given number of blocks share a CU. */
 typedef struct nll_schedule {
   int32_t unroll;             /* events per thread per tile: 2, 4 or 8 (8
                                  falls back to 4 for shapes with more than 8

@@ -604,6 +604,9 @@ nll_status nll_create_model(const nll_model_desc* desc, nll_model** out) {
     nll_destroy_model(m);
     return s;
   };
+  // shapes with many gradient accumulators keep 2 events per thread per
+  // tile (4 interleaved events exceed the register file: measured slower)
+  if (ops->na_grad > 8) m->sched.unroll = 2;
   if ((st = gl_table(m->device, &m->gl)) != NLL_OK) return fail(st);
   const size_t max_grid = (size_t)m->n_cu * 32;
   if ((st = dalloc(&m->partials, max_grid * (size_t)(ops->na_grad + 1) * 2)) != NLL_OK) return fail(st);

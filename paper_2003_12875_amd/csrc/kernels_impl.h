@@ -278,17 +278,9 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   // Evaluation: plan and parameters first, then the first event tile
   // (which does not depend on theta), whose loads overlap the prologue.
   // Fit: the constants of the proposal were prepared by the previous step's
-  // finishing kernel; one parallel copy, then the first tile.
-  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
-  constexpr int PTR = (PT8 + kBlock - 1) / kBlock;
-  double ptv[FIT ? PTR : 1];
-  if constexpr (FIT) {
-#pragma unroll
-    for (int i = 0; i < PTR; ++i) {
-      const int e = threadIdx.x + i * kBlock;
-      ptv[i] = e < PT8 ? reinterpret_cast<const double*>(a.consts)[e] : 0.0;
-    }
-  } else {
+  // finishing kernel; the event pass reads the few it needs straight from
+  // there (uniform loads), overlapping the first tiles' loads.
+  if constexpr (!FIT) {
     stage_plan<kBlock>(pl, &spl);
     stage_theta(a.theta, pl.n_param, s_theta);
   }
@@ -302,21 +294,19 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   double xb[kRing][U][M::NOBS];
   preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
 
+  typename Pass<M, GRAD>::C C;
+  int bad;
   if constexpr (FIT) {
-#pragma unroll
-    for (int i = 0; i < PTR; ++i) {
-      const int e = threadIdx.x + i * kBlock;
-      if (e < PT8) reinterpret_cast<double*>(&pt)[e] = ptv[i];
-    }
-    __syncthreads();
+    C.load(*a.consts, pl);
+    bad = uniform(a.consts->bad);
   } else {
     compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
+    C.load(pt, pl);
+    bad = uniform(pt.bad);
   }
-  typename Pass<M, GRAD>::C C;
-  C.load(pt, pl);
   typename Pass<M, GRAD>::A acc;
   acc.init();
-  if (uniform(pt.bad) == 0) {
+  if (bad == 0) {
     stream_tiles<M, GRAD, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb, C, acc);
     const int64_t rest = nfull * tile;
     if (rest < a.n && blockIdx.x == (unsigned)(nfull % gridDim.x))
@@ -347,7 +337,6 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
   constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
   static_assert(PT8 <= kFinishBlock, "one constant per thread");
   __shared__ Plan spl;
-  __shared__ DD red[kFinishBlock / 64];
   __shared__ DD tot[NV];
   __shared__ double s_grad[kMaxParams];
   __shared__ PerTheta spt;
@@ -364,7 +353,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
   RecordSum<NV, kFinishBlock> rs;
   rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
   if (t < PT8) reinterpret_cast<double*>(&spt)[t] = ptv;
-  rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, red, tot);  // ends with a barrier
+  rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
   finish_block<M, GRAD>(spl, spt, tot, a.n, s_theta, false, &s_nll, &s_st, s_grad);
   if constexpr (FIT) {
     const double next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, a.n, pre);
@@ -459,7 +448,6 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   constexpr int NV = NA + 1;
   constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
   __shared__ Plan spl;
-  __shared__ DD red[kBlock / 64];
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
   __shared__ double s_grad[kMaxParams];
@@ -494,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
     const int e = t + i * kBlock;
     if (e < PT8) reinterpret_cast<double*>(&spt)[e] = ptv[i];
   }
-  rs.reduce(recs, n_items, red, tot);  // ends with a barrier
+  rs.reduce(recs, n_items, tot);  // ends with a barrier
   const int64_t n_s = flag ? 0 : o1 - o0;
   finish_block<M, GRAD>(spl, spt, tot, n_s, s_theta, flag != 0, &s_nll, &s_st, s_grad);
   if constexpr (!FIT) {

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fp32.h"
+#include "fp64.h"
 #include "plan.h"
 
 namespace nllmi {
@@ -323,10 +324,7 @@ struct ChebLeaf {
       gam = 1.0;
     }
     if (GRAD) {
-      // 1/g: hardware reciprocal refined by two Newton steps
-      double r = __builtin_amdgcn_rcp(g);
-      r = fma(r, fma(-g, r, 1.0), r);
-      r = fma(r, fma(-g, r, 1.0), r);
+      const double r = rcp_grad(g);
 #pragma unroll
       for (int k = 0; k < K; ++k) phi[k] = tk[k] * r;
     }
@@ -470,9 +468,10 @@ struct CBLeaf {
   __device__ static C load(const double* ec) {
     return C{ec[0], ec[1], ec[2], ec[3], ec[4], ec[5], ec[6], ec[7], ec[8], ec[9]};
   }
-  // The power-law tail holds a few per cent of the events: it is a real
-  // branch (a wavefront skips it unless one of its lanes is in the tail),
-  // the core a straight line.
+  // The power-law tail is a real branch (a wavefront skips it unless one of
+  // its lanes is in the tail), the core a straight line.  In a mixture every
+  // event evaluates the Crystal Ball, so events of the other components
+  // below the junction take the tail too.
   template <bool GRAD>
   __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
     const double t = fma(x, c.is, c.b);
@@ -486,13 +485,11 @@ struct CBLeaf {
       phi[3] = 0.0;
     }
     if (!(t > c.na)) {
-      const double D = c.B - t;
-      const double lD = log(D);
+      const double D = c.B - t;  // >= n / alpha > 0
+      const double lD = log_pos(D);
       lam = fma(-c.n, lD, c.logA);
       if (GRAD) {
-        double r = __builtin_amdgcn_rcp(D);
-        r = fma(r, fma(-D, r, 1.0), r);
-        r = fma(r, fma(-D, r, 1.0), r);
+        const double r = rcp_grad(D);
         const double nr = c.n * r;
         phi[0] = -nr;
         phi[1] = -nr * t;
@@ -658,19 +655,14 @@ struct ArgusLeaf {
     const double us = in ? u : 1.0;
     if (LIN) {
       lam = in ? c.c * us : -__builtin_inf();
-      gam = in ? x * sqrt(us) : 0.0;
+      gam = in ? x * sqrt_pos(us) : 0.0;  // us: u > 0 (normal) or 1
     } else {
       lam = in ? fma(0.5, log(x * x * us), c.c * us) : -__builtin_inf();
       gam = 1.0;
     }
     if (GRAD) {
       double d0 = 0.0;
-      if (c.dm0 != 0.0) {
-        double r = __builtin_amdgcn_rcp(us);
-        r = fma(r, fma(-us, r, 1.0), r);
-        r = fma(r, fma(-us, r, 1.0), r);
-        d0 = fma(0.5, r, c.c) * (x * x) * c.dm0;
-      }
+      if (c.dm0 != 0.0) d0 = fma(0.5, rcp_grad(us), c.c) * (x * x) * c.dm0;
       phi[0] = in ? d0 : 0.0;
       phi[1] = in ? us : 0.0;
     }

@@ -32,6 +32,7 @@
 #include <utility>
 
 #include "fp32.h"
+#include "fp64.h"
 #include "leaves.h"
 #include "plan.h"
 
@@ -53,34 +54,6 @@ __device__ inline double uniform(double v) {
   return __hiloint2double(hi, lo);
 }
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// e^a for a <= 0 (the log-sum-exp factors e^{L_k - m}).  a = n ln2 + r with
-// |r| <= ln2/2 (ln2 as a two-double sum, each step one FMA); e^r by the
-// degree-11 polynomial that interpolates exp at the 12 Chebyshev points of
-// [-ln2/2, ln2/2] (interpolation error 3.2e-18 relative, below the rounding
-// of its Horner evaluation); then 2^n e^r.  Measured on the device: at most
-// 1 ulp from the correctly rounded value over 4e6 arguments in [-750, 0].
-// The argument is clamped at -746, where e^a rounds to 0, so that -inf (a
-// term with zero density) gives 0.
-__device__ __forceinline__ double exp_nonpos(double a) {
-  a = fmax(a, -746.0);
-  const double n = __builtin_rint(a * 1.4426950408889634);
-  double r = fma(n, -0.6931471805599453, a);
-  r = fma(n, -2.3190468138462996e-17, r);
-  double p = 2.5110037605963777e-08;
-  p = fma(p, r, 2.763263963904103e-07);
-  p = fma(p, r, 2.755724091857897e-06);
-  p = fma(p, r, 2.4801485482328494e-05);
-  p = fma(p, r, 0.00019841269890047113);
-  p = fma(p, r, 0.0013888888952314775);
-  p = fma(p, r, 0.008333333333319601);
-  p = fma(p, r, 0.0416666666664881);
-  p = fma(p, r, 0.1666666666666668);
-  p = fma(p, r, 0.5000000000000019);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
-  return __builtin_ldexp(p, (int)n);
-}
 
 template <class LeafT, int OBS, bool ROOT>
 struct Slot {
@@ -326,10 +299,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       acc.P *= s;
     }
     if constexpr (GRAD) {
-      // hardware reciprocal (2^-24 relative, measured) and one Newton step:
-      // 2^-48, ample for the responsibilities (gradient only; the NLL uses s)
-      double inv = __builtin_amdgcn_rcp(s);
-      inv = fma(inv, fma(-s, inv, 1.0), inv);
+      const double inv = rcp_grad(s);  // responsibilities: gradient only
       double r[K];
       if constexpr (K == 2 && !M::HAS_TLIN) {
         const double rs = es2 * inv;  // the smaller term's responsibility

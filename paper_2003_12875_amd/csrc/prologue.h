@@ -202,7 +202,8 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
         const double iz = 1.0 / s.Z;
         // the FP32 pass evaluates the leaf on x - x0: its log-density is off
         // by the constant kappa, absorbed here into the normalisation
-        pt->logz[l] = M::PREC == 1 ? log(s.Z) - s.kappa : log(s.Z);
+        const double lz = log_pos(s.Z);  // Z > 0 finite unless flagged just above
+        pt->logz[l] = M::PREC == 1 ? lz - s.kappa : lz;
         for (int j = 0; j < kMaxLeafParams; ++j) {
           pt->fscale[l][j] = s.fscale[j];
           pt->dlogz[l][j] = j < Leaf::NP ? s.dZ[j] * iz : 0.0;
@@ -253,7 +254,7 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
       for (int i = 0; i < nc - 1; ++i) f += theta[pl.sum_param[q][i]];
       const double c = (j < nc - 1) ? theta[pl.sum_param[q][j]] : 1.0 - f;
       const double cf = fmax(c, 1e-200);
-      lw += log(cf);
+      lw += log_pos(cf);
       if (j < nc - 1) {
         pt->dlogw[k][pl.sum_param[q][j]] += 1.0 / cf;
       } else {

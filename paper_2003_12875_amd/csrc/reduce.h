@@ -100,14 +100,15 @@ __device__ inline void block_sum_vals(const double (&v)[NV], double* buf, DD* ou
 // between them: issue() starts the loads of the first B records of every
 // lane, reduce() adds them (and any further batches) and combines lanes.
 // Accumulator j is served by the S consecutive threads [j S, (j+1) S): lane
-// k sums records k, k + S, ... in order, then the S lanes are combined by
-// an xor-butterfly (and, for S > 64, the waves in order through lds).  The
-// order depends only on count and NV, so results are reproducible.  The
-// totals land in out[NV].
+// k sums records k, k + S, ... in order, then the S lanes (one wave at
+// most) are combined by an xor-butterfly.  The order depends only on count
+// and NV, so results are reproducible.  The totals land in out[NV].
 template <int NV, int BLOCK>
 struct RecordSum {
+  // at most one wave per accumulator: no cross-wave step (a barrier and an
+  // LDS round trip cost more than the longer per-lane chains)
   static constexpr int S0 = pow2_floor<(BLOCK / NV > 0 ? BLOCK / NV : 1)>();
-  static constexpr int S = S0 > 512 ? 512 : S0;
+  static constexpr int S = S0 > 64 ? 64 : S0;
   static constexpr int B = 8;
   static_assert(S * NV <= BLOCK, "lanes per accumulator");
   DD buf[B];
@@ -122,7 +123,7 @@ struct RecordSum {
     }
   }
 
-  __device__ void reduce(const DD* src, int64_t count, DD* lds, DD* out) {
+  __device__ void reduce(const DD* src, int64_t count, DD* out) {
     const int t = threadIdx.x;
     const int j = t / S, k = t % S;
     DD acc = buf[0];
@@ -137,19 +138,8 @@ struct RecordSum {
 #pragma unroll
       for (int b = 0; b < B; ++b) acc = dd_add(acc, buf[b]);
     }
-    constexpr int W = S < 64 ? S : 64;
-    acc = group_sum_dd<W>(acc);
-    if constexpr (S <= 64) {
-      if (j < NV && k == 0) out[j] = acc;
-    } else {
-      if ((t & 63) == 0) lds[t >> 6] = acc;
-      __syncthreads();
-      if (t < NV) {
-        DD v = lds[t * (S / 64)];
-        for (int q = 1; q < S / 64; ++q) v = dd_add(v, lds[t * (S / 64) + q]);
-        out[t] = v;
-      }
-    }
+    acc = group_sum_dd<S>(acc);
+    if (j < NV && k == 0) out[j] = acc;
     __syncthreads();
   }
 };
