@@ -14,9 +14,9 @@ Also reported, on the same GPU:
     gradient (2P+1 passes per step), the per-fit speed-up of the adjoint;
   * roofline    -- algorithmic bytes per launch of the dominant kernel (the
     fused streaming kernel) over its average duration, measured in the same
-    run with HIP events recorded on the library's stream right before and
-    after that kernel in every step of an eager K-step fit, against the
-    8 TB/s HBM peak; `traffic` is the HBM byte count per launch from the
+    run with HIP start/stop events attached to that kernel's launch on the
+    library's stream (hipExtLaunchKernel) in every step of an eager K-step
+    fit, against the 8 TB/s HBM peak; `traffic` is the HBM byte count per launch from the
     FETCH_SIZE and WRITE_SIZE counter summary under profiles/ (scaled by the
     same counters on a plain streaming kernel of known size), reported only
     while the kernel sources still hash to what was profiled;
@@ -27,7 +27,11 @@ Also reported, on the same GPU:
     and FP32-compensated passes), the 2-D Crystal Ball/ARGUS x Chebyshev
     model (5e7 events), and 4096 batched toy fits (4.1e8 events per step).
 
-    python bench.py [--steps K] [--warmup W] [--quick] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--quick] [--no-cpu-baseline] [--no-tune]
+
+Each workload first runs the library's autotuner (nll_autotune: every
+candidate launch schedule checked against the current one's NLL, the
+fastest kept); --no-tune keeps the default schedules.
 
 Profiling helpers (used to write the summaries under profiles/):
     python bench.py --probe pmc          # calibration copy + a few eager fit steps
@@ -151,6 +155,7 @@ def headline(torch, nllmi, datagen, args):
     model = nllmi.Model.from_spec(spec)
     model.set_data(cols)
     theta0 = w["points"][0]
+    tune(torch, model, theta0, args)
     log(f"c2: timing {args.steps} gradient-descent steps")
     r = timed_fit(torch, model, theta0, args.steps, args.warmup)
     if r["status"] != 0:
@@ -158,8 +163,8 @@ def headline(torch, nllmi, datagen, args):
     ms_per_step = 1e3 * r["wall_s"] / args.steps
     value = n * args.steps / r["wall_s"]
     graph_step_ms = r["gpu_ms"] / args.steps  # HIP events around the replay, per step
-    # the dominant kernel alone: events right before and after the streaming
-    # kernel of every step of an eager fit of the same K steps
+    # the dominant kernel alone: start/stop events attached to the streaming
+    # kernel's launch in every step of an eager fit of the same K steps
     kt = timed_fit(torch, model, theta0, args.steps, 0, step_timing="kernel")
     kern_ms = sum(kt["step_ms"]) / len(kt["step_ms"])
     bytes_per_launch = 8.0 * n * len(spec["obs"])
@@ -197,7 +202,19 @@ def headline(torch, nllmi, datagen, args):
     return res, w, model
 
 
-def cpu_baseline(datagen, w, budget_s=8.0):
+def tune(torch, model, theta, args, offsets=None):
+    """The library's autotuner on this workload (unless --no-tune): every
+    candidate schedule is checked against the default's NLL, the fastest
+    kept.  No cache file: it tunes afresh."""
+    if args.no_tune:
+        return
+    os.environ.pop("NLLMI_TUNE_CACHE", None)
+    th = torch.as_tensor(theta, dtype=torch.float64, device="cuda")
+    model.autotune(th, offsets=offsets)
+    log(f"tuned schedule: {model.schedule}")
+
+
+def cpu_baseline(datagen, w, budget_s=12.0):
     import oracle
     o = oracle.Oracle(w["spec"])
     T = cores()
@@ -243,11 +260,13 @@ def extras(torch, nllmi, datagen, args):
     for prec in ("fp64", "fp32c"):
         m = nllmi.Model.from_spec(w["spec"], precision=prec)
         m.set_data(cols)
+        tune(torch, m, pts[0], args)
         tg = time_launches(torch, lambda: m.eval_grad(pts[0], out=out5, grad=g5), 10)
         vals[prec] = [(float(a.item()), b.cpu().numpy()) for a, b in (m.eval_grad(pts[i]) for i in range(32))]
         res5[prec] = {"eval_grad_ms": tg, "events_per_s": w["n"] / (tg * 1e-3),
                       "achieved_GBs": 8.0 * w["n"] / (tg * 1e-3) / 1e9,
-                      "hbm_frac": 8.0 * w["n"] / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS, "variant": m.info["variant"]}
+                      "hbm_frac": 8.0 * w["n"] / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS, "variant": m.info["variant"],
+                      "schedule": m.schedule}
         del m
     import numpy as np
     nerr = [abs(a[0] / b[0] - 1.0) for a, b in zip(vals["fp32c"], vals["fp64"])]
@@ -266,12 +285,13 @@ def extras(torch, nllmi, datagen, args):
     th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
     out = torch.empty(1, dtype=torch.float64, device="cuda")
     g = torch.empty(m.n_param, dtype=torch.float64, device="cuda")
+    tune(torch, m, th, args)
     tg = time_launches(torch, lambda: m.eval_grad(th, out=out, grad=g), 10)
     tf = time_launches(torch, lambda: m.eval(th, out=out), 10)
     ex["cb_argus_cheb_5e7"] = {"eval_grad_ms": tg, "eval_ms": tf, "events_per_s": w["n"] / (tg * 1e-3),
                                "achieved_GBs": 16.0 * w["n"] / (tg * 1e-3) / 1e9,
                                "hbm_frac": 16.0 * w["n"] / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                               "fd_step_ms": 19 * tf, "speedup_vs_fd": 19 * tf / tg}
+                               "fd_step_ms": 19 * tf, "speedup_vs_fd": 19 * tf / tg, "schedule": m.schedule}
     del m, cols
     torch.cuda.empty_cache()
     # 4096 toys, sizes U[1e3, 2e5], 50 gradient-descent steps each, one graph
@@ -282,6 +302,7 @@ def extras(torch, nllmi, datagen, args):
     m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
     offs = torch.from_numpy(w["offsets"]).cuda()
     start = torch.as_tensor(w["theta_start"], dtype=torch.float64, device="cuda").repeat(4096, 1)
+    tune(torch, m, start, args, offsets=offs)
     bufs = (start.clone(), torch.empty(4096, dtype=torch.float64, device="cuda"),
             torch.empty(4096, 2, dtype=torch.float64, device="cuda"),
             torch.empty(4096, dtype=torch.int32, device="cuda"))
@@ -401,6 +422,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedules")
     ap.add_argument("--probe", choices=["pmc"], help="run the counter-collection workload only")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--workload-name", default="")

@@ -215,7 +215,9 @@ nll_status nll_set_schedule(nll_model* model, const nll_schedule* sched);
 
 /* Time the candidate schedules on the attached data (synchronises; several
  * evaluations per candidate), check each candidate's NLL against the
- * default schedule's, keep the fastest.  which: 1 = single dataset,
+ * current schedule's (1e-12 relative in FP64; max(1e-9, 1e-6/sqrt(N)), or
+ * 1e-6 for sets, in NLL_FP32C, whose single-precision per-thread sums
+ * regroup with the schedule), keep the fastest.  which: 1 = single dataset,
  * 2 = batched with the given sets (n_sets/offsets/theta as in
  * nll_eval_batched).  Results are cached per model shape, precision and
  * event-count bucket in the file named by $NLLMI_TUNE_CACHE, if set. */
@@ -226,11 +228,13 @@ nll_status nll_autotune(nll_model* model, int32_t which, int32_t n_sets, const i
  *   NLL_OPT_GRAPH        1 (default): fits are recorded once into a HIP graph
  *                        and replayed; 0: fits are enqueued eagerly
  *   NLL_OPT_STEP_TIMING  1: fits are enqueued eagerly with a HIP event before
- *                        the first and after every step; 2: eagerly, with a
- *                        HIP event right before and right after the event-
- *                        streaming kernel of every step (its duration alone,
- *                        without the finishing kernel); read by
- *                        nll_step_times; 0 (default): no events.
+ *                        the first and after every step; 2: eagerly, with
+ *                        the event-streaming kernel of every step launched
+ *                        with a start and a stop event attached
+ *                        (hipExtLaunchKernel), so that they record that
+ *                        dispatch's own start and end (its duration alone,
+ *                        without the finishing kernel or queue gaps); read
+ *                        by nll_step_times; 0 (default): no events.
  *                        Other values: NLL_ERR_ARG.                        */
 enum nll_option { NLL_OPT_GRAPH = 1, NLL_OPT_STEP_TIMING = 2 };
 nll_status nll_set_option(nll_model* model, int32_t option, int32_t value);

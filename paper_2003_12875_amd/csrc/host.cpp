@@ -473,7 +473,8 @@ void record_step(nll_model* m, int s, hipStream_t st) {
   if (m->step_timing == 1) (void)hipEventRecord(m->events[s], st);
 }
 
-// events around the streaming kernel of step s (kernel timing only)
+// start and stop events attached to the streaming kernel of step s
+// (kernel timing only)
 hipEvent_t kernel_event(nll_model* m, int s, int which) {
   return m->step_timing == 2 ? m->events[2 * s + which] : nullptr;
 }

@@ -19,6 +19,7 @@
 // No matrix cores: the pass is a streaming map-reduce.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -202,41 +203,46 @@ __device__ inline void compute_tile(const double (&x)[U][M::NOBS], const CT& C, 
 }
 
 // Full tiles base0, base0 + stride, ... (count of them), software
-// pipelined through a ring of kRing register buffers: the first kRing - 1
-// tiles arrive preloaded in xb[0 .. kRing-2], and before tile k is computed
-// the loads of tile k + kRing - 1 are issued into the buffer that tile k - 1
-// used, so each load has kRing - 1 tiles of compute to arrive.  The ring is
-// unrolled (buffers rotate without copies) and its loads are unconditional:
-// past the last tile they re-read the last one (a cache hit, never used),
-// so the loop body has no branches and the compiler's load-counter waits
-// see every load of the ring in flight.
-constexpr int kRing = 3;
+// pipelined through a ring of R register buffers: the first R - 1 tiles
+// arrive preloaded in xb[0 .. R-2], and before tile k is computed the loads
+// of tile k + R - 1 are issued into the buffer that tile k - 1 used, so each
+// load has R - 1 tiles of compute to arrive.  The ring is unrolled (buffers
+// rotate without copies) and its loads are unconditional: past the last
+// tile they re-read the last one (a cache hit, never used), so the loop body
+// has no branches and the compiler's load-counter waits see every load of
+// the ring in flight.  Three buffers for shapes with at most 8 accumulators;
+// two for the heavier ones, whose registers are already scarce (measured:
+// three cost the 2-D model ~4-5 %, two cost the mixture at 1e8 events ~18 %).
+template <class M>
+constexpr int ring_depth() {
+  return M::template NA<true> <= 8 ? 3 : 2;
+}
 
-template <class M, int U>
+template <class M, int U, int R>
 __device__ inline void preload_ring(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
-                                    double (&xb)[kRing][U][M::NOBS]) {
+                                    double (&xb)[R][U][M::NOBS]) {
 #pragma unroll
-  for (int j = 0; j < kRing - 1; ++j)
+  for (int j = 0; j < R - 1; ++j)
     if (j < count) load_tile<M, U>(cols, base0 + j * stride, xb[j]);
 }
 
-template <class M, bool GRAD, int U, class CT, class AT>
+template <class M, bool GRAD, int U, int R, class CT, class AT>
 __device__ inline void stream_tiles(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
-                                    double (&xb)[kRing][U][M::NOBS], const CT& C, AT& acc) {
-  const int64_t groups = count / kRing;
+                                    double (&xb)[R][U][M::NOBS], const CT& C, AT& acc) {
+  const int64_t groups = count / R;
   for (int64_t g = 0; g < groups; ++g) {
 #pragma unroll
-    for (int j = 0; j < kRing; ++j) {
-      const int64_t k = g * kRing + j;
-      const int64_t kl = k + kRing - 1 < count ? k + kRing - 1 : count - 1;
-      load_tile<M, U>(cols, base0 + kl * stride, xb[(j + kRing - 1) % kRing]);
+    for (int j = 0; j < R; ++j) {
+      const int64_t k = g * R + j;
+      const int64_t kl = k + R - 1 < count ? k + R - 1 : count - 1;
+      load_tile<M, U>(cols, base0 + kl * stride, xb[(j + R - 1) % R]);
       compute_tile<M, GRAD, U>(xb[j], C, acc);
     }
   }
-  // tiles groups * kRing + j, j < count % kRing, are in xb[j]
-  const int64_t rem = count - groups * kRing;
+  // tiles groups * R + j, j < count % R, are in xb[j]
+  const int64_t rem = count - groups * R;
 #pragma unroll
-  for (int j = 0; j < kRing - 1; ++j)
+  for (int j = 0; j < R - 1; ++j)
     if (j < rem) compute_tile<M, GRAD, U>(xb[j], C, acc);
 }
 
@@ -291,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   const int64_t nfull = a.n / tile;
   const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const int64_t base0 = (int64_t)blockIdx.x * tile + threadIdx.x;
-  double xb[kRing][U][M::NOBS];
+  double xb[ring_depth<M>()][U][M::NOBS];
   preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
 
   typename Pass<M, GRAD>::C C;
@@ -423,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     if (uniform(pt.bad) == 0 && cur.flag == 0) {
       const int64_t step = (int64_t)kBlock * U;
       const int64_t full = (end - start) / step;
-      double xb[kRing][U][M::NOBS];
+      double xb[ring_depth<M>()][U][M::NOBS];
       preload_ring<M, U>(cols, start + threadIdx.x, step, full, xb);
       stream_tiles<M, GRAD, U>(cols, start + threadIdx.x, step, full, xb, C, acc);
       const int64_t base = start + full * step;
@@ -549,24 +555,30 @@ struct Launch {
   static constexpr bool kU8 = M::NA_GRAD <= 8;
   static int pick_u(int unroll) { return unroll >= 8 && kU8 ? 8 : unroll >= 4 ? 4 : 2; }
 
+  // With timing events (ev0, ev1 both set) the launch carries them, so that
+  // they record the dispatch's own start and end (as a profiler's kernel
+  // trace does) rather than bracketing it with the queue's gaps.
   template <bool GRAD, bool FIT, int U>
-  static void launch_single(const Plan& pl, const SingleArgs& a, int grid, int lds_cap, hipStream_t st) {
+  static void launch_single(const Plan& pl, const SingleArgs& a, int grid, int lds_cap, hipStream_t st,
+                            hipEvent_t ev0, hipEvent_t ev1) {
     const void* k = reinterpret_cast<const void*>(&k_single<M, GRAD, U, FIT>);
-    hipLaunchKernelGGL((k_single<M, GRAD, U, FIT>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+    if (ev0 && ev1)
+      hipExtLaunchKernelGGL((k_single<M, GRAD, U, FIT>), dim3(grid), dim3(kBlock), (uint32_t)pad_lds(k, lds_cap), st,
+                            ev0, ev1, 0u, pl, a);
+    else
+      hipLaunchKernelGGL((k_single<M, GRAD, U, FIT>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
   }
   template <bool GRAD, bool FIT>
   static hipError_t single_t(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-    if (ev0 && hipEventRecord(ev0, st) != hipSuccess) return hipErrorUnknown;
     const int u = pick_u(unroll);
     if constexpr (kU8) {
-      if (u == 8) launch_single<GRAD, FIT, 8>(pl, a, grid, lds_cap, st);
+      if (u == 8) launch_single<GRAD, FIT, 8>(pl, a, grid, lds_cap, st, ev0, ev1);
     }
-    if (u == 4) launch_single<GRAD, FIT, 4>(pl, a, grid, lds_cap, st);
-    if (u == 2) launch_single<GRAD, FIT, 2>(pl, a, grid, lds_cap, st);
+    if (u == 4) launch_single<GRAD, FIT, 4>(pl, a, grid, lds_cap, st, ev0, ev1);
+    if (u == 2) launch_single<GRAD, FIT, 2>(pl, a, grid, lds_cap, st, ev0, ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (ev1 && hipEventRecord(ev1, st) != hipSuccess) return hipErrorUnknown;
     hipLaunchKernelGGL((k_single_finish<M, GRAD, FIT>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
     return hipGetLastError();
   }
@@ -585,27 +597,31 @@ struct Launch {
     return hipGetLastError();
   }
   template <bool GRAD, int U>
-  static void launch_sets(const Plan& pl, const SetsArgs& a, int grid, int lds_cap, hipStream_t st) {
+  static void launch_sets(const Plan& pl, const SetsArgs& a, int grid, int lds_cap, hipStream_t st, hipEvent_t ev0,
+                          hipEvent_t ev1) {
     const void* k = reinterpret_cast<const void*>(&k_sets<M, GRAD, U>);
-    hipLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+    if (ev0 && ev1)
+      hipExtLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), (uint32_t)pad_lds(k, lds_cap), st, ev0,
+                            ev1, 0u, pl, a);
+    else
+      hipLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
   }
   template <bool GRAD>
-  static void sets_u(const Plan& pl, const SetsArgs& a, int unroll, int grid, int lds_cap, hipStream_t st) {
+  static void sets_u(const Plan& pl, const SetsArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
+                     hipEvent_t ev0, hipEvent_t ev1) {
     const int u = pick_u(unroll);
     if constexpr (kU8) {
-      if (u == 8) launch_sets<GRAD, 8>(pl, a, grid, lds_cap, st);
+      if (u == 8) launch_sets<GRAD, 8>(pl, a, grid, lds_cap, st, ev0, ev1);
     }
-    if (u == 4) launch_sets<GRAD, 4>(pl, a, grid, lds_cap, st);
-    if (u == 2) launch_sets<GRAD, 2>(pl, a, grid, lds_cap, st);
+    if (u == 4) launch_sets<GRAD, 4>(pl, a, grid, lds_cap, st, ev0, ev1);
+    if (u == 2) launch_sets<GRAD, 2>(pl, a, grid, lds_cap, st, ev0, ev1);
   }
   static hipError_t sets(const Plan& pl, const SetsArgs& a, bool grad, bool fit, int unroll, int grid, int lds_cap,
                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-    if (ev0 && hipEventRecord(ev0, st) != hipSuccess) return hipErrorUnknown;
-    if (grad || fit) sets_u<true>(pl, a, unroll, grid, lds_cap, st);
-    else sets_u<false>(pl, a, unroll, grid, lds_cap, st);
+    if (grad || fit) sets_u<true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
+    else sets_u<false>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (ev1 && hipEventRecord(ev1, st) != hipSuccess) return hipErrorUnknown;
     const dim3 fg(a.n_sets > 0 ? a.n_sets : 1);
     if (fit) hipLaunchKernelGGL((k_sets_finish<M, true, true>), fg, dim3(kBlock), 0, st, pl, a);
     else if (grad) hipLaunchKernelGGL((k_sets_finish<M, true, false>), fg, dim3(kBlock), 0, st, pl, a);

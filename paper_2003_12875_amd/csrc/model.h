@@ -302,9 +302,10 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       const double inv = rcp_grad(s);  // responsibilities: gradient only
       double r[K];
       if constexpr (K == 2 && !M::HAS_TLIN) {
-        const double rs = es2 * inv;  // the smaller term's responsibility
-        r[0] = d2 >= 0.0 ? inv : rs;
-        r[1] = d2 >= 0.0 ? rs : inv;
+        // r_0 by one select; r_1 = 1 - r_0 (absolute error ~2^-48 where
+        // r_1 is tiny, far below the gradient's rounding scale)
+        r[0] = d2 >= 0.0 ? inv : es2 * inv;
+        r[1] = 1.0 - r[0];
       } else {
 #pragma unroll
         for (int k = 0; k < K; ++k) r[k] = e[k] * inv;

@@ -1,17 +1,21 @@
 // tune.cpp -- launch-schedule autotuner.
 //
-// Candidates: single dataset -- events per thread per tile (2, 4) x blocks
-// per CU (1..16); batched -- events per work item (4k..64k) x blocks per CU.
-// Each candidate is first checked against the default schedule's result
-// (relative NLL difference <= 1e-12 per dataset; only the reduction order
-// differs) and then timed with HIP events over several evaluations; the
-// fastest passing candidate is kept.  Choices are cached in a plain text
+// Candidates: single dataset -- events per thread per tile (2, 4, 8) x
+// blocks per CU (1..16); batched -- events per thread per tile x events per
+// work item (8k..64k) x blocks per CU.  Each candidate is first checked
+// against the default schedule's result (only the summation order differs:
+// relative NLL difference <= 1e-12 per dataset in FP64; in the
+// FP32-compensated mode, where the order also regroups the single-precision
+// per-thread sums, within that mode's accuracy, max(1e-9, 1e-6/sqrt(N)) for
+// one dataset and 1e-6 for sets) and then timed with HIP events over several
+// evaluations; the fastest passing candidate is kept.  Choices are cached in a plain text
 // file named by $NLLMI_TUNE_CACHE, one line per (shape, precision, mode,
 // log2 event count) key.
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <fstream>
 #include <sstream>
@@ -70,9 +74,9 @@ struct Timer {
   }
 };
 
-bool close_rel(double x, double y) {
+bool close_rel(double x, double y, double tol) {
   if (!std::isfinite(x) || !std::isfinite(y)) return x == y;
-  return std::fabs(x - y) <= 1e-12 * std::fmax(1.0, std::fabs(y));
+  return std::fabs(x - y) <= tol * std::fmax(1.0, std::fabs(y));
 }
 
 }  // namespace
@@ -96,6 +100,9 @@ nll_status tune_model(nll_model* m, int which, int n_sets, const int64_t* offset
     return nll_eval_batched(m, n_sets, offsets, theta, d_nll, d_grad, nullptr);
   };
   std::vector<double> ref(S), got(S);
+  double tol = 1e-12;
+  if (m->precision == NLL_FP32C)
+    tol = which == 1 ? std::fmax(1e-9, 1e-6 / std::sqrt((double)std::max<int64_t>(m->n, 1))) : 1e-6;
   const nll_schedule base = m->sched;
   nll_schedule best = base;
   float best_ms = 1e30f;
@@ -118,7 +125,7 @@ nll_status tune_model(nll_model* m, int which, int n_sets, const int64_t* offset
       if (run() != NLL_OK || hipStreamSynchronize(m->stream) != hipSuccess) continue;
       if (hipMemcpy(got.data(), d_nll, sizeof(double) * S, hipMemcpyDeviceToHost) != hipSuccess) continue;
       bool ok = true;
-      for (int s = 0; s < S && ok; ++s) ok = close_rel(got[s], ref[s]);
+      for (int s = 0; s < S && ok; ++s) ok = close_rel(got[s], ref[s], tol);
       if (!ok) continue;  // a schedule must reproduce the reference first
       const int reps = which == 1 ? 20 : 5;
       (void)hipEventRecord(tm.a, m->stream);

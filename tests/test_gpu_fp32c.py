@@ -184,3 +184,19 @@ def test_precision_study_full(torch, nllmi, threads):
     rows = compare(torch, nllmi, w["spec"], w["cols"], w["points"], threads, against_fp64=True, report=True)
     worst = {k: max(r[k] for r in rows) for k in rows[0]}
     print("worst: " + "  ".join(f"{k} {v:.3e}" for k, v in worst.items()), flush=True)
+
+
+def test_autotune_fp32c(torch, nllmi, monkeypatch):
+    """The autotuner accepts single-precision regroupings within the mode's
+    accuracy (it would otherwise keep only the current schedule) and the
+    tuned schedule still meets the oracle bound."""
+    monkeypatch.delenv("NLLMI_TUNE_CACHE", raising=False)
+    w = datagen.workload(5, n=300_000)
+    m = nllmi.Model.from_spec(w["spec"], precision="fp32c")
+    m.set_data(to_dev(torch, w["cols"]))
+    th = w["points"][1]
+    sched = m.autotune(torch.from_numpy(th).cuda())
+    assert sched["unroll"] in (2, 4, 8) and 1 <= sched["blocks_per_cu"] <= 32
+    st, ref, gref, stats = oracle.Oracle(w["spec"]).nll(w["cols"], th, threads=8, stats=True)
+    v, g = m.eval_grad(torch.from_numpy(th))
+    assert abs(float(v.item()) / ref - 1.0) <= nll_tol(len(w["cols"][0]))
