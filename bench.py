@@ -12,14 +12,18 @@ all in the library's HIP kernels, recorded once into a HIP graph.
 Also reported, on the same GPU:
   * fd_baseline -- forward-only FP64 NLL plus a central finite-difference
     gradient (2P+1 passes per step), the per-fit speed-up of the adjoint;
-  * roofline    -- algorithmic bytes per launch of the dominant kernel (the
-    fused streaming kernel) over its average duration, measured in the same
-    run with HIP start/stop events attached to that kernel's launch on the
-    library's stream (hipExtLaunchKernel) in every step of an eager K-step
-    fit, against the 8 TB/s HBM peak; `traffic` is the HBM byte count per launch from the
-    FETCH_SIZE and WRITE_SIZE counter summary under profiles/ (scaled by the
-    same counters on a plain streaming kernel of known size), reported only
-    while the kernel sources still hash to what was profiled;
+  * roofline    -- the dominant kernel (the fused streaming kernel), whose
+    average duration is measured in the same run with HIP start/stop events
+    attached to its launch on the library's stream (hipExtLaunchKernel) in
+    every step of an eager K-step fit.  It is bound by FP64 VALU issue
+    ("alu"): its VALU lane-instructions per launch (SQ_INSTS_VALU summary
+    under profiles/) over that duration, against 256 CUs x 4 SIMDs x 16
+    lanes x 2.4 GHz; `hbm` holds the metric's HBM figure (algorithmic bytes
+    per launch over the same duration, against 8 TB/s); `traffic` is the HBM
+    byte count per launch from the FETCH_SIZE and WRITE_SIZE summary under
+    profiles/ (scaled by the same counters on a plain streaming kernel of
+    known size).  Counter figures are reported only while the kernel
+    sources still hash to what was profiled;
   * cpu_baseline -- the scalar FP64 oracle (test infrastructure) on the
     host cores, same events, same minimiser;
   * extra       -- the other workloads: 1-D Gaussian (1e5 events) at 64
@@ -170,6 +174,10 @@ def headline(torch, nllmi, datagen, args):
     bytes_per_launch = 8.0 * n * len(spec["obs"])
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
     traffic = profiled_traffic()
+    # the kernel is bound by FP64 VALU issue: its measured VALU work per
+    # launch (committed counter summary) over the same launch time
+    valu = profiled_valu()
+    alu_achieved = valu[0] / (kern_ms * 1e-3) / 1e12 if valu else None
 
     # same-GPU baseline: forward-only FP64 NLL + central finite differences
     th = torch.as_tensor(theta0, dtype=torch.float64, device="cuda")
@@ -189,12 +197,20 @@ def headline(torch, nllmi, datagen, args):
                                "update per step (HIP-graph replay)",
                    "n_events": n, "n_params": model.n_param, "schedule": model.schedule,
                    "variant": model.info["variant"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                     "unit": "T FP64-VALU lane-instructions/s",
+                     "frac": alu_achieved / (VALU_PEAK_LANE_OPS / 1e12) if valu else None,
+                     "traffic": traffic,
                      "kernel": "k_single<gauss+exp, grad, fit>: fused per-point constants + NLL/gradient pass",
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kern_ms,
-                     "graph_step_ms": graph_step_ms, "csrc_sha256": csrc_hash(),
-                     "note": "80 MB of events also fit in the 256 MB last-level cache"},
+                     "valu_lane_instructions_per_event": valu[0] / n if valu else None,
+                     "fp64_tflops": valu[1] / (kern_ms * 1e-3) / 1e12 if valu else None,
+                     "fp64_tflops_peak": FP64_PEAK_FLOPS / 1e12,
+                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "avg_launch_ms": kern_ms, "graph_step_ms": graph_step_ms, "csrc_sha256": csrc_hash(),
+                     "note": "VALU peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz; the instruction count is "
+                             "measured (SQ_INSTS_VALU, profiles/); 80 MB of events also fit in the 256 MB "
+                             "last-level cache"},
         "fd_baseline": {"forward_ms": t_fwd, "passes_per_step": fd_passes, "fd_step_ms": fd_step_ms,
                         "eval_grad_ms": t_grad, "speedup_per_fit": fd_step_ms / ms_per_step,
                         "speedup_vs_eval_grad": fd_step_ms / t_grad},
@@ -374,45 +390,115 @@ def summarize_trace(d, workload):
               f"{max(v):.2f} | {100 * sum(v) / tot:.1f} |")
 
 
+def _per_kernel(d, counter, scale=1.0):
+    """{kernel name: [value per dispatch, in dispatch order]} of one counter."""
+    out = {}
+    rows = [r for r in _csv_rows(d, "_counter_collection.csv") if r["Counter_Name"] == counter]
+    for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * scale)
+    return out
+
+
+def _pick(tab, pred):
+    ks = [k for k in tab if pred(k)]
+    if len(ks) != 1:
+        raise SystemExit(f"expected one kernel, found {ks}")
+    return ks[0], tab[ks[0]]
+
+
+def _is_fit_kernel(k):
+    return "k_single<" in k and (", true, 4, true>" in k or ", true, 2, true>" in k or ", true, 8, true>" in k)
+
+
+def _streaming(values):
+    """Indices of the launches that streamed the events: a proposal outside
+    the parameter ranges is rejected before the stream (the step size
+    halved), and its launch reads only the first preloaded tiles."""
+    top = max(values)
+    return [i for i, v in enumerate(values) if v >= 0.5 * top]
+
+
 def summarize_pmc(fetch_dir, write_dir):
     """HBM traffic per launch of the streaming fit kernel from two counter
     runs (FETCH_SIZE, WRITE_SIZE: KiB per dispatch), scaled by what the same
-    counters read for the calibration kernel."""
-    def per_kernel(d, counter):
-        out = {}
-        for r in _csv_rows(d, "_counter_collection.csv"):
-            if r["Counter_Name"] != counter:
-                continue
-            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
-        return out
-    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
-
-    def pick(tab, pred):
-        ks = [k for k in tab if pred(k)]
-        if len(ks) != 1:
-            raise SystemExit(f"expected one kernel, found {ks}")
-        return ks[0], tab[ks[0]]
-    ck, cf = pick(fetch, lambda k: "neg" in k)
-    _, cw = pick(write, lambda k: "neg" in k)
-    kk, kf = pick(fetch, lambda k: "k_single<" in k and "true, 4, true" in k or
-                  ("k_single<" in k and "true, 2, true" in k))
-    _, kw = pick(write, lambda k: k == kk)
+    counters read for the calibration kernel; averaged over the launches
+    that streamed."""
+    fetch, write = _per_kernel(fetch_dir, "FETCH_SIZE", 1024.0), _per_kernel(write_dir, "WRITE_SIZE", 1024.0)
+    ck, cf = _pick(fetch, lambda k: "neg" in k)
+    _, cw = _pick(write, lambda k: "neg" in k)
+    kk, kf_all = _pick(fetch, _is_fit_kernel)
+    _, kw_all = _pick(write, lambda k: k == kk)
+    idx = _streaming(kf_all)
+    kf = [kf_all[i] for i in idx]
+    kw = [kw_all[i] for i in idx if i < len(kw_all)]
     f_fac = COPY_BYTES / (sum(cf) / len(cf))
     w_fac = COPY_BYTES / (sum(cw) / len(cw))
     fb = f_fac * sum(kf) / len(kf)
     wb = w_fac * sum(kw) / len(kw)
     print("# HBM traffic of the streaming fit kernel: gauss+exp mixture, 1e7 FP64 events\n")
     print("Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own run, scaled by")
-    print(f"the same counter on the calibration kernel (elementwise negation, {COPY_BYTES} bytes read and written).\n")
+    print(f"the same counter on the calibration kernel (elementwise negation, {COPY_BYTES} bytes read and written).")
+    print("Averaged over the launches that streamed the events (a rejected out-of-range proposal skips")
+    print("the stream and reads only the first preloaded tiles).\n")
     print(f"- kernel: `{_short(kk)}`")
     print(f"- csrc_sha256: `{csrc_hash()}`")
-    print(f"- dispatches: {len(kf)}")
+    print(f"- dispatches: {len(kf_all)} ({len(kf)} streamed)")
+    print("- fetch_bytes_per_dispatch: " + ", ".join(f"{f_fac * v:.4e}" for v in kf_all))
     print(f"- calibration_fetch_factor: {f_fac:.4f}")
     print(f"- calibration_write_factor: {w_fac:.4f}")
     print(f"- fetch_bytes_per_launch: {fb:.4e}")
     print(f"- write_bytes_per_launch: {wb:.4e}")
     print(f"- traffic_bytes_per_launch: {fb + wb:.4e}")
     print(f"- algorithmic_bytes_per_launch: {8.0e7:.4e}")
+
+
+VALU_FILE = os.path.join(ROOT, "profiles", "k_single_fit_gauss_exp_1e7_valu.txt")
+VALU_COUNTERS = ["SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                 "SQ_INSTS_VALU_TRANS_F64", "SQ_WAVES"]
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: FP64 VALU lane-instructions/s
+FP64_PEAK_FLOPS = 78.6e12
+
+
+def summarize_valu(d):
+    """VALU instructions per launch of the streaming fit kernel from one
+    counter run (wave-level instruction counts, summed over the chip),
+    averaged over the launches that streamed."""
+    tabs = {c: _per_kernel(d, c) for c in VALU_COUNTERS}
+    kk, valu_all = _pick(tabs["SQ_INSTS_VALU"], _is_fit_kernel)
+    idx = _streaming(valu_all)
+    avg = {c: sum(tabs[c][kk][i] for i in idx) / len(idx) for c in VALU_COUNTERS}
+    lane_ops = 64.0 * avg["SQ_INSTS_VALU"]
+    flops = 64.0 * (2.0 * avg["SQ_INSTS_VALU_FMA_F64"] + avg["SQ_INSTS_VALU_ADD_F64"] +
+                    avg["SQ_INSTS_VALU_MUL_F64"] + avg["SQ_INSTS_VALU_TRANS_F64"])
+    print("# VALU work of the streaming fit kernel: gauss+exp mixture, 1e7 FP64 events\n")
+    print("SQ instruction counters (wave instructions per dispatch, all CUs), one run, averaged over the")
+    print("launches that streamed the events. Lane-instructions = 64 x wave instructions (wave64);")
+    print("FP64 FLOPs = 64 x (2 FMA + ADD + MUL + TRANS).\n")
+    print(f"- kernel: `{_short(kk)}`")
+    print(f"- csrc_sha256: `{csrc_hash()}`")
+    print(f"- dispatches: {len(valu_all)} ({len(idx)} streamed)")
+    for c in VALU_COUNTERS:
+        print(f"- {c}: {avg[c]:.4e}")
+    print(f"- valu_lane_instructions_per_launch: {lane_ops:.4e}")
+    print(f"- valu_lane_instructions_per_event: {lane_ops / 1e7:.2f}")
+    print(f"- fp64_flops_per_launch: {flops:.4e}")
+
+
+def profiled_valu():
+    """(VALU lane-instructions, FP64 FLOPs) per launch from the committed
+    counter summary, or None if absent or taken on different sources."""
+    try:
+        kv = {}
+        with open(VALU_FILE) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        if kv.get("csrc_sha256") != csrc_hash():
+            return None
+        return float(kv["valu_lane_instructions_per_launch"]), float(kv["fp64_flops_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -427,12 +513,16 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--workload-name", default="")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-valu", metavar="DIR")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.workload_name)
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
