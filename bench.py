@@ -27,7 +27,8 @@ Also reported, on the same GPU:
   * cpu_baseline -- the scalar FP64 oracle (test infrastructure) on the
     host cores, same events, same minimiser;
   * extra       -- the other workloads: 1-D Gaussian (1e5 events) at 64
-    parameter points and fit steps, the precision study (1e8 events, FP64
+    parameter points (64 launches, and all 64 in one nll_eval_points pass)
+    and fit steps, the precision study (1e8 events, FP64
     and FP32-compensated passes), the 2-D Crystal Ball/ARGUS x Chebyshev
     model (5e7 events), and 4096 batched toy fits (4.1e8 events per step).
 
@@ -257,8 +258,12 @@ def extras(torch, nllmi, datagen, args):
     out = torch.empty(1, dtype=torch.float64, device="cuda")
     g = torch.empty(m.n_param, dtype=torch.float64, device="cuda")
     t64 = time_launches(torch, lambda: [m.eval(pts[i], out=out) for i in range(64)], 5)
+    tpts = time_launches(torch, lambda: m.eval_points(pts, grad=False), 20)
+    tptsg = time_launches(torch, lambda: m.eval_points(pts, grad=True), 20)
     r = timed_fit(torch, m, w["theta"], 50, 5)
-    ex["gauss_1e5"] = {"eval_64_points_ms": t64, "eval_us": 1e3 * t64 / 64, "fit_steps": 50,
+    ex["gauss_1e5"] = {"eval_64_points_ms": t64, "eval_us": 1e3 * t64 / 64,
+                       "eval_points_64_one_pass_ms": tpts, "eval_grad_points_64_one_pass_ms": tptsg,
+                       "fit_steps": 50,
                        "fit_ms_per_step": 1e3 * r["wall_s"] / 50, "fit_avg_step_us": 1e3 * r["gpu_ms"] / 50,
                        "fit_events_per_s": w["n"] * 50 / r["wall_s"]}
     del m

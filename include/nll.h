@@ -170,6 +170,17 @@ nll_status nll_eval_grad(nll_model* model, const double* theta, double* nll_out,
 nll_status nll_eval_batched(nll_model* model, int32_t n_sets, const int64_t* offsets, const double* theta,
                             double* nll_out, double* grad_out, int32_t* status_out);
 
+/* Enqueue: the attached dataset at many parameter points in one pass (the
+ * minimiser's repeated evaluations of the likelihood at different
+ * parameter values, Sec. 1; a likelihood scan).  Point p is
+ * theta[p * n_param ...] (device); nll_out[p] (device), grad_out (device
+ * [n_points * n_param], NULL for NLL only) and status_out[p] (device, NULL
+ * allowed) as in nll_eval_batched, each point normalised and checked on
+ * its own.  The events are read once per point (work items of
+ * tile_events events over all points share the persistent grid). */
+nll_status nll_eval_points(nll_model* model, int32_t n_points, const double* theta, double* nll_out,
+                           double* grad_out, int32_t* status_out);
+
 /* Enqueue: independent gradient-descent fits, one per set, all on the
  * device.  Each of the n_steps steps evaluates NLL and gradient at the
  * current proposal of every set in one launch; a proposal is accepted when

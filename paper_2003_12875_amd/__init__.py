@@ -188,6 +188,21 @@ class Model:
               "nll_eval_batched")
         return nll, g, status
 
+    def eval_points(self, theta, grad: bool = True):
+        """The attached dataset at each row of theta ([n_points, n_param]) in
+        one pass (see nll_eval_points).  Returns (nll, grad or None, status)."""
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        n_points = theta.numel() // self.n_param if self.n_param else 0
+        _buf(theta, torch.float64, self.device, n_points * self.n_param, "theta")
+        nll = torch.empty(n_points, dtype=torch.float64, device=self.device)
+        g = torch.empty(n_points, self.n_param, dtype=torch.float64, device=self.device) if grad else None
+        status = torch.empty(n_points, dtype=torch.int32, device=self.device)
+        self._bind_stream()
+        check(lib().nll_eval_points(self._h, n_points, _ptr(theta), _ptr(nll), _ptr(g), _ptr(status)),
+              "nll_eval_points")
+        return nll, g, status
+
     def fit_batched(self, offsets, theta, n_steps: int, eta: float = 1.0, out=None):
         """Gradient-descent fits of every set (see nll_fit_batched).  Returns
         (theta, nll, grad, status) at the last accepted points."""

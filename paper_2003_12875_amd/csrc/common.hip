@@ -1,5 +1,6 @@
 // common.hip -- model-independent kernels: dataset validation, the tile
-// schedule of the batched pass, and the read-out of a batched fit.
+// schedule of the batched pass (sets of events, or one dataset at many
+// parameter points), and the read-out of a batched fit.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -99,6 +100,38 @@ hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, 
   if (e != hipSuccess || n_sets <= 0) return e;
   hipLaunchKernelGGL(k_items, dim3((n_sets + kBlock - 1) / kBlock), dim3(kBlock), 0, st, offsets, n_sets, tile,
                      tile_off, set_flag, items);
+  return hipGetLastError();
+}
+
+// Points mode: every set is the whole dataset [0, n), evaluated at its own
+// parameter point.  Virtual offsets s * n give each set its event count n
+// (the finishing kernel's n_s); ceil(n / tile) items per set, or one empty
+// item if n == 0; no flags.  One thread per item (and per set for the
+// per-set arrays).
+__global__ __launch_bounds__(kBlock) void k_points(int n_sets, int64_t n, int64_t tile, int64_t per,
+                                                   int64_t* __restrict__ offsets, int64_t* __restrict__ tile_off,
+                                                   int* __restrict__ set_flag, WorkItem* __restrict__ items) {
+  const int64_t total = (int64_t)n_sets * per;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const int64_t s = i / per, k = i - s * per;
+    const int64_t start = k * tile;
+    items[i] = WorkItem{start < n ? start : n, start + tile < n ? start + tile : n, (int32_t)s, 0};
+  }
+  for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s <= n_sets; s += (int64_t)gridDim.x * kBlock) {
+    offsets[s] = s * n;
+    tile_off[s] = s * per;
+    if (s < n_sets) set_flag[s] = 0;
+  }
+}
+
+hipError_t launch_points(int n_sets, int64_t n, int64_t tile, int64_t* offsets, int64_t* tile_off, int* set_flag,
+                         WorkItem* items, hipStream_t st) {
+  const int64_t per = n > 0 ? (n + tile - 1) / tile : 1;
+  int64_t blocks = ((int64_t)n_sets * per + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_points, dim3((unsigned)blocks), dim3(kBlock), 0, st, n_sets, n, tile, per, offsets, tile_off,
+                     set_flag, items);
   return hipGetLastError();
 }
 

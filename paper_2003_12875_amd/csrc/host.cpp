@@ -349,7 +349,9 @@ int single_grid(const nll_model* m) {
   return (int)std::max<int64_t>(1, g);
 }
 
-nll_status ensure_sets(nll_model* m, int n_sets) {
+// per-set arrays for n_sets sets and room for `items` work items (default:
+// the most that consecutive event ranges can need)
+nll_status ensure_sets(nll_model* m, int n_sets, int64_t items = -1) {
   if (n_sets > m->sets_cap) {
     dfree(m->tile_off);
     dfree(m->set_flag);
@@ -366,7 +368,7 @@ nll_status ensure_sets(nll_model* m, int n_sets) {
   const int64_t tile = m->sched.tile_events;
   // work items: at most ceil(len_s / tile) (at least 1) per set, and the
   // sets are consecutive ranges of the events
-  const int64_t items = (m->n > 0 ? m->n / tile : 0) + n_sets + 1;
+  if (items < 0) items = (m->n > 0 ? m->n / tile : 0) + n_sets + 1;
   if ((size_t)items > m->items_cap) {
     dfree(m->items);
     m->items_cap = 0;
@@ -635,6 +637,7 @@ void nll_destroy_model(nll_model* m) {
   dfree(m->status);
   dfree(m->dbad);
   dfree(m->offsets1);
+  dfree(m->pts_offsets);
   dfree(m->tile_off);
   dfree(m->set_flag);
   dfree(m->items);
@@ -719,6 +722,37 @@ nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets
   return NLL_OK;
 }
 
+nll_status nll_eval_points(nll_model* m, int32_t n_points, const double* theta, double* nll_out, double* grad_out,
+                           int32_t* status_out) {
+  if (!m || n_points < 0 || (n_points > 0 && (!theta || !nll_out))) return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  if (n_points == 0) return NLL_OK;
+  DeviceGuard guard(m->device);
+  const int64_t tile = m->sched.tile_events;
+  const int64_t per = m->n > 0 ? (m->n + tile - 1) / tile : 1;
+  nll_status st = ensure_sets(m, n_points, (int64_t)n_points * per);
+  if (st != NLL_OK) return st;
+  if (n_points > m->pts_cap) {
+    dfree(m->pts_offsets);
+    m->pts_cap = 0;
+    if ((st = dalloc(&m->pts_offsets, (size_t)n_points + 1)) != NLL_OK) return st;
+    m->pts_cap = n_points;
+  }
+  SetsArgs a = sets_args(m, n_points, m->pts_offsets);
+  a.theta = theta;
+  a.nll_out = nll_out;
+  a.grad_out = grad_out;
+  a.status_out = reinterpret_cast<int*>(status_out);
+  if (launch_points(n_points, m->n, tile, m->pts_offsets, m->tile_off, m->set_flag, m->items, m->stream) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  if (m->ops->consts(m->plan, theta, n_points, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  if (m->ops->sets(m->plan, a, grad_out != nullptr, false, m->sched.sets_unroll, sets_grid(m),
+                   lds_cap(m, m->sched.sets_blocks_per_cu), m->stream, nullptr, nullptr) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  return NLL_OK;
+}
+
 nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets, double* theta, int32_t n_steps,
                            double eta, double* nll_out, double* grad_out, int32_t* status_out) {
   if (!m || n_sets < 0 || n_steps < 0 || !(eta > 0.0) || (n_sets > 0 && (!offsets || !theta || !nll_out)))
@@ -799,8 +833,8 @@ nll_status nll_get_schedule(const nll_model* m, nll_schedule* out) {
 
 nll_status nll_set_schedule(nll_model* m, const nll_schedule* s) {
   if (!m || !s) return NLL_ERR_ARG;
-  if (!(s->unroll == 2 || s->unroll == 4 || s->unroll == 8)) return NLL_ERR_ARG;
-  if (!(s->sets_unroll == 2 || s->sets_unroll == 4 || s->sets_unroll == 8)) return NLL_ERR_ARG;
+  auto valid_u = [](int u) { return u == 2 || u == 4 || u == 8; };
+  if (!valid_u(s->unroll) || !valid_u(s->sets_unroll)) return NLL_ERR_ARG;
   if (s->blocks_per_cu < 1 || s->blocks_per_cu > 32) return NLL_ERR_ARG;
   if (s->tile_events < 1024 || s->tile_events > (1 << 22) || (s->tile_events % 512) != 0) return NLL_ERR_ARG;
   if (s->sets_blocks_per_cu < 1 || s->sets_blocks_per_cu > 32) return NLL_ERR_ARG;

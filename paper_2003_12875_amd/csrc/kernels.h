@@ -92,6 +92,8 @@ void register_variants_fp32c_2d(std::vector<VariantOps>& out);
 
 hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
                            int64_t* tile_off, int* set_flag, WorkItem* items, hipStream_t st);
+hipError_t launch_points(int n_sets, int64_t n, int64_t tile, int64_t* offsets, int64_t* tile_off, int* set_flag,
+                         WorkItem* items, hipStream_t st);
 hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_out, double* nll_out,
                             double* grad_out, int* status_out, hipStream_t st);
 hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, unsigned long long* bad,

@@ -552,6 +552,9 @@ template <class M>
 struct Launch {
   // events per thread per tile: 2, 4, or 8 (8 only for shapes with few
   // accumulators, where the extra registers do not cost occupancy)
+  // events per thread per tile compiled for this shape: {2, 4, 8}, or
+  // {2, 4} for shapes with more than 8 accumulators (registers); 8 maps to
+  // 4 there
   static constexpr bool kU8 = M::NA_GRAD <= 8;
   static int pick_u(int unroll) { return unroll >= 8 && kU8 ? 8 : unroll >= 4 ? 4 : 2; }
 

@@ -74,6 +74,8 @@ struct nll_model {
   int* status = nullptr;
   unsigned long long* dbad = nullptr;
   int64_t* offsets1 = nullptr;
+  int64_t* pts_offsets = nullptr;  // nll_eval_points: virtual offsets s * n
+  int pts_cap = 0;
 
   // many datasets
   int sets_cap = 0;

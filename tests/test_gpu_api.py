@@ -157,9 +157,47 @@ def test_graph_and_eager_fits_are_identical(torch, nllmi):
 
 def test_schedule_validation(torch, nllmi):
     m = nllmi.Model.from_spec(datagen.gauss_spec())
-    for bad in ({"unroll": 3}, {"sets_unroll": 16}, {"blocks_per_cu": 0}, {"blocks_per_cu": 33},
+    for bad in ({"unroll": 3}, {"unroll": 1}, {"sets_unroll": 16}, {"blocks_per_cu": 0}, {"blocks_per_cu": 33},
                 {"tile_events": 1000}, {"tile_events": (1 << 22) + 512}, {"sets_blocks_per_cu": 0}):
         with pytest.raises(nllmi.NLLError):
             m.set_schedule(**bad)
     m.set_schedule(unroll=8, sets_unroll=8, blocks_per_cu=32, sets_blocks_per_cu=32, tile_events=1 << 22)
     assert m.schedule["unroll"] == 8 and m.schedule["tile_events"] == 1 << 22
+
+
+def test_eval_points(torch, nllmi, threads):
+    """nll_eval_points: one dataset at many parameter points in one pass
+    equals eval_grad point by point (the same per-event arithmetic, summed
+    in a different grouping) and the oracle; a point outside the parameter
+    ranges reports its own status and +inf, the others are unaffected."""
+    w = datagen.workload(1)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    pts = np.array(w["points"], dtype=np.float64)
+    pts[5, 1] = -1.0  # sigma < 0
+    nll, g, st = m.eval_points(torch.from_numpy(pts).cuda())
+    nll, g, st = nll.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+    assert st[5] != 0 and np.isinf(nll[5])
+    o = oracle.Oracle(w["spec"])
+    for i in range(len(pts)):
+        if i == 5:
+            continue
+        assert st[i] == 0
+        v, gi = m.eval_grad(torch.from_numpy(pts[i]))
+        v, gi = float(v.item()), gi.cpu().numpy()
+        assert abs(nll[i] - v) <= 1e-12 * abs(v), (i, nll[i], v)
+        assert np.max(np.abs(g[i] - gi)) <= 1e-10 * max(np.max(np.abs(gi)), 1.0), (i, g[i], gi)
+        if i % 16 == 0:
+            r, ref, gref = o.nll(w["cols"], pts[i], threads=threads)
+            assert r == 0 and abs(nll[i] / ref - 1.0) <= 1e-12, (i, nll[i], ref)
+    # NLL only, the 2-D model, a ragged event count
+    w3 = datagen.workload(3, n=33_333)
+    m3 = nllmi.Model.from_spec(w3["spec"])
+    m3.set_data(to_dev(torch, w3["cols"]))
+    pts3 = np.array(w3["points"][:5], dtype=np.float64)
+    nll3, g3, st3 = m3.eval_points(torch.from_numpy(pts3).cuda(), grad=False)
+    assert g3 is None and (st3.cpu().numpy() == 0).all()
+    o3 = oracle.Oracle(w3["spec"])
+    for i in range(5):
+        r, ref, _ = o3.nll(w3["cols"], pts3[i], threads=threads)
+        assert r == 0 and abs(nll3.cpu().numpy()[i] / ref - 1.0) <= 1e-12, (i,)

@@ -251,6 +251,31 @@ def test_determinism_and_schedules(torch, nllmi):
             assert abs(v.item() - ref) <= 1e-13 * abs(ref), (unroll, bpc)
 
 
+def test_heavy_shape_every_unroll(torch, nllmi, threads):
+    """The 2-D shape (12 accumulators) at each compiled events-per-thread
+    value (2, 4; a request of 8 maps to 4), single dataset and batched,
+    against the oracle: tails of every length below a tile."""
+    w = datagen.workload(3, n=70_001)
+    o = oracle.Oracle(w["spec"])
+    th = w["points"][1]
+    st, ref, gref, stats = o.nll(w["cols"], th, threads=threads, stats=True)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    offs = np.array([0, 1, 1000, 1513, 70_001], dtype=np.int64)
+    subs = [o.nll([c[offs[s]:offs[s + 1]] for c in w["cols"]], th) for s in range(4)]
+    for unroll in (2, 4, 8):
+        m.set_schedule(unroll=unroll, sets_unroll=unroll, blocks_per_cu=3, sets_blocks_per_cu=3,
+                       tile_events=2048)
+        v, g = m.eval_grad(torch.from_numpy(th))
+        ok, err = grad_close(g.cpu().numpy(), gref, stats[1:])
+        assert ok and abs(v.item() - ref) <= NLL_TOL * abs(ref), (unroll, v.item(), ref, err)
+        nll, gb, stb = m.eval_batched(torch.from_numpy(offs).cuda(), torch.from_numpy(np.tile(th, (4, 1))).cuda())
+        nll = nll.cpu().numpy()
+        for s in range(4):
+            assert subs[s][0] == 0 and abs(nll[s] - subs[s][1]) <= NLL_TOL * max(abs(subs[s][1]), 1.0), (unroll, s)
+    assert m.sync() == 0
+
+
 def test_autograd_function(torch, nllmi):
     w = datagen.workload(2, n=20000)
     m = nllmi.Model.from_spec(w["spec"])
