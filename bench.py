@@ -28,7 +28,8 @@ Also reported, on the same GPU:
     host cores, same events, same minimiser;
   * extra       -- the other workloads: 1-D Gaussian (1e5 events) at 64
     parameter points (64 launches, and all 64 in one nll_eval_points pass)
-    and fit steps, the precision study (1e8 events, FP64
+    and fit steps, the extended (Poisson yield) mixture on the 1e7 events,
+    the precision study (1e8 events, FP64
     and FP32-compensated passes), the 2-D Crystal Ball/ARGUS x Chebyshev
     model (5e7 events), and 4096 batched toy fits (4.1e8 events per step).
 
@@ -299,6 +300,26 @@ def extras(torch, nllmi, datagen, args):
     res5["fp32c_vs_fp64_gpu"] = {"points": 32, "max_nll_rel_err": max(nerr), "max_grad_rel_err_vs_max_abs": max(gerr)}
     ex["precision_study_1e8"] = res5
     del cols
+    torch.cuda.empty_cache()
+    # extended model (the c2 mixture with a Poisson yield term nu - N ln nu,
+    # 5 parameters) on the c2 events: NLL+gradient and a 200-step fit
+    w = datagen.workload(2)
+    spec = dict(w["spec"])
+    spec["params"] = list(spec["params"]) + [datagen.param("nu", 0.9 * w["n"], 1.0, 1e12)]
+    spec["extended"] = True
+    spec["yield_param"] = len(spec["params"]) - 1
+    m = nllmi.Model.from_spec(spec)
+    m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    thx = list(w["points"][0]) + [0.9 * w["n"]]
+    th = torch.as_tensor(thx, dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(m.n_param, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: m.eval_grad(th, out=out, grad=g), 20)
+    r = timed_fit(torch, m, thx, 200, 10)
+    ex["extended_c2_1e7"] = {"eval_grad_ms": tg, "events_per_s": w["n"] / (tg * 1e-3),
+                             "fit_ms_per_step": 1e3 * r["wall_s"] / 200, "fit_events_per_s": w["n"] * 200 / r["wall_s"],
+                             "fit_status": r["status"], "n_events": w["n"]}
+    del m
     torch.cuda.empty_cache()
     # 2-D CB/ARGUS x Chebyshev, 5e7 events, 9 free parameters
     log("c3: generating 5e7 events")

@@ -78,6 +78,8 @@ def lib():
         L.orc_nll.argtypes = [pm, ppd, i64, pd, i32, pd, pd, pd]
         L.orc_nll_batched.argtypes = [pm, ppd, P(i64), i32, pd, i32, pd, pd, P(i32)]
         L.orc_gd_fit.argtypes = [pm, ppd, i64, pd, i32, d, i32, pd, pd, pd, pd]
+        L.orc_nll_bhhh.argtypes = [pm, ppd, i64, pd, i32, pd, pd, pd]
+        L.orc_bhhh_fit.argtypes = [pm, ppd, i64, pd, i32, d, i32, pd, pd, pd, pd]
         L.orc_gd_fit_batched.argtypes = [pm, ppd, P(i64), i32, pd, i32, d, i32, pd, pd, P(i32)]
         L.orc_gl_rule.argtypes = [i32, pd, pd]
         for f in ("orc_check_model", "orc_leaf_norm", "orc_log_density", "orc_nll",
@@ -193,6 +195,32 @@ class Oracle:
                               ctypes.byref(out), _dptr(g), ctypes.byref(eta_out),
                               _dptr(tr) if trace else None)
         res = (st, th, out.value, g, eta_out.value)
+        return res + ((tr[:n_steps],) if trace else ())
+
+    def nll_bhhh(self, cols, theta, threads: int = 1):
+        """(status, NLL, gradient, BHHH matrix sum_i s_i s_i^T)."""
+        keep, arr = _cols(cols)
+        n = len(keep[0])
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        out = ctypes.c_double()
+        g = np.zeros(self.n_param)
+        B = np.zeros((self.n_param, self.n_param))
+        st = lib().orc_nll_bhhh(ctypes.byref(self.m), arr, n, _dptr(th), threads, ctypes.byref(out), _dptr(g),
+                                _dptr(B))
+        return st, out.value, g, B
+
+    def bhhh_fit(self, cols, theta, n_steps: int, lam: float = 1e-3, threads: int = 1, trace: bool = False):
+        """Damped BHHH fit: (status, theta, NLL, gradient, final damping[, trace])."""
+        keep, arr = _cols(cols)
+        n = len(keep[0])
+        th = np.array(theta, dtype=np.float64)
+        out = ctypes.c_double()
+        lam_out = ctypes.c_double()
+        g = np.zeros(self.n_param)
+        tr = np.zeros((max(n_steps, 1), self.n_param + 1))
+        st = lib().orc_bhhh_fit(ctypes.byref(self.m), arr, n, _dptr(th), n_steps, lam, threads,
+                                ctypes.byref(out), _dptr(g), ctypes.byref(lam_out), _dptr(tr) if trace else None)
+        res = (st, th, out.value, g, lam_out.value)
         return res + ((tr[:n_steps],) if trace else ())
 
     def gd_fit_batched(self, cols, offsets, theta, n_steps: int, eta: float = 1.0, threads: int = 1):

@@ -611,11 +611,13 @@ struct Partial {
   Neumaier grad[ORC_MAX_PAR];
   Neumaier abs_l;
   Neumaier abs_g[ORC_MAX_PAR];
+  std::vector<Neumaier> outer;  // n_param^2 when the BHHH matrix is wanted
   int status = ORC_OK;
 };
 
 void nll_range(const Prepared& pr, const double* const* cols, int64_t b, int64_t e, bool want_grad,
                Partial& out) {
+  const bool want_outer = !out.outer.empty();
   const orc_model& m = *pr.m;
   const int np = m.n_param;
   double x[ORC_MAX_OBS];
@@ -637,23 +639,34 @@ void nll_range(const Prepared& pr, const double* const* cols, int64_t b, int64_t
     out.nll.add(-l);
     out.abs_l.add(std::fabs(l));
     if (want_grad) {
+      double dl[ORC_MAX_PAR];
       for (int k = 0; k < np; ++k) {
-        double dl = dv[k] / p; /* d log p = dp / p */
-        out.grad[k].add(-dl);
-        out.abs_g[k].add(std::fabs(dl));
+        dl[k] = dv[k] / p; /* d log p = dp / p */
+        out.grad[k].add(-dl[k]);
+        out.abs_g[k].add(std::fabs(dl[k]));
       }
+      /* BHHH: the outer product of the event's score with itself */
+      if (want_outer)
+        for (int j = 0; j < np; ++j)
+          for (int k = j; k < np; ++k) out.outer[(size_t)j * np + k].add(dl[j] * dl[k]);
     }
   }
 }
 
-/* One dataset, one parameter point. */
+/* One dataset, one parameter point.  bhhh (may be NULL): the n_param x
+ * n_param matrix sum_i s_i s_i^T of the events' scores s_i = d log p(x_i)
+ * / d theta (symmetric, row-major), plus the Poisson term's own second
+ * derivative N / nu^2 at (nu, nu) in an extended model; rows and columns of
+ * fixed parameters are 0. */
 int nll_one(const orc_model& m, const double* const* cols, int64_t n, const double* th,
-            int threads, double* nll, double* grad, double* stats) {
+            int threads, double* nll, double* grad, double* stats, double* bhhh = nullptr) {
   const int np = m.n_param;
   auto fail = [&](int st) {
     *nll = kInf;
     if (grad)
       for (int k = 0; k < np; ++k) grad[k] = 0.0;
+    if (bhhh)
+      for (int k = 0; k < np * np; ++k) bhhh[k] = 0.0;
     return st;
   };
   Prepared pr;
@@ -662,7 +675,9 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
   int T = std::max(1, threads);
   if (n < 4096) T = 1;
   std::vector<Partial> parts(T);
-  const bool want_grad = (grad != nullptr) || (stats != nullptr);
+  if (bhhh)
+    for (auto& pt : parts) pt.outer.resize((size_t)np * np);
+  const bool want_grad = (grad != nullptr) || (stats != nullptr) || (bhhh != nullptr);
   if (T == 1) {
     nll_range(pr, cols, 0, n, want_grad, parts[0]);
   } else {
@@ -698,6 +713,24 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
   *nll = v;
   if (grad)
     for (int k = 0; k < np; ++k) grad[k] = m.par_free[k] ? g[k].value() : 0.0;
+  if (bhhh) {
+    for (int j = 0; j < np; ++j)
+      for (int k = j; k < np; ++k) {
+        Neumaier o;
+        for (int t = 0; t < T; ++t) {
+          o.add(parts[t].outer[(size_t)j * np + k].s);
+          o.add(parts[t].outer[(size_t)j * np + k].c);
+        }
+        double b = o.value();
+        if (m.extended && j == m.yield_param && k == m.yield_param) {
+          double nu = th[m.yield_param];
+          b += (double)n / (nu * nu);
+        }
+        if (!m.par_free[j] || !m.par_free[k]) b = 0.0;
+        bhhh[(size_t)j * np + k] = b;
+        bhhh[(size_t)k * np + j] = b;
+      }
+  }
   if (stats) {
     stats[0] = al.value();
     for (int k = 0; k < np; ++k) stats[1 + k] = ag[k].value();
@@ -742,6 +775,101 @@ int gd_fit_one(const orc_model& m, const double* const* cols, int64_t n, double*
   if (grad_out)
     for (int k = 0; k < np; ++k) grad_out[k] = g_acc[k];
   if (eta_out) *eta_out = eta;
+  return std::isfinite(f_acc) ? ORC_OK : (last != ORC_OK ? last : ORC_E_PDF);
+}
+
+/* Solve (B + lambda D) d = -g over the free parameters by Cholesky, D the
+ * diagonal of B floored at 1e-12 of its largest entry; d = 0 for fixed
+ * parameters.  Returns false if the damped matrix is not positive definite
+ * (a pivot <= 0 or not finite). */
+bool damped_solve(const orc_model& m, const double* B, const double* g, double lambda, double* d) {
+  const int np = m.n_param;
+  int idx[ORC_MAX_PAR];
+  int nf = 0;
+  double dmax = 0.0;
+  for (int k = 0; k < np; ++k)
+    if (m.par_free[k]) {
+      idx[nf++] = k;
+      dmax = std::max(dmax, B[(size_t)k * np + k]);
+    }
+  for (int k = 0; k < np; ++k) d[k] = 0.0;
+  if (nf == 0) return true;
+  std::vector<double> A((size_t)nf * nf), L((size_t)nf * nf, 0.0), y(nf);
+  for (int a = 0; a < nf; ++a)
+    for (int b = 0; b < nf; ++b) {
+      double v = B[(size_t)idx[a] * np + idx[b]];
+      if (a == b) v += lambda * std::max(v, 1e-12 * dmax);
+      A[(size_t)a * nf + b] = v;
+    }
+  for (int a = 0; a < nf; ++a) {
+    for (int b = 0; b <= a; ++b) {
+      double s = A[(size_t)a * nf + b];
+      for (int c = 0; c < b; ++c) s -= L[(size_t)a * nf + c] * L[(size_t)b * nf + c];
+      if (a == b) {
+        if (!(s > 0.0) || !std::isfinite(s)) return false;
+        L[(size_t)a * nf + a] = std::sqrt(s);
+      } else {
+        L[(size_t)a * nf + b] = s / L[(size_t)b * nf + b];
+      }
+    }
+  }
+  for (int a = 0; a < nf; ++a) { /* L y = -g */
+    double s = -g[idx[a]];
+    for (int c = 0; c < a; ++c) s -= L[(size_t)a * nf + c] * y[c];
+    y[a] = s / L[(size_t)a * nf + a];
+  }
+  for (int a = nf - 1; a >= 0; --a) { /* L^T d = y */
+    double s = y[a];
+    for (int c = a + 1; c < nf; ++c) s -= L[(size_t)c * nf + a] * d[idx[c]];
+    d[idx[a]] = s / L[(size_t)a * nf + a];
+  }
+  return true;
+}
+
+/* Damped BHHH (Levenberg-Marquardt on the outer-product matrix), see
+ * oracle.h. */
+int bhhh_fit_one(const orc_model& m, const double* const* cols, int64_t n, double* theta,
+                 int n_steps, double lambda, int threads, double* nll_out, double* grad_out,
+                 double* lambda_out, double* trace) {
+  const int np = m.n_param;
+  std::vector<double> acc(theta, theta + np), prop(theta, theta + np), g_acc(np, 0.0), g(np, 0.0),
+      B_acc((size_t)np * np, 0.0), B((size_t)np * np, 0.0), d(np, 0.0);
+  double f_acc = kInf;
+  int last = ORC_OK;
+  for (int s = 0; s < n_steps; ++s) {
+    double f;
+    int st = nll_one(m, cols, n, prop.data(), threads, &f, g.data(), nullptr, B.data());
+    if (trace) {
+      trace[s * (np + 1)] = f;
+      for (int k = 0; k < np; ++k) trace[s * (np + 1) + 1 + k] = prop[k];
+    }
+    if (st == ORC_E_DOMAIN) return st;
+    bool ok = (st == ORC_OK) && std::isfinite(f) && f <= f_acc + 4.0 * DBL_EPSILON * std::fabs(f_acc);
+    if (ok) {
+      acc = prop;
+      f_acc = f;
+      g_acc = g;
+      B_acc = B;
+      lambda = std::max(lambda * 0.1, 1e-12);
+      last = ORC_OK;
+    } else {
+      lambda *= 10.0;
+      if (!std::isfinite(f_acc)) last = st;
+    }
+    /* the next proposal; a damped matrix that is not positive definite is
+       retried with ten times the damping, at most 8 times */
+    bool solved = false;
+    for (int tries = 0; tries < 8 && !solved; ++tries) {
+      solved = damped_solve(m, B_acc.data(), g_acc.data(), lambda, d.data());
+      if (!solved) lambda *= 10.0;
+    }
+    for (int k = 0; k < np; ++k) prop[k] = solved && m.par_free[k] ? acc[k] + d[k] : acc[k];
+  }
+  for (int k = 0; k < np; ++k) theta[k] = acc[k];
+  *nll_out = f_acc;
+  if (grad_out)
+    for (int k = 0; k < np; ++k) grad_out[k] = g_acc[k];
+  if (lambda_out) *lambda_out = lambda;
   return std::isfinite(f_acc) ? ORC_OK : (last != ORC_OK ? last : ORC_E_PDF);
 }
 
@@ -843,6 +971,23 @@ int orc_nll_batched(const orc_model* m, const double* const* cols, const int64_t
     if (status) status[s] = r;
   });
   return ORC_OK;
+}
+
+int orc_nll_bhhh(const orc_model* m, const double* const* cols, int64_t n, const double* theta,
+                 int32_t threads, double* nll, double* grad, double* bhhh) {
+  if (!data_args_ok(m, cols) || !theta || !nll || !bhhh || n < 0) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  return nll_one(*m, cols, n, theta, threads, nll, grad, nullptr, bhhh);
+}
+
+int orc_bhhh_fit(const orc_model* m, const double* const* cols, int64_t n, double* theta,
+                 int32_t n_steps, double lambda, int32_t threads, double* nll, double* grad,
+                 double* lambda_out, double* trace) {
+  if (!data_args_ok(m, cols) || !theta || !nll || n < 0 || n_steps < 0 || !(lambda > 0.0)) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  return bhhh_fit_one(*m, cols, n, theta, n_steps, lambda, threads, nll, grad, lambda_out, trace);
 }
 
 int orc_gd_fit(const orc_model* m, const double* const* cols, int64_t n, double* theta,

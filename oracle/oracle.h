@@ -131,6 +131,29 @@ int orc_gd_fit(const orc_model* m, const double* const* cols, int64_t n,
                double* theta, int32_t n_steps, double eta, int32_t threads,
                double* nll, double* grad, double* eta_out, double* trace);
 
+/* NLL, gradient and the BHHH matrix B = sum_i s_i s_i^T of the events'
+ * scores s_i = d log p(x_i) / d theta (n_param x n_param, row-major,
+ * symmetric), plus the Poisson term's second derivative N / nu^2 at
+ * (nu, nu) in an extended model; rows and columns of fixed parameters 0.
+ * (Berndt, Hall, Hall and Hausman, 1974: the outer product of the scores
+ * approximates the Hessian of the NLL near the optimum.)                 */
+int orc_nll_bhhh(const orc_model* m, const double* const* cols, int64_t n,
+                 const double* theta, int32_t threads, double* nll, double* grad,
+                 double* bhhh);
+
+/* Damped BHHH minimiser (Levenberg-Marquardt on B): the proposal is
+ * theta_acc + d with (B_acc + lambda D) d = -g_acc over the free
+ * parameters, D = diag(B_acc) floored at 1e-12 of its largest entry,
+ * solved by Cholesky.  Acceptance as in orc_gd_fit (finite, at most 4 ulps
+ * above the last accepted NLL); on acceptance lambda = max(lambda / 10,
+ * 1e-12), otherwise lambda *= 10.  A damped matrix that is not positive
+ * definite is retried with ten times the damping, at most 8 times, else
+ * the proposal is theta_acc.  Exactly n_steps evaluations, the first at
+ * the start point; outputs as orc_gd_fit (lambda_out: final damping).    */
+int orc_bhhh_fit(const orc_model* m, const double* const* cols, int64_t n,
+                 double* theta, int32_t n_steps, double lambda, int32_t threads,
+                 double* nll, double* grad, double* lambda_out, double* trace);
+
 /* The same minimiser run independently on every set (threads over sets). */
 int orc_gd_fit_batched(const orc_model* m, const double* const* cols,
                        const int64_t* offsets, int32_t n_sets, double* theta,

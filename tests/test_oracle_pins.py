@@ -512,3 +512,106 @@ def test_single_panel_quadrature_on_smooth_leaves(kind, params, lo, hi):
     zs = oracle.Oracle(single_leaf_spec(kind, params, lo, hi, "gl256_single")).leaf_norm(0, params)
     assert abs(za[1] - zs[1]) <= 1e-13 * za[1]
     np.testing.assert_allclose(zs[2], za[2], rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# BHHH (outer product of the events' scores) and the damped BHHH minimiser
+# ---------------------------------------------------------------------------
+
+def _fd_scores(o, cols, th, h_rel=1e-6):
+    """Per-event scores d log p(x_i) / d theta by central differences of the
+    per-event log-density value alone (its analytic derivative unused)."""
+    n, P = len(cols[0]), len(th)
+    S = np.zeros((n, P))
+    for k in range(P):
+        h = h_rel * max(1.0, abs(th[k]))
+        tp, tm = np.array(th, dtype=float), np.array(th, dtype=float)
+        tp[k] += h
+        tm[k] -= h
+        for i in range(n):
+            x = [c[i] for c in cols]
+            S[i, k] = (o.log_density(x, tp)[1] - o.log_density(x, tm)[1]) / (2 * h)
+    return S
+
+
+@pytest.mark.parametrize("config", [1, 2, 3])
+def test_bhhh_matrix_is_outer_product_of_fd_scores(config):
+    """B = sum_i s_i s_i^T with s_i from finite differences of log p(x_i);
+    symmetric, positive semi-definite."""
+    w = datagen.workload(config, n=300)
+    o = oracle.Oracle(w["spec"])
+    th = w["points"][1]
+    st, nll, g, B = o.nll_bhhh(w["cols"], th)
+    assert st == OK
+    S = _fd_scores(o, w["cols"], th)
+    free = np.array([p.get("free", True) for p in w["spec"]["params"]], dtype=float)
+    ref = (S.T @ S) * np.outer(free, free)  # fixed parameters: zero rows and columns
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(B - ref)) <= 1e-6 * scale, (B, ref)
+    assert np.array_equal(B, B.T)
+    assert np.min(np.linalg.eigvalsh(B)) >= -1e-12 * scale
+    # the gradient is minus the sum of the same scores
+    assert np.max(np.abs(g + free * S.sum(axis=0))) <= 1e-6 * max(1.0, np.max(np.abs(S).sum(axis=0)))
+
+
+def test_bhhh_matrix_approaches_fisher_information():
+    """For a Gaussian on a range of +-6.7 sigma, B / N at the truth tends to
+    the Fisher information diag(1/sigma^2, 2/sigma^2) with 1/sqrt(N)
+    fluctuations."""
+    w = datagen.workload(1)
+    o = oracle.Oracle(w["spec"])
+    st, nll, g, B = o.nll_bhhh(w["cols"], w["theta"])
+    n, s = len(w["cols"][0]), w["theta"][1]
+    I = np.array([[1 / s**2, 0.0], [0.0, 2 / s**2]])
+    assert np.max(np.abs(B / n - I)) <= 6 * np.sqrt(2.0 / n) * np.max(I)
+
+
+def test_bhhh_extended_and_fixed_parameters():
+    """The Poisson term adds N / nu^2 at (nu, nu); a fixed parameter's row
+    and column are 0."""
+    spec = datagen.mixture_spec()
+    spec["params"].append(datagen.param("nu", 1000.0, 1.0, 1e7))
+    spec["extended"] = True
+    spec["yield_param"] = 4
+    cols = datagen.generate(datagen.mixture_spec(), 400, seed=8)
+    th = np.array([0.2, 5.0, 0.4, -0.7, 800.0])
+    st, nll, g, B = oracle.Oracle(spec).nll_bhhh(cols, th)
+    st4, nll4, g4, B4 = oracle.Oracle(datagen.mixture_spec()).nll_bhhh(cols, th[:4])
+    assert np.array_equal(B[:4, :4], B4) and np.all(B[4, :4] == 0.0)
+    assert B[4, 4] == 400 / 800.0**2
+    spec2 = datagen.mixture_spec()
+    spec2["params"][3]["free"] = False
+    st, nll, g, B2 = oracle.Oracle(spec2).nll_bhhh(cols, th[:4])
+    assert np.all(B2[3] == 0.0) and np.all(B2[:, 3] == 0.0)
+    assert np.array_equal(B2[:3, :3], B4[:3, :3])
+
+
+def test_bhhh_fit_reaches_closed_form_mle_in_few_steps():
+    """Damped BHHH on the wide-range Gaussian lands on the MLE mu =
+    mean(x), sigma^2 = mean((x - mean)^2) in far fewer steps than gradient
+    descent (which needs ~50 here), with a monotone NLL."""
+    w = datagen.workload(1)
+    x = w["cols"][0].astype(np.longdouble)
+    mu_hat = float(x.mean())
+    s_hat = float(np.sqrt(((x - x.mean()) ** 2).mean()))
+    st, th, nll, g, lam, tr = oracle.Oracle(w["spec"]).bhhh_fit(w["cols"], w["points"][0], 12, 1e-3, trace=True)
+    assert st == OK
+    assert abs(th[0] - mu_hat) <= 1e-8 * abs(mu_hat)
+    assert abs(th[1] - s_hat) <= 1e-8 * s_hat
+    acc = np.minimum.accumulate(tr[:, 0])
+    assert np.all(np.diff(acc) <= 0.0)
+    assert np.max(np.abs(g)) / len(x) < 1e-9
+
+
+def test_bhhh_fit_mixture_converges_to_stationary_point():
+    """On the signal+background mixture BHHH reaches a point whose gradient
+    vanishes (relative to the per-event score scale), and the NLL there is
+    no higher than gradient descent's after many more steps."""
+    w = datagen.workload(2, n=20_000)
+    o = oracle.Oracle(w["spec"])
+    st, th, nll, g, lam = o.bhhh_fit(w["cols"], w["points"][0], 25, 1e-3, threads=4)
+    assert st == OK
+    st2, th2, nll2, g2, eta2 = o.gd_fit(w["cols"], w["points"][0], 400, 1.0, threads=4)
+    _, _, _, stats = o.nll(w["cols"], th, stats=True)
+    assert np.max(np.abs(g) / stats[1:]) < 1e-8
+    assert nll <= nll2 + 1e-9 * abs(nll2)
