@@ -198,6 +198,31 @@ nll_status nll_fit_batched(nll_model* model, int32_t n_sets, const int64_t* offs
 nll_status nll_fit(nll_model* model, double* theta, int32_t n_steps, double eta, double* nll_out,
                    double* grad_out, int32_t* status_out);
 
+/* Enqueue: NLL, gradient and the BHHH matrix B = sum_i s_i s_i^T of the
+ * events' scores s_i = d log p(x_i) / d theta (device [n_param * n_param],
+ * row-major, symmetric; plus N / nu^2 at (nu, nu) in an extended model;
+ * rows and columns of fixed parameters 0) from one pass.  B approximates
+ * the NLL's Hessian near the optimum (Berndt, Hall, Hall and Hausman 1974):
+ * the outer-product information for the second-order minimiser that the
+ * paper's fitTo leaves to MINUIT (Sec. 5.3), and a covariance estimate.
+ * Compiled for FP64 shapes with at most 6 score features (responsibilities
+ * of a mixture's terms plus the leaves' parameter features); other shapes
+ * return NLL_ERR_UNSUPPORTED. */
+nll_status nll_eval_bhhh(nll_model* model, const double* theta, double* nll_out, double* grad_out,
+                         double* bhhh_out);
+
+/* Enqueue: a damped BHHH fit (Levenberg-Marquardt on B) on all attached
+ * events.  The proposal is theta_acc + d with (B_acc + lambda D) d =
+ * -grad_acc over the free parameters, D the diagonal of B_acc floored at
+ * 1e-12 of its largest entry, solved by Cholesky; acceptance as in nll_fit,
+ * then lambda = max(lambda / 10, 1e-12), otherwise lambda *= 10; a damped
+ * matrix that is not positive definite is retried with ten times the
+ * damping at most 8 times, else the proposal is theta_acc.  lambda (> 0) is
+ * the starting damping; the rest as nll_fit (recorded into a HIP graph).
+ * NLL_ERR_UNSUPPORTED where nll_eval_bhhh is. */
+nll_status nll_fit_bhhh(nll_model* model, double* theta, int32_t n_steps, double lambda, double* nll_out,
+                        double* grad_out, int32_t* status_out);
+
 /* Synchronise the model's stream and report (and clear) the errors found on
  * the device since the last call: NLL_ERR_PARAM_RANGE or NLL_ERR_INVALID_PDF
  * (also in *status_out if non-NULL), NLL_ERR_DEVICE on a runtime error. */

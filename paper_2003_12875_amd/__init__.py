@@ -247,6 +247,40 @@ class Model:
         check(lib().nll_fit(self._h, _ptr(th), int(n_steps), float(eta), _ptr(nll), _ptr(g), _ptr(status)), "nll_fit")
         return th, nll, g, status
 
+    def eval_bhhh(self, theta):
+        """(NLL, gradient, BHHH matrix [n_param, n_param]) at theta (see
+        nll_eval_bhhh)."""
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        _buf(theta, torch.float64, self.device, self.n_param, "theta")
+        nll = torch.empty(1, dtype=torch.float64, device=self.device)
+        g = torch.empty(self.n_param, dtype=torch.float64, device=self.device)
+        B = torch.empty(self.n_param, self.n_param, dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        check(lib().nll_eval_bhhh(self._h, _ptr(theta), _ptr(nll), _ptr(g), _ptr(B)), "nll_eval_bhhh")
+        return nll, g, B
+
+    def fit_bhhh(self, theta, n_steps: int, lam: float = 1e-3, out=None):
+        """Damped BHHH fit on all attached events (see nll_fit_bhhh); the
+        same buffers and return values as fit()."""
+        torch = _torch()
+        if out is None:
+            th = _dev_tensor(theta, torch.float64, self.device).clone()
+            nll = torch.empty(1, dtype=torch.float64, device=self.device)
+            g = torch.empty(self.n_param, dtype=torch.float64, device=self.device)
+            status = torch.empty(1, dtype=torch.int32, device=self.device)
+        else:
+            th, nll, g, status = out
+            th.copy_(_dev_tensor(theta, torch.float64, self.device))
+        _buf(th, torch.float64, self.device, self.n_param, "theta")
+        _buf(nll, torch.float64, self.device, 1, "nll")
+        _buf(g, torch.float64, self.device, self.n_param, "grad")
+        _buf(status, torch.int32, self.device, 1, "status")
+        self._bind_stream()
+        check(lib().nll_fit_bhhh(self._h, _ptr(th), int(n_steps), float(lam), _ptr(nll), _ptr(g), _ptr(status)),
+              "nll_fit_bhhh")
+        return th, nll, g, status
+
     def sync(self) -> int:
         """Synchronise and return (and clear) the device status (0 = ok)."""
         st = ctypes.c_int32(0)

@@ -15,7 +15,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported model shape", -3: "p
 
 # every entry point declared in include/nll.h
 EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_data", "nll_eval",
-           "nll_eval_grad", "nll_eval_batched", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_sync", "nll_get_schedule",
+           "nll_eval_grad", "nll_eval_batched", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_eval_bhhh",
+           "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
            "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
            "nll_status_string")
 
@@ -77,6 +78,8 @@ def lib():
         L.nll_eval_points.argtypes = [vp, i32, vp, vp, vp, vp]
         L.nll_fit_batched.argtypes = [vp, i32, vp, vp, i32, d, vp, vp, vp]
         L.nll_fit.argtypes = [vp, vp, i32, d, vp, vp, vp]
+        L.nll_eval_bhhh.argtypes = [vp, vp, vp, vp, vp]
+        L.nll_fit_bhhh.argtypes = [vp, vp, i32, d, vp, vp, vp]
         L.nll_sync.argtypes = [vp, ctypes.POINTER(i32)]
         L.nll_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
         L.nll_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]

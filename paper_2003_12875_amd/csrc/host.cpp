@@ -393,11 +393,13 @@ nll_status ensure_gd(nll_model* m, int n_sets) {
   if (n_sets <= m->gd_cap) return NLL_OK;
   dfree(m->gd_mem);
   dfree(m->gd_status);
+  dfree(m->gd_bacc);
   m->gd_cap = 0;
   const size_t P = (size_t)m->plan.n_param;
   nll_status st;
   if ((st = dalloc(&m->gd_mem, (size_t)n_sets * (3 * P + 2))) != NLL_OK) return st;
   if ((st = dalloc(&m->gd_status, (size_t)n_sets)) != NLL_OK) return st;
+  if ((st = dalloc(&m->gd_bacc, (size_t)n_sets * P * P)) != NLL_OK) return st;
   m->gd_cap = n_sets;
   m->have_graph = false;
   return NLL_OK;
@@ -412,6 +414,7 @@ GDState gd_state(const nll_model* m) {
   g.f_acc = m->gd_mem + 3 * S * P;
   g.eta = m->gd_mem + 3 * S * P + S;
   g.last_status = m->gd_status;
+  g.b_acc = m->gd_bacc;
   return g;
 }
 
@@ -484,7 +487,7 @@ hipEvent_t kernel_event(nll_model* m, int s, int which) {
 // a whole single-dataset fit: one persistent launch per step, the last
 // block of each launch takes the gradient-descent step
 nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n_steps, double eta, double* nll_out,
-                              double* grad_out, int32_t* status_out) {
+                              double* grad_out, int32_t* status_out, bool bhhh = false) {
   GDState gd = gd_state(m);
   hipError_t e = m->ops->fit_init(m->plan, theta, 1, eta, gd, m->consts, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
@@ -492,8 +495,11 @@ nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n
   a.gd = gd;
   record_step(m, 0, st);
   for (int s = 0; s < n_steps; ++s) {
-    e = m->ops->single_fit(m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), st,
-                           kernel_event(m, s, 0), kernel_event(m, s, 1));
+    e = bhhh ? m->ops->single_bhhh_fit(m->plan, a, m->sched.unroll, single_grid(m),
+                                       lds_cap(m, m->sched.blocks_per_cu), st, kernel_event(m, s, 0),
+                                       kernel_event(m, s, 1))
+             : m->ops->single_fit(m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), st,
+                                  kernel_event(m, s, 0), kernel_event(m, s, 1));
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     record_step(m, s + 1, st);
   }
@@ -612,7 +618,8 @@ nll_status nll_create_model(const nll_model_desc* desc, nll_model** out) {
   if (ops->na_grad > 8) m->sched.unroll = 2;
   if ((st = gl_table(m->device, &m->gl)) != NLL_OK) return fail(st);
   const size_t max_grid = (size_t)m->n_cu * 32;
-  if ((st = dalloc(&m->partials, max_grid * (size_t)(ops->na_grad + 1) * 2)) != NLL_OK) return fail(st);
+  const size_t record = std::max<size_t>((size_t)ops->na_grad + 1, (size_t)ops->bhhh_record);
+  if ((st = dalloc(&m->partials, max_grid * record * 2)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->pt_single, 1)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->status, 1)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->dbad, 1)) != NLL_OK) return fail(st);
@@ -645,6 +652,7 @@ void nll_destroy_model(nll_model* m) {
   dfree(m->set_partials);
   dfree(m->gd_mem);
   dfree(m->gd_status);
+  dfree(m->gd_bacc);
   delete m;
 }
 
@@ -686,6 +694,18 @@ static nll_status nll_eval_impl(nll_model* m, const double* theta, double* nll_o
   SingleArgs a = single_args(m, theta, nll_out, grad_out);
   hipError_t e = m->ops->single(m->plan, a, grad, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu),
                                 m->stream);
+  return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+}
+
+nll_status nll_eval_bhhh(nll_model* m, const double* theta, double* nll_out, double* grad_out, double* bhhh_out) {
+  if (!m || !theta || !nll_out || !grad_out || !bhhh_out) return NLL_ERR_ARG;
+  if (!m->ops->single_bhhh) return NLL_ERR_UNSUPPORTED;
+  if (m->n < 0) return NLL_ERR_STATE;
+  DeviceGuard guard(m->device);
+  SingleArgs a = single_args(m, theta, nll_out, grad_out);
+  a.bhhh_out = bhhh_out;
+  hipError_t e = m->ops->single_bhhh(m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu),
+                                     m->stream);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
 
@@ -783,16 +803,17 @@ nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets,
   });
 }
 
-nll_status nll_fit(nll_model* m, double* theta, int32_t n_steps, double eta, double* nll_out, double* grad_out,
-                   int32_t* status_out) {
+static nll_status fit_single_impl(nll_model* m, double* theta, int32_t n_steps, double eta, double* nll_out,
+                                  double* grad_out, int32_t* status_out, bool bhhh) {
   if (!m || !theta || !nll_out || n_steps < 0 || !(eta > 0.0)) return NLL_ERR_ARG;
+  if (bhhh && !m->ops->single_bhhh_fit) return NLL_ERR_UNSUPPORTED;
   if (m->n < 0) return NLL_ERR_STATE;
   DeviceGuard guard(m->device);
   nll_status st = ensure_sets(m, 1);
   if (st != NLL_OK) return st;
   if ((st = ensure_gd(m, 1)) != NLL_OK) return st;
   FitKey k;
-  k.mode = 1;
+  k.mode = bhhh ? 3 : 1;
   k.timing = m->step_timing;
   if ((st = ensure_events(m, n_steps)) != NLL_OK) return st;
   m->timed_steps = m->step_timing ? n_steps : -1;
@@ -806,8 +827,18 @@ nll_status nll_fit(nll_model* m, double* theta, int32_t n_steps, double eta, dou
   k.status = status_out;
   k.sched = m->sched;
   return run_recorded(m, k, [&](hipStream_t s) {
-    return enqueue_fit_single(m, s, theta, n_steps, eta, nll_out, grad_out, status_out);
+    return enqueue_fit_single(m, s, theta, n_steps, eta, nll_out, grad_out, status_out, bhhh);
   });
+}
+
+nll_status nll_fit(nll_model* m, double* theta, int32_t n_steps, double eta, double* nll_out, double* grad_out,
+                   int32_t* status_out) {
+  return fit_single_impl(m, theta, n_steps, eta, nll_out, grad_out, status_out, false);
+}
+
+nll_status nll_fit_bhhh(nll_model* m, double* theta, int32_t n_steps, double lambda, double* nll_out,
+                        double* grad_out, int32_t* status_out) {
+  return fit_single_impl(m, theta, n_steps, lambda, nll_out, grad_out, status_out, true);
 }
 
 nll_status nll_sync(nll_model* m, int32_t* status_out) {

@@ -17,8 +17,9 @@ struct GDState {
   double* g_acc;    // n_sets * P  its gradient
   double* th_prop;  // n_sets * P  point being evaluated
   double* f_acc;    // n_sets      its NLL (+inf before the first acceptance)
-  double* eta;      // n_sets      step size
+  double* eta;      // n_sets      step size (BHHH: damping lambda)
   int* last_status; // n_sets
+  double* b_acc;    // n_sets * P * P  BHHH: matrix at the last accepted point
 };
 
 struct SingleArgs {
@@ -27,6 +28,7 @@ struct SingleArgs {
   const double* theta;          // n_param (device)
   double* nll_out;              // 1 (device)
   double* grad_out;             // n_param (device) or null
+  double* bhhh_out;             // n_param^2 (device): BHHH matrix (evaluation)
   double* partials;             // grid * (NA + 1) double-double pairs
   PerTheta* pt_out;             // per-point constants left by block 0 (evaluation)
   PerTheta* consts;             // fit: constants of the proposal being evaluated,
@@ -81,6 +83,12 @@ struct VariantOps {
                      hipStream_t, hipEvent_t ev0, hipEvent_t ev1);
   hipError_t (*fit_init)(const Plan&, const double* theta, int n_sets, double eta, const GDState&,
                          PerTheta* consts, const double* glx, const double* glw, hipStream_t);
+  // BHHH (FP64 shapes with few score features; null where not compiled):
+  // NLL, gradient and BHHH matrix at one point, and damped BHHH fit steps
+  hipError_t (*single_bhhh)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t);
+  hipError_t (*single_bhhh_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
+                                hipEvent_t ev0, hipEvent_t ev1);
+  int bhhh_record;  // values per block record of the BHHH pass (0: not compiled)
 };
 
 // registry: every variants_*.hip file appends its compiled shapes

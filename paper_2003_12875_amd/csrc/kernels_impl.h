@@ -184,6 +184,219 @@ __device__ inline double gd_update(const Plan& pl, const GDState& gd, int s, int
 }
 
 // ------------------------------------------------------------------------
+// BHHH: B = sum_i s_i s_i^T of the events' scores s_i = d log p(x_i)/d theta
+// (Berndt, Hall, Hall and Hausman), the outer-product approximation of the
+// NLL's Hessian, and the damped (Levenberg-Marquardt) step on it.
+// ------------------------------------------------------------------------
+// index of the second moment of score features (i, j), i <= j, in the
+// upper-triangle row order of AccBhhh
+template <int NVF>
+__device__ __forceinline__ int mom_index(int i, int j) {
+  return i * NVF - i * (i - 1) / 2 + (j - i);
+}
+
+// B (LDS, P x P row-major, symmetric) from the reduced totals: the score is
+// affine in the features, s_i = c0 + A v_i, with, for parameter q,
+//   A[q][k]         = d log w_k/d theta_q - sum_{non-root l in S_k, p -> q} d log Z_lp
+//   A[q][NT+off+p]  = fscale_lp             (leaf l's local parameter p is q)
+//   c0[q]           = - sum_{root l, p -> q} d log Z_lp,
+// so B = N c0 c0^T + c0 (A m1)^T + (A m1) c0^T + A M2 A^T with m1 = sum v and
+// M2 = sum v v^T; plus N / nu^2 at (nu, nu) in an extended model.  Rows and
+// columns of fixed parameters, and everything after an invalid evaluation,
+// are 0.  Every entry is formed for (min, max) of its indices, so B is
+// exactly symmetric.  Ends with a barrier.
+template <class M>
+__device__ __forceinline__ void bhhh_assemble(const Plan& pl, const PerTheta& pt, const DD* tot, int64_t n,
+                                              const double* theta, int st, double* B) {
+  using AB = AccBhhh<M>;
+  constexpr int NT = AB::NT, NVF = AB::NVF, NA = AB::NA;
+  __shared__ double sA[kMaxParams][NVF];
+  __shared__ double sc0[kMaxParams], sAm1[kMaxParams];
+  const int P = pl.n_param, t = threadIdx.x;
+  const double dn = (double)n;
+  if (t < P) {
+    const int q = t;
+    double Aq[NVF];
+#pragma unroll
+    for (int j = 0; j < NVF; ++j) Aq[j] = 0.0;
+    double c0 = 0.0;
+    if constexpr (NT > 0) {
+#pragma unroll
+      for (int k = 0; k < M::K; ++k) Aq[k] = pt.dlogw[k][q];
+    }
+    static_for<M::L>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      constexpr int off = M::template leaf_off<l>();
+#pragma unroll
+      for (int p = 0; p < M::NPs[l]; ++p) {
+        if (pl.leaf_param[l][p] == q) {
+          Aq[NT + off + p] += pt.fscale[l][p];
+          if constexpr (M::ROOTs[l]) {
+            c0 -= pt.dlogz[l][p];
+          } else {
+#pragma unroll
+            for (int k = 0; k < M::K; ++k)
+              if ((pl.term_mask[k] >> l) & 1) Aq[k] -= pt.dlogz[l][p];
+          }
+        }
+      }
+    });
+    double m1[NVF];
+    if constexpr (NT > 0) {
+      double Tsum = 0.0;
+#pragma unroll
+      for (int k = 0; k < M::K - 1; ++k) {
+        m1[k] = tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo;
+        Tsum += m1[k];
+      }
+      m1[M::K - 1] = dn - Tsum;
+    }
+#pragma unroll
+    for (int j = 0; j < M::NPT; ++j) m1[NT + j] = tot[M::LEAF_BASE + j].hi + tot[M::LEAF_BASE + j].lo;
+    double am = 0.0;
+#pragma unroll
+    for (int j = 0; j < NVF; ++j) {
+      am = fma(Aq[j], m1[j], am);
+      sA[q][j] = Aq[j];
+    }
+    sc0[q] = c0;
+    sAm1[q] = am;
+  }
+  __syncthreads();
+  for (int e = t; e < P * P; e += blockDim.x) {
+    const int q0 = e / P, r0 = e - q0 * P;
+    const int q = q0 < r0 ? q0 : r0, r = q0 < r0 ? r0 : q0;
+    double b = 0.0;
+    if (st == 0 && pl.par_free[q] && pl.par_free[r]) {
+      double quad = 0.0;
+#pragma unroll
+      for (int i = 0; i < NVF; ++i) {
+        double row = 0.0;  // (M2 A_r^T)_i
+#pragma unroll
+        for (int j = 0; j < NVF; ++j) {
+          const DD mm = tot[NA + 1 + (i <= j ? mom_index<NVF>(i, j) : mom_index<NVF>(j, i))];
+          row = fma(mm.hi + mm.lo, sA[r][j], row);
+        }
+        quad = fma(sA[q][i], row, quad);
+      }
+      b = ((dn * sc0[q]) * sc0[r] + sc0[q] * sAm1[r]) + (sAm1[q] * sc0[r] + quad);
+      if (pl.extended && q == pl.yield_param && r == q) b += dn / (theta[q] * theta[q]);
+    }
+    B[e] = b;
+  }
+  __syncthreads();
+}
+
+// Solve (B + lambda D) d = -g over the free parameters by Cholesky, D the
+// diagonal of B floored at 1e-12 of its largest free entry; fixed
+// parameters enter as identity rows (d = 0), which leaves the free part's
+// arithmetic unchanged.  One thread; L is P x P scratch (LDS).  False if the
+// damped matrix is not positive definite.
+__device__ inline bool damped_solve(const Plan& pl, const double* B, const double* g, double lambda, double* d,
+                                    double* L) {
+  const int P = pl.n_param;
+  double dmax = 0.0;
+  for (int k = 0; k < P; ++k)
+    if (pl.par_free[k]) dmax = fmax(dmax, B[k * P + k]);
+  for (int a = 0; a < P; ++a) {
+    for (int b = 0; b <= a; ++b) {
+      double s;
+      if (!pl.par_free[a] || !pl.par_free[b]) {
+        s = a == b ? 1.0 : 0.0;
+      } else {
+        s = B[a * P + b];
+        if (a == b) s += lambda * fmax(s, 1e-12 * dmax);
+      }
+      for (int c = 0; c < b; ++c) s -= L[a * P + c] * L[b * P + c];
+      if (a == b) {
+        if (!(s > 0.0) || !__builtin_isfinite(s)) return false;
+        L[a * P + a] = sqrt(s);
+      } else {
+        L[a * P + b] = s / L[b * P + b];
+      }
+    }
+  }
+  for (int a = 0; a < P; ++a) {  // L y = -g  (y kept in d)
+    double s = pl.par_free[a] ? -g[a] : 0.0;
+    for (int c = 0; c < a; ++c) s -= L[a * P + c] * d[c];
+    d[a] = s / L[a * P + a];
+  }
+  for (int a = P - 1; a >= 0; --a) {  // L^T d = y
+    double s = d[a];
+    for (int c = a + 1; c < P; ++c) s -= L[c * P + a] * d[c];
+    d[a] = s / L[a * P + a];
+  }
+  return true;
+}
+
+// Damped BHHH step by a whole block (set 0): thread 0 accepts the
+// evaluated proposal when its NLL is finite and at most 4 ulps above the
+// last accepted one (lambda /= 10, floored at 1e-12), else lambda *= 10;
+// the accepted point, gradient and matrix are kept (B, LDS, becomes the
+// accepted matrix; bpre is this thread's entry of the previously accepted
+// one); thread 0 solves the damped system, retrying with ten times the
+// damping at most 8 times; thread q < P stores and returns its parameter of
+// the next proposal (theta_acc if no solve succeeded), threads q >= P 0.
+__device__ inline double bhhh_update(const Plan& pl, const GDState& gd, int st, double nll, const double* grad,
+                                     double* B, double bpre, const GDPre& pre) {
+  __shared__ int s_ok, s_solved;
+  __shared__ double s_lam;
+  __shared__ double s_acc[kMaxParams], s_g[kMaxParams], s_d[kMaxParams];
+  __shared__ double s_L[kMaxParams * kMaxParams];
+  const int P = pl.n_param, t = threadIdx.x;
+  if (t == 0) {
+    const double fa = pre.fa;
+    const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
+    double lam = pre.eta;
+    if (ok) {
+      gd.f_acc[0] = nll;
+      gd.last_status[0] = 0;
+      lam = fmax(lam * 0.1, 1e-12);
+    } else {
+      lam *= 10.0;
+      if (!__builtin_isfinite(fa)) gd.last_status[0] = st != 0 ? st : -5;
+    }
+    s_ok = ok;
+    s_lam = lam;
+  }
+  __syncthreads();
+  const bool ok = s_ok;
+  if (t < P) {
+    double acc = pre.acc, ga = pre.ga;
+    if (ok) {
+      acc = pre.prop;
+      ga = grad[t];
+      gd.th_acc[t] = acc;
+      gd.g_acc[t] = ga;
+    }
+    s_acc[t] = acc;
+    s_g[t] = ga;
+  }
+  if (t < P * P) {
+    if (ok) gd.b_acc[t] = B[t];
+    else B[t] = bpre;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double lam = s_lam;
+    bool solved = false;
+    for (int tries = 0; tries < 8 && !solved; ++tries) {
+      solved = damped_solve(pl, B, s_g, lam, s_d, s_L);
+      if (!solved) lam *= 10.0;
+    }
+    gd.eta[0] = lam;
+    s_solved = solved;
+  }
+  __syncthreads();
+  double next = 0.0;
+  if (t < P) {
+    next = s_solved && pl.par_free[t] ? s_acc[t] + s_d[t] : s_acc[t];
+    gd.th_prop[t] = next;
+  }
+  return next;
+}
+
+// ------------------------------------------------------------------------
 // per-tile event loops
 // ------------------------------------------------------------------------
 template <class M, int U>
@@ -270,14 +483,17 @@ __device__ inline void stream_part_tile(const double* const* cols, int64_t base,
 // one compensated partial per block (plain stores; the next kernel on the
 // stream reads them).  Block 0 also leaves its per-point constants for the
 // finishing kernel.
-template <class M, bool GRAD, int U, bool FIT = false>
+template <class M, bool GRAD, int U, bool FIT = false, bool BH = false>
 __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleArgs a) {
+  static_assert(!BH || (GRAD && M::PREC == 0), "BHHH moments: FP64 gradient pass only");
   constexpr int NA = M::template NA<GRAD>;
-  constexpr int NV = NA + 1;  // + invalid-event count
+  constexpr int NM = BH ? AccBhhh<M>::NM : 0;  // BHHH second moments
+  constexpr int NV = NA + 1 + NM;              // + invalid-event count
+  constexpr int NR = NA + 1 > NM ? NA + 1 : NM;  // values per block_sum_vals pass
   __shared__ Plan spl;
   __shared__ double s_theta[kMaxParams];
   __shared__ PerTheta pt;
-  __shared__ double red[NV * (kBlock + 1)];
+  __shared__ double red[NR * (kBlock + 1)];
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
 
@@ -310,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
     C.load(pt, pl);
     bad = uniform(pt.bad);
   }
-  typename Pass<M, GRAD>::A acc;
+  std::conditional_t<BH, AccBhhh<M>, typename Pass<M, GRAD>::A> acc;
   acc.init();
   if (bad == 0) {
     stream_tiles<M, GRAD, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb, C, acc);
@@ -319,10 +535,24 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
       stream_part_tile<M, GRAD, U>(cols, rest + threadIdx.x, a.n, C, acc);
   }
 
-  double v[NV];
-  acc.finalize(reinterpret_cast<double(&)[NA]>(v));
-  v[NA] = (double)acc.bad;
-  block_sum_vals<NV, kBlock>(v, red, tot);
+  // partial record: the NA sums, the invalid-event count, the NM moments
+  if constexpr (BH) {
+    double w[NA + NM];
+    acc.finalize(w);
+    double v0[NA + 1], v1[NM];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) v0[j] = w[j];
+    v0[NA] = (double)acc.run.bad;
+#pragma unroll
+    for (int j = 0; j < NM; ++j) v1[j] = w[NA + j];
+    block_sum_vals<NA + 1, kBlock>(v0, red, tot);
+    block_sum_vals<NM, kBlock>(v1, red, tot + NA + 1);
+  } else {
+    double v[NV];
+    acc.finalize(reinterpret_cast<double(&)[NA]>(v));
+    v[NA] = (double)acc.bad;
+    block_sum_vals<NV, kBlock>(v, red, tot);
+  }
   if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
   if (!FIT && blockIdx.x == 0) {
     const double* src = reinterpret_cast<const double*>(&pt);
@@ -336,10 +566,10 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
 // step of the proposal just evaluated and the per-point constants of the
 // next proposal (for the next step's streaming kernel).  Every load it
 // needs is issued at once at the start.
-template <class M, bool GRAD, bool FIT = false>
+template <class M, bool GRAD, bool FIT = false, bool BH = false>
 __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, const SingleArgs a, int n_blocks) {
   constexpr int NA = M::template NA<GRAD>;
-  constexpr int NV = NA + 1;
+  constexpr int NV = NA + 1 + (BH ? AccBhhh<M>::NM : 0);
   constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
   static_assert(PT8 <= kFinishBlock, "one constant per thread");
   __shared__ Plan spl;
@@ -356,13 +586,25 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
   stage_theta(FIT ? a.gd.th_prop : a.theta, pl.n_param, s_theta);
   GDPre pre{};
   if constexpr (FIT) pre = gd_preload(a.gd, 0, pl.n_param);
+  double bpre = 0.0;  // BHHH fit: this thread's entry of the accepted matrix
+  if constexpr (FIT && BH) {
+    const int P = pl.n_param;
+    if (t < P * P) bpre = a.gd.b_acc[t];
+  }
   RecordSum<NV, kFinishBlock> rs;
   rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
   if (t < PT8) reinterpret_cast<double*>(&spt)[t] = ptv;
   rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
   finish_block<M, GRAD>(spl, spt, tot, a.n, s_theta, false, &s_nll, &s_st, s_grad);
+  __shared__ double s_B[BH ? kMaxParams * kMaxParams : 1];
+  if constexpr (BH) bhhh_assemble<M>(spl, spt, tot, a.n, s_theta, s_st, s_B);
   if constexpr (FIT) {
-    const double next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, a.n, pre);
+    double next;
+    if constexpr (BH) {
+      next = bhhh_update(spl, a.gd, s_st, s_nll, s_grad, s_B, bpre, pre);
+    } else {
+      next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, a.n, pre);
+    }
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
     // the next proposal's constants, built in LDS (its phases read back
     // what other threads wrote) and stored with one parallel copy
@@ -375,6 +617,10 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
       if (s_st == -5) atomicOr(a.status, (int)kStatusPdf);
     }
     if (GRAD && a.grad_out && t < spl.n_param) a.grad_out[t] = s_grad[t];
+    if constexpr (BH) {
+      const int P = spl.n_param;
+      if (a.bhhh_out && t < P * P) a.bhhh_out[t] = s_B[t];
+    }
   }
 }
 
@@ -532,6 +778,8 @@ __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double
     gd.eta[s] = eta;
     gd.last_status[s] = 0;
   }
+  if (gd.b_acc)
+    for (int e = threadIdx.x; e < P * P; e += kBlock) gd.b_acc[(size_t)s * P * P + e] = 0.0;
   compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
   for (int e = threadIdx.x; e < (int)(sizeof(PerTheta) / sizeof(double)); e += kBlock)
     reinterpret_cast<double*>(&consts[s])[e] = reinterpret_cast<const double*>(&spt)[e];
@@ -588,6 +836,41 @@ struct Launch {
   static hipError_t single_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
                                hipEvent_t ev0, hipEvent_t ev1) {
     return single_t<true, true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
+  }
+  // BHHH: compiled for FP64 shapes with at most 6 score features (21 second
+  // moments), at 2 and 4 events per thread per tile (8 maps to 4)
+  static constexpr bool kBH = M::PREC == 0 && AccBhhh<M>::NVF <= 6;
+  template <bool FIT, int U>
+  static void launch_bh(const Plan& pl, const SingleArgs& a, int grid, int lds_cap, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+    const void* k = reinterpret_cast<const void*>(&k_single<M, true, U, FIT, true>);
+    if (ev0 && ev1)
+      hipExtLaunchKernelGGL((k_single<M, true, U, FIT, true>), dim3(grid), dim3(kBlock), (uint32_t)pad_lds(k, lds_cap),
+                            st, ev0, ev1, 0u, pl, a);
+    else
+      hipLaunchKernelGGL((k_single<M, true, U, FIT, true>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+  }
+  template <bool FIT>
+  static hipError_t bh_t(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
+                         hipEvent_t ev0, hipEvent_t ev1) {
+    if constexpr (kBH) {
+      if (unroll >= 4) launch_bh<FIT, 4>(pl, a, grid, lds_cap, st, ev0, ev1);
+      else launch_bh<FIT, 2>(pl, a, grid, lds_cap, st, ev0, ev1);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_single_finish<M, true, FIT, true>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  static hipError_t single_bhhh(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap,
+                                hipStream_t st) {
+    return bh_t<false>(pl, a, unroll, grid, lds_cap, st, nullptr, nullptr);
+  }
+  static hipError_t single_bhhh_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap,
+                                    hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    return bh_t<true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
   }
   static hipError_t single(const Plan& pl, const SingleArgs& a, bool grad, int unroll, int grid, int lds_cap,
                            hipStream_t st) {
@@ -666,6 +949,11 @@ VariantOps make_ops(const char* name) {
   v.consts = &Launch<M>::consts;
   v.sets = &Launch<M>::sets;
   v.fit_init = &Launch<M>::fit_init;
+  if constexpr (Launch<M>::kBH) {
+    v.single_bhhh = &Launch<M>::single_bhhh;
+    v.single_bhhh_fit = &Launch<M>::single_bhhh_fit;
+    v.bhhh_record = M::template NA<true> + 1 + AccBhhh<M>::NM;
+  }
   return v;
 }
 

@@ -586,6 +586,64 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts32<M>
 }
 
 // event-pass types of a compiled model
+// BHHH accumulator (FP64 pass): the gradient sums of Acc plus the second
+// moments sum_i v_i v_i^T (upper triangle, row by row) of each event's
+// score features v = (r_0 .. r_{K-1} if K > 1, then R_l phi_lp).  The score
+// of an event is affine in v with per-point coefficients, s_i = c0 + A v_i,
+// so sum_i s_i s_i^T follows from these moments after the reduction.  Each
+// event is evaluated into a fresh Acc and folded in.
+template <class M>
+struct AccBhhh {
+  static constexpr int NA = M::template NA<true>;
+  static constexpr int NT = M::K > 1 ? M::K : 0;  // responsibilities in v
+  static constexpr int NVF = NT + M::NPT;
+  static constexpr int NM = NVF * (NVF + 1) / 2;
+  Acc<M, true> run;
+  double mom[NM];
+  __device__ void init() {
+    run.init();
+#pragma unroll
+    for (int j = 0; j < NM; ++j) mom[j] = 0.0;
+  }
+  __device__ void begin_tile() { run.begin_tile(); }
+  __device__ void end_tile() { run.end_tile(); }
+  __device__ void finalize(double (&v)[NA + NM]) {
+    run.finalize(reinterpret_cast<double(&)[NA]>(v));
+#pragma unroll
+    for (int j = 0; j < NM; ++j) v[NA + j] = mom[j];
+  }
+};
+
+template <class M, bool GRAD>
+__device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& C, AccBhhh<M>& acc) {
+  static_assert(GRAD, "the BHHH pass is a gradient pass");
+  using AB = AccBhhh<M>;
+  Acc<M, true> ev;
+  ev.init();
+  model_event<M, true>(x, C, ev);
+#pragma unroll
+  for (int j = 0; j < AB::NA; ++j) acc.run.a[j] += ev.a[j];
+  if constexpr (M::NEED_PROD) acc.run.P *= ev.P;
+  acc.run.bad += ev.bad;
+  double v[AB::NVF];
+  if constexpr (AB::NT > 0) {
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < M::K - 1; ++k) {
+      v[k] = ev.a[M::TERM_BASE + k];
+      rs += v[k];
+    }
+    v[M::K - 1] = 1.0 - rs;  // the responsibilities of an event sum to 1
+  }
+#pragma unroll
+  for (int j = 0; j < M::NPT; ++j) v[AB::NT + j] = ev.a[M::LEAF_BASE + j];
+  int m = 0;
+#pragma unroll
+  for (int i = 0; i < AB::NVF; ++i)
+#pragma unroll
+    for (int j = i; j < AB::NVF; ++j, ++m) acc.mom[m] = fma(v[i], v[j], acc.mom[m]);
+}
+
 template <class M, bool GRAD>
 struct Pass {
   using C = std::conditional_t<M::PREC == 1, Consts32<M>, Consts<M>>;

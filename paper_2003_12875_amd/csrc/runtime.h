@@ -34,7 +34,7 @@ void gauss_legendre(int n, double* nodes, double* weights);
 }  // namespace nllmi
 
 struct FitKey {
-  int mode = 0;  // 1: single-dataset fit, 2: batched fit
+  int mode = 0;  // 1: single-dataset fit, 2: batched fit, 3: single-dataset BHHH fit
   int n_sets = -1;
   const int64_t* offsets = nullptr;
   double* theta = nullptr;
@@ -89,6 +89,7 @@ struct nll_model {
   int gd_cap = 0;
   double* gd_mem = nullptr;
   int* gd_status = nullptr;
+  double* gd_bacc = nullptr;  // BHHH fits: accepted matrix per set (n_sets * P * P)
 
   // step timing of fits
   int step_timing = 0;             // 0 off, 1 whole steps, 2 streaming kernels
