@@ -28,7 +28,8 @@ Also reported, on the same GPU:
     host cores, same events, same minimiser;
   * extra       -- the other workloads: 1-D Gaussian (1e5 events) at 64
     parameter points (64 launches, and all 64 in one nll_eval_points pass)
-    and fit steps, the extended (Poisson yield) mixture on the 1e7 events,
+    and fit steps, the damped BHHH fit and the extended (Poisson yield)
+    mixture on the 1e7 events,
     the precision study (1e8 events, FP64
     and FP32-compensated passes), the 2-D Crystal Ball/ARGUS x Chebyshev
     model (5e7 events), and 4096 batched toy fits (4.1e8 events per step).
@@ -300,6 +301,30 @@ def extras(torch, nllmi, datagen, args):
     res5["fp32c_vs_fp64_gpu"] = {"points": 32, "max_nll_rel_err": max(nerr), "max_grad_rel_err_vs_max_abs": max(gerr)}
     ex["precision_study_1e8"] = res5
     del cols
+    torch.cuda.empty_cache()
+    # second-order fit on the headline workload: damped BHHH from the same
+    # start, steps until the NLL is within 1e-9 (relative) of its final value,
+    # against gradient descent's 200 steps
+    w = datagen.workload(2)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    th0 = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    P = m.n_param
+    bb = (torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.float64, device="cuda"),
+          torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.int32, device="cuda"))
+    m.fit_bhhh(th0, 30, 1e-3, out=bb)
+    torch.cuda.synchronize()
+    t_bh = time_launches(torch, lambda: m.fit_bhhh(th0, 30, 1e-3, out=bb), 3)
+    f_bh = float(bb[1].item())
+    trace = []
+    for k in (1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20, 25, 30):
+        trace.append((k, float(m.fit_bhhh(th0, k, 1e-3)[1].item())))
+    steps_to = next((k for k, f in trace if abs(f - f_bh) <= 1e-9 * abs(f_bh)), None)
+    gd = m.fit(th0, 200)
+    ex["bhhh_c2_1e7"] = {"steps": 30, "ms_per_step": t_bh / 30, "nll": f_bh, "status": int(bb[3].item()),
+                         "steps_to_1e-9": steps_to, "gd_200_steps_nll": float(gd[1].item()),
+                         "nll_by_steps": trace}
+    del m
     torch.cuda.empty_cache()
     # extended model (the c2 mixture with a Poisson yield term nu - N ln nu,
     # 5 parameters) on the c2 events: NLL+gradient and a 200-step fit
