@@ -461,7 +461,9 @@ def _pick(tab, pred):
 
 
 def _is_fit_kernel(k):
-    return "k_single<" in k and (", true, 4, true>" in k or ", true, 2, true>" in k or ", true, 8, true>" in k)
+    """The gradient-descent fit's streaming kernel k_single<M, GRAD=true, U,
+    FIT=true, BHHH=false>."""
+    return "k_single<" in k and any(f", true, {u}, true, false>" in k for u in (2, 4, 8))
 
 
 def _streaming(values):
