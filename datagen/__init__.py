@@ -14,7 +14,9 @@ The five workloads stand in for the paper's benchmark models (its Fig. 1
 covers 100k-300k events of "various likelihood models" whose definitions
 are not given): a wide Gaussian, a Gaussian-plus-exponential mixture, a
 2-D Crystal Ball / ARGUS mixture times a Chebyshev series, batched toy
-datasets of the Gaussian, and the mixture at 1e8 events.
+datasets of the Gaussian, and the mixture at 1e8 events.  A sixth, a
+Johnson S_U peak over an exponential background, exercises the Johnson
+density the paper adds to the built-in ones (Sec. 3).
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdatagen.so")
 
 MASTER_SEED = 2003012875
-KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7}
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8}
 
 
 def build() -> str:
@@ -124,6 +126,29 @@ def mixture_spec(f=0.2, mu=5.0, sigma=0.4, c=-0.7, lo=0.0, hi=10.0, norm="analyt
                       {"kind": "exp", "obs": 0, "params": [3], "norm": norm},
                       {"kind": "sum", "params": [0], "children": [0, 1]}],
             "root": 2}
+
+
+def johnson_spec(f=0.3, mu=5.28, lam=0.02, gam=-0.5, delta=1.5, c=-1.5, lo=5.0, hi=5.6, norm="analytic"):
+    """f * Johnson S_U(m; mu, lambda, gamma, delta) + (1 - f) * Exp(m; c) on
+    m in [5.0, 5.6]: a skewed mass peak over a falling background, the use
+    the Johnson density is made for.  Parameters (f, mu, lambda, gamma,
+    delta, c); seeded points jitter them by a fraction of the peak's scale."""
+    return {"obs": [{"name": "m", "lo": lo, "hi": hi}],
+            "params": [param("f", f, 0.0, 1.0, jitter=0.03), param("mu", mu, lo, hi, jitter=0.002),
+                       param("lambda", lam, 1e-4, 1.0, jitter=0.002), param("gamma", gam, -10.0, 10.0, jitter=0.05),
+                       param("delta", delta, 0.05, 20.0, jitter=0.15), param("c", c, -10.0, 10.0, jitter=0.15)],
+            "nodes": [{"kind": "johnson", "obs": 0, "params": [1, 2, 3, 4], "norm": norm},
+                      {"kind": "exp", "obs": 0, "params": [5], "norm": norm},
+                      {"kind": "sum", "params": [0], "children": [0, 1]}],
+            "root": 2}
+
+
+def johnson_single_spec(mu=5.28, lam=0.02, gam=-0.5, delta=1.5, lo=5.0, hi=5.6, norm="analytic"):
+    """The Johnson S_U peak of johnson_spec() alone; parameters (mu, lambda,
+    gamma, delta)."""
+    s = johnson_spec(mu=mu, lam=lam, gam=gam, delta=delta, lo=lo, hi=hi, norm=norm)
+    return {"obs": s["obs"], "params": s["params"][1:5],
+            "nodes": [{"kind": "johnson", "obs": 0, "params": [0, 1, 2, 3], "norm": norm}], "root": 0}
 
 
 def cheb_coefficients(seed: int, order: int = 4, lo: float = -1.0, hi: float = 1.0,
@@ -308,6 +333,19 @@ def workload(config: int, n: int | None = None, threads: int | None = None) -> d
     points = parameter_points(spec, pts, seed + 1)
     return {"config": config, "spec": spec, "cols": cols, "n": N, "theta": theta, "points": points,
             "seed": seed}
+
+
+JOHNSON_SEED = MASTER_SEED + 6000
+
+
+def johnson_workload(n: int = 10_000_000, single: bool = False, n_points: int = 8,
+                     threads: int | None = None, norm: str = "analytic") -> dict:
+    """The Johnson S_U mixture of johnson_spec() (or its peak alone) with n
+    events: data seed master + 6000, parameter-point seed one more."""
+    spec = johnson_single_spec(norm=norm) if single else johnson_spec(norm=norm)
+    cols = generate(spec, n, JOHNSON_SEED, threads=threads)
+    return {"spec": spec, "cols": cols, "n": n, "theta": theta_of(spec),
+            "points": parameter_points(spec, n_points, JOHNSON_SEED + 1), "seed": JOHNSON_SEED}
 
 
 def toys_workload(n_sets: int = 4096, size_lo: int = 1000, size_hi: int = 200000,

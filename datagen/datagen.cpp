@@ -86,7 +86,7 @@ struct EventRng {
 extern "C" {
 
 typedef struct dg_node {
-  int32_t kind; /* 1 gauss, 2 exp, 3 cheb, 4 cb, 5 argus, 6 sum, 7 prod */
+  int32_t kind; /* 1 gauss, 2 exp, 3 cheb, 4 cb, 5 argus, 6 sum, 7 prod, 8 johnson */
   int32_t obs;
   int32_t n_param;
   double p[8]; /* parameter VALUES (truth) */
@@ -113,6 +113,18 @@ double sample_gauss(EventRng& r, double mu, double s, double lo, double hi) {
     double u1 = r.u01_open0(), u2 = r.u01();
     double z = std::sqrt(-2.0 * std::log(u1)) * std::cos(kTwoPi * u2);
     double x = mu + s * z;
+    if (x >= lo && x <= hi) return x;
+  }
+  return std::nan("");
+}
+
+/* Johnson S_U by its defining transformation: n standard normal,
+ * x = mu + lambda sinh((n - gamma)/delta), kept when inside [lo, hi]. */
+double sample_johnson(EventRng& r, double mu, double la, double ga, double de, double lo, double hi) {
+  for (int t = 0; t < kMaxTries; ++t) {
+    double u1 = r.u01_open0(), u2 = r.u01();
+    double n = std::sqrt(-2.0 * std::log(u1)) * std::cos(kTwoPi * u2);
+    double x = mu + la * std::sinh((n - ga) / de);
     if (x >= lo && x <= hi) return x;
   }
   return std::nan("");
@@ -209,6 +221,9 @@ void sample_node(const dg_model& m, int i, EventRng& r, double* x) {
     }
     case 7:
       for (int k = 0; k < nd.n_child; ++k) sample_node(m, nd.child[k], r, x);
+      return;
+    case 8:
+      x[nd.obs] = sample_johnson(r, nd.p[0], nd.p[1], nd.p[2], nd.p[3], lo, hi);
       return;
   }
 }

@@ -186,6 +186,31 @@ double g_argus(const orc_node& nd, const double* th, double x, double* dg) {
   return g;
 }
 
+/* Johnson's S_U density (Sec. 3 names it among the built-in densities):
+ * with z = (x - mu)/lambda and u = gamma + delta asinh(z),
+ *   g = exp(-u^2/2) / sqrt(1 + z^2)
+ * (the normalised density is delta/(lambda sqrt(2 pi)) g on the real line).
+ * log g = -u^2/2 - ln(1 + z^2)/2, so with w = u delta/sqrt(1 + z^2) + z/(1 + z^2)
+ * (which is -d log g/dz) and dz/dmu = -1/lambda, dz/dlambda = -z/lambda:
+ *   dg/dmu = g w/lambda, dg/dlambda = g w z/lambda,
+ *   dg/dgamma = -g u,    dg/ddelta = -g u asinh(z).                     */
+double g_johnson(const orc_node& nd, const double* th, double x, double* dg) {
+  double mu = P(th, nd, 0), la = P(th, nd, 1), ga = P(th, nd, 2), de = P(th, nd, 3);
+  double z = (x - mu) / la;
+  double q = 1.0 + z * z;
+  double A = std::asinh(z);
+  double u = ga + de * A;
+  double g = std::exp(-0.5 * u * u) / std::sqrt(q);
+  if (dg) {
+    double w = u * de / std::sqrt(q) + z / q;
+    dg[0] = g * w / la;
+    dg[1] = g * w * z / la;
+    dg[2] = -g * u;
+    dg[3] = -g * u * A;
+  }
+  return g;
+}
+
 double leaf_g(const orc_model& m, const orc_node& nd, const double* th, double x, double* dg) {
   switch (nd.kind) {
     case ORC_GAUSS: return g_gauss(nd, th, x, dg);
@@ -193,6 +218,7 @@ double leaf_g(const orc_model& m, const orc_node& nd, const double* th, double x
     case ORC_CHEB: return g_cheb(nd, th, m.lo[nd.obs], m.hi[nd.obs], x, dg);
     case ORC_CB: return g_cb(nd, th, x, dg);
     case ORC_ARGUS: return g_argus(nd, th, x, dg);
+    case ORC_JOHNSON: return g_johnson(nd, th, x, dg);
   }
   return std::nan("");
 }
@@ -348,6 +374,34 @@ void norm_argus_closed(double m0, double c, double lo, double hi, double* Z, dou
   d[1] = 0.5 * m0 * m0 * j3;
 }
 
+/* Johnson S_U over [lo, hi].  The substitution u = gamma + delta asinh(z),
+ * du = delta dx / (lambda sqrt(1 + z^2)), turns g dx into
+ * (lambda/delta) e^{-u^2/2} du, so
+ *   Z = (lambda/delta) sqrt(pi/2) [erf(u_hi/sqrt2) - erf(u_lo/sqrt2)].
+ * Derivatives: the prefactor's, plus e^{-u^2/2} times the derivative of
+ * each limit u_b (du_b/dmu = -delta/(lambda s_b), du_b/dlambda =
+ * -delta z_b/(lambda s_b), du_b/dgamma = 1, du_b/ddelta = asinh(z_b), with
+ * s_b = sqrt(1 + z_b^2)), taken between lo and hi:
+ *   dZ/dmu     = e_lo/s_lo - e_hi/s_hi
+ *   dZ/dlambda = Z/lambda + z_lo e_lo/s_lo - z_hi e_hi/s_hi
+ *   dZ/dgamma  = (lambda/delta) (e_hi - e_lo)
+ *   dZ/ddelta  = -Z/delta + (lambda/delta) (A_hi e_hi - A_lo e_lo).       */
+void norm_johnson_closed(double mu, double la, double ga, double de, double lo, double hi,
+                         double* Z, double* d) {
+  double zl = (lo - mu) / la, zh = (hi - mu) / la;
+  double Al = std::asinh(zl), Ah = std::asinh(zh);
+  double ul = ga + de * Al, uh = ga + de * Ah;
+  double sl = std::sqrt(1.0 + zl * zl), sh = std::sqrt(1.0 + zh * zh);
+  double el = std::exp(-0.5 * ul * ul), eh = std::exp(-0.5 * uh * uh);
+  double k = la / de;
+  double z = k * std::sqrt(kPi / 2.0) * erf_diff(ul, uh);
+  *Z = z;
+  d[0] = el / sl - eh / sh;
+  d[1] = z / la + zl * el / sl - zh * eh / sh;
+  d[2] = k * (eh - el);
+  d[3] = -z / de + k * (Ah * eh - Al * el);
+}
+
 /* 256-point Gauss-Legendre on [a, b] of g and dg (np local derivatives). */
 void gl_panel(const orc_model& m, const orc_node& nd, const double* th, double a, double b,
               double* Z, double* d) {
@@ -397,6 +451,9 @@ void leaf_norm_local(const orc_model& m, const orc_node& nd, const double* th, d
         norm_cb_closed(P(th, nd, 0), P(th, nd, 1), P(th, nd, 2), P(th, nd, 3), lo, hi, Z, d);
         return;
       case ORC_ARGUS: norm_argus_closed(P(th, nd, 0), P(th, nd, 1), lo, hi, Z, d); return;
+      case ORC_JOHNSON:
+        norm_johnson_closed(P(th, nd, 0), P(th, nd, 1), P(th, nd, 2), P(th, nd, 3), lo, hi, Z, d);
+        return;
     }
     return;
   }
@@ -434,14 +491,17 @@ int expected_params(const orc_node& nd) {
     case ORC_ARGUS: return 2;
     case ORC_SUM: return nd.n_child - 1;
     case ORC_PROD: return 0;
+    case ORC_JOHNSON: return 4;
   }
   return -1;
 }
 
+bool is_leaf(int kind) { return (kind >= ORC_GAUSS && kind <= ORC_ARGUS) || kind == ORC_JOHNSON; }
+
 /* Bit mask of observables a node depends on. */
 unsigned obs_mask(const orc_model& m, int i) {
   const orc_node& nd = m.node[i];
-  if (nd.kind <= ORC_ARGUS) return 1u << nd.obs;
+  if (is_leaf(nd.kind)) return 1u << nd.obs;
   unsigned r = 0;
   for (int j = 0; j < nd.n_child; ++j) r |= obs_mask(m, nd.child[j]);
   return r;
@@ -456,12 +516,12 @@ int check_model(const orc_model& m) {
     if (!(m.lo[o] < m.hi[o])) return ORC_E_ARG;
   for (int i = 0; i < m.n_node; ++i) {
     const orc_node& nd = m.node[i];
-    if (nd.kind < ORC_GAUSS || nd.kind > ORC_PROD) return ORC_E_ARG;
+    if (nd.kind < ORC_GAUSS || nd.kind > ORC_JOHNSON) return ORC_E_ARG;
     if (nd.n_param < 0 || nd.n_param > ORC_NODE_PAR) return ORC_E_ARG;
     if (expected_params(nd) != nd.n_param) return ORC_E_ARG;
     for (int k = 0; k < nd.n_param; ++k)
       if (nd.param[k] < 0 || nd.param[k] >= m.n_param) return ORC_E_ARG;
-    if (nd.kind <= ORC_ARGUS) {
+    if (is_leaf(nd.kind)) {
       if (nd.obs < 0 || nd.obs >= m.n_obs || nd.n_child != 0) return ORC_E_ARG;
       if (nd.norm < ORC_NORM_CLOSED || nd.norm > ORC_NORM_GL_SINGLE) return ORC_E_ARG;
       if (nd.kind == ORC_ARGUS && m.lo[nd.obs] < 0.0) return ORC_E_UNSUPPORTED;
@@ -508,6 +568,9 @@ int check_params(const orc_model& m, const double* th) {
       case ORC_ARGUS:
         if (!(P(th, nd, 0) > m.lo[nd.obs])) return ORC_E_PARAM;
         break;
+      case ORC_JOHNSON:
+        if (!(P(th, nd, 1) > 0.0) || !(P(th, nd, 3) > 0.0)) return ORC_E_PARAM;
+        break;
       case ORC_SUM: {
         double f = 0.0;
         for (int k = 0; k < nd.n_param; ++k) {
@@ -540,7 +603,7 @@ int prepare(const orc_model& m, const double* th, Prepared& pr) {
   if (st != ORC_OK) return st;
   for (int i = 0; i < m.n_node; ++i) {
     const orc_node& nd = m.node[i];
-    if (nd.kind > ORC_ARGUS) continue;
+    if (!is_leaf(nd.kind)) continue;
     leaf_norm_local(m, nd, th, &pr.Z[i], pr.dZ[i]);
     if (!(pr.Z[i] > 0.0) || !std::isfinite(pr.Z[i])) return ORC_E_PARAM;
   }
@@ -553,7 +616,7 @@ double node_value(const Prepared& pr, int i, const double* x, double* dv) {
   const orc_model& m = *pr.m;
   const orc_node& nd = m.node[i];
   const int np = m.n_param;
-  if (nd.kind <= ORC_ARGUS) {
+  if (is_leaf(nd.kind)) {
     double dg[ORC_NODE_PAR];
     double g = leaf_g(m, nd, pr.th, x[nd.obs], dv ? dg : nullptr);
     double Z = pr.Z[i];
@@ -913,7 +976,7 @@ int orc_leaf_norm(const orc_model* m, int32_t node, const double* theta, double*
   if (!m || !theta || !Z || !dZ) return ORC_E_ARG;
   int st = check_model(*m);
   if (st != ORC_OK) return st;
-  if (node < 0 || node >= m->n_node || m->node[node].kind > ORC_ARGUS) return ORC_E_ARG;
+  if (node < 0 || node >= m->n_node || !is_leaf(m->node[node].kind)) return ORC_E_ARG;
   st = check_params(*m, theta);
   if (st != ORC_OK) return st;
   double d[ORC_NODE_PAR];

@@ -45,7 +45,8 @@ enum orc_kind {
   ORC_CB = 4,    /* params (m0, sigma, alpha, n), low-side tail   */
   ORC_ARGUS = 5, /* params (m0, c), power 1/2                    */
   ORC_SUM = 6,   /* params (f_1..f_{k-1}) over k children         */
-  ORC_PROD = 7   /* no params; children on disjoint observables   */
+  ORC_PROD = 7,  /* no params; children on disjoint observables   */
+  ORC_JOHNSON = 8 /* params (mu, lambda, gamma, delta), S_U family */
 };
 
 enum orc_norm {

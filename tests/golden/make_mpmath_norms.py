@@ -4,7 +4,7 @@
 The shapes are the textbook densities the paper's models are built from
 (Sec. 3 and 5): Gaussian, exponential, Chebyshev series with unit T_0
 coefficient, Crystal Ball with a low-side power-law tail, ARGUS with power
-1/2.  This script calls only mpmath; the stored numbers pin the closed
+1/2, Johnson's S_U.  This script calls only mpmath; the stored numbers pin the closed
 forms and the Gauss-Legendre rules of both implementations.
 
     python tests/golden/make_mpmath_norms.py
@@ -27,6 +27,9 @@ CASES = [
     ("cb", ["0", "1", "1", "2.5"], "-8", "4"),
     ("argus", ["5.29", "-20"], "5.20", "5.30"),
     ("argus", ["1", "-5"], "0.1", "0.95"),
+    ("johnson", ["5.28", "0.02", "-0.5", "1.5"], "5.0", "5.6"),
+    ("johnson", ["0", "1", "0.8", "0.7"], "-10", "10"),
+    ("johnson", ["0", "1", "0", "1"], "5", "30"),
 ]
 
 
@@ -60,6 +63,13 @@ def shape(kind, p, lo, hi):
             u = 1 - (x / m0) ** 2
             return x * mp.sqrt(u) * mp.exp(c * u)
         return g, [m0]
+    if kind == "johnson":
+        mu, la, ga, de = p
+
+        def g(x):
+            z = (x - mu) / la
+            return mp.exp(-(ga + de * mp.asinh(z)) ** 2 / 2) / mp.sqrt(1 + z * z)
+        return g, [mu]
     raise ValueError(kind)
 
 

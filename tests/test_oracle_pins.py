@@ -51,6 +51,12 @@ def lib_logpdf(kind, params, lo, hi, x):
         d = stats.argus(math.sqrt(-2.0 * c), scale=m0)
         top = min(hi, m0)
         return d.logpdf(x) - np.log(d.cdf(top) - d.cdf(lo))
+    if kind == "johnson":
+        mu, la, ga, de = params
+        d = stats.johnsonsu(ga, de, loc=mu, scale=la)
+        # mass inside the range from the side whose tail the range is in
+        mass = d.sf(lo) - d.sf(hi) if d.cdf(lo) > 0.5 else d.cdf(hi) - d.cdf(lo)
+        return d.logpdf(x) - np.log(mass)
     if kind == "cheb":
         coef = np.concatenate([[1.0], np.asarray(params, dtype=np.float64)])
         y = (2 * x - lo - hi) / (hi - lo)
@@ -75,6 +81,10 @@ LEAF_CASES = [
     ("argus", (1.0, -5.0), 0.1, 0.95),
     ("cheb", (-0.28, -0.27, -0.07, 0.10), -1.0, 1.0),
     ("cheb", (0.2, -0.1), 2.0, 6.0),
+    ("johnson", (5.28, 0.02, -0.5, 1.5), 5.0, 5.6),   # skewed mass peak
+    ("johnson", (0.0, 1.0, 0.8, 0.7), -10.0, 10.0),  # heavy tails, truncated
+    ("johnson", (2.0, 0.5, 2.0, 2.0), 0.0, 3.0),
+    ("johnson", (0.0, 1.0, 0.0, 1.0), 5.0, 30.0),   # both limits in the right tail
 ]
 
 
@@ -615,3 +625,76 @@ def test_bhhh_fit_mixture_converges_to_stationary_point():
     _, _, _, stats = o.nll(w["cols"], th, stats=True)
     assert np.max(np.abs(g) / stats[1:]) < 1e-8
     assert nll <= nll2 + 1e-9 * abs(nll2)
+
+
+# ---------------------------------------------------------------------------
+# Johnson S_U (Sec. 3)
+# ---------------------------------------------------------------------------
+
+def test_johnson_large_delta_is_gaussian():
+    """gamma = 0, lambda = delta sigma: as delta grows the S_U density tends
+    to the Gaussian(mu, sigma) (asinh z -> z, sqrt(1 + z^2) -> 1), with
+    log-density corrections (t^4/6 - t^2/2) / delta^2 to leading order,
+    t = (x - mu)/sigma (from asinh z = z - z^3/6 and ln(1 + z^2) = z^2), plus
+    a shift of the normalisation of the same order."""
+    mu, sg, lo, hi = 0.3, 1.5, -6.0, 7.0
+    for de in (1e3, 1e5):
+        params = (mu, de * sg, 0.0, de)
+        spec = single_leaf_spec("johnson", params, lo, hi)
+        for p in spec["params"]:
+            p["lo"], p["hi"] = -1e9, 1e9
+        o = oracle.Oracle(spec)
+        xs = np.linspace(lo, hi, 27)
+        res = [o.log_density([x], params) for x in xs]
+        assert all(r[0] == OK for r in res)
+        got = np.array([r[1] for r in res])
+        ref = lib_logpdf("gauss", (mu, sg), lo, hi, xs)
+        t = (xs - mu) / sg
+        bound = (1.2 * (t ** 4 / 6 + t ** 2 / 2) + 2.0) / de ** 2 + 1e-12
+        assert np.all(np.abs(got - ref) <= bound), (de, np.abs(got - ref) / bound)
+
+
+def test_johnson_mixture_nll_matches_library_brute_force():
+    spec = datagen.johnson_spec()
+    theta = datagen.theta_of(spec)
+    cols = datagen.generate(spec, 16, seed=5)
+    cols[0][:4] = [5.0, 5.6, 5.28, 5.2801]
+    lo, hi = spec["obs"][0]["lo"], spec["obs"][0]["hi"]
+    f = theta[0]
+    o = oracle.Oracle(spec)
+    for n in (1, 2, 3, 16):
+        x = cols[0][:n]
+        p = f * np.exp(lib_logpdf("johnson", theta[1:5], lo, hi, x)) + (1 - f) * np.exp(lib_logpdf("exp", theta[5:6], lo, hi, x))
+        ref = -math.fsum(np.log(p))
+        st, nll, _ = o.nll([x], theta)
+        assert st == OK
+        assert abs(nll - ref) <= 2e-13 * max(1.0, abs(ref)), (n, nll, ref)
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_johnson_gradient_matches_central_differences(single):
+    w = datagen.johnson_workload(4000, single=single, n_points=3)
+    o = oracle.Oracle(w["spec"])
+    th = w["points"][2]
+    st, nll, g = o.nll(w["cols"], th)
+    assert st == OK
+    widths = datagen.jitter_widths(w["spec"])
+    for k in range(len(th)):
+        h = 1e-3 * widths[k]
+
+        def f(v):
+            t = th.copy()
+            t[k] = v
+            return o.nll(w["cols"], t)[1]
+
+        fd = (f(th[k] - 2 * h) - 8 * f(th[k] - h) + 8 * f(th[k] + h) - f(th[k] + 2 * h)) / (12 * h)
+        bound = 50 * (2.2e-16 * abs(nll) / h) + 1e-6 * abs(g[k])
+        assert abs(fd - g[k]) <= bound, (k, fd, g[k], bound)
+
+
+def test_johnson_parameter_checks():
+    spec = single_leaf_spec("johnson", (0.0, 1.0, 0.0, 1.0), -5.0, 5.0)
+    o = oracle.Oracle(spec)
+    for bad in ((0.0, 0.0, 0.0, 1.0), (0.0, -1.0, 0.0, 1.0), (0.0, 1.0, 0.0, 0.0), (0.0, 1.0, 0.0, -2.0)):
+        assert o.log_density([0.1], bad)[0] == E_PARAM
+    assert o.log_density([0.1], (0.0, 1.0, 0.0, 1.0))[0] == OK
