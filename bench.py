@@ -346,6 +346,39 @@ def extras(torch, nllmi, datagen, args):
                              "fit_status": r["status"], "n_events": w["n"]}
     del m
     torch.cuda.empty_cache()
+    # Johnson S_U peak over an exponential background (the Johnson density
+    # of Sec. 3), 1e7 events: NLL+gradient and NLL alone; then the peak
+    # alone (4 score features) fitted by damped BHHH from a seeded start
+    w = datagen.johnson_workload()
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(m.n_param, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: m.eval_grad(th, out=out, grad=g), 20)
+    tf = time_launches(torch, lambda: m.eval(th, out=out), 20)
+    res_j = {"variant": m.info["variant"], "n_events": w["n"], "eval_grad_ms": tg, "eval_ms": tf,
+             "events_per_s": w["n"] / (tg * 1e-3), "achieved_GBs": 8.0 * w["n"] / (tg * 1e-3) / 1e9,
+             "schedule": m.schedule}
+    del m
+    w = datagen.johnson_workload(single=True)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    th0 = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    P = m.n_param
+    bb = (torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.float64, device="cuda"),
+          torch.empty(P, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.int32, device="cuda"))
+    m.fit_bhhh(th0, 20, 1e-3, out=bb)
+    torch.cuda.synchronize()
+    t_bh = time_launches(torch, lambda: m.fit_bhhh(th0, 20, 1e-3, out=bb), 3)
+    f_bh = float(bb[1].item())
+    trace = [(k, float(m.fit_bhhh(th0, k, 1e-3)[1].item())) for k in (1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20)]
+    res_j["peak_alone_bhhh"] = {"variant": m.info["variant"], "steps": 20, "ms_per_step": t_bh / 20,
+                                "nll": f_bh, "status": int(bb[3].item()),
+                                "steps_to_1e-9": next((k for k, f in trace if abs(f - f_bh) <= 1e-9 * abs(f_bh)), None)}
+    ex["johnson_exp_1e7"] = res_j
+    del m
+    torch.cuda.empty_cache()
     # 2-D CB/ARGUS x Chebyshev, 5e7 events, 9 free parameters
     log("c3: generating 5e7 events")
     w = datagen.workload(3)

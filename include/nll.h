@@ -73,12 +73,19 @@ typedef enum nll_status {
  *              sigma > 0, alpha > 0, n > 1
  *   NLL_ARGUS  (m0, c)                g = x sqrt(u) exp(c u), u = 1 - (x/m0)^2 for
  *              x < m0, 0 above; m0 > observable lo >= 0
+ *   NLL_JOHNSON (mu, lambda, gamma, delta)  Johnson's S_U family (one of the
+ *              built-in densities of Sec. 3): g = exp(-u^2/2) / sqrt(1 + z^2),
+ *              z = (x-mu)/lambda, u = gamma + delta asinh(z); lambda > 0,
+ *              delta > 0; closed-form normalisation through the substitution
+ *              u(x), under which the density is a Gaussian in u
  * Composite nodes:
  *   NLL_SUM    params (f_1 .. f_{k-1}) over k >= 2 children on the same
  *              observables: p = sum_{j<k} f_j p_j + (1 - sum f) p_k,
  *              f_j in [0, 1], sum f <= 1
  *   NLL_PROD   no params; children on disjoint observables: p = prod p_d   */
-enum nll_node_kind { NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7 };
+enum nll_node_kind {
+  NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7, NLL_JOHNSON = 8
+};
 
 /* Normalisation of a leaf over its observable range [lo, hi]:
  *   NLL_NORM_ANALYTIC      closed form (Sec. 3 "Analytic Integrals")

@@ -31,6 +31,7 @@ static const std::vector<VariantOps>& registry() {
     register_variants_2d(reg);
     register_variants_fp32c_1d(reg);
     register_variants_fp32c_2d(reg);
+    register_variants_johnson(reg);
   });
   return reg;
 }
@@ -87,11 +88,12 @@ int expected_params(int kind, int np) {
     case NLL_CHEB: return (np >= 1 && np <= 8) ? np : -1;
     case NLL_CB: return 4;
     case NLL_ARGUS: return 2;
+    case NLL_JOHNSON: return 4;
     default: return -1;
   }
 }
 
-bool is_leaf(int kind) { return kind >= NLL_GAUSS && kind <= NLL_ARGUS; }
+bool is_leaf(int kind) { return (kind >= NLL_GAUSS && kind <= NLL_ARGUS) || kind == NLL_JOHNSON; }
 
 // ---------------------------------------------------------------------------
 // lowering: graph -> sum of products of leaves

@@ -20,6 +20,8 @@
 //   CrystalBall(m0,s,a,n)   g = exp(-t^2/2) for t > -a, A (B - t)^-n below,
 //                           A = (n/a)^n e^{-a^2/2}, B = n/a - a
 //   Argus(m0, c)            g = m sqrt(u) e^{c u}, u = 1 - (m/m0)^2, m < m0
+//   Johnson(mu,lam,gam,del) g = e^{-u^2/2} / sqrt(1 + z^2), z = (x - mu)/lam,
+//                           u = gam + del asinh(z)   (Johnson's S_U family)
 // Selects are branch-free (both sides computed, one kept, as in Sec. 5.3)
 // where both sides are cheap; the Crystal Ball's rare power-law tail is a
 // real branch, which a 64-lane wavefront skips when none of its events is
@@ -692,6 +694,166 @@ struct ArgusLeaf {
       if (c.dm0 != 0.0) d0 = (float)(fma(0.5, (double)rcp_f32(us), c.c) * (x * x) * c.dm0);
       phi[0] = in ? d0 : 0.0f;
       phi[1] = in ? us : 0.0f;
+    }
+  }
+};
+
+// ------------------------------------------------------------------------
+// Johnson S_U; linear (its factor 1/sqrt(1 + z^2) kept out of the log)
+// ------------------------------------------------------------------------
+// log g = -u^2/2 - ln sqrt(1 + z^2).  With s = sqrt(1 + z^2) and
+// A = asinh z = sign(z) ln(|z| + s):
+//   d log g/dmu     = w / lam,   w = u del / s + z / s^2
+//   d log g/dlam    = w z / lam
+//   d log g/dgam    = -u
+//   d log g/ddel    = -u A
+// Normalisation: u = gam + del asinh(z) maps g dx to (lam/del) e^{-u^2/2} du,
+// so Z = (lam/del) sqrt(pi/2) [erf(u_hi/sqrt2) - erf(u_lo/sqrt2)]; dZ from
+// the prefactor and the limits u_lo, u_hi.
+struct JohnsonLeaf {
+  static constexpr int kKind = kJohnson;
+  static constexpr int NP = 4;
+  static constexpr bool kLinear = true;
+  struct C {
+    double mu, il, ga, de;
+  };
+  __device__ static bool valid(const double* p) { return p[1] > 0.0 && p[3] > 0.0; }
+  __device__ static void consts(const double* p, LeafSetup& s) {
+    const double il = 1.0 / p[1];
+    s.ec[0] = p[0];
+    s.ec[1] = il;
+    s.ec[2] = p[2];
+    s.ec[3] = p[3];
+    s.fscale[0] = il;
+    s.fscale[1] = il;
+    s.fscale[2] = -1.0;
+    s.fscale[3] = -1.0;
+  }
+  // the limits in u-space and what dZ needs of them
+  struct Limits {
+    double zl, zh, Al, Ah, ul, uh, sl, sh;
+  };
+  __device__ static Limits limits(const double* p, double lo, double hi) {
+    Limits b;
+    const double il = 1.0 / p[1];
+    b.zl = (lo - p[0]) * il;
+    b.zh = (hi - p[0]) * il;
+    b.Al = asinh(b.zl);
+    b.Ah = asinh(b.zh);
+    b.ul = fma(p[3], b.Al, p[2]);
+    b.uh = fma(p[3], b.Ah, p[2]);
+    b.sl = sqrt(fma(b.zl, b.zl, 1.0));
+    b.sh = sqrt(fma(b.zh, b.zh, 1.0));
+    return b;
+  }
+  __device__ static void finish(const double* p, const Limits& b, double span, double el, double eh,
+                                LeafSetup& s) {
+    const double k = p[1] / p[3];
+    s.Z = k * kSqrtPiOver2 * span;
+    s.dZ[0] = el / b.sl - eh / b.sh;
+    s.dZ[1] = s.Z / p[1] + b.zl * el / b.sl - b.zh * eh / b.sh;
+    s.dZ[2] = k * (eh - el);
+    s.dZ[3] = -s.Z / p[3] + k * (b.Ah * eh - b.Al * el);
+  }
+  __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
+    consts(p, s);
+    if (!analytic) return;
+    const Limits b = limits(p, lo, hi);
+    finish(p, b, erf_span(b.ul, b.uh), exp(-0.5 * b.ul * b.ul), exp(-0.5 * b.uh * b.uh), s);
+  }
+  // setup() over 4 lanes, as the Gaussian's: the two error-function values
+  // and the two boundary exponentials each on a lane of their own (same
+  // operations, same bits); complete on lane 0.
+  static constexpr int kSetupLanes = 4;
+  __device__ static void setup_coop(const double* p, double lo, double hi, bool analytic, LeafSetup& s, int lane) {
+    consts(p, s);
+    if (!analytic) return;
+    const Limits b = limits(p, lo, hi);
+    double v;
+    if (lane >= 2) {
+      const double t = lane == 2 ? b.ul : b.uh;
+      v = exp(-0.5 * t * t);
+    } else if (b.ul >= 0.0) {
+      v = erfc((lane ? b.uh : b.ul) * kInvSqrt2);
+    } else if (b.uh <= 0.0) {
+      v = erfc((lane ? -b.ul : -b.uh) * kInvSqrt2);
+    } else {
+      v = erf((lane ? b.ul : b.uh) * kInvSqrt2);
+    }
+    const int base = (int)(threadIdx.x & 63) - lane;
+    const double u0 = __shfl(v, base, 64), u1 = __shfl(v, base + 1, 64);
+    const double el = __shfl(v, base + 2, 64), eh = __shfl(v, base + 3, 64);
+    finish(p, b, u0 - u1, el, eh, s);
+  }
+  __device__ static double shape(const double* p, double, double, double x, double* dg) {
+    const double z = (x - p[0]) / p[1];
+    const double q = fma(z, z, 1.0), sq = sqrt(q);
+    const double A = asinh(z);
+    const double u = fma(p[3], A, p[2]);
+    const double g = exp(-0.5 * u * u) / sq;
+    const double w = u * p[3] / sq + z / q;
+    dg[0] = g * w / p[1];
+    dg[1] = g * w * z / p[1];
+    dg[2] = -g * u;
+    dg[3] = -g * u * A;
+    return g;
+  }
+  __device__ static C load(const double* ec) { return C{ec[0], ec[1], ec[2], ec[3]}; }
+  // LIN: lam = -u^2/2 and the linear factor 1/s; else the log of both.
+  template <bool GRAD, bool LIN = false>
+  __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
+    const double z = (x - c.mu) * c.il;
+    const double q = fma(z, z, 1.0);  // >= 1
+    const double s = sqrt_pos(q);
+    const double a = log_pos(fabs(z) + s);  // asinh |z|; the argument is >= 1
+    const double A = copysign(a, z);
+    const double u = fma(c.de, A, c.ga);
+    const double r = rcp_full(s);
+    if (LIN) {
+      lam = -0.5 * u * u;
+      gam = r;
+    } else {
+      lam = fma(-0.5, log_pos(q), -0.5 * u * u);
+      gam = 1.0;
+    }
+    if (GRAD) {
+      const double w = fma(u * c.de, r, z * (r * r));
+      phi[0] = w;
+      phi[1] = w * z;
+      phi[2] = u;
+      phi[3] = u * A;
+    }
+  }
+  // FP32 pass: x - mu in FP64, z, the square root, logarithm and reciprocal
+  // in single precision; u = gam + del A (a per-point constant added) and
+  // u^2 in FP64.
+  struct C32 {
+    double mu, ga, de;
+    F2 il;
+  };
+  __device__ static C32 load32(const double* ec) { return C32{ec[0], ec[2], ec[3], split2(ec[1])}; }
+  template <bool GRAD, bool LIN = false>
+  __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
+    const float z = mul2((float)(x - c.mu), c.il);
+    const float q = fmaf(z, z, 1.0f);
+    const float s = sqrt_f32(q);
+    const float A = copysignf(log_f32(fabsf(z) + s), z);
+    const double u64 = fma(c.de, (double)A, c.ga);
+    const float r = rcp_f32(s);
+    if (LIN) {
+      lam = (float)(-0.5 * u64 * u64);
+      gam = r;
+    } else {
+      lam = (float)fma(-0.5, (double)log_f32(q), -0.5 * u64 * u64);
+      gam = 1.0f;
+    }
+    if (GRAD) {
+      const float u = (float)u64;
+      const float w = fmaf((float)(u64 * c.de), r, z * (r * r));
+      phi[0] = w;
+      phi[1] = w * z;
+      phi[2] = u;
+      phi[3] = u * A;
     }
   }
 };

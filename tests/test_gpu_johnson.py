@@ -1,0 +1,194 @@
+"""GPU parity of the Johnson S_U leaf (Sec. 3) against the oracle: alone
+and as the peak of a mixture over an exponential background, with
+closed-form and Gauss-Legendre normalisation, ragged event counts, every
+unroll, the gradient-descent and BHHH minimisers, many datasets and the
+FP32-compensated pass.
+
+Tolerances as for the other leaves: NLL 1e-12 relative, gradient 1e-8 of
+max(|g|, G) with G the largest per-parameter sum of |d l_i/d theta|;
+fitted points 1e-9 relative; the FP32-compensated pass as in its own tests.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+NLL_TOL = 1e-12
+GRAD_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def nllmi():
+    import paper_2003_12875_amd as m
+    m.lib()
+    return m
+
+
+def to_dev(torch, cols):
+    return [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in cols]
+
+
+def check(torch, nllmi, spec, cols, points, threads, unroll=None, variant=None):
+    m = nllmi.Model.from_spec(spec)
+    if variant:
+        assert m.info["variant"] == variant, m.info
+    m.set_data(to_dev(torch, cols))
+    if unroll:
+        m.set_schedule(unroll=unroll)
+    o = oracle.Oracle(spec)
+    for th in points:
+        st, ref, gref, stats = o.nll(cols, th, threads=threads, stats=True)
+        assert st == 0
+        v, g = m.eval_grad(torch.from_numpy(np.ascontiguousarray(th)))
+        v, g = float(v.item()), g.cpu().numpy()
+        assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
+        err = np.max(np.abs(g - gref))
+        assert err <= GRAD_TOL * max(np.max(np.abs(gref)), np.max(stats[1:])), (th, g, gref)
+        v1 = float(m.eval(torch.from_numpy(np.ascontiguousarray(th))).item())
+        assert abs(v1 - ref) <= NLL_TOL * abs(ref), (th, v1, ref)
+    assert m.sync() == 0
+    return m
+
+
+@pytest.mark.parametrize("single", [True, False])
+@pytest.mark.parametrize("norm", ["analytic", "gl256"])
+@pytest.mark.parametrize("n", [1, 257, 100_003])
+def test_johnson_small(torch, nllmi, threads, single, norm, n):
+    w = datagen.johnson_workload(n, single=single, n_points=3, norm=norm)
+    print(f"[johnson single={single} {norm} n={n}]", flush=True)
+    check(torch, nllmi, w["spec"], w["cols"], w["points"], threads,
+          variant="johnson" if single else "johnson+exp")
+
+
+def test_johnson_mixture_full(torch, nllmi, threads):
+    """The benchmarked size: 1e7 events."""
+    w = datagen.johnson_workload(n_points=2)
+    print("[johnson+exp n=1e7]", flush=True)
+    check(torch, nllmi, w["spec"], w["cols"], w["points"], threads)
+
+
+@pytest.mark.parametrize("unroll", [2, 4, 8])
+def test_johnson_every_unroll(torch, nllmi, threads, unroll):
+    w = datagen.johnson_workload(4097 * 5 + 13, n_points=2)
+    print(f"[johnson unroll={unroll}]", flush=True)
+    check(torch, nllmi, w["spec"], w["cols"], w["points"], threads, unroll=unroll)
+
+
+def test_johnson_far_tails_and_range_edges(torch, nllmi, threads):
+    """Events at the range edges and deep in both tails (|z| up to 1e3), a
+    range lying wholly in the right tail, and z = 0 exactly."""
+    spec = {"obs": [{"name": "x", "lo": -500.0, "hi": 1000.0}],
+            "params": [datagen.param("mu", 0.0, -5, 5), datagen.param("lambda", 1.0, 0.1, 5),
+                       datagen.param("gamma", -0.3, -5, 5), datagen.param("delta", 0.6, 0.1, 10)],
+            "nodes": [{"kind": "johnson", "obs": 0, "params": [0, 1, 2, 3]}], "root": 0}
+    x = datagen.generate(spec, 20_000, seed=31)[0]
+    x[:6] = [-500.0, 1000.0, 0.0, 1e-12, -1e-12, 999.999]
+    pts = [datagen.theta_of(spec), np.array([0.0, 1.0, -0.3, 0.6])]
+    check(torch, nllmi, spec, [x], pts, threads)
+    tail = {"obs": [{"name": "x", "lo": 5.0, "hi": 30.0}], "params": spec["params"], "nodes": spec["nodes"],
+            "root": 0}
+    xt = datagen.generate(tail, 5_000, seed=32)[0]
+    check(torch, nllmi, tail, [xt], pts, threads)
+
+
+def test_johnson_parameter_checks(torch, nllmi):
+    """lambda <= 0 or delta <= 0 inside the parameters' boxes: the density
+    check (Sec. 3) flags the point; the value is +inf and the status reads
+    NLL_ERR_PARAM_RANGE once."""
+    w = datagen.johnson_workload(1000, single=True, n_points=1)
+    spec = datagen.johnson_single_spec()
+    spec["params"][1]["lo"] = -1.0
+    spec["params"][3]["lo"] = -1.0
+    m = nllmi.Model.from_spec(spec)
+    m.set_data(to_dev(torch, w["cols"]))
+    for k, v in ((1, 0.0), (1, -0.01), (3, 0.0), (3, -0.5)):
+        th = datagen.theta_of(spec)
+        th[k] = v
+        val = m.eval(torch.from_numpy(th))
+        assert math.isinf(val.item())
+        assert m.sync() == -3
+        assert m.sync() == 0
+    val = m.eval(torch.from_numpy(datagen.theta_of(spec)))
+    assert math.isfinite(val.item()) and m.sync() == 0
+
+
+def test_johnson_fit_matches_oracle(torch, nllmi, threads):
+    w = datagen.johnson_workload(200_000, n_points=1)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    th0 = w["points"][0]
+    print("[johnson gd fit]", flush=True)
+    th, nll, g, status = m.fit(torch.from_numpy(th0), 30, 1.0)
+    st, th_o, nll_o, g_o, eta_o = oracle.Oracle(w["spec"]).gd_fit(w["cols"], th0, 30, 1.0, threads=threads)
+    assert status.item() == 0 and st == 0
+    np.testing.assert_allclose(th.cpu().numpy(), th_o, rtol=1e-9)
+    assert abs(nll.item() - nll_o) <= NLL_TOL * abs(nll_o)
+
+
+def test_johnson_bhhh(torch, nllmi, threads):
+    """The Johnson peak alone has four score features: the BHHH pass and
+    minimiser are compiled for it."""
+    w = datagen.johnson_workload(150_001, single=True, n_points=2)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    o = oracle.Oracle(w["spec"])
+    for th in w["points"]:
+        st, ref, gref, Bref = o.nll_bhhh(w["cols"], th, threads=threads)
+        v, g, B = m.eval_bhhh(torch.from_numpy(th))
+        assert abs(v.item() - ref) <= NLL_TOL * abs(ref)
+        B = B.cpu().numpy()
+        assert np.max(np.abs(B - Bref)) <= 1e-10 * np.max(np.abs(Bref)), (B, Bref)
+    print("[johnson bhhh fit]", flush=True)
+    th0 = w["points"][0]
+    out = m.fit_bhhh(torch.from_numpy(th0), 15, 1e-3)
+    st, th_o, nll_o, g_o, lam_o = o.bhhh_fit(w["cols"], th0, 15, 1e-3, threads=threads)
+    assert out[3].item() == 0 and st == 0
+    np.testing.assert_allclose(out[0].cpu().numpy(), th_o, rtol=1e-9)
+    _, _, _, stats = o.nll(w["cols"], th_o, threads=threads, stats=True)
+    assert np.max(np.abs(out[2].cpu().numpy()) / stats[1:]) < 1e-6
+
+
+def test_johnson_many_datasets(torch, nllmi, threads):
+    """Batched evaluation over 40 Johnson datasets of ragged sizes (some
+    empty) at per-set points equals the oracle per set."""
+    spec = datagen.johnson_single_spec()
+    sizes = datagen.toy_sizes(40, datagen.JOHNSON_SEED, 0, 9000)
+    offsets = np.zeros(41, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    truths = datagen.jittered_points(datagen.theta_of(spec), 40, datagen.JOHNSON_SEED + 2,
+                                     widths=datagen.jitter_widths(spec))
+    cols = datagen.generate_sets(spec, truths, offsets, datagen.JOHNSON_SEED, 5 << 32, threads=threads)
+    o = oracle.Oracle(spec)
+    st, ref, gref, _ = o.nll_batched(cols, offsets, truths, threads=threads)
+    m = nllmi.Model.from_spec(spec)
+    m.set_data(to_dev(torch, cols))
+    m.set_schedule(tile_events=2048)
+    nll, g, status = m.eval_batched(torch.from_numpy(offsets), torch.from_numpy(truths))
+    nll, g = nll.cpu().numpy(), g.cpu().numpy()
+    assert np.all(status.cpu().numpy() == 0)
+    for s in range(40):
+        assert abs(nll[s] - ref[s]) <= NLL_TOL * max(1.0, abs(ref[s])), (s, nll[s], ref[s])
+        a, b = offsets[s], offsets[s + 1]
+        G = np.max(o.nll([cols[0][a:b]], truths[s], stats=True)[3][1:]) if b > a else 0.0
+        assert np.max(np.abs(g[s] - gref[s])) <= GRAD_TOL * max(1.0, np.max(np.abs(gref[s])), G), s
+    assert math.isfinite(float(nll.sum()))
+
+
+def test_johnson_fp32c(torch, nllmi, threads):
+    from test_gpu_fp32c import compare
+    w = datagen.johnson_workload(300_001, n_points=2)
+    print("[johnson+exp fp32c]", flush=True)
+    compare(torch, nllmi, w["spec"], w["cols"], w["points"], threads, against_fp64=True, report=True)

@@ -325,6 +325,8 @@ SINGLE_LEAVES = [
     ("argus", [("m0", 1.0, 0.96, 1.2), ("c", -6.0, -50, 0)], 0.2, 0.99),
     ("cheb", [("a1", 0.2, -1, 1), ("a2", -0.1, -1, 1)], 1.0, 3.0),
     ("cheb", [("a1", 0.1, -1, 1), ("a2", -0.2, -1, 1), ("a3", 0.05, -1, 1), ("a4", 0.1, -1, 1)], -1.0, 1.0),
+    ("johnson", [("mu", 0.3, -3, 3), ("lambda", 0.9, 0.1, 5), ("gamma", 0.6, -5, 5), ("delta", 0.8, 0.1, 10)],
+     -8.0, 12.0),
 ]
 
 
