@@ -16,7 +16,8 @@ are not given): a wide Gaussian, a Gaussian-plus-exponential mixture, a
 2-D Crystal Ball / ARGUS mixture times a Chebyshev series, batched toy
 datasets of the Gaussian, and the mixture at 1e8 events.  A sixth, a
 Johnson S_U peak over an exponential background, exercises the Johnson
-density the paper adds to the built-in ones (Sec. 3).
+density the paper adds to the built-in ones (Sec. 3), and a seventh, one
+chi-square density, the "ChiSquarePdf" entry of its speed-up figure.
 """
 from __future__ import annotations
 
@@ -31,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdatagen.so")
 
 MASTER_SEED = 2003012875
-KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8}
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9}
 
 
 def build() -> str:
@@ -149,6 +150,15 @@ def johnson_single_spec(mu=5.28, lam=0.02, gam=-0.5, delta=1.5, lo=5.0, hi=5.6, 
     s = johnson_spec(mu=mu, lam=lam, gam=gam, delta=delta, lo=lo, hi=hi, norm=norm)
     return {"obs": s["obs"], "params": s["params"][1:5],
             "nodes": [{"kind": "johnson", "obs": 0, "params": [0, 1, 2, 3], "norm": norm}], "root": 0}
+
+
+def chi2_spec(nu=5.0, lo=0.0, hi=40.0, norm="analytic"):
+    """One chi-square density with nu degrees of freedom on x in [0, 40]
+    (the "ChiSquarePdf" model of the paper's speed-up figure)."""
+    return {"obs": [{"name": "x", "lo": lo, "hi": hi}],
+            "params": [param("nu", nu, 0.1, 200.0)],
+            "nodes": [{"kind": "chi2", "obs": 0, "params": [0], "norm": norm}],
+            "root": 0}
 
 
 def cheb_coefficients(seed: int, order: int = 4, lo: float = -1.0, hi: float = 1.0,
@@ -346,6 +356,19 @@ def johnson_workload(n: int = 10_000_000, single: bool = False, n_points: int = 
     cols = generate(spec, n, JOHNSON_SEED, threads=threads)
     return {"spec": spec, "cols": cols, "n": n, "theta": theta_of(spec),
             "points": parameter_points(spec, n_points, JOHNSON_SEED + 1), "seed": JOHNSON_SEED}
+
+
+CHI2_SEED = MASTER_SEED + 7000
+
+
+def chi2_workload(n: int = 10_000_000, n_points: int = 8, threads: int | None = None,
+                  norm: str = "analytic") -> dict:
+    """chi2_spec() with n events: data seed master + 7000, parameter-point
+    seed one more."""
+    spec = chi2_spec(norm=norm)
+    cols = generate(spec, n, CHI2_SEED, threads=threads)
+    return {"spec": spec, "cols": cols, "n": n, "theta": theta_of(spec),
+            "points": parameter_points(spec, n_points, CHI2_SEED + 1), "seed": CHI2_SEED}
 
 
 def toys_workload(n_sets: int = 4096, size_lo: int = 1000, size_hi: int = 200000,

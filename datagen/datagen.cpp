@@ -86,7 +86,7 @@ struct EventRng {
 extern "C" {
 
 typedef struct dg_node {
-  int32_t kind; /* 1 gauss, 2 exp, 3 cheb, 4 cb, 5 argus, 6 sum, 7 prod, 8 johnson */
+  int32_t kind; /* 1 gauss, 2 exp, 3 cheb, 4 cb, 5 argus, 6 sum, 7 prod, 8 johnson, 9 chi2 */
   int32_t obs;
   int32_t n_param;
   double p[8]; /* parameter VALUES (truth) */
@@ -125,6 +125,37 @@ double sample_johnson(EventRng& r, double mu, double la, double ga, double de, d
     double u1 = r.u01_open0(), u2 = r.u01();
     double n = std::sqrt(-2.0 * std::log(u1)) * std::cos(kTwoPi * u2);
     double x = mu + la * std::sinh((n - ga) / de);
+    if (x >= lo && x <= hi) return x;
+  }
+  return std::nan("");
+}
+
+/* standard normal by Box-Muller (one of the pair) */
+double normal01(EventRng& r) {
+  double u1 = r.u01_open0(), u2 = r.u01();
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(kTwoPi * u2);
+}
+
+/* Gamma(k, 1) by Marsaglia and Tsang's squeeze method (k >= 1); for k < 1
+ * Gamma(k + 1) U^(1/k). */
+double sample_gamma(EventRng& r, double k) {
+  if (k < 1.0) return sample_gamma(r, k + 1.0) * std::pow(r.u01_open0(), 1.0 / k);
+  double d = k - 1.0 / 3.0, c = 1.0 / std::sqrt(9.0 * d);
+  for (int t = 0; t < kMaxTries; ++t) {
+    double n = normal01(r);
+    double v = 1.0 + c * n;
+    if (v <= 0.0) continue;
+    v = v * v * v;
+    double u = r.u01_open0();
+    if (std::log(u) < 0.5 * n * n + d - d * v + d * std::log(v)) return d * v;
+  }
+  return std::nan("");
+}
+
+/* chi-square with nu degrees of freedom = 2 Gamma(nu/2, 1), kept when in [lo, hi] */
+double sample_chi2(EventRng& r, double nu, double lo, double hi) {
+  for (int t = 0; t < kMaxTries; ++t) {
+    double x = 2.0 * sample_gamma(r, 0.5 * nu);
     if (x >= lo && x <= hi) return x;
   }
   return std::nan("");
@@ -224,6 +255,9 @@ void sample_node(const dg_model& m, int i, EventRng& r, double* x) {
       return;
     case 8:
       x[nd.obs] = sample_johnson(r, nd.p[0], nd.p[1], nd.p[2], nd.p[3], lo, hi);
+      return;
+    case 9:
+      x[nd.obs] = sample_chi2(r, nd.p[0], lo, hi);
       return;
   }
 }

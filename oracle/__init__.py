@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 MAX_OBS, MAX_PAR, MAX_NODE, NODE_PAR, NODE_CHILD = 4, 32, 16, 8, 8
 
-KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8}
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9}
 NORM = {"analytic": 0, "gl256": 1, "gl256_single": 2}
 
 OK, E_ARG, E_UNSUPPORTED, E_PARAM, E_DOMAIN, E_PDF = 0, -1, -2, -3, -4, -5

@@ -211,6 +211,19 @@ double g_johnson(const orc_node& nd, const double* th, double x, double* dg) {
   return g;
 }
 
+/* Chi-square with nu degrees of freedom (the "ChiSquarePdf" of Sec. 5.2's
+ * benchmark): g = x^(nu/2 - 1) e^(-x/2) for x > 0; dg/dnu = g ln(x)/2. */
+double g_chi2(const orc_node& nd, const double* th, double x, double* dg) {
+  double nu = P(th, nd, 0);
+  if (!(x >= 0.0)) {
+    if (dg) dg[0] = 0.0;
+    return 0.0;
+  }
+  double g = std::pow(x, 0.5 * nu - 1.0) * std::exp(-0.5 * x); /* at x = 0: 0, 1 or inf */
+  if (dg) dg[0] = 0.5 * g * std::log(x);
+  return g;
+}
+
 double leaf_g(const orc_model& m, const orc_node& nd, const double* th, double x, double* dg) {
   switch (nd.kind) {
     case ORC_GAUSS: return g_gauss(nd, th, x, dg);
@@ -219,6 +232,7 @@ double leaf_g(const orc_model& m, const orc_node& nd, const double* th, double x
     case ORC_CB: return g_cb(nd, th, x, dg);
     case ORC_ARGUS: return g_argus(nd, th, x, dg);
     case ORC_JOHNSON: return g_johnson(nd, th, x, dg);
+    case ORC_CHI2: return g_chi2(nd, th, x, dg);
   }
   return std::nan("");
 }
@@ -402,6 +416,50 @@ void norm_johnson_closed(double mu, double la, double ga, double de, double lo, 
   d[3] = -z / de + k * (Ah * eh - Al * el);
 }
 
+/* Lower incomplete gamma function gamma(k, y) = int_0^y t^(k-1) e^(-t) dt
+ * and its derivative in k, from the series
+ *   gamma(k, y) = y^k e^(-y) sum_{n>=0} y^n / (k (k+1) ... (k+n))
+ * (all terms positive); differentiating each term in k gives
+ *   d gamma/dk = gamma ln y - y^k e^(-y) sum_n t_n H_n,
+ * t_n the n-th term, H_n = sum_{j=0..n} 1/(k+j).  y^k e^(-y) is formed as
+ * exp(k ln y - y) after the sum, so that y up to ~700 neither over- nor
+ * underflows.  gamma(k, 0) = 0 and its k-derivative is 0 (k > 0). */
+void lower_gamma(double k, double y, double* g, double* dg) {
+  *g = 0.0;
+  *dg = 0.0;
+  if (!(y > 0.0)) return;
+  Neumaier S, D;
+  double t = 1.0 / k, H = 1.0 / k;
+  for (int n = 0; n < 100000; ++n) {
+    S.add(t);
+    D.add(t * H);
+    if (n > y && t < 1e-19 * S.value()) break;
+    t *= y / (k + n + 1);
+    H += 1.0 / (k + n + 1);
+  }
+  double pre = std::exp(k * std::log(y) - y);
+  *g = pre * S.value();
+  *dg = *g * std::log(y) - pre * D.value();
+}
+
+/* Chi-square over [lo, hi], lo >= 0: with x = 2t and k = nu/2,
+ *   Z = int x^(k-1) e^(-x/2) dx = 2^k [gamma(k, hi/2) - gamma(k, lo/2)],
+ *   dZ/dnu = (1/2) dZ/dk = (1/2) { ln2 Z + 2^k [gamma'(k, hi/2) - gamma'(k, lo/2)] }
+ * (gamma' the k-derivative).  Both ends are evaluated separately, so a
+ * range that starts deep in the upper tail loses digits to cancellation;
+ * there the Gauss-Legendre rule (the integrand is analytic for lo > 0) is
+ * the accurate choice. */
+void norm_chi2_closed(double nu, double lo, double hi, double* Z, double* d) {
+  double k = 0.5 * nu;
+  double ga, dga, gb, dgb;
+  lower_gamma(k, 0.5 * lo, &ga, &dga);
+  lower_gamma(k, 0.5 * hi, &gb, &dgb);
+  double p2 = std::exp2(k);
+  double z = p2 * (gb - ga);
+  *Z = z;
+  d[0] = 0.5 * (std::log(2.0) * z + p2 * (dgb - dga));
+}
+
 /* 256-point Gauss-Legendre on [a, b] of g and dg (np local derivatives). */
 void gl_panel(const orc_model& m, const orc_node& nd, const double* th, double a, double b,
               double* Z, double* d) {
@@ -436,6 +494,23 @@ void gl_argus_subst(const orc_node& nd, const double* th, double lo, double hi, 
   }
 }
 
+/* Chi-square on [0, hi] after x = s^2 (dx = 2 s ds): the integrand
+ * 2 s^(nu-1) e^(-s^2/2) is a polynomial times a Gaussian for integer nu
+ * (and smooth enough for 256 nodes to reach double precision for
+ * nu >~ 3 otherwise); dg/dnu = g ln s. */
+void gl_chi2_subst(const orc_node& nd, const double* th, double hi, double* Z, double* d) {
+  double nu = P(th, nd, 0);
+  const Rule& r = rule256();
+  double sb = std::sqrt(hi);
+  double h = 0.5 * sb, cc = 0.5 * sb;
+  for (size_t i = 0; i < r.x.size(); ++i) {
+    double sv = cc + h * r.x[i];
+    double g = 2.0 * std::pow(sv, nu - 1.0) * std::exp(-0.5 * sv * sv);
+    *Z += h * r.w[i] * g;
+    d[0] += h * r.w[i] * g * std::log(sv);
+  }
+}
+
 /* Z and dZ (local parameter order) of one leaf. */
 void leaf_norm_local(const orc_model& m, const orc_node& nd, const double* th, double* Z,
                      double* d) {
@@ -454,6 +529,7 @@ void leaf_norm_local(const orc_model& m, const orc_node& nd, const double* th, d
       case ORC_JOHNSON:
         norm_johnson_closed(P(th, nd, 0), P(th, nd, 1), P(th, nd, 2), P(th, nd, 3), lo, hi, Z, d);
         return;
+      case ORC_CHI2: norm_chi2_closed(P(th, nd, 0), lo, hi, Z, d); return;
     }
     return;
   }
@@ -476,6 +552,10 @@ void leaf_norm_local(const orc_model& m, const orc_node& nd, const double* th, d
     gl_argus_subst(nd, th, lo, hi, Z, d);
     return;
   }
+  if (nd.kind == ORC_CHI2 && lo == 0.0) {
+    gl_chi2_subst(nd, th, hi, Z, d);
+    return;
+  }
   gl_panel(m, nd, th, lo, hi, Z, d);
 }
 
@@ -492,11 +572,12 @@ int expected_params(const orc_node& nd) {
     case ORC_SUM: return nd.n_child - 1;
     case ORC_PROD: return 0;
     case ORC_JOHNSON: return 4;
+    case ORC_CHI2: return 1;
   }
   return -1;
 }
 
-bool is_leaf(int kind) { return (kind >= ORC_GAUSS && kind <= ORC_ARGUS) || kind == ORC_JOHNSON; }
+bool is_leaf(int kind) { return (kind >= ORC_GAUSS && kind <= ORC_ARGUS) || kind == ORC_JOHNSON || kind == ORC_CHI2; }
 
 /* Bit mask of observables a node depends on. */
 unsigned obs_mask(const orc_model& m, int i) {
@@ -516,7 +597,7 @@ int check_model(const orc_model& m) {
     if (!(m.lo[o] < m.hi[o])) return ORC_E_ARG;
   for (int i = 0; i < m.n_node; ++i) {
     const orc_node& nd = m.node[i];
-    if (nd.kind < ORC_GAUSS || nd.kind > ORC_JOHNSON) return ORC_E_ARG;
+    if (nd.kind < ORC_GAUSS || nd.kind > ORC_CHI2) return ORC_E_ARG;
     if (nd.n_param < 0 || nd.n_param > ORC_NODE_PAR) return ORC_E_ARG;
     if (expected_params(nd) != nd.n_param) return ORC_E_ARG;
     for (int k = 0; k < nd.n_param; ++k)
@@ -525,6 +606,7 @@ int check_model(const orc_model& m) {
       if (nd.obs < 0 || nd.obs >= m.n_obs || nd.n_child != 0) return ORC_E_ARG;
       if (nd.norm < ORC_NORM_CLOSED || nd.norm > ORC_NORM_GL_SINGLE) return ORC_E_ARG;
       if (nd.kind == ORC_ARGUS && m.lo[nd.obs] < 0.0) return ORC_E_UNSUPPORTED;
+      if (nd.kind == ORC_CHI2 && (m.lo[nd.obs] < 0.0 || m.hi[nd.obs] > 1000.0)) return ORC_E_UNSUPPORTED;
     } else {
       if (nd.n_child < (nd.kind == ORC_SUM ? 2 : 1) || nd.n_child > ORC_NODE_CHILD)
         return ORC_E_ARG;
@@ -570,6 +652,9 @@ int check_params(const orc_model& m, const double* th) {
         break;
       case ORC_JOHNSON:
         if (!(P(th, nd, 1) > 0.0) || !(P(th, nd, 3) > 0.0)) return ORC_E_PARAM;
+        break;
+      case ORC_CHI2:
+        if (!(P(th, nd, 0) > 0.0)) return ORC_E_PARAM;
         break;
       case ORC_SUM: {
         double f = 0.0;

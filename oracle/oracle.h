@@ -46,7 +46,8 @@ enum orc_kind {
   ORC_ARGUS = 5, /* params (m0, c), power 1/2                    */
   ORC_SUM = 6,   /* params (f_1..f_{k-1}) over k children         */
   ORC_PROD = 7,  /* no params; children on disjoint observables   */
-  ORC_JOHNSON = 8 /* params (mu, lambda, gamma, delta), S_U family */
+  ORC_JOHNSON = 8, /* params (mu, lambda, gamma, delta), S_U family */
+  ORC_CHI2 = 9     /* params (nu): g = x^(nu/2-1) e^(-x/2), 0 <= lo  */
 };
 
 enum orc_norm {

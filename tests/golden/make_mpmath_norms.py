@@ -4,7 +4,7 @@
 The shapes are the textbook densities the paper's models are built from
 (Sec. 3 and 5): Gaussian, exponential, Chebyshev series with unit T_0
 coefficient, Crystal Ball with a low-side power-law tail, ARGUS with power
-1/2, Johnson's S_U.  This script calls only mpmath; the stored numbers pin the closed
+1/2, Johnson's S_U, chi-square.  This script calls only mpmath; the stored numbers pin the closed
 forms and the Gauss-Legendre rules of both implementations.
 
     python tests/golden/make_mpmath_norms.py
@@ -30,6 +30,9 @@ CASES = [
     ("johnson", ["5.28", "0.02", "-0.5", "1.5"], "5.0", "5.6"),
     ("johnson", ["0", "1", "0.8", "0.7"], "-10", "10"),
     ("johnson", ["0", "1", "0", "1"], "5", "30"),
+    ("chi2", ["5"], "0", "40"),
+    ("chi2", ["3.5"], "0", "12"),
+    ("chi2", ["30"], "10", "60"),
 ]
 
 
@@ -70,6 +73,9 @@ def shape(kind, p, lo, hi):
             z = (x - mu) / la
             return mp.exp(-(ga + de * mp.asinh(z)) ** 2 / 2) / mp.sqrt(1 + z * z)
         return g, [mu]
+    if kind == "chi2":
+        (nu,) = p
+        return lambda x: x ** (nu / 2 - 1) * mp.exp(-x / 2), []
     raise ValueError(kind)
 
 

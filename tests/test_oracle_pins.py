@@ -57,6 +57,11 @@ def lib_logpdf(kind, params, lo, hi, x):
         # mass inside the range from the side whose tail the range is in
         mass = d.sf(lo) - d.sf(hi) if d.cdf(lo) > 0.5 else d.cdf(hi) - d.cdf(lo)
         return d.logpdf(x) - np.log(mass)
+    if kind == "chi2":
+        (nu,) = params
+        d = stats.chi2(nu)
+        mass = d.sf(lo) - d.sf(hi) if d.cdf(lo) > 0.5 else d.cdf(hi) - d.cdf(lo)
+        return d.logpdf(x) - np.log(mass)
     if kind == "cheb":
         coef = np.concatenate([[1.0], np.asarray(params, dtype=np.float64)])
         y = (2 * x - lo - hi) / (hi - lo)
@@ -85,6 +90,10 @@ LEAF_CASES = [
     ("johnson", (0.0, 1.0, 0.8, 0.7), -10.0, 10.0),  # heavy tails, truncated
     ("johnson", (2.0, 0.5, 2.0, 2.0), 0.0, 3.0),
     ("johnson", (0.0, 1.0, 0.0, 1.0), 5.0, 30.0),   # both limits in the right tail
+    ("chi2", (5.0,), 0.0, 40.0),
+    ("chi2", (3.5,), 0.0, 12.0),
+    ("chi2", (30.0,), 10.0, 60.0),
+    ("chi2", (3.0,), 0.5, 8.0),
 ]
 
 
@@ -96,6 +105,8 @@ def test_leaf_log_density_matches_library(kind, params, lo, hi, norm):
     top = min(hi, params[0]) if kind == "argus" else hi
     xs = np.concatenate([np.linspace(lo, top, 41)[:-1] if kind == "argus" else np.linspace(lo, hi, 41),
                          [lo + 0.37 * (top - lo), lo + 0.91 * (top - lo)]])
+    if kind == "chi2":
+        xs = xs[xs > 0.0]  # the density is 0 there (nu > 2)
     ref = lib_logpdf(kind, params, lo, hi, xs)
     got = np.array([o.log_density([x], params)[1] for x in xs])
     np.testing.assert_allclose(got, ref, rtol=0, atol=2e-12 * np.maximum(1.0, np.abs(ref)).max())
@@ -698,3 +709,57 @@ def test_johnson_parameter_checks():
     for bad in ((0.0, 0.0, 0.0, 1.0), (0.0, -1.0, 0.0, 1.0), (0.0, 1.0, 0.0, 0.0), (0.0, 1.0, 0.0, -2.0)):
         assert o.log_density([0.1], bad)[0] == E_PARAM
     assert o.log_density([0.1], (0.0, 1.0, 0.0, 1.0))[0] == OK
+
+
+# ---------------------------------------------------------------------------
+# chi-square (the ChiSquarePdf of Sec. 5.2's speed-up figure)
+# ---------------------------------------------------------------------------
+
+def test_chi2_two_dof_is_exponential():
+    """nu = 2: x^0 e^{-x/2}, the exponential with c = -1/2 (library truncexpon)."""
+    lo, hi = 0.0, 9.0
+    o = oracle.Oracle(single_leaf_spec("chi2", (2.0,), lo, hi))
+    xs = np.linspace(lo, hi, 19)
+    got = np.array([o.log_density([x], (2.0,))[1] for x in xs])
+    np.testing.assert_allclose(got, lib_logpdf("exp", (-0.5,), lo, hi, xs), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("nu", [0.7, 2.0, 5.0, 17.3, 120.0])
+def test_chi2_norm_is_scaled_lower_incomplete_gamma(nu):
+    """Z over [0, hi] = 2^{nu/2} Gamma(nu/2) P(nu/2, hi/2) with scipy's
+    regularised gamma P; dZ/dnu against a fourth-order central difference."""
+    from scipy import special
+    for hi in (0.3, 4.0, 40.0, 400.0):
+        o = oracle.Oracle(single_leaf_spec("chi2", (nu,), 0.0, hi))
+        st, Z, dZ = o.leaf_norm(0, (nu,))
+        assert st == OK
+        k = nu / 2
+        ref = math.exp(k * math.log(2.0) + special.gammaln(k)) * special.gammainc(k, hi / 2)
+        assert abs(Z - ref) <= 1e-13 * ref, (nu, hi, Z, ref)
+        h = 1e-3 * min(nu, 1.0)
+        z = lambda v: o.leaf_norm(0, (v,))[1]
+        fd = (z(nu - 2 * h) - 8 * z(nu - h) + 8 * z(nu + h) - z(nu + 2 * h)) / (12 * h)
+        assert abs(fd - dZ[0]) <= 1e-8 * max(abs(dZ[0]), Z), (nu, hi, fd, dZ)
+
+
+def test_chi2_range_checks():
+    """Observable ranges below 0 or beyond 1000 are not supported; nu <= 0 is
+    outside the density's parameter domain."""
+    for lo, hi in ((-1.0, 5.0), (0.0, 1000.5)):
+        with pytest.raises(ValueError):
+            oracle.Oracle(single_leaf_spec("chi2", (3.0,), lo, hi))
+    o = oracle.Oracle(single_leaf_spec("chi2", (3.0,), 0.0, 5.0))
+    assert o.log_density([1.0], (0.0,))[0] == E_PARAM
+    assert o.log_density([1.0], (-1.0,))[0] == E_PARAM
+
+
+def test_chi2_gradient_matches_central_differences():
+    w = datagen.chi2_workload(5000, n_points=2)
+    o = oracle.Oracle(w["spec"])
+    th = w["points"][1]
+    st, nll, g = o.nll(w["cols"], th)
+    assert st == OK
+    h = 1e-4
+    f = lambda v: o.nll(w["cols"], np.array([v]))[1]
+    fd = (f(th[0] - 2 * h) - 8 * f(th[0] - h) + 8 * f(th[0] + h) - f(th[0] + 2 * h)) / (12 * h)
+    assert abs(fd - g[0]) <= 50 * 2.2e-16 * abs(nll) / h + 1e-7 * abs(g[0]), (fd, g)
