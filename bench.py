@@ -379,6 +379,27 @@ def extras(torch, nllmi, datagen, args):
     ex["johnson_exp_1e7"] = res_j
     del m
     torch.cuda.empty_cache()
+    # chi-square (the ChiSquarePdf model of the paper's speed-up figure),
+    # 1e7 events: NLL+gradient, NLL alone, and damped BHHH to convergence
+    w = datagen.chi2_workload()
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(1, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: m.eval_grad(th, out=out, grad=g), 20)
+    tf = time_launches(torch, lambda: m.eval(th, out=out), 20)
+    bb = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.float64, device="cuda"),
+          torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.int32, device="cuda"))
+    m.fit_bhhh(th, 10, 1e-3, out=bb)
+    torch.cuda.synchronize()
+    t_bh = time_launches(torch, lambda: m.fit_bhhh(th, 10, 1e-3, out=bb), 3)
+    ex["chi2_1e7"] = {"variant": m.info["variant"], "n_events": w["n"], "eval_grad_ms": tg, "eval_ms": tf,
+                      "events_per_s": w["n"] / (tg * 1e-3), "achieved_GBs": 8.0 * w["n"] / (tg * 1e-3) / 1e9,
+                      "bhhh_10_steps_ms_per_step": t_bh / 10, "bhhh_status": int(bb[3].item()),
+                      "schedule": m.schedule}
+    del m
+    torch.cuda.empty_cache()
     # 2-D CB/ARGUS x Chebyshev, 5e7 events, 9 free parameters
     log("c3: generating 5e7 events")
     w = datagen.workload(3)

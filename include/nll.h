@@ -78,13 +78,19 @@ typedef enum nll_status {
  *              z = (x-mu)/lambda, u = gamma + delta asinh(z); lambda > 0,
  *              delta > 0; closed-form normalisation through the substitution
  *              u(x), under which the density is a Gaussian in u
+ *   NLL_CHI2   (nu)                   chi-square (the "ChiSquarePdf" model of
+ *              Sec. 5.2): g = x^(nu/2-1) exp(-x/2), nu > 0; the observable
+ *              range must lie in [0, 1000] (else NLL_ERR_UNSUPPORTED);
+ *              closed-form normalisation by the lower incomplete gamma
+ *              function, Gauss-Legendre after x = s^2 when lo = 0
  * Composite nodes:
  *   NLL_SUM    params (f_1 .. f_{k-1}) over k >= 2 children on the same
  *              observables: p = sum_{j<k} f_j p_j + (1 - sum f) p_k,
  *              f_j in [0, 1], sum f <= 1
  *   NLL_PROD   no params; children on disjoint observables: p = prod p_d   */
 enum nll_node_kind {
-  NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7, NLL_JOHNSON = 8
+  NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7, NLL_JOHNSON = 8,
+  NLL_CHI2 = 9
 };
 
 /* Normalisation of a leaf over its observable range [lo, hi]:

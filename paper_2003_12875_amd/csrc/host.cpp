@@ -32,6 +32,7 @@ static const std::vector<VariantOps>& registry() {
     register_variants_fp32c_1d(reg);
     register_variants_fp32c_2d(reg);
     register_variants_johnson(reg);
+    register_variants_chi2(reg);
   });
   return reg;
 }
@@ -89,11 +90,12 @@ int expected_params(int kind, int np) {
     case NLL_CB: return 4;
     case NLL_ARGUS: return 2;
     case NLL_JOHNSON: return 4;
+    case NLL_CHI2: return 1;
     default: return -1;
   }
 }
 
-bool is_leaf(int kind) { return (kind >= NLL_GAUSS && kind <= NLL_ARGUS) || kind == NLL_JOHNSON; }
+bool is_leaf(int kind) { return (kind >= NLL_GAUSS && kind <= NLL_ARGUS) || kind == NLL_JOHNSON || kind == NLL_CHI2; }
 
 // ---------------------------------------------------------------------------
 // lowering: graph -> sum of products of leaves
@@ -133,6 +135,7 @@ struct Lowering {
         if (expected_params(nd.kind, nd.n_param) != nd.n_param) return NLL_ERR_ARG;
         if (nd.norm < NLL_NORM_ANALYTIC || nd.norm > NLL_NORM_GL256_SINGLE) return NLL_ERR_ARG;
         if (nd.kind == NLL_ARGUS && D.obs_lo[nd.obs] < 0.0) return NLL_ERR_UNSUPPORTED;
+        if (nd.kind == NLL_CHI2 && (D.obs_lo[nd.obs] < 0.0 || D.obs_hi[nd.obs] > 1000.0)) return NLL_ERR_UNSUPPORTED;
         obs_mask[i] = 1u << nd.obs;
       } else if (nd.kind == NLL_SUM || nd.kind == NLL_PROD) {
         if (nd.kind == NLL_SUM && (nd.n_child < 2 || nd.n_param != nd.n_child - 1)) return NLL_ERR_ARG;

@@ -98,6 +98,7 @@ void register_variants_2d(std::vector<VariantOps>& out);
 void register_variants_fp32c_1d(std::vector<VariantOps>& out);
 void register_variants_fp32c_2d(std::vector<VariantOps>& out);
 void register_variants_johnson(std::vector<VariantOps>& out);
+void register_variants_chi2(std::vector<VariantOps>& out);
 
 hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
                            int64_t* tile_off, int* set_flag, WorkItem* items, hipStream_t st);

@@ -22,6 +22,7 @@
 //   Argus(m0, c)            g = m sqrt(u) e^{c u}, u = 1 - (m/m0)^2, m < m0
 //   Johnson(mu,lam,gam,del) g = e^{-u^2/2} / sqrt(1 + z^2), z = (x - mu)/lam,
 //                           u = gam + del asinh(z)   (Johnson's S_U family)
+//   ChiSquare(nu)           g = x^{nu/2 - 1} e^{-x/2}, 0 <= x
 // Selects are branch-free (both sides computed, one kept, as in Sec. 5.3)
 // where both sides are cheap; the Crystal Ball's rare power-law tail is a
 // real branch, which a 64-lane wavefront skips when none of its events is
@@ -855,6 +856,112 @@ struct JohnsonLeaf {
       phi[2] = u;
       phi[3] = u * A;
     }
+  }
+};
+
+// ------------------------------------------------------------------------
+// Chi-square with nu degrees of freedom
+// ------------------------------------------------------------------------
+// log g = (nu/2 - 1) ln x - x/2, d log g/dnu = ln(x)/2: one logarithm per
+// event.  Z over [lo, hi] (0 <= lo, hi <= 1000) = 2^k [gamma(k, hi/2) -
+// gamma(k, lo/2)] with k = nu/2 and the lower incomplete gamma function
+//   gamma(k, y) = y^k e^{-y} sum_n t_n,  t_n = y^n / (k (k+1) ... (k+n)),
+// whose k-derivative is gamma ln y - y^k e^{-y} sum_n t_n H_n with
+// H_n = sum_{j<=n} 1/(k+j); the terms are positive, so the partial sums
+// have no cancellation.  About y + 10 sqrt(y) + 20 terms.
+__device__ inline void lower_gamma_dk(double k, double y, double& g, double& dg) {
+  g = 0.0;
+  dg = 0.0;
+  if (!(y > 0.0)) return;
+  double S = 0.0, D = 0.0, t = 1.0 / k, H = t;
+  for (int n = 0; n < 4096; ++n) {
+    S += t;
+    D = fma(t, H, D);
+    if (n > y && t < 1e-18 * S) break;
+    const double kn = k + (double)(n + 1);
+    t *= y / kn;
+    H += 1.0 / kn;
+  }
+  const double ly = log(y);
+  const double pre = exp(fma(k, ly, -y));
+  g = pre * S;
+  dg = fma(g, ly, -pre * D);
+}
+
+struct Chi2Leaf {
+  static constexpr int kKind = kChi2;
+  static constexpr int NP = 1;
+  static constexpr bool kLinear = false;
+  struct C {
+    double km1;  // nu/2 - 1
+  };
+  __device__ static bool valid(const double* p) { return p[0] > 0.0; }
+  __device__ static void consts(const double* p, LeafSetup& s) {
+    s.ec[0] = fma(0.5, p[0], -1.0);
+    s.fscale[0] = 0.5;
+  }
+  __device__ static void finish(double k, double ga, double dga, double gb, double dgb, LeafSetup& s) {
+    const double p2 = exp2(k);
+    s.Z = p2 * (gb - ga);
+    s.dZ[0] = 0.5 * fma(kLn2, s.Z, p2 * (dgb - dga));
+  }
+  __device__ static void setup(const double* p, double lo, double hi, bool analytic, LeafSetup& s) {
+    consts(p, s);
+    if (!analytic) return;
+    const double k = 0.5 * p[0];
+    double ga, dga, gb, dgb;
+    lower_gamma_dk(k, 0.5 * lo, ga, dga);
+    lower_gamma_dk(k, 0.5 * hi, gb, dgb);
+    finish(k, ga, dga, gb, dgb, s);
+  }
+  // setup() over 2 lanes: the series at hi on lane 0, at lo on lane 1.
+  static constexpr int kSetupLanes = 2;
+  __device__ static void setup_coop(const double* p, double lo, double hi, bool analytic, LeafSetup& s, int lane) {
+    consts(p, s);
+    if (!analytic) return;
+    const double k = 0.5 * p[0];
+    double g, dg;
+    lower_gamma_dk(k, 0.5 * (lane ? lo : hi), g, dg);
+    const int base = (int)(threadIdx.x & 63) - lane;
+    const double gb = __shfl(g, base, 64), dgb = __shfl(dg, base, 64);
+    const double ga = __shfl(g, base + 1, 64), dga = __shfl(dg, base + 1, 64);
+    finish(k, ga, dga, gb, dgb, s);
+  }
+  __device__ static double shape(const double* p, double, double, double x, double* dg) {
+    const double lx = log(x);
+    const double g = exp(fma(fma(0.5, p[0], -1.0), lx, -0.5 * x));
+    dg[0] = 0.5 * g * lx;
+    return g;
+  }
+  // the integrand on [0, hi] after x = s^2 (dx = 2 s ds): 2 s^{nu-1} e^{-s^2/2}
+  __device__ static double shape_subst(const double* p, double sv, double* dg) {
+    const double ls = log(sv);
+    const double g = 2.0 * exp(fma(p[0] - 1.0, ls, -0.5 * sv * sv));
+    dg[0] = g * ls;
+    return g;
+  }
+  __device__ static C load(const double* ec) { return C{ec[0]}; }
+  template <bool GRAD>
+  __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
+    const double lx = x > 0.0 ? log_pos(x) : -__builtin_inf();  // x = 0: p = 0 or inf (flagged)
+    lam = fma(c.km1, lx, -0.5 * x);
+    gam = 1.0;
+    if (GRAD) phi[0] = lx;
+  }
+  // FP32 pass: the logarithm in single precision, corrected to first order
+  // for the rounding of x to single; the combination in FP64.
+  struct C32 {
+    double km1;
+  };
+  __device__ static C32 load32(const double* ec) { return C32{ec[0]}; }
+  template <bool GRAD>
+  __device__ static inline void event32(double x, const C32& c, float& lam, float& gam, float* phi) {
+    const float xf = (float)x;
+    double lx = -__builtin_inf();
+    if (x > 0.0) lx = (double)log_f32(xf) + (x - (double)xf) * (double)rcp_f32(xf);
+    lam = (float)fma(c.km1, lx, -0.5 * x);
+    gam = 1.0f;
+    if (GRAD) phi[0] = (float)lx;
   }
 };
 

@@ -33,7 +33,7 @@ constexpr int kBlock = 256;         // threads per block (4 wave64)
 constexpr int kFinishBlock = 1024;  // threads of the single-dataset finishing kernel
 constexpr int kMaxAcc = 1 + kMaxTerms + kMaxLeaves * kMaxLeafParams;
 
-enum LeafKind : int32_t { kGauss = 1, kExp = 2, kCheb = 3, kCB = 4, kArgus = 5, kJohnson = 8 };
+enum LeafKind : int32_t { kGauss = 1, kExp = 2, kCheb = 3, kCB = 4, kArgus = 5, kJohnson = 8, kChi2 = 9 };
 enum NormKind : int32_t { kNormAnalytic = 0, kNormGL = 1, kNormGLSingle = 2 };
 
 // Runtime description of one lowered model (kernel argument, by value).

@@ -6,7 +6,8 @@
 //    closed form ("Analytic Integrals", Sec. 3) or by a 256-point
 //    Gauss-Legendre rule, one node per thread, on panels where the integrand
 //    is analytic (the Crystal Ball split at its junction; the ARGUS
-//    endpoint removed by m = m0 - s^2) or on one panel;
+//    endpoint removed by m = m0 - s^2, the chi-square's at 0 by x = s^2)
+//    or on one panel;
 //  * per term: log of its weight (product of sum coefficients) minus the
 //    log normalisations of its leaves, and d log w_k / d theta.
 #pragma once
@@ -80,6 +81,16 @@ __device__ inline void gl_node(const double* p, int norm, double lo, double hi, 
     v[0] += w * g;
     v[1] += w * dg[0];
     v[2] += w * dg[1];
+  } else if constexpr (Leaf::kKind == kChi2) {
+    if (lo == 0.0) {  // x = s^2 removes the x^{nu/2-1} endpoint behaviour
+      const double sb = sqrt(hi), h = 0.5 * sb;
+      const double w = h * glw[i];
+      const double g = Chi2Leaf::shape_subst(p, fma(h, glx[i], h), dg);
+      v[0] += w * g;
+      v[1] += w * dg[0];
+    } else {
+      panel(lo, hi);
+    }
   } else {
     panel(lo, hi);
   }

@@ -327,6 +327,8 @@ SINGLE_LEAVES = [
     ("cheb", [("a1", 0.1, -1, 1), ("a2", -0.2, -1, 1), ("a3", 0.05, -1, 1), ("a4", 0.1, -1, 1)], -1.0, 1.0),
     ("johnson", [("mu", 0.3, -3, 3), ("lambda", 0.9, 0.1, 5), ("gamma", 0.6, -5, 5), ("delta", 0.8, 0.1, 10)],
      -8.0, 12.0),
+    ("chi2", [("nu", 5.0, 0.5, 50)], 0.0, 30.0),
+    ("chi2", [("nu", 12.0, 0.5, 50)], 3.0, 40.0),
 ]
 
 
