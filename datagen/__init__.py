@@ -287,6 +287,18 @@ def toy_sizes(n_sets: int, seed: int, lo: int = 1000, hi: int = 200000, stream: 
 # Named workloads
 # --------------------------------------------------------------------------
 
+def binned(x: np.ndarray, lo: float, hi: float, n_bins: int):
+    """A binned dataset: the centres of n_bins equal bins of [lo, hi] and the
+    number of events of x in each (as float64 weights)."""
+    counts, edges = np.histogram(x, bins=n_bins, range=(lo, hi))
+    return 0.5 * (edges[:-1] + edges[1:]), counts.astype(np.float64)
+
+
+def signed_weights(n: int, seed: int, lo: float = -0.5, hi: float = 1.5) -> np.ndarray:
+    """n weights uniform in [lo, hi] (either sign, as sWeights have)."""
+    return lo + (hi - lo) * uniforms(seed, 11, n)
+
+
 def data_seed(config: int) -> int:
     return MASTER_SEED + 1000 * config
 

@@ -78,6 +78,8 @@ def lib():
         L.orc_nll.argtypes = [pm, ppd, i64, pd, i32, pd, pd, pd]
         L.orc_nll_batched.argtypes = [pm, ppd, P(i64), i32, pd, i32, pd, pd, P(i32)]
         L.orc_gd_fit.argtypes = [pm, ppd, i64, pd, i32, d, i32, pd, pd, pd, pd]
+        L.orc_nll_weighted.argtypes = [pm, ppd, pd, i64, pd, i32, pd, pd, pd, pd]
+        L.orc_gd_fit_weighted.argtypes = [pm, ppd, pd, i64, pd, i32, d, i32, pd, pd, pd, pd]
         L.orc_nll_bhhh.argtypes = [pm, ppd, i64, pd, i32, pd, pd, pd]
         L.orc_bhhh_fit.argtypes = [pm, ppd, i64, pd, i32, d, i32, pd, pd, pd, pd]
         L.orc_gd_fit_batched.argtypes = [pm, ppd, P(i64), i32, pd, i32, d, i32, pd, pd, P(i32)]
@@ -158,15 +160,23 @@ class Oracle:
         st = lib().orc_log_density(ctypes.byref(self.m), _dptr(xv), _dptr(th), ctypes.byref(lp), _dptr(d))
         return st, lp.value, d
 
-    def nll(self, cols, theta, threads: int = 1, grad: bool = True, stats: bool = False):
+    def nll(self, cols, theta, threads: int = 1, grad: bool = True, stats: bool = False, weights=None):
+        """weights (optional, one per event): the weighted NLL -sum w_i log p_i."""
         keep, arr = _cols(cols)
         n = len(keep[0])
         th = np.ascontiguousarray(theta, dtype=np.float64)
         out = ctypes.c_double()
         g = np.zeros(self.n_param)
         s = np.zeros(self.n_param + 1)
-        st = lib().orc_nll(ctypes.byref(self.m), arr, n, _dptr(th), threads, ctypes.byref(out),
-                           _dptr(g) if grad else None, _dptr(s) if stats else None)
+        if weights is not None:
+            w = np.ascontiguousarray(weights, dtype=np.float64)
+            assert len(w) == n
+            st = lib().orc_nll_weighted(ctypes.byref(self.m), arr, _dptr(w), n, _dptr(th), threads,
+                                        ctypes.byref(out), _dptr(g) if grad else None,
+                                        _dptr(s) if stats else None, None)
+        else:
+            st = lib().orc_nll(ctypes.byref(self.m), arr, n, _dptr(th), threads, ctypes.byref(out),
+                               _dptr(g) if grad else None, _dptr(s) if stats else None)
         res = (st, out.value, g if grad else None)
         return res + ((s,) if stats else ())
 
@@ -183,7 +193,8 @@ class Oracle:
                                    status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         return st, nll, (g if grad else None), status
 
-    def gd_fit(self, cols, theta, n_steps: int, eta: float = 1.0, threads: int = 1, trace: bool = False):
+    def gd_fit(self, cols, theta, n_steps: int, eta: float = 1.0, threads: int = 1, trace: bool = False,
+               weights=None):
         keep, arr = _cols(cols)
         n = len(keep[0])
         th = np.array(theta, dtype=np.float64)
@@ -191,9 +202,16 @@ class Oracle:
         eta_out = ctypes.c_double()
         g = np.zeros(self.n_param)
         tr = np.zeros((max(n_steps, 1), self.n_param + 1))
-        st = lib().orc_gd_fit(ctypes.byref(self.m), arr, n, _dptr(th), n_steps, eta, threads,
-                              ctypes.byref(out), _dptr(g), ctypes.byref(eta_out),
-                              _dptr(tr) if trace else None)
+        if weights is not None:
+            w = np.ascontiguousarray(weights, dtype=np.float64)
+            assert len(w) == n
+            st = lib().orc_gd_fit_weighted(ctypes.byref(self.m), arr, _dptr(w), n, _dptr(th), n_steps, eta,
+                                           threads, ctypes.byref(out), _dptr(g), ctypes.byref(eta_out),
+                                           _dptr(tr) if trace else None)
+        else:
+            st = lib().orc_gd_fit(ctypes.byref(self.m), arr, n, _dptr(th), n_steps, eta, threads,
+                                  ctypes.byref(out), _dptr(g), ctypes.byref(eta_out),
+                                  _dptr(tr) if trace else None)
         res = (st, th, out.value, g, eta_out.value)
         return res + ((tr[:n_steps],) if trace else ())
 

@@ -759,12 +759,15 @@ struct Partial {
   Neumaier grad[ORC_MAX_PAR];
   Neumaier abs_l;
   Neumaier abs_g[ORC_MAX_PAR];
+  Neumaier wsum;                /* sum of the events' weights */
   std::vector<Neumaier> outer;  // n_param^2 when the BHHH matrix is wanted
   int status = ORC_OK;
 };
 
-void nll_range(const Prepared& pr, const double* const* cols, int64_t b, int64_t e, bool want_grad,
-               Partial& out) {
+/* Events [b, e).  w (may be NULL: every weight 1): per-event weights; the
+ * event's log-density and its derivatives enter multiplied by w_i. */
+void nll_range(const Prepared& pr, const double* const* cols, const double* w, int64_t b, int64_t e,
+               bool want_grad, Partial& out) {
   const bool want_outer = !out.outer.empty();
   const orc_model& m = *pr.m;
   const int np = m.n_param;
@@ -784,14 +787,16 @@ void nll_range(const Prepared& pr, const double* const* cols, int64_t b, int64_t
       return;
     }
     double l = std::log(p);
-    out.nll.add(-l);
-    out.abs_l.add(std::fabs(l));
+    double wi = w ? w[i] : 1.0;
+    out.nll.add(-wi * l);
+    out.abs_l.add(std::fabs(wi * l));
+    out.wsum.add(wi);
     if (want_grad) {
       double dl[ORC_MAX_PAR];
       for (int k = 0; k < np; ++k) {
         dl[k] = dv[k] / p; /* d log p = dp / p */
-        out.grad[k].add(-dl[k]);
-        out.abs_g[k].add(std::fabs(dl[k]));
+        out.grad[k].add(-wi * dl[k]);
+        out.abs_g[k].add(std::fabs(wi * dl[k]));
       }
       /* BHHH: the outer product of the event's score with itself */
       if (want_outer)
@@ -807,7 +812,8 @@ void nll_range(const Prepared& pr, const double* const* cols, int64_t b, int64_t
  * derivative N / nu^2 at (nu, nu) in an extended model; rows and columns of
  * fixed parameters are 0. */
 int nll_one(const orc_model& m, const double* const* cols, int64_t n, const double* th,
-            int threads, double* nll, double* grad, double* stats, double* bhhh = nullptr) {
+            int threads, double* nll, double* grad, double* stats, double* bhhh = nullptr,
+            const double* w = nullptr, double* wsum_out = nullptr) {
   const int np = m.n_param;
   auto fail = [&](int st) {
     *nll = kInf;
@@ -827,21 +833,23 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
     for (auto& pt : parts) pt.outer.resize((size_t)np * np);
   const bool want_grad = (grad != nullptr) || (stats != nullptr) || (bhhh != nullptr);
   if (T == 1) {
-    nll_range(pr, cols, 0, n, want_grad, parts[0]);
+    nll_range(pr, cols, w, 0, n, want_grad, parts[0]);
   } else {
     std::vector<std::thread> pool;
     for (int t = 0; t < T; ++t) {
       int64_t b = n * t / T, e = n * (t + 1) / T;
-      pool.emplace_back([&, b, e, t]() { nll_range(pr, cols, b, e, want_grad, parts[t]); });
+      pool.emplace_back([&, b, e, t]() { nll_range(pr, cols, w, b, e, want_grad, parts[t]); });
     }
     for (auto& th_ : pool) th_.join();
   }
   /* fixed-order combine of the per-chunk compensated sums */
-  Neumaier tot, g[ORC_MAX_PAR], al, ag[ORC_MAX_PAR];
+  Neumaier tot, g[ORC_MAX_PAR], al, ag[ORC_MAX_PAR], ws;
   for (int t = 0; t < T; ++t) {
     if (parts[t].status != ORC_OK) return fail(parts[t].status);
     tot.add(parts[t].nll.s);
     tot.add(parts[t].nll.c);
+    ws.add(parts[t].wsum.s);
+    ws.add(parts[t].wsum.c);
     al.add(parts[t].abs_l.s);
     al.add(parts[t].abs_l.c);
     for (int k = 0; k < np; ++k) {
@@ -852,11 +860,14 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
     }
   }
   double v = tot.value();
+  /* the number of events, or with weights their sum W */
+  double nw = w ? ws.value() : (double)n;
+  if (wsum_out) *wsum_out = nw;
   if (m.extended) {
-    /* Poisson term for the total yield nu: nu - N ln nu */
+    /* Poisson term for the total yield nu: nu - N ln nu (N -> W with weights) */
     double nu = th[m.yield_param];
-    v += nu - (double)n * std::log(nu);
-    g[m.yield_param].add(1.0 - (double)n / nu);
+    v += nu - nw * std::log(nu);
+    g[m.yield_param].add(1.0 - nw / nu);
   }
   *nll = v;
   if (grad)
@@ -887,18 +898,25 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
 }
 
 /* Gradient descent with step halving, see oracle.h. */
+/* w (may be NULL): event weights; the step is then scaled by 1/W, W their
+ * sum (the weighted analogue of the mean NLL). */
 int gd_fit_one(const orc_model& m, const double* const* cols, int64_t n, double* theta,
                int n_steps, double eta, int threads, double* nll_out, double* grad_out,
-               double* eta_out, double* trace) {
+               double* eta_out, double* trace, const double* w = nullptr) {
   const int np = m.n_param;
   std::vector<double> acc(theta, theta + np), prop(theta, theta + np), g_acc(np, 0.0),
       g(np, 0.0);
   double f_acc = kInf;
   double inv_n = 1.0 / (double)std::max<int64_t>(n, 1);
+  if (w) {
+    Neumaier W;
+    for (int64_t i = 0; i < n; ++i) W.add(w[i]);
+    inv_n = W.value() > 0.0 ? 1.0 / W.value() : 1.0;
+  }
   int last = ORC_OK;
   for (int s = 0; s < n_steps; ++s) {
     double f;
-    int st = nll_one(m, cols, n, prop.data(), threads, &f, g.data(), nullptr);
+    int st = nll_one(m, cols, n, prop.data(), threads, &f, g.data(), nullptr, nullptr, w);
     if (trace) {
       trace[s * (np + 1)] = f;
       for (int k = 0; k < np; ++k) trace[s * (np + 1) + 1 + k] = prop[k];
@@ -1100,6 +1118,24 @@ int orc_nll(const orc_model* m, const double* const* cols, int64_t n, const doub
   int st = check_model(*m);
   if (st != ORC_OK) return st;
   return nll_one(*m, cols, n, theta, threads, nll, grad, stats);
+}
+
+int orc_nll_weighted(const orc_model* m, const double* const* cols, const double* w, int64_t n,
+                     const double* theta, int32_t threads, double* nll, double* grad, double* stats,
+                     double* wsum) {
+  if (!data_args_ok(m, cols) || !w || !theta || !nll || n < 0) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  return nll_one(*m, cols, n, theta, threads, nll, grad, stats, nullptr, w, wsum);
+}
+
+int orc_gd_fit_weighted(const orc_model* m, const double* const* cols, const double* w, int64_t n,
+                        double* theta, int32_t n_steps, double eta, int32_t threads, double* nll,
+                        double* grad, double* eta_out, double* trace) {
+  if (!data_args_ok(m, cols) || !w || !theta || !nll || n < 0 || n_steps < 0) return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  return gd_fit_one(*m, cols, n, theta, n_steps, eta, threads, nll, grad, eta_out, trace, w);
 }
 
 int orc_nll_batched(const orc_model* m, const double* const* cols, const int64_t* offsets,

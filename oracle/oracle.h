@@ -115,6 +115,15 @@ int orc_nll(const orc_model* m, const double* const* cols, int64_t n,
             const double* theta, int32_t threads, double* nll, double* grad,
             double* stats);
 
+/* Weighted events (a binned dataset is its bin centres weighted by the
+ * counts, Sec. 5.1 contrasts such fits with unbinned ones; sWeighted fits
+ * have weights of either sign): NLL = -sum_i w_i log p(x_i), its gradient
+ * likewise, and in an extended model nu - W ln nu with W = sum_i w_i.
+ * stats as orc_nll over the weighted terms; wsum (may be NULL) gets W.   */
+int orc_nll_weighted(const orc_model* m, const double* const* cols, const double* w,
+                     int64_t n, const double* theta, int32_t threads, double* nll,
+                     double* grad, double* stats, double* wsum);
+
 /* Many datasets: set s holds events [offsets[s], offsets[s+1]) and its own
  * parameter row theta[s*n_param ...].  Per-set status in status[s].      */
 int orc_nll_batched(const orc_model* m, const double* const* cols,
@@ -132,6 +141,13 @@ int orc_nll_batched(const orc_model* m, const double* const* cols,
 int orc_gd_fit(const orc_model* m, const double* const* cols, int64_t n,
                double* theta, int32_t n_steps, double eta, int32_t threads,
                double* nll, double* grad, double* eta_out, double* trace);
+
+/* orc_gd_fit over weighted events: the weighted NLL of orc_nll_weighted,
+ * steps scaled by 1/W instead of 1/N (W <= 0: no scaling).              */
+int orc_gd_fit_weighted(const orc_model* m, const double* const* cols, const double* w,
+                        int64_t n, double* theta, int32_t n_steps, double eta,
+                        int32_t threads, double* nll, double* grad, double* eta_out,
+                        double* trace);
 
 /* NLL, gradient and the BHHH matrix B = sum_i s_i s_i^T of the events'
  * scores s_i = d log p(x_i) / d theta (n_param x n_param, row-major,

@@ -763,3 +763,59 @@ def test_chi2_gradient_matches_central_differences():
     f = lambda v: o.nll(w["cols"], np.array([v]))[1]
     fd = (f(th[0] - 2 * h) - 8 * f(th[0] - h) + 8 * f(th[0] + h) - f(th[0] + 2 * h)) / (12 * h)
     assert abs(fd - g[0]) <= 50 * 2.2e-16 * abs(nll) / h + 1e-7 * abs(g[0]), (fd, g)
+
+
+# ---------------------------------------------------------------------------
+# weighted events (binned datasets, sWeights)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("config", [1, 2, 3])
+def test_integer_weights_equal_repeated_events(config):
+    """Weights 0..4: the weighted NLL and gradient equal those of the dataset
+    with every event repeated w_i times (also with an extended yield term)."""
+    w = datagen.workload(config, n=3000)
+    spec, th = w["spec"], w["points"][1]
+    wt = np.floor(5 * datagen.uniforms(7, 3, 3000))
+    rep = [np.repeat(c, wt.astype(np.int64)) for c in w["cols"]]
+    o = oracle.Oracle(spec)
+    st, v, g, s = o.nll(w["cols"], th, weights=wt, stats=True)
+    st2, v2, g2, s2 = o.nll(rep, th, stats=True)
+    assert st == OK and st2 == OK
+    assert abs(v - v2) <= 1e-13 * abs(v2)
+    np.testing.assert_allclose(g, g2, rtol=0, atol=1e-12 * max(np.abs(g2).max(), s2[1:].max()))
+    ext = dict(spec)
+    ext["params"] = list(spec["params"]) + [datagen.param("nu", 1000.0, 1.0, 1e7)]
+    ext["extended"] = True
+    ext["yield_param"] = len(ext["params"]) - 1
+    the = np.append(th, 2100.0)
+    oe = oracle.Oracle(ext)
+    _, ve, ge = oe.nll(w["cols"], the, weights=wt)
+    _, ve2, ge2 = oe.nll(rep, the)
+    assert abs(ve - ve2) <= 1e-13 * abs(ve2)
+    assert abs(ge[-1] - (1 - wt.sum() / 2100.0)) <= 1e-14 and abs(ge[-1] - ge2[-1]) <= 1e-14
+
+
+def test_weighted_nll_matches_library():
+    """-fsum(w_i log p(x_i)) from library densities, signed weights."""
+    for config in (1, 2, 3):
+        w = datagen.workload(config, n=16)
+        wt = datagen.signed_weights(16, seed=config)
+        ref = -math.fsum(wt * lib_model_logpdf(w["spec"], w["cols"], w["theta"]))
+        st, v, _ = oracle.Oracle(w["spec"]).nll(w["cols"], w["theta"], weights=wt)
+        assert st == OK and abs(v - ref) <= 2e-13 * max(1.0, abs(ref)), (config, v, ref)
+
+
+def test_binned_gauss_fit_reaches_weighted_mle():
+    """A binned fit (bin centres weighted by counts) of the wide-range
+    Gaussian lands on the weighted-moment MLE mu = sum w x / W,
+    sigma^2 = sum w (x - mu)^2 / W."""
+    w = datagen.workload(1)
+    xc, cnt = datagen.binned(w["cols"][0], -10.0, 10.0, 400)
+    x = xc.astype(np.longdouble)
+    W = cnt.astype(np.longdouble).sum()
+    mu_hat = float((cnt * x).sum() / W)
+    s_hat = float(np.sqrt((cnt * (x - mu_hat) ** 2).sum() / W))
+    st, th, nll, g, eta = oracle.Oracle(w["spec"]).gd_fit([xc], w["theta"], 50, 1.0, weights=cnt)
+    assert st == OK
+    assert abs(th[0] - mu_hat) <= 1e-8 * abs(mu_hat)
+    assert abs(th[1] - s_hat) <= 1e-8 * s_hat
