@@ -166,6 +166,23 @@ nll_status nll_set_stream(nll_model* model, void* stream);
  * closed observable range or is NaN (the data are then not attached). */
 nll_status nll_set_data(nll_model* model, const double* const* cols, int64_t n_events);
 
+/* Attach per-event weights to the attached data (weights: device array of
+ * n_events doubles, borrowed until the next nll_set_weights, nll_set_data
+ * or nll_destroy_model; NULL detaches them).  A binned dataset is its bin
+ * centres weighted by the counts (Sec. 5.1 sets such binned fits against
+ * unbinned ones); sWeights may be of either sign; weights are not
+ * checked.  With weights attached:
+ *   NLL = -sum_i w_i log p(x_i), gradient likewise; an extended model adds
+ *   nu - W ln nu with W = sum_i w_i; nll_fit scales its steps by 1/W.
+ *   nll_eval, nll_eval_grad, nll_fit and their step timing take them; the
+ *   other entry points (batched, points, BHHH, autotuner) return
+ *   NLL_ERR_UNSUPPORTED while they are attached.
+ * Compiled for FP64 shapes over at most 3 observables.  One logarithm more
+ * per event than the unweighted pass.  Errors: NLL_ERR_STATE (no data),
+ * NLL_ERR_ARG (misaligned), NLL_ERR_UNSUPPORTED (FP32C or no weighted
+ * kernel for the shape). */
+nll_status nll_set_weights(nll_model* model, const double* weights);
+
 /* Enqueue: NLL at theta (device [n_param]) into *nll_out (device [1]).
  * A parameter outside its range or an invalid density yields +inf and a
  * status bit read by nll_sync. */

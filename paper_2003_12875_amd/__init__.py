@@ -151,7 +151,23 @@ class Model:
         self._bind_stream()
         check(lib().nll_set_data(self._h, arr, ctypes.c_int64(n)), "nll_set_data")
         self._cols = cols
+        self._weights = None
         self.n_events = n
+
+    def set_weights(self, weights):
+        """Attach per-event float64 weights (device tensor, one per event) to
+        the attached data, or detach them with None: the NLL becomes
+        -sum w_i log p(x_i) (a binned dataset: bin centres weighted by the
+        counts).  Cleared by set_data."""
+        ptr = None
+        if weights is not None:
+            weights = _dev_tensor(weights, _torch().float64, self.device)
+            if weights.numel() != self.n_events:
+                raise NLLError(-1, "one weight per attached event required")
+            ptr = weights.data_ptr()
+        self._bind_stream()
+        check(lib().nll_set_weights(self._h, ptr), "nll_set_weights")
+        self._weights = weights
 
     # -- evaluation ------------------------------------------------------------
     def eval(self, theta, out=None):

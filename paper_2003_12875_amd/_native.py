@@ -14,7 +14,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported model shape", -3: "p
           -7: "out of device memory", -8: "call out of order"}
 
 # every entry point declared in include/nll.h
-EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_data", "nll_eval",
+EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_data", "nll_set_weights", "nll_eval",
            "nll_eval_grad", "nll_eval_batched", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_eval_bhhh",
            "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
            "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
@@ -72,6 +72,7 @@ def lib():
         L.nll_destroy_model.restype = None
         L.nll_set_stream.argtypes = [vp, vp]
         L.nll_set_data.argtypes = [vp, ctypes.POINTER(vp), i64]
+        L.nll_set_weights.argtypes = [vp, vp]
         L.nll_eval.argtypes = [vp, vp, vp]
         L.nll_eval_grad.argtypes = [vp, vp, vp, vp]
         L.nll_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp]

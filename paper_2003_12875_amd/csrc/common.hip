@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "reduce.h"
 
 namespace nllmi {
 
@@ -140,6 +141,40 @@ hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_
   const int grid = (n_sets + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_fit_final, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, st, n_sets, P, gd, theta_out,
                      nll_out, grad_out, status_out);
+  return hipGetLastError();
+}
+
+// Sum of the per-event weights: each thread a double-double sum over a
+// fixed stride, the block's hi and lo parts summed by block_sum_vals, one
+// partial per block; then one block adds the partials in block order.
+__global__ __launch_bounds__(kBlock) void k_wsum_part(const double* __restrict__ w, int64_t n, DD* __restrict__ part) {
+  __shared__ double buf[2 * (kBlock + 1)];
+  __shared__ DD tot[2];
+  DD acc{0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) acc = dd_add1(acc, w[i]);
+  const double v[2] = {acc.hi, acc.lo};
+  block_sum_vals<2, kBlock>(v, buf, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = dd_add(tot[0], tot[1]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_wsum_final(const DD* __restrict__ part, int n_part, double* __restrict__ out) {
+  __shared__ DD tot[1];
+  RecordSum<1, kBlock> rs;
+  rs.issue(part, n_part);
+  rs.reduce(part, n_part, tot);
+  if (threadIdx.x == 0) *out = tot[0].hi + tot[0].lo;
+}
+
+hipError_t launch_wsum(const double* w, int64_t n, double* part, double* out, hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > kWsumBlocks) blocks = kWsumBlocks;
+  if (blocks < 1) blocks = 1;
+  DD* p = reinterpret_cast<DD*>(part);
+  hipLaunchKernelGGL(k_wsum_part, dim3((unsigned)blocks), dim3(kBlock), 0, st, w, n, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wsum_final, dim3(1), dim3(kBlock), 0, st, p, (int)blocks, out);
   return hipGetLastError();
 }
 

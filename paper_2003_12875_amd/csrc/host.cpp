@@ -453,6 +453,8 @@ int lds_cap(const nll_model* m, int bpc) {
 SingleArgs single_args(const nll_model* m, const double* theta, double* nll_out, double* grad_out) {
   SingleArgs a{};
   for (int o = 0; o < kMaxObs; ++o) a.cols[o] = m->cols[o];
+  if (m->weights) a.cols[m->plan.n_obs] = m->weights;  // read after the observables
+  a.wsum = m->wsum;
   a.n = m->n;
   a.theta = theta;
   a.nll_out = nll_out;
@@ -503,8 +505,9 @@ nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n
     e = bhhh ? m->ops->single_bhhh_fit(m->plan, a, m->sched.unroll, single_grid(m),
                                        lds_cap(m, m->sched.blocks_per_cu), st, kernel_event(m, s, 0),
                                        kernel_event(m, s, 1))
-             : m->ops->single_fit(m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), st,
-                                  kernel_event(m, s, 0), kernel_event(m, s, 1));
+             : (m->weights ? m->ops->single_w_fit : m->ops->single_fit)(
+                   m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), st,
+                   kernel_event(m, s, 0), kernel_event(m, s, 1));
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     record_step(m, s + 1, st);
   }
@@ -658,6 +661,8 @@ void nll_destroy_model(nll_model* m) {
   dfree(m->gd_mem);
   dfree(m->gd_status);
   dfree(m->gd_bacc);
+  dfree(m->wsum);
+  dfree(m->wsum_part);
   delete m;
 }
 
@@ -686,9 +691,28 @@ nll_status nll_set_data(nll_model* m, const double* const* cols, int64_t n_event
   if (bad) return NLL_ERR_DOMAIN;
   for (int o = 0; o < kMaxObs; ++o) m->cols[o] = (o < m->plan.n_obs && n_events > 0) ? cols[o] : nullptr;
   m->n = n_events;
+  m->weights = nullptr;  // weights belong to the data they were attached to
   const int64_t off[2] = {0, n_events};
   if (hipMemcpy(m->offsets1, off, sizeof(off), hipMemcpyHostToDevice) != hipSuccess) return NLL_ERR_DEVICE;
   m->have_graph = false;
+  return NLL_OK;
+}
+
+nll_status nll_set_weights(nll_model* m, const double* weights) {
+  if (!m) return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  if (weights && (reinterpret_cast<uintptr_t>(weights) & 7u)) return NLL_ERR_ARG;
+  if (weights && !m->ops->single_w) return NLL_ERR_UNSUPPORTED;
+  DeviceGuard guard(m->device);
+  m->weights = nullptr;
+  m->have_graph = false;
+  if (!weights || m->n == 0) return NLL_OK;
+  nll_status st = NLL_OK;
+  if (!m->wsum && (st = dalloc(&m->wsum, 1)) != NLL_OK) return st;
+  if (!m->wsum_part && (st = dalloc(&m->wsum_part, 2 * (size_t)kWsumBlocks)) != NLL_OK) return st;
+  // W once per attachment, on the model's stream (ahead of every use)
+  if (launch_wsum(weights, m->n, m->wsum_part, m->wsum, m->stream) != hipSuccess) return NLL_ERR_DEVICE;
+  m->weights = weights;
   return NLL_OK;
 }
 
@@ -697,14 +721,14 @@ static nll_status nll_eval_impl(nll_model* m, const double* theta, double* nll_o
   if (m->n < 0) return NLL_ERR_STATE;
   DeviceGuard guard(m->device);
   SingleArgs a = single_args(m, theta, nll_out, grad_out);
-  hipError_t e = m->ops->single(m->plan, a, grad, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu),
-                                m->stream);
+  hipError_t e = (m->weights ? m->ops->single_w : m->ops->single)(
+      m->plan, a, grad, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), m->stream);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
 
 nll_status nll_eval_bhhh(nll_model* m, const double* theta, double* nll_out, double* grad_out, double* bhhh_out) {
   if (!m || !theta || !nll_out || !grad_out || !bhhh_out) return NLL_ERR_ARG;
-  if (!m->ops->single_bhhh) return NLL_ERR_UNSUPPORTED;
+  if (!m->ops->single_bhhh || m->weights) return NLL_ERR_UNSUPPORTED;
   if (m->n < 0) return NLL_ERR_STATE;
   DeviceGuard guard(m->device);
   SingleArgs a = single_args(m, theta, nll_out, grad_out);
@@ -726,6 +750,7 @@ nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets
                             double* nll_out, double* grad_out, int32_t* status_out) {
   if (!m || n_sets < 0 || (n_sets > 0 && (!offsets || !theta || !nll_out))) return NLL_ERR_ARG;
   if (m->n < 0) return NLL_ERR_STATE;
+  if (m->weights) return NLL_ERR_UNSUPPORTED;
   if (n_sets == 0) return NLL_OK;
   DeviceGuard guard(m->device);
   nll_status st = ensure_sets(m, n_sets);
@@ -751,6 +776,7 @@ nll_status nll_eval_points(nll_model* m, int32_t n_points, const double* theta, 
                            int32_t* status_out) {
   if (!m || n_points < 0 || (n_points > 0 && (!theta || !nll_out))) return NLL_ERR_ARG;
   if (m->n < 0) return NLL_ERR_STATE;
+  if (m->weights) return NLL_ERR_UNSUPPORTED;
   if (n_points == 0) return NLL_OK;
   DeviceGuard guard(m->device);
   const int64_t tile = m->sched.tile_events;
@@ -783,6 +809,7 @@ nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets,
   if (!m || n_sets < 0 || n_steps < 0 || !(eta > 0.0) || (n_sets > 0 && (!offsets || !theta || !nll_out)))
     return NLL_ERR_ARG;
   if (m->n < 0) return NLL_ERR_STATE;
+  if (m->weights) return NLL_ERR_UNSUPPORTED;
   if (n_sets == 0) return NLL_OK;
   DeviceGuard guard(m->device);
   nll_status st = ensure_sets(m, n_sets);
@@ -811,7 +838,7 @@ nll_status nll_fit_batched(nll_model* m, int32_t n_sets, const int64_t* offsets,
 static nll_status fit_single_impl(nll_model* m, double* theta, int32_t n_steps, double eta, double* nll_out,
                                   double* grad_out, int32_t* status_out, bool bhhh) {
   if (!m || !theta || !nll_out || n_steps < 0 || !(eta > 0.0)) return NLL_ERR_ARG;
-  if (bhhh && !m->ops->single_bhhh_fit) return NLL_ERR_UNSUPPORTED;
+  if (bhhh && (!m->ops->single_bhhh_fit || m->weights)) return NLL_ERR_UNSUPPORTED;
   if (m->n < 0) return NLL_ERR_STATE;
   DeviceGuard guard(m->device);
   nll_status st = ensure_sets(m, 1);
@@ -882,6 +909,7 @@ nll_status nll_set_schedule(nll_model* m, const nll_schedule* s) {
 nll_status nll_autotune(nll_model* m, int32_t which, int32_t n_sets, const int64_t* offsets, const double* theta) {
   if (!m || (which != 1 && which != 2)) return NLL_ERR_ARG;
   if (m->n < 0) return NLL_ERR_STATE;
+  if (m->weights) return NLL_ERR_UNSUPPORTED;
   DeviceGuard guard(m->device);
   return tune_model(m, which, n_sets, offsets, theta);
 }

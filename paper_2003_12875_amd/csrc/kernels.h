@@ -37,6 +37,7 @@ struct SingleArgs {
   const double* glx;            // 256-point Gauss-Legendre rule on [-1, 1]
   const double* glw;
   GDState gd;                   // fit mode: theta = gd.th_prop, set 0
+  const double* wsum;           // weighted events: the weights' sum W (device, 1)
 };
 
 // One work item of the batched pass: events [start, end) of one set.
@@ -89,6 +90,11 @@ struct VariantOps {
   hipError_t (*single_bhhh_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
                                 hipEvent_t ev0, hipEvent_t ev1);
   int bhhh_record;  // values per block record of the BHHH pass (0: not compiled)
+  // weighted events (FP64 shapes; null where not compiled): as single and
+  // single_fit, with the weights in SingleArgs::cols[nobs]
+  hipError_t (*single_w)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, int lds_cap, hipStream_t);
+  hipError_t (*single_w_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
+                             hipEvent_t ev0, hipEvent_t ev1);
 };
 
 // registry: every variants_*.hip file appends its compiled shapes
@@ -106,6 +112,10 @@ hipError_t launch_points(int n_sets, int64_t n, int64_t tile, int64_t* offsets, 
                          WorkItem* items, hipStream_t st);
 hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_out, double* nll_out,
                             double* grad_out, int* status_out, hipStream_t st);
+// W = sum of n weights into *out (deterministic, compensated): per-block
+// partials in part (at most kWsumBlocks double-double pairs), then one block.
+constexpr int kWsumBlocks = 1024;
+hipError_t launch_wsum(const double* w, int64_t n, double* part, double* out, hipStream_t st);
 hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, unsigned long long* bad,
                               hipStream_t st);
 

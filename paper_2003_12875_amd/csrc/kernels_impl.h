@@ -38,11 +38,12 @@ namespace nllmi {
 // with T_k = sum_i r_k, F_lp = sum_i R_l phi_lp and Rtot_l = sum_{k ∋ l} T_k
 // (N for root leaves); the leaf and term loops are compile-time.
 // Results: *s_nll, *s_st (thread 0 writes) and g[q], visible after the
-// trailing barrier.
+// trailing barrier.  n: the number of events, or over weighted events the
+// weights' sum W.
 // ------------------------------------------------------------------------
 template <class M, bool GRAD>
-__device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt, const DD* tot, int64_t n, const double* theta,
-                             bool flagged, double* s_nll, int* s_st, double* g) {
+__device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt, const DD* tot, double n,
+                                             const double* theta, bool flagged, double* s_nll, int* s_st, double* g) {
   constexpr int NA = M::template NA<GRAD>;
   const int64_t bad_events = (int64_t)(tot[NA].hi + tot[NA].lo);
   const double sum_l = tot[0].hi + tot[0].lo;
@@ -58,10 +59,10 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
       cterms += (pt.ck[k] - pt.ck[0]) * (c.hi + c.lo);
     }
   }
-  double nll = -((sum_l + cterms) + (double)n * cn);
+  double nll = -((sum_l + cterms) + n * cn);
   if (pl.extended) {
     const double nu = theta[pl.yield_param];
-    nll += nu - (double)n * log(nu);
+    nll += nu - n * log(nu);
   }
   int status = 0;
   if (flagged) status = -1;                                                 // malformed offsets
@@ -84,7 +85,7 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
           T[k] = tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo;
           Tsum += T[k];
         }
-        T[M::K - 1] = M::K > 1 ? (double)n - Tsum : 0.0;  // sum_k r_k = 1 per event
+        T[M::K - 1] = M::K > 1 ? n - Tsum : 0.0;  // sum_k r_k = 1 per event
         if constexpr (M::K > 1) {
 #pragma unroll
           for (int k = 0; k < M::K; ++k) acc += T[k] * pt.dlogw[k][q];
@@ -92,7 +93,7 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
         static_for<M::L>([&](auto lc) {
           constexpr int l = decltype(lc)::value;
           constexpr int off = M::template leaf_off<l>();
-          double R = (double)n;
+          double R = n;
           if constexpr (!M::ROOTs[l]) {
             const int mask_l = 1 << l;
             R = 0.0;
@@ -110,7 +111,7 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
           }
         });
         acc = -acc;
-        if (pl.extended && q == pl.yield_param) acc += 1.0 - (double)n / theta[q];
+        if (pl.extended && q == pl.yield_param) acc += 1.0 - n / theta[q];
       }
       g[q] = pl.par_free[q] ? acc : 0.0;
     }
@@ -147,7 +148,7 @@ __device__ inline GDPre gd_preload(const GDState& gd, int s, int P) {
 // parameter q (free parameters only), stores it and returns it (threads
 // q >= P return 0).  st/nll are block-uniform LDS values; grad is in LDS.
 __device__ inline double gd_update(const Plan& pl, const GDState& gd, int s, int st, double nll,
-                                   const double* grad, int64_t n_s, const GDPre& pre) {
+                                   const double* grad, double n_s, const GDPre& pre) {
   __shared__ int s_ok;
   __shared__ double s_step;
   const int P = pl.n_param;
@@ -164,7 +165,7 @@ __device__ inline double gd_update(const Plan& pl, const GDState& gd, int s, int
       if (!__builtin_isfinite(fa)) gd.last_status[s] = st != 0 ? st : -5;
     }
     s_ok = ok;
-    s_step = eta / (double)(n_s > 0 ? n_s : 1);
+    s_step = eta / (n_s > 0.0 ? n_s : 1.0);
   }
   __syncthreads();
   const int q = threadIdx.x;
@@ -591,11 +592,14 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
     const int P = pl.n_param;
     if (t < P * P) bpre = a.gd.b_acc[t];
   }
+  // the events' count, or the weights' sum W (attached with the weights)
+  double neff = (double)a.n;
+  if constexpr (M::WEIGHTED) neff = *a.wsum;
   RecordSum<NV, kFinishBlock> rs;
   rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
   if (t < PT8) reinterpret_cast<double*>(&spt)[t] = ptv;
   rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
-  finish_block<M, GRAD>(spl, spt, tot, a.n, s_theta, false, &s_nll, &s_st, s_grad);
+  finish_block<M, GRAD>(spl, spt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
   __shared__ double s_B[BH ? kMaxParams * kMaxParams : 1];
   if constexpr (BH) bhhh_assemble<M>(spl, spt, tot, a.n, s_theta, s_st, s_B);
   if constexpr (FIT) {
@@ -603,7 +607,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
     if constexpr (BH) {
       next = bhhh_update(spl, a.gd, s_st, s_nll, s_grad, s_B, bpre, pre);
     } else {
-      next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, a.n, pre);
+      next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, neff, pre);
     }
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
     // the next proposal's constants, built in LDS (its phases read back
@@ -796,6 +800,16 @@ inline size_t pad_lds(const void* kernel, int lds_cap) {
   return (size_t)lds_cap > fa.sharedSizeBytes ? (size_t)lds_cap - fa.sharedSizeBytes : 0;
 }
 
+// BHHH pass compiled: FP64 unweighted shapes with at most 6 score features
+template <class M>
+constexpr bool bh_compiled() {
+  if constexpr (M::PREC != 0 || M::WEIGHTED) {
+    return false;
+  } else {
+    return AccBhhh<M>::NVF <= 6;
+  }
+}
+
 template <class M>
 struct Launch {
   // events per thread per tile: 2, 4, or 8 (8 only for shapes with few
@@ -803,7 +817,7 @@ struct Launch {
   // events per thread per tile compiled for this shape: {2, 4, 8}, or
   // {2, 4} for shapes with more than 8 accumulators (registers); 8 maps to
   // 4 there
-  static constexpr bool kU8 = M::NA_GRAD <= 8;
+  static constexpr bool kU8 = !M::WEIGHTED && M::NA_GRAD <= 8;
   static int pick_u(int unroll) { return unroll >= 8 && kU8 ? 8 : unroll >= 4 ? 4 : 2; }
 
   // With timing events (ev0, ev1 both set) the launch carries them, so that
@@ -839,7 +853,7 @@ struct Launch {
   }
   // BHHH: compiled for FP64 shapes with at most 6 score features (21 second
   // moments), at 2 and 4 events per thread per tile (8 maps to 4)
-  static constexpr bool kBH = M::PREC == 0 && AccBhhh<M>::NVF <= 6;
+  static constexpr bool kBH = bh_compiled<M>();
   template <bool FIT, int U>
   static void launch_bh(const Plan& pl, const SingleArgs& a, int grid, int lds_cap, hipStream_t st, hipEvent_t ev0,
                         hipEvent_t ev1) {
@@ -949,6 +963,10 @@ VariantOps make_ops(const char* name) {
   v.consts = &Launch<M>::consts;
   v.sets = &Launch<M>::sets;
   v.fit_init = &Launch<M>::fit_init;
+  if constexpr (M::PREC == 0 && M::NOBS < kMaxObs) {  // weighted events: the weights take one column
+    v.single_w = &Launch<Weighted<M>>::single;
+    v.single_w_fit = &Launch<Weighted<M>>::single_fit;
+  }
   if constexpr (Launch<M>::kBH) {
     v.single_bhhh = &Launch<M>::single_bhhh;
     v.single_bhhh_fit = &Launch<M>::single_bhhh_fit;

@@ -107,6 +107,7 @@ struct Model {
   using LeafCs = std::tuple<typename Slots::Leaf::C...>;
   using LeafC32s = std::tuple<typename Slots::Leaf::C32...>;
   static constexpr int PREC = 0;  // 0: FP64 event pass, 1: FP32-compensated
+  static constexpr bool WEIGHTED = false;
 
   static_assert(L >= 1 && L <= kMaxLeaves, "1..kMaxLeaves leaves");
   static_assert(K >= 1 && K <= kMaxTerms, "1..kMaxTerms terms");
@@ -126,6 +127,25 @@ struct FP32C : Base {
   template <bool GRAD>
   static constexpr int NA = Base::template NA<GRAD> + NCNT;
   static_assert(Base::NA_GRAD + NCNT <= kMaxAcc, "accumulator budget");
+};
+
+// The same compiled shape over weighted events (a binned dataset as its bin
+// centres weighted by the counts, or sWeighted events; Sec. 5.1 sets such
+// binned fits against unbinned ones): the weights are one more column,
+// read after the observables.  Each event's log-density and gradient
+// features enter the sums multiplied by its weight.  After the reduction
+// the weights' sum W (computed once when the weights are attached, so that
+// it does not depend on the parameter point) takes the place of the event
+// count N: in the term constants, the last term's responsibility total, the
+// root leaves' normalisation terms, the extended term nu - W ln nu and the
+// gradient-descent scale 1/W.
+template <class B>
+struct Weighted : B {
+  using Base = B;
+  static constexpr bool WEIGHTED = true;
+  static constexpr int NOBS = B::NOBS + 1;
+  static_assert(B::PREC == 0 && !B::WEIGHTED, "weighted events: FP64 event pass");
+  static_assert(NOBS <= kMaxObs, "weights take one observable slot");
 };
 
 // Uniform per-point constants of a compiled model, held in scalar registers.
@@ -644,10 +664,57 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
     for (int j = i; j < AB::NVF; ++j, ++m) acc.mom[m] = fma(v[i], v[j], acc.mom[m]);
 }
 
+// Weighted events: each event is evaluated into a fresh accumulator of the
+// unweighted shape, whose log-domain sum and running product give its
+// log-density (one logarithm per event: a weighted sum cannot be folded
+// into a product of mantissas), and is added with its weight.
+template <class M, bool GRAD>
+struct AccW {
+  using B = typename M::Base;
+  static constexpr int NA = B::template NA<GRAD>;
+  double a[NA];
+  int bad;
+  __device__ void init() {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) a[j] = 0.0;
+    bad = 0;
+  }
+  __device__ void begin_tile() {}
+  __device__ void end_tile() {}
+  __device__ void finalize(double (&v)[NA]) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) v[j] = a[j];
+  }
+};
+
+template <class M, bool GRAD>
+__device__ inline void model_event(const double (&x)[M::NOBS], const Consts<typename M::Base>& C,
+                                   AccW<M, GRAD>& acc) {
+  using B = typename M::Base;
+  constexpr int NA = AccW<M, GRAD>::NA;
+  Acc<B, GRAD> e;
+  e.init();
+  model_event<B, GRAD>(reinterpret_cast<const double(&)[B::NOBS]>(x), C, e);
+  const double w = x[B::NOBS];
+  double lp = e.a[0];
+  // one event's product is s times the root linear factors: a normal
+  // double when the density is valid; otherwise log gives -inf or NaN
+  if constexpr (B::NEED_PROD) lp += e.P > 0.0 ? log_pos(e.P) : log(e.P);
+  acc.a[0] = fma(w, lp, acc.a[0]);
+#pragma unroll
+  for (int j = 1; j < NA; ++j) acc.a[j] = fma(w, e.a[j], acc.a[j]);
+  acc.bad += e.bad;
+}
+
 template <class M, bool GRAD>
 struct Pass {
   using C = std::conditional_t<M::PREC == 1, Consts32<M>, Consts<M>>;
   using A = std::conditional_t<M::PREC == 1, Acc32<M, GRAD>, Acc<M, GRAD>>;
+};
+template <class B, bool GRAD>
+struct Pass<Weighted<B>, GRAD> {
+  using C = Consts<B>;
+  using A = AccW<Weighted<B>, GRAD>;
 };
 
 }  // namespace nllmi

@@ -66,6 +66,9 @@ struct nll_model {
 
   const double* cols[nllmi::kMaxObs] = {};
   int64_t n = -1;
+  const double* weights = nullptr;  // per-event weights (borrowed), or none
+  double* wsum = nullptr;           // their sum W (device, 1)
+  double* wsum_part = nullptr;      // per-block partials of W (device)
   nll_schedule sched{4, 2, 16384, 16, 2};
 
   // single dataset
