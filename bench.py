@@ -400,6 +400,33 @@ def extras(torch, nllmi, datagen, args):
                       "schedule": m.schedule}
     del m
     torch.cuda.empty_cache()
+    # weighted events on the headline mixture: the 1e7 events with weights
+    # in [0.5, 1.5] (16 bytes per event, one logarithm more), and a binned
+    # fit of the same events (1e4 bins of [0, 10], centres weighted by the
+    # counts)
+    w = datagen.workload(2)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    m.set_weights(torch.from_numpy(0.5 + datagen.uniforms(5, 12, w["n"])).cuda())
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(m.n_param, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: m.eval_grad(th, out=out, grad=g), 20)
+    r = timed_fit(torch, m, w["points"][0], 50, 5)
+    xc, cnt = datagen.binned(w["cols"][0], 0.0, 10.0, 10_000)
+    mb = nllmi.Model.from_spec(w["spec"])
+    mb.set_data([torch.from_numpy(xc).cuda()])
+    mb.set_weights(torch.from_numpy(cnt).cuda())
+    tb = time_launches(torch, lambda: mb.eval_grad(th, out=out, grad=g), 50)
+    rb = timed_fit(torch, mb, w["points"][0], 200, 10)
+    ex["weighted_c2_1e7"] = {"n_events": w["n"], "eval_grad_ms": tg, "events_per_s": w["n"] / (tg * 1e-3),
+                             "achieved_GBs": 16.0 * w["n"] / (tg * 1e-3) / 1e9,
+                             "fit_ms_per_step": 1e3 * r["wall_s"] / 50, "fit_status": r["status"],
+                             "binned_10000_bins": {"eval_grad_us": 1e3 * tb,
+                                                   "fit_us_per_step": 1e6 * rb["wall_s"] / 200,
+                                                   "fit_status": rb["status"]}}
+    del m, mb
+    torch.cuda.empty_cache()
     # 2-D CB/ARGUS x Chebyshev, 5e7 events, 9 free parameters
     log("c3: generating 5e7 events")
     w = datagen.workload(3)
