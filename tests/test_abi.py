@@ -48,6 +48,7 @@ def test_argument_errors_without_device(L):
     assert L.nll_sync(None, None) == -1
     assert L.nll_set_schedule(None, None) == -1
     assert L.nll_get_info(None, None) == -1
+    assert L.nll_set_weights(None, None) == -1
     L.nll_destroy_model(None)  # no-op
 
 
