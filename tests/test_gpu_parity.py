@@ -348,3 +348,40 @@ def test_single_leaf_shapes(torch, nllmi, threads, kind, params, lo, hi, norm):
     if kind == "cb" and norm == "gl256_single":
         pytest.skip("single-panel quadrature across the Crystal Ball junction is not accurate to 1e-12 (by design)")
     check_points(torch, nllmi, spec, cols, points, threads)
+
+
+def test_fit_toys_full_c4_sampled(torch, nllmi, threads):
+    """The benchmarked batched fit at full size: 4096 toys (4.1e8 events),
+    50 gradient-descent steps in one recorded graph, with the launch
+    schedule the benchmark times.  Eight sampled toys (the smallest, the
+    largest and six seeded ones) equal the oracle's fit of that toy alone;
+    every toy lands on its closed-form MLE."""
+    w = datagen.toys_workload()
+    n_sets = 4096
+    print("[fit toys 4096 x 50]", flush=True)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    m.set_schedule(unroll=4, blocks_per_cu=2, tile_events=16384, sets_blocks_per_cu=2, sets_unroll=4)
+    start = np.tile(w["theta_start"], (n_sets, 1))
+    th, nll, g, status = m.fit_batched(torch.from_numpy(w["offsets"]), torch.from_numpy(start), 50, 1.0)
+    th, nll, status = th.cpu().numpy(), nll.cpu().numpy(), status.cpu().numpy()
+    assert np.all(status == 0)
+    sizes = w["sizes"]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))} |
+                  set(int(v) for v in np.floor(datagen.uniforms(44, 1, 6) * n_sets)))
+    o = oracle.Oracle(w["spec"])
+    x = w["cols"][0]
+    for s in pick:
+        a, b = w["offsets"][s], w["offsets"][s + 1]
+        st, th_o, nll_o, g_o, eta_o = o.gd_fit([x[a:b]], w["theta_start"], 50, 1.0, threads=threads)
+        assert st == 0
+        np.testing.assert_allclose(th[s], th_o, rtol=1e-9, err_msg=f"toy {s}")
+        assert abs(nll[s] - nll_o) <= NLL_TOL * abs(nll_o), (s, nll[s], nll_o)
+    # every toy: mean and standard deviation of its events (closed-form MLE)
+    off = w["offsets"]
+    sums = np.add.reduceat(x, off[:-1])
+    mean = sums / sizes
+    dev = x - np.repeat(mean, sizes)
+    sd = np.sqrt(np.add.reduceat(dev * dev, off[:-1]) / sizes)
+    np.testing.assert_allclose(th[:, 0], mean, rtol=0, atol=1e-7 * np.maximum(1.0, np.abs(mean)).max())
+    np.testing.assert_allclose(th[:, 1], sd, rtol=1e-7)
