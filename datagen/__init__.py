@@ -299,6 +299,63 @@ def signed_weights(n: int, seed: int, lo: float = -0.5, hi: float = 1.5) -> np.n
     return lo + (hi - lo) * uniforms(seed, 11, n)
 
 
+HF_SEED = MASTER_SEED + 8000
+
+
+def hf_workload(n_bins: int = 2_000_000, n_samples: int = 4, n_histosys: int = 16, n_normsys: int = 4,
+                n_points: int = 4, seed: int = HF_SEED) -> dict:
+    """A binned template model of HistFactory type: n_bins bins in channels
+    of 100; sample 0 a Gaussian peak per channel (signal), the others
+    exponentially falling backgrounds; histosys h on sample h % S with up and
+    down templates tilted by +-(2..10) % across the channel; normsys k on
+    sample k % S with hi = 1 + U[0.02, 0.1], lo = 1 - U[0.02, 0.1];
+    normfactors mu_sig (sample 0) and mu_bkg (sample 1), unconstrained; the
+    alphas constrained.  Counts are Poisson with means sum_s T_sb (all
+    modifiers at their nominal values), from numpy's Philox generator.
+    Parameter points: mu's jittered by 10 %, alphas uniform in [-1.5, 1.5]."""
+    S, H, K = n_samples, n_histosys, n_normsys
+    x = (np.arange(n_bins) % 100 + 0.5) / 100.0
+    ch = np.arange(n_bins) // 100
+    u = uniforms(seed, 21, 4 * S + 3 * H + 2 * K + 16)
+    nominal = []
+    for s in range(S):
+        if s == 0:
+            nominal.append(20.0 * np.exp(-0.5 * ((x - 0.5) / 0.08) ** 2))
+        else:
+            tau = 0.2 + 0.6 * u[s]
+            amp = 50.0 + 100.0 * u[S + s]
+            nominal.append(amp * np.exp(-x / tau) * (1.0 + 0.1 * np.cos(0.37 * ch)) + 1.0)
+    up, down, mods = [], [], []
+    params = [param("mu_sig", 1.0, 0.0, 10.0), param("mu_bkg", 1.0, 0.0, 10.0)]
+    for k in range(2):
+        params[k]["constrained"] = False
+    mods.append({"type": "normfactor", "sample": 0, "param": 0})
+    mods.append({"type": "normfactor", "sample": 1 % S, "param": 1})
+    for h in range(H):
+        s = h % S
+        e_up, e_dn = 0.02 + 0.08 * u[2 * S + h], 0.02 + 0.08 * u[2 * S + H + h]
+        tilt = (x - 0.5) * (1.0 if u[2 * S + 2 * H + h] < 0.5 else -1.0)
+        up.append(nominal[s] * (1.0 + e_up * (1.0 + tilt)))
+        down.append(nominal[s] * (1.0 - e_dn * (1.0 - tilt)))
+        p = len(params)
+        params.append(param(f"alpha_h{h}", 0.0, -5.0, 5.0, jitter=1.5))
+        params[p]["constrained"] = True
+        mods.append({"type": "histosys", "sample": s, "param": p})
+    for k in range(K):
+        p = len(params)
+        params.append(param(f"alpha_n{k}", 0.0, -5.0, 5.0, jitter=1.5))
+        params[p]["constrained"] = True
+        mods.append({"type": "normsys", "sample": k % S, "param": p,
+                     "hi": 1.02 + 0.08 * u[2 * S + 3 * H + k], "lo": 0.98 - 0.08 * u[2 * S + 3 * H + K + k]})
+    spec = {"n_bins": n_bins, "samples": [f"s{s}" for s in range(S)], "params": params, "modifiers": mods}
+    lam = np.sum(nominal, axis=0)
+    counts = np.random.Generator(np.random.Philox(key=seed)).poisson(lam).astype(np.float64)
+    theta = theta_of(spec)
+    pts = jittered_points(theta, n_points, seed + 1, widths=jitter_widths(spec))
+    return {"spec": spec, "counts": counts, "nominal": nominal, "up": up, "down": down,
+            "theta": theta, "points": pts, "seed": seed}
+
+
 def data_seed(config: int) -> int:
     return MASTER_SEED + 1000 * config
 
