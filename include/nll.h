@@ -321,6 +321,82 @@ nll_status nll_get_info(const nll_model* model, nll_info* out);
 
 const char* nll_status_string(nll_status status);
 
+/* ------------------------------------------------------------------------
+ * Binned template likelihood of HistFactory type (the binned models the
+ * paper names as the next target of its work, Summary; HistFactory builds
+ * models from histograms, Sec. 1).  The paper defines no formulas; the
+ * reading follows the HistFactory definitions:
+ *   bins b (channels concatenated), observed counts n_b >= 0, samples s with
+ *   nominal expected counts T_sb, and modifiers, each acting on one sample
+ *   through one parameter (a parameter may drive several):
+ *     NLL_HF_NORMFACTOR  the sample times theta_p
+ *     NLL_HF_NORMSYS     the sample times hi^a (a >= 0) or lo^-a (a < 0),
+ *                        a = theta_p; hi, lo > 0
+ *     NLL_HF_HISTOSYS    the sample's bins plus a (up_b - T_sb) (a >= 0) or
+ *                        a (T_sb - down_b) (a < 0)
+ *   nu_b = sum_s (product of the sample's factors) (T_sb + histosys terms)
+ *   NLL  = sum_b (nu_b - n_b ln nu_b) + 1/2 sum_{constrained p} theta_p^2
+ *   (a bin with n_b = 0 contributes nu_b; no ln n_b! terms; unit Gaussian
+ *   constraints without their normalisation).  The derivative at a = 0 is
+ *   the a >= 0 side's.  A parameter outside [lo, hi] gives +inf and
+ *   NLL_ERR_PARAM_RANGE, nu_b < 0 or nu_b = 0 with n_b > 0 gives +inf and
+ *   NLL_ERR_INVALID_PDF, both through nll_hf_sync.
+ * Limits: 1..8 samples, <= 24 histosys, <= 16 normsys, <= 8 normfactor
+ * modifiers, 1..32 parameters.
+ * ---------------------------------------------------------------------- */
+enum nll_hf_modifier_type { NLL_HF_NORMFACTOR = 1, NLL_HF_NORMSYS = 2, NLL_HF_HISTOSYS = 3 };
+
+typedef struct nll_hf_modifier {
+  int32_t type;    /* nll_hf_modifier_type */
+  int32_t sample;  /* 0 .. n_samples-1 */
+  int32_t param;   /* 0 .. n_param-1 */
+  double hi, lo;   /* NLL_HF_NORMSYS only */
+} nll_hf_modifier;
+
+typedef struct nll_hf_desc {
+  int64_t n_bins;
+  int32_t n_samples;
+  int32_t n_param;
+  const double* param_lo;            /* n_param (host) */
+  const double* param_hi;
+  const uint8_t* param_free;         /* n_param, 0: fixed (gradient entry 0) */
+  const uint8_t* param_constrained;  /* n_param, 1: + theta^2/2 */
+  int32_t n_modifiers;
+  const nll_hf_modifier* modifiers;  /* n_modifiers (host) */
+  int32_t device;
+  void* stream;                      /* hipStream_t, 0 = default stream */
+} nll_hf_desc;
+
+typedef struct nll_hf_model nll_hf_model; /* opaque, owned by the library */
+
+/* Validate the descriptor and allocate the model's device scratch.
+ * Descriptor arrays are copied.  Errors: NLL_ERR_ARG (bad counts or
+ * indices, hi or lo <= 0), NLL_ERR_UNSUPPORTED (beyond the limits),
+ * NLL_ERR_DEVICE, NLL_ERR_OOM. */
+nll_status nll_hf_create(const nll_hf_desc* desc, nll_hf_model** out);
+
+/* Release the model (waits for its stream). */
+void nll_hf_destroy(nll_hf_model* model);
+
+/* Attach the data (device arrays of n_bins doubles): counts, nominal[s] for
+ * every sample, and up[h], down[h] for the h-th histosys modifier in
+ * modifier order (may be NULL without histosys).  counts and nominal are
+ * borrowed until the next nll_hf_set_data or nll_hf_destroy; the histosys
+ * templates are read once into the library's delta templates up - T and
+ * T - down (2 n_bins doubles per histosys).  Validates the counts
+ * (finite, >= 0) and SYNCHRONISES the stream: NLL_ERR_DOMAIN otherwise. */
+nll_status nll_hf_set_data(nll_hf_model* model, const double* counts, const double* const* nominal,
+                           const double* const* up, const double* const* down);
+
+/* Enqueue: NLL at theta (device [n_param]) into *nll_out (device [1]) and,
+ * if grad_out is not NULL, its gradient (device [n_param]).  One streaming
+ * pass over the bins (8 (1 + samples + histosys) bytes per bin) and one
+ * finishing block. */
+nll_status nll_hf_eval(nll_hf_model* model, const double* theta, double* nll_out, double* grad_out);
+
+/* Synchronise and return (and clear) the device status (as nll_sync). */
+nll_status nll_hf_sync(nll_hf_model* model, int32_t* status_out);
+
 #ifdef __cplusplus
 }
 #endif

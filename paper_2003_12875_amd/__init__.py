@@ -18,7 +18,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-from ._native import (MAX_NODE_CHILDREN, MAX_NODE_PARAMS, NLLError, NodeDesc, ModelDesc, Schedule, Info,
+from ._native import (HF_MODIFIER, HFDesc, HFModifier, MAX_NODE_CHILDREN, MAX_NODE_PARAMS, NLLError, NodeDesc,
+                      ModelDesc, Schedule, Info,
                       STATUS, check, lib, LIB_PATH)
 
 KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9}
@@ -355,6 +356,91 @@ class Model:
         return {"variant": i.variant.decode(), "n_leaf": i.n_leaf, "n_term": i.n_term,
                 "n_accumulators": i.n_accumulators, "precision": i.precision, "n_cu": i.n_cu,
                 "n_events": i.n_events}
+
+
+class HFModel:
+    """A binned template likelihood of HistFactory type on one device
+    (``nll_hf_model``), bound to the current torch stream at creation."""
+
+    def __init__(self, spec: dict, device: int = 0):
+        """spec: {"n_bins": B, "samples": [names], "params": [{"name",
+        "value", "lo", "hi", "free", "constrained"}...], "modifiers":
+        [{"type": "normfactor"|"normsys"|"histosys", "sample": s,
+        "param": p, ("hi", "lo" for normsys)}...]}"""
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        params, mods = spec["params"], spec["modifiers"]
+        P, M = len(params), len(mods)
+        self.n_param, self.n_samples, self.n_bins = P, len(spec["samples"]), int(spec["n_bins"])
+        self.n_histosys = sum(1 for m in mods if m["type"] == "histosys")
+        plo = (ctypes.c_double * P)(*[float(p["lo"]) for p in params])
+        phi = (ctypes.c_double * P)(*[float(p["hi"]) for p in params])
+        pfree = (ctypes.c_uint8 * P)(*[1 if p.get("free", True) else 0 for p in params])
+        pcon = (ctypes.c_uint8 * P)(*[1 if p.get("constrained", False) else 0 for p in params])
+        md = (HFModifier * max(M, 1))()
+        for i, m in enumerate(mods):
+            md[i].type = HF_MODIFIER[m["type"]]
+            md[i].sample, md[i].param = int(m["sample"]), int(m["param"])
+            md[i].hi, md[i].lo = float(m.get("hi", 1.0)), float(m.get("lo", 1.0))
+        d = HFDesc()
+        d.n_bins, d.n_samples, d.n_param = self.n_bins, self.n_samples, P
+        d.param_lo, d.param_hi, d.param_free, d.param_constrained = plo, phi, pfree, pcon
+        d.n_modifiers, d.modifiers = M, md
+        d.device = device
+        d.stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        handle = ctypes.c_void_p()
+        check(lib().nll_hf_create(ctypes.byref(d), ctypes.byref(handle)), "nll_hf_create")
+        self._h = handle
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().nll_hf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_data(self, counts, nominal, up=(), down=()):
+        """counts[B], nominal: one [B] per sample, up/down: one [B] per
+        histosys modifier in modifier order (float64, moved to the device)."""
+        torch = _torch()
+        f64 = torch.float64
+        counts = _dev_tensor(counts, f64, self.device)
+        nominal = [_dev_tensor(t, f64, self.device) for t in nominal]
+        up = [_dev_tensor(t, f64, self.device) for t in up]
+        down = [_dev_tensor(t, f64, self.device) for t in down]
+        if len(nominal) != self.n_samples or len(up) != self.n_histosys or len(down) != self.n_histosys:
+            raise NLLError(-1, "one nominal per sample and one up/down pair per histosys required")
+        if any(t.numel() != self.n_bins for t in [counts, *nominal, *up, *down]):
+            raise NLLError(-1, "every template needs n_bins entries")
+        ptrs = lambda ts: (ctypes.c_void_p * max(len(ts), 1))(*[t.data_ptr() for t in ts])
+        check(lib().nll_hf_set_data(self._h, counts.data_ptr(), ptrs(nominal), ptrs(up), ptrs(down)),
+              "nll_hf_set_data")
+        self._keep = (counts, nominal)  # borrowed by the library
+
+    def eval(self, theta, out=None):
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        check(lib().nll_hf_eval(self._h, theta.data_ptr(), out.data_ptr(), None), "nll_hf_eval")
+        return out
+
+    def eval_grad(self, theta, out=None, grad=None):
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        grad = torch.empty(self.n_param, dtype=torch.float64, device=self.device) if grad is None else grad
+        check(lib().nll_hf_eval(self._h, theta.data_ptr(), out.data_ptr(), grad.data_ptr()), "nll_hf_eval")
+        return out, grad
+
+    def sync(self) -> int:
+        st = ctypes.c_int32(0)
+        check(lib().nll_hf_sync(self._h, ctypes.byref(st)), "nll_hf_sync")
+        return st.value
 
 
 def _nll_function():

@@ -18,7 +18,10 @@ EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_d
            "nll_eval_grad", "nll_eval_batched", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_eval_bhhh",
            "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
            "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
-           "nll_status_string")
+           "nll_status_string", "nll_hf_create", "nll_hf_destroy", "nll_hf_set_data", "nll_hf_eval", "nll_hf_sync")
+
+HF_MAX_SAMPLES, HF_MAX_HISTOSYS = 8, 24
+HF_MODIFIER = {"normfactor": 1, "normsys": 2, "histosys": 3}
 
 
 class NLLError(RuntimeError):
@@ -41,6 +44,19 @@ class ModelDesc(ctypes.Structure):
                 ("nodes", ctypes.POINTER(NodeDesc)), ("root", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("extended", ctypes.c_int32), ("yield_param", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
+
+
+class HFModifier(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("sample", ctypes.c_int32), ("param", ctypes.c_int32),
+                ("hi", ctypes.c_double), ("lo", ctypes.c_double)]
+
+
+class HFDesc(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int64), ("n_samples", ctypes.c_int32), ("n_param", ctypes.c_int32),
+                ("param_lo", ctypes.POINTER(ctypes.c_double)), ("param_hi", ctypes.POINTER(ctypes.c_double)),
+                ("param_free", ctypes.POINTER(ctypes.c_uint8)), ("param_constrained", ctypes.POINTER(ctypes.c_uint8)),
+                ("n_modifiers", ctypes.c_int32), ("modifiers", ctypes.POINTER(HFModifier)),
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class Schedule(ctypes.Structure):
@@ -90,8 +106,14 @@ def lib():
         L.nll_step_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         L.nll_status_string.argtypes = [i32]
         L.nll_status_string.restype = ctypes.c_char_p
+        L.nll_hf_create.argtypes = [ctypes.POINTER(HFDesc), ctypes.POINTER(vp)]
+        L.nll_hf_destroy.argtypes = [vp]
+        L.nll_hf_destroy.restype = None
+        L.nll_hf_set_data.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.nll_hf_eval.argtypes = [vp, vp, vp, vp]
+        L.nll_hf_sync.argtypes = [vp, ctypes.POINTER(i32)]
         for f in EXPORTS:
-            if f not in ("nll_destroy_model", "nll_status_string"):
+            if f not in ("nll_destroy_model", "nll_status_string", "nll_hf_destroy"):
                 getattr(L, f).restype = ctypes.c_int32
         _lib = L
     return _lib

@@ -1,0 +1,60 @@
+// histfactory.h -- plain data of the binned template likelihood (the
+// HistFactory-type binned models the paper names as the next target of its
+// work, Summary; built from histograms, Sec. 1), shared by the host runtime
+// and the device kernels.
+//
+//   nu_b = sum_s F_s(theta) T_sb + sum_h c_h(theta) d_hb
+//   NLL  = sum_b (nu_b - n_b ln nu_b) + 1/2 sum_{constrained p} theta_p^2
+//
+// F_s: the sample's normfactors times its normsys factors
+// (eta = hi^alpha for alpha >= 0, lo^-alpha below); histosys h on sample
+// s_h with parameter alpha_h adds alpha_h (up - T) or alpha_h (T - down)
+// to the sample's bins, i.e. c_h = F_{s_h} alpha_h times the delta template
+// d_hb of alpha_h's side.  The streaming pass accumulates, besides the
+// NLL, the per-sample sums ST_s = sum_b w_b T_sb and per-histosys sums
+// SD_h = sum_b w_b d_hb with w_b = 1 - n_b/nu_b; every parameter
+// derivative is assembled from them after the reduction.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "plan.h"
+
+namespace nllmi {
+
+constexpr int kHfMaxSamples = 8;
+constexpr int kHfMaxHisto = 24;
+constexpr int kHfMaxNormsys = 16;
+constexpr int kHfMaxNormfactor = 8;
+// block record: NLL, ST_s, SD_h, invalid-bin count
+constexpr int kHfNV = 1 + kHfMaxSamples + kHfMaxHisto + 1;
+
+struct HFPlan {
+  int32_t n_samples, n_histo, n_normsys, n_normfactor, n_param;
+  int32_t histo_sample[kHfMaxHisto], histo_param[kHfMaxHisto];
+  int32_t ns_sample[kHfMaxNormsys], ns_param[kHfMaxNormsys];
+  double ns_lnhi[kHfMaxNormsys], ns_lnlo[kHfMaxNormsys];
+  int32_t nf_sample[kHfMaxNormfactor], nf_param[kHfMaxNormfactor];
+  double par_lo[kMaxParams], par_hi[kMaxParams];
+  int32_t par_free[kMaxParams], par_constrained[kMaxParams];
+};
+
+struct HFArgs {
+  int64_t n_bins;
+  const double* counts;                 // n_b (caller's)
+  const double* nominal[kHfMaxSamples]; // T_sb (caller's)
+  const double* dup[kHfMaxHisto];       // up - T (library's)
+  const double* ddn[kHfMaxHisto];       // T - down (library's)
+  const double* theta;                  // n_param
+  double* nll_out;
+  double* grad_out;                     // n_param or null
+  double* partials;                     // grid * kHfNV double-double pairs
+  int* status;                          // accumulated status bits
+};
+
+hipError_t launch_hf_deltas(const double* nominal, const double* up, const double* down, int64_t n, double* dup,
+                            double* ddn, hipStream_t st);
+hipError_t launch_hf_eval(const HFPlan& pl, const HFArgs& a, bool grad, int grid, hipStream_t st);
+
+}  // namespace nllmi

@@ -1,0 +1,228 @@
+// histfactory.hip -- the binned template likelihood on the device: a
+// persistent streaming pass over the bins (one load per template and bin,
+// coalesced) and a finishing block.  HBM-bound: 8 (1 + S + H) bytes per bin.
+#include <hip/hip_runtime.h>
+
+#include "fp64.h"
+#include "histfactory.h"
+#include "kernels.h"
+#include "reduce.h"
+
+namespace nllmi {
+
+// Delta templates of one histosys: up - T and T - down, once at attachment.
+__global__ __launch_bounds__(kBlock) void k_hf_deltas(const double* __restrict__ nominal,
+                                                      const double* __restrict__ up,
+                                                      const double* __restrict__ down, int64_t n,
+                                                      double* __restrict__ dup, double* __restrict__ ddn) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double t = nominal[i];
+    dup[i] = up[i] - t;
+    ddn[i] = t - down[i];
+  }
+}
+
+// F_s: the normfactors and normsys factors of sample s at theta.  Shared by
+// both kernels, so that they use the same bits.
+__device__ inline double hf_factor(const HFPlan& pl, const double* theta, int s) {
+  double f = 1.0;
+  for (int i = 0; i < pl.n_normfactor; ++i)
+    if (pl.nf_sample[i] == s) f *= theta[pl.nf_param[i]];
+  for (int k = 0; k < pl.n_normsys; ++k)
+    if (pl.ns_sample[k] == s) {
+      const double a = theta[pl.ns_param[k]];
+      f *= exp(a >= 0.0 ? a * pl.ns_lnhi[k] : -a * pl.ns_lnlo[k]);
+    }
+  return f;
+}
+
+// lane 0's value for the whole wave (kept in scalar registers)
+__device__ inline double hf_uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ inline const double* hf_uniform(const double* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return reinterpret_cast<const double*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline bool hf_in_range(const HFPlan& pl, const double* theta) {
+  bool ok = true;
+  for (int p = 0; p < pl.n_param; ++p) ok = ok && theta[p] >= pl.par_lo[p] && theta[p] <= pl.par_hi[p];
+  return ok;
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan pl, const HFArgs a) {
+  constexpr int NH = kHfNV / 2, NH2 = kHfNV - NH;  // two reduction passes
+  __shared__ double s_theta[kMaxParams];
+  __shared__ double s_F[kHfMaxSamples], s_c[kHfMaxHisto];
+  __shared__ int s_side[kHfMaxHisto];
+  __shared__ int s_ok;
+  __shared__ double red[(NH2 > NH ? NH2 : NH) * (kBlock + 1)];
+  __shared__ DD tot[kHfNV];
+  const int t = threadIdx.x;
+  if (t < pl.n_param) s_theta[t] = a.theta[t];
+  __syncthreads();
+  if (t < kHfMaxSamples) s_F[t] = t < pl.n_samples ? hf_factor(pl, s_theta, t) : 0.0;
+  if (t == 64) s_ok = hf_in_range(pl, s_theta);
+  __syncthreads();
+  if (t < kHfMaxHisto) {
+    const bool on = t < pl.n_histo;
+    const double al = on ? s_theta[pl.histo_param[t]] : 0.0;
+    s_c[t] = on ? s_F[pl.histo_sample[t]] * al : 0.0;
+    s_side[t] = al >= 0.0;
+  }
+  __syncthreads();
+  const int S = pl.n_samples, H = pl.n_histo;
+  double F[kHfMaxSamples], c[kHfMaxHisto];
+  const double* dp[kHfMaxHisto];
+#pragma unroll
+  for (int s = 0; s < kHfMaxSamples; ++s) F[s] = hf_uniform(s_F[s]);
+#pragma unroll
+  for (int h = 0; h < kHfMaxHisto; ++h) {
+    c[h] = hf_uniform(s_c[h]);
+    dp[h] = hf_uniform(s_side[h] ? a.dup[h] : a.ddn[h]);
+  }
+  double acc[kHfNV - 1];
+#pragma unroll
+  for (int j = 0; j < kHfNV - 1; ++j) acc[j] = 0.0;
+  int bad = 0;
+  if (s_ok) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t b = (int64_t)blockIdx.x * kBlock + t; b < a.n_bins; b += stride) {
+      const double n = a.counts[b];
+      double T[kHfMaxSamples], d[kHfMaxHisto];
+#pragma unroll
+      for (int s = 0; s < kHfMaxSamples; ++s) T[s] = s < S ? a.nominal[s][b] : 0.0;
+#pragma unroll
+      for (int h = 0; h < kHfMaxHisto; ++h) d[h] = h < H ? dp[h][b] : 0.0;
+      double nu = 0.0;
+#pragma unroll
+      for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(F[s], T[s], nu);
+#pragma unroll
+      for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(c[h], d[h], nu);
+      const bool pos = n > 0.0;
+      bad += !(nu >= 0.0) || (pos && !(nu > 0.0));
+      // n = 0: the bin contributes nu and no logarithm
+      const double lnu = pos && nu > 0.0 ? log_pos(nu) : 0.0;
+      acc[0] += fma(-n, lnu, nu);
+      if constexpr (GRAD) {
+        const double w = pos ? fma(-n, rcp_full(nu), 1.0) : 1.0;
+#pragma unroll
+        for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(w, T[s], acc[1 + s]);
+#pragma unroll
+        for (int h = 0; h < kHfMaxHisto; ++h) acc[1 + kHfMaxSamples + h] = fma(w, d[h], acc[1 + kHfMaxSamples + h]);
+      }
+    }
+  }
+  double v0[NH], v1[NH2];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) v0[j] = acc[j];
+#pragma unroll
+  for (int j = 0; j < NH2 - 1; ++j) v1[j] = acc[NH + j];
+  v1[NH2 - 1] = (double)bad;
+  block_sum_vals<NH, kBlock>(v0, red, tot);
+  block_sum_vals<NH2, kBlock>(v1, red, tot + NH);
+  if (t < kHfNV) reinterpret_cast<DD*>(a.partials)[(size_t)blockIdx.x * kHfNV + t] = tot[t];
+}
+
+// Finishing block: the partials in block order, then NLL, status and the
+// gradient from the per-sample and per-histosys sums:
+//   SA_s = ST_s + sum_{h on s} alpha_h SD_h  (= sum_b w_b (T_sb + deltas))
+//   normfactor mu on s:  (F_s / mu) SA_s, F_s / mu formed as the product of
+//                        the sample's other factors
+//   normsys alpha on s:  F_s L SA_s, L = ln hi (alpha >= 0) or -ln lo
+//   histosys h:          F_{s_h} SD_h
+//   constrained p:       + theta_p
+template <bool GRAD>
+__global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan pl, const HFArgs a, int n_blocks) {
+  __shared__ DD tot[kHfNV];
+  __shared__ double s_theta[kMaxParams], s_F[kHfMaxSamples], s_SA[kHfMaxSamples];
+  const int t = threadIdx.x;
+  if (t < pl.n_param) s_theta[t] = a.theta[t];
+  RecordSum<kHfNV, kFinishBlock> rs;
+  rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
+  __syncthreads();
+  if (t < kHfMaxSamples) s_F[t] = t < pl.n_samples ? hf_factor(pl, s_theta, t) : 0.0;
+  rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
+  const auto val = [&](int j) { return tot[j].hi + tot[j].lo; };
+  const bool ok = hf_in_range(pl, s_theta);
+  const double bad_bins = val(kHfNV - 1);
+  double nll = val(0);
+  for (int p = 0; p < pl.n_param; ++p)
+    if (pl.par_constrained[p]) nll += 0.5 * s_theta[p] * s_theta[p];
+  int status = 0;
+  if (!ok) status = -3;
+  else if (bad_bins > 0.0 || !__builtin_isfinite(nll)) status = -5;
+  if (status != 0) nll = __builtin_inf();
+  if (t < kHfMaxSamples) {
+    double sa = 0.0;
+    if (t < pl.n_samples) {
+      sa = val(1 + t);
+      for (int h = 0; h < pl.n_histo; ++h)
+        if (pl.histo_sample[h] == t) sa = fma(s_theta[pl.histo_param[h]], val(1 + kHfMaxSamples + h), sa);
+    }
+    s_SA[t] = sa;
+  }
+  __syncthreads();
+  if (t == 0) {
+    *a.nll_out = nll;
+    if (status == -3) atomicOr(a.status, (int)kStatusParam);
+    if (status == -5) atomicOr(a.status, (int)kStatusPdf);
+  }
+  if (GRAD && a.grad_out && t < pl.n_param) {
+    const int q = t;
+    double g = 0.0;
+    if (status == 0) {
+      for (int i = 0; i < pl.n_normfactor; ++i) {
+        if (pl.nf_param[i] != q) continue;
+        const int s = pl.nf_sample[i];
+        double others = 1.0;  // the sample's factors except this one
+        for (int j = 0; j < pl.n_normfactor; ++j)
+          if (j != i && pl.nf_sample[j] == s) others *= s_theta[pl.nf_param[j]];
+        for (int k = 0; k < pl.n_normsys; ++k)
+          if (pl.ns_sample[k] == s) {
+            const double al = s_theta[pl.ns_param[k]];
+            others *= exp(al >= 0.0 ? al * pl.ns_lnhi[k] : -al * pl.ns_lnlo[k]);
+          }
+        g = fma(others, s_SA[s], g);
+      }
+      for (int k = 0; k < pl.n_normsys; ++k) {
+        if (pl.ns_param[k] != q) continue;
+        const int s = pl.ns_sample[k];
+        const double L = s_theta[q] >= 0.0 ? pl.ns_lnhi[k] : -pl.ns_lnlo[k];
+        g = fma(s_F[s] * L, s_SA[s], g);
+      }
+      for (int h = 0; h < pl.n_histo; ++h)
+        if (pl.histo_param[h] == q) g = fma(s_F[pl.histo_sample[h]], val(1 + kHfMaxSamples + h), g);
+      if (pl.par_constrained[q]) g += s_theta[q];
+    }
+    a.grad_out[q] = pl.par_free[q] ? g : 0.0;
+  }
+}
+
+hipError_t launch_hf_deltas(const double* nominal, const double* up, const double* down, int64_t n, double* dup,
+                            double* ddn, hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_hf_deltas, dim3((unsigned)blocks), dim3(kBlock), 0, st, nominal, up, down, n, dup, ddn);
+  return hipGetLastError();
+}
+
+hipError_t launch_hf_eval(const HFPlan& pl, const HFArgs& a, bool grad, int grid, hipStream_t st) {
+  if (grad) hipLaunchKernelGGL((k_hf_stream<true>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  else hipLaunchKernelGGL((k_hf_stream<false>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (grad) hipLaunchKernelGGL((k_hf_finish<true>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
+  else hipLaunchKernelGGL((k_hf_finish<false>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
+  return hipGetLastError();
+}
+
+}  // namespace nllmi

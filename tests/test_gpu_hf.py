@@ -1,0 +1,133 @@
+"""GPU parity of the binned template likelihood (HistFactory type) against
+the numpy oracle: NLL 1e-12 relative; gradient 1e-8 of max(|g|, G) with G
+the largest per-parameter sum of |w_b d nu_b / d theta| (the gradient's own
+rounding scale); ragged bin counts, the benchmarked size, the limits of
+the model description, parameters shared across samples, empty bins,
+alpha exactly 0, fixed parameters, and the status conventions."""
+import copy
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import histfactory as hf
+
+pytestmark = pytest.mark.gpu
+
+NLL_TOL = 1e-12
+GRAD_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def nllmi():
+    import paper_2003_12875_amd as m
+    m.lib()
+    return m
+
+
+def make(nllmi, w, spec=None):
+    spec = spec or w["spec"]
+    m = nllmi.HFModel(spec)
+    m.set_data(w["counts"], w["nominal"], w["up"], w["down"])
+    return m
+
+
+def check(torch, m, spec, w, points):
+    for th in points:
+        st, ref, gref = hf.nll(spec, w["counts"], w["nominal"], w["up"], w["down"], th)
+        assert st == hf.OK
+        nu, dnu = hf.expected(spec, w["nominal"], w["up"], w["down"], th)
+        n = w["counts"]
+        wgt = np.where(n > 0, 1.0 - n / np.where(nu > 0, nu, 1.0), 1.0)
+        G = max(float(np.sum(np.abs(wgt * d))) for d in dnu) if len(dnu) else 0.0
+        v, g = m.eval_grad(torch.from_numpy(np.ascontiguousarray(th)))
+        v, g = float(v.item()), g.cpu().numpy()
+        assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), G), (th, g, gref)
+        v1 = float(m.eval(torch.from_numpy(np.ascontiguousarray(th))).item())
+        assert abs(v1 - ref) <= NLL_TOL * abs(ref)
+    assert m.sync() == 0
+
+
+@pytest.mark.parametrize("n_bins", [1, 257, 100_003])
+def test_hf_small(torch, nllmi, n_bins):
+    w = datagen.hf_workload(n_bins=n_bins, n_samples=3, n_histosys=5, n_normsys=3, n_points=3)
+    print(f"[hf B={n_bins}]", flush=True)
+    check(torch, make(nllmi, w), w["spec"], w, w["points"])
+
+
+def test_hf_full(torch, nllmi):
+    """The benchmarked model: 2e6 bins, 4 samples, 16 histosys, 4 normsys."""
+    w = datagen.hf_workload(n_points=2)
+    print("[hf B=2e6]", flush=True)
+    check(torch, make(nllmi, w), w["spec"], w, w["points"])
+
+
+def test_hf_limits_and_shared_parameters(torch, nllmi):
+    """At the limits: 8 samples, 24 histosys and 32 parameters; 16 normsys;
+    then one alpha driving two histosys of different samples and one
+    normsys on two samples."""
+    w = datagen.hf_workload(n_bins=5000, n_samples=8, n_histosys=24, n_normsys=6, n_points=2)
+    assert len(w["spec"]["params"]) == 32
+    check(torch, make(nllmi, w), w["spec"], w, w["points"])
+    w = datagen.hf_workload(n_bins=5000, n_samples=5, n_histosys=8, n_normsys=16, n_points=2)
+    check(torch, make(nllmi, w), w["spec"], w, w["points"])
+    too_many = copy.deepcopy(w["spec"])
+    too_many["modifiers"].append(dict(too_many["modifiers"][-1]))
+    with pytest.raises(nllmi.NLLError) as e:
+        nllmi.HFModel(too_many)
+    assert e.value.status == -2
+    w = datagen.hf_workload(n_bins=4099, n_samples=3, n_histosys=6, n_normsys=4, n_points=2)
+    spec = copy.deepcopy(w["spec"])
+    hs = [m for m in spec["modifiers"] if m["type"] == "histosys"]
+    ns = [m for m in spec["modifiers"] if m["type"] == "normsys"]
+    hs[1]["param"] = hs[0]["param"]
+    ns[1]["param"] = ns[0]["param"]
+    check(torch, make(nllmi, w, spec), spec, w, w["points"])
+
+
+def test_hf_empty_bins_alpha_zero_and_fixed(torch, nllmi):
+    w = datagen.hf_workload(n_bins=3001, n_samples=3, n_histosys=4, n_normsys=2, n_points=2)
+    w["counts"][::7] = 0.0
+    spec = copy.deepcopy(w["spec"])
+    spec["params"][3]["free"] = False
+    pts = w["points"].copy()
+    pts[:, 2] = 0.0  # alpha exactly 0: the upper side's derivative
+    pts[1, 4] = -0.0
+    m = make(nllmi, w, spec)
+    check(torch, m, spec, w, pts)
+    g = m.eval_grad(torch.from_numpy(pts[0]))[1].cpu().numpy()
+    assert g[3] == 0.0
+
+
+def test_hf_status_conventions(torch, nllmi):
+    w = datagen.hf_workload(n_bins=2000, n_samples=2, n_histosys=2, n_normsys=1, n_points=1)
+    m = make(nllmi, w)
+    th = w["points"][0].copy()
+    th[2] = 7.0  # alpha outside [-5, 5]
+    assert math.isinf(m.eval(torch.from_numpy(th)).item()) and m.sync() == -3
+    th = w["points"][0].copy()
+    th[0] = th[1] = 0.0  # every normfactor 0: nu = 0 where n > 0
+    assert math.isinf(m.eval(torch.from_numpy(th)).item()) and m.sync() == -5
+    assert m.sync() == 0
+    bad = w["counts"].copy()
+    bad[5] = -1.0
+    with pytest.raises(nllmi.NLLError) as e:
+        m.set_data(bad, w["nominal"], w["up"], w["down"])
+    assert e.value.status == -4
+    spec = copy.deepcopy(w["spec"])
+    spec["n_bins"] = 0
+    m0 = nllmi.HFModel(spec)
+    m0.set_data([], [[]] * 2, [[]] * 2, [[]] * 2)
+    th = w["points"][0]
+    cons = 0.5 * sum(th[p] ** 2 for p, par in enumerate(spec["params"]) if par["constrained"])
+    assert abs(m0.eval(torch.from_numpy(th)).item() - cons) <= 1e-15 * max(cons, 1.0)
