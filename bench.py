@@ -427,6 +427,25 @@ def extras(torch, nllmi, datagen, args):
                                                    "fit_status": rb["status"]}}
     del m, mb
     torch.cuda.empty_cache()
+    # binned template likelihood of HistFactory type: 2e6 bins, 4 samples,
+    # 16 histosys, 4 normsys, 2 normfactors (22 parameters); HBM-bound,
+    # 8 (1 + 4 + 16) bytes per bin
+    w = datagen.hf_workload()
+    mh = nllmi.HFModel(w["spec"])
+    mh.set_data(w["counts"], w["nominal"], w["up"], w["down"])
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(mh.n_param, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: mh.eval_grad(th, out=out, grad=g), 20)
+    tf = time_launches(torch, lambda: mh.eval(th, out=out), 20)
+    nbytes = 8.0 * (1 + mh.n_samples + mh.n_histosys) * mh.n_bins
+    ex["histfactory_2e6_bins"] = {"n_bins": mh.n_bins, "samples": mh.n_samples, "histosys": mh.n_histosys,
+                                  "params": mh.n_param, "eval_grad_ms": tg, "eval_ms": tf,
+                                  "bytes_per_eval": nbytes, "achieved_GBs": nbytes / (tg * 1e-3) / 1e9,
+                                  "hbm_frac": nbytes / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "status": mh.sync()}
+    del mh
+    torch.cuda.empty_cache()
     # 2-D CB/ARGUS x Chebyshev, 5e7 events, 9 free parameters
     log("c3: generating 5e7 events")
     w = datagen.workload(3)

@@ -30,21 +30,29 @@ constexpr int kHfMaxNormfactor = 8;
 // block record: NLL, ST_s, SD_h, invalid-bin count
 constexpr int kHfNV = 1 + kHfMaxSamples + kHfMaxHisto + 1;
 
+// Modifiers are sorted by sample on the host, so that sample s owns the
+// index ranges [x_start[s], x_start[s + 1]) of each kind; each parameter's
+// modifiers are listed as contribution slots (normfactors 0.., normsys
+// kHfMaxNormfactor.., histosys kHfMaxNormfactor + kHfMaxNormsys..).
+constexpr int kHfSlots = kHfMaxNormfactor + kHfMaxNormsys + kHfMaxHisto;
 struct HFPlan {
   int32_t n_samples, n_histo, n_normsys, n_normfactor, n_param;
-  int32_t histo_sample[kHfMaxHisto], histo_param[kHfMaxHisto];
-  int32_t ns_sample[kHfMaxNormsys], ns_param[kHfMaxNormsys];
-  double ns_lnhi[kHfMaxNormsys], ns_lnlo[kHfMaxNormsys];
+  int32_t nf_start[kHfMaxSamples + 1], ns_start[kHfMaxSamples + 1], hs_start[kHfMaxSamples + 1];
   int32_t nf_sample[kHfMaxNormfactor], nf_param[kHfMaxNormfactor];
-  double par_lo[kMaxParams], par_hi[kMaxParams];
+  int32_t ns_sample[kHfMaxNormsys], ns_param[kHfMaxNormsys];
+  int32_t histo_sample[kHfMaxHisto], histo_param[kHfMaxHisto];
+  int32_t par_start[kMaxParams + 1], par_slot[kHfSlots];
   int32_t par_free[kMaxParams], par_constrained[kMaxParams];
+  int32_t pad;
+  double ns_lnhi[kHfMaxNormsys], ns_lnlo[kHfMaxNormsys];
+  double par_lo[kMaxParams], par_hi[kMaxParams];
 };
 
 struct HFArgs {
   int64_t n_bins;
   const double* counts;                 // n_b (caller's)
   const double* nominal[kHfMaxSamples]; // T_sb (caller's)
-  const double* dup[kHfMaxHisto];       // up - T (library's)
+  const double* dup[kHfMaxHisto];       // up - T (library's), in sorted order
   const double* ddn[kHfMaxHisto];       // T - down (library's)
   const double* theta;                  // n_param
   double* nll_out;

@@ -23,17 +23,15 @@ __global__ __launch_bounds__(kBlock) void k_hf_deltas(const double* __restrict__
   }
 }
 
-// F_s: the normfactors and normsys factors of sample s at theta.  Shared by
-// both kernels, so that they use the same bits.
+// F_s: the normfactors and normsys factors of sample s at theta (its own
+// index ranges).  Shared by both kernels, so that they use the same bits.
 __device__ inline double hf_factor(const HFPlan& pl, const double* theta, int s) {
   double f = 1.0;
-  for (int i = 0; i < pl.n_normfactor; ++i)
-    if (pl.nf_sample[i] == s) f *= theta[pl.nf_param[i]];
-  for (int k = 0; k < pl.n_normsys; ++k)
-    if (pl.ns_sample[k] == s) {
-      const double a = theta[pl.ns_param[k]];
-      f *= exp(a >= 0.0 ? a * pl.ns_lnhi[k] : -a * pl.ns_lnlo[k]);
-    }
+  for (int i = pl.nf_start[s]; i < pl.nf_start[s + 1]; ++i) f *= theta[pl.nf_param[i]];
+  for (int k = pl.ns_start[s]; k < pl.ns_start[s + 1]; ++k) {
+    const double a = theta[pl.ns_param[k]];
+    f *= exp(a >= 0.0 ? a * pl.ns_lnhi[k] : -a * pl.ns_lnlo[k]);
+  }
   return f;
 }
 
@@ -50,15 +48,26 @@ __device__ inline const double* hf_uniform(const double* p) {
   return reinterpret_cast<const double*>(((uint64_t)hi << 32) | lo);
 }
 
-__device__ inline bool hf_in_range(const HFPlan& pl, const double* theta) {
-  bool ok = true;
-  for (int p = 0; p < pl.n_param; ++p) ok = ok && theta[p] >= pl.par_lo[p] && theta[p] <= pl.par_hi[p];
-  return ok;
+// The plan into LDS with one parallel copy: the set-up loops below look
+// fields up by runtime indices, which from the kernel-argument segment would
+// cost a dependent scalar load each.
+template <int NT>
+__device__ inline void hf_stage_plan(const HFPlan& src, HFPlan* dst) {
+  static_assert(sizeof(HFPlan) % 8 == 0, "plan copied as 8-byte words");
+  const uint2* a = reinterpret_cast<const uint2*>(&src);
+  uint2* b = reinterpret_cast<uint2*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(HFPlan) / 8); i += NT) b[i] = a[i];
+}
+
+// parameter p inside its range (one thread per parameter)
+__device__ inline bool hf_par_ok(const HFPlan& pl, const double* theta, int p) {
+  return theta[p] >= pl.par_lo[p] && theta[p] <= pl.par_hi[p];  // NaN fails
 }
 
 template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan pl, const HFArgs a) {
+__global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const HFArgs a) {
   constexpr int NH = kHfNV / 2, NH2 = kHfNV - NH;  // two reduction passes
+  __shared__ HFPlan pl;
   __shared__ double s_theta[kMaxParams];
   __shared__ double s_F[kHfMaxSamples], s_c[kHfMaxHisto];
   __shared__ int s_side[kHfMaxHisto];
@@ -66,10 +75,12 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan pl, const HFA
   __shared__ double red[(NH2 > NH ? NH2 : NH) * (kBlock + 1)];
   __shared__ DD tot[kHfNV];
   const int t = threadIdx.x;
-  if (t < pl.n_param) s_theta[t] = a.theta[t];
+  hf_stage_plan<kBlock>(plan, &pl);
+  if (t < plan.n_param) s_theta[t] = a.theta[t];
+  if (t == 0) s_ok = 1;
   __syncthreads();
   if (t < kHfMaxSamples) s_F[t] = t < pl.n_samples ? hf_factor(pl, s_theta, t) : 0.0;
-  if (t == 64) s_ok = hf_in_range(pl, s_theta);
+  if (t >= 64 && t < 64 + pl.n_param && !hf_par_ok(pl, s_theta, t - 64)) s_ok = 0;
   __syncthreads();
   if (t < kHfMaxHisto) {
     const bool on = t < pl.n_histo;
@@ -139,37 +150,85 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan pl, const HFA
 //   normsys alpha on s:  F_s L SA_s, L = ln hi (alpha >= 0) or -ln lo
 //   histosys h:          F_{s_h} SD_h
 //   constrained p:       + theta_p
+// Each modifier's term is formed by a thread of its own; a parameter's
+// thread then adds the terms of the modifiers it drives, in modifier order.
 template <bool GRAD>
-__global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan pl, const HFArgs a, int n_blocks) {
+__global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan plan, const HFArgs a, int n_blocks) {
+  __shared__ HFPlan pl;
   __shared__ DD tot[kHfNV];
-  __shared__ double s_theta[kMaxParams], s_F[kHfMaxSamples], s_SA[kHfMaxSamples];
+  __shared__ double s_theta[kMaxParams], s_cons[kMaxParams], s_F[kHfMaxSamples], s_SA[kHfMaxSamples];
+  __shared__ double s_term[kHfSlots];
+  __shared__ int s_ok;
   const int t = threadIdx.x;
-  if (t < pl.n_param) s_theta[t] = a.theta[t];
-  RecordSum<kHfNV, kFinishBlock> rs;
+  hf_stage_plan<kFinishBlock>(plan, &pl);
+  if (t < plan.n_param) s_theta[t] = a.theta[t];
+  if (t == 0) s_ok = 1;
+  // 16 lanes per value (34 values), 16 records per lane in flight: the
+  // 512 block records in two memory round trips (32 would spill at 1024
+  // threads)
+  RecordSum<kHfNV, kFinishBlock, 16> rs;
   rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
   __syncthreads();
   if (t < kHfMaxSamples) s_F[t] = t < pl.n_samples ? hf_factor(pl, s_theta, t) : 0.0;
+  if (t >= 64 && t < 64 + kMaxParams) {  // range checks and constraint terms, one thread per parameter
+    const int p = t - 64;
+    double c = 0.0;
+    if (p < pl.n_param) {
+      if (!hf_par_ok(pl, s_theta, p)) s_ok = 0;
+      if (pl.par_constrained[p]) c = 0.5 * s_theta[p] * s_theta[p];
+    }
+    s_cons[p] = c;
+  }
   rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
   const auto val = [&](int j) { return tot[j].hi + tot[j].lo; };
-  const bool ok = hf_in_range(pl, s_theta);
-  const double bad_bins = val(kHfNV - 1);
-  double nll = val(0);
-  for (int p = 0; p < pl.n_param; ++p)
-    if (pl.par_constrained[p]) nll += 0.5 * s_theta[p] * s_theta[p];
-  int status = 0;
-  if (!ok) status = -3;
-  else if (bad_bins > 0.0 || !__builtin_isfinite(nll)) status = -5;
-  if (status != 0) nll = __builtin_inf();
   if (t < kHfMaxSamples) {
     double sa = 0.0;
     if (t < pl.n_samples) {
       sa = val(1 + t);
-      for (int h = 0; h < pl.n_histo; ++h)
-        if (pl.histo_sample[h] == t) sa = fma(s_theta[pl.histo_param[h]], val(1 + kHfMaxSamples + h), sa);
+      for (int h = pl.hs_start[t]; h < pl.hs_start[t + 1]; ++h)
+        sa = fma(s_theta[pl.histo_param[h]], val(1 + kHfMaxSamples + h), sa);
     }
     s_SA[t] = sa;
   }
   __syncthreads();
+  // one thread per modifier forms its term (slot order: normfactors,
+  // normsys, histosys)
+  if (t >= 64 && t < 64 + kHfSlots) {
+    const int j = t - 64;
+    double term = 0.0;
+    if (j < kHfMaxNormfactor) {
+      if (j < pl.n_normfactor) {
+        const int s = pl.nf_sample[j];
+        double others = 1.0;  // the sample's factors except this one
+        for (int i = pl.nf_start[s]; i < pl.nf_start[s + 1]; ++i)
+          if (i != j) others *= s_theta[pl.nf_param[i]];
+        for (int k = pl.ns_start[s]; k < pl.ns_start[s + 1]; ++k) {
+          const double al = s_theta[pl.ns_param[k]];
+          others *= exp(al >= 0.0 ? al * pl.ns_lnhi[k] : -al * pl.ns_lnlo[k]);
+        }
+        term = others * s_SA[s];
+      }
+    } else if (j < kHfMaxNormfactor + kHfMaxNormsys) {
+      const int k = j - kHfMaxNormfactor;
+      if (k < pl.n_normsys) {
+        const int s = pl.ns_sample[k];
+        const double L = s_theta[pl.ns_param[k]] >= 0.0 ? pl.ns_lnhi[k] : -pl.ns_lnlo[k];
+        term = s_F[s] * L * s_SA[s];
+      }
+    } else {
+      const int h = j - kHfMaxNormfactor - kHfMaxNormsys;
+      if (h < pl.n_histo) term = s_F[pl.histo_sample[h]] * val(1 + kHfMaxSamples + h);
+    }
+    s_term[j] = term;
+  }
+  __syncthreads();
+  double nll = val(0);
+#pragma unroll
+  for (int p = 0; p < kMaxParams; ++p) nll += s_cons[p];
+  int status = 0;
+  if (!s_ok) status = -3;
+  else if (val(kHfNV - 1) > 0.0 || !__builtin_isfinite(nll)) status = -5;
+  if (status != 0) nll = __builtin_inf();
   if (t == 0) {
     *a.nll_out = nll;
     if (status == -3) atomicOr(a.status, (int)kStatusParam);
@@ -179,27 +238,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan pl, con
     const int q = t;
     double g = 0.0;
     if (status == 0) {
-      for (int i = 0; i < pl.n_normfactor; ++i) {
-        if (pl.nf_param[i] != q) continue;
-        const int s = pl.nf_sample[i];
-        double others = 1.0;  // the sample's factors except this one
-        for (int j = 0; j < pl.n_normfactor; ++j)
-          if (j != i && pl.nf_sample[j] == s) others *= s_theta[pl.nf_param[j]];
-        for (int k = 0; k < pl.n_normsys; ++k)
-          if (pl.ns_sample[k] == s) {
-            const double al = s_theta[pl.ns_param[k]];
-            others *= exp(al >= 0.0 ? al * pl.ns_lnhi[k] : -al * pl.ns_lnlo[k]);
-          }
-        g = fma(others, s_SA[s], g);
-      }
-      for (int k = 0; k < pl.n_normsys; ++k) {
-        if (pl.ns_param[k] != q) continue;
-        const int s = pl.ns_sample[k];
-        const double L = s_theta[q] >= 0.0 ? pl.ns_lnhi[k] : -pl.ns_lnlo[k];
-        g = fma(s_F[s] * L, s_SA[s], g);
-      }
-      for (int h = 0; h < pl.n_histo; ++h)
-        if (pl.histo_param[h] == q) g = fma(s_F[pl.histo_sample[h]], val(1 + kHfMaxSamples + h), g);
+      for (int i = pl.par_start[q]; i < pl.par_start[q + 1]; ++i) g += s_term[pl.par_slot[i]];
       if (pl.par_constrained[q]) g += s_theta[q];
     }
     a.grad_out[q] = pl.par_free[q] ? g : 0.0;

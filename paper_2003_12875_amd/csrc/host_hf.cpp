@@ -19,6 +19,7 @@ struct nll_hf_model {
   hipStream_t stream = nullptr;
   int n_cu = 256;
   HFPlan plan{};
+  int histo_caller[kHfMaxHisto] = {};  // sorted histosys -> caller's template index
   int64_t n_bins = 0;
   const double* counts = nullptr;
   const double* nominal[kHfMaxSamples] = {};
@@ -45,9 +46,15 @@ void hf_free(T*& p) {
   p = nullptr;
 }
 
+// persistent grid: at most kHfBlocksPerCu blocks per CU (the partials
+// buffer holds exactly that many records).  Measured at 2e6 and 2e7 bins:
+// one block per CU streams ~20 % slower; three stream no faster and the
+// finisher pays a third round trip for the records.
+constexpr int kHfBlocksPerCu = 2;
+
 int hf_grid(const nll_hf_model* m) {
   const int64_t want = (m->n_bins + kBlock - 1) / kBlock;
-  const int64_t cap = (int64_t)m->n_cu * 2;
+  const int64_t cap = (int64_t)m->n_cu * kHfBlocksPerCu;
   return (int)(want < 1 ? 1 : want > cap ? cap : want);
 }
 
@@ -73,41 +80,78 @@ nll_status nll_hf_create(const nll_hf_desc* d, nll_hf_model** out) {
     pl.par_free[p] = d->param_free ? (d->param_free[p] != 0) : 1;
     pl.par_constrained[p] = d->param_constrained ? (d->param_constrained[p] != 0) : 0;
   }
+  int n_nf = 0, n_ns = 0, n_hs = 0;
   for (int i = 0; i < d->n_modifiers; ++i) {
     const nll_hf_modifier& md = d->modifiers[i];
     if (md.sample < 0 || md.sample >= d->n_samples || md.param < 0 || md.param >= d->n_param) return NLL_ERR_ARG;
     if (md.type == NLL_HF_NORMFACTOR) {
-      if (pl.n_normfactor >= kHfMaxNormfactor) return NLL_ERR_UNSUPPORTED;
-      pl.nf_sample[pl.n_normfactor] = md.sample;
-      pl.nf_param[pl.n_normfactor++] = md.param;
+      ++n_nf;
     } else if (md.type == NLL_HF_NORMSYS) {
       if (!(md.hi > 0.0 && md.lo > 0.0 && std::isfinite(md.hi) && std::isfinite(md.lo))) return NLL_ERR_ARG;
-      if (pl.n_normsys >= kHfMaxNormsys) return NLL_ERR_UNSUPPORTED;
-      pl.ns_sample[pl.n_normsys] = md.sample;
-      pl.ns_param[pl.n_normsys] = md.param;
-      pl.ns_lnhi[pl.n_normsys] = std::log(md.hi);
-      pl.ns_lnlo[pl.n_normsys++] = std::log(md.lo);
+      ++n_ns;
     } else if (md.type == NLL_HF_HISTOSYS) {
-      if (pl.n_histo >= kHfMaxHisto) return NLL_ERR_UNSUPPORTED;
-      pl.histo_sample[pl.n_histo] = md.sample;
-      pl.histo_param[pl.n_histo++] = md.param;
+      ++n_hs;
     } else {
       return NLL_ERR_ARG;
     }
   }
+  if (n_nf > kHfMaxNormfactor || n_ns > kHfMaxNormsys || n_hs > kHfMaxHisto) return NLL_ERR_UNSUPPORTED;
+  // each kind sorted by sample (stable), with per-sample ranges; histo_caller
+  // maps a sorted histosys to its position in the caller's template order
+  int histo_caller[kHfMaxHisto] = {};
+  for (int s = 0; s < d->n_samples; ++s) {
+    pl.nf_start[s] = pl.n_normfactor;
+    pl.ns_start[s] = pl.n_normsys;
+    pl.hs_start[s] = pl.n_histo;
+    int caller_h = 0;
+    for (int i = 0; i < d->n_modifiers; ++i) {
+      const nll_hf_modifier& md = d->modifiers[i];
+      if (md.type == NLL_HF_HISTOSYS) ++caller_h;
+      if (md.sample != s) continue;
+      if (md.type == NLL_HF_NORMFACTOR) {
+        pl.nf_sample[pl.n_normfactor] = s;
+        pl.nf_param[pl.n_normfactor++] = md.param;
+      } else if (md.type == NLL_HF_NORMSYS) {
+        pl.ns_sample[pl.n_normsys] = s;
+        pl.ns_param[pl.n_normsys] = md.param;
+        pl.ns_lnhi[pl.n_normsys] = std::log(md.hi);
+        pl.ns_lnlo[pl.n_normsys++] = std::log(md.lo);
+      } else {
+        histo_caller[pl.n_histo] = caller_h - 1;
+        pl.histo_sample[pl.n_histo] = s;
+        pl.histo_param[pl.n_histo++] = md.param;
+      }
+    }
+  }
+  pl.nf_start[d->n_samples] = pl.n_normfactor;
+  pl.ns_start[d->n_samples] = pl.n_normsys;
+  pl.hs_start[d->n_samples] = pl.n_histo;
+  // per parameter: the contribution slots of the modifiers it drives
+  int n_slot = 0;
+  for (int p = 0; p < d->n_param; ++p) {
+    pl.par_start[p] = n_slot;
+    for (int i = 0; i < pl.n_normfactor; ++i)
+      if (pl.nf_param[i] == p) pl.par_slot[n_slot++] = i;
+    for (int k = 0; k < pl.n_normsys; ++k)
+      if (pl.ns_param[k] == p) pl.par_slot[n_slot++] = kHfMaxNormfactor + k;
+    for (int h = 0; h < pl.n_histo; ++h)
+      if (pl.histo_param[h] == p) pl.par_slot[n_slot++] = kHfMaxNormfactor + kHfMaxNormsys + h;
+  }
+  pl.par_start[d->n_param] = n_slot;
   DeviceGuard guard(d->device);
   nll_hf_model* m = new (std::nothrow) nll_hf_model();
   if (!m) return NLL_ERR_OOM;
   m->device = d->device;
   m->stream = reinterpret_cast<hipStream_t>(d->stream);
   m->plan = pl;
+  for (int h = 0; h < kHfMaxHisto; ++h) m->histo_caller[h] = histo_caller[h];
   m->n_bins = d->n_bins;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d->device) == hipSuccess && cus > 0)
     m->n_cu = cus;
   nll_status st;
   if ((st = hf_alloc(&m->deltas, 2 * (size_t)pl.n_histo * (size_t)d->n_bins)) != NLL_OK ||
-      (st = hf_alloc(&m->partials, (size_t)m->n_cu * 2 * kHfNV * 2)) != NLL_OK ||
+      (st = hf_alloc(&m->partials, (size_t)m->n_cu * kHfBlocksPerCu * kHfNV * 2)) != NLL_OK ||
       (st = hf_alloc(&m->status, 1)) != NLL_OK || (st = hf_alloc(&m->dbad, 1)) != NLL_OK) {
     nll_hf_destroy(m);
     return st;
@@ -152,7 +196,8 @@ nll_status nll_hf_set_data(nll_hf_model* m, const double* counts, const double* 
     for (int h = 0; h < H; ++h) {
       double* dup = m->deltas + (size_t)(2 * h) * (size_t)B;
       double* ddn = m->deltas + (size_t)(2 * h + 1) * (size_t)B;
-      if (launch_hf_deltas(nominal[m->plan.histo_sample[h]], up[h], down[h], B, dup, ddn, m->stream) != hipSuccess)
+      const int j = m->histo_caller[h];
+      if (launch_hf_deltas(nominal[m->plan.histo_sample[h]], up[j], down[j], B, dup, ddn, m->stream) != hipSuccess)
         return NLL_ERR_DEVICE;
     }
     unsigned long long bad = 0;

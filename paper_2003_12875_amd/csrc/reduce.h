@@ -102,14 +102,15 @@ __device__ inline void block_sum_vals(const double (&v)[NV], double* buf, DD* ou
 // Accumulator j is served by the S consecutive threads [j S, (j+1) S): lane
 // k sums records k, k + S, ... in order, then the S lanes (one wave at
 // most) are combined by an xor-butterfly.  The order depends only on count
-// and NV, so results are reproducible.  The totals land in out[NV].
-template <int NV, int BLOCK>
+// and NV, so results are reproducible.  The totals land in out[NV].  B:
+// records per lane in flight (one memory round trip covers S * B records).
+template <int NV, int BLOCK, int B_ = 8>
 struct RecordSum {
   // at most one wave per accumulator: no cross-wave step (a barrier and an
   // LDS round trip cost more than the longer per-lane chains)
   static constexpr int S0 = pow2_floor<(BLOCK / NV > 0 ? BLOCK / NV : 1)>();
   static constexpr int S = S0 > 64 ? 64 : S0;
-  static constexpr int B = 8;
+  static constexpr int B = B_;
   static_assert(S * NV <= BLOCK, "lanes per accumulator");
   DD buf[B];
 
