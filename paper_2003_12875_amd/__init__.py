@@ -360,7 +360,8 @@ class Model:
 
 class HFModel:
     """A binned template likelihood of HistFactory type on one device
-    (``nll_hf_model``), bound to the current torch stream at creation."""
+    (``nll_hf_model``), bound to the current torch stream at creation.
+    ``NLL.apply(theta, model)`` takes it as it takes a ``Model``."""
 
     def __init__(self, spec: dict, device: int = 0):
         """spec: {"n_bins": B, "samples": [names], "params": [{"name",

@@ -78,3 +78,18 @@ def test_points_and_toys():
     sizes = datagen.toy_sizes(4096, datagen.data_seed(4))
     assert sizes.min() >= 1000 and sizes.max() <= 200000
     assert abs(sizes.mean() - 100500) < 3 * 57500 / math.sqrt(4096)
+
+
+def test_hf_workload_is_seeded_and_well_formed():
+    a = datagen.hf_workload(n_bins=3000, n_samples=3, n_histosys=5, n_normsys=2, n_points=2)
+    b = datagen.hf_workload(n_bins=3000, n_samples=3, n_histosys=5, n_normsys=2, n_points=2)
+    assert np.array_equal(a["counts"], b["counts"]) and np.array_equal(a["points"], b["points"])
+    assert all(np.array_equal(x, y) for x, y in zip(a["up"], b["up"]))
+    assert np.all(a["counts"] >= 0) and np.all(a["counts"] == np.floor(a["counts"]))
+    assert all(np.all(t > 0) for t in a["nominal"] + a["up"] + a["down"])
+    spec = a["spec"]
+    assert len(spec["params"]) == 2 + 5 + 2
+    assert sum(m["type"] == "histosys" for m in spec["modifiers"]) == 5
+    # alphas jittered over both sides of the interpolation
+    al = a["points"][:, 2:]
+    assert np.any(al < 0) and np.any(al > 0)
