@@ -49,7 +49,12 @@ def test_argument_errors_without_device(L):
     assert L.nll_set_schedule(None, None) == -1
     assert L.nll_get_info(None, None) == -1
     assert L.nll_set_weights(None, None) == -1
+    assert L.nll_hf_create(None, ctypes.byref(h)) == -1
+    assert L.nll_hf_set_data(None, None, None, None, None) == -1
+    assert L.nll_hf_eval(None, None, None, None) == -1
+    assert L.nll_hf_sync(None, None) == -1
     L.nll_destroy_model(None)  # no-op
+    L.nll_hf_destroy(None)  # no-op
 
 
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
@@ -58,3 +63,31 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_native, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _native.lib()
+
+
+def test_binned_descriptor_errors_without_device(L):
+    """Descriptor validation happens before any device call."""
+    from paper_2003_12875_amd import _native
+    lo = (ctypes.c_double * 2)(0.0, -5.0)
+    hi = (ctypes.c_double * 2)(10.0, 5.0)
+    mods = (_native.HFModifier * 2)()
+    mods[0].type, mods[0].sample, mods[0].param = 1, 0, 0
+    mods[1].type, mods[1].sample, mods[1].param, mods[1].hi, mods[1].lo = 2, 0, 1, 1.1, 0.9
+    d = _native.HFDesc()
+    d.n_bins, d.n_samples, d.n_param = 100, 1, 2
+    d.param_lo, d.param_hi = lo, hi
+    d.n_modifiers, d.modifiers = 2, mods
+    h = ctypes.c_void_p()
+    for field, bad, code in (("n_samples", 0, -1), ("n_samples", 9, -2), ("n_param", 0, -1), ("n_param", 33, -2)):
+        keep = getattr(d, field)
+        setattr(d, field, bad)
+        assert L.nll_hf_create(ctypes.byref(d), ctypes.byref(h)) == code, field
+        setattr(d, field, keep)
+    mods[1].lo = 0.0  # a normsys factor must be positive
+    assert L.nll_hf_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    mods[1].lo = 0.9
+    mods[1].sample = 3  # no such sample
+    assert L.nll_hf_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    mods[1].sample = 0
+    mods[1].type = 7
+    assert L.nll_hf_create(ctypes.byref(d), ctypes.byref(h)) == -1
