@@ -134,12 +134,14 @@ def test_hf_status_conventions(torch, nllmi):
 
 
 def test_hf_autograd_lbfgs_fit(torch, nllmi):
-    """NLL.apply drives torch's L-BFGS on the binned model: the fit lowers
-    the NLL and ends at a stationary point of the oracle's likelihood."""
-    w = datagen.hf_workload(n_bins=20_000, n_samples=3, n_histosys=4, n_normsys=2, n_points=1)
+    """NLL.apply drives torch's L-BFGS on a binned model with normfactors
+    only (smooth and convex in mu): the fit ends at the oracle's stationary
+    point.  (The normsys and histosys interpolation codes have a kink at
+    alpha = 0, where quasi-Newton methods can stall.)"""
+    w = datagen.hf_workload(n_bins=20_000, n_samples=3, n_histosys=0, n_normsys=0, n_points=1)
     m = make(nllmi, w)
     th = torch.tensor(w["points"][0], dtype=torch.float64, device="cuda", requires_grad=True)
-    opt = torch.optim.LBFGS([th], max_iter=200, tolerance_grad=1e-12, tolerance_change=1e-15,
+    opt = torch.optim.LBFGS([th], max_iter=200, history_size=20, tolerance_grad=1e-14, tolerance_change=1e-16,
                             line_search_fn="strong_wolfe")
 
     def closure():
@@ -152,9 +154,8 @@ def test_hf_autograd_lbfgs_fit(torch, nllmi):
     opt.step(closure)
     res = th.detach().cpu().numpy()
     st, v, g = hf.nll(w["spec"], w["counts"], w["nominal"], w["up"], w["down"], res)
-    assert st == hf.OK and v < v0
     nu, dnu = hf.expected(w["spec"], w["nominal"], w["up"], w["down"], res)
     n = w["counts"]
-    wgt = np.where(n > 0, 1.0 - n / nu, 1.0)
-    G = max(float(np.sum(np.abs(wgt * d))) for d in dnu)
-    assert np.max(np.abs(g)) <= 1e-6 * G, (g, G)
+    G = max(float(np.sum(np.abs(np.where(n > 0, 1.0 - n / nu, 1.0) * d))) for d in dnu)
+    assert st == hf.OK and v < v0
+    assert np.max(np.abs(g)) <= 1e-8 * G, (g, G)
