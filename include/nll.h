@@ -397,6 +397,55 @@ nll_status nll_hf_eval(nll_hf_model* model, const double* theta, double* nll_out
 /* Synchronise and return (and clear) the device status (as nll_sync). */
 nll_status nll_hf_sync(nll_hf_model* model, int32_t* status_out);
 
+/* ------------------------------------------------------------------------
+ * Just-in-time densities (Sec. 4: PDFs given as formula strings, compiled
+ * at run time).  One observable x on [obs_lo, obs_hi] and a density
+ * expression g(x; p[0] .. p[n_param-1]) in C syntax (double arithmetic;
+ * + - * /, exp log sqrt pow sin cos tan atan tanh sinh cosh asinh erf fabs),
+ * normalised over the range by 256-point Gauss-Legendre on one panel (the
+ * expression should be smooth there):
+ *   NLL = -sum_i log g(x_i) + N log Z,   Z = int g dx,
+ * with the gradient from forward-mode dual numbers in the same pass.  An
+ * event with g <= 0 or non-finite, or Z <= 0, gives +inf and
+ * NLL_ERR_INVALID_PDF; a parameter outside its range NLL_ERR_PARAM_RANGE
+ * (both through nll_jit_sync).  The expression is compiled into device code
+ * as given: it must come from a trusted source, as any code the process
+ * runs.  1 <= n_param <= 8.
+ * ---------------------------------------------------------------------- */
+typedef struct nll_jit_desc {
+  const char* density;        /* C expression in x and p[k], <= 4096 characters */
+  double obs_lo, obs_hi;
+  int32_t n_param;
+  const double* param_lo;     /* n_param (host) */
+  const double* param_hi;
+  const uint8_t* param_free;  /* n_param or NULL (all free) */
+  int32_t device;
+  void* stream;               /* hipStream_t, 0 = default stream */
+} nll_jit_desc;
+
+typedef struct nll_jit_model nll_jit_model; /* opaque, owned by the library */
+
+/* Compile the density for the device (hipRTC; ~0.5-2 s) and allocate the
+ * model's scratch.  log (may be NULL): the compiler's messages, truncated
+ * to log_cap bytes.  Errors: NLL_ERR_ARG (bad descriptor, or the expression
+ * does not compile: see log), NLL_ERR_UNSUPPORTED (more than 8 parameters or
+ * a longer expression), NLL_ERR_DEVICE, NLL_ERR_OOM. */
+nll_status nll_jit_create(const nll_jit_desc* desc, nll_jit_model** out, char* log, int32_t log_cap);
+
+/* Release the model and its code object (waits for its stream). */
+void nll_jit_destroy(nll_jit_model* model);
+
+/* Attach n events (device array, borrowed until the next call or destroy);
+ * validates the range and SYNCHRONISES the stream (NLL_ERR_DOMAIN). */
+nll_status nll_jit_set_data(nll_jit_model* model, const double* x, int64_t n);
+
+/* Enqueue: NLL at theta (device [n_param]) into *nll_out (device [1]) and,
+ * if grad_out is not NULL, its gradient (device [n_param]). */
+nll_status nll_jit_eval(nll_jit_model* model, const double* theta, double* nll_out, double* grad_out);
+
+/* Synchronise and return (and clear) the device status (as nll_sync). */
+nll_status nll_jit_sync(nll_jit_model* model, int32_t* status_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,14 +21,14 @@ import math
 import warnings
 
 import numpy as np
-from scipy import integrate
+from scipy import integrate, special
 
 OK, E_PARAM, E_PDF = 0, -3, -5
 H = 1e-30  # complex step
 
 FUNCS = {"exp": np.exp, "log": np.log, "sqrt": np.sqrt, "pow": np.power, "sin": np.sin, "cos": np.cos,
          "tan": np.tan, "atan": np.arctan, "tanh": np.tanh, "sinh": np.sinh, "cosh": np.cosh,
-         "asinh": np.arcsinh}
+         "asinh": np.arcsinh, "erf": special.erf}
 
 
 def g(expr: str, x, p):

@@ -18,7 +18,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-from ._native import (HF_MODIFIER, HFDesc, HFModifier, MAX_NODE_CHILDREN, MAX_NODE_PARAMS, NLLError, NodeDesc,
+from ._native import (HF_MODIFIER, HFDesc, HFModifier, JitDesc, MAX_NODE_CHILDREN, MAX_NODE_PARAMS, NLLError, NodeDesc,
                       ModelDesc, Schedule, Info,
                       STATUS, check, lib, LIB_PATH)
 
@@ -441,6 +441,76 @@ class HFModel:
     def sync(self) -> int:
         st = ctypes.c_int32(0)
         check(lib().nll_hf_sync(self._h, ctypes.byref(st)), "nll_hf_sync")
+        return st.value
+
+
+class JITModel:
+    """A density given as a C expression in x and p[k], compiled for the
+    device at construction (``nll_jit_model``); bound to the current torch
+    stream then.  ``NLL.apply(theta, model)`` takes it as it takes a
+    ``Model``."""
+
+    def __init__(self, density: str, lo: float, hi: float, params, device: int = 0):
+        """params: [{"name", "value", "lo", "hi", "free"}...]."""
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        P = len(params)
+        self.n_param = P
+        plo = (ctypes.c_double * P)(*[float(p["lo"]) for p in params])
+        phi = (ctypes.c_double * P)(*[float(p["hi"]) for p in params])
+        pfree = (ctypes.c_uint8 * P)(*[1 if p.get("free", True) else 0 for p in params])
+        d = JitDesc()
+        d.density = density.encode()
+        d.obs_lo, d.obs_hi = float(lo), float(hi)
+        d.n_param, d.param_lo, d.param_hi, d.param_free = P, plo, phi, pfree
+        d.device = device
+        d.stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        log = ctypes.create_string_buffer(8192)
+        handle = ctypes.c_void_p()
+        st = lib().nll_jit_create(ctypes.byref(d), ctypes.byref(handle), log, len(log))
+        self.compile_log = log.value.decode(errors="replace")
+        if st != 0:
+            raise NLLError(st, "nll_jit_create" + (": " + self.compile_log if self.compile_log else ""))
+        self._h = handle
+        self._x = None
+        self.n_events = -1
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().nll_jit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_data(self, x):
+        torch = _torch()
+        x = _dev_tensor(x, torch.float64, self.device)
+        check(lib().nll_jit_set_data(self._h, x.data_ptr(), ctypes.c_int64(x.numel())), "nll_jit_set_data")
+        self._x = x
+        self.n_events = x.numel()
+
+    def eval(self, theta, out=None):
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        check(lib().nll_jit_eval(self._h, theta.data_ptr(), out.data_ptr(), None), "nll_jit_eval")
+        return out
+
+    def eval_grad(self, theta, out=None, grad=None):
+        torch = _torch()
+        theta = _dev_tensor(theta, torch.float64, self.device)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        grad = torch.empty(self.n_param, dtype=torch.float64, device=self.device) if grad is None else grad
+        check(lib().nll_jit_eval(self._h, theta.data_ptr(), out.data_ptr(), grad.data_ptr()), "nll_jit_eval")
+        return out, grad
+
+    def sync(self) -> int:
+        st = ctypes.c_int32(0)
+        check(lib().nll_jit_sync(self._h, ctypes.byref(st)), "nll_jit_sync")
         return st.value
 
 

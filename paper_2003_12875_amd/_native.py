@@ -18,7 +18,8 @@ EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_d
            "nll_eval_grad", "nll_eval_batched", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_eval_bhhh",
            "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
            "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
-           "nll_status_string", "nll_hf_create", "nll_hf_destroy", "nll_hf_set_data", "nll_hf_eval", "nll_hf_sync")
+           "nll_status_string", "nll_hf_create", "nll_hf_destroy", "nll_hf_set_data", "nll_hf_eval", "nll_hf_sync",
+           "nll_jit_create", "nll_jit_destroy", "nll_jit_set_data", "nll_jit_eval", "nll_jit_sync")
 
 HF_MAX_SAMPLES, HF_MAX_HISTOSYS = 8, 24
 HF_MODIFIER = {"normfactor": 1, "normsys": 2, "histosys": 3}
@@ -56,6 +57,13 @@ class HFDesc(ctypes.Structure):
                 ("param_lo", ctypes.POINTER(ctypes.c_double)), ("param_hi", ctypes.POINTER(ctypes.c_double)),
                 ("param_free", ctypes.POINTER(ctypes.c_uint8)), ("param_constrained", ctypes.POINTER(ctypes.c_uint8)),
                 ("n_modifiers", ctypes.c_int32), ("modifiers", ctypes.POINTER(HFModifier)),
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class JitDesc(ctypes.Structure):
+    _fields_ = [("density", ctypes.c_char_p), ("obs_lo", ctypes.c_double), ("obs_hi", ctypes.c_double),
+                ("n_param", ctypes.c_int32), ("param_lo", ctypes.POINTER(ctypes.c_double)),
+                ("param_hi", ctypes.POINTER(ctypes.c_double)), ("param_free", ctypes.POINTER(ctypes.c_uint8)),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
@@ -112,8 +120,14 @@ def lib():
         L.nll_hf_set_data.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
         L.nll_hf_eval.argtypes = [vp, vp, vp, vp]
         L.nll_hf_sync.argtypes = [vp, ctypes.POINTER(i32)]
+        L.nll_jit_create.argtypes = [ctypes.POINTER(JitDesc), ctypes.POINTER(vp), ctypes.c_char_p, i32]
+        L.nll_jit_destroy.argtypes = [vp]
+        L.nll_jit_destroy.restype = None
+        L.nll_jit_set_data.argtypes = [vp, vp, i64]
+        L.nll_jit_eval.argtypes = [vp, vp, vp, vp]
+        L.nll_jit_sync.argtypes = [vp, ctypes.POINTER(i32)]
         for f in EXPORTS:
-            if f not in ("nll_destroy_model", "nll_status_string", "nll_hf_destroy"):
+            if f not in ("nll_destroy_model", "nll_status_string", "nll_hf_destroy", "nll_jit_destroy"):
                 getattr(L, f).restype = ctypes.c_int32
         _lib = L
     return _lib

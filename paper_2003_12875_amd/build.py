@@ -55,7 +55,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
                 print(msg, file=sys.stderr)
     objs = [u[-1] for u in units]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp, "-lhiprtc"])
     os.replace(tmp, LIB)
     return LIB
 
