@@ -446,6 +446,26 @@ def extras(torch, nllmi, datagen, args):
                                   "status": mh.sync()}
     del mh
     torch.cuda.empty_cache()
+    # just-in-time density: a Gaussian written as an expression string on the
+    # c1 range with 1e7 events, against the built-in Gaussian leaf on the same
+    # events (compile time included once)
+    w = datagen.workload(1, n=10_000_000)
+    x = torch.from_numpy(w["cols"][0]).cuda()
+    t0 = time.perf_counter()
+    mj = nllmi.JITModel("exp(-0.5*((x-p[0])/p[1])*((x-p[0])/p[1]))", -10.0, 10.0, w["spec"]["params"])
+    t_compile = time.perf_counter() - t0
+    mj.set_data(x)
+    mb = nllmi.Model.from_spec(w["spec"])
+    mb.set_data([x])
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(2, dtype=torch.float64, device="cuda")
+    tj = time_launches(torch, lambda: mj.eval_grad(th, out=out, grad=g), 20)
+    tb = time_launches(torch, lambda: mb.eval_grad(th, out=out, grad=g), 20)
+    ex["jit_gauss_1e7"] = {"compile_s": t_compile, "eval_grad_ms": tj, "events_per_s": 1e7 / (tj * 1e-3),
+                           "builtin_gauss_eval_grad_ms": tb, "status": mj.sync()}
+    del mj, mb, x
+    torch.cuda.empty_cache()
     # 2-D CB/ARGUS x Chebyshev, 5e7 events, 9 free parameters
     log("c3: generating 5e7 events")
     w = datagen.workload(3)
