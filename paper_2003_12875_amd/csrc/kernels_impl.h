@@ -517,7 +517,10 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   double xb[ring_depth<M>()][U][M::NOBS];
   preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
 
-  typename Pass<M, GRAD>::C C;
+  using CT = typename Pass<M, GRAD>::C;
+  __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
+  if constexpr (CT::kExpTab) stage_exp_table(s_etab);
+  CT C;
   int bad;
   if constexpr (FIT) {
     C.load(*a.consts, pl);
@@ -526,6 +529,10 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
     compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
     C.load(pt, pl);
     bad = uniform(pt.bad);
+  }
+  if constexpr (CT::kExpTab) {
+    C.etab = s_etab;
+    __syncthreads();
   }
   std::conditional_t<BH, AccBhhh<M>, typename Pass<M, GRAD>::A> acc;
   acc.init();
@@ -659,6 +666,12 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
   const double* cols[M::NOBS];
 #pragma unroll
   for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
+  using CT = typename Pass<M, GRAD>::C;
+  __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
+  if constexpr (CT::kExpTab) {
+    stage_exp_table(s_etab);
+    __syncthreads();
+  }
 
   // the next item's descriptor is loaded while the current one streams
   int64_t item = blockIdx.x;
@@ -672,8 +685,9 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     const PerTheta& pt = a.consts[s];
     const int64_t start = cur.start, end = cur.end;
 
-    typename Pass<M, GRAD>::C C;
+    CT C;
     C.load(pt, pl);
+    C.etab = s_etab;
     typename Pass<M, GRAD>::A acc;
     acc.init();
     if (uniform(pt.bad) == 0 && cur.flag == 0) {

@@ -151,9 +151,13 @@ struct Weighted : B {
 // Uniform per-point constants of a compiled model, held in scalar registers.
 template <class M>
 struct Consts {
+  // mixtures take one e^x per event from the LDS table of exp_nonpos_tab;
+  // the kernel stages it and sets etab
+  static constexpr bool kExpTab = M::K > 1;
   typename M::LeafCs leaf;
   double ck[M::K];
   int mask[M::K];  // non-root leaves of term k
+  const double* etab;
 
   __device__ void load(const PerTheta& pt, const Plan& pl) {
     static_for<M::L>([&](auto lc) {
@@ -285,7 +289,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
     if constexpr (K == 2) {
       const double d = Lk[0] - Lk[1];
       m = fmax(Lk[0], Lk[1]);
-      const double es = exp_nonpos(-fabs(d));
+      const double es = exp_nonpos_tab(-fabs(d), C.etab);
       d2 = d;
       es2 = es;
       e[0] = d >= 0.0 ? 1.0 : es;
@@ -304,7 +308,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<M>& 
       s = 0.0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        e[k] = exp_nonpos(Lk[k] - m);
+        e[k] = exp_nonpos_tab(Lk[k] - m, C.etab);
         if constexpr (M::HAS_TLIN) e[k] *= Gk[k];
         s += e[k];
       }
@@ -383,6 +387,8 @@ __device__ inline float uniformf(float v) {
 
 template <class M>
 struct Consts32 {
+  static constexpr bool kExpTab = false;
+  const double* etab;
   typename M::LeafC32s leaf;
   double dck[M::K];  // ck_k - ck_0
   int mask[M::K];
