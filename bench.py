@@ -7,13 +7,15 @@ with 1e7 synthetic FP64 events.  One step = one gradient-descent iteration
 on the device: per-point constants (normalisation and its derivatives),
 one fused pass over the events computing NLL and the adjoint gradient of
 all 4 parameters, the compensated reduction, and the parameter update --
-all in the library's HIP kernels, recorded once into a HIP graph.
+all in the library's HIP kernels (one launch per step), recorded once into
+a HIP graph.
 
 Also reported, on the same GPU:
   * fd_baseline -- forward-only FP64 NLL plus a central finite-difference
     gradient (2P+1 passes per step), the per-fit speed-up of the adjoint;
-  * roofline    -- the dominant kernel (the fused streaming kernel), whose
-    average duration is measured in the same run with HIP start/stop events
+  * roofline    -- the dominant kernel (k_single_fit, one launch per step:
+    the previous step's update and this proposal's constants in every
+    block, then the fused streaming pass), whose average duration is measured in the same run with HIP start/stop events
     attached to its launch on the library's stream (hipExtLaunchKernel) in
     every step of an eager K-step fit.  It is bound by FP64 VALU issue
     ("alu"): its VALU lane-instructions per launch (SQ_INSTS_VALU summary
@@ -207,7 +209,8 @@ def headline(torch, nllmi, datagen, args):
                      "unit": "T FP64-VALU lane-instructions/s",
                      "frac": alu_achieved / (VALU_PEAK_LANE_OPS / 1e12) if valu else None,
                      "traffic": traffic,
-                     "kernel": "k_single<gauss+exp, grad, fit>: fused per-point constants + NLL/gradient pass",
+                     "kernel": "k_single_fit<gauss+exp>: the previous step's update and this proposal's "
+                               "constants, then the NLL/gradient pass",
                      "valu_lane_instructions_per_event": valu[0] / n if valu else None,
                      "fp64_tflops": valu[1] / (kern_ms * 1e-3) / 1e12 if valu else None,
                      "fp64_tflops_peak": FP64_PEAK_FLOPS / 1e12,
@@ -581,9 +584,9 @@ def _pick(tab, pred):
 
 
 def _is_fit_kernel(k):
-    """The gradient-descent fit's streaming kernel k_single<M, GRAD=true, U,
-    FIT=true, BHHH=false>."""
-    return "k_single<" in k and any(f", true, {u}, true, false>" in k for u in (2, 4, 8))
+    """The gradient-descent fit's streaming kernel k_single_fit<M, U> (one
+    launch per step: the previous step's update, then the pass)."""
+    return "k_single_fit<" in k
 
 
 def _streaming(values):

@@ -491,8 +491,25 @@ hipEvent_t kernel_event(nll_model* m, int s, int which) {
   return m->step_timing == 2 ? m->events[2 * s + which] : nullptr;
 }
 
-// a whole single-dataset fit: one persistent launch per step, the last
-// block of each launch takes the gradient-descent step
+// the state of set `set` of the gradient-descent arrays, as a set-0 view
+GDState gd_view(const GDState& g, int set, int P) {
+  GDState v = g;
+  v.th_acc += (size_t)set * P;
+  v.g_acc += (size_t)set * P;
+  v.th_prop += (size_t)set * P;
+  v.f_acc += set;
+  v.eta += set;
+  v.last_status += set;
+  if (v.b_acc) v.b_acc += (size_t)set * P * P;
+  return v;
+}
+
+// a whole single-dataset fit.  Gradient descent: one launch per step, each
+// taking the previous step's update before its pass (state, constants and
+// block records alternate between two buffers by step parity; sets 0 and 1
+// of the state arrays, constants 0 and 1, the two halves of the partials),
+// and one finishing kernel for the last step's update.  BHHH: a streaming
+// launch and a finishing kernel per step.
 nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n_steps, double eta, double* nll_out,
                               double* grad_out, int32_t* status_out, bool bhhh = false) {
   GDState gd = gd_state(m);
@@ -501,17 +518,49 @@ nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n
   SingleArgs a = single_args(m, nullptr, nullptr, nullptr);
   a.gd = gd;
   record_step(m, 0, st);
-  for (int s = 0; s < n_steps; ++s) {
-    e = bhhh ? m->ops->single_bhhh_fit(m->plan, a, m->sched.unroll, single_grid(m),
-                                       lds_cap(m, m->sched.blocks_per_cu), st, kernel_event(m, s, 0),
-                                       kernel_event(m, s, 1))
-             : (m->weights ? m->ops->single_w_fit : m->ops->single_fit)(
-                   m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), st,
-                   kernel_event(m, s, 0), kernel_event(m, s, 1));
-    if (e != hipSuccess) return NLL_ERR_DEVICE;
-    record_step(m, s + 1, st);
+  const int grid = single_grid(m);
+  const int cap = lds_cap(m, m->sched.blocks_per_cu);
+  if (bhhh) {
+    for (int s = 0; s < n_steps; ++s) {
+      e = m->ops->single_bhhh_fit(m->plan, a, m->sched.unroll, grid, cap, st, kernel_event(m, s, 0),
+                                  kernel_event(m, s, 1));
+      if (e != hipSuccess) return NLL_ERR_DEVICE;
+      record_step(m, s + 1, st);
+    }
+    e = launch_fit_final(1, m->plan.n_param, gd, theta, nll_out, grad_out, reinterpret_cast<int*>(status_out), st);
+    return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
   }
-  e = launch_fit_final(1, m->plan.n_param, gd, theta, nll_out, grad_out, reinterpret_cast<int*>(status_out), st);
+  const int P = m->plan.n_param;
+  const GDState gs[2] = {gd_view(gd, 0, P), gd_view(gd, 1, P)};
+  double* part[2] = {m->partials, m->partials + m->partials_half};
+  const auto step_fn = m->weights ? m->ops->single_w_fit : m->ops->single_fit;
+  for (int s = 0; s < n_steps; ++s) {
+    const int cur = s & 1, prev = cur ^ 1;
+    a.partials = part[cur];
+    a.partials_prev = s > 0 ? part[prev] : nullptr;
+    a.gd = gs[prev];
+    a.gd_out = gs[cur];
+    a.consts = m->consts + (s > 0 ? prev : 0);
+    a.consts_out = m->consts + cur;
+    e = step_fn(m->plan, a, m->sched.unroll, grid, cap, st, kernel_event(m, s, 0), kernel_event(m, s, 1));
+    if (e != hipSuccess) return NLL_ERR_DEVICE;
+    if (s + 1 < n_steps) record_step(m, s + 1, st);  // the last step ends after its update
+  }
+  int last = 0;  // the buffer holding the final state
+  if (n_steps > 0) {
+    const int prev = (n_steps - 1) & 1;
+    last = n_steps & 1;
+    a.partials = part[prev];
+    a.partials_prev = nullptr;
+    a.gd = gs[prev];
+    a.gd_out = gs[last];
+    a.consts = m->consts + prev;
+    a.consts_out = nullptr;
+    e = (m->weights ? m->ops->w_fit_finish : m->ops->fit_finish)(m->plan, a, grid, st);
+    if (e != hipSuccess) return NLL_ERR_DEVICE;
+    record_step(m, n_steps, st);
+  }
+  e = launch_fit_final(1, P, gs[last], theta, nll_out, grad_out, reinterpret_cast<int*>(status_out), st);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
 
@@ -627,7 +676,9 @@ nll_status nll_create_model(const nll_model_desc* desc, nll_model** out) {
   if ((st = gl_table(m->device, &m->gl)) != NLL_OK) return fail(st);
   const size_t max_grid = (size_t)m->n_cu * 32;
   const size_t record = std::max<size_t>((size_t)ops->na_grad + 1, (size_t)ops->bhhh_record);
-  if ((st = dalloc(&m->partials, max_grid * record * 2)) != NLL_OK) return fail(st);
+  // two halves: gradient-descent steps alternate between them
+  m->partials_half = max_grid * record * 2;
+  if ((st = dalloc(&m->partials, 2 * m->partials_half)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->pt_single, 1)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->status, 1)) != NLL_OK) return fail(st);
   if ((st = dalloc(&m->dbad, 1)) != NLL_OK) return fail(st);
@@ -843,7 +894,7 @@ static nll_status fit_single_impl(nll_model* m, double* theta, int32_t n_steps, 
   DeviceGuard guard(m->device);
   nll_status st = ensure_sets(m, 1);
   if (st != NLL_OK) return st;
-  if ((st = ensure_gd(m, 1)) != NLL_OK) return st;
+  if ((st = ensure_gd(m, 2)) != NLL_OK) return st;  // gradient descent: two state buffers
   FitKey k;
   k.mode = bhhh ? 3 : 1;
   k.timing = m->step_timing;

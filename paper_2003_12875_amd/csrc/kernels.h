@@ -38,6 +38,10 @@ struct SingleArgs {
   const double* glw;
   GDState gd;                   // fit mode: theta = gd.th_prop, set 0
   const double* wsum;           // weighted events: the weights' sum W (device, 1)
+  // gradient-descent fit, double-buffered by step parity (k_single_fit):
+  const double* partials_prev;  // the previous step's block records (null at the first step)
+  GDState gd_out;               // the state the update writes (gd is the one it reads)
+  PerTheta* consts_out;         // constants of the proposal this step evaluates
 };
 
 // One work item of the batched pass: events [start, end) of one set.
@@ -95,6 +99,10 @@ struct VariantOps {
   hipError_t (*single_w)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, int lds_cap, hipStream_t);
   hipError_t (*single_w_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
                              hipEvent_t ev0, hipEvent_t ev1);
+  // after the last gradient-descent step: the update of the proposal it
+  // evaluated (single_fit steps take the previous step's update themselves)
+  hipError_t (*fit_finish)(const Plan&, const SingleArgs&, int grid, hipStream_t);
+  hipError_t (*w_fit_finish)(const Plan&, const SingleArgs&, int grid, hipStream_t);
 };
 
 // registry: every variants_*.hip file appends its compiled shapes

@@ -124,14 +124,16 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
 // that these loads travel together with the kernel's other loads.
 struct GDPre {
   double fa, eta;         // thread 0
+  int ls;                 // thread 0: last status
   double acc, ga, prop;   // thread q < P
 };
 __device__ inline GDPre gd_preload(const GDState& gd, int s, int P) {
-  GDPre r{0.0, 0.0, 0.0, 0.0, 0.0};
+  GDPre r{0.0, 0.0, 0, 0.0, 0.0, 0.0};
   const int q = threadIdx.x;
   if (q == 0) {
     r.fa = gd.f_acc[s];
     r.eta = gd.eta[s];
+    r.ls = gd.last_status[s];
   }
   if (q < P) {
     r.acc = gd.th_acc[(size_t)s * P + q];
@@ -180,6 +182,52 @@ __device__ inline double gd_update(const Plan& pl, const GDState& gd, int s, int
     }
     next = pl.par_free[q] ? acc - s_step * ga : acc;
     gd.th_prop[(size_t)s * P + q] = next;
+  }
+  return next;
+}
+
+// The same step for a state kept in two buffers (by step parity): the
+// state is read from pre (gd_preload of the input buffer) and, when
+// `writer`, every field is written to `out`, changed or not.  Threads
+// q >= P return 0.  Every block of a streaming launch calls it with the
+// same inputs (same bits everywhere); only one writes.
+__device__ inline double gd_update_to(const Plan& pl, const GDState& out, int st, double nll, const double* grad,
+                                      double n_s, const GDPre& pre, bool writer) {
+  __shared__ int s_ok;
+  __shared__ double s_step;
+  const int P = pl.n_param;
+  if (threadIdx.x == 0) {
+    const double fa = pre.fa;
+    const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
+    double eta = pre.eta, f = fa;
+    int ls = pre.ls;
+    if (ok) {
+      f = nll;
+      ls = 0;
+    } else {
+      eta *= 0.5;
+      if (!__builtin_isfinite(fa)) ls = st != 0 ? st : -5;
+    }
+    if (writer) {
+      out.f_acc[0] = f;
+      out.eta[0] = eta;
+      out.last_status[0] = ls;
+    }
+    s_ok = ok;
+    s_step = eta / (n_s > 0.0 ? n_s : 1.0);
+  }
+  __syncthreads();
+  const int q = threadIdx.x;
+  double next = 0.0;
+  if (q < P) {
+    const double acc = s_ok ? pre.prop : pre.acc;
+    const double ga = s_ok ? grad[q] : pre.ga;
+    next = pl.par_free[q] ? acc - s_step * ga : acc;
+    if (writer) {
+      out.th_acc[q] = acc;
+      out.g_acc[q] = ga;
+      out.th_prop[q] = next;
+    }
   }
   return next;
 }
@@ -602,20 +650,20 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
   // the events' count, or the weights' sum W (attached with the weights)
   double neff = (double)a.n;
   if constexpr (M::WEIGHTED) neff = *a.wsum;
-  RecordSum<NV, kFinishBlock> rs;
+  // the gradient-descent steps (k_single_fit) store their records value-major
+  std::conditional_t<FIT && !BH, RecordSumT<NV, kFinishBlock>, RecordSum<NV, kFinishBlock>> rs;
   rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
   if (t < PT8) reinterpret_cast<double*>(&spt)[t] = ptv;
   rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
   finish_block<M, GRAD>(spl, spt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
   __shared__ double s_B[BH ? kMaxParams * kMaxParams : 1];
   if constexpr (BH) bhhh_assemble<M>(spl, spt, tot, a.n, s_theta, s_st, s_B);
-  if constexpr (FIT) {
-    double next;
-    if constexpr (BH) {
-      next = bhhh_update(spl, a.gd, s_st, s_nll, s_grad, s_B, bpre, pre);
-    } else {
-      next = gd_update(spl, a.gd, 0, s_st, s_nll, s_grad, neff, pre);
-    }
+  if constexpr (FIT && !BH) {
+    // after the last step of a gradient-descent fit (k_single_fit): that
+    // step's update, into the other state buffer
+    (void)gd_update_to(spl, a.gd_out, s_st, s_nll, s_grad, neff, pre, true);
+  } else if constexpr (FIT) {
+    const double next = bhhh_update(spl, a.gd, s_st, s_nll, s_grad, s_B, bpre, pre);
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
     // the next proposal's constants, built in LDS (its phases read back
     // what other threads wrote) and stored with one parallel copy
@@ -633,6 +681,109 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
       if (a.bhhh_out && t < P * P) a.bhhh_out[t] = s_B[t];
     }
   }
+}
+
+// One gradient-descent step over one dataset in one launch.  Every block
+// first finishes the previous step itself: the previous launch's block
+// records (stored value-major, summed in a fixed order), that
+// proposal's NLL and gradient, the accept-or-halve update and the
+// constants of the next proposal -- the same inputs and arithmetic in every
+// block, so the same bits everywhere; block 0 stores the new state and
+// constants.  Then the block streams its tiles at the new proposal.  State,
+// constants and records alternate between two buffers by step parity, so
+// that no block overwrites what another block of the same launch still
+// reads; the launch boundary makes them visible to the next step.  The
+// first step (partials_prev null) takes the constants k_fit_init made.
+// This removes one kernel per step: the loads of the first event tiles are
+// issued before the finishing work and arrive during it.
+template <class M, int U>
+__global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const SingleArgs a) {
+  constexpr int NA = M::template NA<true>;
+  constexpr int NV = NA + 1;  // + invalid-event count
+  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
+  constexpr int PTL = (PT8 + kBlock - 1) / kBlock;  // constants per thread
+  using CT = typename Pass<M, true>::C;
+  __shared__ Plan spl;
+  __shared__ double s_theta[kMaxParams];
+  __shared__ double s_grad[kMaxParams];
+  __shared__ PerTheta pt;
+  __shared__ double red[NV * (kBlock + 1)];
+  __shared__ DD tot[NV];
+  __shared__ double small[4 * (kMaxLeafParams + 1)];
+  __shared__ double s_nll;
+  __shared__ int s_st;
+  __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
+  const int t = threadIdx.x;
+  const bool first = a.partials_prev == nullptr;
+
+  // loads in the order they are needed (they complete in order): plan,
+  // state and the previous proposal's constants and records, then the
+  // first event tiles
+  GDPre pre{};
+  double ptv[PTL];
+  double neff = (double)a.n;
+  RecordSumT<NV, kBlock, 16> rs;
+  if (!first) {
+    stage_plan<kBlock>(pl, &spl);
+    stage_theta(a.gd.th_prop, pl.n_param, s_theta);
+    pre = gd_preload(a.gd, 0, pl.n_param);
+    if constexpr (M::WEIGHTED) neff = *a.wsum;
+#pragma unroll
+    for (int i = 0; i < PTL; ++i) {
+      const int e = t + i * kBlock;
+      ptv[i] = e < PT8 ? reinterpret_cast<const double*>(a.consts)[e] : 0.0;
+    }
+    rs.issue(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x);
+  }
+  const double* cols[M::NOBS];
+#pragma unroll
+  for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
+  const int64_t tile = (int64_t)kBlock * U;
+  const int64_t nfull = a.n / tile;
+  const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const int64_t base0 = (int64_t)blockIdx.x * tile + t;
+  double xb[ring_depth<M>()][U][M::NOBS];
+  preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
+  if constexpr (CT::kExpTab) stage_exp_table(s_etab);
+
+  CT C;
+  int bad;
+  if (first) {
+    C.load(*a.consts, pl);
+    bad = uniform(a.consts->bad);
+  } else {
+#pragma unroll
+    for (int i = 0; i < PTL; ++i) {
+      const int e = t + i * kBlock;
+      if (e < PT8) reinterpret_cast<double*>(&pt)[e] = ptv[i];
+    }
+    rs.reduce(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x, tot);  // ends with a barrier
+    finish_block<M, true>(spl, pt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
+    const double next = gd_update_to(spl, a.gd_out, s_st, s_nll, s_grad, neff, pre, blockIdx.x == 0);
+    if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
+    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
+    if (blockIdx.x == 0)
+      for (int e = t; e < PT8; e += kBlock)
+        reinterpret_cast<double*>(a.consts_out)[e] = reinterpret_cast<const double*>(&pt)[e];
+    C.load(pt, pl);
+    bad = uniform(pt.bad);
+  }
+  if constexpr (CT::kExpTab) C.etab = s_etab;
+  __syncthreads();
+
+  typename Pass<M, true>::A acc;
+  acc.init();
+  if (bad == 0) {
+    stream_tiles<M, true, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb, C, acc);
+    const int64_t rest = nfull * tile;
+    if (rest < a.n && blockIdx.x == (unsigned)(nfull % gridDim.x))
+      stream_part_tile<M, true, U>(cols, rest + t, a.n, C, acc);
+  }
+  double v[NV];
+  acc.finalize(reinterpret_cast<double(&)[NA]>(v));
+  v[NA] = (double)acc.bad;
+  block_sum_vals<NV, kBlock>(v, red, tot);
+  if (t < NV) reinterpret_cast<DD*>(a.partials)[(size_t)t * gridDim.x + blockIdx.x] = tot[t];  // value-major
 }
 
 // ------------------------------------------------------------------------
@@ -861,9 +1012,32 @@ struct Launch {
     hipLaunchKernelGGL((k_single_finish<M, GRAD, FIT>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
     return hipGetLastError();
   }
+  template <int U>
+  static void launch_fit(const Plan& pl, const SingleArgs& a, int grid, int lds_cap, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1) {
+    const void* k = reinterpret_cast<const void*>(&k_single_fit<M, U>);
+    if (ev0 && ev1)
+      hipExtLaunchKernelGGL((k_single_fit<M, U>), dim3(grid), dim3(kBlock), (uint32_t)pad_lds(k, lds_cap), st, ev0,
+                            ev1, 0u, pl, a);
+    else
+      hipLaunchKernelGGL((k_single_fit<M, U>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+  }
+  // one gradient-descent step (k_single_fit: the previous step's update,
+  // then this step's pass)
   static hipError_t single_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
                                hipEvent_t ev0, hipEvent_t ev1) {
-    return single_t<true, true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
+    const int u = pick_u(unroll);
+    if constexpr (kU8) {
+      if (u == 8) launch_fit<8>(pl, a, grid, lds_cap, st, ev0, ev1);
+    }
+    if (u == 4) launch_fit<4>(pl, a, grid, lds_cap, st, ev0, ev1);
+    if (u == 2) launch_fit<2>(pl, a, grid, lds_cap, st, ev0, ev1);
+    return hipGetLastError();
+  }
+  // the update of the last step's proposal (grid: that launch's blocks)
+  static hipError_t fit_finish(const Plan& pl, const SingleArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_single_finish<M, true, true>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
+    return hipGetLastError();
   }
   // BHHH: compiled for FP64 shapes with at most 6 score features (21 second
   // moments), at 2 and 4 events per thread per tile (8 maps to 4)
@@ -974,12 +1148,14 @@ VariantOps make_ops(const char* name) {
   v.precision = M::PREC;
   v.single = &Launch<M>::single;
   v.single_fit = &Launch<M>::single_fit;
+  v.fit_finish = &Launch<M>::fit_finish;
   v.consts = &Launch<M>::consts;
   v.sets = &Launch<M>::sets;
   v.fit_init = &Launch<M>::fit_init;
   if constexpr (M::PREC == 0 && M::NOBS < kMaxObs) {  // weighted events: the weights take one column
     v.single_w = &Launch<Weighted<M>>::single;
     v.single_w_fit = &Launch<Weighted<M>>::single_fit;
+    v.w_fit_finish = &Launch<Weighted<M>>::fit_finish;
   }
   if constexpr (Launch<M>::kBH) {
     v.single_bhhh = &Launch<M>::single_bhhh;

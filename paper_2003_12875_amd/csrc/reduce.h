@@ -145,6 +145,50 @@ struct RecordSum {
   }
 };
 
+// The same sum over records stored value-major (value j of record r at
+// src[j * count + r]: the S lanes of an accumulator read consecutive
+// addresses), with each lane's batch of B records added as a pairwise tree
+// (a dependent chain of log2 B additions instead of B - 1).  The order
+// depends only on count and NV.
+template <int NV, int BLOCK, int B_ = 8>
+struct RecordSumT {
+  static constexpr int S0 = pow2_floor<(BLOCK / NV > 0 ? BLOCK / NV : 1)>();
+  static constexpr int S = S0 > 64 ? 64 : S0;
+  static constexpr int B = B_;
+  static_assert(S * NV <= BLOCK, "lanes per accumulator");
+  static_assert((B & (B - 1)) == 0, "batch: a power of two");
+  DD buf[B];
+  __device__ void load(const DD* src, int64_t count, int64_t r0) {
+    const int t = threadIdx.x;
+    const int j = t / S, k = t % S;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int64_t r = r0 + k + (int64_t)b * S;
+      buf[b] = (j < NV && r < count) ? src[(int64_t)j * count + r] : DD{0.0, 0.0};
+    }
+  }
+  __device__ DD tree() {
+#pragma unroll
+    for (int w = 1; w < B; w *= 2)
+#pragma unroll
+      for (int b = 0; b + w < B; b += 2 * w) buf[b] = dd_add(buf[b], buf[b + w]);
+    return buf[0];
+  }
+  __device__ void issue(const DD* src, int64_t count) { load(src, count, 0); }
+  __device__ void reduce(const DD* src, int64_t count, DD* out) {
+    const int t = threadIdx.x;
+    const int j = t / S, k = t % S;
+    DD acc = tree();
+    for (int64_t r0 = (int64_t)B * S; r0 < count; r0 += (int64_t)B * S) {
+      load(src, count, r0);
+      acc = dd_add(acc, tree());
+    }
+    acc = group_sum_dd<S>(acc);
+    if (j < NV && k == 0) out[j] = acc;
+    __syncthreads();
+  }
+};
+
 __device__ inline int block_sum_int(int v, int* lds) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -72,7 +72,8 @@ struct nll_model {
   nll_schedule sched{4, 2, 16384, 16, 2};
 
   // single dataset
-  double* partials = nullptr;
+  double* partials = nullptr;       // two halves of partials_half doubles each
+  size_t partials_half = 0;
   nllmi::PerTheta* pt_single = nullptr;
   int* status = nullptr;
   unsigned long long* dbad = nullptr;
