@@ -224,7 +224,11 @@ nll_status nll_eval_points(nll_model* model, int32_t n_points, const double* the
 nll_status nll_fit_batched(nll_model* model, int32_t n_sets, const int64_t* offsets, double* theta,
                            int32_t n_steps, double eta, double* nll_out, double* grad_out, int32_t* status_out);
 
-/* Enqueue: the same fit on all attached events as one dataset. */
+/* Enqueue: the same fit on all attached events as one dataset.  One launch
+ * per step: each launch first takes the previous step's update (in every
+ * block, from that step's block records) and then evaluates the new
+ * proposal; one finishing kernel takes the last step's update.  Library
+ * scratch holds the fit state in two buffers by step parity. */
 nll_status nll_fit(nll_model* model, double* theta, int32_t n_steps, double eta, double* nll_out,
                    double* grad_out, int32_t* status_out);
 
@@ -299,7 +303,8 @@ nll_status nll_autotune(nll_model* model, int32_t which, int32_t n_sets, const i
  *                        with a start and a stop event attached
  *                        (hipExtLaunchKernel), so that they record that
  *                        dispatch's own start and end (its duration alone,
- *                        without the finishing kernel or queue gaps); read
+ *                        without queue gaps; in a gradient-descent fit the
+ *                        launch includes the previous step's update); read
  *                        by nll_step_times; 0 (default): no events.
  *                        Other values: NLL_ERR_ARG.                        */
 enum nll_option { NLL_OPT_GRAPH = 1, NLL_OPT_STEP_TIMING = 2 };
