@@ -385,3 +385,35 @@ def test_fit_toys_full_c4_sampled(torch, nllmi, threads):
     sd = np.sqrt(np.add.reduceat(dev * dev, off[:-1]) / sizes)
     np.testing.assert_allclose(th[:, 0], mean, rtol=0, atol=1e-7 * np.maximum(1.0, np.abs(mean)).max())
     np.testing.assert_allclose(th[:, 1], sd, rtol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# mixtures whose terms lie far apart in log-density
+# ---------------------------------------------------------------------------
+
+def _narrow_peak_specs():
+    gx = datagen.mixture_spec(f=0.05, mu=5.0, sigma=0.02, c=-0.3)
+    gg = {"obs": [{"name": "x", "lo": 0.0, "hi": 10.0}],
+          "params": [datagen.param("f", 0.1, 0.0, 1.0), datagen.param("mu1", 5.0, 0.0, 10.0),
+                     datagen.param("s1", 0.02, 0.001, 5.0), datagen.param("mu2", 4.0, 0.0, 10.0),
+                     datagen.param("s2", 3.0, 0.01, 20.0)],
+          "nodes": [{"kind": "gauss", "obs": 0, "params": [1, 2], "norm": "analytic"},
+                    {"kind": "gauss", "obs": 0, "params": [3, 4], "norm": "analytic"},
+                    {"kind": "sum", "params": [0], "children": [0, 1]}],
+          "root": 2}
+    return {"gauss+exp": gx, "gauss+gauss": gg}
+
+
+@pytest.mark.parametrize("shape", ["gauss+exp", "gauss+gauss"])
+def test_mixture_terms_far_apart(torch, nllmi, threads, shape):
+    """A peak 0.02 wide over a broad term on [0, 10]: per event the terms'
+    log-densities differ by up to ~3e4, so the factor e^(L_k - m) spans the
+    whole double range, underflows to 0 (the clamp of the per-event exp) for
+    most events, and the responsibilities reach exactly 0 and 1.  NLL and
+    gradient against the oracle at the nominal point and jittered points."""
+    spec = _narrow_peak_specs()[shape]
+    th0 = datagen.theta_of(spec)
+    print(f"[far-apart mixture {shape}]", flush=True)
+    cols = datagen.generate(spec, 60_001, seed=4242)
+    points = np.vstack([th0[None, :], datagen.jittered_points(th0, 3, seed=4243, rel=0.02)])
+    check_points(torch, nllmi, spec, cols, points, threads)
