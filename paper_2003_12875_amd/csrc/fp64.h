@@ -56,6 +56,47 @@ __device__ __forceinline__ double exp_nonpos_tab(double a, const double* __restr
   return __builtin_ldexp(fma(t, p, t), n >> 8);
 }
 
+// ln x for finite x > 0 by a table (the per-event logarithms): x = 2^e m,
+// m in [1/2, 1); the top 8 fraction bits of m pick j, the centre c_j of
+// m's interval of width 1/512, k_j = 1/c_j rounded to double and
+// L_j = -ln k_j (a table the kernel keeps in LDS), so that
+// ln m = ln(m k_j) + L_j holds exactly; r = m k_j - 1 from one FMA
+// (|r| <= 2^-9), ln(1 + r) = r + r^2 Q(r) with Q the Taylor polynomial of
+// degree 4 (truncation below 2e-20), then e ln 2 added with the two-part
+// ln 2.  The table's L_j carries the device log's rounding (about 1e-16
+// absolute), which is what the likelihood's sums of logarithms need.
+// 16 VALU instructions and one LDS read, against ~28 (with a quarter-rate
+// reciprocal) for log_pos.
+constexpr int kLogTabSize = 256;
+
+// {k_j, L_j} for j < kLogTabSize, one entry per thread of the block at the
+// kernel's start (the caller synchronises the block before the first
+// log_pos_tab).
+__device__ __forceinline__ void stage_log_table(double2* tab) {
+  for (int j = threadIdx.x; j < kLogTabSize; j += blockDim.x) {
+    const double k = 1.0 / (0.5 + ((double)j + 0.5) * (1.0 / (2 * kLogTabSize)));
+    tab[j] = make_double2(k, -log(k));
+  }
+}
+
+__device__ __forceinline__ double log_pos_tab(double x, const double2* __restrict__ tab) {
+  int e;
+  const double m = frexp(x, &e);  // m in [1/2, 1)
+  const double2 kl = tab[(__double2hiint(m) >> 12) & (kLogTabSize - 1)];
+  const double r = fma(m, kl.x, -1.0);
+  double q = fma(-0.16666666666666666, r, 0.2);
+  q = fma(q, r, -0.25);
+  q = fma(q, r, 0.3333333333333333);
+  q = fma(q, r, -0.5);
+  const double p = fma(r * r, q, r);
+  const double ed = (double)e;
+  return fma(ed, kLn2Hi, kl.y + fma(ed, kLn2Lo, p));
+}
+
+// The per-event logarithms' table: one per block, staged by the kernels
+// whose compiled shape takes a logarithm per event.
+static __shared__ double2 g_log_tab[kLogTabSize];
+
 // 1/x for the gradient features only (never the likelihood value): the
 // hardware reciprocal (2^-24 relative, measured) and one Newton step, 2^-48.
 __device__ __forceinline__ double rcp_grad(double x) {

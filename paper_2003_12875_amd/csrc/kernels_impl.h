@@ -568,6 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   using CT = typename Pass<M, GRAD>::C;
   __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
   if constexpr (CT::kExpTab) stage_exp_table(s_etab);
+  if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
   CT C;
   int bad;
   if constexpr (FIT) {
@@ -578,10 +579,8 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
     C.load(pt, pl);
     bad = uniform(pt.bad);
   }
-  if constexpr (CT::kExpTab) {
-    C.etab = s_etab;
-    __syncthreads();
-  }
+  if constexpr (CT::kExpTab) C.etab = s_etab;
+  if constexpr (CT::kExpTab || M::EVENT_LOG) __syncthreads();
   std::conditional_t<BH, AccBhhh<M>, typename Pass<M, GRAD>::A> acc;
   acc.init();
   if (bad == 0) {
@@ -745,6 +744,7 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
   double xb[ring_depth<M>()][U][M::NOBS];
   preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
   if constexpr (CT::kExpTab) stage_exp_table(s_etab);
+  if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
 
   CT C;
   int bad;
@@ -819,10 +819,9 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
   for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
   using CT = typename Pass<M, GRAD>::C;
   __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
-  if constexpr (CT::kExpTab) {
-    stage_exp_table(s_etab);
-    __syncthreads();
-  }
+  if constexpr (CT::kExpTab) stage_exp_table(s_etab);
+  if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
+  if constexpr (CT::kExpTab || M::EVENT_LOG) __syncthreads();
 
   // the next item's descriptor is loaded while the current one streams
   int64_t item = blockIdx.x;

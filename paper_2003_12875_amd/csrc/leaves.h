@@ -70,6 +70,7 @@ struct GaussLeaf {
   static constexpr int kKind = kGauss;
   static constexpr int NP = 2;
   static constexpr bool kLinear = false;
+  static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   struct C {
     double is, b;
   };
@@ -165,6 +166,7 @@ struct ExpLeaf {
   static constexpr int kKind = kExp;
   static constexpr int NP = 1;
   static constexpr bool kLinear = false;
+  static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   struct C {
     double c;
   };
@@ -260,6 +262,7 @@ struct ChebLeaf {
   static constexpr int kKind = kCheb;
   static constexpr int NP = K;
   static constexpr bool kLinear = true;
+  static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double sx, ox, a[K];
@@ -387,6 +390,7 @@ struct CBLeaf {
   static constexpr int kKind = kCB;
   static constexpr int NP = 4;
   static constexpr bool kLinear = false;
+  static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double is, b, na, logA, B, n, Ka, Kb, Kc, nOverA;
@@ -489,7 +493,7 @@ struct CBLeaf {
     }
     if (!(t > c.na)) {
       const double D = c.B - t;  // >= n / alpha > 0
-      const double lD = log_pos(D);
+      const double lD = log_pos_tab(D, g_log_tab);
       lam = fma(-c.n, lD, c.logA);
       if (GRAD) {
         const double r = rcp_grad(D);
@@ -604,6 +608,7 @@ struct ArgusLeaf {
   static constexpr int kKind = kArgus;
   static constexpr int NP = 2;
   static constexpr bool kLinear = true;
+  static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double m0, im02, c, dm0;  // dm0: 2/m0^3, or 0 when m0 is not differentiated
@@ -715,6 +720,7 @@ struct JohnsonLeaf {
   static constexpr int kKind = kJohnson;
   static constexpr int NP = 4;
   static constexpr bool kLinear = true;
+  static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
   struct C {
     double mu, il, ga, de;
   };
@@ -806,7 +812,7 @@ struct JohnsonLeaf {
     const double z = (x - c.mu) * c.il;
     const double q = fma(z, z, 1.0);  // >= 1
     const double s = sqrt_pos(q);
-    const double a = log_pos(fabs(z) + s);  // asinh |z|; the argument is >= 1
+    const double a = log_pos_tab(fabs(z) + s, g_log_tab);  // asinh |z|; the argument is >= 1
     const double A = copysign(a, z);
     const double u = fma(c.de, A, c.ga);
     const double r = rcp_full(s);
@@ -814,7 +820,7 @@ struct JohnsonLeaf {
       lam = -0.5 * u * u;
       gam = r;
     } else {
-      lam = fma(-0.5, log_pos(q), -0.5 * u * u);
+      lam = fma(-0.5, log_pos_tab(q, g_log_tab), -0.5 * u * u);
       gam = 1.0;
     }
     if (GRAD) {
@@ -900,6 +906,7 @@ struct Chi2Leaf {
   static constexpr int kKind = kChi2;
   static constexpr int NP = 1;
   static constexpr bool kLinear = false;
+  static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
   struct C {
     double km1;  // nu/2 - 1
   };
@@ -951,7 +958,7 @@ struct Chi2Leaf {
   __device__ static C load(const double* ec) { return C{ec[0]}; }
   template <bool GRAD>
   __device__ static inline void event(double x, const C& c, double& lam, double& gam, double* phi) {
-    const double lx = x > 0.0 ? log_pos(x) : -__builtin_inf();  // x = 0: p = 0 or inf (flagged)
+    const double lx = x > 0.0 ? log_pos_tab(x, g_log_tab) : -__builtin_inf();  // x = 0: p = 0 or inf (flagged)
     lam = fma(c.km1, lx, -0.5 * x);
     gam = 1.0;
     if (GRAD) phi[0] = lx;

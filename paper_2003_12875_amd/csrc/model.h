@@ -108,6 +108,8 @@ struct Model {
   using LeafC32s = std::tuple<typename Slots::Leaf::C32...>;
   static constexpr int PREC = 0;  // 0: FP64 event pass, 1: FP32-compensated
   static constexpr bool WEIGHTED = false;
+  // a logarithm per event (the kernels stage g_log_tab)
+  static constexpr bool EVENT_LOG = (Slots::Leaf::kEventLog || ...);
 
   static_assert(L >= 1 && L <= kMaxLeaves, "1..kMaxLeaves leaves");
   static_assert(K >= 1 && K <= kMaxTerms, "1..kMaxTerms terms");
@@ -121,6 +123,7 @@ struct Model {
 template <class Base>
 struct FP32C : Base {
   static constexpr int PREC = 1;
+  static constexpr bool EVENT_LOG = false;  // single-precision logarithms of its own
   static constexpr int NCNT = Base::K > 1 ? Base::K - 1 : 0;
   template <bool GRAD>
   static constexpr int CNT_BASE = Base::template NA<GRAD>;
@@ -143,6 +146,7 @@ template <class B>
 struct Weighted : B {
   using Base = B;
   static constexpr bool WEIGHTED = true;
+  static constexpr bool EVENT_LOG = true;  // each event's log-density
   static constexpr int NOBS = B::NOBS + 1;
   static_assert(B::PREC == 0 && !B::WEIGHTED, "weighted events: FP64 event pass");
   static_assert(NOBS <= kMaxObs, "weights take one observable slot");
@@ -705,7 +709,7 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<type
   double lp = e.a[0];
   // one event's product is s times the root linear factors: a normal
   // double when the density is valid; otherwise log gives -inf or NaN
-  if constexpr (B::NEED_PROD) lp += e.P > 0.0 ? log_pos(e.P) : log(e.P);
+  if constexpr (B::NEED_PROD) lp += e.P > 0.0 ? log_pos_tab(e.P, g_log_tab) : log(e.P);
   acc.a[0] = fma(w, lp, acc.a[0]);
 #pragma unroll
   for (int j = 1; j < NA; ++j) acc.a[j] = fma(w, e.a[j], acc.a[j]);
