@@ -4,9 +4,13 @@
 //   k_single   one dataset: persistent grid, each block computes the
 //              per-point constants itself, streams its tiles of the SoA
 //              event columns once (coalesced, U events per thread per
-//              tile), reduces in double-double and the last block to finish
-//              combines the block partials in block order and writes
-//              NLL (and the gradient) to device memory.
+//              tile), reduces in double-double and writes one record per
+//              block.
+//   k_single_finish  one block: the block records in block order, NLL
+//              (and the gradient) to device memory; in a fit, the update.
+//   k_single_fit  one gradient-descent step per launch: every block first
+//              takes the previous step's update from that launch's records
+//              (same bits in every block), then streams at the new proposal.
 //   k_consts   per-set constants for many datasets (one block per set).
 //   k_schedule tile counts per set and their prefix (one block).
 //   k_sets     many datasets: work items (set, tile) over a persistent
