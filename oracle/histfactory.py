@@ -21,6 +21,19 @@ checked by eye:
   (the Poisson terms without ln n_b!, unit Gaussian constraints without
   their normalisation; a bin with n_b = 0 contributes nu_b).
 
+Per-bin statistical parameters (HistFactory's "staterror", the
+Barlow-Beeston-lite treatment of the templates' own statistical error):
+samples flagged in a mask share one factor gamma_b per bin, with a
+Gaussian constraint of width sigma_b (the templates' relative statistical
+error in that bin):
+  nu_b = gamma_b nu_b^(flagged) + nu_b^(others),
+  NLL += 1/2 sum_b (gamma_b - 1)^2 / sigma_b^2,
+  d NLL / d gamma_b = w_b nu_b^(flagged) + (gamma_b - 1) / sigma_b^2,
+  w_b = 1 - n_b / nu_b (1 where n_b = 0).
+Bins with sigma_b <= 0 (or not finite) have no gamma: gamma_b is taken as
+1 there and its derivative is 0.  Reading: the constraint without its
+normalisation, like the unit Gaussians.
+
 Status codes as the unbinned oracle: 0 ok, -3 a parameter outside its
 range, -5 an expected count nu_b <= 0 where n_b > 0, or nu_b < 0.
 The derivative at alpha = 0 exactly is the alpha >= 0 side's.
@@ -43,8 +56,10 @@ def histosys_list(spec):
     return [m for m in spec["modifiers"] if m["type"] == "histosys"]
 
 
-def expected(spec, nominal, up, down, theta):
-    """nu_b (and, per parameter, d nu_b / d theta_p) by the definition."""
+def expected(spec, nominal, up, down, theta, stat=None):
+    """nu_b (and, per parameter, d nu_b / d theta_p) by the definition.
+    stat = (mask, sigma, gamma): the flagged samples' contributions to bin b
+    are multiplied by gamma_b where sigma_b > 0."""
     th = np.asarray(theta, dtype=np.float64)
     S, P = len(spec["samples"]), len(spec["params"])
     T = [np.asarray(nominal[s], dtype=np.float64) for s in range(S)]
@@ -71,6 +86,18 @@ def expected(spec, nominal, up, down, theta):
         elif m["type"] == "normsys":
             a = th[p]
             factor[s] *= m["hi"] ** a if a >= 0 else m["lo"] ** (-a)
+    # per sample and bin: the gamma_b of flagged samples (else 1)
+    gfac = [np.ones_like(T[0]) for _ in range(S)]
+    if stat is not None:
+        mask, sigma, gamma = stat
+        sig = np.asarray(sigma, dtype=np.float64)
+        active = (sig > 0) & np.isfinite(sig)
+        g_eff = np.where(active, np.asarray(gamma, dtype=np.float64), 1.0)
+        for s in range(S):
+            if (mask >> s) & 1:
+                gfac[s] = g_eff
+    shape = [gfac[s] * shape[s] for s in range(S)]
+    dshape = {k: gfac[k[0]] * v for k, v in dshape.items()}
     nu = np.zeros_like(T[0])
     for s in range(S):
         nu = nu + factor[s] * shape[s]
@@ -104,28 +131,45 @@ def expected(spec, nominal, up, down, theta):
     return nu, dnu
 
 
-def nll(spec, counts, nominal, up, down, theta, grad=True):
-    """(status, NLL, gradient) with exactly rounded sums over bins."""
+def nll(spec, counts, nominal, up, down, theta, grad=True, stat=None):
+    """(status, NLL, gradient) with exactly rounded sums over bins.  With
+    stat = (mask, sigma, gamma) (per-bin statistical parameters, see the
+    header): (status, NLL, gradient, d NLL / d gamma_b per bin)."""
     th = np.asarray(theta, dtype=np.float64)
     P = len(spec["params"])
+    n = np.asarray(counts, dtype=np.float64)
+    bad = (E_PARAM, math.inf, np.zeros(P)) + ((np.zeros(len(n)),) if stat is not None else ())
     for p, par in enumerate(spec["params"]):
         if not (par["lo"] <= th[p] <= par["hi"]):
-            return E_PARAM, math.inf, np.zeros(P)
-    n = np.asarray(counts, dtype=np.float64)
-    nu, dnu = expected(spec, nominal, up, down, th)
+            return bad
+    nu, dnu = expected(spec, nominal, up, down, th, stat)
     if np.any(nu < 0) or np.any((n > 0) & ~(nu > 0)) or not np.all(np.isfinite(nu)):
-        return E_PDF, math.inf, np.zeros(P)
+        return (E_PDF,) + bad[1:]
     pos = n > 0
     terms = nu.copy()
     terms[pos] = nu[pos] - n[pos] * np.log(nu[pos])
     cons = [0.5 * th[p] ** 2 for p, par in enumerate(spec["params"]) if par.get("constrained", False)]
+    if stat is not None:
+        mask, sigma, gamma = stat
+        sig = np.asarray(sigma, dtype=np.float64)
+        active = (sig > 0) & np.isfinite(sig)
+        gam = np.asarray(gamma, dtype=np.float64)
+        cons.append(math.fsum(0.5 * (gam[active] - 1.0) ** 2 / sig[active] ** 2))
     value = math.fsum(terms) + math.fsum(cons)
     g = np.zeros(P)
+    w = np.ones_like(nu)
+    w[pos] = 1.0 - n[pos] / nu[pos]
     if grad:
-        w = np.ones_like(nu)
-        w[pos] = 1.0 - n[pos] / nu[pos]
         for p, par in enumerate(spec["params"]):
             if not par.get("free", True):
                 continue
             g[p] = math.fsum(w * dnu[p]) + (th[p] if par.get("constrained", False) else 0.0)
-    return OK, value, g
+    if stat is None:
+        return OK, value, g
+    # d nu_b / d gamma_b = the flagged samples' part of nu_b without gamma:
+    # nu_b with the other samples multiplied by 0 and gamma = 1
+    S = len(spec["samples"])
+    others = (~mask) & ((1 << S) - 1)
+    nu_flag = expected(spec, nominal, up, down, th, (others, np.ones(len(n)), np.zeros(len(n))))[0]
+    gg = np.where(active, w * nu_flag + (gam - 1.0) / np.where(active, sig, 1.0) ** 2, 0.0)
+    return OK, value, g, gg

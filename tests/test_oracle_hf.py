@@ -108,3 +108,114 @@ def test_constraint_term_and_status(small):
     one = {"n_bins": 1000, "samples": ["s0"], "params": [spec["params"][0]],
            "modifiers": [{"type": "normfactor", "sample": 0, "param": 0}]}
     assert hf.nll(one, n, T[:1], [], [], [0.0])[0] == hf.E_PDF
+
+
+# ---------------------------------------------------------------------------
+# per-bin statistical parameters (gamma_b of the flagged samples)
+# ---------------------------------------------------------------------------
+
+def _stat(n_bins, seed=5):
+    rng = np.random.default_rng(seed)
+    sigma = rng.uniform(0.01, 0.1, n_bins)
+    sigma[::7] = 0.0          # bins without a statistical parameter
+    sigma[3::11] = np.inf     # not finite: none either
+    gamma = 1.0 + rng.uniform(-0.05, 0.05, n_bins)
+    return sigma, gamma
+
+
+def test_stat_gamma_one_is_the_plain_model(small):
+    """gamma = 1 everywhere: the plain NLL and gradient (no constraint
+    contribution), and d NLL / d gamma_b = w_b times the flagged samples'
+    part of nu_b."""
+    spec, n, T, up, dn = args(small)
+    sigma, _ = _stat(len(n))
+    mask = 0b101
+    th = small["points"][0]
+    st0, v0, g0 = hf.nll(spec, n, T, up, dn, th)
+    st, v, g, gg = hf.nll(spec, n, T, up, dn, th, stat=(mask, sigma, np.ones(len(n))))
+    assert st == st0 == hf.OK
+    assert v == v0 and np.array_equal(g, g0)
+    nu, _ = hf.expected(spec, T, up, dn, th)
+    # the flagged samples' part: switch the others off with a zero normfactor-free copy of the model
+    spec_f = copy.deepcopy(spec)
+    nu_f = np.zeros(len(n))
+    for s in range(len(spec["samples"])):
+        if (mask >> s) & 1:
+            Ts = [T[k] if k == s else np.zeros(len(n)) for k in range(len(T))]
+            ups = [u if m["sample"] == s else np.zeros(len(n)) for u, m in zip(up, hf.histosys_list(spec))]
+            dns = [d if m["sample"] == s else np.zeros(len(n)) for d, m in zip(dn, hf.histosys_list(spec))]
+            nu_f += hf.expected(spec_f, Ts, ups, dns, th)[0]
+    w = np.where(n > 0, 1.0 - n / nu, 1.0)
+    active = (sigma > 0) & np.isfinite(sigma)
+    np.testing.assert_allclose(gg[active], (w * nu_f)[active], rtol=1e-12, atol=1e-12 * np.abs(nu_f).max())
+    assert np.all(gg[~active] == 0.0)
+
+
+def test_stat_poisson_terms_and_constraint_match_scipy():
+    """One flagged sample scaled by a normfactor: nu_b = mu gamma_b T_b by
+    hand, the NLL against scipy's Poisson log-probability plus the Gaussian
+    constraints (gamma_b - 1)^2 / (2 sigma_b^2) of the bins that have one."""
+    w = datagen.hf_workload(n_bins=2000, n_samples=1, n_histosys=0, n_normsys=0)
+    spec = {"n_bins": 2000, "samples": ["s0"], "params": [w["spec"]["params"][0]],
+            "modifiers": [{"type": "normfactor", "sample": 0, "param": 0}]}
+    n, T = w["counts"], w["nominal"]
+    sigma, gamma = _stat(2000, seed=9)
+    mu = 1.07
+    st, v, g, gg = hf.nll(spec, n, T, [], [], [mu], stat=(1, sigma, gamma))
+    active = (sigma > 0) & np.isfinite(sigma)
+    nu = mu * np.where(active, gamma, 1.0) * T[0]
+    ref = (-math.fsum(stats.poisson.logpmf(n, nu)) - math.fsum(special.gammaln(n + 1))
+           + math.fsum(0.5 * ((gamma - 1.0) / sigma)[active] ** 2))
+    assert st == hf.OK and abs(v - ref) <= 1e-12 * abs(ref)
+    # d/d mu and d/d gamma_b by hand
+    wb = np.where(n > 0, 1.0 - n / nu, 1.0)
+    assert abs(g[0] - math.fsum(wb * nu / mu)) <= 1e-10 * abs(g[0])
+    np.testing.assert_allclose(gg[active], (wb * nu / gamma + (gamma - 1.0) / sigma ** 2)[active], rtol=1e-10)
+
+
+def test_stat_one_bin_closed_form_minimum():
+    """One bin, one flagged sample A gamma with a Gaussian constraint of width
+    sigma: A - n / gamma + (gamma - 1) / sigma^2 = 0 has the positive root
+    gamma = [tau - A + sqrt((A - tau)^2 + 4 tau n)] / (2 tau), tau = 1/sigma^2;
+    the oracle's derivative vanishes there and the NLL rises on both sides."""
+    spec = {"n_bins": 1, "samples": ["s0"],
+            "params": [{"name": "mu", "value": 1.0, "lo": 0.0, "hi": 10.0, "free": False, "constrained": False}],
+            "modifiers": [{"type": "normfactor", "sample": 0, "param": 0}]}
+    for A, n_obs, sig in ((40.0, 52.0, 0.1), (7.5, 3.0, 0.3), (1000.0, 1100.0, 0.02)):
+        tau = 1.0 / sig ** 2
+        gam = (tau - A + math.sqrt((A - tau) ** 2 + 4.0 * tau * n_obs)) / (2.0 * tau)
+        s = (1, np.array([sig]), np.array([gam]))
+        st, v, _, gg = hf.nll(spec, np.array([n_obs]), [np.array([A])], [], [], [1.0], stat=s)
+        assert st == hf.OK and abs(gg[0]) <= 1e-9 * (A + tau)
+        for d in (1e-4, -1e-4):
+            s2 = (1, np.array([sig]), np.array([gam * (1 + d)]))
+            assert hf.nll(spec, np.array([n_obs]), [np.array([A])], [], [], [1.0], stat=s2)[1] > v
+
+
+def test_stat_gradients_match_central_differences(small):
+    spec, n, T, up, dn = args(small)
+    sigma, gamma = _stat(len(n), seed=11)
+    mask = 0b011
+    th = small["points"][1]
+    st, v, g, gg = hf.nll(spec, n, T, up, dn, th, stat=(mask, sigma, gamma))
+    assert st == hf.OK
+    h = 1e-6
+    for b in (0, 1, 2, 7, 14, 500, 999):
+        gp, gm = gamma.copy(), gamma.copy()
+        gp[b] += h
+        gm[b] -= h
+        fd = (hf.nll(spec, n, T, up, dn, th, grad=False, stat=(mask, sigma, gp))[1]
+              - hf.nll(spec, n, T, up, dn, th, grad=False, stat=(mask, sigma, gm))[1]) / (2 * h)
+        assert abs(fd - gg[b]) <= 1e-5 * (1 + abs(gg[b])) + 20 * 2.2e-16 * abs(v) / h, (b, fd, gg[b])
+    for p in range(len(th)):
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (hf.nll(spec, n, T, up, dn, tp, grad=False, stat=(mask, sigma, gamma))[1]
+              - hf.nll(spec, n, T, up, dn, tm, grad=False, stat=(mask, sigma, gamma))[1]) / (2 * h)
+        assert abs(fd - g[p]) <= 1e-5 * (1 + abs(g[p])) + 20 * 2.2e-16 * abs(v) / h, (p, fd, g[p])
+    # bins without a statistical parameter ignore gamma_b
+    inactive = np.flatnonzero(~((sigma > 0) & np.isfinite(sigma)))
+    g2 = gamma.copy()
+    g2[inactive] = 3.0
+    assert hf.nll(spec, n, T, up, dn, th, grad=False, stat=(mask, sigma, g2))[1] == v
