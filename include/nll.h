@@ -399,6 +399,34 @@ nll_status nll_hf_set_data(nll_hf_model* model, const double* counts, const doub
  * finishing block. */
 nll_status nll_hf_eval(nll_hf_model* model, const double* theta, double* nll_out, double* grad_out);
 
+/* Per-bin statistical parameters (HistFactory's staterror: the templates'
+ * own statistical error, Barlow-Beeston lite).  The samples flagged in
+ * sample_mask (bit s: sample s; nonzero, below 2^n_samples) share one
+ * factor gamma_b per bin, with a Gaussian constraint of width sigma_b:
+ *   nu_b = gamma_b (flagged samples' terms of bin b, histosys deltas
+ *          included) + (the other samples' terms),
+ *   NLL += 1/2 sum_b (gamma_b - 1)^2 / sigma_b^2.
+ * sigma (device [n_bins]; the flagged templates' relative statistical
+ * error per bin) is read once, now, into the library's 1/sigma_b^2; a bin
+ * with sigma_b <= 0 or not finite has no parameter (gamma_b taken as 1,
+ * derivative 0).  Enqueued on the model's stream; may be called again to
+ * replace mask and widths.  Errors: NLL_ERR_ARG (mask, unaligned sigma),
+ * NLL_ERR_DEVICE, NLL_ERR_OOM. */
+nll_status nll_hf_set_staterror(nll_hf_model* model, uint32_t sample_mask, const double* sigma);
+
+/* Enqueue: as nll_hf_eval with the per-bin statistical parameters at gamma
+ * (device [n_bins], caller's): NLL into *nll_out, the parameters' gradient
+ * into grad_out (device [n_param] or NULL) and d NLL / d gamma_b =
+ * w_b (flagged part of nu_b) + (gamma_b - 1) / sigma_b^2, w_b = 1 - n_b/nu_b
+ * (1 where n_b = 0), into grad_gamma (device [n_bins] or NULL; 0 for bins
+ * without a parameter).  24 more bytes per bin than nll_hf_eval (gamma,
+ * 1/sigma^2, the derivative).  Status as nll_hf_eval (a non-finite or
+ * negative gamma_b that makes nu_b invalid: NLL_ERR_INVALID_PDF through
+ * nll_hf_sync).  NLL_ERR_STATE before nll_hf_set_data and
+ * nll_hf_set_staterror. */
+nll_status nll_hf_eval_stat(nll_hf_model* model, const double* theta, const double* gamma, double* nll_out,
+                            double* grad_out, double* grad_gamma);
+
 /* Synchronise and return (and clear) the device status (as nll_sync). */
 nll_status nll_hf_sync(nll_hf_model* model, int32_t* status_out);
 

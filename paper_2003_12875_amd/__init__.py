@@ -438,6 +438,37 @@ class HFModel:
         check(lib().nll_hf_eval(self._h, theta.data_ptr(), out.data_ptr(), grad.data_ptr()), "nll_hf_eval")
         return out, grad
 
+    def set_staterror(self, samples, sigma):
+        """Per-bin statistical parameters gamma_b shared by `samples` (sample
+        indices), with Gaussian constraints of widths sigma[B] (relative
+        statistical error per bin; <= 0: no parameter in that bin)."""
+        torch = _torch()
+        mask = 0
+        for s in samples:
+            mask |= 1 << int(s)
+        sigma = _dev_tensor(sigma, torch.float64, self.device)
+        if sigma.numel() != self.n_bins:
+            raise NLLError(-1, "sigma needs n_bins entries")
+        check(lib().nll_hf_set_staterror(self._h, mask, sigma.data_ptr()), "nll_hf_set_staterror")
+        self._keep_sigma = sigma  # read on the stream; kept until that is done
+
+    def eval_stat(self, theta, gamma, grad=True):
+        """(NLL, gradient or None, d NLL / d gamma or None) at theta and the
+        per-bin statistical parameters gamma[B]."""
+        torch = _torch()
+        f64 = torch.float64
+        theta = _dev_tensor(theta, f64, self.device)
+        gamma = _dev_tensor(gamma, f64, self.device)
+        if gamma.numel() != self.n_bins:
+            raise NLLError(-1, "gamma needs n_bins entries")
+        out = torch.empty(1, dtype=f64, device=self.device)
+        g = torch.empty(self.n_param, dtype=f64, device=self.device) if grad else None
+        gg = torch.empty(self.n_bins, dtype=f64, device=self.device) if grad else None
+        check(lib().nll_hf_eval_stat(self._h, theta.data_ptr(), gamma.data_ptr(), out.data_ptr(),
+                                     g.data_ptr() if grad else None, gg.data_ptr() if grad else None),
+              "nll_hf_eval_stat")
+        return out, g, gg
+
     def sync(self) -> int:
         st = ctypes.c_int32(0)
         check(lib().nll_hf_sync(self._h, ctypes.byref(st)), "nll_hf_sync")

@@ -19,6 +19,7 @@ EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_d
            "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
            "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
            "nll_status_string", "nll_hf_create", "nll_hf_destroy", "nll_hf_set_data", "nll_hf_eval", "nll_hf_sync",
+           "nll_hf_set_staterror", "nll_hf_eval_stat",
            "nll_jit_create", "nll_jit_destroy", "nll_jit_set_data", "nll_jit_eval", "nll_jit_sync")
 
 HF_MAX_SAMPLES, HF_MAX_HISTOSYS = 8, 24
@@ -119,6 +120,8 @@ def lib():
         L.nll_hf_destroy.restype = None
         L.nll_hf_set_data.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
         L.nll_hf_eval.argtypes = [vp, vp, vp, vp]
+        L.nll_hf_set_staterror.argtypes = [vp, ctypes.c_uint32, vp]
+        L.nll_hf_eval_stat.argtypes = [vp, vp, vp, vp, vp, vp]
         L.nll_hf_sync.argtypes = [vp, ctypes.POINTER(i32)]
         L.nll_jit_create.argtypes = [ctypes.POINTER(JitDesc), ctypes.POINTER(vp), ctypes.c_char_p, i32]
         L.nll_jit_destroy.argtypes = [vp]

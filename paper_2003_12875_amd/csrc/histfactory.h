@@ -5,6 +5,9 @@
 //
 //   nu_b = sum_s F_s(theta) T_sb + sum_h c_h(theta) d_hb
 //   NLL  = sum_b (nu_b - n_b ln nu_b) + 1/2 sum_{constrained p} theta_p^2
+// and, with per-bin statistical parameters (HistFactory's staterror), the
+// flagged samples' terms of bin b times gamma_b, plus
+// 1/2 sum_b (gamma_b - 1)^2 / sigma_b^2 over the bins that have one.
 //
 // F_s: the sample's normfactors times its normsys factors
 // (eta = hi^alpha for alpha >= 0, lo^-alpha below); histosys h on sample
@@ -43,7 +46,7 @@ struct HFPlan {
   int32_t histo_sample[kHfMaxHisto], histo_param[kHfMaxHisto];
   int32_t par_start[kMaxParams + 1], par_slot[kHfSlots];
   int32_t par_free[kMaxParams], par_constrained[kMaxParams];
-  int32_t pad;
+  int32_t stat_mask;  // samples scaled by the per-bin statistical parameters gamma_b
   double ns_lnhi[kHfMaxNormsys], ns_lnlo[kHfMaxNormsys];
   double par_lo[kMaxParams], par_hi[kMaxParams];
 };
@@ -59,10 +62,17 @@ struct HFArgs {
   double* grad_out;                     // n_param or null
   double* partials;                     // grid * kHfNV double-double pairs
   int* status;                          // accumulated status bits
+  // per-bin statistical parameters (nll_hf_eval_stat): gamma_b (caller's),
+  // tau_b = 1/sigma_b^2 (library's; < 0 where the bin has none), and
+  // d NLL / d gamma_b (caller's, n_bins, or null)
+  const double* gamma;
+  const double* stat_tau;
+  double* grad_gamma;
 };
 
 hipError_t launch_hf_deltas(const double* nominal, const double* up, const double* down, int64_t n, double* dup,
                             double* ddn, hipStream_t st);
 hipError_t launch_hf_eval(const HFPlan& pl, const HFArgs& a, bool grad, int grid, hipStream_t st);
+hipError_t launch_hf_tau(const double* sigma, int64_t n, double* tau, hipStream_t st);
 
 }  // namespace nllmi

@@ -64,7 +64,23 @@ __device__ inline bool hf_par_ok(const HFPlan& pl, const double* theta, int p) {
   return theta[p] >= pl.par_lo[p] && theta[p] <= pl.par_hi[p];  // NaN fails
 }
 
-template <bool GRAD>
+// tau_b = 1/sigma_b^2 of the per-bin statistical parameters, -1 where the
+// bin has none (sigma_b <= 0 or not finite), once at nll_hf_set_staterror.
+__global__ __launch_bounds__(kBlock) void k_hf_tau(const double* __restrict__ sigma, int64_t n,
+                                                   double* __restrict__ tau) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double s = sigma[i];
+    tau[i] = (s > 0.0 && __builtin_isfinite(s)) ? 1.0 / (s * s) : -1.0;
+  }
+}
+
+// STAT: the flagged samples' terms (nominal and histosys deltas) of bin b
+// are summed apart, nu_b = gamma_b nu_flagged + nu_rest, their weighted sums
+// take gamma_b, the constraint 1/2 tau_b (gamma_b - 1)^2 joins the bin's
+// term, and d NLL / d gamma_b = w_b nu_flagged + tau_b (gamma_b - 1) is
+// written per bin (0 where the bin has no parameter: gamma_b taken as 1).
+template <bool GRAD, bool STAT>
 __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const HFArgs a) {
   constexpr int NH = kHfNV / 2, NH2 = kHfNV - NH;  // two reduction passes
   __shared__ HFPlan pl;
@@ -92,6 +108,11 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
   const int S = pl.n_samples, H = pl.n_histo;
   double F[kHfMaxSamples], c[kHfMaxHisto];
   const double* dp[kHfMaxHisto];
+  bool fs[kHfMaxSamples], fh[kHfMaxHisto];  // flagged for gamma (uniform)
+#pragma unroll
+  for (int s = 0; s < kHfMaxSamples; ++s) fs[s] = STAT && ((pl.stat_mask >> s) & 1);
+#pragma unroll
+  for (int h = 0; h < kHfMaxHisto; ++h) fh[h] = STAT && h < H && ((pl.stat_mask >> pl.histo_sample[h]) & 1);
 #pragma unroll
   for (int s = 0; s < kHfMaxSamples; ++s) F[s] = hf_uniform(s_F[s]);
 #pragma unroll
@@ -112,22 +133,50 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
       for (int s = 0; s < kHfMaxSamples; ++s) T[s] = s < S ? a.nominal[s][b] : 0.0;
 #pragma unroll
       for (int h = 0; h < kHfMaxHisto; ++h) d[h] = h < H ? dp[h][b] : 0.0;
-      double nu = 0.0;
+      double nu = 0.0, nu_f = 0.0, g = 1.0, tau = 0.0;
+      bool act = false;
+      if constexpr (STAT) {
+        tau = a.stat_tau[b];
+        act = tau > 0.0;
+        const double gb = a.gamma[b];
+        g = act ? gb : 1.0;
 #pragma unroll
-      for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(F[s], T[s], nu);
+        for (int s = 0; s < kHfMaxSamples; ++s) {
+          if (fs[s]) nu_f = fma(F[s], T[s], nu_f);
+          else nu = fma(F[s], T[s], nu);
+        }
 #pragma unroll
-      for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(c[h], d[h], nu);
+        for (int h = 0; h < kHfMaxHisto; ++h) {
+          if (fh[h]) nu_f = fma(c[h], d[h], nu_f);
+          else nu = fma(c[h], d[h], nu);
+        }
+        nu = fma(g, nu_f, nu);
+      } else {
+#pragma unroll
+        for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(F[s], T[s], nu);
+#pragma unroll
+        for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(c[h], d[h], nu);
+      }
       const bool pos = n > 0.0;
       bad += !(nu >= 0.0) || (pos && !(nu > 0.0));
       // n = 0: the bin contributes nu and no logarithm
       const double lnu = pos && nu > 0.0 ? log_pos(nu) : 0.0;
       acc[0] += fma(-n, lnu, nu);
+      if constexpr (STAT) {
+        const double dg = g - 1.0;
+        if (act) acc[0] = fma(0.5 * tau * dg, dg, acc[0]);
+      }
       if constexpr (GRAD) {
         const double w = pos ? fma(-n, rcp_full(nu), 1.0) : 1.0;
+        const double wg = w * g;
 #pragma unroll
-        for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(w, T[s], acc[1 + s]);
+        for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(fs[s] ? wg : w, T[s], acc[1 + s]);
 #pragma unroll
-        for (int h = 0; h < kHfMaxHisto; ++h) acc[1 + kHfMaxSamples + h] = fma(w, d[h], acc[1 + kHfMaxSamples + h]);
+        for (int h = 0; h < kHfMaxHisto; ++h)
+          acc[1 + kHfMaxSamples + h] = fma(fh[h] ? wg : w, d[h], acc[1 + kHfMaxSamples + h]);
+        if constexpr (STAT) {
+          if (a.grad_gamma) a.grad_gamma[b] = act ? fma(w, nu_f, tau * (g - 1.0)) : 0.0;
+        }
       }
     }
   }
@@ -254,9 +303,23 @@ hipError_t launch_hf_deltas(const double* nominal, const double* up, const doubl
   return hipGetLastError();
 }
 
+hipError_t launch_hf_tau(const double* sigma, int64_t n, double* tau, hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_hf_tau, dim3((unsigned)blocks), dim3(kBlock), 0, st, sigma, n, tau);
+  return hipGetLastError();
+}
+
 hipError_t launch_hf_eval(const HFPlan& pl, const HFArgs& a, bool grad, int grid, hipStream_t st) {
-  if (grad) hipLaunchKernelGGL((k_hf_stream<true>), dim3(grid), dim3(kBlock), 0, st, pl, a);
-  else hipLaunchKernelGGL((k_hf_stream<false>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  const bool stat = a.gamma != nullptr;
+  if (stat) {
+    if (grad) hipLaunchKernelGGL((k_hf_stream<true, true>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+    else hipLaunchKernelGGL((k_hf_stream<false, true>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  } else {
+    if (grad) hipLaunchKernelGGL((k_hf_stream<true, false>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+    else hipLaunchKernelGGL((k_hf_stream<false, false>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (grad) hipLaunchKernelGGL((k_hf_finish<true>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);

@@ -28,6 +28,8 @@ struct nll_hf_model {
   int* status = nullptr;
   unsigned long long* dbad = nullptr;
   bool have_data = false;
+  double* stat_tau = nullptr;    // per-bin statistical parameters: 1/sigma_b^2, -1 where none
+  bool have_stat = false;
 };
 
 namespace {
@@ -172,6 +174,7 @@ void nll_hf_destroy(nll_hf_model* m) {
   hf_free(m->partials);
   hf_free(m->status);
   hf_free(m->dbad);
+  hf_free(m->stat_tau);
   delete m;
 }
 
@@ -212,9 +215,24 @@ nll_status nll_hf_set_data(nll_hf_model* m, const double* counts, const double* 
   return NLL_OK;
 }
 
-nll_status nll_hf_eval(nll_hf_model* m, const double* theta, double* nll_out, double* grad_out) {
-  if (!m || !theta || !nll_out) return NLL_ERR_ARG;
-  if (!m->have_data) return NLL_ERR_STATE;
+nll_status nll_hf_set_staterror(nll_hf_model* m, uint32_t sample_mask, const double* sigma) {
+  if (!m) return NLL_ERR_ARG;
+  const int S = m->plan.n_samples;
+  if (sample_mask == 0 || (S < 32 && (sample_mask >> S) != 0)) return NLL_ERR_ARG;
+  if (m->n_bins > 0 && !aligned(sigma)) return NLL_ERR_ARG;
+  DeviceGuard guard(m->device);
+  if (!m->stat_tau) {
+    const nll_status st = hf_alloc(&m->stat_tau, (size_t)m->n_bins);
+    if (st != NLL_OK) return st;
+  }
+  if (m->n_bins > 0 && launch_hf_tau(sigma, m->n_bins, m->stat_tau, m->stream) != hipSuccess) return NLL_ERR_DEVICE;
+  m->plan.stat_mask = (int32_t)sample_mask;
+  m->have_stat = true;
+  return NLL_OK;
+}
+
+static nll_status hf_eval_impl(nll_hf_model* m, const double* theta, const double* gamma, double* nll_out,
+                               double* grad_out, double* grad_gamma) {
   DeviceGuard guard(m->device);
   HFArgs a{};
   a.n_bins = m->n_bins;
@@ -229,8 +247,27 @@ nll_status nll_hf_eval(nll_hf_model* m, const double* theta, double* nll_out, do
   a.grad_out = grad_out;
   a.partials = m->partials;
   a.status = m->status;
-  const hipError_t e = launch_hf_eval(m->plan, a, grad_out != nullptr, hf_grid(m), m->stream);
+  a.gamma = gamma;
+  a.stat_tau = gamma ? m->stat_tau : nullptr;
+  a.grad_gamma = gamma ? grad_gamma : nullptr;
+  const bool grad = grad_out != nullptr || a.grad_gamma != nullptr;
+  const hipError_t e = launch_hf_eval(m->plan, a, grad, hf_grid(m), m->stream);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
+}
+
+nll_status nll_hf_eval(nll_hf_model* m, const double* theta, double* nll_out, double* grad_out) {
+  if (!m || !theta || !nll_out) return NLL_ERR_ARG;
+  if (!m->have_data) return NLL_ERR_STATE;
+  return hf_eval_impl(m, theta, nullptr, nll_out, grad_out, nullptr);
+}
+
+nll_status nll_hf_eval_stat(nll_hf_model* m, const double* theta, const double* gamma, double* nll_out,
+                            double* grad_out, double* grad_gamma) {
+  if (!m || !theta || !nll_out) return NLL_ERR_ARG;
+  if (m->n_bins > 0 && (!aligned(gamma) || (grad_gamma && !aligned(grad_gamma)))) return NLL_ERR_ARG;
+  if (!m->have_data || !m->have_stat) return NLL_ERR_STATE;
+  if (m->n_bins == 0) return hf_eval_impl(m, theta, nullptr, nll_out, grad_out, nullptr);
+  return hf_eval_impl(m, theta, gamma, nll_out, grad_out, grad_gamma);
 }
 
 nll_status nll_hf_sync(nll_hf_model* m, int32_t* status_out) {

@@ -159,3 +159,88 @@ def test_hf_autograd_lbfgs_fit(torch, nllmi):
     G = max(float(np.sum(np.abs(np.where(n > 0, 1.0 - n / nu, 1.0) * d))) for d in dnu)
     assert st == hf.OK and v < v0
     assert np.max(np.abs(g)) <= 1e-8 * G, (g, G)
+
+
+# ---------------------------------------------------------------------------
+# per-bin statistical parameters (HistFactory's staterror)
+# ---------------------------------------------------------------------------
+
+def _stat_inputs(n_bins, seed):
+    rng = np.random.default_rng(seed)
+    sigma = rng.uniform(0.01, 0.1, n_bins)
+    sigma[::7] = 0.0       # bins without a parameter
+    sigma[3::11] = np.inf  # not finite: none either
+    gamma = 1.0 + rng.uniform(-0.05, 0.05, n_bins)
+    return sigma, gamma
+
+
+def check_stat(torch, m, spec, w, mask, sigma, gamma, points):
+    for th in points:
+        st, ref, gref, ggref = hf.nll(spec, w["counts"], w["nominal"], w["up"], w["down"], th,
+                                      stat=(mask, sigma, gamma))
+        assert st == hf.OK
+        nu, dnu = hf.expected(spec, w["nominal"], w["up"], w["down"], th, (mask, sigma, gamma))
+        n = w["counts"]
+        wgt = np.where(n > 0, 1.0 - n / np.where(nu > 0, nu, 1.0), 1.0)
+        G = max(float(np.sum(np.abs(wgt * d))) for d in dnu) if len(dnu) else 0.0
+        v, g, gg = m.eval_stat(torch.from_numpy(np.ascontiguousarray(th)), torch.from_numpy(gamma))
+        v, g, gg = float(v.item()), g.cpu().numpy(), gg.cpu().numpy()
+        assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), G), (th, g, gref)
+        # per bin: one term and the constraint, so relative to the bin's own scale
+        scale = np.abs(wgt) * np.abs(nu) + np.abs(ggref) + 1.0
+        assert np.all(np.abs(gg - ggref) <= 1e-12 * scale), np.max(np.abs(gg - ggref) / scale)
+        v0, g0, gg0 = m.eval_stat(torch.from_numpy(np.ascontiguousarray(th)), torch.from_numpy(gamma), grad=False)
+        assert abs(float(v0.item()) - ref) <= NLL_TOL * abs(ref) and g0 is None and gg0 is None
+    assert m.sync() == 0
+
+
+@pytest.mark.parametrize("n_bins", [1, 257, 100_003])
+def test_hf_staterror(torch, nllmi, n_bins):
+    """Two of three samples (histosys deltas included) scaled by gamma_b, bins
+    with and without a parameter; NLL, gradient and d NLL / d gamma_b per bin
+    against the oracle.  The plain evaluation of the same model is unchanged."""
+    w = datagen.hf_workload(n_bins=n_bins, n_samples=3, n_histosys=5, n_normsys=3, n_points=2)
+    print(f"[hf staterror B={n_bins}]", flush=True)
+    m = make(nllmi, w)
+    sigma, gamma = _stat_inputs(n_bins, seed=21 + n_bins)
+    m.set_staterror([0, 2], sigma)
+    check_stat(torch, m, w["spec"], w, 0b101, sigma, gamma, w["points"])
+    check(torch, m, w["spec"], w, w["points"][:1])
+    # gamma = 1: the plain model's NLL and gradient
+    v, g, _ = m.eval_stat(torch.from_numpy(np.ascontiguousarray(w["points"][0])), torch.ones(n_bins, dtype=torch.float64))
+    v1, g1 = m.eval_grad(torch.from_numpy(np.ascontiguousarray(w["points"][0])))
+    assert abs(float(v.item()) - float(v1.item())) <= 1e-13 * abs(float(v1.item()))
+    np.testing.assert_allclose(g.cpu().numpy(), g1.cpu().numpy(), rtol=1e-12, atol=1e-9)
+
+
+def test_hf_staterror_full(torch, nllmi):
+    """The benchmarked template model (2e6 bins) with the first two samples
+    flagged."""
+    w = datagen.hf_workload(n_points=1)
+    print("[hf staterror B=2e6]", flush=True)
+    m = make(nllmi, w)
+    sigma, gamma = _stat_inputs(w["spec"]["n_bins"], seed=33)
+    m.set_staterror([0, 1], sigma)
+    check_stat(torch, m, w["spec"], w, 0b11, sigma, gamma, w["points"])
+
+
+def test_hf_staterror_errors(torch, nllmi):
+    w = datagen.hf_workload(n_bins=1000, n_samples=2, n_histosys=1, n_normsys=1, n_points=1)
+    m = make(nllmi, w)
+    th = torch.from_numpy(np.ascontiguousarray(w["points"][0]))
+    gamma = torch.ones(1000, dtype=torch.float64)
+    with pytest.raises(nllmi.NLLError):
+        m.eval_stat(th, gamma)  # no staterror set yet
+    sigma = np.full(1000, 0.05)
+    for bad in ([], [2], [0, 5]):
+        with pytest.raises(nllmi.NLLError):
+            m.set_staterror(bad, sigma)
+    m.set_staterror([1], sigma)
+    # a negative gamma_b that makes nu_b negative: +inf and the invalid-density status
+    g2 = gamma.clone()
+    g2[10] = -50.0
+    v, _, _ = m.eval_stat(th, g2)
+    assert math.isinf(float(v.item())) and m.sync() == -5
+    v, _, _ = m.eval_stat(th, gamma)
+    assert math.isfinite(float(v.item())) and m.sync() == 0
