@@ -447,6 +447,22 @@ def extras(torch, nllmi, datagen, args):
                                   "bytes_per_eval": nbytes, "achieved_GBs": nbytes / (tg * 1e-3) / 1e9,
                                   "hbm_frac": nbytes / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                   "status": mh.sync()}
+    # the same model with per-bin statistical parameters on the first two
+    # samples: gamma_b and 1/sigma_b^2 read, d NLL / d gamma_b written per bin
+    import numpy as np
+    rng = np.random.default_rng(2003012875 + 9000)
+    sigma = torch.as_tensor(rng.uniform(0.01, 0.1, mh.n_bins), dtype=torch.float64, device="cuda")
+    gam = torch.as_tensor(1.0 + rng.uniform(-0.05, 0.05, mh.n_bins), dtype=torch.float64, device="cuda")
+    gg = torch.empty(mh.n_bins, dtype=torch.float64, device="cuda")
+    mh.set_staterror([0, 1], sigma)
+    L = nllmi.lib()
+    ts = time_launches(torch, lambda: L.nll_hf_eval_stat(mh._h, th.data_ptr(), gam.data_ptr(), out.data_ptr(),
+                                                         g.data_ptr(), gg.data_ptr()), 20)
+    sbytes = nbytes + 24.0 * mh.n_bins
+    ex["histfactory_2e6_bins"]["staterror"] = {"eval_grad_ms": ts, "bytes_per_eval": sbytes,
+                                               "achieved_GBs": sbytes / (ts * 1e-3) / 1e9,
+                                               "hbm_frac": sbytes / (ts * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                               "status": mh.sync()}
     del mh
     torch.cuda.empty_cache()
     # just-in-time density: a Gaussian written as an expression string on the
