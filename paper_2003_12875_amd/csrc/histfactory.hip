@@ -108,17 +108,25 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
   const int S = pl.n_samples, H = pl.n_histo;
   double F[kHfMaxSamples], c[kHfMaxHisto];
   const double* dp[kHfMaxHisto];
-  bool fs[kHfMaxSamples], fh[kHfMaxHisto];  // flagged for gamma (uniform)
-#pragma unroll
-  for (int s = 0; s < kHfMaxSamples; ++s) fs[s] = STAT && ((pl.stat_mask >> s) & 1);
-#pragma unroll
-  for (int h = 0; h < kHfMaxHisto; ++h) fh[h] = STAT && h < H && ((pl.stat_mask >> pl.histo_sample[h]) & 1);
+  // STAT: the flagged samples' coefficients (F_s, c_h of their histosys;
+  // 0 for the others), uniform: nu_flagged = sum Ff_s T_s + sum cf_h d_h
+  double Ff[kHfMaxSamples], cf[kHfMaxHisto], fsm[kHfMaxSamples], fhm[kHfMaxHisto];
 #pragma unroll
   for (int s = 0; s < kHfMaxSamples; ++s) F[s] = hf_uniform(s_F[s]);
 #pragma unroll
   for (int h = 0; h < kHfMaxHisto; ++h) {
     c[h] = hf_uniform(s_c[h]);
     dp[h] = hf_uniform(s_side[h] ? a.dup[h] : a.ddn[h]);
+  }
+#pragma unroll
+  for (int s = 0; s < kHfMaxSamples; ++s) {
+    fsm[s] = (STAT && ((pl.stat_mask >> s) & 1)) ? 1.0 : 0.0;
+    Ff[s] = fsm[s] * F[s];
+  }
+#pragma unroll
+  for (int h = 0; h < kHfMaxHisto; ++h) {
+    fhm[h] = (STAT && h < H && ((pl.stat_mask >> pl.histo_sample[h]) & 1)) ? 1.0 : 0.0;
+    cf[h] = fhm[h] * c[h];
   }
   double acc[kHfNV - 1];
 #pragma unroll
@@ -135,27 +143,20 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
       for (int h = 0; h < kHfMaxHisto; ++h) d[h] = h < H ? dp[h][b] : 0.0;
       double nu = 0.0, nu_f = 0.0, g = 1.0, tau = 0.0;
       bool act = false;
+#pragma unroll
+      for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(F[s], T[s], nu);
+#pragma unroll
+      for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(c[h], d[h], nu);
       if constexpr (STAT) {
         tau = a.stat_tau[b];
         act = tau > 0.0;
         const double gb = a.gamma[b];
         g = act ? gb : 1.0;
 #pragma unroll
-        for (int s = 0; s < kHfMaxSamples; ++s) {
-          if (fs[s]) nu_f = fma(F[s], T[s], nu_f);
-          else nu = fma(F[s], T[s], nu);
-        }
+        for (int s = 0; s < kHfMaxSamples; ++s) nu_f = fma(Ff[s], T[s], nu_f);
 #pragma unroll
-        for (int h = 0; h < kHfMaxHisto; ++h) {
-          if (fh[h]) nu_f = fma(c[h], d[h], nu_f);
-          else nu = fma(c[h], d[h], nu);
-        }
-        nu = fma(g, nu_f, nu);
-      } else {
-#pragma unroll
-        for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(F[s], T[s], nu);
-#pragma unroll
-        for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(c[h], d[h], nu);
+        for (int h = 0; h < kHfMaxHisto; ++h) nu_f = fma(cf[h], d[h], nu_f);
+        nu = fma(g - 1.0, nu_f, nu);  // gamma_b nu_flagged + nu_rest
       }
       const bool pos = n > 0.0;
       bad += !(nu >= 0.0) || (pos && !(nu > 0.0));
@@ -168,12 +169,20 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
       }
       if constexpr (GRAD) {
         const double w = pos ? fma(-n, rcp_full(nu), 1.0) : 1.0;
-        const double wg = w * g;
+        if constexpr (STAT) {
+          // the flagged samples' sums take w gamma_b: w + w (gamma_b - 1) [flagged]
+          const double wd = w * (g - 1.0);
 #pragma unroll
-        for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(fs[s] ? wg : w, T[s], acc[1 + s]);
+          for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(fma(wd, fsm[s], w), T[s], acc[1 + s]);
 #pragma unroll
-        for (int h = 0; h < kHfMaxHisto; ++h)
-          acc[1 + kHfMaxSamples + h] = fma(fh[h] ? wg : w, d[h], acc[1 + kHfMaxSamples + h]);
+          for (int h = 0; h < kHfMaxHisto; ++h)
+            acc[1 + kHfMaxSamples + h] = fma(fma(wd, fhm[h], w), d[h], acc[1 + kHfMaxSamples + h]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(w, T[s], acc[1 + s]);
+#pragma unroll
+          for (int h = 0; h < kHfMaxHisto; ++h) acc[1 + kHfMaxSamples + h] = fma(w, d[h], acc[1 + kHfMaxSamples + h]);
+        }
         if constexpr (STAT) {
           if (a.grad_gamma) a.grad_gamma[b] = act ? fma(w, nu_f, tau * (g - 1.0)) : 0.0;
         }
