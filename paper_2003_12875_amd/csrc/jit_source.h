@@ -105,6 +105,23 @@ template <int N> __device__ inline Dual<N> pow(const Dual<N>& a, const Dual<N>& 
   return r;
 }
 
+// Sum of log g over a thread's events as one logarithm: the running
+// product of the g, renormalised to a mantissa in [1/2, 1) and an exponent
+// after every factor (a positive normal or subnormal g keeps it finite).
+__device__ inline void prod_mul(double& P, int& E, double g) {
+  int e;
+  P = frexp(P * g, &e);
+  E += e;
+}
+// 1/g for the gradient features g'_k / g (never the likelihood value): the
+// hardware reciprocal and one Newton step (relative error ~2^-48) for
+// normal g, the division otherwise.
+__device__ inline double rcp_feature(double g) {
+  if (!(g >= 2.2250738585072014e-308)) return 1.0 / g;
+  const double r = __builtin_amdgcn_rcp(g);
+  return fma(r, fma(-g, r, 1.0), r);
+}
+
 // the density, as given
 template <class T> __device__ inline T jit_g(double x, const T* p) { return (T)(@EXPR@); }
 template <> __device__ inline Dual<NP> jit_g<Dual<NP>>(double x, const Dual<NP>* p) { return dconst<NP>(0.0) + (@EXPR@); }
@@ -117,6 +134,8 @@ __device__ inline void stream(const JitArgs& a) {
   __shared__ DD s_red[4];
   __shared__ DD s_tot[NV];
   double l = 0.0, f[NP > 0 ? NP : 1];
+  double P = 1.0;  // running product of the events' g (mantissa) and its binary exponent
+  int E = 0;
   for (int k = 0; k < NP; ++k) f[k] = 0.0;
   int bad = 0;
   const i64 stride = (i64)gridDim.x * NTH;
@@ -130,8 +149,8 @@ __device__ inline void stream(const JitArgs& a) {
       const Dual<NP> g = jit_g<Dual<NP>>(a.x[i], p);
       const bool ok = g.v > 0.0 && isfinite(g.v);
       bad += ok ? 0 : 1;
-      l += ok ? log(g.v) : 0.0;
-      const double r = ok ? 1.0 / g.v : 0.0;
+      prod_mul(P, E, ok ? g.v : 1.0);
+      const double r = ok ? rcp_feature(g.v) : 0.0;
       for (int k = 0; k < NP; ++k) f[k] = fma(g.d[k], r, f[k]);
     }
   } else {
@@ -141,9 +160,10 @@ __device__ inline void stream(const JitArgs& a) {
       const double g = jit_g<double>(a.x[i], p);
       const bool ok = g > 0.0 && isfinite(g);
       bad += ok ? 0 : 1;
-      l += ok ? log(g) : 0.0;
+      prod_mul(P, E, ok ? g : 1.0);
     }
   }
+  l = log(P) + (double)E * 0.6931471805599453;  // the thread's sum of log g, one logarithm
   DD v; v.lo = 0.0;
   v.hi = l;
   DD t = block_sum(v, s_red);
