@@ -78,6 +78,7 @@ def lib():
         L.orc_nll.argtypes = [pm, ppd, i64, pd, i32, pd, pd, pd]
         L.orc_nll_batched.argtypes = [pm, ppd, P(i64), i32, pd, i32, pd, pd, P(i32)]
         L.orc_gd_fit.argtypes = [pm, ppd, i64, pd, i32, d, i32, pd, pd, pd, pd]
+        L.orc_gd_fit_accept.argtypes = [pm, ppd, i64, pd, i32, d, d, i32, pd, pd, pd, pd]
         L.orc_nll_weighted.argtypes = [pm, ppd, pd, i64, pd, i32, pd, pd, pd, pd]
         L.orc_gd_fit_weighted.argtypes = [pm, ppd, pd, i64, pd, i32, d, i32, pd, pd, pd, pd]
         L.orc_nll_bhhh.argtypes = [pm, ppd, i64, pd, i32, pd, pd, pd]
@@ -85,7 +86,7 @@ def lib():
         L.orc_gd_fit_batched.argtypes = [pm, ppd, P(i64), i32, pd, i32, d, i32, pd, pd, P(i32)]
         L.orc_gl_rule.argtypes = [i32, pd, pd]
         for f in ("orc_check_model", "orc_leaf_norm", "orc_log_density", "orc_nll",
-                  "orc_nll_batched", "orc_gd_fit", "orc_gd_fit_batched", "orc_gl_rule"):
+                  "orc_nll_batched", "orc_gd_fit", "orc_gd_fit_accept", "orc_gd_fit_batched", "orc_gl_rule"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -194,7 +195,10 @@ class Oracle:
         return st, nll, (g if grad else None), status
 
     def gd_fit(self, cols, theta, n_steps: int, eta: float = 1.0, threads: int = 1, trace: bool = False,
-               weights=None):
+               weights=None, accept_ulps=None):
+        """Gradient descent (status, theta, NLL, gradient, final step[, trace]).
+        accept_ulps: acceptance slack in ulps of the accepted NLL (default 4;
+        0 is the literal no-increase rule)."""
         keep, arr = _cols(cols)
         n = len(keep[0])
         th = np.array(theta, dtype=np.float64)
@@ -208,6 +212,10 @@ class Oracle:
             st = lib().orc_gd_fit_weighted(ctypes.byref(self.m), arr, _dptr(w), n, _dptr(th), n_steps, eta,
                                            threads, ctypes.byref(out), _dptr(g), ctypes.byref(eta_out),
                                            _dptr(tr) if trace else None)
+        elif accept_ulps is not None:
+            st = lib().orc_gd_fit_accept(ctypes.byref(self.m), arr, n, _dptr(th), n_steps, eta,
+                                         float(accept_ulps), threads, ctypes.byref(out), _dptr(g),
+                                         ctypes.byref(eta_out), _dptr(tr) if trace else None)
         else:
             st = lib().orc_gd_fit(ctypes.byref(self.m), arr, n, _dptr(th), n_steps, eta, threads,
                                   ctypes.byref(out), _dptr(g), ctypes.byref(eta_out),

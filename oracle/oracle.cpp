@@ -900,9 +900,13 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
 /* Gradient descent with step halving, see oracle.h. */
 /* w (may be NULL): event weights; the step is then scaled by 1/W, W their
  * sum (the weighted analogue of the mean NLL). */
+/* accept_ulps: the largest computed increase of the NLL, in units of
+ * DBL_EPSILON * |NLL_acc|, still taken as no increase (4 by default, 0 for
+ * the literal rule). */
 int gd_fit_one(const orc_model& m, const double* const* cols, int64_t n, double* theta,
                int n_steps, double eta, int threads, double* nll_out, double* grad_out,
-               double* eta_out, double* trace, const double* w = nullptr) {
+               double* eta_out, double* trace, const double* w = nullptr,
+               double accept_ulps = 4.0) {
   const int np = m.n_param;
   std::vector<double> acc(theta, theta + np), prop(theta, theta + np), g_acc(np, 0.0),
       g(np, 0.0);
@@ -921,8 +925,10 @@ int gd_fit_one(const orc_model& m, const double* const* cols, int64_t n, double*
       trace[s * (np + 1)] = f;
       for (int k = 0; k < np; ++k) trace[s * (np + 1) + 1 + k] = prop[k];
     }
-    /* an increase of at most 4 ulps of the NLL is rounding noise, not an increase */
-    bool ok = (st == ORC_OK) && std::isfinite(f) && f <= f_acc + 4.0 * DBL_EPSILON * std::fabs(f_acc);
+    /* a computed increase within the evaluation's own rounding (a few ulps
+     * of the NLL) is not an increase of the function */
+    bool ok = (st == ORC_OK) && std::isfinite(f) &&
+              (f <= f_acc || f - f_acc <= accept_ulps * DBL_EPSILON * std::fabs(f_acc));
     if (st == ORC_E_DOMAIN) return st;
     if (ok) {
       acc = prop;
@@ -1181,6 +1187,17 @@ int orc_gd_fit(const orc_model* m, const double* const* cols, int64_t n, double*
   int st = check_model(*m);
   if (st != ORC_OK) return st;
   return gd_fit_one(*m, cols, n, theta, n_steps, eta, threads, nll, grad, eta_out, trace);
+}
+
+int orc_gd_fit_accept(const orc_model* m, const double* const* cols, int64_t n, double* theta,
+                      int32_t n_steps, double eta, double accept_ulps, int32_t threads,
+                      double* nll, double* grad, double* eta_out, double* trace) {
+  if (!data_args_ok(m, cols) || !theta || !nll || n < 0 || n_steps < 0 || !(accept_ulps >= 0.0))
+    return ORC_E_ARG;
+  int st = check_model(*m);
+  if (st != ORC_OK) return st;
+  return gd_fit_one(*m, cols, n, theta, n_steps, eta, threads, nll, grad, eta_out, trace, nullptr,
+                    accept_ulps);
 }
 
 int orc_gd_fit_batched(const orc_model* m, const double* const* cols, const int64_t* offsets,

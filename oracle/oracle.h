@@ -142,6 +142,14 @@ int orc_gd_fit(const orc_model* m, const double* const* cols, int64_t n,
                double* theta, int32_t n_steps, double eta, int32_t threads,
                double* nll, double* grad, double* eta_out, double* trace);
 
+/* orc_gd_fit with the acceptance slack given: a proposal is accepted when
+ * its NLL is finite and at most accept_ulps * DBL_EPSILON * |NLL_acc| above
+ * the last accepted one (0: the literal "no increase" rule).             */
+int orc_gd_fit_accept(const orc_model* m, const double* const* cols, int64_t n,
+                      double* theta, int32_t n_steps, double eta, double accept_ulps,
+                      int32_t threads, double* nll, double* grad, double* eta_out,
+                      double* trace);
+
 /* orc_gd_fit over weighted events: the weighted NLL of orc_nll_weighted,
  * steps scaled by 1/W instead of 1/N (W <= 0: no scaling).              */
 int orc_gd_fit_weighted(const orc_model* m, const double* const* cols, const double* w,

@@ -109,8 +109,12 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
   double F[kHfMaxSamples], c[kHfMaxHisto];
   const double* dp[kHfMaxHisto];
   // STAT: the flagged samples' coefficients (F_s, c_h of their histosys;
-  // 0 for the others), uniform: nu_flagged = sum Ff_s T_s + sum cf_h d_h
+  // 0 for the others) and the rest's, uniform: nu_flagged = sum Ff_s T_s +
+  // sum cf_h d_h and nu_rest = sum Fr_s T_s + sum cr_h d_h (Fr = F, cr = c
+  // without STAT), so that nu = gamma_b nu_flagged + nu_rest has no
+  // cancellation however small gamma_b is
   double Ff[kHfMaxSamples], cf[kHfMaxHisto], fsm[kHfMaxSamples], fhm[kHfMaxHisto];
+  double Fr[kHfMaxSamples], cr[kHfMaxHisto];
 #pragma unroll
   for (int s = 0; s < kHfMaxSamples; ++s) F[s] = hf_uniform(s_F[s]);
 #pragma unroll
@@ -122,11 +126,13 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
   for (int s = 0; s < kHfMaxSamples; ++s) {
     fsm[s] = (STAT && ((pl.stat_mask >> s) & 1)) ? 1.0 : 0.0;
     Ff[s] = fsm[s] * F[s];
+    Fr[s] = F[s] - Ff[s];
   }
 #pragma unroll
   for (int h = 0; h < kHfMaxHisto; ++h) {
     fhm[h] = (STAT && h < H && ((pl.stat_mask >> pl.histo_sample[h]) & 1)) ? 1.0 : 0.0;
     cf[h] = fhm[h] * c[h];
+    cr[h] = c[h] - cf[h];
   }
   double acc[kHfNV - 1];
 #pragma unroll
@@ -144,9 +150,9 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
       double nu = 0.0, nu_f = 0.0, g = 1.0, tau = 0.0;
       bool act = false;
 #pragma unroll
-      for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(F[s], T[s], nu);
+      for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(Fr[s], T[s], nu);
 #pragma unroll
-      for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(c[h], d[h], nu);
+      for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(cr[h], d[h], nu);
       if constexpr (STAT) {
         tau = a.stat_tau[b];
         act = tau > 0.0;
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
         for (int s = 0; s < kHfMaxSamples; ++s) nu_f = fma(Ff[s], T[s], nu_f);
 #pragma unroll
         for (int h = 0; h < kHfMaxHisto; ++h) nu_f = fma(cf[h], d[h], nu_f);
-        nu = fma(g - 1.0, nu_f, nu);  // gamma_b nu_flagged + nu_rest
+        nu = fma(g, nu_f, nu);  // gamma_b nu_flagged + nu_rest
       }
       const bool pos = n > 0.0;
       bad += !(nu >= 0.0) || (pos && !(nu > 0.0));

@@ -7,9 +7,11 @@
 // double (the NLL alone) and of type Dual<NP> (forward-mode derivatives:
 // every arithmetic operation and elementary function carries d/dp_k along),
 // so that the gradient features d log g / d p_k = g'_k / g come out of the
-// same streaming pass.  Normalisation: the finishing block evaluates g and
-// its derivatives at the 256 Gauss-Legendre nodes of [lo, hi], one per
-// thread.  Reductions are double-double, in fixed orders.
+// same streaming pass.  Normalisation: the finishing block integrates g and
+// its derivatives by composite 256-point Gauss-Legendre on 1, 2, 4, ...
+// equal panels (node t of every panel on thread t) until two successive
+// levels agree, so that a peak narrow against the range is resolved.
+// Reductions are double-double, in fixed orders.
 #pragma once
 
 namespace nllmi {
@@ -107,19 +109,27 @@ template <int N> __device__ inline Dual<N> pow(const Dual<N>& a, const Dual<N>& 
 
 // Sum of log g over a thread's events as one logarithm: the running
 // product of the g, renormalised to a mantissa in [1/2, 1) and an exponent
-// after every factor (a positive normal or subnormal g keeps it finite).
+// after every factor.  g is split into its own mantissa and exponent first,
+// so that a subnormal g is multiplied in at full precision.
 __device__ inline void prod_mul(double& P, int& E, double g) {
-  int e;
-  P = frexp(P * g, &e);
-  E += e;
+  int eg, e;
+  const double m = frexp(g, &eg);
+  P = frexp(P * m, &e);
+  E += e + eg;
 }
-// 1/g for the gradient features g'_k / g (never the likelihood value): the
-// hardware reciprocal and one Newton step (relative error ~2^-48) for
-// normal g, the division otherwise.
-__device__ inline double rcp_feature(double g) {
-  if (!(g >= 2.2250738585072014e-308)) return 1.0 / g;
-  const double r = __builtin_amdgcn_rcp(g);
-  return fma(r, fma(-g, r, 1.0), r);
+// The gradient features g'_k / g (never the likelihood value): for normal
+// g, g'_k times the hardware reciprocal refined by one Newton step
+// (relative error ~2^-48); for subnormal g, whose reciprocal overflows, the
+// division itself (a divergent branch only where such an event occurs).
+template <int N>
+__device__ inline void add_features(const Dual<N>& g, double* f) {
+  if (g.v >= 2.2250738585072014e-308) {
+    const double r0 = __builtin_amdgcn_rcp(g.v);
+    const double r = fma(r0, fma(-g.v, r0, 1.0), r0);
+    for (int k = 0; k < N; ++k) f[k] = fma(g.d[k], r, f[k]);
+  } else {
+    for (int k = 0; k < N; ++k) f[k] += g.d[k] / g.v;
+  }
 }
 
 // the density, as given
@@ -150,8 +160,7 @@ __device__ inline void stream(const JitArgs& a) {
       const bool ok = g.v > 0.0 && isfinite(g.v);
       bad += ok ? 0 : 1;
       prod_mul(P, E, ok ? g.v : 1.0);
-      const double r = ok ? rcp_feature(g.v) : 0.0;
-      for (int k = 0; k < NP; ++k) f[k] = fma(g.d[k], r, f[k]);
+      if (ok) add_features(g, f);
     }
   } else {
     double p[NP > 0 ? NP : 1];
@@ -182,9 +191,48 @@ __device__ inline void stream(const JitArgs& a) {
   if (threadIdx.x < NV) ((DD*)a.partials)[(i64)blockIdx.x * NV + threadIdx.x] = s_tot[threadIdx.x];
 }
 
-// Finishing block: Z and dZ/dp_k by 256-point Gauss-Legendre (one node per
-// thread), the block partials in block order, then
+// Z and dZ/dp_k (z[0], z[1 + k]) by composite 256-point Gauss-Legendre on
+// n_pan equal panels of [lo, hi], thread t taking node t of every panel,
+// with the integrals of |g| and |g'_k| (sc) as their error scales.  Every
+// thread returns the same values.
+__device__ inline void gl_panels(const JitArgs& a, int n_pan, const Dual<NP>* p, DD* s_red, double* z,
+                                 double* sc) {
+  const int t = threadIdx.x;
+  const double H = (a.hi - a.lo) / n_pan, h = 0.5 * H;
+  const double w = h * a.glw[t], xt = a.glx[t];
+  DD acc[1 + NP];
+  double ab[1 + NP];
+  for (int k = 0; k <= NP; ++k) {
+    acc[k].hi = acc[k].lo = 0.0;
+    ab[k] = 0.0;
+  }
+  for (int j = 0; j < n_pan; ++j) {
+    const double x = j + 1 == n_pan ? fma(h, xt, a.hi - h) : fma(h, xt, fma((double)j, H, a.lo + h));
+    const Dual<NP> g = jit_g<Dual<NP>>(x, p);
+    acc[0] = dd_add1(acc[0], w * g.v);
+    ab[0] += w * fabs(g.v);
+    for (int k = 0; k < NP; ++k) {
+      acc[1 + k] = dd_add1(acc[1 + k], w * g.d[k]);
+      ab[1 + k] += w * fabs(g.d[k]);
+    }
+  }
+  for (int k = 0; k <= NP; ++k) {
+    const DD r = block_sum(acc[k], s_red);
+    z[k] = r.hi + r.lo;
+    DD q; q.hi = ab[k]; q.lo = 0.0;
+    const DD rs = block_sum(q, s_red);
+    sc[k] = rs.hi + rs.lo;
+  }
+}
+
+// Finishing block: Z and dZ/dp_k by composite Gauss-Legendre, doubling the
+// panels (1, 2, 4, ... kMaxPanels) until the last two levels agree to
+// 1e-13 of the integral of |g| and 1e-11 of that of |g'_k| (a level that
+// resolves the density is exact to rounding, so agreement means the finer
+// one is); no agreement at kMaxPanels panels is reported as an invalid
+// density.  Then the block partials in block order, and
 //   NLL = -sum log g + N log Z,  dNLL/dp_k = -sum g'_k/g + N dZ_k / Z.
+#define MAX_PANELS 256
 template <bool GRAD>
 __device__ inline void finish(const JitArgs& a) {
   constexpr int NV = 1 + (GRAD ? NP : 0) + 1;
@@ -201,18 +249,18 @@ __device__ inline void finish(const JitArgs& a) {
     p[k] = dconst<NP>(a.theta[k]);
     p[k].d[k] = 1.0;
   }
-  const double h = 0.5 * (a.hi - a.lo), c = 0.5 * (a.hi + a.lo);
-  const double w = h * a.glw[t];
-  const Dual<NP> g = jit_g<Dual<NP>>(fma(h, a.glx[t], c), p);
-  DD v; v.lo = 0.0;
-  v.hi = w * g.v;
-  DD z = block_sum(v, s_red);
-  if (t == 0) s_z[0] = z.hi + z.lo;
-  for (int k = 0; k < NP; ++k) {
-    v.hi = w * g.d[k];
-    z = block_sum(v, s_red);
-    if (t == 0) s_z[1 + k] = z.hi + z.lo;
+  double zp[1 + NP], zc[1 + NP], sc[1 + NP];
+  gl_panels(a, 1, p, s_red, zp, sc);
+  bool conv = false;
+  for (int n_pan = 2; n_pan <= MAX_PANELS && !conv; n_pan *= 2) {
+    gl_panels(a, n_pan, p, s_red, zc, sc);
+    conv = isfinite(zc[0]) && fabs(zc[0] - zp[0]) <= 1e-13 * sc[0];
+    for (int k = 0; k < NP; ++k) conv = conv && fabs(zc[1 + k] - zp[1 + k]) <= 1e-11 * sc[1 + k];
+    for (int k = 0; k <= NP; ++k) zp[k] = zc[k];
   }
+  if (t == 0)
+    for (int k = 0; k <= NP; ++k) s_z[k] = zp[k];
+  DD z;
   for (int j = 0; j < NV; ++j) {
     DD acc; acc.hi = 0.0; acc.lo = 0.0;
     for (int b = t; b < a.n_blocks; b += NTH) acc = dd_add(acc, ((const DD*)a.partials)[(i64)b * NV + j]);
@@ -223,7 +271,7 @@ __device__ inline void finish(const JitArgs& a) {
   const double Z = s_z[0], N = (double)a.n;
   int status = 0;
   if (s_bad) status = -3;
-  else if (s_s[NV - 1] > 0.0 || !(Z > 0.0) || !isfinite(Z)) status = -5;
+  else if (s_s[NV - 1] > 0.0 || !(Z > 0.0) || !isfinite(Z) || !conv) status = -5;
   double nll = -s_s[0] + N * log(Z);
   if (status == 0 && !isfinite(nll)) status = -5;
   if (status != 0) nll = __builtin_inf();

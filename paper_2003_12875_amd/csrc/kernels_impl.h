@@ -14,10 +14,12 @@
 //   k_consts   per-set constants for many datasets (one block per set).
 //   k_schedule tile counts per set and their prefix (one block).
 //   k_sets     many datasets: work items (set, tile) over a persistent
-//              grid; the last item of a set to finish reduces that set's
-//              partials in item order, writes its NLL / gradient / status
-//              and, when fitting, performs the gradient-descent step and
-//              prepares the constants of the next proposal.
+//              grid, one double-double record per item.
+//   k_sets_finish  one block per set, launched after k_sets: that set's
+//              item records in item order, its NLL / gradient / status
+//              and, when fitting, the gradient-descent step and the
+//              constants of the next proposal (a batched fit step is these
+//              two launches).
 //   k_fit_init / k_fit_final   state set-up and read-out around the steps.
 //
 // No matrix cores: the pass is a streaming map-reduce.

@@ -54,8 +54,11 @@ def test_extended_term_single_and_batched(torch, nllmi, precision, tol):
         v, g = m.eval_grad(torch.from_numpy(th))
         v, g = float(v.item()), g.cpu().numpy()
         assert abs(v / ref - 1) <= tol, (nu, v, ref)
-        scale = max(np.max(np.abs(gref)), np.max(stats[1:]))
-        assert np.max(np.abs(g - gref)) <= max(1e-8, 1e-5 / np.sqrt(len(cols[0]))) * scale, (nu, g, gref)
+        if precision == "fp64":
+            assert np.max(np.abs(g - gref)) <= 1e-8 * np.max(np.abs(gref)), (nu, g, gref)
+        else:  # the FP32 pass's random-walk bound (its own tests derive it)
+            scale = max(np.max(np.abs(gref)), np.max(stats[1:]))
+            assert np.max(np.abs(g - gref)) <= max(1e-8, 1e-5 / np.sqrt(len(cols[0]))) * scale, (nu, g, gref)
         assert abs(g[4] - (1.0 - len(cols[0]) / nu)) <= 1e-12 * max(1.0, len(cols[0]) / nu)
     # batched: the yield term uses each set's own event count
     offsets = np.array([0, 1000, 1000, 51_000, 200_000], dtype=np.int64)

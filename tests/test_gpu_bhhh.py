@@ -2,8 +2,9 @@
 outer-product matrix B = sum_i s_i s_i^T of the events' scores) and of the
 damped BHHH minimiser (nll_fit_bhhh) against the oracle.
 
-Tolerances: NLL 1e-12 relative and gradient 1e-8 of max(|g|, G) as for the
-FP64 pass; B entry-wise 1e-10 of max|B| (its entries are sums of
+Tolerances: NLL 1e-12 relative and gradient 1e-8 of ||g_oracle||_inf as for
+the FP64 pass (gradients after a fit, where g -> 0, on the scale G =
+max_k sum_i |d l_i / d theta_k|); B entry-wise 1e-10 of max|B| (its entries are sums of
 non-negative-definite terms of the size of that maximum, and the kernel
 forms them from reduced second moments instead of per-event products);
 fitted points 1e-9 relative, as for gradient descent.
@@ -72,7 +73,7 @@ def check_bhhh(torch, nllmi, spec, cols, points, threads, unroll=None):
         v, g, B = m.eval_bhhh(torch.from_numpy(np.ascontiguousarray(th)))
         v, g, B = float(v.item()), g.cpu().numpy(), B.cpu().numpy()
         assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
-        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), np.max(stats[1:])), (g, gref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (g, gref)
         assert np.array_equal(B, B.T)
         assert np.max(np.abs(B - Bref)) <= B_TOL * np.max(np.abs(Bref)), (th, B, Bref)
     assert m.sync() == 0

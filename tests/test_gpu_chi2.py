@@ -5,8 +5,9 @@ to the benchmarked 1e7 events, every unroll, invalid events and parameters,
 gradient descent, BHHH, many datasets and the FP32-compensated pass.
 
 Tolerances as for the other leaves: NLL 1e-12 relative, gradient 1e-8 of
-max(|g|, G) with G the largest per-parameter sum of |d l_i/d theta|; fitted
-points 1e-9 relative.
+||g_oracle||_inf at seeded points (after a fit, where g -> 0, of G, the
+largest per-parameter sum of |d l_i/d theta|); fitted points 1e-9
+relative.
 """
 import math
 
@@ -54,7 +55,7 @@ def check(torch, nllmi, spec, cols, points, threads, unroll=None):
         v, g = m.eval_grad(torch.from_numpy(np.ascontiguousarray(th)))
         v, g = float(v.item()), g.cpu().numpy()
         assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
-        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), np.max(stats[1:])), (th, g, gref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
         v1 = float(m.eval(torch.from_numpy(np.ascontiguousarray(th))).item())
         assert abs(v1 - ref) <= NLL_TOL * abs(ref), (th, v1, ref)
     assert m.sync() == 0
@@ -159,8 +160,7 @@ def test_chi2_many_datasets(torch, nllmi, threads):
     for s in range(40):
         assert abs(nll[s] - ref[s]) <= NLL_TOL * max(1.0, abs(ref[s])), (s, nll[s], ref[s])
         a, b = offsets[s], offsets[s + 1]
-        G = np.max(o.nll([cols[0][a:b]], truths[s], stats=True)[3][1:]) if b > a else 0.0
-        assert np.max(np.abs(g[s] - gref[s])) <= GRAD_TOL * max(1.0, np.max(np.abs(gref[s])), G), s
+        assert np.max(np.abs(g[s] - gref[s])) <= GRAD_TOL * np.max(np.abs(gref[s])), (s, g[s], gref[s])
 
 
 def test_chi2_fp32c(torch, nllmi, threads):

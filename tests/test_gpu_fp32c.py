@@ -2,18 +2,26 @@
 per-event density arithmetic in FP32 with two-sum-compensated per-thread
 sums; normalisation, cross-thread reductions and the minimiser in FP64.
 
-Tolerances: relative NLL error <= 1e-9 against the scalar FP64 oracle;
-gradient error ||g - g_orc||_inf <= 1e-8 * max(||g_orc||_inf, G) with G the
-largest per-parameter sum of |d l_i / d theta| (as for the FP64 path).
-These hold at the precision-study size (1e8 events).  Each event's value
-carries FP32 rounding errors of a few units of 2^-24 relative; they are
-unbiased (the pass is built so) and their sum grows as sqrt(N), so for
-small N the NLL bound is 1e-6 / sqrt(N) instead (about five standard
-deviations of that random walk): e.g. 3e-9 at N = 1e5, 1.7e-7 at N = 30.
-Gradient components see larger per-event errors: a feature such as t^2 of
-the Crystal Ball with |t| ~ 5 carries 2^-24 |t|^2 absolute, and only the
-events of one component (a tenth of them in the 2-D model) carry its
-parameters, so their small-N bound is 1e-5 / sqrt(N).
+Tolerances: relative NLL error <= 1e-9 against the scalar FP64 oracle at
+the precision-study size (1e8 events).  The gradient of this mode is
+reported, not bound by 1e-8 of ||g_orc||_inf (that bound is the FP64
+path's): each row carries ||g - g_orc||_inf / ||g_orc||_inf.  It is
+checked against the random walk of its per-event FP32 roundings, on the
+scale G = max_k sum_i |d l_i / d theta_k|.
+
+The random-walk bounds.  Each event's value carries FP32 rounding errors
+of a few units of u = 2^-24 relative; they are unbiased (the pass is built
+so), so their sum grows as sqrt(N): for the NLL, 5 standard deviations of
+c u sqrt(N) |l| with c ~ 4 over |NLL| ~ N |l| is ~ 1e-6 / sqrt(N) (3e-9 at
+N = 1e5, 1.7e-7 at N = 30); 1e-9 is the larger from N = 1e6 on.  A
+gradient feature phi of parameter k carries c u |phi_i| per event, and the
+sum of those errors has standard deviation c u sqrt(sum_i phi_i^2) =
+c u r G_k / sqrt(N) with r = rms / mean of |phi| over the events.  r is
+~1.7 for t^2 of a Gaussian and grows as 1/sqrt(q) when only a fraction q
+of the events carries the feature (the Crystal Ball's tenth of the 2-D
+model's events: r ~ 5); 5 standard deviations at c = 4 and r = 5 give
+6e-6 G / sqrt(N), so the bound is 1e-5 G / sqrt(N) (and 1e-8 G from
+N = 1e6 on).
 """
 import numpy as np
 import pytest
@@ -75,13 +83,20 @@ def compare(torch, nllmi, spec, cols, points, threads, n_check=None, against_fp6
         v, g = m.eval_grad(torch.from_numpy(th))
         v, g = float(v.item()), g.cpu().numpy()
         scale = max(np.max(np.abs(gref)), np.max(stats[1:]))
+        gnorm = np.max(np.abs(gref))
         nerr = abs(v / ref - 1.0)
         gerr = np.max(np.abs(g - gref)) / scale
-        row = {"nll_rel_err": nerr, "grad_rel_err": gerr}
+        row = {"nll_rel_err": nerr, "grad_rel_err": gerr, "grad_err_vs_norm": np.max(np.abs(g - gref)) / gnorm}
         if m64 is not None:
             v64, g64 = m64.eval_grad(torch.from_numpy(th))
-            row["nll_rel_err_vs_fp64_gpu"] = abs(v / float(v64.item()) - 1.0)
-            row["grad_rel_err_vs_fp64_gpu"] = np.max(np.abs(g - g64.cpu().numpy())) / scale
+            v64, g64 = float(v64.item()), g64.cpu().numpy()
+            row["nll_rel_err_vs_fp64_gpu"] = abs(v / v64 - 1.0)
+            row["grad_rel_err_vs_fp64_gpu"] = np.max(np.abs(g - g64)) / scale
+            # the FP64 GPU leg against the oracle, to the FP64 bounds
+            row["fp64_nll_rel_err"] = abs(v64 / ref - 1.0)
+            row["fp64_grad_err_vs_norm"] = np.max(np.abs(g64 - gref)) / gnorm
+            assert row["fp64_nll_rel_err"] <= 1e-12, (th, v64, ref)
+            assert row["fp64_grad_err_vs_norm"] <= 1e-8, (th, g64, gref)
         rows.append(row)
         if report:
             print(f"point {len(rows) - 1:2d}: " + "  ".join(f"{k} {v:.3e}" for k, v in row.items()), flush=True)
@@ -181,7 +196,8 @@ def test_fit_reaches_fp64_minimum(torch, nllmi):
 def test_precision_study_full(torch, nllmi, threads):
     """The precision-study workload: 1e8 events of the signal+background
     mixture, NLL and gradient at 32 seeded parameter points, fp32c against
-    the oracle and against the fp64 GPU path (errors printed per point)."""
+    the oracle and against the fp64 GPU path, and the fp64 GPU path against
+    the oracle to the FP64 bounds (errors printed per point)."""
     w = datagen.workload(5, threads=threads)
     print(f"[fp32c precision study n={w['n']}]", flush=True)
     assert nll_tol(w["n"]) == NLL_TOL and grad_tol(w["n"]) == GRAD_TOL

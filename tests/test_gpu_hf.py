@@ -1,7 +1,7 @@
 """GPU parity of the binned template likelihood (HistFactory type) against
-the numpy oracle: NLL 1e-12 relative; gradient 1e-8 of max(|g|, G) with G
-the largest per-parameter sum of |w_b d nu_b / d theta| (the gradient's own
-rounding scale); ragged bin counts, the benchmarked size, the limits of
+the numpy oracle: NLL 1e-12 relative; gradient 1e-8 of ||g_oracle||_inf at
+seeded points (at the one-bin minimum, where g -> 0, of G, the largest
+per-parameter sum of |w_b d nu_b / d theta|); ragged bin counts, the benchmarked size, the limits of
 the model description, parameters shared across samples, empty bins,
 alpha exactly 0, fixed parameters, and the status conventions."""
 import copy
@@ -48,11 +48,10 @@ def check(torch, m, spec, w, points):
         nu, dnu = hf.expected(spec, w["nominal"], w["up"], w["down"], th)
         n = w["counts"]
         wgt = np.where(n > 0, 1.0 - n / np.where(nu > 0, nu, 1.0), 1.0)
-        G = max(float(np.sum(np.abs(wgt * d))) for d in dnu) if len(dnu) else 0.0
         v, g = m.eval_grad(torch.from_numpy(np.ascontiguousarray(th)))
         v, g = float(v.item()), g.cpu().numpy()
         assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
-        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), G), (th, g, gref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
         v1 = float(m.eval(torch.from_numpy(np.ascontiguousarray(th))).item())
         assert abs(v1 - ref) <= NLL_TOL * abs(ref)
     assert m.sync() == 0
@@ -182,11 +181,10 @@ def check_stat(torch, m, spec, w, mask, sigma, gamma, points):
         nu, dnu = hf.expected(spec, w["nominal"], w["up"], w["down"], th, (mask, sigma, gamma))
         n = w["counts"]
         wgt = np.where(n > 0, 1.0 - n / np.where(nu > 0, nu, 1.0), 1.0)
-        G = max(float(np.sum(np.abs(wgt * d))) for d in dnu) if len(dnu) else 0.0
         v, g, gg = m.eval_stat(torch.from_numpy(np.ascontiguousarray(th)), torch.from_numpy(gamma))
         v, g, gg = float(v.item()), g.cpu().numpy(), gg.cpu().numpy()
         assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
-        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), G), (th, g, gref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
         # per bin: one term and the constraint, so relative to the bin's own scale
         scale = np.abs(wgt) * np.abs(nu) + np.abs(ggref) + 1.0
         assert np.all(np.abs(gg - ggref) <= 1e-12 * scale), np.max(np.abs(gg - ggref) / scale)
@@ -223,6 +221,23 @@ def test_hf_staterror_full(torch, nllmi):
     sigma, gamma = _stat_inputs(w["spec"]["n_bins"], seed=33)
     m.set_staterror([0, 1], sigma)
     check_stat(torch, m, w["spec"], w, 0b11, sigma, gamma, w["points"])
+
+
+def test_hf_staterror_small_gamma(torch, nllmi):
+    """gamma_b in [1e-6, 1e-2] on the flagged samples that dominate most
+    bins (the two backgrounds; the unflagged peak is small away from its
+    centre): nu_b = gamma_b nu_flagged + nu_rest is formed without
+    cancelling terms, so it keeps full relative precision.  Against the
+    oracle."""
+    n_bins = 20_000
+    w = datagen.hf_workload(n_bins=n_bins, n_samples=3, n_histosys=4, n_normsys=2, n_points=2)
+    print("[hf staterror small gamma]", flush=True)
+    m = make(nllmi, w)
+    rng = np.random.default_rng(77)
+    sigma = rng.uniform(0.01, 0.1, n_bins)
+    gamma = 10.0 ** rng.uniform(-6.0, -2.0, n_bins)
+    m.set_staterror([1, 2], sigma)
+    check_stat(torch, m, w["spec"], w, 0b110, sigma, gamma, w["points"])
 
 
 def test_hf_staterror_errors(torch, nllmi):

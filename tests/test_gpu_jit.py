@@ -2,10 +2,8 @@
 oracle (numpy, adaptive quadrature, complex-step derivatives) and, for a
 Gaussian written as an expression, against the built-in Gaussian kernels.
 
-Tolerances: NLL 1e-12 relative; gradient 1e-8 of max(|g|, G) with G the
-largest per-parameter sum of |d l_i / d theta| (l_i = log g(x_i) - log Z).
-The device normalises by 256-point Gauss-Legendre on one panel, which is
-exact to rounding for the smooth densities used here."""
+Tolerances: NLL 1e-12 relative; gradient 1e-8 of ||g_oracle||_inf at the
+seeded points."""
 import math
 
 import numpy as np
@@ -52,11 +50,10 @@ def check(torch, nllmi, expr, lo, hi, ps, x, points):
         assert st == jit.OK
         v, d = jit.g_and_grad(expr, x, th)
         Z, dZ = jit.norm(expr, lo, hi, th)
-        G = max(float(np.sum(np.abs(dk / v - dz / Z))) for dk, dz in zip(d, dZ))
         val, g = m.eval_grad(torch.from_numpy(th))
         val, g = float(val.item()), g.cpu().numpy()
         assert abs(val - ref) <= NLL_TOL * abs(ref), (th, val, ref)
-        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), G), (th, g, gref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
         v1 = float(m.eval(torch.from_numpy(th)).item())
         assert abs(v1 - ref) <= NLL_TOL * abs(ref)
     assert m.sync() == 0
@@ -113,3 +110,59 @@ def test_compile_errors_limits_and_status(torch, nllmi):
     with pytest.raises(nllmi.NLLError) as e:
         m.set_data(torch.tensor([0.5, 2.5], dtype=torch.float64).cuda())
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("sigma", [0.05, 0.02, 0.005])
+def test_narrow_peak_expression(torch, nllmi, threads, sigma):
+    """A Gaussian expression whose width is 1/200 to 1/2000 of the range:
+    one 256-node Gauss-Legendre panel misses most of it (Z off by 24 % at
+    sigma = 0.02), so the finishing block refines the panels until two
+    levels agree.  Against the scalar oracle's built-in Gaussian (closed-
+    form normalisation through erf)."""
+    import oracle
+    spec = datagen.gauss_spec(5.0, sigma, 0.0, 10.0)
+    x = datagen.generate(spec, 40_000, seed=321)[0]
+    o = oracle.Oracle(spec)
+    m = nllmi.JITModel(GAUSS, 0.0, 10.0, params([5.0, sigma], [0.0, 1e-4], [10.0, 5.0]))
+    m.set_data(torch.from_numpy(x).cuda())
+    print(f"[jit narrow peak sigma={sigma}]", flush=True)
+    for th in ([5.0, sigma], [5.0 + 0.3 * sigma, 1.1 * sigma], [5.0 - 0.2 * sigma, 0.93 * sigma]):
+        th = np.asarray(th)
+        st, ref, gref = o.nll([x], th, threads=threads)
+        assert st == 0
+        v, g = m.eval_grad(torch.from_numpy(th))
+        v, g = float(v.item()), g.cpu().numpy()
+        assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
+    assert m.sync() == 0
+
+
+def test_subnormal_density_values(torch, nllmi):
+    """Events where g is subnormal (down to 1e-320): the running product
+    takes each g's own mantissa and exponent, so log g keeps full
+    precision, and the features g'_k / g are divided directly where 1/g
+    would overflow.  g = (p0 x) e^(-p1 x) and its derivatives x e^(-p1 x)
+    and -x g are formed by the same correctly rounded operations on both
+    sides (e^(-p1 x) is exactly 1 at the subnormal events), so the
+    reference takes them written out in numpy (the complex step of the
+    expression oracle underflows there); Z and dZ/dp by the expression
+    oracle's quadrature."""
+    expr = "p[0] * x * exp(-p[1] * x)"
+    x = np.array([1e-320, 3.3e-318, 2.5e-315, 7e-310, 1e-305, 0.25, 0.5, 0.9, 3.0])
+    ps = params([1.0, 0.5], [0.5, 0.0], [2.0, 2.0])
+    m = nllmi.JITModel(expr, 0.0, 4.0, ps)
+    m.set_data(torch.from_numpy(x).cuda())
+    for th in ([1.0, 0.5], [0.999, 0.7], [1.3, 0.2]):
+        p0, p1 = th
+        e = np.exp(-p1 * x)
+        gv = (p0 * x) * e
+        d0, d1 = x * e, (p0 * x) * (-x * e)
+        Z, dZ = jit.norm(expr, 0.0, 4.0, np.asarray(th))
+        n = len(x)
+        ref = -math.fsum(np.log(gv)) + n * math.log(Z)
+        gref = np.array([-math.fsum(d0 / gv) + n * dZ[0] / Z, -math.fsum(d1 / gv) + n * dZ[1] / Z])
+        v, g = m.eval_grad(torch.from_numpy(np.asarray(th)))
+        assert abs(v.item() - ref) <= NLL_TOL * abs(ref), (th, v.item(), ref)
+        assert np.max(np.abs(g.cpu().numpy() - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
+        assert abs(m.eval(torch.from_numpy(np.asarray(th))).item() - ref) <= NLL_TOL * abs(ref)
+    assert m.sync() == 0

@@ -2,9 +2,10 @@
 oracle on the same seeded inputs.
 
 Tolerances: relative NLL error <= 1e-12 in FP64; gradient error
-||g_gpu - g_orc||_inf <= 1e-8 * max(||g_orc||_inf, G) where G is the
-largest per-parameter sum of |d l_i / d theta| (the gradient's own
-rounding scale, relevant where the gradient nearly vanishes).
+||g_gpu - g_orc||_inf <= 1e-8 * ||g_orc||_inf at every seeded parameter
+point (none of them is near a stationary point).  Only the gradients left
+after a fit, where g -> 0, are compared on the scale G = max_k sum_i
+|d l_i / d theta_k| (the gradient's own rounding scale); those tests say so.
 """
 import math
 
@@ -39,9 +40,10 @@ def to_dev(torch, cols):
     return [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in cols]
 
 
-def grad_close(g, ref, scale):
+def grad_close(g, ref):
+    """||g - ref||_inf <= 1e-8 ||ref||_inf (seeded, non-stationary points)."""
     err = np.max(np.abs(np.asarray(g) - ref))
-    return err <= GRAD_TOL * max(np.max(np.abs(ref)), np.max(scale)), err
+    return err <= GRAD_TOL * np.max(np.abs(ref)), err
 
 
 def check_points(torch, nllmi, spec, cols, points, threads, grad=True, n_check=None, precision="fp64"):
@@ -54,7 +56,7 @@ def check_points(torch, nllmi, spec, cols, points, threads, grad=True, n_check=N
         if grad:
             v, g = m.eval_grad(torch.from_numpy(th))
             v, g = float(v.item()), g.cpu().numpy()
-            ok, err = grad_close(g, gref, stats[1:])
+            ok, err = grad_close(g, gref)
             assert ok, (th, g, gref, err)
         else:
             v = float(m.eval(torch.from_numpy(th)).item())
@@ -104,7 +106,93 @@ def test_cb_argus_cheb_c3_small(torch, nllmi, threads, n, norm):
 def test_cb_argus_cheb_c3_full(torch, nllmi, threads):
     w = datagen.workload(3)
     print("[c3 n=5e7]", flush=True)
-    check_points(torch, nllmi, w["spec"], w["cols"], w["points"], threads, n_check=2)
+    check_points(torch, nllmi, w["spec"], w["cols"], w["points"], threads, n_check=8)
+
+
+# ---------------------------------------------------------------------------
+# every launch schedule the autotuner can pick, against the oracle
+# ---------------------------------------------------------------------------
+
+SINGLE_UNROLLS = (2, 4, 8)
+SINGLE_BPC = (1, 2, 4, 8, 16)
+
+
+def test_every_single_schedule_c2(torch, nllmi, threads):
+    """The mixture's NLL+gradient kernel at each events-per-thread value and
+    blocks-per-CU candidate of the autotuner, and its one-launch fit step at
+    each events-per-thread value (the benchmark times whichever the tuner
+    keeps), against the oracle."""
+    w = datagen.workload(2, n=2_000_003)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    o = oracle.Oracle(w["spec"])
+    th = w["points"][2]
+    st, ref, gref = o.nll(w["cols"], th, threads=threads)
+    for unroll in SINGLE_UNROLLS:
+        for bpc in SINGLE_BPC:
+            print(f"[c2 schedule u={unroll} bpc={bpc}]", flush=True)
+            m.set_schedule(unroll=unroll, blocks_per_cu=bpc)
+            v, g = m.eval_grad(torch.from_numpy(th))
+            ok, err = grad_close(g.cpu().numpy(), gref)
+            assert ok and abs(v.item() - ref) <= NLL_TOL * abs(ref), (unroll, bpc, v.item(), ref, err)
+    st, th_o, nll_o, g_o, eta_o = o.gd_fit(w["cols"], th, 7, 1.0, threads=threads)
+    for unroll in SINGLE_UNROLLS:
+        print(f"[c2 fit u={unroll}]", flush=True)
+        m.set_schedule(unroll=unroll, blocks_per_cu=2)
+        th_g, nll_g, g_g, st_g = m.fit(torch.from_numpy(th), 7, 1.0)
+        np.testing.assert_allclose(th_g.cpu().numpy(), th_o, rtol=1e-12, err_msg=f"u={unroll}")
+        assert abs(nll_g.item() - nll_o) <= NLL_TOL * abs(nll_o)
+        assert np.max(np.abs(g_g.cpu().numpy() - g_o)) <= GRAD_TOL * np.max(np.abs(g_o))
+    assert m.sync() == 0
+
+
+def test_every_single_schedule_c3(torch, nllmi, threads):
+    """The 2-D model (12 accumulators: events per thread 2 or 4) at every
+    single-dataset candidate of the autotuner, against the oracle."""
+    w = datagen.workload(3, n=300_007)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    th = w["points"][3]
+    st, ref, gref = oracle.Oracle(w["spec"]).nll(w["cols"], th, threads=threads)
+    for unroll in (2, 4):
+        for bpc in SINGLE_BPC:
+            print(f"[c3 schedule u={unroll} bpc={bpc}]", flush=True)
+            m.set_schedule(unroll=unroll, blocks_per_cu=bpc)
+            v, g = m.eval_grad(torch.from_numpy(th))
+            ok, err = grad_close(g.cpu().numpy(), gref)
+            assert ok and abs(v.item() - ref) <= NLL_TOL * abs(ref), (unroll, bpc, v.item(), ref, err)
+    assert m.sync() == 0
+
+
+def test_every_batched_schedule(torch, nllmi, threads):
+    """Many datasets at every batched candidate of the autotuner (events per
+    thread x events per work item x blocks per CU), per-set NLL and gradient
+    against the oracle, and a five-step batched fit per events-per-thread
+    value against the oracle's fits."""
+    w = datagen.toys_workload(n_sets=40, size_lo=1000, size_hi=150_000)
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data(to_dev(torch, w["cols"]))
+    o = oracle.Oracle(w["spec"])
+    th = w["truths"]
+    st, ref, gref, sref = o.nll_batched(w["cols"], w["offsets"], th, threads=threads)
+    offs, thd = torch.from_numpy(w["offsets"]).cuda(), torch.from_numpy(th).cuda()
+    for unroll in SINGLE_UNROLLS:
+        for tile in (8192, 16384, 32768, 65536):
+            for bpc in (2, 4, 8, 16):
+                m.set_schedule(sets_unroll=unroll, tile_events=tile, sets_blocks_per_cu=bpc)
+                nll, g, status = m.eval_batched(offs, thd)
+                nll, g = nll.cpu().numpy(), g.cpu().numpy()
+                assert np.all(status.cpu().numpy() == 0)
+                err = np.abs(nll - ref) / np.abs(ref)
+                gerr = np.max(np.abs(g - gref), axis=1) / np.max(np.abs(gref), axis=1)
+                assert err.max() <= NLL_TOL and gerr.max() <= GRAD_TOL, (unroll, tile, bpc, err.max(), gerr.max())
+    start = np.tile(w["theta_start"], (40, 1))
+    st, th_o, nll_o, g_o, status_o = o.gd_fit_batched(w["cols"], w["offsets"], start, 5, 1.0, threads=threads)
+    for unroll in SINGLE_UNROLLS:
+        m.set_schedule(sets_unroll=unroll, tile_events=16384, sets_blocks_per_cu=2)
+        thf, nllf, gf, stf = m.fit_batched(offs, torch.from_numpy(start).cuda(), 5, 1.0)
+        np.testing.assert_allclose(thf.cpu().numpy(), th_o, rtol=1e-12, err_msg=f"u={unroll}")
+        np.testing.assert_allclose(nllf.cpu().numpy(), nll_o, rtol=NLL_TOL)
 
 
 # ---------------------------------------------------------------------------
@@ -126,7 +214,7 @@ def test_batched_toys_small(torch, nllmi, threads):
     assert np.all(status == 0)
     for s in range(96):
         assert abs(nll[s] - ref[s]) <= NLL_TOL * max(1.0, abs(ref[s])), (s, nll[s], ref[s])
-        assert np.max(np.abs(g[s] - gref[s])) <= GRAD_TOL * max(1.0, np.max(np.abs(gref[s]))) * 100, s
+        assert np.max(np.abs(g[s] - gref[s])) <= GRAD_TOL * np.max(np.abs(gref[s])), (s, g[s], gref[s])
     # additivity: the sum over sets at one common point equals the NLL of the concatenation
     common = np.tile(w["theta_start"], (96, 1))
     nll2, _, _ = m.eval_batched(torch.from_numpy(w["offsets"]), torch.from_numpy(common))
@@ -267,7 +355,7 @@ def test_heavy_shape_every_unroll(torch, nllmi, threads):
         m.set_schedule(unroll=unroll, sets_unroll=unroll, blocks_per_cu=3, sets_blocks_per_cu=3,
                        tile_events=2048)
         v, g = m.eval_grad(torch.from_numpy(th))
-        ok, err = grad_close(g.cpu().numpy(), gref, stats[1:])
+        ok, err = grad_close(g.cpu().numpy(), gref)
         assert ok and abs(v.item() - ref) <= NLL_TOL * abs(ref), (unroll, v.item(), ref, err)
         nll, gb, stb = m.eval_batched(torch.from_numpy(offs).cuda(), torch.from_numpy(np.tile(th, (4, 1))).cuda())
         nll = nll.cpu().numpy()
@@ -290,7 +378,8 @@ def test_autograd_function(torch, nllmi):
 def test_gradient_against_central_differences_c2(torch, nllmi):
     """Adjoint gradient vs central finite differences with h = 1e-6 on each
     parameter; tolerance = 10 x (truncation + rounding) bound of the FD."""
-    w = datagen.workload(2, n=1_000_000)
+    w = datagen.workload(2)
+    print(f"[c2 central differences n={w['n']}]", flush=True)
     m = nllmi.Model.from_spec(w["spec"])
     m.set_data(to_dev(torch, w["cols"]))
     th = w["points"][3]

@@ -4,8 +4,7 @@ the counts; sWeights of either sign) against the oracle: the weighted NLL
 descent scaled by 1/W, and the entry points that refuse weights.
 
 Tolerances as for the unweighted pass: NLL 1e-12 relative, gradient 1e-8 of
-max(|g|, G) with G the largest per-parameter sum of |w_i d l_i/d theta|;
-fitted points 1e-9 relative.
+||g_oracle||_inf at seeded points; fitted points 1e-9 relative.
 """
 import numpy as np
 import pytest
@@ -51,7 +50,7 @@ def check(torch, nllmi, spec, cols, wt, points, threads, unroll=None):
         v, g = m.eval_grad(torch.from_numpy(np.ascontiguousarray(th)))
         v, g = float(v.item()), g.cpu().numpy()
         assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
-        assert np.max(np.abs(g - gref)) <= GRAD_TOL * max(np.max(np.abs(gref)), np.max(stats[1:])), (th, g, gref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
         v1 = float(m.eval(torch.from_numpy(np.ascontiguousarray(th))).item())
         assert abs(v1 - ref) <= NLL_TOL * abs(ref), (th, v1, ref)
     assert m.sync() == 0
