@@ -121,6 +121,7 @@ def test_narrow_peak_expression(torch, nllmi, threads, sigma):
     form normalisation through erf)."""
     import oracle
     spec = datagen.gauss_spec(5.0, sigma, 0.0, 10.0)
+    spec["params"][1]["lo"] = 1e-4  # the oracle's range check: widths below the spec's default floor
     x = datagen.generate(spec, 40_000, seed=321)[0]
     o = oracle.Oracle(spec)
     m = nllmi.JITModel(GAUSS, 0.0, 10.0, params([5.0, sigma], [0.0, 1e-4], [10.0, 5.0]))
