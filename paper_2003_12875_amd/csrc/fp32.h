@@ -12,7 +12,9 @@
 // values that one Newton step then corrects.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 namespace nllmi {
 

@@ -12,7 +12,9 @@
 //     arithmetic and rounded to double.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 namespace nllmi {
 

@@ -7,67 +7,10 @@
 
 #include <vector>
 
+#include "args.h"
 #include "plan.h"
 
 namespace nllmi {
-
-// State of a gradient-descent fit (device arrays).
-struct GDState {
-  double* th_acc;   // n_sets * P  last accepted point
-  double* g_acc;    // n_sets * P  its gradient
-  double* th_prop;  // n_sets * P  point being evaluated
-  double* f_acc;    // n_sets      its NLL (+inf before the first acceptance)
-  double* eta;      // n_sets      step size (BHHH: damping lambda)
-  int* last_status; // n_sets
-  double* b_acc;    // n_sets * P * P  BHHH: matrix at the last accepted point
-};
-
-struct SingleArgs {
-  const double* cols[kMaxObs];  // SoA event columns (device)
-  int64_t n;
-  const double* theta;          // n_param (device)
-  double* nll_out;              // 1 (device)
-  double* grad_out;             // n_param (device) or null
-  double* bhhh_out;             // n_param^2 (device): BHHH matrix (evaluation)
-  double* partials;             // grid * (NA + 1) double-double pairs
-  PerTheta* pt_out;             // per-point constants left by block 0 (evaluation)
-  PerTheta* consts;             // fit: constants of the proposal being evaluated,
-                                // written by the previous step's finishing kernel
-  int* status;                  // accumulated status bits
-  const double* glx;            // 256-point Gauss-Legendre rule on [-1, 1]
-  const double* glw;
-  GDState gd;                   // fit mode: theta = gd.th_prop, set 0
-  const double* wsum;           // weighted events: the weights' sum W (device, 1)
-  // gradient-descent fit, double-buffered by step parity (k_single_fit):
-  const double* partials_prev;  // the previous step's block records (null at the first step)
-  GDState gd_out;               // the state the update writes (gd is the one it reads)
-  PerTheta* consts_out;         // constants of the proposal this step evaluates
-};
-
-// One work item of the batched pass: events [start, end) of one set.
-struct WorkItem {
-  int64_t start, end;
-  int32_t set, flag;  // flag: the offsets were malformed (no events)
-};
-
-struct SetsArgs {
-  const double* cols[kMaxObs];
-  int n_sets;
-  const int64_t* offsets;   // n_sets + 1 (device)
-  int64_t tile;             // events per work item
-  const int64_t* tile_off;  // n_sets + 1 prefix of item counts (device)
-  const int* set_flag;      // n_sets: 1 = malformed offsets
-  const WorkItem* items;    // tile_off[n_sets] work items in set order
-  PerTheta* consts;         // n_sets
-  double* partials;         // items * (NA + 1) double-double pairs
-  const double* theta;      // n_sets * P (evaluation mode)
-  double* nll_out;          // n_sets
-  double* grad_out;         // n_sets * P or null
-  int* status_out;          // n_sets or null
-  GDState gd;               // fit mode
-  const double* glx;
-  const double* glw;
-};
 
 struct VariantOps {
   const char* name;

@@ -1,963 +1,15 @@
-// kernels_impl.h -- the streaming NLL kernels for gfx950 and their launchers
-// (templates; instantiated per compiled model shape in variants_*.hip).
-//
-//   k_single   one dataset: persistent grid, each block computes the
-//              per-point constants itself, streams its tiles of the SoA
-//              event columns once (coalesced, U events per thread per
-//              tile), reduces in double-double and writes one record per
-//              block.
-//   k_single_finish  one block: the block records in block order, NLL
-//              (and the gradient) to device memory; in a fit, the update.
-//   k_single_fit  one gradient-descent step per launch: every block first
-//              takes the previous step's update from that launch's records
-//              (same bits in every block), then streams at the new proposal.
-//   k_consts   per-set constants for many datasets (one block per set).
-//   k_schedule tile counts per set and their prefix (one block).
-//   k_sets     many datasets: work items (set, tile) over a persistent
-//              grid, one double-double record per item.
-//   k_sets_finish  one block per set, launched after k_sets: that set's
-//              item records in item order, its NLL / gradient / status
-//              and, when fitting, the gradient-descent step and the
-//              constants of the next proposal (a batched fit step is these
-//              two launches).
-//   k_fit_init / k_fit_final   state set-up and read-out around the steps.
-//
-// No matrix cores: the pass is a streaming map-reduce.
+// kernels_impl.h -- launchers of the streaming NLL kernels and the
+// registry entry of a compiled model shape (instantiated per shape in
+// variants_*.hip).
 #pragma once
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
-#include "model.h"
-#include "prologue.h"
-#include "reduce.h"
+#include "kernels_dev.h"
 
 namespace nllmi {
-
-// ------------------------------------------------------------------------
-// finisher: block totals -> NLL, status and gradient, by a whole block.
-// pl, pt and theta are LDS copies.  Every thread forms NLL and status (the
-// same bits everywhere); thread q < n_param forms d NLL / d theta_q from
-//   sum_k T_k d log w_k/d theta_q
-//     + sum_{l,p: param(l,p) = q} [ fscale_lp F_lp - Rtot_l d log Z_l/d theta_p ]
-// with T_k = sum_i r_k, F_lp = sum_i R_l phi_lp and Rtot_l = sum_{k ∋ l} T_k
-// (N for root leaves); the leaf and term loops are compile-time.
-// Results: *s_nll, *s_st (thread 0 writes) and g[q], visible after the
-// trailing barrier.  n: the number of events, or over weighted events the
-// weights' sum W.
-// ------------------------------------------------------------------------
-template <class M, bool GRAD>
-__device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt, const DD* tot, double n,
-                                             const double* theta, bool flagged, double* s_nll, int* s_st, double* g) {
-  constexpr int NA = M::template NA<GRAD>;
-  const int64_t bad_events = (int64_t)(tot[NA].hi + tot[NA].lo);
-  const double sum_l = tot[0].hi + tot[0].lo;
-  // the FP32 pass sums log-densities without the term constants: croot +
-  // ck_0 for every event, ck_k - ck_0 for every event whose largest term is k
-  double cn = pt.croot;
-  double cterms = 0.0;
-  if constexpr (M::PREC == 1 && M::K > 1) {
-    cn += pt.ck[0];
-#pragma unroll
-    for (int k = 1; k < M::K; ++k) {
-      const DD c = tot[M::template CNT_BASE<GRAD> + k - 1];
-      cterms += (pt.ck[k] - pt.ck[0]) * (c.hi + c.lo);
-    }
-  }
-  double nll = -((sum_l + cterms) + n * cn);
-  if (pl.extended) {
-    const double nu = theta[pl.yield_param];
-    nll += nu - n * log(nu);
-  }
-  int status = 0;
-  if (flagged) status = -1;                                                 // malformed offsets
-  else if (pt.bad) status = -3;                                             // parameter range
-  else if (bad_events > 0 || !__builtin_isfinite(nll)) status = -5;         // invalid density
-  if (status != 0) nll = __builtin_inf();
-  if (threadIdx.x == 0) {
-    *s_nll = nll;
-    *s_st = status;
-  }
-  if constexpr (GRAD) {
-    const int q = threadIdx.x;
-    if (q < pl.n_param) {
-      double acc = 0.0;
-      if (status == 0) {
-        double T[M::K];
-        double Tsum = 0.0;
-#pragma unroll
-        for (int k = 0; k < M::K - 1; ++k) {
-          T[k] = tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo;
-          Tsum += T[k];
-        }
-        T[M::K - 1] = M::K > 1 ? n - Tsum : 0.0;  // sum_k r_k = 1 per event
-        if constexpr (M::K > 1) {
-#pragma unroll
-          for (int k = 0; k < M::K; ++k) acc += T[k] * pt.dlogw[k][q];
-        }
-        static_for<M::L>([&](auto lc) {
-          constexpr int l = decltype(lc)::value;
-          constexpr int off = M::template leaf_off<l>();
-          double R = n;
-          if constexpr (!M::ROOTs[l]) {
-            const int mask_l = 1 << l;
-            R = 0.0;
-#pragma unroll
-            for (int k = 0; k < M::K; ++k) R += (pl.term_mask[k] & mask_l) ? T[k] : 0.0;
-          }
-#pragma unroll
-          for (int p = 0; p < M::NPs[l]; ++p) {
-            if (pl.leaf_param[l][p] == q) {
-              const DD v = tot[M::LEAF_BASE + off + p];
-              double F = v.hi + v.lo;
-              if constexpr (M::PREC == 1) F += pt.phioff[l][p] * R;  // features of x - x0
-              acc += pt.fscale[l][p] * F - R * pt.dlogz[l][p];
-            }
-          }
-        });
-        acc = -acc;
-        if (pl.extended && q == pl.yield_param) acc += 1.0 - n / theta[q];
-      }
-      g[q] = pl.par_free[q] ? acc : 0.0;
-    }
-  }
-  __syncthreads();
-}
-
-// Gradient-descent state of set s as read at the start of a finishing
-// kernel (thread 0: f_acc, eta; thread q < P: its parameter's entries), so
-// that these loads travel together with the kernel's other loads.
-struct GDPre {
-  double fa, eta;         // thread 0
-  int ls;                 // thread 0: last status
-  double acc, ga, prop;   // thread q < P
-};
-__device__ inline GDPre gd_preload(const GDState& gd, int s, int P) {
-  GDPre r{0.0, 0.0, 0, 0.0, 0.0, 0.0};
-  const int q = threadIdx.x;
-  if (q == 0) {
-    r.fa = gd.f_acc[s];
-    r.eta = gd.eta[s];
-    r.ls = gd.last_status[s];
-  }
-  if (q < P) {
-    r.acc = gd.th_acc[(size_t)s * P + q];
-    r.ga = gd.g_acc[(size_t)s * P + q];
-    r.prop = gd.th_prop[(size_t)s * P + q];
-  }
-  return r;
-}
-
-// Gradient descent on the mean NLL with step halving, by a whole block:
-// thread 0 accepts the evaluated proposal when its NLL is finite and exceeds
-// the last accepted one by at most 4 ulps (rounding noise), else halves the
-// step; then thread q forms the next proposal theta_acc - eta g_acc / N of
-// parameter q (free parameters only), stores it and returns it (threads
-// q >= P return 0).  st/nll are block-uniform LDS values; grad is in LDS.
-__device__ inline double gd_update(const Plan& pl, const GDState& gd, int s, int st, double nll,
-                                   const double* grad, double n_s, const GDPre& pre) {
-  __shared__ int s_ok;
-  __shared__ double s_step;
-  const int P = pl.n_param;
-  if (threadIdx.x == 0) {
-    const double fa = pre.fa;
-    const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
-    double eta = pre.eta;
-    if (ok) {
-      gd.f_acc[s] = nll;
-      gd.last_status[s] = 0;
-    } else {
-      eta *= 0.5;
-      gd.eta[s] = eta;
-      if (!__builtin_isfinite(fa)) gd.last_status[s] = st != 0 ? st : -5;
-    }
-    s_ok = ok;
-    s_step = eta / (n_s > 0.0 ? n_s : 1.0);
-  }
-  __syncthreads();
-  const int q = threadIdx.x;
-  double next = 0.0;
-  if (q < P) {
-    double acc = pre.acc, ga = pre.ga;
-    if (s_ok) {
-      acc = pre.prop;
-      ga = grad[q];
-      gd.th_acc[(size_t)s * P + q] = acc;
-      gd.g_acc[(size_t)s * P + q] = ga;
-    }
-    next = pl.par_free[q] ? acc - s_step * ga : acc;
-    gd.th_prop[(size_t)s * P + q] = next;
-  }
-  return next;
-}
-
-// The same step for a state kept in two buffers (by step parity): the
-// state is read from pre (gd_preload of the input buffer) and, when
-// `writer`, every field is written to `out`, changed or not.  Threads
-// q >= P return 0.  Every block of a streaming launch calls it with the
-// same inputs (same bits everywhere); only one writes.
-__device__ inline double gd_update_to(const Plan& pl, const GDState& out, int st, double nll, const double* grad,
-                                      double n_s, const GDPre& pre, bool writer) {
-  __shared__ int s_ok;
-  __shared__ double s_step;
-  const int P = pl.n_param;
-  if (threadIdx.x == 0) {
-    const double fa = pre.fa;
-    const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
-    double eta = pre.eta, f = fa;
-    int ls = pre.ls;
-    if (ok) {
-      f = nll;
-      ls = 0;
-    } else {
-      eta *= 0.5;
-      if (!__builtin_isfinite(fa)) ls = st != 0 ? st : -5;
-    }
-    if (writer) {
-      out.f_acc[0] = f;
-      out.eta[0] = eta;
-      out.last_status[0] = ls;
-    }
-    s_ok = ok;
-    s_step = eta / (n_s > 0.0 ? n_s : 1.0);
-  }
-  __syncthreads();
-  const int q = threadIdx.x;
-  double next = 0.0;
-  if (q < P) {
-    const double acc = s_ok ? pre.prop : pre.acc;
-    const double ga = s_ok ? grad[q] : pre.ga;
-    next = pl.par_free[q] ? acc - s_step * ga : acc;
-    if (writer) {
-      out.th_acc[q] = acc;
-      out.g_acc[q] = ga;
-      out.th_prop[q] = next;
-    }
-  }
-  return next;
-}
-
-// ------------------------------------------------------------------------
-// BHHH: B = sum_i s_i s_i^T of the events' scores s_i = d log p(x_i)/d theta
-// (Berndt, Hall, Hall and Hausman), the outer-product approximation of the
-// NLL's Hessian, and the damped (Levenberg-Marquardt) step on it.
-// ------------------------------------------------------------------------
-// index of the second moment of score features (i, j), i <= j, in the
-// upper-triangle row order of AccBhhh
-template <int NVF>
-__device__ __forceinline__ int mom_index(int i, int j) {
-  return i * NVF - i * (i - 1) / 2 + (j - i);
-}
-
-// B (LDS, P x P row-major, symmetric) from the reduced totals: the score is
-// affine in the features, s_i = c0 + A v_i, with, for parameter q,
-//   A[q][k]         = d log w_k/d theta_q - sum_{non-root l in S_k, p -> q} d log Z_lp
-//   A[q][NT+off+p]  = fscale_lp             (leaf l's local parameter p is q)
-//   c0[q]           = - sum_{root l, p -> q} d log Z_lp,
-// so B = N c0 c0^T + c0 (A m1)^T + (A m1) c0^T + A M2 A^T with m1 = sum v and
-// M2 = sum v v^T; plus N / nu^2 at (nu, nu) in an extended model.  Rows and
-// columns of fixed parameters, and everything after an invalid evaluation,
-// are 0.  Every entry is formed for (min, max) of its indices, so B is
-// exactly symmetric.  Ends with a barrier.
-template <class M>
-__device__ __forceinline__ void bhhh_assemble(const Plan& pl, const PerTheta& pt, const DD* tot, int64_t n,
-                                              const double* theta, int st, double* B) {
-  using AB = AccBhhh<M>;
-  constexpr int NT = AB::NT, NVF = AB::NVF, NA = AB::NA;
-  __shared__ double sA[kMaxParams][NVF];
-  __shared__ double sc0[kMaxParams], sAm1[kMaxParams];
-  const int P = pl.n_param, t = threadIdx.x;
-  const double dn = (double)n;
-  if (t < P) {
-    const int q = t;
-    double Aq[NVF];
-#pragma unroll
-    for (int j = 0; j < NVF; ++j) Aq[j] = 0.0;
-    double c0 = 0.0;
-    if constexpr (NT > 0) {
-#pragma unroll
-      for (int k = 0; k < M::K; ++k) Aq[k] = pt.dlogw[k][q];
-    }
-    static_for<M::L>([&](auto lc) {
-      constexpr int l = decltype(lc)::value;
-      constexpr int off = M::template leaf_off<l>();
-#pragma unroll
-      for (int p = 0; p < M::NPs[l]; ++p) {
-        if (pl.leaf_param[l][p] == q) {
-          Aq[NT + off + p] += pt.fscale[l][p];
-          if constexpr (M::ROOTs[l]) {
-            c0 -= pt.dlogz[l][p];
-          } else {
-#pragma unroll
-            for (int k = 0; k < M::K; ++k)
-              if ((pl.term_mask[k] >> l) & 1) Aq[k] -= pt.dlogz[l][p];
-          }
-        }
-      }
-    });
-    double m1[NVF];
-    if constexpr (NT > 0) {
-      double Tsum = 0.0;
-#pragma unroll
-      for (int k = 0; k < M::K - 1; ++k) {
-        m1[k] = tot[M::TERM_BASE + k].hi + tot[M::TERM_BASE + k].lo;
-        Tsum += m1[k];
-      }
-      m1[M::K - 1] = dn - Tsum;
-    }
-#pragma unroll
-    for (int j = 0; j < M::NPT; ++j) m1[NT + j] = tot[M::LEAF_BASE + j].hi + tot[M::LEAF_BASE + j].lo;
-    double am = 0.0;
-#pragma unroll
-    for (int j = 0; j < NVF; ++j) {
-      am = fma(Aq[j], m1[j], am);
-      sA[q][j] = Aq[j];
-    }
-    sc0[q] = c0;
-    sAm1[q] = am;
-  }
-  __syncthreads();
-  for (int e = t; e < P * P; e += blockDim.x) {
-    const int q0 = e / P, r0 = e - q0 * P;
-    const int q = q0 < r0 ? q0 : r0, r = q0 < r0 ? r0 : q0;
-    double b = 0.0;
-    if (st == 0 && pl.par_free[q] && pl.par_free[r]) {
-      double quad = 0.0;
-#pragma unroll
-      for (int i = 0; i < NVF; ++i) {
-        double row = 0.0;  // (M2 A_r^T)_i
-#pragma unroll
-        for (int j = 0; j < NVF; ++j) {
-          const DD mm = tot[NA + 1 + (i <= j ? mom_index<NVF>(i, j) : mom_index<NVF>(j, i))];
-          row = fma(mm.hi + mm.lo, sA[r][j], row);
-        }
-        quad = fma(sA[q][i], row, quad);
-      }
-      b = ((dn * sc0[q]) * sc0[r] + sc0[q] * sAm1[r]) + (sAm1[q] * sc0[r] + quad);
-      if (pl.extended && q == pl.yield_param && r == q) b += dn / (theta[q] * theta[q]);
-    }
-    B[e] = b;
-  }
-  __syncthreads();
-}
-
-// Solve (B + lambda D) d = -g over the free parameters by Cholesky, D the
-// diagonal of B floored at 1e-12 of its largest free entry; fixed
-// parameters enter as identity rows (d = 0), which leaves the free part's
-// arithmetic unchanged.  One thread; L is P x P scratch (LDS).  False if the
-// damped matrix is not positive definite.
-__device__ inline bool damped_solve(const Plan& pl, const double* B, const double* g, double lambda, double* d,
-                                    double* L) {
-  const int P = pl.n_param;
-  double dmax = 0.0;
-  for (int k = 0; k < P; ++k)
-    if (pl.par_free[k]) dmax = fmax(dmax, B[k * P + k]);
-  for (int a = 0; a < P; ++a) {
-    for (int b = 0; b <= a; ++b) {
-      double s;
-      if (!pl.par_free[a] || !pl.par_free[b]) {
-        s = a == b ? 1.0 : 0.0;
-      } else {
-        s = B[a * P + b];
-        if (a == b) s += lambda * fmax(s, 1e-12 * dmax);
-      }
-      for (int c = 0; c < b; ++c) s -= L[a * P + c] * L[b * P + c];
-      if (a == b) {
-        if (!(s > 0.0) || !__builtin_isfinite(s)) return false;
-        L[a * P + a] = sqrt(s);
-      } else {
-        L[a * P + b] = s / L[b * P + b];
-      }
-    }
-  }
-  for (int a = 0; a < P; ++a) {  // L y = -g  (y kept in d)
-    double s = pl.par_free[a] ? -g[a] : 0.0;
-    for (int c = 0; c < a; ++c) s -= L[a * P + c] * d[c];
-    d[a] = s / L[a * P + a];
-  }
-  for (int a = P - 1; a >= 0; --a) {  // L^T d = y
-    double s = d[a];
-    for (int c = a + 1; c < P; ++c) s -= L[c * P + a] * d[c];
-    d[a] = s / L[a * P + a];
-  }
-  return true;
-}
-
-// Damped BHHH step by a whole block (set 0): thread 0 accepts the
-// evaluated proposal when its NLL is finite and at most 4 ulps above the
-// last accepted one (lambda /= 10, floored at 1e-12), else lambda *= 10;
-// the accepted point, gradient and matrix are kept (B, LDS, becomes the
-// accepted matrix; bpre is this thread's entry of the previously accepted
-// one); thread 0 solves the damped system, retrying with ten times the
-// damping at most 8 times; thread q < P stores and returns its parameter of
-// the next proposal (theta_acc if no solve succeeded), threads q >= P 0.
-__device__ inline double bhhh_update(const Plan& pl, const GDState& gd, int st, double nll, const double* grad,
-                                     double* B, double bpre, const GDPre& pre) {
-  __shared__ int s_ok, s_solved;
-  __shared__ double s_lam;
-  __shared__ double s_acc[kMaxParams], s_g[kMaxParams], s_d[kMaxParams];
-  __shared__ double s_L[kMaxParams * kMaxParams];
-  const int P = pl.n_param, t = threadIdx.x;
-  if (t == 0) {
-    const double fa = pre.fa;
-    const bool ok = st == 0 && __builtin_isfinite(nll) && nll <= fa + 4.0 * 2.220446049250313e-16 * fabs(fa);
-    double lam = pre.eta;
-    if (ok) {
-      gd.f_acc[0] = nll;
-      gd.last_status[0] = 0;
-      lam = fmax(lam * 0.1, 1e-12);
-    } else {
-      lam *= 10.0;
-      if (!__builtin_isfinite(fa)) gd.last_status[0] = st != 0 ? st : -5;
-    }
-    s_ok = ok;
-    s_lam = lam;
-  }
-  __syncthreads();
-  const bool ok = s_ok;
-  if (t < P) {
-    double acc = pre.acc, ga = pre.ga;
-    if (ok) {
-      acc = pre.prop;
-      ga = grad[t];
-      gd.th_acc[t] = acc;
-      gd.g_acc[t] = ga;
-    }
-    s_acc[t] = acc;
-    s_g[t] = ga;
-  }
-  if (t < P * P) {
-    if (ok) gd.b_acc[t] = B[t];
-    else B[t] = bpre;
-  }
-  __syncthreads();
-  if (t == 0) {
-    double lam = s_lam;
-    bool solved = false;
-    for (int tries = 0; tries < 8 && !solved; ++tries) {
-      solved = damped_solve(pl, B, s_g, lam, s_d, s_L);
-      if (!solved) lam *= 10.0;
-    }
-    gd.eta[0] = lam;
-    s_solved = solved;
-  }
-  __syncthreads();
-  double next = 0.0;
-  if (t < P) {
-    next = s_solved && pl.par_free[t] ? s_acc[t] + s_d[t] : s_acc[t];
-    gd.th_prop[t] = next;
-  }
-  return next;
-}
-
-// ------------------------------------------------------------------------
-// per-tile event loops
-// ------------------------------------------------------------------------
-template <class M, int U>
-__device__ inline void load_tile(const double* const* cols, int64_t base, double (&x)[U][M::NOBS]) {
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int o = 0; o < M::NOBS; ++o) x[u][o] = cols[o][base + (int64_t)u * kBlock];
-}
-
-template <class M, bool GRAD, int U, class CT, class AT>
-__device__ inline void compute_tile(const double (&x)[U][M::NOBS], const CT& C, AT& acc) {
-  acc.begin_tile();
-#pragma unroll
-  for (int u = 0; u < U; ++u) model_event<M, GRAD>(x[u], C, acc);
-  acc.end_tile();
-}
-
-// Full tiles base0, base0 + stride, ... (count of them), software
-// pipelined through a ring of R register buffers: the first R - 1 tiles
-// arrive preloaded in xb[0 .. R-2], and before tile k is computed the loads
-// of tile k + R - 1 are issued into the buffer that tile k - 1 used, so each
-// load has R - 1 tiles of compute to arrive.  The ring is unrolled (buffers
-// rotate without copies) and its loads are unconditional: past the last
-// tile they re-read the last one (a cache hit, never used), so the loop body
-// has no branches and the compiler's load-counter waits see every load of
-// the ring in flight.  Three buffers for shapes with at most 8 accumulators;
-// two for the heavier ones, whose registers are already scarce (measured:
-// three cost the 2-D model ~4-5 %, two cost the mixture at 1e8 events ~18 %).
-template <class M>
-constexpr int ring_depth() {
-  return M::template NA<true> <= 8 ? 3 : 2;
-}
-
-template <class M, int U, int R>
-__device__ inline void preload_ring(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
-                                    double (&xb)[R][U][M::NOBS]) {
-#pragma unroll
-  for (int j = 0; j < R - 1; ++j)
-    if (j < count) load_tile<M, U>(cols, base0 + j * stride, xb[j]);
-}
-
-template <class M, bool GRAD, int U, int R, class CT, class AT>
-__device__ inline void stream_tiles(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
-                                    double (&xb)[R][U][M::NOBS], const CT& C, AT& acc) {
-  const int64_t groups = count / R;
-  for (int64_t g = 0; g < groups; ++g) {
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int64_t k = g * R + j;
-      const int64_t kl = k + R - 1 < count ? k + R - 1 : count - 1;
-      load_tile<M, U>(cols, base0 + kl * stride, xb[(j + R - 1) % R]);
-      compute_tile<M, GRAD, U>(xb[j], C, acc);
-    }
-  }
-  // tiles groups * R + j, j < count % R, are in xb[j]
-  const int64_t rem = count - groups * R;
-#pragma unroll
-  for (int j = 0; j < R - 1; ++j)
-    if (j < rem) compute_tile<M, GRAD, U>(xb[j], C, acc);
-}
-
-template <class M, bool GRAD, int U, class CT, class AT>
-__device__ inline void stream_part_tile(const double* const* cols, int64_t base, int64_t end, const CT& C,
-                                        AT& acc) {
-  acc.begin_tile();
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t i = base + (int64_t)u * kBlock;
-    if (i < end) {
-      double x[M::NOBS];
-#pragma unroll
-      for (int o = 0; o < M::NOBS; ++o) x[o] = cols[o][i];
-      model_event<M, GRAD>(x, C, acc);
-    }
-  }
-  acc.end_tile();
-}
-
-// ------------------------------------------------------------------------
-// single dataset
-// ------------------------------------------------------------------------
-// Streaming pass over one dataset: per-block prologue, the block's tiles,
-// one compensated partial per block (plain stores; the next kernel on the
-// stream reads them).  Block 0 also leaves its per-point constants for the
-// finishing kernel.
-template <class M, bool GRAD, int U, bool FIT = false, bool BH = false>
-__global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleArgs a) {
-  static_assert(!BH || (GRAD && M::PREC == 0), "BHHH moments: FP64 gradient pass only");
-  constexpr int NA = M::template NA<GRAD>;
-  constexpr int NM = BH ? AccBhhh<M>::NM : 0;  // BHHH second moments
-  constexpr int NV = NA + 1 + NM;              // + invalid-event count
-  constexpr int NR = NA + 1 > NM ? NA + 1 : NM;  // values per block_sum_vals pass
-  __shared__ Plan spl;
-  __shared__ double s_theta[kMaxParams];
-  __shared__ PerTheta pt;
-  __shared__ double red[NR * (kBlock + 1)];
-  __shared__ DD tot[NV];
-  __shared__ double small[4 * (kMaxLeafParams + 1)];
-
-  // Evaluation: plan and parameters first, then the first event tile
-  // (which does not depend on theta), whose loads overlap the prologue.
-  // Fit: the constants of the proposal were prepared by the previous step's
-  // finishing kernel; the event pass reads the few it needs straight from
-  // there (uniform loads), overlapping the first tiles' loads.
-  if constexpr (!FIT) {
-    stage_plan<kBlock>(pl, &spl);
-    stage_theta(a.theta, pl.n_param, s_theta);
-  }
-  const double* cols[M::NOBS];
-#pragma unroll
-  for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
-  const int64_t tile = (int64_t)kBlock * U;
-  const int64_t nfull = a.n / tile;
-  const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-  const int64_t base0 = (int64_t)blockIdx.x * tile + threadIdx.x;
-  double xb[ring_depth<M>()][U][M::NOBS];
-  preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
-
-  using CT = typename Pass<M, GRAD>::C;
-  __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
-  if constexpr (CT::kExpTab) stage_exp_table(s_etab);
-  if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
-  CT C;
-  int bad;
-  if constexpr (FIT) {
-    C.load(*a.consts, pl);
-    bad = uniform(a.consts->bad);
-  } else {
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
-    C.load(pt, pl);
-    bad = uniform(pt.bad);
-  }
-  if constexpr (CT::kExpTab) C.etab = s_etab;
-  if constexpr (CT::kExpTab || M::EVENT_LOG) __syncthreads();
-  std::conditional_t<BH, AccBhhh<M>, typename Pass<M, GRAD>::A> acc;
-  acc.init();
-  if (bad == 0) {
-    stream_tiles<M, GRAD, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb, C, acc);
-    const int64_t rest = nfull * tile;
-    if (rest < a.n && blockIdx.x == (unsigned)(nfull % gridDim.x))
-      stream_part_tile<M, GRAD, U>(cols, rest + threadIdx.x, a.n, C, acc);
-  }
-
-  // partial record: the NA sums, the invalid-event count, the NM moments
-  if constexpr (BH) {
-    double w[NA + NM];
-    acc.finalize(w);
-    double v0[NA + 1], v1[NM];
-#pragma unroll
-    for (int j = 0; j < NA; ++j) v0[j] = w[j];
-    v0[NA] = (double)acc.run.bad;
-#pragma unroll
-    for (int j = 0; j < NM; ++j) v1[j] = w[NA + j];
-    block_sum_vals<NA + 1, kBlock>(v0, red, tot);
-    block_sum_vals<NM, kBlock>(v1, red, tot + NA + 1);
-  } else {
-    double v[NV];
-    acc.finalize(reinterpret_cast<double(&)[NA]>(v));
-    v[NA] = (double)acc.bad;
-    block_sum_vals<NV, kBlock>(v, red, tot);
-  }
-  if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
-  if (!FIT && blockIdx.x == 0) {
-    const double* src = reinterpret_cast<const double*>(&pt);
-    double* dst = reinterpret_cast<double*>(a.pt_out);
-    for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kBlock) dst[i] = src[i];
-  }
-}
-
-// Finishing kernel (one block of kFinishBlock threads): the block partials
-// in block order, then NLL and gradient; in fit mode the gradient-descent
-// step of the proposal just evaluated and the per-point constants of the
-// next proposal (for the next step's streaming kernel).  Every load it
-// needs is issued at once at the start.
-template <class M, bool GRAD, bool FIT = false, bool BH = false>
-__global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, const SingleArgs a, int n_blocks) {
-  constexpr int NA = M::template NA<GRAD>;
-  constexpr int NV = NA + 1 + (BH ? AccBhhh<M>::NM : 0);
-  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
-  static_assert(PT8 <= kFinishBlock, "one constant per thread");
-  __shared__ Plan spl;
-  __shared__ DD tot[NV];
-  __shared__ double s_grad[kMaxParams];
-  __shared__ PerTheta spt;
-  __shared__ double s_theta[kMaxParams];
-  __shared__ double s_nll;
-  __shared__ int s_st;
-  __shared__ double small[(kFinishBlock / 64) * (kMaxLeafParams + 1)];
-  const int t = threadIdx.x;
-  stage_plan<kFinishBlock>(pl, &spl);
-  const double ptv = t < PT8 ? reinterpret_cast<const double*>(FIT ? a.consts : a.pt_out)[t] : 0.0;
-  stage_theta(FIT ? a.gd.th_prop : a.theta, pl.n_param, s_theta);
-  GDPre pre{};
-  if constexpr (FIT) pre = gd_preload(a.gd, 0, pl.n_param);
-  double bpre = 0.0;  // BHHH fit: this thread's entry of the accepted matrix
-  if constexpr (FIT && BH) {
-    const int P = pl.n_param;
-    if (t < P * P) bpre = a.gd.b_acc[t];
-  }
-  // the events' count, or the weights' sum W (attached with the weights)
-  double neff = (double)a.n;
-  if constexpr (M::WEIGHTED) neff = *a.wsum;
-  // the gradient-descent steps (k_single_fit) store their records value-major
-  std::conditional_t<FIT && !BH, RecordSumT<NV, kFinishBlock>, RecordSum<NV, kFinishBlock>> rs;
-  rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
-  if (t < PT8) reinterpret_cast<double*>(&spt)[t] = ptv;
-  rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
-  finish_block<M, GRAD>(spl, spt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
-  __shared__ double s_B[BH ? kMaxParams * kMaxParams : 1];
-  if constexpr (BH) bhhh_assemble<M>(spl, spt, tot, a.n, s_theta, s_st, s_B);
-  if constexpr (FIT && !BH) {
-    // after the last step of a gradient-descent fit (k_single_fit): that
-    // step's update, into the other state buffer
-    (void)gd_update_to(spl, a.gd_out, s_st, s_nll, s_grad, neff, pre, true);
-  } else if constexpr (FIT) {
-    const double next = bhhh_update(spl, a.gd, s_st, s_nll, s_grad, s_B, bpre, pre);
-    if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
-    // the next proposal's constants, built in LDS (its phases read back
-    // what other threads wrote) and stored with one parallel copy
-    compute_pertheta<M, kFinishBlock>(spl, s_theta, a.glx, a.glw, &spt, small);
-    if (t < PT8) reinterpret_cast<double*>(a.consts)[t] = reinterpret_cast<const double*>(&spt)[t];
-  } else {
-    if (t == 0) {
-      *a.nll_out = s_nll;
-      if (s_st == -3) atomicOr(a.status, (int)kStatusParam);
-      if (s_st == -5) atomicOr(a.status, (int)kStatusPdf);
-    }
-    if (GRAD && a.grad_out && t < spl.n_param) a.grad_out[t] = s_grad[t];
-    if constexpr (BH) {
-      const int P = spl.n_param;
-      if (a.bhhh_out && t < P * P) a.bhhh_out[t] = s_B[t];
-    }
-  }
-}
-
-// One gradient-descent step over one dataset in one launch.  Every block
-// first finishes the previous step itself: the previous launch's block
-// records (stored value-major, summed in a fixed order), that
-// proposal's NLL and gradient, the accept-or-halve update and the
-// constants of the next proposal -- the same inputs and arithmetic in every
-// block, so the same bits everywhere; block 0 stores the new state and
-// constants.  Then the block streams its tiles at the new proposal.  State,
-// constants and records alternate between two buffers by step parity, so
-// that no block overwrites what another block of the same launch still
-// reads; the launch boundary makes them visible to the next step.  The
-// first step (partials_prev null) takes the constants k_fit_init made.
-// This removes one kernel per step: the loads of the first event tiles are
-// issued before the finishing work and arrive during it.
-template <class M, int U>
-__global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const SingleArgs a) {
-  constexpr int NA = M::template NA<true>;
-  constexpr int NV = NA + 1;  // + invalid-event count
-  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
-  constexpr int PTL = (PT8 + kBlock - 1) / kBlock;  // constants per thread
-  using CT = typename Pass<M, true>::C;
-  __shared__ Plan spl;
-  __shared__ double s_theta[kMaxParams];
-  __shared__ double s_grad[kMaxParams];
-  __shared__ PerTheta pt;
-  __shared__ double red[NV * (kBlock + 1)];
-  __shared__ DD tot[NV];
-  __shared__ double small[4 * (kMaxLeafParams + 1)];
-  __shared__ double s_nll;
-  __shared__ int s_st;
-  __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
-  const int t = threadIdx.x;
-  const bool first = a.partials_prev == nullptr;
-
-  // loads in the order they are needed (they complete in order): plan,
-  // state and the previous proposal's constants and records, then the
-  // first event tiles
-  GDPre pre{};
-  double ptv[PTL];
-  double neff = (double)a.n;
-  RecordSumT<NV, kBlock, 16> rs;
-  if (!first) {
-    stage_plan<kBlock>(pl, &spl);
-    stage_theta(a.gd.th_prop, pl.n_param, s_theta);
-    pre = gd_preload(a.gd, 0, pl.n_param);
-    if constexpr (M::WEIGHTED) neff = *a.wsum;
-#pragma unroll
-    for (int i = 0; i < PTL; ++i) {
-      const int e = t + i * kBlock;
-      ptv[i] = e < PT8 ? reinterpret_cast<const double*>(a.consts)[e] : 0.0;
-    }
-    rs.issue(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x);
-  }
-  const double* cols[M::NOBS];
-#pragma unroll
-  for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
-  const int64_t tile = (int64_t)kBlock * U;
-  const int64_t nfull = a.n / tile;
-  const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-  const int64_t base0 = (int64_t)blockIdx.x * tile + t;
-  double xb[ring_depth<M>()][U][M::NOBS];
-  preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
-  if constexpr (CT::kExpTab) stage_exp_table(s_etab);
-  if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
-
-  CT C;
-  int bad;
-  if (first) {
-    C.load(*a.consts, pl);
-    bad = uniform(a.consts->bad);
-  } else {
-#pragma unroll
-    for (int i = 0; i < PTL; ++i) {
-      const int e = t + i * kBlock;
-      if (e < PT8) reinterpret_cast<double*>(&pt)[e] = ptv[i];
-    }
-    rs.reduce(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x, tot);  // ends with a barrier
-    finish_block<M, true>(spl, pt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
-    const double next = gd_update_to(spl, a.gd_out, s_st, s_nll, s_grad, neff, pre, blockIdx.x == 0);
-    if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
-    if (blockIdx.x == 0)
-      for (int e = t; e < PT8; e += kBlock)
-        reinterpret_cast<double*>(a.consts_out)[e] = reinterpret_cast<const double*>(&pt)[e];
-    C.load(pt, pl);
-    bad = uniform(pt.bad);
-  }
-  if constexpr (CT::kExpTab) C.etab = s_etab;
-  __syncthreads();
-
-  typename Pass<M, true>::A acc;
-  acc.init();
-  if (bad == 0) {
-    stream_tiles<M, true, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb, C, acc);
-    const int64_t rest = nfull * tile;
-    if (rest < a.n && blockIdx.x == (unsigned)(nfull % gridDim.x))
-      stream_part_tile<M, true, U>(cols, rest + t, a.n, C, acc);
-  }
-  double v[NV];
-  acc.finalize(reinterpret_cast<double(&)[NA]>(v));
-  v[NA] = (double)acc.bad;
-  block_sum_vals<NV, kBlock>(v, red, tot);
-  if (t < NV) reinterpret_cast<DD*>(a.partials)[(size_t)t * gridDim.x + blockIdx.x] = tot[t];  // value-major
-}
-
-// ------------------------------------------------------------------------
-// many datasets
-// ------------------------------------------------------------------------
-template <class M>
-__global__ __launch_bounds__(kBlock) void k_consts(const Plan pl, const double* __restrict__ theta,
-                                                  int n_sets, PerTheta* __restrict__ out,
-                                                  const double* __restrict__ glx,
-                                                  const double* __restrict__ glw) {
-  __shared__ double small[4 * (kMaxLeafParams + 1)];
-  __shared__ Plan spl;
-  __shared__ double s_theta[kMaxParams];
-  __shared__ PerTheta spt;
-  const int s = blockIdx.x;
-  if (s >= n_sets) return;
-  stage_plan<kBlock>(pl, &spl);
-  stage_theta(theta + (size_t)s * pl.n_param, pl.n_param, s_theta);
-  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
-  for (int e = threadIdx.x; e < (int)(sizeof(PerTheta) / sizeof(double)); e += kBlock)
-    reinterpret_cast<double*>(&out[s])[e] = reinterpret_cast<const double*>(&spt)[e];
-}
-
-template <class M, bool GRAD, int U>
-__global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a) {
-  constexpr int NA = M::template NA<GRAD>;
-  constexpr int NV = NA + 1;
-  __shared__ double red[NV * (kBlock + 1)];
-  __shared__ DD tot[NV];
-  const int64_t total = a.tile_off[a.n_sets];
-  const double* cols[M::NOBS];
-#pragma unroll
-  for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
-  using CT = typename Pass<M, GRAD>::C;
-  __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
-  if constexpr (CT::kExpTab) stage_exp_table(s_etab);
-  if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
-  if constexpr (CT::kExpTab || M::EVENT_LOG) __syncthreads();
-
-  // the next item's descriptor is loaded while the current one streams
-  int64_t item = blockIdx.x;
-  WorkItem cur{0, 0, 0, 0};
-  if (item < total) cur = a.items[item];
-  while (item < total) {
-    const int64_t nxt = item + gridDim.x;
-    WorkItem next = cur;
-    if (nxt < total) next = a.items[nxt];
-    const int s = cur.set;
-    const PerTheta& pt = a.consts[s];
-    const int64_t start = cur.start, end = cur.end;
-
-    CT C;
-    C.load(pt, pl);
-    C.etab = s_etab;
-    typename Pass<M, GRAD>::A acc;
-    acc.init();
-    if (uniform(pt.bad) == 0 && cur.flag == 0) {
-      const int64_t step = (int64_t)kBlock * U;
-      const int64_t full = (end - start) / step;
-      double xb[ring_depth<M>()][U][M::NOBS];
-      preload_ring<M, U>(cols, start + threadIdx.x, step, full, xb);
-      stream_tiles<M, GRAD, U>(cols, start + threadIdx.x, step, full, xb, C, acc);
-      const int64_t base = start + full * step;
-      if (base < end) stream_part_tile<M, GRAD, U>(cols, base + threadIdx.x, end, C, acc);
-    }
-    double v[NV];
-    acc.finalize(reinterpret_cast<double(&)[NA]>(v));
-    v[NA] = (double)acc.bad;
-    block_sum_vals<NV, kBlock>(v, red, tot);
-    if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)item * NV + threadIdx.x] = tot[threadIdx.x];
-    cur = next;
-    item = nxt;
-  }
-}
-
-// One block per set: reduce the set's work-item partials in item order,
-// write NLL / gradient / status, or (fitting) take the gradient-descent step
-// and prepare the constants of the next proposal.
-template <class M, bool GRAD, bool FIT>
-__global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const SetsArgs a) {
-  constexpr int NA = M::template NA<GRAD>;
-  constexpr int NV = NA + 1;
-  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
-  __shared__ Plan spl;
-  __shared__ DD tot[NV];
-  __shared__ double small[4 * (kMaxLeafParams + 1)];
-  __shared__ double s_grad[kMaxParams];
-  __shared__ PerTheta spt;
-  __shared__ double s_theta[kMaxParams];
-  __shared__ double s_nll;
-  __shared__ int s_st;
-  const int s = blockIdx.x;
-  if (s >= a.n_sets) return;
-  const int P = pl.n_param;
-  const int t = threadIdx.x;
-  // every independent load at once: plan, constants, parameters, fit
-  // state, offsets and the first batch of partial records
-  stage_plan<kBlock>(pl, &spl);
-  double ptv[(PT8 + kBlock - 1) / kBlock];
-#pragma unroll
-  for (int i = 0; i < (PT8 + kBlock - 1) / kBlock; ++i) {
-    const int e = t + i * kBlock;
-    ptv[i] = e < PT8 ? reinterpret_cast<const double*>(&a.consts[s])[e] : 0.0;
-  }
-  stage_theta(FIT ? a.gd.th_prop + (size_t)s * P : a.theta + (size_t)s * P, P, s_theta);
-  GDPre pre{};
-  if constexpr (FIT) pre = gd_preload(a.gd, s, P);
-  const int64_t first = a.tile_off[s], n_items = a.tile_off[s + 1] - first;
-  const int flag = a.set_flag[s];
-  const int64_t o0 = a.offsets[s], o1 = a.offsets[s + 1];
-  const DD* recs = reinterpret_cast<const DD*>(a.partials) + (size_t)first * NV;
-  RecordSum<NV, kBlock> rs;
-  rs.issue(recs, n_items);
-#pragma unroll
-  for (int i = 0; i < (PT8 + kBlock - 1) / kBlock; ++i) {
-    const int e = t + i * kBlock;
-    if (e < PT8) reinterpret_cast<double*>(&spt)[e] = ptv[i];
-  }
-  rs.reduce(recs, n_items, tot);  // ends with a barrier
-  const int64_t n_s = flag ? 0 : o1 - o0;
-  finish_block<M, GRAD>(spl, spt, tot, n_s, s_theta, flag != 0, &s_nll, &s_st, s_grad);
-  if constexpr (!FIT) {
-    if (t == 0) {
-      a.nll_out[s] = s_nll;
-      if (a.status_out) a.status_out[s] = s_st;
-    }
-    if (GRAD && a.grad_out && t < P) a.grad_out[(size_t)s * P + t] = s_st == 0 ? s_grad[t] : 0.0;
-  } else {
-    const double next = gd_update(spl, a.gd, s, s_st, s_nll, s_grad, n_s, pre);
-    if (t < P) s_theta[t] = next;  // compute_pertheta starts with a barrier
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &spt, small);
-    for (int e = t; e < PT8; e += kBlock)
-      reinterpret_cast<double*>(&a.consts[s])[e] = reinterpret_cast<const double*>(&spt)[e];
-  }
-}
-
-template <class M>
-__global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double* __restrict__ theta,
-                                                    int n_sets, double eta, GDState gd,
-                                                    PerTheta* __restrict__ consts,
-                                                    const double* __restrict__ glx,
-                                                    const double* __restrict__ glw) {
-  __shared__ double small[4 * (kMaxLeafParams + 1)];
-  __shared__ Plan spl;
-  __shared__ double s_theta[kMaxParams];
-  __shared__ PerTheta spt;
-  const int s = blockIdx.x;
-  if (s >= n_sets) return;
-  const int P = pl.n_param;
-  stage_plan<kBlock>(pl, &spl);
-  if (threadIdx.x < P) {
-    const double v = theta[(size_t)s * P + threadIdx.x];
-    s_theta[threadIdx.x] = v;
-    gd.th_acc[(size_t)s * P + threadIdx.x] = v;
-    gd.th_prop[(size_t)s * P + threadIdx.x] = v;
-    gd.g_acc[(size_t)s * P + threadIdx.x] = 0.0;
-  }
-  if (threadIdx.x == 0) {
-    gd.f_acc[s] = __builtin_inf();
-    gd.eta[s] = eta;
-    gd.last_status[s] = 0;
-  }
-  if (gd.b_acc)
-    for (int e = threadIdx.x; e < P * P; e += kBlock) gd.b_acc[(size_t)s * P * P + e] = 0.0;
-  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
-  for (int e = threadIdx.x; e < (int)(sizeof(PerTheta) / sizeof(double)); e += kBlock)
-    reinterpret_cast<double*>(&consts[s])[e] = reinterpret_cast<const double*>(&spt)[e];
-}
 
 // ------------------------------------------------------------------------
 // launchers
@@ -968,16 +20,6 @@ inline size_t pad_lds(const void* kernel, int lds_cap) {
   hipFuncAttributes fa;
   if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) return 0;
   return (size_t)lds_cap > fa.sharedSizeBytes ? (size_t)lds_cap - fa.sharedSizeBytes : 0;
-}
-
-// BHHH pass compiled: FP64 unweighted shapes with at most 6 score features
-template <class M>
-constexpr bool bh_compiled() {
-  if constexpr (M::PREC != 0 || M::WEIGHTED) {
-    return false;
-  } else {
-    return AccBhhh<M>::NVF <= 6;
-  }
 }
 
 template <class M>

@@ -29,7 +29,9 @@
 // in the tail.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "fp32.h"
 #include "fp64.h"

@@ -25,7 +25,9 @@
 // (the sum of r_{K-1} is N minus the others: sum_k r_k = 1 per event).
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include <tuple>
 #include <type_traits>

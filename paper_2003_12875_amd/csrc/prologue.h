@@ -12,7 +12,9 @@
 //    log normalisations of its leaves, and d log w_k / d theta.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "leaves.h"
 #include "model.h"

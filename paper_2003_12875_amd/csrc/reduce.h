@@ -9,7 +9,9 @@
 // kernel (the kernel boundary makes them visible across the chip's XCDs).
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 namespace nllmi {
 
