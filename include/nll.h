@@ -60,7 +60,8 @@ typedef enum nll_status {
   NLL_ERR_INVALID_PDF = -5,  /* some p(x_i) <= 0 or non-finite               */
   NLL_ERR_DEVICE = -6,       /* HIP runtime error                           */
   NLL_ERR_OOM = -7,          /* device allocation failed                    */
-  NLL_ERR_STATE = -8         /* call out of order (e.g. no data attached)    */
+  NLL_ERR_STATE = -8,        /* call out of order (e.g. no data attached)    */
+  NLL_ERR_SCRATCH = -9       /* request larger than the fixed scratch array  */
 } nll_status;
 
 /* Node kinds.  Leaf parameters, in this order:
@@ -200,6 +201,34 @@ nll_status nll_eval_grad(nll_model* model, const double* theta, double* nll_out,
 nll_status nll_eval_batched(nll_model* model, int32_t n_sets, const int64_t* offsets, const double* theta,
                             double* nll_out, double* grad_out, int32_t* status_out);
 
+/* Bytes of the fixed device array that nll_eval_batched_noalloc works in
+ * (one copy per GPU, held until the process ends). */
+#define NLL_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* Enqueue: nll_eval_batched without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * must not call hipMalloc).  Arguments, results and errors as
+ * nll_eval_batched, and the same kernels and launch schedule, so the
+ * results are the same bits.  The pass's scratch (tile schedule, per-set
+ * constants, the work items and their partial sums) lives in one fixed
+ * array of NLL_NOALLOC_SCRATCH_BYTES per GPU instead of the model's own
+ * buffers; the array is looked up (hipGetSymbolAddress) on the first call
+ * on each device.  It needs
+ *   align256(8 (n_sets + 1)) + align256(4 n_sets) + align256(24 I)
+ *   + align256(S n_sets) + I * 16 (A + 1)  bytes,
+ * with I = n_events / tile_events + n_sets + 1 work items, S the per-set
+ * constant block (nll_model_info's per_set_bytes) and A the model's
+ * accumulators (n_accumulators); a larger request returns NLL_ERR_SCRATCH
+ * before anything is enqueued (4096 sets over 4.1e8 events of a one-leaf
+ * model need about 21 MB).  Every word the pass reads is written earlier
+ * in the same call, so nothing has to start at zero.  All calls on one GPU
+ * share the array: calls that overlap on that GPU (other models, other
+ * streams, other host threads) race and must be serialised by the caller;
+ * the array keeps the last call's contents. */
+nll_status nll_eval_batched_noalloc(nll_model* model, int32_t n_sets, const int64_t* offsets,
+                                    const double* theta, double* nll_out, double* grad_out,
+                                    int32_t* status_out);
+
 /* Enqueue: the attached dataset at many parameter points in one pass (the
  * minimiser's repeated evaluations of the likelihood at different
  * parameter values, Sec. 1; a likelihood scan).  Point p is
@@ -321,6 +350,7 @@ typedef struct nll_info {
   int32_t n_leaf, n_term, n_accumulators, precision;
   int32_t n_cu;
   int64_t n_events;
+  int32_t per_set_bytes;  /* device bytes of one set's per-point constants */
 } nll_info;
 nll_status nll_get_info(const nll_model* model, nll_info* out);
 

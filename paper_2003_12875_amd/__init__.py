@@ -355,7 +355,7 @@ class Model:
         check(lib().nll_get_info(self._h, ctypes.byref(i)), "nll_get_info")
         return {"variant": i.variant.decode(), "n_leaf": i.n_leaf, "n_term": i.n_term,
                 "n_accumulators": i.n_accumulators, "precision": i.precision, "n_cu": i.n_cu,
-                "n_events": i.n_events}
+                "n_events": i.n_events, "per_set_bytes": i.per_set_bytes}
 
 
 class HFModel:

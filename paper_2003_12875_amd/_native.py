@@ -11,11 +11,11 @@ MAX_OBS, MAX_PARAMS, MAX_NODES, MAX_NODE_PARAMS, MAX_NODE_CHILDREN = 4, 32, 16, 
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported model shape", -3: "parameter out of range",
           -4: "event outside observable range", -5: "invalid density", -6: "device error",
-          -7: "out of device memory", -8: "call out of order"}
+          -7: "out of device memory", -8: "call out of order", -9: "request larger than the fixed scratch array"}
 
 # every entry point declared in include/nll.h
 EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_data", "nll_set_weights", "nll_eval",
-           "nll_eval_grad", "nll_eval_batched", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_eval_bhhh",
+           "nll_eval_grad", "nll_eval_batched", "nll_eval_batched_noalloc", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_eval_bhhh",
            "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
            "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
            "nll_status_string", "nll_hf_create", "nll_hf_destroy", "nll_hf_set_data", "nll_hf_eval", "nll_hf_sync",
@@ -76,7 +76,7 @@ class Schedule(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_char * 64), ("n_leaf", ctypes.c_int32), ("n_term", ctypes.c_int32),
                 ("n_accumulators", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_cu", ctypes.c_int32),
-                ("n_events", ctypes.c_int64)]
+                ("n_events", ctypes.c_int64), ("per_set_bytes", ctypes.c_int32)]
 
 
 _lib = None
@@ -101,6 +101,7 @@ def lib():
         L.nll_eval.argtypes = [vp, vp, vp]
         L.nll_eval_grad.argtypes = [vp, vp, vp, vp]
         L.nll_eval_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.nll_eval_batched_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.nll_eval_points.argtypes = [vp, i32, vp, vp, vp, vp]
         L.nll_fit_batched.argtypes = [vp, i32, vp, vp, i32, d, vp, vp, vp]
         L.nll_fit.argtypes = [vp, vp, i32, d, vp, vp, vp]

@@ -622,6 +622,49 @@ nll_status run_recorded(nll_model* m, const FitKey& k, F&& enqueue) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+namespace nllmi {
+
+nll_status batched_args_ok(const nll_model* m, int32_t n_sets, const int64_t* offsets, const double* theta,
+                           const double* nll_out) {
+  if (!m || n_sets < 0 || (n_sets > 0 && (!offsets || !theta || !nll_out))) return NLL_ERR_ARG;
+  if (m->n < 0) return NLL_ERR_STATE;
+  if (m->weights) return NLL_ERR_UNSUPPORTED;
+  return NLL_OK;
+}
+
+int64_t batched_items_bound(const nll_model* m, int32_t n_sets) {
+  const int64_t tile = m->sched.tile_events;
+  return (m->n > 0 ? m->n / tile : 0) + n_sets + 1;
+}
+
+size_t batched_record_bytes(const nll_model* m) { return (size_t)(m->ops->na_grad + 1) * 2 * sizeof(double); }
+
+nll_status eval_batched_on(nll_model* m, int32_t n_sets, const int64_t* offsets, const double* theta,
+                           double* nll_out, double* grad_out, int32_t* status_out, const SetsScratch& s) {
+  const bool grad = grad_out != nullptr;
+  SetsArgs a = sets_args(m, n_sets, offsets);
+  a.tile_off = s.tile_off;
+  a.set_flag = s.set_flag;
+  a.items = s.items;
+  a.consts = s.consts;
+  a.partials = s.partials;
+  a.theta = theta;
+  a.nll_out = nll_out;
+  a.grad_out = grad_out;
+  a.status_out = reinterpret_cast<int*>(status_out);
+  if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, s.tile_off, s.set_flag, s.items, m->stream) !=
+      hipSuccess)
+    return NLL_ERR_DEVICE;
+  if (m->ops->consts(m->plan, theta, n_sets, s.consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  if (m->ops->sets(m->plan, a, grad, false, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
+                   m->stream, nullptr, nullptr) != hipSuccess)
+    return NLL_ERR_DEVICE;
+  return NLL_OK;
+}
+
+}  // namespace nllmi
+
 extern "C" {
 
 const char* nll_status_string(nll_status s) {
@@ -635,6 +678,7 @@ const char* nll_status_string(nll_status s) {
     case NLL_ERR_DEVICE: return "HIP runtime error";
     case NLL_ERR_OOM: return "out of device memory";
     case NLL_ERR_STATE: return "call out of order";
+    case NLL_ERR_SCRATCH: return "request larger than the fixed scratch array of the no-allocation entry point";
   }
   return "unknown status";
 }
@@ -799,28 +843,17 @@ nll_status nll_eval_grad(nll_model* m, const double* theta, double* nll_out, dou
 
 nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets, const double* theta,
                             double* nll_out, double* grad_out, int32_t* status_out) {
-  if (!m || n_sets < 0 || (n_sets > 0 && (!offsets || !theta || !nll_out))) return NLL_ERR_ARG;
-  if (m->n < 0) return NLL_ERR_STATE;
-  if (m->weights) return NLL_ERR_UNSUPPORTED;
-  if (n_sets == 0) return NLL_OK;
+  nll_status st = batched_args_ok(m, n_sets, offsets, theta, nll_out);
+  if (st != NLL_OK || n_sets == 0) return st;
   DeviceGuard guard(m->device);
-  nll_status st = ensure_sets(m, n_sets);
-  if (st != NLL_OK) return st;
-  const bool grad = grad_out != nullptr;
-  SetsArgs a = sets_args(m, n_sets, offsets);
-  a.theta = theta;
-  a.nll_out = nll_out;
-  a.grad_out = grad_out;
-  a.status_out = reinterpret_cast<int*>(status_out);
-  if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->items, m->stream) !=
-      hipSuccess)
-    return NLL_ERR_DEVICE;
-  if (m->ops->consts(m->plan, theta, n_sets, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
-    return NLL_ERR_DEVICE;
-  if (m->ops->sets(m->plan, a, grad, false, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
-                   m->stream, nullptr, nullptr) != hipSuccess)
-    return NLL_ERR_DEVICE;
-  return NLL_OK;
+  if ((st = ensure_sets(m, n_sets)) != NLL_OK) return st;
+  SetsScratch s;
+  s.tile_off = m->tile_off;
+  s.set_flag = m->set_flag;
+  s.items = m->items;
+  s.consts = m->consts;
+  s.partials = m->set_partials;
+  return eval_batched_on(m, n_sets, offsets, theta, nll_out, grad_out, status_out, s);
 }
 
 nll_status nll_eval_points(nll_model* m, int32_t n_points, const double* theta, double* nll_out, double* grad_out,
@@ -1004,6 +1037,7 @@ nll_status nll_get_info(const nll_model* m, nll_info* out) {
   out->precision = m->precision;
   out->n_cu = m->n_cu;
   out->n_events = m->n;
+  out->per_set_bytes = (int32_t)sizeof(PerTheta);
   return NLL_OK;
 }
 

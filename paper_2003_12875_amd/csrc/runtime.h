@@ -111,5 +111,26 @@ struct nll_model {
 
 
 namespace nllmi {
+// Device buffers of one batched pass: the tile schedule (n_sets + 1 prefix
+// entries, n_sets flags, the work items), the per-set constants and the
+// items' partial records.
+struct SetsScratch {
+  int64_t* tile_off = nullptr;
+  int* set_flag = nullptr;
+  WorkItem* items = nullptr;
+  PerTheta* consts = nullptr;
+  double* partials = nullptr;
+};
+// argument checks of the batched evaluation (no device work)
+nll_status batched_args_ok(const nll_model* m, int32_t n_sets, const int64_t* offsets, const double* theta,
+                           const double* nll_out);
+// most work items n_sets consecutive event ranges of the attached data can need
+int64_t batched_items_bound(const nll_model* m, int32_t n_sets);
+// bytes of one item's partial record
+size_t batched_record_bytes(const nll_model* m);
+// enqueue the batched pass on the model's stream with the given buffers
+// (nothing is allocated)
+nll_status eval_batched_on(nll_model* m, int32_t n_sets, const int64_t* offsets, const double* theta,
+                           double* nll_out, double* grad_out, int32_t* status_out, const SetsScratch& s);
 nll_status tune_model(nll_model* m, int which, int n_sets, const int64_t* offsets, const double* theta);
 }  // namespace nllmi

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_status_strings(L):
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9):
         assert L.nll_status_string(code)
     assert L.nll_status_string(0) == b"ok"
 
@@ -45,6 +45,7 @@ def test_argument_errors_without_device(L):
     assert L.nll_create_model(None, ctypes.byref(h)) == -1
     assert L.nll_eval(None, None, None) == -1
     assert L.nll_eval_grad(None, None, None, None) == -1
+    assert L.nll_eval_batched_noalloc(None, 1, None, None, None, None, None) == -1
     assert L.nll_sync(None, None) == -1
     assert L.nll_set_schedule(None, None) == -1
     assert L.nll_get_info(None, None) == -1
