@@ -218,10 +218,15 @@ def _dg_model(spec: dict, theta=None) -> DgModel:
         d.kind = KIND[nd["kind"]]
         d.obs = int(nd.get("obs", -1))
         ps = nd.get("params", [])
-        d.n_param = len(ps)
-        for j, pi in enumerate(ps):
-            d.p[j] = th[pi]
         cs = nd.get("children", [])
+        vals = [th[pi] for pi in ps]
+        if nd["kind"] == "sum" and len(ps) == len(cs):
+            # a sum of yields: the children are drawn with probabilities nu_j / sum nu
+            tot = sum(vals)
+            vals = [v / tot for v in vals[:-1]]
+        d.n_param = len(vals)
+        for j, v in enumerate(vals):
+            d.p[j] = v
         d.n_child = len(cs)
         for j, c in enumerate(cs):
             d.child[j] = c

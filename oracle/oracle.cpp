@@ -569,12 +569,51 @@ int expected_params(const orc_node& nd) {
     case ORC_CHEB: return (nd.n_param >= 1 && nd.n_param <= ORC_NODE_PAR) ? nd.n_param : -1;
     case ORC_CB: return 4;
     case ORC_ARGUS: return 2;
-    case ORC_SUM: return nd.n_child - 1;
+    case ORC_SUM: return (nd.n_param == nd.n_child) ? nd.n_child : nd.n_child - 1;
     case ORC_PROD: return 0;
     case ORC_JOHNSON: return 4;
     case ORC_CHI2: return 1;
   }
   return -1;
+}
+
+/* A SUM with one coefficient per child takes them as yields. */
+bool sum_of_yields(const orc_node& nd) { return nd.kind == ORC_SUM && nd.n_param == nd.n_child; }
+
+/* The SUM whose yields make the expected event count of an extended model
+ * without a separate yield parameter: the root if it is a sum of yields,
+ * else the one sum of yields among the children of a root product; -1 if
+ * there is none (or more than one). */
+int extended_sum(const orc_model& m) {
+  const orc_node& r = m.node[m.root];
+  if (sum_of_yields(r)) return m.root;
+  if (r.kind != ORC_PROD) return -1;
+  int found = -1;
+  for (int j = 0; j < r.n_child; ++j) {
+    if (sum_of_yields(m.node[r.child[j]])) {
+      if (found >= 0) return -1;
+      found = r.child[j];
+    }
+  }
+  return found;
+}
+
+/* Parameter k enters the expected event count of an extended model. */
+bool is_yield(const orc_model& m, int k) {
+  if (m.yield_param >= 0) return k == m.yield_param;
+  const orc_node& s = m.node[extended_sum(m)];
+  for (int q = 0; q < s.n_param; ++q)
+    if (s.param[q] == k) return true;
+  return false;
+}
+
+/* The expected event count nu of an extended model at theta. */
+double total_yield(const orc_model& m, const double* th) {
+  if (m.yield_param >= 0) return th[m.yield_param];
+  const orc_node& s = m.node[extended_sum(m)];
+  double nu = 0.0;
+  for (int k = 0; k < s.n_param; ++k) nu += th[s.param[k]];
+  return nu;
 }
 
 bool is_leaf(int kind) { return (kind >= ORC_GAUSS && kind <= ORC_ARGUS) || kind == ORC_JOHNSON || kind == ORC_CHI2; }
@@ -627,7 +666,10 @@ int check_model(const orc_model& m) {
     }
   }
   if (obs_mask(m, m.root) != (1u << m.n_obs) - 1u) return ORC_E_UNSUPPORTED;
-  if (m.extended && (m.yield_param < 0 || m.yield_param >= m.n_param)) return ORC_E_ARG;
+  if (m.extended) {
+    if (m.yield_param >= m.n_param) return ORC_E_ARG;
+    if (m.yield_param < 0 && extended_sum(m) < 0) return ORC_E_ARG;
+  }
   return ORC_OK;
 }
 
@@ -658,6 +700,15 @@ int check_params(const orc_model& m, const double* th) {
         break;
       case ORC_SUM: {
         double f = 0.0;
+        if (sum_of_yields(nd)) { /* yields >= 0 with a positive total */
+          for (int k = 0; k < nd.n_param; ++k) {
+            double v = P(th, nd, k);
+            if (!(v >= 0.0)) return ORC_E_PARAM;
+            f += v;
+          }
+          if (!(f > 0.0) || !std::isfinite(f)) return ORC_E_PARAM;
+          break;
+        }
         for (int k = 0; k < nd.n_param; ++k) {
           double v = P(th, nd, k);
           if (!(v >= 0.0 && v <= 1.0)) return ORC_E_PARAM;
@@ -669,7 +720,7 @@ int check_params(const orc_model& m, const double* th) {
       default: break;
     }
   }
-  if (m.extended && !(th[m.yield_param] > 0.0)) return ORC_E_PARAM;
+  if (m.extended && !(total_yield(m, th) > 0.0)) return ORC_E_PARAM;
   return ORC_OK;
 }
 
@@ -714,6 +765,25 @@ double node_value(const Prepared& pr, int i, const double* x, double* dv) {
     return v;
   }
   double cd[ORC_MAX_PAR];
+  if (sum_of_yields(nd)) {
+    /* p = sum_j nu_j p_j / S, S = sum_j nu_j; d p / d nu_j = (p_j - p) / S */
+    double S = 0.0;
+    for (int k = 0; k < nd.n_param; ++k) S += P(pr.th, nd, k);
+    double v = 0.0;
+    double vals[ORC_NODE_CHILD];
+    if (dv)
+      for (int k = 0; k < np; ++k) dv[k] = 0.0;
+    for (int j = 0; j < nd.n_child; ++j) {
+      vals[j] = node_value(pr, nd.child[j], x, dv ? cd : nullptr);
+      double coef = P(pr.th, nd, j) / S;
+      v += coef * vals[j];
+      if (dv)
+        for (int k = 0; k < np; ++k) dv[k] += coef * cd[k];
+    }
+    if (dv)
+      for (int j = 0; j < nd.n_child; ++j) dv[nd.param[j]] += (vals[j] - v) / S;
+    return v;
+  }
   if (nd.kind == ORC_SUM) {
     double v = 0.0, flast = 1.0;
     if (dv)
@@ -864,10 +934,17 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
   double nw = w ? ws.value() : (double)n;
   if (wsum_out) *wsum_out = nw;
   if (m.extended) {
-    /* Poisson term for the total yield nu: nu - N ln nu (N -> W with weights) */
-    double nu = th[m.yield_param];
+    /* Poisson term for the expected count nu: nu - N ln nu (N -> W with
+     * weights); nu is one parameter or the sum of the root's yields, and
+     * d/d nu_j = 1 - N / nu for each of them */
+    double nu = total_yield(m, th);
     v += nu - nw * std::log(nu);
-    g[m.yield_param].add(1.0 - nw / nu);
+    if (m.yield_param >= 0) {
+      g[m.yield_param].add(1.0 - nw / nu);
+    } else {
+      const orc_node& ys = m.node[extended_sum(m)];
+      for (int k = 0; k < ys.n_param; ++k) g[ys.param[k]].add(1.0 - nw / nu);
+    }
   }
   *nll = v;
   if (grad)
@@ -881,8 +958,8 @@ int nll_one(const orc_model& m, const double* const* cols, int64_t n, const doub
           o.add(parts[t].outer[(size_t)j * np + k].c);
         }
         double b = o.value();
-        if (m.extended && j == m.yield_param && k == m.yield_param) {
-          double nu = th[m.yield_param];
+        if (m.extended && is_yield(m, j) && is_yield(m, k)) {
+          double nu = total_yield(m, th);
           b += (double)n / (nu * nu);
         }
         if (!m.par_free[j] || !m.par_free[k]) b = 0.0;

@@ -44,7 +44,8 @@ enum orc_kind {
   ORC_CHEB = 3,  /* params (a_1..a_K)     g = 1 + sum a_k T_k(x') */
   ORC_CB = 4,    /* params (m0, sigma, alpha, n), low-side tail   */
   ORC_ARGUS = 5, /* params (m0, c), power 1/2                    */
-  ORC_SUM = 6,   /* params (f_1..f_{k-1}) over k children         */
+  ORC_SUM = 6,   /* params (f_1..f_{k-1}) over k children: fractions,
+                    or (nu_1..nu_k): yields, p = sum nu_j p_j / sum nu */
   ORC_PROD = 7,  /* no params; children on disjoint observables   */
   ORC_JOHNSON = 8, /* params (mu, lambda, gamma, delta), S_U family */
   ORC_CHI2 = 9     /* params (nu): g = x^(nu/2-1) e^(-x/2), 0 <= lo  */
@@ -91,7 +92,10 @@ typedef struct orc_model {
   orc_node node[ORC_MAX_NODE];
   int32_t root;
   int32_t extended;    /* 1: add nu - N ln nu (Poisson yield term) */
-  int32_t yield_param; /* index of nu when extended               */
+  int32_t yield_param; /* index of nu when extended, or -1: nu is the sum
+                          of the yields of the root's yield SUM (the root
+                          itself, or the one such SUM among the children of
+                          a root PROD)                                    */
 } orc_model;
 
 /* Structural validation (topological order, arities, disjoint products). */

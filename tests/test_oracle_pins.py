@@ -864,3 +864,130 @@ def test_binned_gauss_fit_reaches_weighted_mle():
     assert st == OK
     assert abs(th[0] - mu_hat) <= 1e-8 * abs(mu_hat)
     assert abs(th[1] - s_hat) <= 1e-8 * s_hat
+
+
+# ---------------------------------------------------------------------------
+# Sums of yields (extended models with one yield per component)
+# ---------------------------------------------------------------------------
+
+def yields_spec(extended=True):
+    """nu_1 Gauss(2, 0.3) + nu_2 Gauss(7, 0.5) + nu_3 Exp(-0.2) on [0, 10],
+    shapes fixed, yields free: p = sum nu_j p_j / sum nu_j."""
+    P = datagen.param
+    return {"obs": [{"name": "x", "lo": 0.0, "hi": 10.0}],
+            "params": [P("n1", 300.0, 0.0, 1e7), P("n2", 500.0, 0.0, 1e7), P("n3", 1200.0, 0.0, 1e7),
+                       P("mu1", 2.0, 0.0, 10.0, free=False), P("s1", 0.3, 0.01, 5.0, free=False),
+                       P("mu2", 7.0, 0.0, 10.0, free=False), P("s2", 0.5, 0.01, 5.0, free=False),
+                       P("c", -0.2, -5.0, 5.0, free=False)],
+            "nodes": [{"kind": "gauss", "obs": 0, "params": [3, 4]}, {"kind": "gauss", "obs": 0, "params": [5, 6]},
+                      {"kind": "exp", "obs": 0, "params": [7]},
+                      {"kind": "sum", "params": [0, 1, 2], "children": [0, 1, 2]}],
+            "root": 3, "extended": extended, "yield_param": -1}
+
+
+def test_yields_nll_matches_library():
+    """Extended NLL with yields = sum nu - sum_i log(sum_j nu_j p_j(x_i))
+    (the Poisson term nu - N ln nu plus -sum log p), every p_j a scipy
+    truncated density."""
+    spec = yields_spec()
+    th = np.array([310.0, 480.0, 1250.0, 2.0, 0.3, 7.0, 0.5, -0.2])
+    x = datagen.generate(spec, 2000, seed=41)[0]
+    dens = (th[0] * np.exp(lib_logpdf("gauss", (2.0, 0.3), 0.0, 10.0, x))
+            + th[1] * np.exp(lib_logpdf("gauss", (7.0, 0.5), 0.0, 10.0, x))
+            + th[2] * np.exp(lib_logpdf("exp", (-0.2,), 0.0, 10.0, x)))
+    ref = math.fsum(th[:3]) - math.fsum(np.log(dens))
+    st, v, g = oracle.Oracle(spec).nll([x], th)
+    assert st == OK
+    assert abs(v - ref) <= 1e-12 * abs(ref)
+    # without the Poisson term: the normalised mixture with fractions nu_j / sum nu
+    st, v0, g0 = oracle.Oracle(yields_spec(extended=False)).nll([x], th)
+    ref0 = -math.fsum(np.log(dens / math.fsum(th[:3])))
+    assert abs(v0 - ref0) <= 1e-12 * abs(ref0)
+
+
+def test_yields_gradient_vanishes_at_the_counts_of_separated_components():
+    """Components with (numerically) disjoint support: at nu_j = n_j (the
+    number of events drawn from component j) the extended NLL is stationary,
+    and d NLL / d nu_j = 1 - n_j / nu_j elsewhere (closed forms)."""
+    P = datagen.param
+    spec = {"obs": [{"name": "x", "lo": 0.0, "hi": 10.0}],
+            "params": [P("n1", 400.0, 0.0, 1e7), P("n2", 600.0, 0.0, 1e7), P("mu1", 2.0, 0.0, 10.0),
+                       P("s1", 0.1, 0.01, 5.0), P("mu2", 8.0, 0.0, 10.0), P("s2", 0.1, 0.01, 5.0)],
+            "nodes": [{"kind": "gauss", "obs": 0, "params": [2, 3]}, {"kind": "gauss", "obs": 0, "params": [4, 5]},
+                      {"kind": "sum", "params": [0, 1], "children": [0, 1]}],
+            "root": 2, "extended": True, "yield_param": -1}
+    x = datagen.generate(spec, 1000, seed=42)[0]
+    n1, n2 = int(np.sum(x < 5.0)), int(np.sum(x >= 5.0))
+    o = oracle.Oracle(spec)
+    st, v, g = o.nll([x], np.array([n1, n2, 2.0, 0.1, 8.0, 0.1]))
+    assert st == OK and abs(g[0]) < 1e-12 and abs(g[1]) < 1e-12
+    st, v2, g2 = o.nll([x], np.array([n1 + 40.0, n2 - 25.0, 2.0, 0.1, 8.0, 0.1]))
+    assert abs(g2[0] - (1.0 - n1 / (n1 + 40.0))) < 1e-12
+    assert abs(g2[1] - (1.0 - n2 / (n2 - 25.0))) < 1e-12
+    assert v2 > v
+
+
+def test_yields_equal_fractions_plus_poisson_term():
+    """The sum of yields equals the fraction form with f_j = nu_j / sum nu
+    (a different path through the oracle) plus nu - N ln nu."""
+    spec = yields_spec()
+    th = np.array([310.0, 480.0, 1250.0, 2.0, 0.3, 7.0, 0.5, -0.2])
+    x = datagen.generate(spec, 3000, seed=43)[0]
+    P = datagen.param
+    frac = {"obs": spec["obs"],
+            "params": [P("f1", 0.1, 0.0, 1.0), P("f2", 0.1, 0.0, 1.0)] + spec["params"][3:],
+            "nodes": [{"kind": "gauss", "obs": 0, "params": [2, 3]}, {"kind": "gauss", "obs": 0, "params": [4, 5]},
+                      {"kind": "exp", "obs": 0, "params": [6]},
+                      {"kind": "sum", "params": [0, 1], "children": [0, 1, 2]}],
+            "root": 3}
+    S = th[:3].sum()
+    thf = np.concatenate([[th[0] / S, th[1] / S], th[3:]])
+    vf = oracle.Oracle(frac).nll([x], thf)[1]
+    v = oracle.Oracle(spec).nll([x], th)[1]
+    assert abs(v - (vf + S - 3000 * math.log(S))) <= 1e-12 * abs(v)
+
+
+def test_yields_gradient_matches_central_differences():
+    spec = yields_spec()
+    for p in spec["params"]:
+        p["free"] = True
+    th = np.array([310.0, 480.0, 1250.0, 2.1, 0.28, 6.9, 0.55, -0.25])
+    x = datagen.generate(spec, 3000, seed=44)[0]
+    o = oracle.Oracle(spec)
+    st, nll, g = o.nll([x], th)
+    for k in range(len(th)):
+        h = 1e-4 * max(abs(th[k]), 0.1)
+
+        def f(v):
+            t = th.copy()
+            t[k] = v
+            return o.nll([x], t)[1]
+
+        fd = (f(th[k] - 2 * h) - 8 * f(th[k] - h) + 8 * f(th[k] + h) - f(th[k] + 2 * h)) / (12 * h)
+        bound = 50 * (2.2e-16 * abs(nll) / h) + 1e-6 * abs(g[k])
+        assert abs(fd - g[k]) <= bound, (k, fd, g[k], bound)
+
+
+def test_yields_checks_and_product_root():
+    """Negative yields or a zero total are out of range; a product whose one
+    child is a sum of yields takes that sum's total as the expected count."""
+    spec = yields_spec()
+    o = oracle.Oracle(spec)
+    x = datagen.generate(spec, 500, seed=45)[0]
+    th = np.array([310.0, 480.0, 1250.0, 2.0, 0.3, 7.0, 0.5, -0.2])
+    bad = th.copy()
+    bad[1] = -1.0
+    assert o.nll([x], bad)[0] == E_PARAM
+    zero = th.copy()
+    zero[:3] = 0.0
+    assert o.nll([x], zero)[0] == E_PARAM
+    P = datagen.param
+    prod = {"obs": [{"name": "x", "lo": 0.0, "hi": 10.0}, {"name": "y", "lo": -1.0, "hi": 1.0}],
+            "params": spec["params"] + [P("a1", 0.0, -1.0, 1.0)],
+            "nodes": spec["nodes"] + [{"kind": "cheb", "obs": 1, "params": [8]},
+                                      {"kind": "prod", "children": [3, 4]}],
+            "root": 5, "extended": True, "yield_param": -1}
+    y = np.linspace(-1.0, 1.0, 500)
+    st, v, g = oracle.Oracle(prod).nll([x, y], np.concatenate([th, [0.0]]))
+    v1 = o.nll([x], th)[1]
+    assert st == OK and abs(v - (v1 + 500 * math.log(2.0))) <= 1e-12 * abs(v)
