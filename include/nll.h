@@ -85,9 +85,12 @@ typedef enum nll_status {
  *              closed-form normalisation by the lower incomplete gamma
  *              function, Gauss-Legendre after x = s^2 when lo = 0
  * Composite nodes:
- *   NLL_SUM    params (f_1 .. f_{k-1}) over k >= 2 children on the same
- *              observables: p = sum_{j<k} f_j p_j + (1 - sum f) p_k,
- *              f_j in [0, 1], sum f <= 1
+ *   NLL_SUM    over k >= 2 children on the same observables, either
+ *              fractions (f_1 .. f_{k-1}): p = sum_{j<k} f_j p_j +
+ *              (1 - sum f) p_k, f_j in [0, 1], sum f <= 1; or yields
+ *              (nu_1 .. nu_k), as RooAddPdf takes k coefficients for k
+ *              densities: p = sum_j nu_j p_j / sum_j nu_j, nu_j >= 0 with a
+ *              positive total (an extended model's expected count, below)
  *   NLL_PROD   no params; children on disjoint observables: p = prod p_d   */
 enum nll_node_kind {
   NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7, NLL_JOHNSON = 8,
@@ -139,19 +142,38 @@ typedef struct nll_model_desc {
   int32_t root;                   /* index of the top density                 */
   int32_t precision;              /* nll_precision                            */
   int32_t extended;               /* 1: add nu - N ln nu (Poisson yield term) */
-  int32_t yield_param;            /* index of nu when extended                */
+  int32_t yield_param;            /* index of nu when extended, or -1: nu is
+                                     the total of the root's sum of yields (the
+                                     root itself, or the one sum of yields
+                                     among a root product's children), whose
+                                     yields then each get 1 - N / nu       */
   int32_t device;                 /* HIP device ordinal                       */
   void* stream;                   /* hipStream_t for all enqueued work (NULL: default) */
 } nll_model_desc;
 
 typedef struct nll_model nll_model; /* opaque, owned by the library */
 
-/* Validate the descriptor, lower the graph onto a compiled kernel shape and
- * allocate the model's device scratch.  Descriptor arrays are copied; the
- * caller may free them afterwards.  Errors: NLL_ERR_ARG (malformed graph,
- * bad indices, non-topological order, SUM over different observables, PROD
- * over shared observables, unused observable), NLL_ERR_UNSUPPORTED (no
- * compiled shape matches), NLL_ERR_DEVICE, NLL_ERR_OOM. */
+/* Validate the descriptor, lower the graph onto a kernel shape and allocate
+ * the model's device scratch.  Descriptor arrays are copied; the caller may
+ * free them afterwards.
+ * Lowering: the graph becomes a sum of K terms, each a product of leaf
+ * densities with one coefficient (the product of the SUM fractions on its
+ * path); leaves in every term are factors outside the per-event
+ * log-sum-exp.  Any graph within these limits is supported: at most 8
+ * leaves, 8 terms, 4 SUM nodes, 4 SUM nodes on the path to a term and 48
+ * per-event sums (1 + (K if K > 1) + the leaves' parameters, + K - 1 in
+ * NLL_FP32C).  Shapes compiled ahead of time (one leaf; two-term sums of
+ * Gauss+Exp, Gauss+Gauss, CB+ARGUS, Johnson+Exp; (CB+ARGUS) x Chebyshev-4;
+ * Gauss x Gauss) are ready at once; any other shape is compiled for the
+ * model's device at creation from the same kernel templates (hipRTC, the
+ * counterpart of the paper's just-in-time compilation, Sec. 4; about
+ * 5-15 s, once per shape and device in a process, code objects cached on
+ * disk under $NLLMI_RTC_CACHE, default ~/.cache/nllmi, "off" to disable).
+ * Errors: NLL_ERR_ARG (malformed graph, bad indices, non-topological
+ * order, SUM over different observables, PROD over shared observables,
+ * unused observable), NLL_ERR_UNSUPPORTED (beyond the limits above),
+ * NLL_ERR_DEVICE (also a failed run-time compilation: the compiler's log
+ * goes to stderr), NLL_ERR_OOM. */
 nll_status nll_create_model(const nll_model_desc* desc, nll_model** out);
 
 /* Release the model and its device scratch (waits for its stream). */
@@ -263,7 +285,8 @@ nll_status nll_fit(nll_model* model, double* theta, int32_t n_steps, double eta,
 
 /* Enqueue: NLL, gradient and the BHHH matrix B = sum_i s_i s_i^T of the
  * events' scores s_i = d log p(x_i) / d theta (device [n_param * n_param],
- * row-major, symmetric; plus N / nu^2 at (nu, nu) in an extended model;
+ * row-major, symmetric; plus N / nu^2 at every pair (nu_i, nu_j) of the
+ * parameters that make the expected count of an extended model;
  * rows and columns of fixed parameters 0) from one pass.  B approximates
  * the NLL's Hessian near the optimum (Berndt, Hall, Hall and Hausman 1974):
  * the outer-product information for the second-order minimiser that the
@@ -355,6 +378,17 @@ typedef struct nll_info {
 nll_status nll_get_info(const nll_model* model, nll_info* out);
 
 const char* nll_status_string(nll_status status);
+
+/* Measurement utility: enqueue one read of n doubles at x (device, 16-byte
+ * aligned) on `stream` (hipStream_t, NULL: default) by a streaming kernel of
+ * n_blocks blocks of 256 threads (16-byte loads, four in flight per
+ * thread); block b writes the sum of the values it read to block_sums[b]
+ * (device [n_blocks]).  Timed by the caller, it gives the HBM read rate a
+ * streaming pass reaches on the device, next to the data sheet's peak
+ * (the likelihood kernels read their event columns the same way, Sec. 5.2).
+ * Errors: NLL_ERR_ARG (null or misaligned pointers, n < 0, n_blocks outside
+ * 1 .. 2^20), NLL_ERR_DEVICE. */
+nll_status nll_read_probe(const double* x, int64_t n, double* block_sums, int32_t n_blocks, void* stream);
 
 /* ------------------------------------------------------------------------
  * Binned template likelihood of HistFactory type (the binned models the

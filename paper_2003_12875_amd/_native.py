@@ -17,7 +17,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported model shape", -3: "p
 EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_data", "nll_set_weights", "nll_eval",
            "nll_eval_grad", "nll_eval_batched", "nll_eval_batched_noalloc", "nll_eval_points", "nll_fit_batched", "nll_fit", "nll_eval_bhhh",
            "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
-           "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info",
+           "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info", "nll_read_probe",
            "nll_status_string", "nll_hf_create", "nll_hf_destroy", "nll_hf_set_data", "nll_hf_eval", "nll_hf_sync",
            "nll_hf_set_staterror", "nll_hf_eval_stat",
            "nll_jit_create", "nll_jit_destroy", "nll_jit_set_data", "nll_jit_eval", "nll_jit_sync")
@@ -112,6 +112,7 @@ def lib():
         L.nll_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
         L.nll_autotune.argtypes = [vp, i32, i32, vp, vp]
         L.nll_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.nll_read_probe.argtypes = [vp, i64, vp, i32, vp]
         L.nll_set_option.argtypes = [vp, i32, i32]
         L.nll_step_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         L.nll_status_string.argtypes = [i32]

@@ -187,4 +187,40 @@ hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, 
   return hipGetLastError();
 }
 
+// Read-bandwidth probe: streams n doubles once (16-byte loads, four in
+// flight per thread, grid-stride over a persistent grid) and writes one sum
+// per block, so that the loads cannot be dropped.  Measures the HBM read
+// rate a streaming kernel can reach on this device, the yardstick next to
+// the data sheet's peak.
+__global__ __launch_bounds__(kBlock) void k_read_probe(const double* __restrict__ x, int64_t n,
+                                                      double* __restrict__ out) {
+  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
+  const int64_t n2 = n / 2;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double acc = 0.0;
+  for (; i + 3 * stride < n2; i += 4 * stride) {
+    const double2 a = x2[i], b = x2[i + stride], c = x2[i + 2 * stride], d = x2[i + 3 * stride];
+    acc += ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+  }
+  for (; i < n2; i += stride) {
+    const double2 a = x2[i];
+    acc += a.x + a.y;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) acc += x[n - 1];
+  __shared__ double s[kBlock];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+hipError_t launch_read_probe(const double* x, int64_t n, double* out, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_read_probe, dim3((unsigned)blocks), dim3(kBlock), 0, st, x, n, out);
+  return hipGetLastError();
+}
+
 }  // namespace nllmi

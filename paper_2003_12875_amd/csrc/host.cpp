@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -15,6 +16,7 @@
 #include "kernels.h"
 #include "nll.h"
 #include "plan.h"
+#include "rtc.h"
 #include "runtime.h"
 
 using namespace nllmi;
@@ -122,7 +124,7 @@ struct Lowering {
       if (!(std::isfinite(D.obs_lo[o]) && std::isfinite(D.obs_hi[o]) && D.obs_lo[o] < D.obs_hi[o])) return NLL_ERR_ARG;
     for (int k = 0; k < D.n_param; ++k)
       if (!(D.param_lo[k] <= D.param_hi[k])) return NLL_ERR_ARG;
-    if (D.extended && (D.yield_param < 0 || D.yield_param >= D.n_param)) return NLL_ERR_ARG;
+    if (D.extended && D.yield_param >= D.n_param) return NLL_ERR_ARG;  // < 0: the root's sum of yields
     obs_mask.assign(D.n_node, 0u);
     for (int i = 0; i < D.n_node; ++i) {
       const nll_node_desc& nd = D.nodes[i];
@@ -138,7 +140,9 @@ struct Lowering {
         if (nd.kind == NLL_CHI2 && (D.obs_lo[nd.obs] < 0.0 || D.obs_hi[nd.obs] > 1000.0)) return NLL_ERR_UNSUPPORTED;
         obs_mask[i] = 1u << nd.obs;
       } else if (nd.kind == NLL_SUM || nd.kind == NLL_PROD) {
-        if (nd.kind == NLL_SUM && (nd.n_child < 2 || nd.n_param != nd.n_child - 1)) return NLL_ERR_ARG;
+        // a sum takes fractions f_1..f_{k-1} or yields nu_1..nu_k
+        if (nd.kind == NLL_SUM && (nd.n_child < 2 || (nd.n_param != nd.n_child - 1 && nd.n_param != nd.n_child)))
+          return NLL_ERR_ARG;
         if (nd.kind == NLL_PROD && (nd.n_child < 1 || nd.n_param != 0)) return NLL_ERR_ARG;
         unsigned acc = 0;
         for (int j = 0; j < nd.n_child; ++j) {
@@ -255,15 +259,58 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
     for (const Term& t : terms) all = all && ((t.mask >> l) & 1u);
     root[l] = all ? 1 : 0;
   }
+  // Flat structure: as many non-root leaves as terms, and each term holds
+  // exactly one of them (a sum of leaves, possibly times root factors).
+  // The kernels then take term k from the k-th non-root slot; otherwise the
+  // term masks decide.
+  int n_nonroot = 0;
+  for (int l = 0; l < L; ++l) n_nonroot += root[l] ? 0 : 1;
+  std::vector<int> term_of_leaf(L, -1);
+  bool flat_struct = K > 1 && n_nonroot == K;
+  for (int l = 0; l < L && flat_struct; ++l) {
+    if (root[l]) continue;
+    int count = 0;
+    for (int k = 0; k < K; ++k) {
+      int nr = 0;
+      for (int q = 0; q < L; ++q)
+        if (((terms[k].mask >> q) & 1u) && !root[q]) ++nr;
+      if (nr == 1 && ((terms[k].mask >> l) & 1u)) {
+        term_of_leaf[l] = k;
+        ++count;
+      }
+    }
+    flat_struct = count == 1;
+  }
+  const int need_flat = flat_struct ? 1 : 0;
   std::vector<int> perm;
   const VariantOps* found = nullptr;
   for (const VariantOps& v : registry()) {
-    if (match_variant(v, kind, obs, root, np, K, D.n_obs, D.precision, perm)) {
+    if (v.flat == need_flat && match_variant(v, kind, obs, root, np, K, D.n_obs, D.precision, perm)) {
       found = &v;
       break;
     }
   }
-  if (!found) return NLL_ERR_UNSUPPORTED;
+  if (!found) {
+    // any other shape: the same kernel templates compiled for it at run time
+    RtcShape shape;
+    shape.kind = kind;
+    shape.obs = obs;
+    shape.root = root;
+    shape.np = np;
+    shape.K = K;
+    shape.n_obs = D.n_obs;
+    shape.precision = D.precision;
+    shape.nonflat = K > 1 && n_nonroot == K && !flat_struct;
+    std::string log;
+    DeviceGuard guard(D.device);
+    found = rtc_variant(shape, D.device, &st, &log);
+    if (!found) {
+      if (!log.empty()) std::fprintf(stderr, "nllmi: run-time compilation failed:\n%s\n", log.c_str());
+      return st != NLL_OK ? st : NLL_ERR_DEVICE;
+    }
+    perm.resize(L);
+    for (int l = 0; l < L; ++l) perm[l] = l;
+  }
 
   std::memset(&pl, 0, sizeof(pl));
   pl.n_obs = D.n_obs;
@@ -290,27 +337,13 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
     pl.leaf_norm[s] = nd.norm;
     pl.leaf_root[s] = root[l];
   }
-  // Flat shapes (as many non-root leaves as terms): term k must be the one
-  // whose only non-root leaf sits in the k-th non-root slot.
-  int n_nonroot = 0;
-  for (int l = 0; l < L; ++l) n_nonroot += root[l] ? 0 : 1;
-  if (K > 1 && n_nonroot == K) {
+  // Flat shapes: term k is the one whose only non-root leaf sits in the
+  // k-th non-root slot.
+  if (flat_struct) {
     std::vector<Term> ordered;
     for (int sidx = 0; sidx < L; ++sidx) {
       const int l = perm[sidx];
-      if (root[l]) continue;
-      int found_k = -1, count = 0;
-      for (int k = 0; k < K; ++k) {
-        int nr = 0;
-        for (int q = 0; q < L; ++q)
-          if (((terms[k].mask >> q) & 1u) && !root[q]) ++nr;
-        if (nr == 1 && ((terms[k].mask >> l) & 1u)) {
-          found_k = k;
-          ++count;
-        }
-      }
-      if (count != 1) return NLL_ERR_UNSUPPORTED;
-      ordered.push_back(terms[found_k]);
+      if (!root[l]) ordered.push_back(terms[term_of_leaf[l]]);
     }
     terms.swap(ordered);
   }
@@ -330,7 +363,30 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
   for (int q = 0; q < pl.n_sum; ++q) {
     const nll_node_desc& nd = D.nodes[lw.sums[q]];
     pl.sum_nchild[q] = nd.n_child;
+    pl.sum_yields[q] = nd.n_param == nd.n_child ? 1 : 0;
     for (int j = 0; j < nd.n_param; ++j) pl.sum_param[q][j] = nd.param[j];
+  }
+  // the expected count of an extended model without a yield parameter: the
+  // root's sum of yields, or the one sum of yields among a root product's
+  // children
+  pl.ext_sum = -1;
+  if (D.extended && D.yield_param < 0) {
+    auto yields_pos = [&](int node) {
+      const nll_node_desc& nd = D.nodes[node];
+      return (nd.kind == NLL_SUM && nd.n_param == nd.n_child) ? lw.sum_pos[node] : -1;
+    };
+    const nll_node_desc& r = D.nodes[D.root];
+    int found_sum = yields_pos(D.root), count = found_sum >= 0 ? 1 : 0;
+    if (r.kind == NLL_PROD)
+      for (int j = 0; j < r.n_child; ++j) {
+        const int q = yields_pos(r.child[j]);
+        if (q >= 0) {
+          found_sum = q;
+          ++count;
+        }
+      }
+    if (count != 1) return NLL_ERR_ARG;
+    pl.ext_sum = found_sum;
   }
   pl.acc_term_base = 1;
   int base = 1 + (K > 1 ? K : 0);
@@ -340,7 +396,7 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
   }
   pl.n_acc = found->na_grad;
   pl.extended = D.extended ? 1 : 0;
-  pl.yield_param = D.extended ? D.yield_param : 0;
+  pl.yield_param = D.extended && D.yield_param >= 0 ? D.yield_param : 0;
   *ops_out = found;
   return NLL_OK;
 }
@@ -513,7 +569,7 @@ GDState gd_view(const GDState& g, int set, int P) {
 nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n_steps, double eta, double* nll_out,
                               double* grad_out, int32_t* status_out, bool bhhh = false) {
   GDState gd = gd_state(m);
-  hipError_t e = m->ops->fit_init(m->plan, theta, 1, eta, gd, m->consts, m->gl.x, m->gl.w, st);
+  hipError_t e = m->ops->fit_init(*m->ops, m->plan, theta, 1, eta, gd, m->consts, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   SingleArgs a = single_args(m, nullptr, nullptr, nullptr);
   a.gd = gd;
@@ -522,7 +578,7 @@ nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n
   const int cap = lds_cap(m, m->sched.blocks_per_cu);
   if (bhhh) {
     for (int s = 0; s < n_steps; ++s) {
-      e = m->ops->single_bhhh_fit(m->plan, a, m->sched.unroll, grid, cap, st, kernel_event(m, s, 0),
+      e = m->ops->single_bhhh_fit(*m->ops, m->plan, a, m->sched.unroll, grid, cap, st, kernel_event(m, s, 0),
                                   kernel_event(m, s, 1));
       if (e != hipSuccess) return NLL_ERR_DEVICE;
       record_step(m, s + 1, st);
@@ -542,7 +598,7 @@ nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n
     a.gd_out = gs[cur];
     a.consts = m->consts + (s > 0 ? prev : 0);
     a.consts_out = m->consts + cur;
-    e = step_fn(m->plan, a, m->sched.unroll, grid, cap, st, kernel_event(m, s, 0), kernel_event(m, s, 1));
+    e = step_fn(*m->ops, m->plan, a, m->sched.unroll, grid, cap, st, kernel_event(m, s, 0), kernel_event(m, s, 1));
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     if (s + 1 < n_steps) record_step(m, s + 1, st);  // the last step ends after its update
   }
@@ -556,7 +612,7 @@ nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n
     a.gd_out = gs[last];
     a.consts = m->consts + prev;
     a.consts_out = nullptr;
-    e = (m->weights ? m->ops->w_fit_finish : m->ops->fit_finish)(m->plan, a, grid, st);
+    e = (m->weights ? m->ops->w_fit_finish : m->ops->fit_finish)(*m->ops, m->plan, a, grid, st);
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     record_step(m, n_steps, st);
   }
@@ -572,11 +628,11 @@ nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* 
   a.gd = gd;
   hipError_t e = launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->items, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
-  e = m->ops->fit_init(m->plan, theta, n_sets, eta, gd, m->consts, m->gl.x, m->gl.w, st);
+  e = m->ops->fit_init(*m->ops, m->plan, theta, n_sets, eta, gd, m->consts, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   record_step(m, 0, st);
   for (int s = 0; s < n_steps; ++s) {
-    e = m->ops->sets(m->plan, a, true, true, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
+    e = m->ops->sets(*m->ops, m->plan, a, true, true, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
                      st, kernel_event(m, s, 0), kernel_event(m, s, 1));
     if (e != hipSuccess) return NLL_ERR_DEVICE;
     record_step(m, s + 1, st);
@@ -655,9 +711,9 @@ nll_status eval_batched_on(nll_model* m, int32_t n_sets, const int64_t* offsets,
   if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, s.tile_off, s.set_flag, s.items, m->stream) !=
       hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->consts(m->plan, theta, n_sets, s.consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
+  if (m->ops->consts(*m->ops, m->plan, theta, n_sets, s.consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->sets(m->plan, a, grad, false, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
+  if (m->ops->sets(*m->ops, m->plan, a, grad, false, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
                    m->stream, nullptr, nullptr) != hipSuccess)
     return NLL_ERR_DEVICE;
   return NLL_OK;
@@ -817,7 +873,7 @@ static nll_status nll_eval_impl(nll_model* m, const double* theta, double* nll_o
   DeviceGuard guard(m->device);
   SingleArgs a = single_args(m, theta, nll_out, grad_out);
   hipError_t e = (m->weights ? m->ops->single_w : m->ops->single)(
-      m->plan, a, grad, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), m->stream);
+      *m->ops, m->plan, a, grad, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu), m->stream);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
 
@@ -828,7 +884,7 @@ nll_status nll_eval_bhhh(nll_model* m, const double* theta, double* nll_out, dou
   DeviceGuard guard(m->device);
   SingleArgs a = single_args(m, theta, nll_out, grad_out);
   a.bhhh_out = bhhh_out;
-  hipError_t e = m->ops->single_bhhh(m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu),
+  hipError_t e = m->ops->single_bhhh(*m->ops, m->plan, a, m->sched.unroll, single_grid(m), lds_cap(m, m->sched.blocks_per_cu),
                                      m->stream);
   return e == hipSuccess ? NLL_OK : NLL_ERR_DEVICE;
 }
@@ -880,9 +936,9 @@ nll_status nll_eval_points(nll_model* m, int32_t n_points, const double* theta, 
   a.status_out = reinterpret_cast<int*>(status_out);
   if (launch_points(n_points, m->n, tile, m->pts_offsets, m->tile_off, m->set_flag, m->items, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->consts(m->plan, theta, n_points, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
+  if (m->ops->consts(*m->ops, m->plan, theta, n_points, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->sets(m->plan, a, grad_out != nullptr, false, m->sched.sets_unroll, sets_grid(m),
+  if (m->ops->sets(*m->ops, m->plan, a, grad_out != nullptr, false, m->sched.sets_unroll, sets_grid(m),
                    lds_cap(m, m->sched.sets_blocks_per_cu), m->stream, nullptr, nullptr) != hipSuccess)
     return NLL_ERR_DEVICE;
   return NLL_OK;
@@ -1025,6 +1081,14 @@ nll_status nll_step_times(nll_model* m, float* ms, int32_t cap, int32_t* n) {
   }
   *n = k;
   return NLL_OK;
+}
+
+nll_status nll_read_probe(const double* x, int64_t n, double* block_sums, int32_t n_blocks, void* stream) {
+  if (!x || !block_sums || n < 0 || n_blocks < 1 || n_blocks > (1 << 20)) return NLL_ERR_ARG;
+  if ((reinterpret_cast<uintptr_t>(x) & 15u) != 0) return NLL_ERR_ARG;
+  return launch_read_probe(x, n, block_sums, n_blocks, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? NLL_OK
+             : NLL_ERR_DEVICE;
 }
 
 nll_status nll_get_info(const nll_model* m, nll_info* out) {

@@ -17,35 +17,41 @@ struct VariantOps {
   int n_leaf, K, nobs, na_grad;
   int kind[kMaxLeaves], obs[kMaxLeaves], root[kMaxLeaves], np[kMaxLeaves];
   int precision;  // 0: FP64 event pass, 1: FP32-compensated
+  // 1: term k is the k-th non-root leaf (with the root factors), as the
+  // kernels then assume; 0: the plan's term masks define the terms
+  int flat;
+  // run-time compiled shapes: their module and kernels (null: compiled
+  // ahead of time); the launchers receive the variant itself
+  const void* rtc;
   // lds_cap > 0: LDS reserved per block of the streaming kernel (padded
   // with dynamic LDS), so that at most the intended number of blocks share
   // a CU and the persistent grid spreads evenly over the CUs
-  hipError_t (*single)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, int lds_cap, hipStream_t);
+  hipError_t (*single)(const VariantOps&, const Plan&, const SingleArgs&, bool grad, int unroll, int grid, int lds_cap, hipStream_t);
   // fit steps; ev0/ev1 (may be null) are recorded on the stream right before
   // and right after the streaming kernel of the step
-  hipError_t (*single_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
+  hipError_t (*single_fit)(const VariantOps&, const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
                            hipEvent_t ev0, hipEvent_t ev1);
-  hipError_t (*consts)(const Plan&, const double* theta, int n_sets, PerTheta* out, const double* glx,
+  hipError_t (*consts)(const VariantOps&, const Plan&, const double* theta, int n_sets, PerTheta* out, const double* glx,
                        const double* glw, hipStream_t);
-  hipError_t (*sets)(const Plan&, const SetsArgs&, bool grad, bool fit, int unroll, int grid, int lds_cap,
+  hipError_t (*sets)(const VariantOps&, const Plan&, const SetsArgs&, bool grad, bool fit, int unroll, int grid, int lds_cap,
                      hipStream_t, hipEvent_t ev0, hipEvent_t ev1);
-  hipError_t (*fit_init)(const Plan&, const double* theta, int n_sets, double eta, const GDState&,
+  hipError_t (*fit_init)(const VariantOps&, const Plan&, const double* theta, int n_sets, double eta, const GDState&,
                          PerTheta* consts, const double* glx, const double* glw, hipStream_t);
   // BHHH (FP64 shapes with few score features; null where not compiled):
   // NLL, gradient and BHHH matrix at one point, and damped BHHH fit steps
-  hipError_t (*single_bhhh)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t);
-  hipError_t (*single_bhhh_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
+  hipError_t (*single_bhhh)(const VariantOps&, const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t);
+  hipError_t (*single_bhhh_fit)(const VariantOps&, const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
                                 hipEvent_t ev0, hipEvent_t ev1);
   int bhhh_record;  // values per block record of the BHHH pass (0: not compiled)
   // weighted events (FP64 shapes; null where not compiled): as single and
   // single_fit, with the weights in SingleArgs::cols[nobs]
-  hipError_t (*single_w)(const Plan&, const SingleArgs&, bool grad, int unroll, int grid, int lds_cap, hipStream_t);
-  hipError_t (*single_w_fit)(const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
+  hipError_t (*single_w)(const VariantOps&, const Plan&, const SingleArgs&, bool grad, int unroll, int grid, int lds_cap, hipStream_t);
+  hipError_t (*single_w_fit)(const VariantOps&, const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
                              hipEvent_t ev0, hipEvent_t ev1);
   // after the last gradient-descent step: the update of the proposal it
   // evaluated (single_fit steps take the previous step's update themselves)
-  hipError_t (*fit_finish)(const Plan&, const SingleArgs&, int grid, hipStream_t);
-  hipError_t (*w_fit_finish)(const Plan&, const SingleArgs&, int grid, hipStream_t);
+  hipError_t (*fit_finish)(const VariantOps&, const Plan&, const SingleArgs&, int grid, hipStream_t);
+  hipError_t (*w_fit_finish)(const VariantOps&, const Plan&, const SingleArgs&, int grid, hipStream_t);
 };
 
 // registry: every variants_*.hip file appends its compiled shapes
@@ -67,6 +73,8 @@ hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_
 // partials in part (at most kWsumBlocks double-double pairs), then one block.
 constexpr int kWsumBlocks = 1024;
 hipError_t launch_wsum(const double* w, int64_t n, double* part, double* out, hipStream_t st);
+// read-bandwidth probe: n doubles (16-byte aligned) once, one sum per block into out[blocks]
+hipError_t launch_read_probe(const double* x, int64_t n, double* out, int blocks, hipStream_t st);
 hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, unsigned long long* bad,
                               hipStream_t st);
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
   }
   double nll = -((sum_l + cterms) + n * cn);
   if (pl.extended) {
-    const double nu = theta[pl.yield_param];
+    const double nu = expected_count(pl, theta);
     nll += nu - n * log(nu);
   }
   int status = 0;
@@ -119,7 +119,7 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
           }
         });
         acc = -acc;
-        if (pl.extended && q == pl.yield_param) acc += 1.0 - n / theta[q];
+        if (pl.extended && is_count_param(pl, q)) acc += 1.0 - n / expected_count(pl, theta);
       }
       g[q] = pl.par_free[q] ? acc : 0.0;
     }
@@ -258,7 +258,8 @@ __device__ __forceinline__ int mom_index(int i, int j) {
 //   A[q][NT+off+p]  = fscale_lp             (leaf l's local parameter p is q)
 //   c0[q]           = - sum_{root l, p -> q} d log Z_lp,
 // so B = N c0 c0^T + c0 (A m1)^T + (A m1) c0^T + A M2 A^T with m1 = sum v and
-// M2 = sum v v^T; plus N / nu^2 at (nu, nu) in an extended model.  Rows and
+// M2 = sum v v^T; plus N / nu^2 at every pair of the parameters that make
+// the expected count nu of an extended model.  Rows and
 // columns of fixed parameters, and everything after an invalid evaluation,
 // are 0.  Every entry is formed for (min, max) of its indices, so B is
 // exactly symmetric.  Ends with a barrier.
@@ -337,7 +338,10 @@ __device__ __forceinline__ void bhhh_assemble(const Plan& pl, const PerTheta& pt
         quad = fma(sA[q][i], row, quad);
       }
       b = ((dn * sc0[q]) * sc0[r] + sc0[q] * sAm1[r]) + (sAm1[q] * sc0[r] + quad);
-      if (pl.extended && q == pl.yield_param && r == q) b += dn / (theta[q] * theta[q]);
+      if (pl.extended && is_count_param(pl, q) && is_count_param(pl, r)) {
+        const double nu = expected_count(pl, theta);
+        b += dn / (nu * nu);
+      }
     }
     B[e] = b;
   }

@@ -71,7 +71,7 @@ struct Launch {
   }
   // one gradient-descent step (k_single_fit: the previous step's update,
   // then this step's pass)
-  static hipError_t single_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
+  static hipError_t single_fit(const VariantOps&, const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,
                                hipEvent_t ev0, hipEvent_t ev1) {
     const int u = pick_u(unroll);
     if constexpr (kU8) {
@@ -82,7 +82,7 @@ struct Launch {
     return hipGetLastError();
   }
   // the update of the last step's proposal (grid: that launch's blocks)
-  static hipError_t fit_finish(const Plan& pl, const SingleArgs& a, int grid, hipStream_t st) {
+  static hipError_t fit_finish(const VariantOps&, const Plan& pl, const SingleArgs& a, int grid, hipStream_t st) {
     hipLaunchKernelGGL((k_single_finish<M, true, true>), dim3(1), dim3(kFinishBlock), 0, st, pl, a, grid);
     return hipGetLastError();
   }
@@ -113,20 +113,20 @@ struct Launch {
       return hipErrorInvalidValue;
     }
   }
-  static hipError_t single_bhhh(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap,
+  static hipError_t single_bhhh(const VariantOps&, const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap,
                                 hipStream_t st) {
     return bh_t<false>(pl, a, unroll, grid, lds_cap, st, nullptr, nullptr);
   }
-  static hipError_t single_bhhh_fit(const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap,
+  static hipError_t single_bhhh_fit(const VariantOps&, const Plan& pl, const SingleArgs& a, int unroll, int grid, int lds_cap,
                                     hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     return bh_t<true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
   }
-  static hipError_t single(const Plan& pl, const SingleArgs& a, bool grad, int unroll, int grid, int lds_cap,
+  static hipError_t single(const VariantOps&, const Plan& pl, const SingleArgs& a, bool grad, int unroll, int grid, int lds_cap,
                            hipStream_t st) {
     return grad ? single_t<true, false>(pl, a, unroll, grid, lds_cap, st)
                 : single_t<false, false>(pl, a, unroll, grid, lds_cap, st);
   }
-  static hipError_t consts(const Plan& pl, const double* theta, int n_sets, PerTheta* out, const double* glx,
+  static hipError_t consts(const VariantOps&, const Plan& pl, const double* theta, int n_sets, PerTheta* out, const double* glx,
                            const double* glw, hipStream_t st) {
     hipLaunchKernelGGL((k_consts<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, out, glx, glw);
     return hipGetLastError();
@@ -151,7 +151,7 @@ struct Launch {
     if (u == 4) launch_sets<GRAD, 4>(pl, a, grid, lds_cap, st, ev0, ev1);
     if (u == 2) launch_sets<GRAD, 2>(pl, a, grid, lds_cap, st, ev0, ev1);
   }
-  static hipError_t sets(const Plan& pl, const SetsArgs& a, bool grad, bool fit, int unroll, int grid, int lds_cap,
+  static hipError_t sets(const VariantOps&, const Plan& pl, const SetsArgs& a, bool grad, bool fit, int unroll, int grid, int lds_cap,
                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     if (grad || fit) sets_u<true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
     else sets_u<false>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
@@ -163,7 +163,7 @@ struct Launch {
     else hipLaunchKernelGGL((k_sets_finish<M, false, false>), fg, dim3(kBlock), 0, st, pl, a);
     return hipGetLastError();
   }
-  static hipError_t fit_init(const Plan& pl, const double* theta, int n_sets, double eta, const GDState& gd,
+  static hipError_t fit_init(const VariantOps&, const Plan& pl, const double* theta, int n_sets, double eta, const GDState& gd,
                              PerTheta* consts, const double* glx, const double* glw, hipStream_t st) {
     hipLaunchKernelGGL((k_fit_init<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, eta, gd, consts,
                        glx, glw);
@@ -193,6 +193,8 @@ VariantOps make_ops(const char* name) {
   fill_slots<M>(v);
   v.na_grad = M::template NA<true>;  // accumulators per record (counters included)
   v.precision = M::PREC;
+  v.flat = M::FLAT ? 1 : 0;
+  v.rtc = nullptr;
   v.single = &Launch<M>::single;
   v.single_fit = &Launch<M>::single_fit;
   v.fit_finish = &Launch<M>::fit_finish;

@@ -118,6 +118,14 @@ struct Model {
   static_assert(NA_GRAD <= kMaxAcc, "accumulator budget");
 };
 
+// A shape with as many non-root leaves as terms whose terms are not one
+// non-root leaf each (a product of two sums: (a + b)(c + d) has four terms
+// of two non-root leaves): the plan's term masks define the terms.
+template <class B>
+struct NonFlat : B {
+  static constexpr bool FLAT = false;
+};
+
 // The same compiled shape with the FP32-compensated event pass.  Its sums
 // gain K - 1 counters: how many events have term k (k >= 1) as the largest
 // one, so that the constant ck_k - ck_0 of that term is added count_k times

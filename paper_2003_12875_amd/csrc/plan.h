@@ -22,7 +22,7 @@ namespace nllmi {
 
 constexpr int kMaxObs = 4;
 constexpr int kMaxParams = 32;
-constexpr int kMaxLeaves = 6;
+constexpr int kMaxLeaves = 8;
 constexpr int kMaxTerms = 8;
 constexpr int kMaxLeafParams = 8;
 constexpr int kLeafConsts = 12;     // per-event constants of one leaf
@@ -60,15 +60,18 @@ struct Plan {
 
   int32_t n_sum;
   int32_t sum_nchild[kMaxSums];
-  int32_t sum_param[kMaxSums][kMaxSumChildren];     // fraction params f_1..f_{k-1}
+  int32_t sum_param[kMaxSums][kMaxSumChildren];     // fractions f_1..f_{k-1}, or yields nu_1..nu_k
+  int32_t sum_yields[kMaxSums];                     // 1: the sum's coefficients are yields
 
   int32_t n_acc;                     // accumulators per event stream
   int32_t acc_leaf_base[kMaxLeaves]; // first gradient accumulator of leaf l
   int32_t acc_term_base;             // first term-responsibility accumulator
 
   int32_t extended;                  // Poisson yield term nu - N ln nu
-  int32_t yield_param;
+  int32_t yield_param;               // nu: this parameter, or (-1) the sum of ...
+  int32_t ext_sum;                   // ... the yields of this sum (-1: none)
   int32_t want_grad;
+  int32_t pad_;
 };
 
 // Per-parameter-point constants (device memory / LDS).

@@ -98,6 +98,22 @@ __device__ inline void gl_node(const double* p, int norm, double lo, double hi, 
   }
 }
 
+// Expected event count of an extended model: one parameter, or the sum of
+// the yields of the root's sum of yields.
+__device__ inline double expected_count(const Plan& pl, const double* theta) {
+  if (pl.ext_sum < 0) return theta[pl.yield_param];
+  double nu = 0.0;
+  for (int j = 0; j < pl.sum_nchild[pl.ext_sum]; ++j) nu += theta[pl.sum_param[pl.ext_sum][j]];
+  return nu;
+}
+// parameter q enters the expected event count
+__device__ inline bool is_count_param(const Plan& pl, int q) {
+  if (pl.ext_sum < 0) return q == pl.yield_param;
+  bool in = false;
+  for (int j = 0; j < pl.sum_nchild[pl.ext_sum]; ++j) in = in || pl.sum_param[pl.ext_sum][j] == q;
+  return in;
+}
+
 // Copies of the plan and of a parameter vector into LDS, so that the
 // prologue's lane-varying and chained look-ups (parameter ranges, leaf
 // parameter indices, sum coefficients) cost one parallel load instead of a
@@ -131,7 +147,10 @@ template <class M, int NT = kBlock>
 __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* theta, const double* __restrict__ glx,
                                  const double* __restrict__ glw, PerTheta* pt, double* lds) {
   static_assert(NT >= kGLNodes && NT % 64 == 0, "at least one thread per quadrature node");
-  static_assert(M::L <= 6 && NT >= 256, "leaf lane groups at lanes 0 and 32 of waves 0..3, checks on 16..31, 48..63");
+  // lanes: leaf l at 64 (l % 4) + 32 (l / 4) (up to 16 each), parameter
+  // checks at 144..159 and 176..191, sum checks at 80..84, term weights at
+  // 208..215 -- disjoint for up to 8 leaves
+  static_assert(M::L <= 8 && NT >= 256, "leaf lane groups at lanes 0 and 32 of waves 0..3");
   static_assert(kMaxParams <= 32 && kMaxSums + 1 <= 16 && kMaxTerms <= 16, "check and weight lanes");
   const int tid = threadIdx.x;
   __shared__ int s_bad;
@@ -229,7 +248,8 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
   // (2b) checks (Sec. 3) on lanes no leaf uses (leaf groups start at lanes 0
   // and 32 of each wave): parameter ranges, one lane per parameter, on
   // lanes 16..31 and 48..63 of wave 2; sum fractions in [0, 1] with a sum
-  // <= 1, one lane per sum node, and a positive yield, on lanes 16..20 of wave 1
+  // <= 1 (or yields >= 0 with a positive finite total), one lane per sum
+  // node, and a positive expected count, on lanes 16..20 of wave 1
   if ((tid >= 144 && tid < 160) || (tid >= 176 && tid < 192)) {
     const int q = tid < 160 ? tid - 144 : tid - 176 + 16;
     if (q < pl.n_param) {
@@ -241,28 +261,51 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
     if (qs < pl.n_sum) {
       double f = 0.0;
       bool ok = true;
-      for (int j = 0; j < pl.sum_nchild[qs] - 1; ++j) {
-        const double v = theta[pl.sum_param[qs][j]];
-        ok = ok && v >= 0.0 && v <= 1.0;
-        f += v;
+      if (pl.sum_yields[qs]) {
+        for (int j = 0; j < pl.sum_nchild[qs]; ++j) {
+          const double v = theta[pl.sum_param[qs][j]];
+          ok = ok && v >= 0.0;
+          f += v;
+        }
+        ok = ok && f > 0.0 && __builtin_isfinite(f);
+      } else {
+        for (int j = 0; j < pl.sum_nchild[qs] - 1; ++j) {
+          const double v = theta[pl.sum_param[qs][j]];
+          ok = ok && v >= 0.0 && v <= 1.0;
+          f += v;
+        }
+        ok = ok && f <= 1.0;
       }
-      if (!ok || !(f <= 1.0)) atomicOr(&s_bad, 1);
+      if (!ok) atomicOr(&s_bad, 1);
     }
   } else if (tid == 80 + kMaxSums) {
-    if (pl.extended && !(theta[pl.yield_param] > 0.0)) atomicOr(&s_bad, 1);
+    if (pl.extended && !(expected_count(pl, theta) > 0.0)) atomicOr(&s_bad, 1);
   }
 
   // (2c) term weights, one lane per term on wave 3 lanes 16..23: log w_k and
-  // d log w_k / d theta over the fraction parameters of every sum on the
-  // path.  Coefficients are floored at 1e-200 so that a fraction at exactly
-  // 0 or 1 keeps a finite log and a finite d/df (the floored term then
-  // carries a weight of 1e-200, i.e. nothing, in the likelihood).
+  // d log w_k / d theta over the coefficient parameters of every sum on the
+  // path: a fraction f_j (the last child 1 - sum f), or a yield's share
+  // nu_j / S with S = sum nu (d log / d nu_i = [i = j] / nu_j - 1 / S).
+  // Coefficients (yields) are floored at 1e-200 so that one at exactly 0
+  // (or a last fraction at 0) keeps a finite log and derivative (the
+  // floored term then carries a weight of 1e-200, i.e. nothing, in the
+  // likelihood).
   if (tid >= 208 && tid < 208 + M::K) {
     const int k = tid - 208;
     double lw = 0.0;
     for (int r = 0; r < pl.term_nref[k]; ++r) {
       const int q = pl.term_ref_sum[k][r], j = pl.term_ref_child[k][r];
       const int nc = pl.sum_nchild[q];
+      if (pl.sum_yields[q]) {
+        double S = 0.0;
+        for (int i = 0; i < nc; ++i) S += theta[pl.sum_param[q][i]];
+        const double cf = fmax(theta[pl.sum_param[q][j]], 1e-200);
+        lw += log_pos(cf) - log_pos(S);
+        pt->dlogw[k][pl.sum_param[q][j]] += 1.0 / cf;
+        const double is = 1.0 / S;
+        for (int i = 0; i < nc; ++i) pt->dlogw[k][pl.sum_param[q][i]] -= is;
+        continue;
+      }
       double f = 0.0;
       for (int i = 0; i < nc - 1; ++i) f += theta[pl.sum_param[q][i]];
       const double c = (j < nc - 1) ? theta[pl.sum_param[q][j]] : 1.0 - f;
