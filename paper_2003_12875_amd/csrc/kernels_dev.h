@@ -621,11 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
     block_sum_vals<NV, kBlock>(v, red, tot);
   }
   if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
-  if (!FIT && blockIdx.x == 0) {
-    const double* src = reinterpret_cast<const double*>(&pt);
-    double* dst = reinterpret_cast<double*>(a.pt_out);
-    for (int i = threadIdx.x; i < (int)(sizeof(PerTheta) / sizeof(double)); i += kBlock) dst[i] = src[i];
-  }
+  if (!FIT && blockIdx.x == 0) copy_pertheta<M, kBlock>(a.pt_out, &pt, pl.n_param);
 }
 
 // Finishing kernel (one block of kFinishBlock threads): the block partials
@@ -637,8 +633,6 @@ template <class M, bool GRAD, bool FIT = false, bool BH = false>
 __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, const SingleArgs a, int n_blocks) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1 + (BH ? AccBhhh<M>::NM : 0);
-  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
-  static_assert(PT8 <= kFinishBlock, "one constant per thread");
   __shared__ Plan spl;
   __shared__ DD tot[NV];
   __shared__ double s_grad[kMaxParams];
@@ -649,7 +643,8 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
   __shared__ double small[(kFinishBlock / 64) * (kMaxLeafParams + 1)];
   const int t = threadIdx.x;
   stage_plan<kFinishBlock>(pl, &spl);
-  const double ptv = t < PT8 ? reinterpret_cast<const double*>(FIT ? a.consts : a.pt_out)[t] : 0.0;
+  PtRegs<M, kFinishBlock> ptv;
+  ptv.load(FIT ? a.consts : a.pt_out, pl.n_param);
   stage_theta(FIT ? a.gd.th_prop : a.theta, pl.n_param, s_theta);
   GDPre pre{};
   if constexpr (FIT) pre = gd_preload(a.gd, 0, pl.n_param);
@@ -664,7 +659,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
   // the gradient-descent steps (k_single_fit) store their records value-major
   std::conditional_t<FIT && !BH, RecordSumT<NV, kFinishBlock>, RecordSum<NV, kFinishBlock>> rs;
   rs.issue(reinterpret_cast<const DD*>(a.partials), n_blocks);
-  if (t < PT8) reinterpret_cast<double*>(&spt)[t] = ptv;
+  ptv.store(&spt, pl.n_param);
   rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
   finish_block<M, GRAD>(spl, spt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
   __shared__ double s_B[BH ? kMaxParams * kMaxParams : 1];
@@ -679,7 +674,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
     // the next proposal's constants, built in LDS (its phases read back
     // what other threads wrote) and stored with one parallel copy
     compute_pertheta<M, kFinishBlock>(spl, s_theta, a.glx, a.glw, &spt, small);
-    if (t < PT8) reinterpret_cast<double*>(a.consts)[t] = reinterpret_cast<const double*>(&spt)[t];
+    copy_pertheta<M, kFinishBlock>(a.consts, &spt, spl.n_param);
   } else {
     if (t == 0) {
       *a.nll_out = s_nll;
@@ -711,8 +706,6 @@ template <class M, int U>
 __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const SingleArgs a) {
   constexpr int NA = M::template NA<true>;
   constexpr int NV = NA + 1;  // + invalid-event count
-  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
-  constexpr int PTL = (PT8 + kBlock - 1) / kBlock;  // constants per thread
   using CT = typename Pass<M, true>::C;
   __shared__ Plan spl;
   __shared__ double s_theta[kMaxParams];
@@ -731,7 +724,7 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
   // state and the previous proposal's constants and records, then the
   // first event tiles
   GDPre pre{};
-  double ptv[PTL];
+  PtRegs<M, kBlock> ptv;
   double neff = (double)a.n;
   RecordSumT<NV, kBlock, 16> rs;
   if (!first) {
@@ -739,11 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
     stage_theta(a.gd.th_prop, pl.n_param, s_theta);
     pre = gd_preload(a.gd, 0, pl.n_param);
     if constexpr (M::WEIGHTED) neff = *a.wsum;
-#pragma unroll
-    for (int i = 0; i < PTL; ++i) {
-      const int e = t + i * kBlock;
-      ptv[i] = e < PT8 ? reinterpret_cast<const double*>(a.consts)[e] : 0.0;
-    }
+    ptv.load(a.consts, pl.n_param);
     rs.issue(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x);
   }
   const double* cols[M::NOBS];
@@ -764,19 +753,13 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
     C.load(*a.consts, pl);
     bad = uniform(a.consts->bad);
   } else {
-#pragma unroll
-    for (int i = 0; i < PTL; ++i) {
-      const int e = t + i * kBlock;
-      if (e < PT8) reinterpret_cast<double*>(&pt)[e] = ptv[i];
-    }
+    ptv.store(&pt, pl.n_param);
     rs.reduce(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x, tot);  // ends with a barrier
     finish_block<M, true>(spl, pt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
     const double next = gd_update_to(spl, a.gd_out, s_st, s_nll, s_grad, neff, pre, blockIdx.x == 0);
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
     compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
-    if (blockIdx.x == 0)
-      for (int e = t; e < PT8; e += kBlock)
-        reinterpret_cast<double*>(a.consts_out)[e] = reinterpret_cast<const double*>(&pt)[e];
+    if (blockIdx.x == 0) copy_pertheta<M, kBlock>(a.consts_out, &pt, spl.n_param);
     C.load(pt, pl);
     bad = uniform(pt.bad);
   }
@@ -815,8 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_consts(const Plan pl, const double* 
   stage_plan<kBlock>(pl, &spl);
   stage_theta(theta + (size_t)s * pl.n_param, pl.n_param, s_theta);
   compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
-  for (int e = threadIdx.x; e < (int)(sizeof(PerTheta) / sizeof(double)); e += kBlock)
-    reinterpret_cast<double*>(&out[s])[e] = reinterpret_cast<const double*>(&spt)[e];
+  copy_pertheta<M, kBlock>(&out[s], &spt, spl.n_param);
 }
 
 template <class M, bool GRAD, int U>
@@ -878,7 +860,6 @@ template <class M, bool GRAD, bool FIT>
 __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const SetsArgs a) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
-  constexpr int PT8 = sizeof(PerTheta) / sizeof(double);
   __shared__ Plan spl;
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
@@ -894,12 +875,8 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   // every independent load at once: plan, constants, parameters, fit
   // state, offsets and the first batch of partial records
   stage_plan<kBlock>(pl, &spl);
-  double ptv[(PT8 + kBlock - 1) / kBlock];
-#pragma unroll
-  for (int i = 0; i < (PT8 + kBlock - 1) / kBlock; ++i) {
-    const int e = t + i * kBlock;
-    ptv[i] = e < PT8 ? reinterpret_cast<const double*>(&a.consts[s])[e] : 0.0;
-  }
+  PtRegs<M, kBlock> ptv;
+  ptv.load(&a.consts[s], P);
   stage_theta(FIT ? a.gd.th_prop + (size_t)s * P : a.theta + (size_t)s * P, P, s_theta);
   GDPre pre{};
   if constexpr (FIT) pre = gd_preload(a.gd, s, P);
@@ -909,11 +886,7 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   const DD* recs = reinterpret_cast<const DD*>(a.partials) + (size_t)first * NV;
   RecordSum<NV, kBlock> rs;
   rs.issue(recs, n_items);
-#pragma unroll
-  for (int i = 0; i < (PT8 + kBlock - 1) / kBlock; ++i) {
-    const int e = t + i * kBlock;
-    if (e < PT8) reinterpret_cast<double*>(&spt)[e] = ptv[i];
-  }
+  ptv.store(&spt, P);
   rs.reduce(recs, n_items, tot);  // ends with a barrier
   const int64_t n_s = flag ? 0 : o1 - o0;
   finish_block<M, GRAD>(spl, spt, tot, n_s, s_theta, flag != 0, &s_nll, &s_st, s_grad);
@@ -927,8 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
     const double next = gd_update(spl, a.gd, s, s_st, s_nll, s_grad, n_s, pre);
     if (t < P) s_theta[t] = next;  // compute_pertheta starts with a barrier
     compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &spt, small);
-    for (int e = t; e < PT8; e += kBlock)
-      reinterpret_cast<double*>(&a.consts[s])[e] = reinterpret_cast<const double*>(&spt)[e];
+    copy_pertheta<M, kBlock>(&a.consts[s], &spt, P);
   }
 }
 
@@ -961,8 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double
   if (gd.b_acc)
     for (int e = threadIdx.x; e < P * P; e += kBlock) gd.b_acc[(size_t)s * P * P + e] = 0.0;
   compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
-  for (int e = threadIdx.x; e < (int)(sizeof(PerTheta) / sizeof(double)); e += kBlock)
-    reinterpret_cast<double*>(&consts[s])[e] = reinterpret_cast<const double*>(&spt)[e];
+  copy_pertheta<M, kBlock>(&consts[s], &spt, P);
 }
 
 // BHHH pass compiled: FP64 unweighted shapes with at most 6 score features

@@ -114,6 +114,89 @@ __device__ inline bool is_count_param(const Plan& pl, int q) {
   return in;
 }
 
+// The words of PerTheta that a model of shape M reads once the prologue
+// has written them: its leaves' rows (event constants, feature scales,
+// d log Z, log Z; the FP32 pass's feature offsets), its terms' constants
+// and d log w rows over the parameters, and the status word.  Kernels pass
+// only these between launches (a one-leaf model's are ~0.5 KB of the
+// 4.5 KB block), so per-set constant traffic follows the model's size.
+template <class M>
+struct PtWords {
+  static constexpr int L = M::L, K = M::K;
+  static constexpr int kEc = (int)(__builtin_offsetof(PerTheta, ec) / 8);
+  static constexpr int kFs = (int)(__builtin_offsetof(PerTheta, fscale) / 8);
+  static constexpr int kDz = (int)(__builtin_offsetof(PerTheta, dlogz) / 8);
+  static constexpr int kLz = (int)(__builtin_offsetof(PerTheta, logz) / 8);
+  static constexpr int kCk = (int)(__builtin_offsetof(PerTheta, ck) / 8);
+  static constexpr int kCr = (int)(__builtin_offsetof(PerTheta, croot) / 8);
+  static constexpr int kDw = (int)(__builtin_offsetof(PerTheta, dlogw) / 8);
+  static constexpr int kPo = (int)(__builtin_offsetof(PerTheta, phioff) / 8);
+  static constexpr int kBad = (int)(__builtin_offsetof(PerTheta, bad) / 8);
+  static constexpr int kFixed = L * (kLeafConsts + 2 * kMaxLeafParams + 1) + K + 1 +
+                                (M::PREC == 1 ? L * kMaxLeafParams : 0) + 1;
+  static constexpr int kMax = kFixed + K * kMaxParams;
+  static_assert(sizeof(PerTheta) % 8 == 0 && __builtin_offsetof(PerTheta, bad) % 8 == 0, "8-byte words");
+  __device__ static int count(int P) { return kFixed + K * P; }
+  // offset (in 8-byte words) of the i-th word, i < count(P)
+  __device__ static int word(int i, int P) {
+    if (i < L * kLeafConsts) return kEc + i;
+    i -= L * kLeafConsts;
+    if (i < L * kMaxLeafParams) return kFs + i;
+    i -= L * kMaxLeafParams;
+    if (i < L * kMaxLeafParams) return kDz + i;
+    i -= L * kMaxLeafParams;
+    if (i < L) return kLz + i;
+    i -= L;
+    if (i < K) return kCk + i;
+    i -= K;
+    if (i == 0) return kCr;
+    i -= 1;
+    if (i == 0) return kBad;
+    i -= 1;
+    if constexpr (M::PREC == 1) {
+      if (i < L * kMaxLeafParams) return kPo + i;
+      i -= L * kMaxLeafParams;
+    }
+    return kDw + (i / P) * kMaxParams + i % P;  // d log w rows, P words each
+  }
+};
+
+// Copy the words M reads from src to dst with NT threads (no barrier).
+template <class M, int NT>
+__device__ inline void copy_pertheta(PerTheta* dst, const PerTheta* src, int P) {
+  using W = PtWords<M>;
+  const double* s = reinterpret_cast<const double*>(src);
+  double* d = reinterpret_cast<double*>(dst);
+  for (int i = threadIdx.x; i < W::count(P); i += NT) {
+    const int o = W::word(i, P);
+    d[o] = s[o];
+  }
+}
+
+// The same copy through registers: load() issues this thread's loads (so
+// that they can overlap other work), store() writes them.
+template <class M, int NT>
+struct PtRegs {
+  static constexpr int N = (PtWords<M>::kMax + NT - 1) / NT;
+  double v[N];
+  __device__ void load(const PerTheta* src, int P) {
+    const double* s = reinterpret_cast<const double*>(src);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int i = threadIdx.x + j * NT;
+      v[j] = i < PtWords<M>::count(P) ? s[PtWords<M>::word(i, P)] : 0.0;
+    }
+  }
+  __device__ void store(PerTheta* dst, int P) const {
+    double* d = reinterpret_cast<double*>(dst);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int i = threadIdx.x + j * NT;
+      if (i < PtWords<M>::count(P)) d[PtWords<M>::word(i, P)] = v[j];
+    }
+  }
+};
+
 // Copies of the plan and of a parameter vector into LDS, so that the
 // prologue's lane-varying and chained look-ups (parameter ranges, leaf
 // parameter indices, sum coefficients) cost one parallel load instead of a
