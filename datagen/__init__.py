@@ -32,7 +32,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdatagen.so")
 
 MASTER_SEED = 2003012875
-KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9}
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9,
+        "hypatia": 10}
 
 
 def build() -> str:
@@ -45,7 +46,7 @@ def build() -> str:
 
 class DgNode(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("obs", ctypes.c_int32), ("n_param", ctypes.c_int32),
-                ("p", ctypes.c_double * 8), ("n_child", ctypes.c_int32), ("child", ctypes.c_int32 * 8)]
+                ("p", ctypes.c_double * 12), ("n_child", ctypes.c_int32), ("child", ctypes.c_int32 * 8)]
 
 
 class DgModel(ctypes.Structure):

@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
+#include <map>
 #include <cstdint>
 #include <thread>
 #include <vector>
@@ -86,10 +88,10 @@ struct EventRng {
 extern "C" {
 
 typedef struct dg_node {
-  int32_t kind; /* 1 gauss, 2 exp, 3 cheb, 4 cb, 5 argus, 6 sum, 7 prod, 8 johnson, 9 chi2 */
+  int32_t kind; /* 1 gauss, 2 exp, 3 cheb, 4 cb, 5 argus, 6 sum, 7 prod, 8 johnson, 9 chi2, 10 hypatia */
   int32_t obs;
   int32_t n_param;
-  double p[8]; /* parameter VALUES (truth) */
+  double p[12]; /* parameter VALUES (truth) */
   int32_t n_child;
   int32_t child[8];
 } dg_node;
@@ -211,6 +213,93 @@ double accept_reject(EventRng& r, double lo, double hi, double M, F&& shape) {
   return std::nan("");
 }
 
+
+/* Hypatia2 for sampling: its log-density on 16384 cells of the range,
+ * events drawn exactly from the piecewise log-linear interpolant of it (a
+ * cell by its mass, then the inverse distribution function of the
+ * exponential segment inside the cell).  The density: with d = x - mu,
+ * nu = lambda - 1/2, delta^2 = sigma^2 zeta K_lambda(zeta)/K_{lambda+1}(zeta),
+ * alpha = zeta/delta, the core r^nu e^{beta d} K_nu(alpha r), r^2 = d^2 +
+ * delta^2, between -a_l sigma and a_r sigma, continued on each side by a
+ * power law with the core's value and slope there.  K_nu from its integral
+ * over exp(-z cosh t) cosh(nu t) by the trapezoidal rule. */
+double dg_log_k(double nu, double z) {
+  const double h = std::min(1.0 / 16.0, 0.25 / std::sqrt(z));
+  double sum = 0.5;
+  for (int j = 1; j < 100000; ++j) {
+    const double t = j * h;
+    const double term = std::exp(-z * (std::cosh(t) - 1.0)) * std::cosh(nu * t);
+    sum += term;
+    if (term < 1e-17 * sum && t > 1.0) break;
+  }
+  return std::log(h * sum) - z;
+}
+
+struct HypTable {
+  std::vector<double> cum;  /* cumulative mass at the cell ends */
+  std::vector<double> lg;   /* log-density at the cell edges */
+  double lo, h;
+};
+
+const HypTable& hyp_table(const dg_node& nd, double lo, double hi) {
+  static std::mutex mu;
+  static std::map<std::vector<double>, HypTable> cache;
+  std::vector<double> key(nd.p, nd.p + 9);
+  key.push_back(lo);
+  key.push_back(hi);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const double m0 = nd.p[0], sg = nd.p[1], la = nd.p[2], ze = nd.p[3], be = nd.p[4];
+  const double al = nd.p[5], nl = nd.p[6], ar = nd.p[7], nr = nd.p[8];
+  const double nu = la - 0.5;
+  const double d2 = sg * sg * ze * std::exp(dg_log_k(la, ze) - dg_log_k(la + 1.0, ze));
+  const double alpha = ze / std::sqrt(d2);
+  auto core = [&](double d) {
+    const double r2 = d * d + d2;
+    return 0.5 * nu * std::log(r2) + be * d + dg_log_k(nu, alpha * std::sqrt(r2));
+  };
+  const double dl = -al * sg, dh = ar * sg, e = 1e-6 * sg;
+  const double Gl = core(dl), sl = (core(dl + e) - core(dl - e)) / (2 * e);
+  const double Gh = core(dh), sh = (core(dh + e) - core(dh - e)) / (2 * e);
+  auto logg = [&](double d) {
+    if (d < dl) return Gl - nl * std::log(1.0 + sl * (dl - d) / nl);
+    if (d > dh) return Gh - nr * std::log(1.0 - sh * (d - dh) / nr);
+    return core(d);
+  };
+  const int cells = 16384;
+  HypTable t;
+  t.lo = lo;
+  t.h = (hi - lo) / cells;
+  t.lg.resize(cells + 1);
+  double top = -1e300;
+  for (int i = 0; i <= cells; ++i) {
+    t.lg[i] = logg(lo + i * t.h - m0);
+    top = std::max(top, t.lg[i]);
+  }
+  t.cum.resize(cells);
+  double acc = 0.0;
+  for (int i = 0; i < cells; ++i) {
+    const double a = t.lg[i] - top, c = t.lg[i + 1] - t.lg[i];
+    const double w = std::fabs(c) > 1e-9 ? std::expm1(c) / c : 1.0 + 0.5 * c;
+    acc += t.h * std::exp(a) * w;
+    t.cum[i] = acc;
+  }
+  return cache.emplace(key, std::move(t)).first->second;
+}
+
+double sample_hypatia(EventRng& r, const dg_node& nd, double lo, double hi) {
+  const HypTable& t = hyp_table(nd, lo, hi);
+  const double u = r.u01() * t.cum.back();
+  const int i = (int)(std::upper_bound(t.cum.begin(), t.cum.end(), u) - t.cum.begin());
+  if (i >= (int)t.cum.size()) return hi;
+  const double prev = i > 0 ? t.cum[i - 1] : 0.0;
+  const double v = (u - prev) / (t.cum[i] - prev);  /* position of u within the cell's mass */
+  const double c = t.lg[i + 1] - t.lg[i];
+  const double s = std::fabs(c) > 1e-9 ? std::log1p(v * std::expm1(c)) / c : v;
+  return std::min(hi, std::max(lo, t.lo + (i + s) * t.h));
+}
+
 void sample_node(const dg_model& m, int i, EventRng& r, double* x) {
   const dg_node& nd = m.node[i];
   double lo = (nd.obs >= 0) ? m.lo[nd.obs] : 0.0, hi = (nd.obs >= 0) ? m.hi[nd.obs] : 0.0;
@@ -258,6 +347,9 @@ void sample_node(const dg_model& m, int i, EventRng& r, double* x) {
       return;
     case 9:
       x[nd.obs] = sample_chi2(r, nd.p[0], lo, hi);
+      return;
+    case 10:
+      x[nd.obs] = sample_hypatia(r, nd, lo, hi);
       return;
   }
 }

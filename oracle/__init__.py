@@ -25,9 +25,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-MAX_OBS, MAX_PAR, MAX_NODE, NODE_PAR, NODE_CHILD = 4, 32, 16, 8, 8
+MAX_OBS, MAX_PAR, MAX_NODE, NODE_PAR, NODE_CHILD = 4, 32, 16, 12, 8
 
-KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9}
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9,
+        "hypatia": 10}
 NORM = {"analytic": 0, "gl256": 1, "gl256_single": 2}
 
 OK, E_ARG, E_UNSUPPORTED, E_PARAM, E_DOMAIN, E_PDF = 0, -1, -2, -3, -4, -5
@@ -85,6 +86,8 @@ def lib():
         L.orc_bhhh_fit.argtypes = [pm, ppd, i64, pd, i32, d, i32, pd, pd, pd, pd]
         L.orc_gd_fit_batched.argtypes = [pm, ppd, P(i64), i32, pd, i32, d, i32, pd, pd, P(i32)]
         L.orc_gl_rule.argtypes = [i32, pd, pd]
+        L.orc_log_bessel_k.argtypes = [d, d, pd]
+        L.orc_log_bessel_k.restype = ctypes.c_int
         for f in ("orc_check_model", "orc_leaf_norm", "orc_log_density", "orc_nll",
                   "orc_nll_batched", "orc_gd_fit", "orc_gd_fit_accept", "orc_gd_fit_batched", "orc_gl_rule"):
             getattr(L, f).restype = ctypes.c_int
@@ -261,6 +264,13 @@ class Oracle:
                                       n_sets, _dptr(th), n_steps, eta, threads, _dptr(nll), _dptr(g),
                                       status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         return st, th, nll, g, status
+
+
+def log_bessel_k(nu: float, z: float) -> float:
+    out = ctypes.c_double()
+    if lib().orc_log_bessel_k(ctypes.c_double(nu), ctypes.c_double(z), ctypes.byref(out)) != OK:
+        raise ValueError("z must be positive")
+    return out.value
 
 
 def gl_rule(n: int):

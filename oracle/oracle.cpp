@@ -21,6 +21,7 @@
 #include <atomic>
 #include <cfloat>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <limits>
 #include <thread>
@@ -224,6 +225,227 @@ double g_chi2(const orc_node& nd, const double* th, double x, double* dg) {
   return g;
 }
 
+/* Hypatia2 (the two-sided Hypatia of Santos and Dupertuis, NIM A 764
+ * (2014) 150, among the densities Sec. 3 adds to RooFit): a generalised
+ * hyperbolic core of width sigma with power-law tails on both sides that
+ * continue it with equal value and slope.  Parameters (mu, sigma, lambda,
+ * zeta, beta, a_l, n_l, a_r, n_r); with d = x - mu, nu = lambda - 1/2,
+ *   A^2 = zeta K_lambda(zeta) / K_{lambda+1}(zeta),  delta^2 = A^2 sigma^2,
+ *   alpha = zeta / delta,  r = sqrt(d^2 + delta^2),
+ *   core  G(d) = r^nu e^{beta d} K_nu(alpha r)          for -a_l sigma <= d <= a_r sigma,
+ *   low   G_l (1 + s_l (d_l - d) / n_l)^{-n_l}           for d < d_l = -a_l sigma,
+ *   high  G_h (1 - s_h (d - d_h) / n_r)^{-n_r}           for d > d_h = a_r sigma,
+ * with G_l = G(d_l), s_l = G'(d_l)/G(d_l) > 0, G_h, s_h < 0 likewise.
+ * K_nu is the modified Bessel function of the second kind, evaluated from
+ * its integral K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt by the
+ * trapezoidal rule (exponentially convergent for this analytic, doubly
+ * exponentially decaying integrand).  Everything is templated on the
+ * number type so that derivatives come from complex steps: for an analytic
+ * f, f'(x) = Im f(x + i h) / h to rounding, with h tiny.                  */
+using cplx = std::complex<double>;
+
+inline double re(double v) { return v; }
+inline double re(const cplx& v) { return v.real(); }
+inline double mag(double v) { return std::fabs(v); }
+inline double mag(const cplx& v) { return std::abs(v); }
+
+/* log K_nu(z), z > 0 (Re), from e^z K_nu(z) = int exp(-z (cosh t - 1)) cosh(nu t) dt. */
+template <class T>
+T log_bessel_k(T nu, T z) {
+  const double zr = re(z);
+  const double h = std::min(1.0 / 16.0, 0.25 / std::sqrt(zr));
+  T sum = 0.5;  /* t = 0 */
+  double prev = 1e300;
+  for (int j = 1; j < 200000; ++j) {
+    const double t = j * h;
+    const T term = std::exp(-z * (std::cosh(t) - 1.0)) * std::cosh(nu * t);
+    sum += term;
+    const double a = mag(term);
+    if (a < 1e-19 * mag(sum) && a <= prev) break;
+    prev = a;
+  }
+  return std::log(h * sum) - z;
+}
+
+template <class T>
+struct HypConst {
+  T mu, nu, beta, delta2, alpha, dl, dh;
+  T lGl, sl, nl, lGh, sh, nr;  /* junction values, log-slopes, exponents */
+  bool ok;
+};
+
+/* log G and d log G / dd of the core at d */
+template <class T>
+void hyp_core(const HypConst<T>& c, T d, T* lg, T* slope) {
+  const T r2 = d * d + c.delta2, r = std::sqrt(r2);
+  const T z = c.alpha * r;
+  const T lk = log_bessel_k(c.nu, z);
+  *lg = 0.5 * c.nu * std::log(r2) + c.beta * d + lk;
+  if (slope) {
+    /* K_nu'(z) / K_nu(z) = nu / z - K_{nu+1}(z) / K_nu(z) */
+    const T q = std::exp(log_bessel_k(c.nu + 1.0, z) - lk);
+    *slope = 2.0 * c.nu * d / r2 + c.beta - c.alpha * (d / r) * q;
+  }
+}
+
+template <class T>
+HypConst<T> hyp_const(const T* p) {
+  HypConst<T> c;
+  const T mu = p[0], sg = p[1], la = p[2], ze = p[3], be = p[4];
+  c.ok = re(sg) > 0.0 && re(ze) > 0.0 && re(p[5]) > 0.0 && re(p[6]) > 1.0 && re(p[7]) > 0.0 && re(p[8]) > 1.0;
+  if (!c.ok) return c;
+  c.mu = mu;
+  c.nu = la - 0.5;
+  c.beta = be;
+  const T a2 = ze * std::exp(log_bessel_k(la, ze) - log_bessel_k(la + 1.0, ze));
+  c.delta2 = a2 * sg * sg;
+  c.alpha = ze / std::sqrt(c.delta2);
+  c.dl = -p[5] * sg;
+  c.dh = p[7] * sg;
+  c.nl = p[6];
+  c.nr = p[8];
+  hyp_core(c, c.dl, &c.lGl, &c.sl);
+  hyp_core(c, c.dh, &c.lGh, &c.sh);
+  c.ok = re(c.sl) > 0.0 && re(c.sh) < 0.0;  /* tails must fall away from the core */
+  return c;
+}
+
+/* log of the unnormalised density at d = x - mu */
+template <class T>
+T hyp_log_g(const HypConst<T>& c, T d) {
+  if (re(d) < re(c.dl)) return c.lGl - c.nl * std::log(1.0 + c.sl * (c.dl - d) / c.nl);
+  if (re(d) > re(c.dh)) return c.lGh - c.nr * std::log(1.0 - c.sh * (d - c.dh) / c.nr);
+  T lg;
+  hyp_core(c, d, &lg, (T*)nullptr);
+  return lg;
+}
+
+/* int_{u}^{v} (1 + k w)^{-n} dw for 0 <= u <= v (a tail in the distance w
+ * from its junction): ((1+kv)^{1-n} - (1+ku)^{1-n}) / (k (1-n)), by a
+ * series in (1-n) log((1+kv)/(1+ku)) when n is close to 1 */
+template <class T>
+T tail_integral(T k, T n, T u, T v) {
+  const T lu = std::log(1.0 + k * u), lv = std::log(1.0 + k * v);
+  const T e = 1.0 - n;
+  if (mag(e * (lv - lu)) > 1e-3) return (std::exp(e * lv) - std::exp(e * lu)) / (k * e);
+  /* exp(e lu) (exp(e L) - 1) / (k e), L = lv - lu, by its series */
+  const T L = lv - lu;
+  T term = L, s = L;
+  for (int j = 2; j < 30; ++j) {
+    term *= e * L / (double)j;
+    s += term;
+  }
+  return std::exp(e * lu) * s / k;
+}
+
+/* Z = int_lo^hi g dx (the density relative to the core's scale exp(lGl)) */
+template <class T>
+T hyp_norm(const HypConst<T>& c, double lo, double hi) {
+  const T a = lo - c.mu, b = hi - c.mu;
+  T Z = 0.0;
+  /* low tail: d in [a, min(b, dl)], w = dl - d in [dl - min(b, dl), dl - a] */
+  if (re(a) < re(c.dl)) {
+    const T top = re(b) < re(c.dl) ? b : c.dl;
+    Z += std::exp(c.lGl) * tail_integral(c.sl / c.nl, c.nl, c.dl - top, c.dl - a);
+  }
+  if (re(b) > re(c.dh)) {
+    const T bot = re(a) > re(c.dh) ? a : c.dh;
+    Z += std::exp(c.lGh) * tail_integral(-c.sh / c.nr, c.nr, bot - c.dh, b - c.dh);
+  }
+  /* core on [max(a, dl), min(b, dh)]: composite 256-point Gauss-Legendre on
+   * 4 panels (peak width ~ sigma, core width (a_l + a_r) sigma) */
+  const T ca = re(a) > re(c.dl) ? a : c.dl, cb = re(b) < re(c.dh) ? b : c.dh;
+  if (re(cb) > re(ca)) {
+    const Rule& R = rule256();
+    const int npan = 4;
+    for (int q = 0; q < npan; ++q) {
+      const T pa = ca + (cb - ca) * ((double)q / npan), pb = ca + (cb - ca) * ((double)(q + 1) / npan);
+      const T hw = 0.5 * (pb - pa), mid = 0.5 * (pa + pb);
+      for (int i = 0; i < 256; ++i) {
+        T lg;
+        hyp_core(c, mid + hw * R.x[i], &lg, (T*)nullptr);
+        Z += hw * R.w[i] * std::exp(lg);
+      }
+    }
+  }
+  return Z;
+}
+
+/* Per-parameter-point state of one Hypatia2 leaf: the constants at theta
+ * and at theta + i h e_k for each of its 9 parameters, the reference log
+ * value (the core at the left junction; every value and Z are taken
+ * relative to it, which cancels in g / Z) and Z.  Cached per thread while
+ * the parameters stay the same (events are processed one point at a time). */
+constexpr int kHypNP = 9;
+constexpr double kCstep = 1e-30;
+
+struct HypPoint {
+  double key[kHypNP];
+  double lo, hi;
+  bool valid = false;
+  HypConst<double> c;
+  HypConst<cplx> cc[kHypNP];
+  cplx ref[kHypNP];
+  double ref0;
+  double Z;
+  double dZ[kHypNP];
+  bool ok;
+};
+
+const HypPoint& hyp_point(const orc_node& nd, const double* th, double lo, double hi) {
+  thread_local HypPoint hp;
+  bool same = hp.valid && hp.lo == lo && hp.hi == hi;
+  for (int k = 0; k < kHypNP && same; ++k) same = hp.key[k] == P(th, nd, k);
+  if (same) return hp;
+  hp.valid = true;
+  hp.lo = lo;
+  hp.hi = hi;
+  double p[kHypNP];
+  for (int k = 0; k < kHypNP; ++k) hp.key[k] = p[k] = P(th, nd, k);
+  hp.c = hyp_const<double>(p);
+  hp.ok = hp.c.ok;
+  if (!hp.ok) return hp;
+  hp.ref0 = hp.c.lGl;
+  hp.Z = hyp_norm(hp.c, lo, hi) * std::exp(-hp.ref0);
+  for (int k = 0; k < kHypNP; ++k) {
+    cplx pc[kHypNP];
+    for (int j = 0; j < kHypNP; ++j) pc[j] = p[j];
+    pc[k] += cplx(0.0, kCstep);
+    hp.cc[k] = hyp_const<cplx>(pc);
+    hp.ref[k] = hp.cc[k].lGl;
+    hp.dZ[k] = (hyp_norm(hp.cc[k], lo, hi) * std::exp(-hp.ref[k])).imag() / kCstep;
+  }
+  return hp;
+}
+
+/* g relative to the reference value, and dg / dtheta_local by complex steps */
+double g_hypatia(const orc_model& m, const orc_node& nd, const double* th, double x, double* dg) {
+  const HypPoint& hp = hyp_point(nd, th, m.lo[nd.obs], m.hi[nd.obs]);
+  if (!hp.ok) {
+    if (dg)
+      for (int k = 0; k < kHypNP; ++k) dg[k] = 0.0;
+    return std::nan("");
+  }
+  const double lg = hyp_log_g(hp.c, x - hp.c.mu) - hp.ref0;
+  const double g = std::exp(lg);
+  if (dg)
+    for (int k = 0; k < kHypNP; ++k) {
+      const cplx l = hyp_log_g(hp.cc[k], cplx(x) - hp.cc[k].mu) - hp.ref[k];
+      dg[k] = g * l.imag() / kCstep;
+    }
+  return g;
+}
+
+void norm_hypatia(const orc_model& m, const orc_node& nd, const double* th, double* Z, double* d) {
+  const HypPoint& hp = hyp_point(nd, th, m.lo[nd.obs], m.hi[nd.obs]);
+  if (!hp.ok) {
+    *Z = std::nan("");
+    return;
+  }
+  *Z = hp.Z;
+  for (int k = 0; k < kHypNP; ++k) d[k] = hp.dZ[k];
+}
+
 double leaf_g(const orc_model& m, const orc_node& nd, const double* th, double x, double* dg) {
   switch (nd.kind) {
     case ORC_GAUSS: return g_gauss(nd, th, x, dg);
@@ -233,6 +455,7 @@ double leaf_g(const orc_model& m, const orc_node& nd, const double* th, double x
     case ORC_ARGUS: return g_argus(nd, th, x, dg);
     case ORC_JOHNSON: return g_johnson(nd, th, x, dg);
     case ORC_CHI2: return g_chi2(nd, th, x, dg);
+    case ORC_HYPATIA: return g_hypatia(m, nd, th, x, dg);
   }
   return std::nan("");
 }
@@ -517,6 +740,10 @@ void leaf_norm_local(const orc_model& m, const orc_node& nd, const double* th, d
   double lo = m.lo[nd.obs], hi = m.hi[nd.obs];
   *Z = 0.0;
   for (int k = 0; k < ORC_NODE_PAR; ++k) d[k] = 0.0;
+  if (nd.kind == ORC_HYPATIA) { /* tails in closed form, the core by quadrature, any norm flag */
+    norm_hypatia(m, nd, th, Z, d);
+    return;
+  }
   if (nd.norm == ORC_NORM_CLOSED) {
     switch (nd.kind) {
       case ORC_GAUSS: norm_gauss_closed(P(th, nd, 0), P(th, nd, 1), lo, hi, Z, d); return;
@@ -573,6 +800,7 @@ int expected_params(const orc_node& nd) {
     case ORC_PROD: return 0;
     case ORC_JOHNSON: return 4;
     case ORC_CHI2: return 1;
+    case ORC_HYPATIA: return 9;
   }
   return -1;
 }
@@ -616,7 +844,9 @@ double total_yield(const orc_model& m, const double* th) {
   return nu;
 }
 
-bool is_leaf(int kind) { return (kind >= ORC_GAUSS && kind <= ORC_ARGUS) || kind == ORC_JOHNSON || kind == ORC_CHI2; }
+bool is_leaf(int kind) {
+  return (kind >= ORC_GAUSS && kind <= ORC_ARGUS) || kind == ORC_JOHNSON || kind == ORC_CHI2 || kind == ORC_HYPATIA;
+}
 
 /* Bit mask of observables a node depends on. */
 unsigned obs_mask(const orc_model& m, int i) {
@@ -636,7 +866,7 @@ int check_model(const orc_model& m) {
     if (!(m.lo[o] < m.hi[o])) return ORC_E_ARG;
   for (int i = 0; i < m.n_node; ++i) {
     const orc_node& nd = m.node[i];
-    if (nd.kind < ORC_GAUSS || nd.kind > ORC_CHI2) return ORC_E_ARG;
+    if (nd.kind < ORC_GAUSS || nd.kind > ORC_HYPATIA) return ORC_E_ARG;
     if (nd.n_param < 0 || nd.n_param > ORC_NODE_PAR) return ORC_E_ARG;
     if (expected_params(nd) != nd.n_param) return ORC_E_ARG;
     for (int k = 0; k < nd.n_param; ++k)
@@ -697,6 +927,9 @@ int check_params(const orc_model& m, const double* th) {
         break;
       case ORC_CHI2:
         if (!(P(th, nd, 0) > 0.0)) return ORC_E_PARAM;
+        break;
+      case ORC_HYPATIA: /* sigma, zeta, a_l, a_r > 0, n_l, n_r > 1, and tails that fall */
+        if (!hyp_point(nd, th, m.lo[nd.obs], m.hi[nd.obs]).ok) return ORC_E_PARAM;
         break;
       case ORC_SUM: {
         double f = 0.0;
@@ -1293,6 +1526,13 @@ int orc_gd_fit_batched(const orc_model* m, const double* const* cols, const int6
                        nullptr);
     if (status) status[s] = r;
   });
+  return ORC_OK;
+}
+
+/* log K_nu(z) by the oracle's own integral (for its pins). */
+int orc_log_bessel_k(double nu, double z, double* out) {
+  if (!out || !(z > 0.0)) return ORC_E_ARG;
+  *out = log_bessel_k(nu, z);
   return ORC_OK;
 }
 

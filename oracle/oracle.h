@@ -48,7 +48,9 @@ enum orc_kind {
                     or (nu_1..nu_k): yields, p = sum nu_j p_j / sum nu */
   ORC_PROD = 7,  /* no params; children on disjoint observables   */
   ORC_JOHNSON = 8, /* params (mu, lambda, gamma, delta), S_U family */
-  ORC_CHI2 = 9     /* params (nu): g = x^(nu/2-1) e^(-x/2), 0 <= lo  */
+  ORC_CHI2 = 9,    /* params (nu): g = x^(nu/2-1) e^(-x/2), 0 <= lo  */
+  ORC_HYPATIA = 10 /* params (mu, sigma, lambda, zeta, beta, a_l, n_l, a_r,
+                      n_r): generalised hyperbolic core, power-law tails */
 };
 
 enum orc_norm {
@@ -69,7 +71,7 @@ enum orc_status {
 #define ORC_MAX_OBS 4
 #define ORC_MAX_PAR 32
 #define ORC_MAX_NODE 16
-#define ORC_NODE_PAR 8
+#define ORC_NODE_PAR 12
 #define ORC_NODE_CHILD 8
 
 typedef struct orc_node {
@@ -189,6 +191,10 @@ int orc_gd_fit_batched(const orc_model* m, const double* const* cols,
                        const int64_t* offsets, int32_t n_sets, double* theta,
                        int32_t n_steps, double eta, int32_t threads,
                        double* nll, double* grad, int32_t* status);
+
+/* log K_nu(z), the modified Bessel function of the second kind of real
+ * order nu at z > 0, by the integral the Hypatia2 density uses.         */
+int orc_log_bessel_k(double nu, double z, double* out);
 
 /* n-point Gauss-Legendre rule on [-1, 1] (nodes ascending). */
 int orc_gl_rule(int32_t n, double* x, double* w);

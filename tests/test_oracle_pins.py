@@ -991,3 +991,136 @@ def test_yields_checks_and_product_root():
     st, v, g = oracle.Oracle(prod).nll([x, y], np.concatenate([th, [0.0]]))
     v1 = o.nll([x], th)[1]
     assert st == OK and abs(v - (v1 + 500 * math.log(2.0))) <= 1e-12 * abs(v)
+
+
+# ---------------------------------------------------------------------------
+# Hypatia2 (generalised hyperbolic core, power-law tails on both sides)
+# ---------------------------------------------------------------------------
+
+HYP_NAMES = ["mu", "sigma", "lambda", "zeta", "beta", "a_l", "n_l", "a_r", "n_r"]
+HYP_CASES = [([5.28, 0.003, -2.0, 0.5, 0.0, 2.0, 3.0, 2.5, 4.0], 5.20, 5.35),
+             ([0.0, 1.0, -1.2, 0.05, 0.1, 1.5, 2.0, 1.8, 6.0], -8.0, 8.0),
+             ([1.0, 0.5, 1.0, 2.0, -0.2, 2.5, 1.5, 3.0, 3.0], -3.0, 5.0),
+             ([0.0, 1.0, 3.0, 20.0, 0.0, 3.0, 5.0, 3.0, 5.0], -6.0, 6.0)]
+
+
+def hypatia_spec(th, lo, hi):
+    return {"obs": [{"name": "m", "lo": lo, "hi": hi}],
+            "params": [datagen.param(n, v, -1e3, 1e3) for n, v in zip(HYP_NAMES, th)],
+            "nodes": [{"kind": "hypatia", "obs": 0, "params": list(range(9)), "norm": "gl256"}], "root": 0}
+
+
+def test_log_bessel_k_against_mpmath():
+    """The oracle's K_nu(z) (trapezoidal rule on its integral over cosh)
+    against mpmath's besselk at 30 digits, orders -3.3..4.2, z 1e-3..700."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    for nu in (-3.3, -1.7, -0.5, 0.0, 0.3, 0.5, 1.0, 2.5, 4.2):
+        for z in (1e-3, 0.05, 0.3, 1.0, 3.0, 10.0, 50.0, 300.0, 700.0):
+            ref = float(mp.log(mp.besselk(nu, z)))
+            assert abs(oracle.log_bessel_k(nu, z) - ref) <= 2e-15 * max(1.0, abs(ref)), (nu, z)
+
+
+def test_hypatia_density_against_mpmath():
+    """log p of the oracle against the same definition written with mpmath
+    (besselk, numerical slope at the junctions, tanh-sinh quadrature for Z)
+    at 30 digits, over the core, both tails and the range ends."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    for th, lo, hi in HYP_CASES:
+        mu, sg, la, ze, be, al, nl, ar, nr = [mp.mpf(v) for v in th]
+        nu = la - mp.mpf(1) / 2
+        d2 = ze * mp.besselk(la, ze) / mp.besselk(la + 1, ze) * sg * sg
+        alpha = ze / mp.sqrt(d2)
+
+        def lG(d):
+            r2 = d * d + d2
+            return nu / 2 * mp.log(r2) + be * d + mp.log(mp.besselk(nu, alpha * mp.sqrt(r2)))
+        dl, dh = -al * sg, ar * sg
+        Gl, sl, Gh, sh = lG(dl), mp.diff(lG, dl), lG(dh), mp.diff(lG, dh)
+
+        def lg(d):
+            if d < dl:
+                return Gl - nl * mp.log(1 + sl * (dl - d) / nl)
+            if d > dh:
+                return Gh - nr * mp.log(1 - sh * (d - dh) / nr)
+            return lG(d)
+        cuts = [lo] + [p for p in (mu + dl, mu, mu + dh) if lo < p < hi] + [hi]
+        logZ = mp.log(mp.quad(lambda x: mp.exp(lg(x - mu) - Gl), cuts)) + Gl
+        o = oracle.Oracle(hypatia_spec(th, lo, hi))
+        for x in np.linspace(lo, hi, 13):
+            ref = float(lg(mp.mpf(x) - mu) - logZ)
+            st, lp, _ = o.log_density([x], np.array(th))
+            assert st == OK and abs(lp - ref) <= 4e-15 * max(1.0, abs(ref)), (th, x, lp, ref)
+
+
+def test_hypatia_lambda_one_is_hyperbolic():
+    """lambda = 1 gives K_{1/2}(z) = sqrt(pi / 2z) e^{-z}: the core is the
+    hyperbolic density, log G = beta d - alpha sqrt(d^2 + delta^2) + const;
+    alpha and delta from scipy's kv (only in A^2 = zeta K_1 / K_2)."""
+    from scipy.special import kv
+    th = [0.4, 0.8, 1.0, 1.3, 0.15, 2.5, 3.0, 2.0, 4.0]
+    mu, sg, la, ze, be = th[:5]
+    delta = np.sqrt(ze * kv(la, ze) / kv(la + 1.0, ze)) * sg
+    alpha = ze / delta
+    o = oracle.Oracle(hypatia_spec(th, -5.0, 5.0))
+    xs = np.linspace(mu - 1.9 * sg, mu + 1.5 * sg, 9)
+    lp = np.array([o.log_density([x], np.array(th))[1] for x in xs])
+    d = xs - mu
+    ref = be * d - alpha * np.sqrt(d * d + delta * delta)
+    np.testing.assert_allclose(lp - lp[0], ref - ref[0], rtol=0, atol=2e-14)
+
+
+def test_hypatia_tails_continue_value_and_slope():
+    """At both junctions the tails continue the core with equal value and
+    slope (one-sided differences of log p on either side)."""
+    for th, lo, hi in HYP_CASES:
+        o = oracle.Oracle(hypatia_spec(th, lo, hi))
+        mu, sg = th[0], th[1]
+        for xj in (mu - th[5] * sg, mu + th[7] * sg):
+            if not (lo < xj < hi):
+                continue
+            h = 1e-5 * sg
+            f = lambda x: o.log_density([x], np.array(th))[1]
+            left = (f(xj) - f(xj - h)) / h
+            right = (f(xj + h) - f(xj)) / h
+            assert abs(f(xj - 1e-12 * sg) - f(xj + 1e-12 * sg)) < 1e-9
+            assert abs(left - right) <= 1e-4 * max(1.0, abs(left)), (th, xj, left, right)
+
+
+def test_hypatia_gradient_matches_central_differences():
+    """d NLL / d theta (complex steps through the Bessel integral, the
+    junctions, the tails and the normalisation) against fourth-order central
+    differences of the oracle's NLL, all nine parameters free."""
+    th, lo, hi = HYP_CASES[1]
+    spec = hypatia_spec(th, lo, hi)
+    rng = np.random.default_rng(51)
+    x = np.clip(rng.standard_t(3, 2000) * 1.2 + 0.1, lo, hi)
+    o = oracle.Oracle(spec)
+    st, nll, g = o.nll([x], np.array(th))
+    assert st == OK
+    for k in range(9):
+        h = 1e-4 * max(abs(th[k]), 0.05)
+
+        def f(v):
+            t = np.array(th, dtype=float)
+            t[k] = v
+            return o.nll([x], t)[1]
+
+        fd = (f(th[k] - 2 * h) - 8 * f(th[k] - h) + 8 * f(th[k] + h) - f(th[k] + 2 * h)) / (12 * h)
+        bound = 50 * (2.2e-16 * abs(nll) / h) + 1e-6 * abs(g[k])
+        assert abs(fd - g[k]) <= bound, (HYP_NAMES[k], fd, g[k], bound)
+
+
+def test_hypatia_parameter_checks():
+    """sigma, zeta, a_l, a_r > 0 and n_l, n_r > 1; a tail whose junction
+    slope does not fall away from the core (a strong skew beta) is out of
+    range."""
+    th, lo, hi = HYP_CASES[1]
+    o = oracle.Oracle(hypatia_spec(th, lo, hi))
+    x = np.linspace(lo, hi, 50)
+    assert o.nll([x], np.array(th))[0] == OK
+    for k, v in ((1, 0.0), (3, 0.0), (5, -1.0), (6, 1.0), (7, 0.0), (8, 0.5), (4, 5.0)):
+        t = np.array(th, dtype=float)
+        t[k] = v
+        assert o.nll([x], t)[0] == E_PARAM, (HYP_NAMES[k], v)
