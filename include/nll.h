@@ -48,7 +48,7 @@ extern "C" {
 #define NLL_MAX_OBS 4
 #define NLL_MAX_PARAMS 32
 #define NLL_MAX_NODES 16
-#define NLL_NODE_MAX_PARAMS 8
+#define NLL_NODE_MAX_PARAMS 12
 #define NLL_NODE_MAX_CHILDREN 8
 
 typedef enum nll_status {
@@ -84,6 +84,21 @@ typedef enum nll_status {
  *              range must lie in [0, 1000] (else NLL_ERR_UNSUPPORTED);
  *              closed-form normalisation by the lower incomplete gamma
  *              function, Gauss-Legendre after x = s^2 when lo = 0
+ *   NLL_HYPATIA (mu, sigma, lambda, zeta, beta, a_l, n_l, a_r, n_r)
+ *              Hypatia2 (Sec. 3): with d = x-mu, nu = lambda-1/2,
+ *              delta^2 = sigma^2 zeta K_lambda(zeta)/K_{lambda+1}(zeta),
+ *              alpha = zeta/delta, r^2 = d^2+delta^2, the core
+ *              g = r^nu e^(beta d) K_nu(alpha r) on -a_l sigma <= d <= a_r sigma,
+ *              continued below and above by power laws
+ *              G (1 + k w)^-n (w: distance from the junction; n = n_l, n_r)
+ *              with the core's value and slope; sigma, zeta, a_l, a_r > 0,
+ *              n_l, n_r > 1, and both tails falling away from the core
+ *              (else NLL_ERR_PARAM).  Normalised numerically whatever
+ *              `norm` says (Gauss-Legendre in asinh(d/delta) on the core,
+ *              in log(1 + k w) on each tail).  At most one per model, FP64
+ *              only (else NLL_ERR_UNSUPPORTED); K_nu is tabulated per
+ *              parameter point on the core's range, which takes
+ *              |lambda| <= 6 and 1e-3 <= alpha r <= 700 over it
  * Composite nodes:
  *   NLL_SUM    over k >= 2 children on the same observables, either
  *              fractions (f_1 .. f_{k-1}): p = sum_{j<k} f_j p_j +
@@ -94,7 +109,7 @@ typedef enum nll_status {
  *   NLL_PROD   no params; children on disjoint observables: p = prod p_d   */
 enum nll_node_kind {
   NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7, NLL_JOHNSON = 8,
-  NLL_CHI2 = 9
+  NLL_CHI2 = 9, NLL_HYPATIA = 10
 };
 
 /* Normalisation of a leaf over its observable range [lo, hi]:
@@ -237,12 +252,13 @@ nll_status nll_eval_batched(nll_model* model, int32_t n_sets, const int64_t* off
  * buffers; the array is looked up (hipGetSymbolAddress) on the first call
  * on each device.  It needs
  *   align256(8 (n_sets + 1)) + align256(4 n_sets) + align256(24 I)
- *   + align256(S n_sets) + I * 16 (A + 1)  bytes,
- * with I = n_events / tile_events + n_sets + 1 work items, S the per-set
- * constant block (nll_model_info's per_set_bytes) and A the model's
+ *   + align256(C n_sets) + align256(T n_sets) + I * 16 (A + 1)  bytes,
+ * with I = n_events / tile_events + n_sets + 1 work items, C the per-set
+ * constant block and T the per-set tables of a Hypatia2 leaf (0 without
+ * one; C + T is nll_info's per_set_bytes), and A the model's
  * accumulators (n_accumulators); a larger request returns NLL_ERR_SCRATCH
  * before anything is enqueued (4096 sets over 4.1e8 events of a one-leaf
- * model need about 21 MB).  Every word the pass reads is written earlier
+ * model need about 24 MB).  Every word the pass reads is written earlier
  * in the same call, so nothing has to start at zero.  All calls on one GPU
  * share the array: calls that overlap on that GPU (other models, other
  * streams, other host threads) race and must be serialised by the caller;

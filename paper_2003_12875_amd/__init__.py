@@ -22,7 +22,8 @@ from ._native import (HF_MODIFIER, HFDesc, HFModifier, JitDesc, MAX_NODE_CHILDRE
                       ModelDesc, Schedule, Info,
                       STATUS, check, lib, LIB_PATH)
 
-KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9}
+KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9,
+        "hypatia": 10}
 NORM = {"analytic": 0, "gl256": 1, "gl256_single": 2}
 PRECISION = {"fp64": 0, "fp32c": 1}
 

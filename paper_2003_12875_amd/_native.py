@@ -7,7 +7,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libnllmi.so")
 
-MAX_OBS, MAX_PARAMS, MAX_NODES, MAX_NODE_PARAMS, MAX_NODE_CHILDREN = 4, 32, 16, 8, 8
+MAX_OBS, MAX_PARAMS, MAX_NODES, MAX_NODE_PARAMS, MAX_NODE_CHILDREN = 4, 32, 16, 12, 8
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported model shape", -3: "parameter out of range",
           -4: "event outside observable range", -5: "invalid density", -6: "device error",

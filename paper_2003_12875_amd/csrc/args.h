@@ -40,6 +40,8 @@ struct SingleArgs {
   const double* partials_prev;  // the previous step's block records (null at the first step)
   GDState gd_out;               // the state the update writes (gd is the one it reads)
   PerTheta* consts_out;         // constants of the proposal this step evaluates
+  double* aux;                  // a leaf's per-point tables (kAuxWords) beside the
+                                // fit's constants in consts (first step, BHHH steps)
 };
 
 // One work item of the batched pass: events [start, end) of one set.
@@ -57,6 +59,7 @@ struct SetsArgs {
   const int* set_flag;      // n_sets: 1 = malformed offsets
   const WorkItem* items;    // tile_off[n_sets] work items in set order
   PerTheta* consts;         // n_sets
+  double* aux;              // n_sets * kAuxWords: a leaf's per-point tables, or null
   double* partials;         // items * (NA + 1) double-double pairs
   const double* theta;      // n_sets * P (evaluation mode)
   double* nll_out;          // n_sets

@@ -35,6 +35,7 @@ static const std::vector<VariantOps>& registry() {
     register_variants_fp32c_2d(reg);
     register_variants_johnson(reg);
     register_variants_chi2(reg);
+    register_variants_hypatia(reg);
   });
   return reg;
 }
@@ -93,11 +94,14 @@ int expected_params(int kind, int np) {
     case NLL_ARGUS: return 2;
     case NLL_JOHNSON: return 4;
     case NLL_CHI2: return 1;
+    case NLL_HYPATIA: return 9;
     default: return -1;
   }
 }
 
-bool is_leaf(int kind) { return (kind >= NLL_GAUSS && kind <= NLL_ARGUS) || kind == NLL_JOHNSON || kind == NLL_CHI2; }
+bool is_leaf(int kind) {
+  return (kind >= NLL_GAUSS && kind <= NLL_ARGUS) || kind == NLL_JOHNSON || kind == NLL_CHI2 || kind == NLL_HYPATIA;
+}
 
 // ---------------------------------------------------------------------------
 // lowering: graph -> sum of products of leaves
@@ -126,6 +130,7 @@ struct Lowering {
       if (!(D.param_lo[k] <= D.param_hi[k])) return NLL_ERR_ARG;
     if (D.extended && D.yield_param >= D.n_param) return NLL_ERR_ARG;  // < 0: the root's sum of yields
     obs_mask.assign(D.n_node, 0u);
+    int n_hypatia = 0;
     for (int i = 0; i < D.n_node; ++i) {
       const nll_node_desc& nd = D.nodes[i];
       if (nd.n_param < 0 || nd.n_param > NLL_NODE_MAX_PARAMS) return NLL_ERR_ARG;
@@ -138,6 +143,9 @@ struct Lowering {
         if (nd.norm < NLL_NORM_ANALYTIC || nd.norm > NLL_NORM_GL256_SINGLE) return NLL_ERR_ARG;
         if (nd.kind == NLL_ARGUS && D.obs_lo[nd.obs] < 0.0) return NLL_ERR_UNSUPPORTED;
         if (nd.kind == NLL_CHI2 && (D.obs_lo[nd.obs] < 0.0 || D.obs_hi[nd.obs] > 1000.0)) return NLL_ERR_UNSUPPORTED;
+        // Hypatia2: its per-point tables sit beside the constants, one set
+        // per model, and the FP32-compensated pass has no form of it
+        if (nd.kind == NLL_HYPATIA && (++n_hypatia > 1 || D.precision != NLL_FP64)) return NLL_ERR_UNSUPPORTED;
         obs_mask[i] = 1u << nd.obs;
       } else if (nd.kind == NLL_SUM || nd.kind == NLL_PROD) {
         // a sum takes fractions f_1..f_{k-1} or yields nu_1..nu_k
@@ -334,7 +342,7 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
     pl.leaf_obs[s] = nd.obs;
     pl.leaf_np[s] = nd.n_param;
     for (int p = 0; p < nd.n_param; ++p) pl.leaf_param[s][p] = nd.param[p];
-    pl.leaf_norm[s] = nd.norm;
+    pl.leaf_norm[s] = nd.kind == NLL_HYPATIA ? kNormGL : nd.norm;  // no closed form
     pl.leaf_root[s] = root[l];
   }
   // Flat shapes: term k is the one whose only non-root leaf sits in the
@@ -417,12 +425,14 @@ nll_status ensure_sets(nll_model* m, int n_sets, int64_t items = -1) {
     dfree(m->tile_off);
     dfree(m->set_flag);
     dfree(m->consts);
+    dfree(m->aux);
     m->sets_cap = 0;
     int cap = std::max(n_sets, 64);
     nll_status st;
     if ((st = dalloc(&m->tile_off, (size_t)cap + 1)) != NLL_OK) return st;
     if ((st = dalloc(&m->set_flag, (size_t)cap)) != NLL_OK) return st;
     if ((st = dalloc(&m->consts, (size_t)cap)) != NLL_OK) return st;
+    if (m->ops->aux && (st = dalloc(&m->aux, (size_t)cap * kAuxWords)) != NLL_OK) return st;
     m->sets_cap = cap;
     m->have_graph = false;
   }
@@ -489,6 +499,7 @@ SetsArgs sets_args(const nll_model* m, int n_sets, const int64_t* offsets) {
   a.set_flag = m->set_flag;
   a.items = m->items;
   a.consts = m->consts;
+  a.aux = m->aux;
   a.partials = m->set_partials;
   a.glx = m->gl.x;
   a.glw = m->gl.w;
@@ -518,6 +529,7 @@ SingleArgs single_args(const nll_model* m, const double* theta, double* nll_out,
   a.partials = m->partials;
   a.pt_out = m->pt_single;
   a.consts = m->consts;
+  a.aux = m->aux;  // beside consts[0]: a fit's first step and BHHH steps
   a.status = m->status;
   a.glx = m->gl.x;
   a.glw = m->gl.w;
@@ -569,7 +581,7 @@ GDState gd_view(const GDState& g, int set, int P) {
 nll_status enqueue_fit_single(nll_model* m, hipStream_t st, double* theta, int n_steps, double eta, double* nll_out,
                               double* grad_out, int32_t* status_out, bool bhhh = false) {
   GDState gd = gd_state(m);
-  hipError_t e = m->ops->fit_init(*m->ops, m->plan, theta, 1, eta, gd, m->consts, m->gl.x, m->gl.w, st);
+  hipError_t e = m->ops->fit_init(*m->ops, m->plan, theta, 1, eta, gd, m->consts, m->aux, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   SingleArgs a = single_args(m, nullptr, nullptr, nullptr);
   a.gd = gd;
@@ -628,7 +640,7 @@ nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* 
   a.gd = gd;
   hipError_t e = launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->items, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
-  e = m->ops->fit_init(*m->ops, m->plan, theta, n_sets, eta, gd, m->consts, m->gl.x, m->gl.w, st);
+  e = m->ops->fit_init(*m->ops, m->plan, theta, n_sets, eta, gd, m->consts, m->aux, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   record_step(m, 0, st);
   for (int s = 0; s < n_steps; ++s) {
@@ -703,6 +715,7 @@ nll_status eval_batched_on(nll_model* m, int32_t n_sets, const int64_t* offsets,
   a.set_flag = s.set_flag;
   a.items = s.items;
   a.consts = s.consts;
+  a.aux = s.aux;
   a.partials = s.partials;
   a.theta = theta;
   a.nll_out = nll_out;
@@ -711,7 +724,7 @@ nll_status eval_batched_on(nll_model* m, int32_t n_sets, const int64_t* offsets,
   if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, s.tile_off, s.set_flag, s.items, m->stream) !=
       hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->consts(*m->ops, m->plan, theta, n_sets, s.consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
+  if (m->ops->consts(*m->ops, m->plan, theta, n_sets, s.consts, s.aux, m->gl.x, m->gl.w, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
   if (m->ops->sets(*m->ops, m->plan, a, grad, false, m->sched.sets_unroll, sets_grid(m), lds_cap(m, m->sched.sets_blocks_per_cu),
                    m->stream, nullptr, nullptr) != hipSuccess)
@@ -808,6 +821,7 @@ void nll_destroy_model(nll_model* m) {
   dfree(m->set_flag);
   dfree(m->items);
   dfree(m->consts);
+  dfree(m->aux);
   dfree(m->set_partials);
   dfree(m->gd_mem);
   dfree(m->gd_status);
@@ -908,6 +922,7 @@ nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets
   s.set_flag = m->set_flag;
   s.items = m->items;
   s.consts = m->consts;
+  s.aux = m->aux;
   s.partials = m->set_partials;
   return eval_batched_on(m, n_sets, offsets, theta, nll_out, grad_out, status_out, s);
 }
@@ -936,7 +951,7 @@ nll_status nll_eval_points(nll_model* m, int32_t n_points, const double* theta, 
   a.status_out = reinterpret_cast<int*>(status_out);
   if (launch_points(n_points, m->n, tile, m->pts_offsets, m->tile_off, m->set_flag, m->items, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
-  if (m->ops->consts(*m->ops, m->plan, theta, n_points, m->consts, m->gl.x, m->gl.w, m->stream) != hipSuccess)
+  if (m->ops->consts(*m->ops, m->plan, theta, n_points, m->consts, m->aux, m->gl.x, m->gl.w, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
   if (m->ops->sets(*m->ops, m->plan, a, grad_out != nullptr, false, m->sched.sets_unroll, sets_grid(m),
                    lds_cap(m, m->sched.sets_blocks_per_cu), m->stream, nullptr, nullptr) != hipSuccess)
@@ -1101,7 +1116,7 @@ nll_status nll_get_info(const nll_model* m, nll_info* out) {
   out->precision = m->precision;
   out->n_cu = m->n_cu;
   out->n_events = m->n;
-  out->per_set_bytes = (int32_t)sizeof(PerTheta);
+  out->per_set_bytes = (int32_t)(sizeof(PerTheta) + (m->ops->aux ? kAuxWords * sizeof(double) : 0));
   return NLL_OK;
 }
 

@@ -20,6 +20,9 @@ struct VariantOps {
   // 1: term k is the k-th non-root leaf (with the root factors), as the
   // kernels then assume; 0: the plan's term masks define the terms
   int flat;
+  // 1: a leaf keeps per-point tables (kAuxWords) beside PerTheta, passed
+  // as SingleArgs::aux / SetsArgs::aux and to consts / fit_init
+  int aux;
   // run-time compiled shapes: their module and kernels (null: compiled
   // ahead of time); the launchers receive the variant itself
   const void* rtc;
@@ -31,12 +34,12 @@ struct VariantOps {
   // and right after the streaming kernel of the step
   hipError_t (*single_fit)(const VariantOps&, const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t,
                            hipEvent_t ev0, hipEvent_t ev1);
-  hipError_t (*consts)(const VariantOps&, const Plan&, const double* theta, int n_sets, PerTheta* out, const double* glx,
-                       const double* glw, hipStream_t);
+  hipError_t (*consts)(const VariantOps&, const Plan&, const double* theta, int n_sets, PerTheta* out, double* aux,
+                       const double* glx, const double* glw, hipStream_t);
   hipError_t (*sets)(const VariantOps&, const Plan&, const SetsArgs&, bool grad, bool fit, int unroll, int grid, int lds_cap,
                      hipStream_t, hipEvent_t ev0, hipEvent_t ev1);
   hipError_t (*fit_init)(const VariantOps&, const Plan&, const double* theta, int n_sets, double eta, const GDState&,
-                         PerTheta* consts, const double* glx, const double* glw, hipStream_t);
+                         PerTheta* consts, double* aux, const double* glx, const double* glw, hipStream_t);
   // BHHH (FP64 shapes with few score features; null where not compiled):
   // NLL, gradient and BHHH matrix at one point, and damped BHHH fit steps
   hipError_t (*single_bhhh)(const VariantOps&, const Plan&, const SingleArgs&, int unroll, int grid, int lds_cap, hipStream_t);
@@ -62,6 +65,7 @@ void register_variants_fp32c_1d(std::vector<VariantOps>& out);
 void register_variants_fp32c_2d(std::vector<VariantOps>& out);
 void register_variants_johnson(std::vector<VariantOps>& out);
 void register_variants_chi2(std::vector<VariantOps>& out);
+void register_variants_hypatia(std::vector<VariantOps>& out);
 
 hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
                            int64_t* tile_off, int* set_flag, WorkItem* items, hipStream_t st);

@@ -537,6 +537,13 @@ __device__ inline void stream_part_tile(const double* const* cols, int64_t base,
   acc.end_tile();
 }
 
+// A leaf's per-point tables (kAuxWords words) copied by NT threads, no
+// barrier.
+template <int NT>
+__device__ inline void copy_aux(double* dst, const double* __restrict__ src) {
+  for (int i = threadIdx.x; i < kAuxWords; i += NT) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------------
 // single dataset
 // ------------------------------------------------------------------------
@@ -557,6 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   __shared__ double red[NR * (kBlock + 1)];
   __shared__ DD tot[NV];
   __shared__ double small[4 * (kMaxLeafParams + 1)];
+  __shared__ double s_aux[M::AUX ? kAuxWords : 1];  // a leaf's per-point tables
 
   // Evaluation: plan and parameters first, then the first event tile
   // (which does not depend on theta), whose loads overlap the prologue.
@@ -584,11 +592,15 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   CT C;
   int bad;
   if constexpr (FIT) {
-    C.load(*a.consts, pl);
+    if constexpr (M::AUX) {
+      copy_aux<kBlock>(s_aux, a.aux);
+      __syncthreads();
+    }
+    C.load(*a.consts, pl, s_aux);
     bad = uniform(a.consts->bad);
   } else {
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
-    C.load(pt, pl);
+    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small, s_aux);
+    C.load(pt, pl, s_aux);
     bad = uniform(pt.bad);
   }
   if constexpr (CT::kExpTab) C.etab = s_etab;
@@ -673,8 +685,10 @@ __global__ __launch_bounds__(kFinishBlock) void k_single_finish(const Plan pl, c
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
     // the next proposal's constants, built in LDS (its phases read back
     // what other threads wrote) and stored with one parallel copy
-    compute_pertheta<M, kFinishBlock>(spl, s_theta, a.glx, a.glw, &spt, small);
+    __shared__ double s_aux[M::AUX ? kAuxWords : 1];
+    compute_pertheta<M, kFinishBlock>(spl, s_theta, a.glx, a.glw, &spt, small, s_aux);
     copy_pertheta<M, kFinishBlock>(a.consts, &spt, spl.n_param);
+    if constexpr (M::AUX) copy_aux<kFinishBlock>(a.aux, s_aux);
   } else {
     if (t == 0) {
       *a.nll_out = s_nll;
@@ -717,6 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
   __shared__ double s_nll;
   __shared__ int s_st;
   __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
+  __shared__ double s_aux[M::AUX ? kAuxWords : 1];  // a leaf's per-point tables
   const int t = threadIdx.x;
   const bool first = a.partials_prev == nullptr;
 
@@ -750,7 +765,11 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
   CT C;
   int bad;
   if (first) {
-    C.load(*a.consts, pl);
+    if constexpr (M::AUX) {
+      copy_aux<kBlock>(s_aux, a.aux);
+      __syncthreads();
+    }
+    C.load(*a.consts, pl, s_aux);
     bad = uniform(a.consts->bad);
   } else {
     ptv.store(&pt, pl.n_param);
@@ -758,9 +777,9 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
     finish_block<M, true>(spl, pt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
     const double next = gd_update_to(spl, a.gd_out, s_st, s_nll, s_grad, neff, pre, blockIdx.x == 0);
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small);
+    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &pt, small, s_aux);
     if (blockIdx.x == 0) copy_pertheta<M, kBlock>(a.consts_out, &pt, spl.n_param);
-    C.load(pt, pl);
+    C.load(pt, pl, s_aux);
     bad = uniform(pt.bad);
   }
   if constexpr (CT::kExpTab) C.etab = s_etab;
@@ -787,18 +806,21 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
 template <class M>
 __global__ __launch_bounds__(kBlock) void k_consts(const Plan pl, const double* __restrict__ theta,
                                                   int n_sets, PerTheta* __restrict__ out,
+                                                  double* __restrict__ aux_out,
                                                   const double* __restrict__ glx,
                                                   const double* __restrict__ glw) {
   __shared__ double small[4 * (kMaxLeafParams + 1)];
   __shared__ Plan spl;
   __shared__ double s_theta[kMaxParams];
   __shared__ PerTheta spt;
+  __shared__ double s_aux[M::AUX ? kAuxWords : 1];
   const int s = blockIdx.x;
   if (s >= n_sets) return;
   stage_plan<kBlock>(pl, &spl);
   stage_theta(theta + (size_t)s * pl.n_param, pl.n_param, s_theta);
-  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
+  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small, s_aux);
   copy_pertheta<M, kBlock>(&out[s], &spt, spl.n_param);
+  if constexpr (M::AUX) copy_aux<kBlock>(aux_out + (size_t)s * kAuxWords, s_aux);
 }
 
 template <class M, bool GRAD, int U>
@@ -813,6 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
   for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
   using CT = typename Pass<M, GRAD>::C;
   __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
+  __shared__ double s_aux[M::AUX ? kAuxWords : 1];  // a leaf's per-point tables (per item)
   if constexpr (CT::kExpTab) stage_exp_table(s_etab);
   if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
   if constexpr (CT::kExpTab || M::EVENT_LOG) __syncthreads();
@@ -829,8 +852,12 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     const PerTheta& pt = a.consts[s];
     const int64_t start = cur.start, end = cur.end;
 
+    if constexpr (M::AUX) {  // the previous item's reads ended in its block sum
+      copy_aux<kBlock>(s_aux, a.aux + (size_t)s * kAuxWords);
+      __syncthreads();
+    }
     CT C;
-    C.load(pt, pl);
+    C.load(pt, pl, s_aux);
     C.etab = s_etab;
     typename Pass<M, GRAD>::A acc;
     acc.init();
@@ -899,8 +926,10 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   } else {
     const double next = gd_update(spl, a.gd, s, s_st, s_nll, s_grad, n_s, pre);
     if (t < P) s_theta[t] = next;  // compute_pertheta starts with a barrier
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &spt, small);
+    __shared__ double s_aux[M::AUX ? kAuxWords : 1];
+    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &spt, small, s_aux);
     copy_pertheta<M, kBlock>(&a.consts[s], &spt, P);
+    if constexpr (M::AUX) copy_aux<kBlock>(a.aux + (size_t)s * kAuxWords, s_aux);
   }
 }
 
@@ -908,12 +937,14 @@ template <class M>
 __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double* __restrict__ theta,
                                                     int n_sets, double eta, GDState gd,
                                                     PerTheta* __restrict__ consts,
+                                                    double* __restrict__ aux,
                                                     const double* __restrict__ glx,
                                                     const double* __restrict__ glw) {
   __shared__ double small[4 * (kMaxLeafParams + 1)];
   __shared__ Plan spl;
   __shared__ double s_theta[kMaxParams];
   __shared__ PerTheta spt;
+  __shared__ double s_aux[M::AUX ? kAuxWords : 1];
   const int s = blockIdx.x;
   if (s >= n_sets) return;
   const int P = pl.n_param;
@@ -932,8 +963,9 @@ __global__ __launch_bounds__(kBlock) void k_fit_init(const Plan pl, const double
   }
   if (gd.b_acc)
     for (int e = threadIdx.x; e < P * P; e += kBlock) gd.b_acc[(size_t)s * P * P + e] = 0.0;
-  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small);
+  compute_pertheta<M>(spl, s_theta, glx, glw, &spt, small, s_aux);
   copy_pertheta<M, kBlock>(&consts[s], &spt, P);
+  if constexpr (M::AUX) copy_aux<kBlock>(aux + (size_t)s * kAuxWords, s_aux);
 }
 
 // BHHH pass compiled: FP64 unweighted shapes with at most 6 score features

@@ -126,9 +126,9 @@ struct Launch {
     return grad ? single_t<true, false>(pl, a, unroll, grid, lds_cap, st)
                 : single_t<false, false>(pl, a, unroll, grid, lds_cap, st);
   }
-  static hipError_t consts(const VariantOps&, const Plan& pl, const double* theta, int n_sets, PerTheta* out, const double* glx,
-                           const double* glw, hipStream_t st) {
-    hipLaunchKernelGGL((k_consts<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, out, glx, glw);
+  static hipError_t consts(const VariantOps&, const Plan& pl, const double* theta, int n_sets, PerTheta* out, double* aux,
+                           const double* glx, const double* glw, hipStream_t st) {
+    hipLaunchKernelGGL((k_consts<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, out, aux, glx, glw);
     return hipGetLastError();
   }
   template <bool GRAD, int U>
@@ -164,8 +164,8 @@ struct Launch {
     return hipGetLastError();
   }
   static hipError_t fit_init(const VariantOps&, const Plan& pl, const double* theta, int n_sets, double eta, const GDState& gd,
-                             PerTheta* consts, const double* glx, const double* glw, hipStream_t st) {
-    hipLaunchKernelGGL((k_fit_init<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, eta, gd, consts,
+                             PerTheta* consts, double* aux, const double* glx, const double* glw, hipStream_t st) {
+    hipLaunchKernelGGL((k_fit_init<M>), dim3(n_sets), dim3(kBlock), 0, st, pl, theta, n_sets, eta, gd, consts, aux,
                        glx, glw);
     return hipGetLastError();
   }
@@ -194,6 +194,7 @@ VariantOps make_ops(const char* name) {
   v.na_grad = M::template NA<true>;  // accumulators per record (counters included)
   v.precision = M::PREC;
   v.flat = M::FLAT ? 1 : 0;
+  v.aux = M::AUX ? 1 : 0;
   v.rtc = nullptr;
   v.single = &Launch<M>::single;
   v.single_fit = &Launch<M>::single_fit;

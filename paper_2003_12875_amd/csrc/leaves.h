@@ -73,6 +73,7 @@ struct GaussLeaf {
   static constexpr int NP = 2;
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
+  static constexpr bool kAux = false;       // no per-point tables beside PerTheta
   struct C {
     double is, b;
   };
@@ -169,6 +170,7 @@ struct ExpLeaf {
   static constexpr int NP = 1;
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
+  static constexpr bool kAux = false;       // no per-point tables beside PerTheta
   struct C {
     double c;
   };
@@ -265,6 +267,7 @@ struct ChebLeaf {
   static constexpr int NP = K;
   static constexpr bool kLinear = true;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
+  static constexpr bool kAux = false;       // no per-point tables beside PerTheta
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double sx, ox, a[K];
@@ -393,6 +396,7 @@ struct CBLeaf {
   static constexpr int NP = 4;
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
+  static constexpr bool kAux = false;       // no per-point tables beside PerTheta
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double is, b, na, logA, B, n, Ka, Kb, Kc, nOverA;
@@ -611,6 +615,7 @@ struct ArgusLeaf {
   static constexpr int NP = 2;
   static constexpr bool kLinear = true;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
+  static constexpr bool kAux = false;       // no per-point tables beside PerTheta
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double m0, im02, c, dm0;  // dm0: 2/m0^3, or 0 when m0 is not differentiated
@@ -723,6 +728,7 @@ struct JohnsonLeaf {
   static constexpr int NP = 4;
   static constexpr bool kLinear = true;
   static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
+  static constexpr bool kAux = false;       // no per-point tables beside PerTheta
   struct C {
     double mu, il, ga, de;
   };
@@ -909,6 +915,7 @@ struct Chi2Leaf {
   static constexpr int NP = 1;
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
+  static constexpr bool kAux = false;       // no per-point tables beside PerTheta
   struct C {
     double km1;  // nu/2 - 1
   };
@@ -987,3 +994,5 @@ static_assert(sizeof(PerTheta::ec[0]) == sizeof(LeafSetup::ec), "leaf constant r
 static_assert(11 <= kLeafConsts && 2 + 8 <= kLeafConsts, "leaf constants");
 
 }  // namespace nllmi
+
+#include "hypatia.h"

@@ -112,6 +112,9 @@ struct Model {
   static constexpr bool WEIGHTED = false;
   // a logarithm per event (the kernels stage g_log_tab)
   static constexpr bool EVENT_LOG = (Slots::Leaf::kEventLog || ...);
+  // a leaf with per-point tables beside PerTheta (at most one)
+  static constexpr bool AUX = (Slots::Leaf::kAux || ...);
+  static_assert(((Slots::Leaf::kAux ? 1 : 0) + ... + 0) <= 1, "at most one leaf with per-point tables");
 
   static_assert(L >= 1 && L <= kMaxLeaves, "1..kMaxLeaves leaves");
   static_assert(K >= 1 && K <= kMaxTerms, "1..kMaxTerms terms");
@@ -132,6 +135,7 @@ struct NonFlat : B {
 // in FP64 instead of being rounded into every event's FP32 value.
 template <class Base>
 struct FP32C : Base {
+  static_assert(!Base::AUX, "no FP32-compensated pass for leaves with per-point tables");
   static constexpr int PREC = 1;
   static constexpr bool EVENT_LOG = false;  // single-precision logarithms of its own
   static constexpr int NCNT = Base::K > 1 ? Base::K - 1 : 0;
@@ -173,13 +177,19 @@ struct Consts {
   int mask[M::K];  // non-root leaves of term k
   const double* etab;
 
-  __device__ void load(const PerTheta& pt, const Plan& pl) {
+  // aux: the per-point tables of a leaf that has them (else unused)
+  __device__ void load(const PerTheta& pt, const Plan& pl, const double* aux) {
     static_for<M::L>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
-      double ec[kLeafConsts];
+      using Leaf = typename M::template S<l>::Leaf;
+      if constexpr (Leaf::kAux) {
+        std::get<l>(leaf) = Leaf::load_aux(aux);
+      } else {
+        double ec[kLeafConsts];
 #pragma unroll
-      for (int j = 0; j < kLeafConsts; ++j) ec[j] = uniform(pt.ec[l][j]);
-      std::get<l>(leaf) = M::template S<l>::Leaf::load(ec);
+        for (int j = 0; j < kLeafConsts; ++j) ec[j] = uniform(pt.ec[l][j]);
+        std::get<l>(leaf) = Leaf::load(ec);
+      }
     });
 #pragma unroll
     for (int k = 0; k < M::K; ++k) {
@@ -407,7 +417,7 @@ struct Consts32 {
   double dck[M::K];  // ck_k - ck_0
   int mask[M::K];
 
-  __device__ void load(const PerTheta& pt, const Plan& pl) {
+  __device__ void load(const PerTheta& pt, const Plan& pl, const double* = nullptr) {
     static_for<M::L>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
       double ec[kLeafConsts];

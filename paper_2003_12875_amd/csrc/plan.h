@@ -24,7 +24,7 @@ constexpr int kMaxObs = 4;
 constexpr int kMaxParams = 32;
 constexpr int kMaxLeaves = 8;
 constexpr int kMaxTerms = 8;
-constexpr int kMaxLeafParams = 8;
+constexpr int kMaxLeafParams = 12;
 constexpr int kLeafConsts = 12;     // per-event constants of one leaf
 constexpr int kMaxSums = 4;
 constexpr int kMaxSumChildren = 8;
@@ -33,7 +33,18 @@ constexpr int kBlock = 256;         // threads per block (4 wave64)
 constexpr int kFinishBlock = 1024;  // threads of the single-dataset finishing kernel
 constexpr int kMaxAcc = 1 + kMaxTerms + kMaxLeaves * kMaxLeafParams;
 
-enum LeafKind : int32_t { kGauss = 1, kExp = 2, kCheb = 3, kCB = 4, kArgus = 5, kJohnson = 8, kChi2 = 9 };
+enum LeafKind : int32_t { kGauss = 1, kExp = 2, kCheb = 3, kCB = 4, kArgus = 5, kJohnson = 8, kChi2 = 9, kHypatia = 10 };
+
+// Hypatia2 per-point tables (at most one such leaf per model; kept beside
+// PerTheta, in LDS or in a per-set device array): Chebyshev interpolants of
+// three functions of log z on up to kHypPanels panels of degree
+// kHypDeg - 1, then scalars and the tails' derivative tables
+constexpr int kHypDeg = 16;
+constexpr int kHypPanels = 8;
+constexpr int kHypCoef = 3 * kHypPanels * kHypDeg;
+constexpr int kHypScal = kHypCoef;          // 32 scalars
+constexpr int kHypTails = kHypCoef + 32;    // 2 x 9 x 3 tail coefficients
+constexpr int kAuxWords = kHypCoef + 32 + 54 + 2;
 enum NormKind : int32_t { kNormAnalytic = 0, kNormGL = 1, kNormGLSingle = 2 };
 
 // Runtime description of one lowered model (kernel argument, by value).

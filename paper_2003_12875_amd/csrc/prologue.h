@@ -219,6 +219,8 @@ __device__ inline void stage_theta(const double* __restrict__ theta_g, int n_par
 // threads); *pt should be LDS (its phases read back what other threads
 // wrote).  All threads of the block must call it; on return *pt is
 // complete and visible to the block.  Phases:
+//   (0) the per-point tables of a leaf that has them (into aux, LDS: all
+//       threads, with barriers);
 //   (1) leaves normalised numerically: one Gauss-Legendre node per thread
 //       (skipped, with its barrier, when every leaf has a closed form);
 //   (2) in parallel: leaf l's constants and closed-form integrals on wave
@@ -228,7 +230,8 @@ __device__ inline void stage_theta(const double* __restrict__ theta_g, int n_par
 //   (3) term constants log w_k - sum log Z over the term's non-root leaves.
 template <class M, int NT = kBlock>
 __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* theta, const double* __restrict__ glx,
-                                 const double* __restrict__ glw, PerTheta* pt, double* lds) {
+                                 const double* __restrict__ glw, PerTheta* pt, double* lds,
+                                 double* aux = nullptr) {
   static_assert(NT >= kGLNodes && NT % 64 == 0, "at least one thread per quadrature node");
   // lanes: leaf l at 64 (l % 4) + 32 (l / 4) (up to 16 each), parameter
   // checks at 144..159 and 176..191, sum checks at 80..84, term weights at
@@ -241,6 +244,20 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
   if (tid == 0) s_bad = 0;
   for (int i = tid; i < kMaxTerms * kMaxParams; i += NT) (&pt->dlogw[0][0])[i] = 0.0;
   __syncthreads();
+
+  // (0)
+  if constexpr (M::AUX) {
+    static_for<M::L>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      using Leaf = typename M::template S<l>::Leaf;
+      if constexpr (Leaf::kAux) {
+        double p[Leaf::NP];
+#pragma unroll
+        for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
+        Leaf::template setup_aux<NT>(p, pl.lo[pl.leaf_obs[l]], pl.hi[pl.leaf_obs[l]], aux);
+      }
+    });
+  }
 
   // (1)
   bool any_gl = false;
@@ -258,7 +275,11 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
         const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
         double v[Leaf::NP + 1];
         if (ok && tid < kGLNodes) {
-          gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
+          if constexpr (Leaf::kAux) {
+            Leaf::gl_norm(aux, lo, hi, glx, glw, v);
+          } else {
+            gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
+          }
         } else {
 #pragma unroll
           for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
@@ -297,7 +318,11 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
       }
       s.Z = 0.0;
       s.kappa = 0.0;
-      if (ok) {
+      if constexpr (Leaf::kAux) {  // constants in the tables; features are d/d parameter
+#pragma unroll
+        for (int j = 0; j < Leaf::NP; ++j) s.fscale[j] = 1.0;
+        if (!Leaf::aux_ok(aux)) atomicOr(&s_bad, 1);
+      } else if (ok) {
         if constexpr (Leaf::kSetupLanes > 1) {
           Leaf::setup_coop(p, lo, hi, analytic, s, lane);
         } else {

@@ -124,9 +124,9 @@ hipError_t op_fit_finish(const VariantOps& self, const Plan& pl, const SingleArg
 }
 
 hipError_t op_consts(const VariantOps& self, const Plan& pl, const double* theta, int n_sets, PerTheta* out,
-                     const double* glx, const double* glw, hipStream_t st) {
+                     double* aux, const double* glx, const double* glw, hipStream_t st) {
   int ns = n_sets;
-  void* args[] = {const_cast<Plan*>(&pl), &theta, &ns, &out, &glx, &glw};
+  void* args[] = {const_cast<Plan*>(&pl), &theta, &ns, &out, &aux, &glx, &glw};
   return launch(R(self).f[kConsts], n_sets, kBlock, 0, st, args);
 }
 
@@ -142,11 +142,12 @@ hipError_t op_sets(const VariantOps& self, const Plan& pl, const SetsArgs& a, bo
 }
 
 hipError_t op_fit_init(const VariantOps& self, const Plan& pl, const double* theta, int n_sets, double eta,
-                       const GDState& gd, PerTheta* consts, const double* glx, const double* glw, hipStream_t st) {
+                       const GDState& gd, PerTheta* consts, double* aux, const double* glx, const double* glw,
+                       hipStream_t st) {
   int ns = n_sets;
   double et = eta;
   GDState g = gd;
-  void* args[] = {const_cast<Plan*>(&pl), &theta, &ns, &et, &g, &consts, &glx, &glw};
+  void* args[] = {const_cast<Plan*>(&pl), &theta, &ns, &et, &g, &consts, &aux, &glx, &glw};
   return launch(R(self).f[kFitInit], n_sets, kBlock, 0, st, args);
 }
 
@@ -201,6 +202,7 @@ std::string leaf_type(int kind, int np) {
     case kArgus: return "nllmi::ArgusLeaf";
     case kJohnson: return "nllmi::JohnsonLeaf";
     case kChi2: return "nllmi::Chi2Leaf";
+    case kHypatia: return "nllmi::HypatiaLeaf";
     default: return "";
   }
 }
@@ -509,6 +511,9 @@ const VariantOps* rtc_variant(const RtcShape& s, int device, nll_status* status,
   for (int l = 0; l < L; ++l) n_nonroot += s.root[l] ? 0 : 1;
   v.flat = (s.K > 1 && n_nonroot == s.K && !s.nonflat) ? 1 : 0;
   v.rtc = r.get();
+  v.aux = 0;
+  for (int l = 0; l < L; ++l)
+    if (s.kind[l] == kHypatia) v.aux = 1;
   v.single = &op_single;
   v.single_fit = &op_single_fit;
   v.fit_finish = &op_fit_finish;

@@ -88,6 +88,7 @@ struct nll_model {
   nllmi::WorkItem* items = nullptr;  // batched work items
   size_t items_cap = 0;
   nllmi::PerTheta* consts = nullptr;
+  double* aux = nullptr;  // sets_cap * kAuxWords: a leaf's per-point tables (models with one)
   size_t set_partials_cap = 0;  // bytes
   double* set_partials = nullptr;
   int gd_cap = 0;
@@ -119,6 +120,7 @@ struct SetsScratch {
   int* set_flag = nullptr;
   WorkItem* items = nullptr;
   PerTheta* consts = nullptr;
+  double* aux = nullptr;  // n_sets * kAuxWords (models with per-point tables)
   double* partials = nullptr;
 };
 // argument checks of the batched evaluation (no device work)

@@ -3,7 +3,8 @@ its scratch in the library's fixed per-GPU device array instead of the
 model's own buffers.  Same kernels and launch schedule as nll_eval_batched,
 so NLL, gradient and status must be the same bits; a few sets are also
 checked against the scalar oracle at the parity tolerances (NLL 1e-12
-relative, gradient 1e-8 of the oracle's max-norm).  Two calls in a row, the
+relative, gradient 1e-8 of the oracle's max-norm), for a two-component
+mixture and for a Hypatia2 leaf (whose per-set tables also live there).  Two calls in a row, the
 second with fewer sets over fewer events, and a request larger than the
 array refused before anything is enqueued."""
 import ctypes
@@ -54,24 +55,40 @@ def _call(torch, L, fn, model, offsets, theta, grad=True):
     return rc, nll.cpu().numpy(), (g.cpu().numpy() if grad else None), st.cpu().numpy()
 
 
-def test_noalloc_matches_batched_and_oracle(torch, nllmi, threads):
+def _hypatia_spec():
+    """A Hypatia2 leaf (its per-set Bessel tables also live in the array)."""
+    P = datagen.param
+    return {"obs": [{"name": "m", "lo": -8.0, "hi": 8.0}],
+            "params": [P("mu", 0.0, -8.0, 8.0, jitter=0.05), P("sigma", 1.0, 1e-6, 100.0, jitter=0.05),
+                       P("lambda", -1.2, -6.0, 6.0, jitter=0.06), P("zeta", 0.05, 1e-3, 100.0, jitter=0.0025),
+                       P("beta", 0.1, -50.0, 50.0, jitter=0.02), P("a_l", 1.5, 0.05, 20.0, jitter=0.075),
+                       P("n_l", 2.0, 1.001, 100.0, jitter=0.1), P("a_r", 1.8, 0.05, 20.0, jitter=0.09),
+                       P("n_r", 6.0, 1.001, 100.0, jitter=0.3)],
+            "nodes": [{"kind": "hypatia", "obs": 0, "params": list(range(9))}], "root": 0}
+
+
+@pytest.mark.parametrize("model", ["mixture", "hypatia"])
+def test_noalloc_matches_batched_and_oracle(torch, nllmi, threads, model):
     L = nllmi.lib()
-    spec = datagen.mixture_spec()
+    spec = datagen.mixture_spec() if model == "mixture" else _hypatia_spec()
     offsets = _sets(71, 700, 1, 20_000)  # uneven sets, several tiles each, ragged tails
     n = int(offsets[-1])
     cols = datagen.generate(spec, n, seed=72)
     m = nllmi.Model.from_spec(spec)
     m.set_data([torch.from_numpy(c).cuda() for c in cols])
-    base = np.array([p["value"] for p in spec["params"]])
-    rng = np.random.default_rng(73)
-    theta = base * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, (700, len(base))))
+    if model == "mixture":
+        base = np.array([p["value"] for p in spec["params"]])
+        rng = np.random.default_rng(73)
+        theta = base * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, (700, len(base))))
+    else:
+        theta = datagen.parameter_points(spec, 700, seed=73)
     o = oracle.Oracle(spec)
     # first call: all 700 sets; second: 90 sets over the first part of the
     # events (fewer sets, fewer events, the array keeps the first call's data)
     small = _sets(74, 90, 0, 3_000)
     assert small[-1] <= n
     for step, (off, th) in enumerate(((offsets, theta), (small, theta[:90]))):
-        print(f"[noalloc call {step}: {len(off) - 1} sets, {int(off[-1])} events]", flush=True)
+        print(f"[noalloc {model} call {step}: {len(off) - 1} sets, {int(off[-1])} events]", flush=True)
         for grad in (False, True):  # the gradient run last: its results are checked below
             rc_a, nll_a, g_a, st_a = _call(torch, L, "nll_eval_batched_noalloc", m, off, th, grad)
             rc_b, nll_b, g_b, st_b = _call(torch, L, "nll_eval_batched", m, off, th, grad)
