@@ -710,6 +710,32 @@ def extras(torch, nllmi, datagen, args, parity):
                       "schedule": m.schedule}
     del m
     torch.cuda.empty_cache()
+    # Hypatia2 peak over an exponential background (the two-sided Hypatia
+    # of Sec. 3), 1e7 events, all 11 parameters free: NLL+gradient and NLL
+    # alone, the per-point table build included in every launch; parity
+    # against the oracle on the first 2e5 events at two points
+    w = datagen.hypatia_workload()
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(m.n_param, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: m.eval_grad(th, out=out, grad=g), 20)
+    tf = time_launches(torch, lambda: m.eval(th, out=out), 20)
+    ex["hypatia_exp_1e7"] = {"variant": m.info["variant"], "n_events": w["n"], "eval_grad_ms": tg, "eval_ms": tf,
+                             "events_per_s": w["n"] / (tg * 1e-3),
+                             "achieved_GBs": 8.0 * w["n"] / (tg * 1e-3) / 1e9,
+                             "hbm_frac": 8.0 * w["n"] / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "schedule": m.schedule, "status": m.sync()}
+    del m
+    n_par = 200_000
+    sub = [c[:n_par] for c in w["cols"]]
+    m = nllmi.Model.from_spec(w["spec"])
+    m.set_data([torch.from_numpy(c).cuda() for c in sub])
+    vals = [(float(a.item()), b.cpu().numpy()) for a, b in (m.eval_grad(torch.from_numpy(p)) for p in w["points"][:2])]
+    parity.check("hypatia_exp_2e5", w["spec"], sub, w["points"][:2], vals, n_par)
+    del m
+    torch.cuda.empty_cache()
     # binned template likelihood of HistFactory type: 2e6 bins, 4 samples,
     # 16 histosys, 4 normsys, 2 normfactors (22 parameters); HBM-bound,
     # 8 (1 + 4 + 16) bytes per bin
@@ -812,16 +838,66 @@ def probe_pmc_2d(torch, nllmi, datagen, reps):
     log(f"probe: {reps} NLL+gradient evaluations of the 2-D model done ({m.schedule})")
 
 
+# How each committed summary is made (from the repository root; the
+# profiler runs from /tmp with TMPDIR=/tmp, paths below relative to the root)
+PROFILE_COMMANDS = {
+    "trace": ["rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_toys -o toys -- "
+              "python3 bench.py --quick --no-cpu-baseline --steps 50 --warmup 5",
+              "python3 bench.py --summarize-trace gpurun_out/trace_toys --workload-name '<workload>'"],
+    "pmc": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o f -- python3 bench.py --probe pmc",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o w -- python3 bench.py --probe pmc",
+            "python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write --kernel <toys|mixture>"],
+    "valu": ["rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
+             "SQ_INSTS_VALU_TRANS_F64 SQ_WAVES --output-format csv -d gpurun_out/pmc_valu -o v -- "
+             "python3 bench.py --probe pmc",
+             "python3 bench.py --summarize-valu gpurun_out/pmc_valu"],
+    "counters": ["rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES "
+                 "SQ_WAVE_CYCLES GRBM_GUI_ACTIVE --output-format csv -d gpurun_out/pmc_2d -o c -- "
+                 "python3 bench.py --probe pmc-2d",
+                 "python3 bench.py --summarize-counters gpurun_out/pmc_2d 'k_single<'"],
+}
+
+
+def print_commands(kind):
+    print("Made by (repository root; the profiler itself run from /tmp with TMPDIR=/tmp):\n")
+    for c in PROFILE_COMMANDS[kind]:
+        print(f"    {c}")
+    print()
+
+
+N_SIMD, N_XCD, N_EVENTS_2D = 256 * 4, 8, 50_000_000
+
+
 def summarize_counters(d, pattern):
     """Average of every counter per dispatch of the kernels whose name
-    contains `pattern` (one line per kernel and counter)."""
+    contains `pattern` (one line per kernel and counter), and the derived
+    issue figures of the 2-D model's NLL+gradient kernel."""
     rows = [r for r in _csv_rows(d, "_counter_collection.csv") if pattern in r["Kernel_Name"]]
     agg = {}
     for r in rows:
         agg.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    print("# SQ counters of the 2-D model's NLL+gradient kernel: (0.1 CB + 0.9 ARGUS)(m) x Cheb4(y), "
+          "5e7 FP64 events x 2 observables\n")
+    print_commands("counters")
     print(f"- csrc_sha256: `{csrc_hash()}`")
     for (k, c), v in sorted(agg.items()):
         print(f"- `{_short(k)}` {c}: {sum(v) / len(v):.6e} (dispatches {len(v)})")
+    kernels = sorted({k for k, _ in agg})
+    for k in kernels:
+        a = {c: sum(v) / len(v) for (kk, c), v in agg.items() if kk == k}
+        if not all(c in a for c in ("SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU")):
+            continue
+        # GRBM_GUI_ACTIVE reads the sum over the XCDs (8 x the kernel's cycles)
+        cyc = a["GRBM_GUI_ACTIVE"] / N_XCD
+        print(f"\nDerived, `{_short(k)}`:\n")
+        print(f"- gpu_cycles_per_xcd: {cyc:.4e} ({cyc / 2.4e3:.1f} us at 2.4 GHz)")
+        print(f"- valu_busy: {a['SQ_ACTIVE_INST_VALU'] * 4 / N_SIMD / cyc:.3f}"
+              "  (SQ_ACTIVE_INST_VALU x 4 / 1024 SIMDs / cycles)")
+        print(f"- valu_issue_4cyc: {a['SQ_INSTS_VALU'] * 4 / N_SIMD / cyc:.3f}"
+              "  (SQ_INSTS_VALU x 4 cycles per wave64 instruction / 1024 SIMDs / cycles)")
+        print(f"- valu_lane_instructions_per_event: {64.0 * a['SQ_INSTS_VALU'] / N_EVENTS_2D:.1f}")
+        if "SQ_INSTS_SALU" in a:
+            print(f"- salu_instructions_per_wave_instruction_valu: {a['SQ_INSTS_SALU'] / a['SQ_INSTS_VALU']:.3f}")
 
 
 def _csv_rows(d, suffix):
@@ -848,6 +924,7 @@ def summarize_trace(d, workload):
         agg.setdefault(r["Kernel_Name"], []).append(dt)
     tot = sum(sum(v) for v in agg.values())
     print(f"# Kernel durations: {workload}\n")
+    print_commands("trace")
     print(f"- csrc_sha256: `{csrc_hash()}`\n")
     print("| kernel | calls | total us | avg us | median us | min us | max us | % |")
     print("|---|---|---|---|---|---|---|---|")
@@ -905,6 +982,7 @@ def summarize_pmc(fetch_dir, write_dir, which):
     print("Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own run, scaled by")
     print(f"the same counter on the calibration kernel (elementwise negation, {COPY_BYTES} bytes read and written).")
     print("Averaged over the launches that streamed the events.\n")
+    print_commands("pmc")
     print(f"- kernel: `{_short(kk)}`")
     print(f"- csrc_sha256: `{csrc_hash()}`")
     print(f"- dispatches: {len(kf_all)} ({len(kf)} streamed)")
@@ -933,6 +1011,7 @@ def summarize_valu(d):
     print("SQ instruction counters (wave instructions per dispatch, all CUs), one run, averaged over the")
     print("launches that streamed the events. Lane-instructions = 64 x wave instructions (wave64);")
     print("FP64 FLOPs = 64 x (2 FMA + ADD + MUL + TRANS).\n")
+    print_commands("valu")
     print(f"- kernel: `{_short(kk)}`")
     print(f"- csrc_sha256: `{csrc_hash()}`")
     print(f"- dispatches: {len(valu_all)} ({len(idx)} streamed)")

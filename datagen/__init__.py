@@ -433,6 +433,39 @@ def johnson_workload(n: int = 10_000_000, single: bool = False, n_points: int = 
             "points": parameter_points(spec, n_points, JOHNSON_SEED + 1), "seed": JOHNSON_SEED}
 
 
+def hypatia_spec(f=0.4, lo=5.20, hi=5.35):
+    """f * Hypatia2(m; 5.28, 0.003, -2, 0.5, 0, 2, 3, 2.5, 4) + (1 - f) *
+    Exp(m; -1.5) on m in [5.20, 5.35]: a B-mass-like peak with power-law
+    tails on both sides (the use the two-sided Hypatia is made for) over a
+    falling background.  Parameters (f, mu, sigma, lambda, zeta, beta, a_l,
+    n_l, a_r, n_r, c), all free; seeded points jitter each by a few per cent
+    of the scale it acts on."""
+    sg = 0.003
+    return {"obs": [{"name": "m", "lo": lo, "hi": hi}],
+            "params": [param("f", f, 0.0, 1.0, jitter=0.02), param("mu", 5.28, lo, hi, jitter=0.05 * sg),
+                       param("sigma", sg, 1e-5, 0.1, jitter=0.05 * sg), param("lambda", -2.0, -6.0, 6.0, jitter=0.1),
+                       param("zeta", 0.5, 1e-3, 100.0, jitter=0.025), param("beta", 0.0, -500.0, 500.0, jitter=0.02 / sg),
+                       param("a_l", 2.0, 0.05, 20.0, jitter=0.1), param("n_l", 3.0, 1.001, 100.0, jitter=0.15),
+                       param("a_r", 2.5, 0.05, 20.0, jitter=0.125), param("n_r", 4.0, 1.001, 100.0, jitter=0.2),
+                       param("c", -1.5, -50.0, 50.0, jitter=0.15)],
+            "nodes": [{"kind": "hypatia", "obs": 0, "params": list(range(1, 10))},
+                      {"kind": "exp", "obs": 0, "params": [10]},
+                      {"kind": "sum", "params": [0], "children": [0, 1]}],
+            "root": 2}
+
+
+HYPATIA_SEED = MASTER_SEED + 10000
+
+
+def hypatia_workload(n: int = 10_000_000, n_points: int = 4, threads: int | None = None) -> dict:
+    """hypatia_spec() with n events: data seed master + 10000, parameter-point
+    seed one more."""
+    spec = hypatia_spec()
+    cols = generate(spec, n, HYPATIA_SEED, threads=threads)
+    return {"spec": spec, "cols": cols, "n": n, "theta": theta_of(spec),
+            "points": parameter_points(spec, n_points, HYPATIA_SEED + 1), "seed": HYPATIA_SEED}
+
+
 CHI2_SEED = MASTER_SEED + 7000
 
 
