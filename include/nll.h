@@ -397,8 +397,10 @@ const char* nll_status_string(nll_status status);
 
 /* Measurement utility: enqueue one read of n doubles at x (device, 16-byte
  * aligned) on `stream` (hipStream_t, NULL: default) by a streaming kernel of
- * n_blocks blocks of 256 threads (16-byte loads, four in flight per
- * thread); block b writes the sum of the values it read to block_sums[b]
+ * n_blocks blocks of 256 threads (the likelihood kernels' pattern: tiles
+ * of 8 x 256 consecutive doubles round robin over the blocks, two tiles of
+ * non-temporal loads in flight ahead); block b writes the sum of the values
+ * it read to block_sums[b]
  * (device [n_blocks]).  Timed by the caller, it gives the HBM read rate a
  * streaming pass reaches on the device, next to the data sheet's peak
  * (the likelihood kernels read their event columns the same way, Sec. 5.2).

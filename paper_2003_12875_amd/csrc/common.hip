@@ -187,27 +187,39 @@ hipError_t launch_check_range(const double* x, int64_t n, double lo, double hi, 
   return hipGetLastError();
 }
 
-// Read-bandwidth probe: streams n doubles once (16-byte loads, four in
-// flight per thread, grid-stride over a persistent grid) and writes one sum
-// per block, so that the loads cannot be dropped.  Measures the HBM read
-// rate a streaming kernel can reach on this device, the yardstick next to
-// the data sheet's peak.
+// Read-bandwidth probe: streams n doubles once with the streaming kernels'
+// access pattern and load policy but no arithmetic (tiles of 8 x 256
+// consecutive doubles, round robin over a persistent grid, loads two tiles
+// ahead, non-temporal) and writes one sum per block, so that the loads
+// cannot be dropped.  Measures the HBM read rate a streaming kernel can
+// reach on this device, the yardstick next to the data sheet's peak.
 __global__ __launch_bounds__(kBlock) void k_read_probe(const double* __restrict__ x, int64_t n,
                                                       double* __restrict__ out) {
-  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
-  const int64_t n2 = n / 2;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  constexpr int U = 8;
+  const int64_t tile = (int64_t)kBlock * U, ntile = n / tile, G = gridDim.x;
+  auto ld = [&](int64_t t, int u) -> double {
+    return t < ntile ? __builtin_nontemporal_load(&x[t * tile + (int64_t)u * kBlock + threadIdx.x]) : 0.0;
+  };
   double acc = 0.0;
-  for (; i + 3 * stride < n2; i += 4 * stride) {
-    const double2 a = x2[i], b = x2[i + stride], c = x2[i + 2 * stride], d = x2[i + 3 * stride];
-    acc += ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+  double r0[U], r1[U], r2[U];
+  int64_t tl = blockIdx.x;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    r0[u] = ld(tl, u);
+    r1[u] = ld(tl + G, u);
   }
-  for (; i < n2; i += stride) {
-    const double2 a = x2[i];
-    acc += a.x + a.y;
+  for (; tl < ntile; tl += G) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) r2[u] = ld(tl + 2 * G, u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += r0[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      r0[u] = r1[u];
+      r1[u] = r2[u];
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) acc += x[n - 1];
+  for (int64_t i = ntile * tile + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += G * kBlock) acc += x[i];
   __shared__ double s[kBlock];
   s[threadIdx.x] = acc;
   __syncthreads();

@@ -460,12 +460,27 @@ __device__ inline double bhhh_update(const Plan& pl, const GDState& gd, int st, 
 // ------------------------------------------------------------------------
 // per-tile event loops
 // ------------------------------------------------------------------------
-template <class M, int U>
+// Event loads.  NT: non-temporal (the nt bit), for passes over more data
+// than the last-level cache holds: a plain read over 4 GiB reaches
+// ~7.3 TB/s on MI355X with it against ~6.4 TB/s with the default policy;
+// data that stay cache-resident between passes (a single dataset of tens
+// of MB evaluated again and again by a minimiser) are read faster with the
+// default policy (the 1e7-event mixture's pass: ~5 % slower with NT).
+template <bool NT>
+__device__ __forceinline__ double ld_event(const double* p) {
+  if constexpr (NT) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
+
+template <class M, int U, bool NT = false>
 __device__ inline void load_tile(const double* const* cols, int64_t base, double (&x)[U][M::NOBS]) {
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int o = 0; o < M::NOBS; ++o) x[u][o] = cols[o][base + (int64_t)u * kBlock];
+    for (int o = 0; o < M::NOBS; ++o) x[u][o] = ld_event<NT>(&cols[o][base + (int64_t)u * kBlock]);
 }
 
 template <class M, bool GRAD, int U, class CT, class AT>
@@ -481,46 +496,52 @@ __device__ inline void compute_tile(const double (&x)[U][M::NOBS], const CT& C, 
 // arrive preloaded in xb[0 .. R-2], and before tile k is computed the loads
 // of tile k + R - 1 are issued into the buffer that tile k - 1 used, so each
 // load has R - 1 tiles of compute to arrive.  The ring is unrolled (buffers
-// rotate without copies) and its loads are unconditional: past the last
-// tile they re-read the last one (a cache hit, never used), so the loop body
-// has no branches and the compiler's load-counter waits see every load of
-// the ring in flight.  Three buffers for shapes with at most 8 accumulators;
-// two for the heavier ones, whose registers are already scarce (measured:
-// three cost the 2-D model ~4-5 %, two cost the mixture at 1e8 events ~18 %).
+// rotate without copies).  The main loop runs over groups of R tiles whose
+// loads all stay in range, with no branches, so that the compiler's
+// load-counter waits see every load of the ring in flight; the last tiles
+// (fewer than 2R) test their loads one by one.  Three buffers for shapes
+// with at most 8 accumulators; two for the heavier ones, whose registers
+// are already scarce (measured: three cost the 2-D model ~4-5 %, two cost
+// the mixture at 1e8 events ~18 %).
 template <class M>
 constexpr int ring_depth() {
   return M::template NA<true> <= 8 ? 3 : 2;
 }
 
-template <class M, int U, int R>
+template <class M, int U, int R, bool NT = false>
 __device__ inline void preload_ring(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
                                     double (&xb)[R][U][M::NOBS]) {
 #pragma unroll
   for (int j = 0; j < R - 1; ++j)
-    if (j < count) load_tile<M, U>(cols, base0 + j * stride, xb[j]);
+    if (j < count) load_tile<M, U, NT>(cols, base0 + j * stride, xb[j]);
 }
 
-template <class M, bool GRAD, int U, int R, class CT, class AT>
+template <class M, bool GRAD, int U, int R, bool NT = false, class CT, class AT>
 __device__ inline void stream_tiles(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
                                     double (&xb)[R][U][M::NOBS], const CT& C, AT& acc) {
-  const int64_t groups = count / R;
-  for (int64_t g = 0; g < groups; ++g) {
+  // tile k sits in xb[k % R]; groups g < safe load tiles up to
+  // safe * R + R - 2 <= count - 1
+  const int64_t safe = count >= R - 1 ? (count - (R - 1)) / R : 0;
+  for (int64_t g = 0; g < safe; ++g) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int64_t k = g * R + j;
-      const int64_t kl = k + R - 1 < count ? k + R - 1 : count - 1;
-      load_tile<M, U>(cols, base0 + kl * stride, xb[(j + R - 1) % R]);
+      load_tile<M, U, NT>(cols, base0 + (k + R - 1) * stride, xb[(j + R - 1) % R]);
       compute_tile<M, GRAD, U>(xb[j], C, acc);
     }
   }
-  // tiles groups * R + j, j < count % R, are in xb[j]
-  const int64_t rem = count - groups * R;
+  // the remaining count - safe * R <= 2R - 2 tiles
 #pragma unroll
-  for (int j = 0; j < R - 1; ++j)
-    if (j < rem) compute_tile<M, GRAD, U>(xb[j], C, acc);
+  for (int j = 0; j < 2 * R - 2; ++j) {
+    const int64_t k = safe * R + j;
+    if (k < count) {
+      if (k + R - 1 < count) load_tile<M, U, NT>(cols, base0 + (k + R - 1) * stride, xb[(j + R - 1) % R]);
+      compute_tile<M, GRAD, U>(xb[j % R], C, acc);
+    }
+  }
 }
 
-template <class M, bool GRAD, int U, class CT, class AT>
+template <class M, bool GRAD, int U, bool NT = false, class CT, class AT>
 __device__ inline void stream_part_tile(const double* const* cols, int64_t base, int64_t end, const CT& C,
                                         AT& acc) {
   acc.begin_tile();
@@ -530,7 +551,7 @@ __device__ inline void stream_part_tile(const double* const* cols, int64_t base,
     if (i < end) {
       double x[M::NOBS];
 #pragma unroll
-      for (int o = 0; o < M::NOBS; ++o) x[o] = cols[o][i];
+      for (int o = 0; o < M::NOBS; ++o) x[o] = ld_event<NT>(&cols[o][i]);
       model_event<M, GRAD>(x, C, acc);
     }
   }
@@ -823,8 +844,14 @@ __global__ __launch_bounds__(kBlock) void k_consts(const Plan pl, const double* 
   if constexpr (M::AUX) copy_aux<kBlock>(aux_out + (size_t)s * kAuxWords, s_aux);
 }
 
+// items and consts also come as kernel arguments of their own: read-only
+// and not aliased by anything the kernel writes, their uniform loads (item
+// descriptors, a set's constants) go through the scalar unit and do not
+// make the vector-load counter waits drain the ring.
 template <class M, bool GRAD, int U>
-__global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a) {
+__global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a,
+                                                 const WorkItem* __restrict__ items,
+                                                 const PerTheta* __restrict__ consts) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
   __shared__ double red[NV * (kBlock + 1)];
@@ -840,43 +867,128 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
   if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
   if constexpr (CT::kExpTab || M::EVENT_LOG) __syncthreads();
 
-  // the next item's descriptor is loaded while the current one streams
-  int64_t item = blockIdx.x;
-  WorkItem cur{0, 0, 0, 0};
-  if (item < total) cur = a.items[item];
-  while (item < total) {
-    const int64_t nxt = item + gridDim.x;
-    WorkItem next = cur;
-    if (nxt < total) next = a.items[nxt];
-    const int s = cur.set;
-    const PerTheta& pt = a.consts[s];
-    const int64_t start = cur.start, end = cur.end;
+  // The block's items form one sequence of tiles (an item of len events has
+  // max(1, ceil(len / (256 U))) tiles, its last one partial), streamed
+  // through one ring of R register buffers that runs across item
+  // boundaries: a load cursor issues the loads of tile k + R - 1 while a
+  // compute cursor evaluates tile k, so loads stay in flight through an
+  // item's last tiles, its block reduction and the switch to the next
+  // item's constants.  Every tile issues its U x NOBS loads unconditionally
+  // (lanes past an item's end, empty items and the ring's run-out read a
+  // dummy word of the Gauss-Legendre table), so that the compiler's
+  // load-counter waits see the whole ring in flight; events past an item's
+  // end are masked in the arithmetic.  Non-temporal loads: the sets
+  // together are read once per pass (a batch of toys is GBs).
+  constexpr int R = ring_depth<M>();
+  const int64_t step = (int64_t)kBlock * U;
+  const int64_t G = gridDim.x;
+  const double* dummy = a.glx;
+  auto ntiles = [&](const WorkItem& w) -> int64_t {
+    const int64_t len = w.end - w.start;
+    return len > 0 ? (len + step - 1) / step : 1;
+  };
+  double xb[R][U][M::NOBS];
 
+  // load cursor (R - 1 tiles ahead of the compute cursor)
+  int64_t l_item = blockIdx.x, l_tile = 0, l_T = 1;
+  WorkItem l_w{0, 0, 0, 0}, l_next{0, 0, 0, 0};
+  if (l_item < total) {
+    l_w = items[l_item];
+    l_T = ntiles(l_w);
+  }
+  if (l_item + G < total) l_next = items[l_item + G];
+  auto issue = [&](double (&buf)[U][M::NOBS]) {
+    const int64_t base = l_w.start + l_tile * step + threadIdx.x;
+    const bool live = l_item < total;
+    const bool full = live && l_w.end - (l_w.start + l_tile * step) >= step;
+    const double* ptr[U][M::NOBS];
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int o = 0; o < M::NOBS; ++o) ptr[u][o] = cols[o] + base + (int64_t)u * kBlock;
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock;
+        const bool ok = live && i < l_w.end;
+#pragma unroll
+        for (int o = 0; o < M::NOBS; ++o) ptr[u][o] = ok ? cols[o] + i : dummy;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int o = 0; o < M::NOBS; ++o) buf[u][o] = ld_event<true>(ptr[u][o]);
+    if (live && ++l_tile == l_T) {
+      l_item += G;
+      l_w = l_next;
+      l_T = ntiles(l_w);
+      l_tile = 0;
+      if (l_item + G < total) l_next = items[l_item + G];
+    }
+  };
+
+  // compute cursor
+  int64_t c_item = blockIdx.x, c_tile = 0, c_T = 1;
+  WorkItem c_w{0, 0, 0, 0}, c_next{0, 0, 0, 0};
+  CT C;
+  bool skip = true;
+  typename Pass<M, GRAD>::A acc;
+  acc.init();
+  auto enter = [&]() {  // constants of item c_item (block-uniform)
+    c_T = ntiles(c_w);
+    c_tile = 0;
+    if (c_item + G < total) c_next = items[c_item + G];
+    const PerTheta& pt = consts[c_w.set];
     if constexpr (M::AUX) {  // the previous item's reads ended in its block sum
-      copy_aux<kBlock>(s_aux, a.aux + (size_t)s * kAuxWords);
+      copy_aux<kBlock>(s_aux, a.aux + (size_t)c_w.set * kAuxWords);
       __syncthreads();
     }
-    CT C;
     C.load(pt, pl, s_aux);
     C.etab = s_etab;
-    typename Pass<M, GRAD>::A acc;
+    skip = uniform(pt.bad) != 0 || c_w.flag != 0;
     acc.init();
-    if (uniform(pt.bad) == 0 && cur.flag == 0) {
-      const int64_t step = (int64_t)kBlock * U;
-      const int64_t full = (end - start) / step;
-      double xb[ring_depth<M>()][U][M::NOBS];
-      preload_ring<M, U>(cols, start + threadIdx.x, step, full, xb);
-      stream_tiles<M, GRAD, U>(cols, start + threadIdx.x, step, full, xb, C, acc);
-      const int64_t base = start + full * step;
-      if (base < end) stream_part_tile<M, GRAD, U>(cols, base + threadIdx.x, end, C, acc);
+  };
+  if (c_item < total) {
+    c_w = items[c_item];
+    enter();
+  }
+
+#pragma unroll
+  for (int j = 0; j < R - 1; ++j) issue(xb[j]);
+  while (c_item < total) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      issue(xb[(j + R - 1) % R]);
+      if (c_item < total) {
+        if (!skip) {
+          const int64_t t0 = c_w.start + c_tile * step;
+          if (c_w.end - t0 >= step) {
+            compute_tile<M, GRAD, U>(xb[j], C, acc);
+          } else {
+            acc.begin_tile();
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              if (t0 + threadIdx.x + (int64_t)u * kBlock < c_w.end) model_event<M, GRAD>(xb[j][u], C, acc);
+            acc.end_tile();
+          }
+        }
+        if (++c_tile == c_T) {  // the item's record
+          double v[NV];
+          acc.finalize(reinterpret_cast<double(&)[NA]>(v));
+          v[NA] = (double)acc.bad;
+          block_sum_vals<NV, kBlock>(v, red, tot);
+          if (threadIdx.x < NV)
+            reinterpret_cast<DD*>(a.partials)[(size_t)c_item * NV + threadIdx.x] = tot[threadIdx.x];
+          c_item += G;
+          if (c_item < total) {
+            c_w = c_next;
+            enter();
+          }
+        }
+      }
     }
-    double v[NV];
-    acc.finalize(reinterpret_cast<double(&)[NA]>(v));
-    v[NA] = (double)acc.bad;
-    block_sum_vals<NV, kBlock>(v, red, tot);
-    if (threadIdx.x < NV) reinterpret_cast<DD*>(a.partials)[(size_t)item * NV + threadIdx.x] = tot[threadIdx.x];
-    cur = next;
-    item = nxt;
   }
 }
 

@@ -24,11 +24,9 @@ inline size_t pad_lds(const void* kernel, int lds_cap) {
 
 template <class M>
 struct Launch {
-  // events per thread per tile: 2, 4, or 8 (8 only for shapes with few
-  // accumulators, where the extra registers do not cost occupancy)
   // events per thread per tile compiled for this shape: {2, 4, 8}, or
-  // {2, 4} for shapes with more than 8 accumulators (registers); 8 maps to
-  // 4 there
+  // {2, 4} for weighted shapes and shapes with more than 8 accumulators
+  // (registers); 8 maps to 4 there
   static constexpr bool kU8 = !M::WEIGHTED && M::NA_GRAD <= 8;
   static int pick_u(int unroll) { return unroll >= 8 && kU8 ? 8 : unroll >= 4 ? 4 : 2; }
 
@@ -137,9 +135,11 @@ struct Launch {
     const void* k = reinterpret_cast<const void*>(&k_sets<M, GRAD, U>);
     if (ev0 && ev1)
       hipExtLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), (uint32_t)pad_lds(k, lds_cap), st, ev0,
-                            ev1, 0u, pl, a);
+                            ev1, 0u, pl, a, static_cast<const WorkItem*>(a.items),
+                            static_cast<const PerTheta*>(a.consts));
     else
-      hipLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a);
+      hipLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a,
+                         static_cast<const WorkItem*>(a.items), static_cast<const PerTheta*>(a.consts));
   }
   template <bool GRAD>
   static void sets_u(const Plan& pl, const SetsArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,

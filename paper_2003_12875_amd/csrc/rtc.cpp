@@ -134,8 +134,11 @@ hipError_t op_sets(const VariantOps& self, const Plan& pl, const SetsArgs& a, bo
                    int grid, int lds_cap, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const RtcModule& r = R(self);
   hipFunction_t f = r.f[kSets + 2 * ((grad || fit) ? 1 : 0) + u_index(unroll)];
+  const WorkItem* items = a.items;
+  const PerTheta* consts = a.consts;
+  void* sargs[] = {const_cast<Plan*>(&pl), const_cast<SetsArgs*>(&a), &items, &consts};
+  hipError_t e = launch(f, grid, kBlock, pad(f, lds_cap), st, sargs, ev0, ev1);
   void* args[] = {const_cast<Plan*>(&pl), const_cast<SetsArgs*>(&a)};
-  hipError_t e = launch(f, grid, kBlock, pad(f, lds_cap), st, args, ev0, ev1);
   if (e != hipSuccess) return e;
   hipFunction_t fin = r.f[kSetsFinish + (fit ? 0 : grad ? 1 : 2)];
   return launch(fin, a.n_sets > 0 ? a.n_sets : 1, kBlock, 0, st, args);

@@ -112,12 +112,12 @@ nll_status tune_model(nll_model* m, int which, int n_sets, const int64_t* offset
     std::vector<nll_schedule> cands;
     if (which == 1) {
       for (int u : {2, 4, 8})
-        for (int b : {1, 2, 4, 8, 16})
+        for (int b : {1, 2, 3, 4, 8, 16})
           cands.push_back(nll_schedule{u, b, base.tile_events, base.sets_blocks_per_cu, base.sets_unroll});
     } else {
       for (int u : {2, 4, 8})
         for (int t : {8192, 16384, 32768, 65536})
-          for (int b : {2, 4, 8, 16}) cands.push_back(nll_schedule{base.unroll, base.blocks_per_cu, t, b, u});
+          for (int b : {2, 3, 4, 8, 16}) cands.push_back(nll_schedule{base.unroll, base.blocks_per_cu, t, b, u});
     }
     Timer tm;
     for (const nll_schedule& c : cands) {
