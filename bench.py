@@ -67,7 +67,7 @@ COPY_BYTES = 1 << 30  # calibration kernel: reads and writes 1 GiB
 REPS = 5              # timed replays of the K-step headline fit (median reported)
 # the fastest of the autotuner's candidates for the 4096-toy workload (a
 # sweep of them on MI355X), fixed so that the profiled kernel is the timed one
-TOYS_SCHEDULE = {"tile_events": 16384, "sets_blocks_per_cu": 3, "sets_unroll": 8}
+TOYS_SCHEDULE = {"tile_events": 32768, "sets_blocks_per_cu": 4, "sets_unroll": 8}
 KERNELS = {
     # name: (summary files, kernel-name test, algorithmic bytes per launch, workload)
     "toys": ("k_sets_gauss_4096toys", lambda k: "k_sets<" in k, None,

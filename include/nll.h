@@ -252,13 +252,16 @@ nll_status nll_eval_batched(nll_model* model, int32_t n_sets, const int64_t* off
  * buffers; the array is looked up (hipGetSymbolAddress) on the first call
  * on each device.  It needs
  *   align256(8 (n_sets + 1)) + align256(4 n_sets) + align256(24 I)
- *   + align256(C n_sets) + align256(T n_sets) + I * 16 (A + 1)  bytes,
- * with I = n_events / tile_events + n_sets + 1 work items, C the per-set
+ *   + align256(8 (H + 1)) + align256(C n_sets) + align256(T n_sets)
+ *   + I * 16 (A + 1)  bytes,
+ * with H = G ceil(n_events / (G tile_events)) chunks of the batched pass
+ * (G = n_cu * sets_blocks_per_cu), I = n_sets + H + 1 work items (a set's
+ * parts in the chunks), C the per-set
  * constant block and T the per-set tables of a Hypatia2 leaf (0 without
  * one; C + T is nll_info's per_set_bytes), and A the model's
  * accumulators (n_accumulators); a larger request returns NLL_ERR_SCRATCH
  * before anything is enqueued (4096 sets over 4.1e8 events of a one-leaf
- * model need about 24 MB).  Every word the pass reads is written earlier
+ * model need about 22 MB).  Every word the pass reads is written earlier
  * in the same call, so nothing has to start at zero.  All calls on one GPU
  * share the array: calls that overlap on that GPU (other models, other
  * streams, other host threads) race and must be serialised by the caller;
@@ -339,8 +342,13 @@ typedef struct nll_schedule {
                                  falls back to 4 for shapes with more than 8
                                  accumulators)                              */
   int32_t blocks_per_cu;      /* persistent grid = CUs * blocks_per_cu     */
-  int32_t tile_events;        /* batched: events per (set, tile) work item */
-  int32_t sets_blocks_per_cu; /* batched: grid = CUs * sets_blocks_per_cu  */
+  int32_t tile_events;        /* batched: events per chunk; the attached
+                                 events are cut into rounds of G chunks,
+                                 block b streams the b-th chunk of every
+                                 round (the last round's G chunks split
+                                 what remains equally); nll_eval_points:
+                                 events per (point, tile) work item        */
+  int32_t sets_blocks_per_cu; /* batched: grid G = CUs * sets_blocks_per_cu */
   int32_t sets_unroll;        /* batched: events per thread per tile, as
                                  unroll                                     */
 } nll_schedule;

@@ -44,6 +44,27 @@ struct SingleArgs {
                                 // fit's constants in consts (first step, BHHH steps)
 };
 
+// The chunks of the batched pass: the events [0, n) in K rounds of G
+// chunks, chunk j = r G + b streamed by block b in round r.  Rounds
+// 0 .. K-2 have chunks of C events; the last round splits the remaining
+// L = n - base events, base = (K - 1) G C, into G equal shares.
+struct ChunkGrid {
+  int64_t n, C, base, L;
+  int32_t G, K;
+};
+#ifndef __HIPCC_RTC__
+inline ChunkGrid make_chunk_grid(int64_t n, int G, int64_t C) {
+  ChunkGrid g;
+  g.n = n;
+  g.C = C;
+  g.G = G;
+  g.K = n > 0 ? (int32_t)((n + (int64_t)G * C - 1) / ((int64_t)G * C)) : 1;
+  g.base = (int64_t)(g.K - 1) * G * C;
+  g.L = n - g.base;
+  return g;
+}
+#endif
+
 // One work item of the batched pass: events [start, end) of one set.
 struct WorkItem {
   int64_t start, end;
@@ -57,7 +78,9 @@ struct SetsArgs {
   int64_t tile;             // events per work item
   const int64_t* tile_off;  // n_sets + 1 prefix of item counts (device)
   const int* set_flag;      // n_sets: 1 = malformed offsets
-  const WorkItem* items;    // tile_off[n_sets] work items in set order
+  const WorkItem* items;    // tile_off[n_sets] work items in set (and event) order
+  const int64_t* chunk_first;  // G K + 1: the first item of each chunk (ChunkGrid)
+  int32_t rounds;               // K: block b streams the items of chunks b, G + b, ..., (K-1) G + b
   PerTheta* consts;         // n_sets
   double* aux;              // n_sets * kAuxWords: a leaf's per-point tables, or null
   double* partials;         // items * (NA + 1) double-double pairs

@@ -8,14 +8,47 @@
 
 namespace nllmi {
 
-// Item counts per set and their exclusive prefix.  The offsets must be
-// non-decreasing within [0, n_total]; if any is not, every set of the batch
-// is flagged (status NLL_ERR_ARG) and gets one empty item, so the number of
-// items never exceeds n_total / tile + n_sets.
+// Work items of the batched pass.  The events [0, n) are cut into chunks
+// (ChunkGrid: K rounds of G chunks, chunk j = r G + b streamed by block b;
+// chunks of C events, the last round's G equal shares of what remains), and
+// an item is the part of one set inside one chunk.  Every block streams the
+// same number of events, and at any time the grid reads neighbouring
+// chunks (one contiguous range per block reads HBM ~10 % slower).  Items
+// are numbered in event order, so the items of a set are consecutive
+// (tile_off[s] .. tile_off[s+1]) and so are those of a chunk
+// (chunk_first[j] .. chunk_first[j+1]).  An empty set gets one empty item,
+// in the chunk that holds its offset.  The offsets must be non-decreasing
+// within [0, n]; if any is not, every set of the batch is flagged (status
+// NLL_ERR_ARG) and gets one empty item.  At most n_sets + G K items.
+__device__ __forceinline__ int64_t chunk_start(int64_t j, const ChunkGrid& g) {
+  const int64_t full = (int64_t)(g.K - 1) * g.G;
+  if (j <= full) return j * g.C;
+  return g.base + (j - full) * g.L / g.G;
+}
+// the chunk that holds event e (0 <= e < n)
+__device__ __forceinline__ int64_t chunk_of(int64_t e, const ChunkGrid& g) {
+  if (e < g.base) return e / g.C;
+  return (int64_t)(g.K - 1) * g.G + ((e - g.base + 1) * g.G - 1) / g.L;
+}
+// the chunks [j0, j1] of set s's items
+__device__ inline void set_chunks(const int64_t* __restrict__ offsets, int s, int n_sets, const ChunkGrid& g,
+                                  int flag, int64_t& j0, int64_t& j1) {
+  const int64_t nc = (int64_t)g.G * g.K;
+  const int64_t a = flag ? 0 : offsets[s], e = flag ? 0 : offsets[s + 1];
+  if (flag || g.n == 0) {
+    j0 = j1 = (int64_t)s * nc / n_sets;  // empty items spread over the chunks, in order
+  } else if (e == a) {
+    j0 = j1 = a < g.n ? chunk_of(a, g) : nc - 1;
+  } else {
+    j0 = chunk_of(a, g);
+    j1 = chunk_of(e - 1, g);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__ offsets, int n_sets,
-                                                     int64_t n_total, int64_t tile,
-                                                     int64_t* __restrict__ tile_off,
-                                                     int* __restrict__ set_flag) {
+                                                     const ChunkGrid g, int64_t* __restrict__ tile_off,
+                                                     int* __restrict__ set_flag,
+                                                     int64_t* __restrict__ chunk_first) {
   __shared__ int64_t scan[kBlock];
   __shared__ int any_bad;
   const int t = threadIdx.x;
@@ -25,15 +58,16 @@ __global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__
   const int s0 = min(n_sets, t * per), s1 = min(n_sets, s0 + per);
   for (int s = s0; s < s1; ++s) {
     const int64_t a = offsets[s], b = offsets[s + 1];
-    if (!(a >= 0 && b >= a && b <= n_total)) atomicOr(&any_bad, 1);
+    if (!(a >= 0 && b >= a && b <= g.n)) atomicOr(&any_bad, 1);
   }
   __syncthreads();
   const int bad = any_bad;
   int64_t local = 0;
   for (int s = s0; s < s1; ++s) {
     set_flag[s] = bad;
-    const int64_t len = bad ? 0 : offsets[s + 1] - offsets[s];
-    local += len > 0 ? (len + tile - 1) / tile : 1;
+    int64_t j0, j1;
+    set_chunks(offsets, s, n_sets, g, bad, j0, j1);
+    local += j1 - j0 + 1;
   }
   scan[t] = local;
   __syncthreads();
@@ -46,27 +80,48 @@ __global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__
   int64_t run = scan[t] - local;  // exclusive prefix
   for (int s = s0; s < s1; ++s) {
     tile_off[s] = run;
-    const int64_t len = bad ? 0 : offsets[s + 1] - offsets[s];
-    run += len > 0 ? (len + tile - 1) / tile : 1;
+    int64_t j0, j1;
+    set_chunks(offsets, s, n_sets, g, bad, j0, j1);
+    run += j1 - j0 + 1;
   }
   if (t == kBlock - 1) tile_off[n_sets] = scan[kBlock - 1];
+  if (n_sets == 0)
+    for (int64_t j = t; j <= (int64_t)g.G * g.K; j += kBlock) chunk_first[j] = 0;
 }
 
-// The work items of every set (one thread per set), in tile_off order: the
-// batched kernel then reads an item's set and range with one load instead
-// of searching the prefix.
-__global__ __launch_bounds__(kBlock) void k_items(const int64_t* __restrict__ offsets, int n_sets, int64_t tile,
+// The items of every set (one thread per set), and chunk_first: the first
+// item of each chunk (chunk_first[G K] = the item count).
+__global__ __launch_bounds__(kBlock) void k_items(const int64_t* __restrict__ offsets, int n_sets, const ChunkGrid g,
                                                   const int64_t* __restrict__ tile_off,
-                                                  const int* __restrict__ set_flag, WorkItem* __restrict__ items) {
+                                                  const int* __restrict__ set_flag, WorkItem* __restrict__ items,
+                                                  int64_t* __restrict__ chunk_first) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= n_sets) return;
   const int flag = set_flag[s];
-  const int64_t a = flag ? 0 : offsets[s], b = flag ? 0 : offsets[s + 1];
-  const int64_t i0 = tile_off[s], i1 = tile_off[s + 1];
-  for (int64_t i = i0; i < i1; ++i) {
-    const int64_t start = a + (i - i0) * tile;
-    items[i] = WorkItem{start, start + tile < b ? start + tile : b, s, flag};
+  const int64_t a = flag ? 0 : offsets[s], e = flag ? 0 : offsets[s + 1];
+  int64_t j0, j1;
+  set_chunks(offsets, s, n_sets, g, flag, j0, j1);
+  int64_t prev = -1;  // the chunk of the previous set's last item
+  if (s > 0) {
+    int64_t p0, p1;
+    set_chunks(offsets, s - 1, n_sets, g, set_flag[s - 1], p0, p1);
+    prev = p1;
   }
+  const int64_t i0 = tile_off[s];
+  for (int64_t j = prev + 1; j <= j0; ++j) chunk_first[j] = i0;
+  for (int64_t j = j0; j <= j1; ++j) {
+    const int64_t i = i0 + (j - j0);
+    if (j > j0) chunk_first[j] = i;
+    int64_t lo = a, hi = e;
+    if (e > a) {
+      const int64_t r0 = chunk_start(j, g), r1 = chunk_start(j + 1, g);
+      lo = a > r0 ? a : r0;
+      hi = e < r1 ? e : r1;
+    }
+    items[i] = WorkItem{lo, hi, s, flag};
+  }
+  if (s == n_sets - 1)
+    for (int64_t j = j1 + 1; j <= (int64_t)g.G * g.K; ++j) chunk_first[j] = tile_off[n_sets];
 }
 
 __global__ __launch_bounds__(kBlock) void k_fit_final(int n_sets, int P, GDState gd, double* theta_out,
@@ -94,25 +149,30 @@ __global__ __launch_bounds__(kBlock) void k_check_range(const double* __restrict
   if (local) atomicAdd(bad, local);
 }
 
-hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
-                           int64_t* tile_off, int* set_flag, WorkItem* items, hipStream_t st) {
-  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kBlock), 0, st, offsets, n_sets, n_total, tile, tile_off, set_flag);
+hipError_t launch_schedule(const int64_t* offsets, int n_sets, const ChunkGrid& g, int64_t* tile_off,
+                           int* set_flag, WorkItem* items, int64_t* chunk_first, hipStream_t st) {
+  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kBlock), 0, st, offsets, n_sets, g, tile_off, set_flag,
+                     chunk_first);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n_sets <= 0) return e;
-  hipLaunchKernelGGL(k_items, dim3((n_sets + kBlock - 1) / kBlock), dim3(kBlock), 0, st, offsets, n_sets, tile,
-                     tile_off, set_flag, items);
+  hipLaunchKernelGGL(k_items, dim3((n_sets + kBlock - 1) / kBlock), dim3(kBlock), 0, st, offsets, n_sets, g,
+                     tile_off, set_flag, items, chunk_first);
   return hipGetLastError();
 }
 
 // Points mode: every set is the whole dataset [0, n), evaluated at its own
 // parameter point.  Virtual offsets s * n give each set its event count n
 // (the finishing kernel's n_s); ceil(n / tile) items per set, or one empty
-// item if n == 0; no flags.  One thread per item (and per set for the
-// per-set arrays).
-__global__ __launch_bounds__(kBlock) void k_points(int n_sets, int64_t n, int64_t tile, int64_t per,
+// item if n == 0; no flags; one round of G chunks, the blocks taking equal
+// runs of consecutive items.  One thread per item (and per set for the
+// per-set arrays, per block for chunk_first).
+__global__ __launch_bounds__(kBlock) void k_points(int n_sets, int64_t n, int64_t tile, int64_t per, int G,
                                                    int64_t* __restrict__ offsets, int64_t* __restrict__ tile_off,
-                                                   int* __restrict__ set_flag, WorkItem* __restrict__ items) {
+                                                   int* __restrict__ set_flag, WorkItem* __restrict__ items,
+                                                   int64_t* __restrict__ chunk_first) {
   const int64_t total = (int64_t)n_sets * per;
+  for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b <= G; b += (int64_t)gridDim.x * kBlock)
+    chunk_first[b] = b * total / G;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
     const int64_t s = i / per, k = i - s * per;
     const int64_t start = k * tile;
@@ -125,14 +185,14 @@ __global__ __launch_bounds__(kBlock) void k_points(int n_sets, int64_t n, int64_
   }
 }
 
-hipError_t launch_points(int n_sets, int64_t n, int64_t tile, int64_t* offsets, int64_t* tile_off, int* set_flag,
-                         WorkItem* items, hipStream_t st) {
+hipError_t launch_points(int n_sets, int64_t n, int64_t tile, int G, int64_t* offsets, int64_t* tile_off,
+                         int* set_flag, WorkItem* items, int64_t* chunk_first, hipStream_t st) {
   const int64_t per = n > 0 ? (n + tile - 1) / tile : 1;
   int64_t blocks = ((int64_t)n_sets * per + kBlock - 1) / kBlock;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_points, dim3((unsigned)blocks), dim3(kBlock), 0, st, n_sets, n, tile, per, offsets, tile_off,
-                     set_flag, items);
+  hipLaunchKernelGGL(k_points, dim3((unsigned)blocks), dim3(kBlock), 0, st, n_sets, n, tile, per, G, offsets,
+                     tile_off, set_flag, items, chunk_first);
   return hipGetLastError();
 }
 

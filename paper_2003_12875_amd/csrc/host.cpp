@@ -411,6 +411,12 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
 
 int tile_events(const nll_model* m) { return m->sched.unroll * kBlock; }
 
+// the batched pass's chunks for the attached data and the current schedule
+ChunkGrid chunk_grid(const nll_model* m) {
+  return make_chunk_grid(std::max<int64_t>(m->n, 0), std::max(1, m->n_cu * m->sched.sets_blocks_per_cu),
+                         m->sched.tile_events);
+}
+
 int single_grid(const nll_model* m) {
   const int64_t tiles = m->n > 0 ? (m->n + tile_events(m) - 1) / tile_events(m) : 1;
   int64_t g = (int64_t)m->n_cu * m->sched.blocks_per_cu;
@@ -436,10 +442,20 @@ nll_status ensure_sets(nll_model* m, int n_sets, int64_t items = -1) {
     m->sets_cap = cap;
     m->have_graph = false;
   }
-  const int64_t tile = m->sched.tile_events;
-  // work items: at most ceil(len_s / tile) (at least 1) per set, and the
-  // sets are consecutive ranges of the events
-  if (items < 0) items = (m->n > 0 ? m->n / tile : 0) + n_sets + 1;
+  // work items: the parts of the sets in the chunks of the batched pass (a
+  // set's part per chunk it meets, at least one per set): at most
+  // n_sets + chunks
+  const ChunkGrid g = chunk_grid(m);
+  const size_t chunks = (size_t)g.G * (size_t)g.K;
+  if (items < 0) items = (int64_t)n_sets + (int64_t)chunks + 1;
+  if (chunks + 1 > m->chunk_cap) {
+    dfree(m->chunk_first);
+    m->chunk_cap = 0;
+    nll_status st = dalloc(&m->chunk_first, chunks + 1);
+    if (st != NLL_OK) return st;
+    m->chunk_cap = chunks + 1;
+    m->have_graph = false;
+  }
   if ((size_t)items > m->items_cap) {
     dfree(m->items);
     m->items_cap = 0;
@@ -498,6 +514,8 @@ SetsArgs sets_args(const nll_model* m, int n_sets, const int64_t* offsets) {
   a.tile_off = m->tile_off;
   a.set_flag = m->set_flag;
   a.items = m->items;
+  a.chunk_first = m->chunk_first;
+  a.rounds = chunk_grid(m).K;
   a.consts = m->consts;
   a.aux = m->aux;
   a.partials = m->set_partials;
@@ -638,7 +656,8 @@ nll_status enqueue_fit(nll_model* m, hipStream_t st, int n_sets, const int64_t* 
   GDState gd = gd_state(m);
   SetsArgs a = sets_args(m, n_sets, offsets);
   a.gd = gd;
-  hipError_t e = launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, m->tile_off, m->set_flag, m->items, st);
+  hipError_t e = launch_schedule(offsets, n_sets, chunk_grid(m), m->tile_off, m->set_flag, m->items,
+                                 m->chunk_first, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
   e = m->ops->fit_init(*m->ops, m->plan, theta, n_sets, eta, gd, m->consts, m->aux, m->gl.x, m->gl.w, st);
   if (e != hipSuccess) return NLL_ERR_DEVICE;
@@ -701,8 +720,8 @@ nll_status batched_args_ok(const nll_model* m, int32_t n_sets, const int64_t* of
 }
 
 int64_t batched_items_bound(const nll_model* m, int32_t n_sets) {
-  const int64_t tile = m->sched.tile_events;
-  return (m->n > 0 ? m->n / tile : 0) + n_sets + 1;
+  const ChunkGrid g = chunk_grid(m);
+  return (int64_t)n_sets + (int64_t)g.G * g.K + 1;
 }
 
 size_t batched_record_bytes(const nll_model* m) { return (size_t)(m->ops->na_grad + 1) * 2 * sizeof(double); }
@@ -714,6 +733,7 @@ nll_status eval_batched_on(nll_model* m, int32_t n_sets, const int64_t* offsets,
   a.tile_off = s.tile_off;
   a.set_flag = s.set_flag;
   a.items = s.items;
+  a.chunk_first = s.chunk_first;
   a.consts = s.consts;
   a.aux = s.aux;
   a.partials = s.partials;
@@ -721,7 +741,8 @@ nll_status eval_batched_on(nll_model* m, int32_t n_sets, const int64_t* offsets,
   a.nll_out = nll_out;
   a.grad_out = grad_out;
   a.status_out = reinterpret_cast<int*>(status_out);
-  if (launch_schedule(offsets, n_sets, m->n, m->sched.tile_events, s.tile_off, s.set_flag, s.items, m->stream) !=
+  if (launch_schedule(offsets, n_sets, chunk_grid(m), s.tile_off, s.set_flag, s.items, s.chunk_first,
+                      m->stream) !=
       hipSuccess)
     return NLL_ERR_DEVICE;
   if (m->ops->consts(*m->ops, m->plan, theta, n_sets, s.consts, s.aux, m->gl.x, m->gl.w, m->stream) != hipSuccess)
@@ -820,6 +841,7 @@ void nll_destroy_model(nll_model* m) {
   dfree(m->tile_off);
   dfree(m->set_flag);
   dfree(m->items);
+  dfree(m->chunk_first);
   dfree(m->consts);
   dfree(m->aux);
   dfree(m->set_partials);
@@ -919,6 +941,7 @@ nll_status nll_eval_batched(nll_model* m, int32_t n_sets, const int64_t* offsets
   if ((st = ensure_sets(m, n_sets)) != NLL_OK) return st;
   SetsScratch s;
   s.tile_off = m->tile_off;
+  s.chunk_first = m->chunk_first;
   s.set_flag = m->set_flag;
   s.items = m->items;
   s.consts = m->consts;
@@ -949,7 +972,9 @@ nll_status nll_eval_points(nll_model* m, int32_t n_points, const double* theta, 
   a.nll_out = nll_out;
   a.grad_out = grad_out;
   a.status_out = reinterpret_cast<int*>(status_out);
-  if (launch_points(n_points, m->n, tile, m->pts_offsets, m->tile_off, m->set_flag, m->items, m->stream) != hipSuccess)
+  a.rounds = 1;  // points: one round of G chunks of equal item counts
+  if (launch_points(n_points, m->n, tile, sets_grid(m), m->pts_offsets, m->tile_off, m->set_flag, m->items,
+                    m->chunk_first, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;
   if (m->ops->consts(*m->ops, m->plan, theta, n_points, m->consts, m->aux, m->gl.x, m->gl.w, m->stream) != hipSuccess)
     return NLL_ERR_DEVICE;

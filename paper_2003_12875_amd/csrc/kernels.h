@@ -67,10 +67,13 @@ void register_variants_johnson(std::vector<VariantOps>& out);
 void register_variants_chi2(std::vector<VariantOps>& out);
 void register_variants_hypatia(std::vector<VariantOps>& out);
 
-hipError_t launch_schedule(const int64_t* offsets, int n_sets, int64_t n_total, int64_t tile,
-                           int64_t* tile_off, int* set_flag, WorkItem* items, hipStream_t st);
-hipError_t launch_points(int n_sets, int64_t n, int64_t tile, int64_t* offsets, int64_t* tile_off, int* set_flag,
-                         WorkItem* items, hipStream_t st);
+// work items of the batched pass over the chunks of g (see common.hip),
+// chunk_first[G K + 1]
+hipError_t launch_schedule(const int64_t* offsets, int n_sets, const ChunkGrid& g, int64_t* tile_off,
+                           int* set_flag, WorkItem* items, int64_t* chunk_first, hipStream_t st);
+// points mode: one round of G chunks (chunk_first[G + 1])
+hipError_t launch_points(int n_sets, int64_t n, int64_t tile, int G, int64_t* offsets, int64_t* tile_off,
+                         int* set_flag, WorkItem* items, int64_t* chunk_first, hipStream_t st);
 hipError_t launch_fit_final(int n_sets, int P, const GDState& gd, double* theta_out, double* nll_out,
                             double* grad_out, int* status_out, hipStream_t st);
 // W = sum of n weights into *out (deterministic, compensated): per-block

@@ -844,19 +844,20 @@ __global__ __launch_bounds__(kBlock) void k_consts(const Plan pl, const double* 
   if constexpr (M::AUX) copy_aux<kBlock>(aux_out + (size_t)s * kAuxWords, s_aux);
 }
 
-// items and consts also come as kernel arguments of their own: read-only
-// and not aliased by anything the kernel writes, their uniform loads (item
-// descriptors, a set's constants) go through the scalar unit and do not
-// make the vector-load counter waits drain the ring.
+// items, consts and chunk_first also come as kernel arguments of their
+// own: read-only and not aliased by anything the kernel writes, their
+// uniform loads (item descriptors, a set's constants, the chunk table) go
+// through the scalar unit and do not make the vector-load counter waits
+// drain the ring.
 template <class M, bool GRAD, int U>
 __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a,
                                                  const WorkItem* __restrict__ items,
-                                                 const PerTheta* __restrict__ consts) {
+                                                 const PerTheta* __restrict__ consts,
+                                                 const int64_t* __restrict__ chunk_first) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
   __shared__ double red[NV * (kBlock + 1)];
   __shared__ DD tot[NV];
-  const int64_t total = a.tile_off[a.n_sets];
   const double* cols[M::NOBS];
 #pragma unroll
   for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
@@ -867,39 +868,62 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
   if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
   if constexpr (CT::kExpTab || M::EVENT_LOG) __syncthreads();
 
-  // The block's items form one sequence of tiles (an item of len events has
-  // max(1, ceil(len / (256 U))) tiles, its last one partial), streamed
-  // through one ring of R register buffers that runs across item
-  // boundaries: a load cursor issues the loads of tile k + R - 1 while a
-  // compute cursor evaluates tile k, so loads stay in flight through an
-  // item's last tiles, its block reduction and the switch to the next
-  // item's constants.  Every tile issues its U x NOBS loads unconditionally
-  // (lanes past an item's end, empty items and the ring's run-out read a
-  // dummy word of the Gauss-Legendre table), so that the compiler's
-  // load-counter waits see the whole ring in flight; events past an item's
-  // end are masked in the arithmetic.  Non-temporal loads: the sets
-  // together are read once per pass (a batch of toys is GBs).
+  // Block b streams the items of its chunks b, G + b, ..., (K-1) G + b in
+  // turn (every block the same number of events; at any time the grid
+  // reads neighbouring chunks).  Its items form one sequence of tiles (an
+  // item of len events has max(1, ceil(len / (256 U))) tiles, its last one
+  // partial), streamed through one ring of R register buffers that runs
+  // across item boundaries: a load cursor issues the loads of tile k + R - 1
+  // while a compute cursor evaluates tile k, so loads stay in flight
+  // through an item's last tiles, its block reduction and the switch to the
+  // next item's constants.  Every tile issues its U x NOBS loads
+  // unconditionally (lanes past an item's end, empty items and the ring's
+  // run-out read a dummy word of the Gauss-Legendre table), so that the
+  // compiler's load-counter waits see the whole ring in flight; events past
+  // an item's end are masked in the arithmetic.  Non-temporal loads: the
+  // sets together are read once per pass (a batch of toys is GBs).
   constexpr int R = ring_depth<M>();
   const int64_t step = (int64_t)kBlock * U;
-  const int64_t G = gridDim.x;
   const double* dummy = a.glx;
   auto ntiles = [&](const WorkItem& w) -> int64_t {
     const int64_t len = w.end - w.start;
     return len > 0 ? (len + step - 1) / step : 1;
   };
+  // a position in the block's item sequence: item i of the chunk of round
+  // r (items chunk_first[j] .. chunk_first[j+1] - 1, j = r G + b)
+  struct Seq {
+    int64_t i, ie;
+    int r;
+  };
+  const int64_t G = gridDim.x;
+  const int K = a.rounds;
+  auto settle = [&](Seq& q) -> bool {  // skip chunks without items; false at the end
+    while (q.i >= q.ie) {
+      if (++q.r >= K) return false;
+      q.i = chunk_first[(int64_t)q.r * G + blockIdx.x];
+      q.ie = chunk_first[(int64_t)q.r * G + blockIdx.x + 1];
+    }
+    return true;
+  };
+  Seq q0{chunk_first[blockIdx.x], chunk_first[blockIdx.x + 1], 0};
+  const bool any = settle(q0);
   double xb[R][U][M::NOBS];
 
   // load cursor (R - 1 tiles ahead of the compute cursor)
-  int64_t l_item = blockIdx.x, l_tile = 0, l_T = 1;
+  Seq lnq = q0;
+  bool l_live = any, ln_live = false;
+  int64_t l_tile = 0, l_T = 1;
   WorkItem l_w{0, 0, 0, 0}, l_next{0, 0, 0, 0};
-  if (l_item < total) {
-    l_w = items[l_item];
+  if (l_live) {
+    l_w = items[q0.i];
     l_T = ntiles(l_w);
+    ++lnq.i;
+    ln_live = settle(lnq);
+    if (ln_live) l_next = items[lnq.i];
   }
-  if (l_item + G < total) l_next = items[l_item + G];
   auto issue = [&](double (&buf)[U][M::NOBS]) {
     const int64_t base = l_w.start + l_tile * step + threadIdx.x;
-    const bool live = l_item < total;
+    const bool live = l_live;
     const bool full = live && l_w.end - (l_w.start + l_tile * step) >= step;
     const double* ptr[U][M::NOBS];
     if (full) {
@@ -921,25 +945,34 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
 #pragma unroll
       for (int o = 0; o < M::NOBS; ++o) buf[u][o] = ld_event<true>(ptr[u][o]);
     if (live && ++l_tile == l_T) {
-      l_item += G;
+      l_live = ln_live;
       l_w = l_next;
       l_T = ntiles(l_w);
       l_tile = 0;
-      if (l_item + G < total) l_next = items[l_item + G];
+      if (l_live) {
+        ++lnq.i;
+        ln_live = settle(lnq);
+        if (ln_live) l_next = items[lnq.i];
+      }
     }
   };
 
   // compute cursor
-  int64_t c_item = blockIdx.x, c_tile = 0, c_T = 1;
+  Seq cq = q0, cnq = q0;
+  bool c_live = any, cn_live = false;
+  int64_t c_tile = 0, c_T = 1;
   WorkItem c_w{0, 0, 0, 0}, c_next{0, 0, 0, 0};
   CT C;
   bool skip = true;
   typename Pass<M, GRAD>::A acc;
   acc.init();
-  auto enter = [&]() {  // constants of item c_item (block-uniform)
+  auto enter = [&]() {  // constants of the item at cq (block-uniform)
     c_T = ntiles(c_w);
     c_tile = 0;
-    if (c_item + G < total) c_next = items[c_item + G];
+    cnq = cq;
+    ++cnq.i;
+    cn_live = settle(cnq);
+    if (cn_live) c_next = items[cnq.i];
     const PerTheta& pt = consts[c_w.set];
     if constexpr (M::AUX) {  // the previous item's reads ended in its block sum
       copy_aux<kBlock>(s_aux, a.aux + (size_t)c_w.set * kAuxWords);
@@ -950,18 +983,18 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
     skip = uniform(pt.bad) != 0 || c_w.flag != 0;
     acc.init();
   };
-  if (c_item < total) {
-    c_w = items[c_item];
+  if (c_live) {
+    c_w = items[cq.i];
     enter();
   }
 
 #pragma unroll
   for (int j = 0; j < R - 1; ++j) issue(xb[j]);
-  while (c_item < total) {
+  while (c_live) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       issue(xb[(j + R - 1) % R]);
-      if (c_item < total) {
+      if (c_live) {
         if (!skip) {
           const int64_t t0 = c_w.start + c_tile * step;
           if (c_w.end - t0 >= step) {
@@ -980,9 +1013,10 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
           v[NA] = (double)acc.bad;
           block_sum_vals<NV, kBlock>(v, red, tot);
           if (threadIdx.x < NV)
-            reinterpret_cast<DD*>(a.partials)[(size_t)c_item * NV + threadIdx.x] = tot[threadIdx.x];
-          c_item += G;
-          if (c_item < total) {
+            reinterpret_cast<DD*>(a.partials)[(size_t)cq.i * NV + threadIdx.x] = tot[threadIdx.x];
+          cq = cnq;
+          c_live = cn_live;
+          if (c_live) {
             c_w = c_next;
             enter();
           }

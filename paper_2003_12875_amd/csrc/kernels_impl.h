@@ -136,10 +136,11 @@ struct Launch {
     if (ev0 && ev1)
       hipExtLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), (uint32_t)pad_lds(k, lds_cap), st, ev0,
                             ev1, 0u, pl, a, static_cast<const WorkItem*>(a.items),
-                            static_cast<const PerTheta*>(a.consts));
+                            static_cast<const PerTheta*>(a.consts), a.chunk_first);
     else
       hipLaunchKernelGGL((k_sets<M, GRAD, U>), dim3(grid), dim3(kBlock), pad_lds(k, lds_cap), st, pl, a,
-                         static_cast<const WorkItem*>(a.items), static_cast<const PerTheta*>(a.consts));
+                         static_cast<const WorkItem*>(a.items), static_cast<const PerTheta*>(a.consts),
+                         a.chunk_first);
   }
   template <bool GRAD>
   static void sets_u(const Plan& pl, const SetsArgs& a, int unroll, int grid, int lds_cap, hipStream_t st,

@@ -47,12 +47,14 @@ extern "C" nll_status nll_eval_batched_noalloc(nll_model* m, int32_t n_sets, con
                                                int32_t* status_out) {
   nll_status st = batched_args_ok(m, n_sets, offsets, theta, nll_out);
   if (st != NLL_OK || n_sets == 0) return st;
-  // layout: tile prefix | set flags | work items | per-set constants |
-  // per-set tables (models with them) | item records
+  // layout: item prefix | set flags | work items | chunks' first items |
+  // per-set constants | per-set tables (models with them) | item records
   const size_t items = (size_t)batched_items_bound(m, n_sets);
+  const size_t chunks = items - (size_t)n_sets - 1;
   const size_t o_flag = align256(((size_t)n_sets + 1) * sizeof(int64_t));
   const size_t o_items = o_flag + align256((size_t)n_sets * sizeof(int));
-  const size_t o_consts = o_items + align256(items * sizeof(WorkItem));
+  const size_t o_first = o_items + align256(items * sizeof(WorkItem));
+  const size_t o_consts = o_first + align256((chunks + 1) * sizeof(int64_t));
   const size_t o_aux = o_consts + align256((size_t)n_sets * sizeof(PerTheta));
   const size_t o_part = o_aux + (m->ops->aux ? align256((size_t)n_sets * kAuxWords * sizeof(double)) : 0);
   const size_t need = o_part + items * batched_record_bytes(m);
@@ -64,6 +66,7 @@ extern "C" nll_status nll_eval_batched_noalloc(nll_model* m, int32_t n_sets, con
   s.tile_off = reinterpret_cast<int64_t*>(base);
   s.set_flag = reinterpret_cast<int*>(base + o_flag);
   s.items = reinterpret_cast<WorkItem*>(base + o_items);
+  s.chunk_first = reinterpret_cast<int64_t*>(base + o_first);
   s.consts = reinterpret_cast<PerTheta*>(base + o_consts);
   s.aux = m->ops->aux ? reinterpret_cast<double*>(base + o_aux) : nullptr;
   s.partials = reinterpret_cast<double*>(base + o_part);

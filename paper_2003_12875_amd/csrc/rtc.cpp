@@ -136,7 +136,8 @@ hipError_t op_sets(const VariantOps& self, const Plan& pl, const SetsArgs& a, bo
   hipFunction_t f = r.f[kSets + 2 * ((grad || fit) ? 1 : 0) + u_index(unroll)];
   const WorkItem* items = a.items;
   const PerTheta* consts = a.consts;
-  void* sargs[] = {const_cast<Plan*>(&pl), const_cast<SetsArgs*>(&a), &items, &consts};
+  const int64_t* chunk_first = a.chunk_first;
+  void* sargs[] = {const_cast<Plan*>(&pl), const_cast<SetsArgs*>(&a), &items, &consts, &chunk_first};
   hipError_t e = launch(f, grid, kBlock, pad(f, lds_cap), st, sargs, ev0, ev1);
   void* args[] = {const_cast<Plan*>(&pl), const_cast<SetsArgs*>(&a)};
   if (e != hipSuccess) return e;

@@ -87,6 +87,8 @@ struct nll_model {
   int* set_flag = nullptr;
   nllmi::WorkItem* items = nullptr;  // batched work items
   size_t items_cap = 0;
+  int64_t* chunk_first = nullptr;    // the first item of each chunk of the batched pass
+  size_t chunk_cap = 0;
   nllmi::PerTheta* consts = nullptr;
   double* aux = nullptr;  // sets_cap * kAuxWords: a leaf's per-point tables (models with one)
   size_t set_partials_cap = 0;  // bytes
@@ -119,6 +121,7 @@ struct SetsScratch {
   int64_t* tile_off = nullptr;
   int* set_flag = nullptr;
   WorkItem* items = nullptr;
+  int64_t* chunk_first = nullptr;  // chunks + 1
   PerTheta* consts = nullptr;
   double* aux = nullptr;  // n_sets * kAuxWords (models with per-point tables)
   double* partials = nullptr;

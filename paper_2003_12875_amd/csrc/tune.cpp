@@ -2,7 +2,7 @@
 //
 // Candidates: single dataset -- events per thread per tile (2, 4, 8) x
 // blocks per CU (1..16); batched -- events per thread per tile x events per
-// work item (8k..64k) x blocks per CU.  Each candidate is first checked
+// chunk (8k..32k) x blocks per CU.  Each candidate is first checked
 // against the default schedule's result (only the summation order differs:
 // relative NLL difference <= 1e-12 per dataset in FP64; in the
 // FP32-compensated mode, where the order also regroups the single-precision
@@ -116,8 +116,9 @@ nll_status tune_model(nll_model* m, int which, int n_sets, const int64_t* offset
           cands.push_back(nll_schedule{u, b, base.tile_events, base.sets_blocks_per_cu, base.sets_unroll});
     } else {
       for (int u : {2, 4, 8})
-        for (int t : {8192, 16384, 32768, 65536})
-          for (int b : {2, 3, 4, 8, 16}) cands.push_back(nll_schedule{base.unroll, base.blocks_per_cu, t, b, u});
+        for (int t : {8192, 16384, 32768})
+          for (int b : {2, 3, 4, 8})
+            cands.push_back(nll_schedule{base.unroll, base.blocks_per_cu, t, b, u});
     }
     Timer tm;
     for (const nll_schedule& c : cands) {
