@@ -20,15 +20,27 @@ namespace nllmi {
 // in the chunk that holds its offset.  The offsets must be non-decreasing
 // within [0, n]; if any is not, every set of the batch is flagged (status
 // NLL_ERR_ARG) and gets one empty item.  At most n_sets + G K items.
+// floor(a / b) for 0 <= a < 2^53 (exact as a double), b > 0: the
+// double-precision quotient is off by at most one and is corrected with
+// integer products; a 64-bit integer division is a long software routine
+// here.
+__device__ __forceinline__ int64_t div_floor(int64_t a, int64_t b) {
+  int64_t q = (int64_t)((double)a / (double)b);
+  const int64_t r = a - q * b;
+  if (r < 0) --q;
+  else if (r >= b) ++q;
+  return q;
+}
+
 __device__ __forceinline__ int64_t chunk_start(int64_t j, const ChunkGrid& g) {
   const int64_t full = (int64_t)(g.K - 1) * g.G;
   if (j <= full) return j * g.C;
-  return g.base + (j - full) * g.L / g.G;
+  return g.base + div_floor((j - full) * g.L, g.G);
 }
 // the chunk that holds event e (0 <= e < n)
 __device__ __forceinline__ int64_t chunk_of(int64_t e, const ChunkGrid& g) {
-  if (e < g.base) return e / g.C;
-  return (int64_t)(g.K - 1) * g.G + ((e - g.base + 1) * g.G - 1) / g.L;
+  if (e < g.base) return div_floor(e, g.C);
+  return (int64_t)(g.K - 1) * g.G + div_floor((e - g.base + 1) * g.G - 1, g.L);
 }
 // the chunks [j0, j1] of set s's items
 __device__ inline void set_chunks(const int64_t* __restrict__ offsets, int s, int n_sets, const ChunkGrid& g,
@@ -45,16 +57,18 @@ __device__ inline void set_chunks(const int64_t* __restrict__ offsets, int s, in
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__ offsets, int n_sets,
+constexpr int kSchedThreads = 1024;  // one block: the per-set counts and their prefix
+
+__global__ __launch_bounds__(kSchedThreads) void k_schedule(const int64_t* __restrict__ offsets, int n_sets,
                                                      const ChunkGrid g, int64_t* __restrict__ tile_off,
                                                      int* __restrict__ set_flag,
                                                      int64_t* __restrict__ chunk_first) {
-  __shared__ int64_t scan[kBlock];
+  __shared__ int64_t scan[kSchedThreads];
   __shared__ int any_bad;
   const int t = threadIdx.x;
   if (t == 0) any_bad = 0;
   __syncthreads();
-  const int per = (n_sets + kBlock - 1) / kBlock;
+  const int per = (n_sets + kSchedThreads - 1) / kSchedThreads;
   const int s0 = min(n_sets, t * per), s1 = min(n_sets, s0 + per);
   for (int s = s0; s < s1; ++s) {
     const int64_t a = offsets[s], b = offsets[s + 1];
@@ -71,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__
   }
   scan[t] = local;
   __syncthreads();
-  for (int d = 1; d < kBlock; d <<= 1) {
+  for (int d = 1; d < kSchedThreads; d <<= 1) {
     const int64_t v = t >= d ? scan[t - d] : 0;
     __syncthreads();
     scan[t] += v;
@@ -84,9 +98,9 @@ __global__ __launch_bounds__(kBlock) void k_schedule(const int64_t* __restrict__
     set_chunks(offsets, s, n_sets, g, bad, j0, j1);
     run += j1 - j0 + 1;
   }
-  if (t == kBlock - 1) tile_off[n_sets] = scan[kBlock - 1];
+  if (t == kSchedThreads - 1) tile_off[n_sets] = scan[kSchedThreads - 1];
   if (n_sets == 0)
-    for (int64_t j = t; j <= (int64_t)g.G * g.K; j += kBlock) chunk_first[j] = 0;
+    for (int64_t j = t; j <= (int64_t)g.G * g.K; j += kSchedThreads) chunk_first[j] = 0;
 }
 
 // The items of every set (one thread per set), and chunk_first: the first
@@ -151,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_check_range(const double* __restrict
 
 hipError_t launch_schedule(const int64_t* offsets, int n_sets, const ChunkGrid& g, int64_t* tile_off,
                            int* set_flag, WorkItem* items, int64_t* chunk_first, hipStream_t st) {
-  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kBlock), 0, st, offsets, n_sets, g, tile_off, set_flag,
+  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedThreads), 0, st, offsets, n_sets, g, tile_off, set_flag,
                      chunk_first);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n_sets <= 0) return e;

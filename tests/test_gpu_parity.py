@@ -195,6 +195,56 @@ def test_every_batched_schedule(torch, nllmi, threads):
         np.testing.assert_allclose(nllf.cpu().numpy(), nll_o, rtol=NLL_TOL)
 
 
+@pytest.mark.parametrize("case", ["gaps", "tiny_data", "many_rounds", "one_set"])
+def test_batched_chunk_schedule_edges(torch, nllmi, threads, case):
+    """The batched pass's chunk schedule (rounds of G chunks, items = set
+    parts per chunk) at its edges, per set against the oracle: sets that
+    leave events between and around them uncovered (chunks with no item),
+    fewer events than blocks, the smallest chunk at one block per CU (many
+    rounds, sets spanning many chunks), and one set over all the events;
+    then a three-step batched fit against the oracle's."""
+    spec = datagen.gauss_spec()
+    n = {"gaps": 300_000, "tiny_data": 100, "many_rounds": 400_000, "one_set": 250_000}[case]
+    cols = datagen.generate(spec, n, seed=1300 + len(case))
+    offsets = {"gaps": [5000, 5000, 60000, 61000, 200000, 250000],
+               "tiny_data": [0, 30, 30, 100],
+               "many_rounds": [0, 1, 170_001, 170_001, 399_000, 400_000],
+               "one_set": [0, n]}[case]
+    offsets = np.array(offsets, dtype=np.int64)
+    S = len(offsets) - 1
+    m = nllmi.Model.from_spec(spec)
+    m.set_data(to_dev(torch, cols))
+    if case == "many_rounds":
+        m.set_schedule(sets_unroll=8, tile_events=1024, sets_blocks_per_cu=1)
+    else:
+        m.set_schedule(sets_unroll=8, tile_events=32768, sets_blocks_per_cu=4)
+    th = datagen.jittered_points(datagen.theta_of(spec), S, seed=1310)
+    o = oracle.Oracle(spec)
+    nll, g, status = m.eval_batched(torch.from_numpy(offsets).cuda(), torch.from_numpy(th).cuda())
+    nll, g, status = nll.cpu().numpy(), g.cpu().numpy(), status.cpu().numpy()
+    for s in range(S):
+        a, b = offsets[s], offsets[s + 1]
+        sto, ref, gref = o.nll([c[a:b] for c in cols], th[s], threads=threads)
+        assert status[s] == sto == 0, (case, s)
+        if b == a:
+            assert nll[s] == 0.0 and np.all(g[s] == 0.0), (case, s)
+            continue
+        assert abs(nll[s] - ref) <= NLL_TOL * abs(ref), (case, s, nll[s], ref)
+        ok, err = grad_close(g[s], gref)
+        assert ok, (case, s, err)
+    start = np.tile(datagen.theta_of(spec), (S, 1))
+    sets = [(a, b) for a, b in zip(offsets[:-1], offsets[1:])]
+    thf, nllf, gf, stf = m.fit_batched(torch.from_numpy(offsets).cuda(), torch.from_numpy(start).cuda(), 3, 1.0)
+    thf, nllf, stf = thf.cpu().numpy(), nllf.cpu().numpy(), stf.cpu().numpy()
+    for s, (a, b) in enumerate(sets):
+        sto, th_o, f_o, g_o, _ = o.gd_fit([c[a:b] for c in cols], start[s], 3, 1.0, threads=threads)
+        assert stf[s] == sto, (case, s)
+        if b > a:
+            assert abs(nllf[s] / f_o - 1.0) <= NLL_TOL, (case, s)
+            np.testing.assert_allclose(thf[s], th_o, rtol=1e-12, atol=1e-14)
+    assert m.sync() == 0
+
+
 # ---------------------------------------------------------------------------
 # many datasets
 # ---------------------------------------------------------------------------
