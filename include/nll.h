@@ -430,14 +430,23 @@ nll_status nll_read_probe(const double* x, int64_t n, double* block_sums, int32_
  *     NLL_HF_HISTOSYS    the sample's bins plus a (up_b - T_sb) (a >= 0) or
  *                        a (T_sb - down_b) (a < 0)
  *   nu_b = sum_s (product of the sample's factors) (T_sb + histosys terms)
- *   NLL  = sum_b (nu_b - n_b ln nu_b) + 1/2 sum_{constrained p} theta_p^2
- *   (a bin with n_b = 0 contributes nu_b; no ln n_b! terms; unit Gaussian
- *   constraints without their normalisation).  The derivative at a = 0 is
- *   the a >= 0 side's.  A parameter outside [lo, hi] gives +inf and
- *   NLL_ERR_PARAM_RANGE, nu_b < 0 or nu_b = 0 with n_b > 0 gives +inf and
- *   NLL_ERR_INVALID_PDF, both through nll_hf_sync.
- * Limits: 1..8 samples, <= 24 histosys, <= 16 normsys, <= 8 normfactor
- * modifiers, 1..32 parameters.
+ *   NLL  = sum_b (nu_b - n_b ln nu_b)
+ *          + 1/2 sum_{constrained p} ((theta_p - m_p) / s_p)^2
+ *   (a bin with n_b = 0 contributes nu_b; no ln n_b! terms; Gaussian
+ *   constraints of mean m_p and width s_p, 0 and 1 by default, without
+ *   their normalisation; a luminosity parameter is a normfactor on the
+ *   samples it scales, constrained with mean 1 and width its relative
+ *   uncertainty).  The derivative at a = 0 is the a >= 0 side's.  With
+ *   interp = 1 a modifier uses the smooth codes instead (HistFactory's
+ *   "code 4"): for |a| < 1 a normsys factor is 1 + sum_{i=1..6} c_i a^i,
+ *   the polynomial meeting hi^a and lo^-a at a = +1, -1 with equal value,
+ *   slope and curvature, and a histosys delta is
+ *   a (S + a A (15 + a^2 (3 a^2 - 10))), S = (du + dd)/2, A = (du - dd)/16,
+ *   du = up - T, dd = T - down (linear beyond +-1).  A parameter outside
+ *   [lo, hi] gives +inf and NLL_ERR_PARAM_RANGE, nu_b < 0 or nu_b = 0 with
+ *   n_b > 0 gives +inf and NLL_ERR_INVALID_PDF, both through nll_hf_sync.
+ * Limits: 1..8 samples, <= 24 histosys (<= 12 when any uses interp = 1),
+ * <= 16 normsys, <= 8 normfactor modifiers, 1..32 parameters.
  * ---------------------------------------------------------------------- */
 enum nll_hf_modifier_type { NLL_HF_NORMFACTOR = 1, NLL_HF_NORMSYS = 2, NLL_HF_HISTOSYS = 3 };
 
@@ -445,6 +454,7 @@ typedef struct nll_hf_modifier {
   int32_t type;    /* nll_hf_modifier_type */
   int32_t sample;  /* 0 .. n_samples-1 */
   int32_t param;   /* 0 .. n_param-1 */
+  int32_t interp;  /* normsys, histosys: 0 exponential / linear, 1 smooth */
   double hi, lo;   /* NLL_HF_NORMSYS only */
 } nll_hf_modifier;
 
@@ -455,7 +465,9 @@ typedef struct nll_hf_desc {
   const double* param_lo;            /* n_param (host) */
   const double* param_hi;
   const uint8_t* param_free;         /* n_param, 0: fixed (gradient entry 0) */
-  const uint8_t* param_constrained;  /* n_param, 1: + theta^2/2 */
+  const uint8_t* param_constrained;  /* n_param, 1: + ((theta - mean) / sigma)^2 / 2 */
+  const double* param_mean;          /* n_param or NULL (0): constraint means */
+  const double* param_sigma;         /* n_param or NULL (1): constraint widths, > 0 */
   int32_t n_modifiers;
   const nll_hf_modifier* modifiers;  /* n_modifiers (host) */
   int32_t device;
@@ -466,7 +478,8 @@ typedef struct nll_hf_model nll_hf_model; /* opaque, owned by the library */
 
 /* Validate the descriptor and allocate the model's device scratch.
  * Descriptor arrays are copied.  Errors: NLL_ERR_ARG (bad counts or
- * indices, hi or lo <= 0), NLL_ERR_UNSUPPORTED (beyond the limits),
+ * indices, hi or lo <= 0, interp not 0 or 1, a constraint width not
+ * positive and finite), NLL_ERR_UNSUPPORTED (beyond the limits),
  * NLL_ERR_DEVICE, NLL_ERR_OOM. */
 nll_status nll_hf_create(const nll_hf_desc* desc, nll_hf_model** out);
 
@@ -503,6 +516,16 @@ nll_status nll_hf_eval(nll_hf_model* model, const double* theta, double* nll_out
  * replace mask and widths.  Errors: NLL_ERR_ARG (mask, unaligned sigma),
  * NLL_ERR_DEVICE, NLL_ERR_OOM. */
 nll_status nll_hf_set_staterror(nll_hf_model* model, uint32_t sample_mask, const double* sigma);
+
+/* As nll_hf_set_staterror with a Poisson constraint instead (HistFactory's
+ * shapesys: the templates' statistical error as an auxiliary count
+ * tau_b = 1/sigma_b^2 observed for the mean gamma_b tau_b):
+ *   NLL += sum_b tau_b (gamma_b - ln gamma_b)
+ * (the Poisson term without its constant ln Gamma(tau + 1) - tau ln tau),
+ * d NLL / d gamma_b = w_b (flagged part of nu_b) + tau_b (1 - 1/gamma_b);
+ * gamma_b <= 0 in a bin with a parameter is an invalid density.  The model
+ * keeps the last of nll_hf_set_staterror / nll_hf_set_shapesys. */
+nll_status nll_hf_set_shapesys(nll_hf_model* model, uint32_t sample_mask, const double* sigma);
 
 /* Enqueue: as nll_hf_eval with the per-bin statistical parameters at gamma
  * (device [n_bins], caller's): NLL into *nll_out, the parameters' gradient

@@ -366,9 +366,10 @@ class HFModel:
 
     def __init__(self, spec: dict, device: int = 0):
         """spec: {"n_bins": B, "samples": [names], "params": [{"name",
-        "value", "lo", "hi", "free", "constrained"}...], "modifiers":
-        [{"type": "normfactor"|"normsys"|"histosys", "sample": s,
-        "param": p, ("hi", "lo" for normsys)}...]}"""
+        "value", "lo", "hi", "free", "constrained", ("constraint_mean",
+        "constraint_sigma")}...], "modifiers": [{"type":
+        "normfactor"|"normsys"|"histosys", "sample": s, "param": p, ("hi",
+        "lo" for normsys), ("interp": "poly6" for the smooth codes)}...]}"""
         torch = _torch()
         self.device = torch.device("cuda", device)
         params, mods = spec["params"], spec["modifiers"]
@@ -379,14 +380,19 @@ class HFModel:
         phi = (ctypes.c_double * P)(*[float(p["hi"]) for p in params])
         pfree = (ctypes.c_uint8 * P)(*[1 if p.get("free", True) else 0 for p in params])
         pcon = (ctypes.c_uint8 * P)(*[1 if p.get("constrained", False) else 0 for p in params])
+        pmean = (ctypes.c_double * P)(*[float(p.get("constraint_mean", 0.0)) for p in params])
+        psig = (ctypes.c_double * P)(*[float(p.get("constraint_sigma", 1.0)) for p in params])
         md = (HFModifier * max(M, 1))()
         for i, m in enumerate(mods):
             md[i].type = HF_MODIFIER[m["type"]]
             md[i].sample, md[i].param = int(m["sample"]), int(m["param"])
             md[i].hi, md[i].lo = float(m.get("hi", 1.0)), float(m.get("lo", 1.0))
+            md[i].interp = {"exp": 0, "linear": 0, "poly6": 1}[m.get("interp", "linear" if m["type"] == "histosys"
+                                                                   else "exp")]
         d = HFDesc()
         d.n_bins, d.n_samples, d.n_param = self.n_bins, self.n_samples, P
         d.param_lo, d.param_hi, d.param_free, d.param_constrained = plo, phi, pfree, pcon
+        d.param_mean, d.param_sigma = pmean, psig
         d.n_modifiers, d.modifiers = M, md
         d.device = device
         d.stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
@@ -452,6 +458,19 @@ class HFModel:
             raise NLLError(-1, "sigma needs n_bins entries")
         check(lib().nll_hf_set_staterror(self._h, mask, sigma.data_ptr()), "nll_hf_set_staterror")
         self._keep_sigma = sigma  # read on the stream; kept until that is done
+
+    def set_shapesys(self, samples, sigma):
+        """As set_staterror with Poisson constraints (shapesys): tau_b =
+        1/sigma_b^2 auxiliary counts for the means gamma_b tau_b."""
+        torch = _torch()
+        mask = 0
+        for s in samples:
+            mask |= 1 << int(s)
+        sigma = _dev_tensor(sigma, torch.float64, self.device)
+        if sigma.numel() != self.n_bins:
+            raise NLLError(-1, "sigma needs n_bins entries")
+        check(lib().nll_hf_set_shapesys(self._h, mask, sigma.data_ptr()), "nll_hf_set_shapesys")
+        self._keep_sigma = sigma
 
     def eval_stat(self, theta, gamma, grad=True):
         """(NLL, gradient or None, d NLL / d gamma or None) at theta and the

@@ -19,7 +19,7 @@ EXPORTS = ("nll_create_model", "nll_destroy_model", "nll_set_stream", "nll_set_d
            "nll_fit_bhhh", "nll_sync", "nll_get_schedule",
            "nll_set_schedule", "nll_autotune", "nll_set_option", "nll_step_times", "nll_get_info", "nll_read_probe",
            "nll_status_string", "nll_hf_create", "nll_hf_destroy", "nll_hf_set_data", "nll_hf_eval", "nll_hf_sync",
-           "nll_hf_set_staterror", "nll_hf_eval_stat",
+           "nll_hf_set_staterror", "nll_hf_set_shapesys", "nll_hf_eval_stat",
            "nll_jit_create", "nll_jit_destroy", "nll_jit_set_data", "nll_jit_eval", "nll_jit_sync")
 
 HF_MAX_SAMPLES, HF_MAX_HISTOSYS = 8, 24
@@ -50,13 +50,14 @@ class ModelDesc(ctypes.Structure):
 
 class HFModifier(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("sample", ctypes.c_int32), ("param", ctypes.c_int32),
-                ("hi", ctypes.c_double), ("lo", ctypes.c_double)]
+                ("interp", ctypes.c_int32), ("hi", ctypes.c_double), ("lo", ctypes.c_double)]
 
 
 class HFDesc(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int64), ("n_samples", ctypes.c_int32), ("n_param", ctypes.c_int32),
                 ("param_lo", ctypes.POINTER(ctypes.c_double)), ("param_hi", ctypes.POINTER(ctypes.c_double)),
                 ("param_free", ctypes.POINTER(ctypes.c_uint8)), ("param_constrained", ctypes.POINTER(ctypes.c_uint8)),
+                ("param_mean", ctypes.POINTER(ctypes.c_double)), ("param_sigma", ctypes.POINTER(ctypes.c_double)),
                 ("n_modifiers", ctypes.c_int32), ("modifiers", ctypes.POINTER(HFModifier)),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
@@ -123,6 +124,7 @@ def lib():
         L.nll_hf_set_data.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
         L.nll_hf_eval.argtypes = [vp, vp, vp, vp]
         L.nll_hf_set_staterror.argtypes = [vp, ctypes.c_uint32, vp]
+        L.nll_hf_set_shapesys.argtypes = [vp, ctypes.c_uint32, vp]
         L.nll_hf_eval_stat.argtypes = [vp, vp, vp, vp, vp, vp]
         L.nll_hf_sync.argtypes = [vp, ctypes.POINTER(i32)]
         L.nll_jit_create.argtypes = [ctypes.POINTER(JitDesc), ctypes.POINTER(vp), ctypes.c_char_p, i32]

@@ -23,14 +23,63 @@ __global__ __launch_bounds__(kBlock) void k_hf_deltas(const double* __restrict__
   }
 }
 
+// A normsys factor eta(a) and d eta / d a.  Code 0: hi^a (a >= 0), lo^-a.
+// Code 1 for |a| < 1: eta = 1 + E(a) + O(a), E = c2 a^2 + c4 a^4 + c6 a^6
+// and O = c1 a + c3 a^3 + c5 a^5, whose value, slope and curvature at +-1
+// equal those of hi^a and lo^-a: E and O at a = 1 follow from the sums and
+// differences of the six conditions, and each 3 x 3 system is solved here
+// in closed form.
+__device__ inline void hf_eta(double a, double lnhi, double lnlo, int code, double& eta, double& deta) {
+  if (code == 1 && fabs(a) < 1.0) {
+    const double hi = exp(lnhi), lo = exp(lnlo);
+    const double h1 = hi * lnhi, l1 = lo * lnlo, h2 = h1 * lnhi, l2 = l1 * lnlo;
+    const double E0 = 0.5 * (hi + lo) - 1.0, E1 = 0.5 * (h1 + l1), E2 = 0.5 * (h2 + l2);
+    const double O0 = 0.5 * (hi - lo), O1 = 0.5 * (h1 - l1), O2 = 0.5 * (h2 - l2);
+    const double c6 = 0.125 * (E2 - 5.0 * E1 + 8.0 * E0);
+    const double c4 = 0.5 * (E1 - 2.0 * E0) - 2.0 * c6;
+    const double c2 = E0 - c4 - c6;
+    const double c5 = 0.125 * (O2 - 3.0 * O1 + 3.0 * O0);
+    const double c3 = 0.5 * (O1 - O0) - 2.0 * c5;
+    const double c1 = O0 - c3 - c5;
+    eta = fma(a, fma(a, fma(a, fma(a, fma(a, fma(a, c6, c5), c4), c3), c2), c1), 1.0);
+    deta = fma(a, fma(a, fma(a, fma(a, fma(a, 6.0 * c6, 5.0 * c5), 4.0 * c4), 3.0 * c3), 2.0 * c2), c1);
+    return;
+  }
+  const double L = a >= 0.0 ? lnhi : -lnlo;
+  eta = exp(a * L);
+  deta = L * eta;
+}
+
+// A histosys delta c_u du + c_d dd (du = up - T, dd = T - down) and its
+// derivative g_u du + g_d dd at a.  Code 0: a du (a >= 0), a dd.  Code 1 for
+// |a| < 1: a (S + a A (15 + a^2 (3 a^2 - 10))) with S = (du + dd)/2,
+// A = (du - dd)/16, i.e. c_u = a/2 + p/16, c_d = a/2 - p/16,
+// p = 15 a^2 - 10 a^4 + 3 a^6.
+__device__ inline void hf_histo_coef(double a, int code, double& cu, double& cd, double& gu, double& gd) {
+  if (code == 1 && fabs(a) < 1.0) {
+    const double a2 = a * a;
+    const double p = a2 * fma(a2, fma(3.0, a2, -10.0), 15.0);
+    const double dp = a * fma(a2, fma(18.0, a2, -40.0), 30.0);
+    cu = fma(0.0625, p, 0.5 * a);
+    cd = fma(-0.0625, p, 0.5 * a);
+    gu = fma(0.0625, dp, 0.5);
+    gd = fma(-0.0625, dp, 0.5);
+  } else if (a >= 0.0) {
+    cu = a, cd = 0.0, gu = 1.0, gd = 0.0;
+  } else {
+    cu = 0.0, cd = a, gu = 0.0, gd = 1.0;
+  }
+}
+
 // F_s: the normfactors and normsys factors of sample s at theta (its own
 // index ranges).  Shared by both kernels, so that they use the same bits.
 __device__ inline double hf_factor(const HFPlan& pl, const double* theta, int s) {
   double f = 1.0;
   for (int i = pl.nf_start[s]; i < pl.nf_start[s + 1]; ++i) f *= theta[pl.nf_param[i]];
   for (int k = pl.ns_start[s]; k < pl.ns_start[s + 1]; ++k) {
-    const double a = theta[pl.ns_param[k]];
-    f *= exp(a >= 0.0 ? a * pl.ns_lnhi[k] : -a * pl.ns_lnlo[k]);
+    double eta, deta;
+    hf_eta(theta[pl.ns_param[k]], pl.ns_lnhi[k], pl.ns_lnlo[k], pl.ns_code[k], eta, deta);
+    f *= eta;
   }
   return f;
 }
@@ -77,15 +126,20 @@ __global__ __launch_bounds__(kBlock) void k_hf_tau(const double* __restrict__ si
 
 // STAT: the flagged samples' terms (nominal and histosys deltas) of bin b
 // are summed apart, nu_b = gamma_b nu_flagged + nu_rest, their weighted sums
-// take gamma_b, the constraint 1/2 tau_b (gamma_b - 1)^2 joins the bin's
-// term, and d NLL / d gamma_b = w_b nu_flagged + tau_b (gamma_b - 1) is
+// take gamma_b, the bin's constraint (1/2 tau_b (gamma_b - 1)^2, or
+// tau_b (gamma_b - ln gamma_b) for shapesys) joins its term, and
+// d NLL / d gamma_b = w_b nu_flagged + (the constraint's derivative) is
 // written per bin (0 where the bin has no parameter: gamma_b taken as 1).
-template <bool GRAD, bool STAT>
+// SMOOTH: every histosys reads both delta templates, adds c_u du + c_d dd
+// and sums w du and w dd apart (U_h, L_h); otherwise only the template of
+// alpha's side, a d, and its sum SD_h.
+template <bool GRAD, bool STAT, bool SMOOTH>
 __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const HFArgs a) {
   constexpr int NH = kHfNV / 2, NH2 = kHfNV - NH;  // two reduction passes
+  constexpr int HM = SMOOTH ? kHfPolyHisto : kHfMaxHisto;  // histosys handled
   __shared__ HFPlan pl;
   __shared__ double s_theta[kMaxParams];
-  __shared__ double s_F[kHfMaxSamples], s_c[kHfMaxHisto];
+  __shared__ double s_F[kHfMaxSamples], s_c[kHfMaxHisto], s_cd[kHfMaxHisto];
   __shared__ int s_side[kHfMaxHisto];
   __shared__ int s_ok;
   __shared__ double red[(NH2 > NH ? NH2 : NH) * (kBlock + 1)];
@@ -101,26 +155,43 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
   if (t < kHfMaxHisto) {
     const bool on = t < pl.n_histo;
     const double al = on ? s_theta[pl.histo_param[t]] : 0.0;
-    s_c[t] = on ? s_F[pl.histo_sample[t]] * al : 0.0;
+    const double F = on ? s_F[pl.histo_sample[t]] : 0.0;
+    if constexpr (SMOOTH) {
+      double cu, cd, gu, gd;
+      hf_histo_coef(al, on ? pl.hs_code[t] : 0, cu, cd, gu, gd);
+      s_c[t] = F * cu;
+      s_cd[t] = F * cd;
+    } else {
+      s_c[t] = F * al;
+      s_cd[t] = 0.0;
+    }
     s_side[t] = al >= 0.0;
   }
   __syncthreads();
   const int S = pl.n_samples, H = pl.n_histo;
-  double F[kHfMaxSamples], c[kHfMaxHisto];
-  const double* dp[kHfMaxHisto];
+  double F[kHfMaxSamples], c[HM], c2[HM];
+  const double* dp[HM];
+  const double* dq[HM];
   // STAT: the flagged samples' coefficients (F_s, c_h of their histosys;
   // 0 for the others) and the rest's, uniform: nu_flagged = sum Ff_s T_s +
   // sum cf_h d_h and nu_rest = sum Fr_s T_s + sum cr_h d_h (Fr = F, cr = c
   // without STAT), so that nu = gamma_b nu_flagged + nu_rest has no
   // cancellation however small gamma_b is
-  double Ff[kHfMaxSamples], cf[kHfMaxHisto], fsm[kHfMaxSamples], fhm[kHfMaxHisto];
-  double Fr[kHfMaxSamples], cr[kHfMaxHisto];
+  double Ff[kHfMaxSamples], cf[HM], cf2[HM], fsm[kHfMaxSamples], fhm[HM];
+  double Fr[kHfMaxSamples], cr[HM], cr2[HM];
 #pragma unroll
   for (int s = 0; s < kHfMaxSamples; ++s) F[s] = hf_uniform(s_F[s]);
 #pragma unroll
-  for (int h = 0; h < kHfMaxHisto; ++h) {
+  for (int h = 0; h < HM; ++h) {
     c[h] = hf_uniform(s_c[h]);
-    dp[h] = hf_uniform(s_side[h] ? a.dup[h] : a.ddn[h]);
+    c2[h] = hf_uniform(s_cd[h]);
+    if constexpr (SMOOTH) {
+      dp[h] = a.dup[h];  // both templates
+      dq[h] = a.ddn[h];
+    } else {
+      dp[h] = hf_uniform(s_side[h] ? a.dup[h] : a.ddn[h]);
+      dq[h] = nullptr;
+    }
   }
 #pragma unroll
   for (int s = 0; s < kHfMaxSamples; ++s) {
@@ -129,11 +200,14 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
     Fr[s] = F[s] - Ff[s];
   }
 #pragma unroll
-  for (int h = 0; h < kHfMaxHisto; ++h) {
+  for (int h = 0; h < HM; ++h) {
     fhm[h] = (STAT && h < H && ((pl.stat_mask >> pl.histo_sample[h]) & 1)) ? 1.0 : 0.0;
     cf[h] = fhm[h] * c[h];
     cr[h] = c[h] - cf[h];
+    cf2[h] = fhm[h] * c2[h];
+    cr2[h] = c2[h] - cf2[h];
   }
+  const bool poisson = STAT && pl.stat_kind == 1;
   double acc[kHfNV - 1];
 #pragma unroll
   for (int j = 0; j < kHfNV - 1; ++j) acc[j] = 0.0;
@@ -142,17 +216,23 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t b = (int64_t)blockIdx.x * kBlock + t; b < a.n_bins; b += stride) {
       const double n = a.counts[b];
-      double T[kHfMaxSamples], d[kHfMaxHisto];
+      double T[kHfMaxSamples], d[HM], e[HM];
 #pragma unroll
       for (int s = 0; s < kHfMaxSamples; ++s) T[s] = s < S ? a.nominal[s][b] : 0.0;
 #pragma unroll
-      for (int h = 0; h < kHfMaxHisto; ++h) d[h] = h < H ? dp[h][b] : 0.0;
+      for (int h = 0; h < HM; ++h) {
+        d[h] = h < H ? dp[h][b] : 0.0;
+        e[h] = (SMOOTH && h < H) ? dq[h][b] : 0.0;
+      }
       double nu = 0.0, nu_f = 0.0, g = 1.0, tau = 0.0;
       bool act = false;
 #pragma unroll
       for (int s = 0; s < kHfMaxSamples; ++s) nu = fma(Fr[s], T[s], nu);
 #pragma unroll
-      for (int h = 0; h < kHfMaxHisto; ++h) nu = fma(cr[h], d[h], nu);
+      for (int h = 0; h < HM; ++h) {
+        nu = fma(cr[h], d[h], nu);
+        if constexpr (SMOOTH) nu = fma(cr2[h], e[h], nu);
+      }
       if constexpr (STAT) {
         tau = a.stat_tau[b];
         act = tau > 0.0;
@@ -161,7 +241,10 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
 #pragma unroll
         for (int s = 0; s < kHfMaxSamples; ++s) nu_f = fma(Ff[s], T[s], nu_f);
 #pragma unroll
-        for (int h = 0; h < kHfMaxHisto; ++h) nu_f = fma(cf[h], d[h], nu_f);
+        for (int h = 0; h < HM; ++h) {
+          nu_f = fma(cf[h], d[h], nu_f);
+          if constexpr (SMOOTH) nu_f = fma(cf2[h], e[h], nu_f);
+        }
         nu = fma(g, nu_f, nu);  // gamma_b nu_flagged + nu_rest
       }
       const bool pos = n > 0.0;
@@ -170,27 +253,37 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
       const double lnu = pos && nu > 0.0 ? log_pos(nu) : 0.0;
       acc[0] += fma(-n, lnu, nu);
       if constexpr (STAT) {
-        const double dg = g - 1.0;
-        if (act) acc[0] = fma(0.5 * tau * dg, dg, acc[0]);
+        if (act) {
+          if (poisson) {
+            bad += !(g > 0.0);
+            acc[0] = fma(tau, g - (g > 0.0 ? log_pos(g) : 0.0), acc[0]);
+          } else {
+            const double dg = g - 1.0;
+            acc[0] = fma(0.5 * tau * dg, dg, acc[0]);
+          }
+        }
       }
       if constexpr (GRAD) {
         const double w = pos ? fma(-n, rcp_full(nu), 1.0) : 1.0;
-        if constexpr (STAT) {
-          // the flagged samples' sums take w gamma_b: w + w (gamma_b - 1) [flagged]
-          const double wd = w * (g - 1.0);
+        // the flagged samples' sums take w gamma_b: w + w (gamma_b - 1) [flagged]
+        const double wd = STAT ? w * (g - 1.0) : 0.0;
 #pragma unroll
-          for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(fma(wd, fsm[s], w), T[s], acc[1 + s]);
+        for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(fma(wd, fsm[s], w), T[s], acc[1 + s]);
 #pragma unroll
-          for (int h = 0; h < kHfMaxHisto; ++h)
-            acc[1 + kHfMaxSamples + h] = fma(fma(wd, fhm[h], w), d[h], acc[1 + kHfMaxSamples + h]);
-        } else {
-#pragma unroll
-          for (int s = 0; s < kHfMaxSamples; ++s) acc[1 + s] = fma(w, T[s], acc[1 + s]);
-#pragma unroll
-          for (int h = 0; h < kHfMaxHisto; ++h) acc[1 + kHfMaxSamples + h] = fma(w, d[h], acc[1 + kHfMaxSamples + h]);
+        for (int h = 0; h < HM; ++h) {
+          const double wh = fma(wd, fhm[h], w);
+          if constexpr (SMOOTH) {
+            acc[1 + kHfMaxSamples + 2 * h] = fma(wh, d[h], acc[1 + kHfMaxSamples + 2 * h]);
+            acc[2 + kHfMaxSamples + 2 * h] = fma(wh, e[h], acc[2 + kHfMaxSamples + 2 * h]);
+          } else {
+            acc[1 + kHfMaxSamples + h] = fma(wh, d[h], acc[1 + kHfMaxSamples + h]);
+          }
         }
         if constexpr (STAT) {
-          if (a.grad_gamma) a.grad_gamma[b] = act ? fma(w, nu_f, tau * (g - 1.0)) : 0.0;
+          if (a.grad_gamma) {
+            const double dc = poisson ? tau * (1.0 - (g > 0.0 ? 1.0 / g : 0.0)) : tau * (g - 1.0);
+            a.grad_gamma[b] = act ? fma(w, nu_f, dc) : 0.0;
+          }
         }
       }
     }
@@ -208,12 +301,14 @@ __global__ __launch_bounds__(kBlock) void k_hf_stream(const HFPlan plan, const H
 
 // Finishing block: the partials in block order, then NLL, status and the
 // gradient from the per-sample and per-histosys sums:
-//   SA_s = ST_s + sum_{h on s} alpha_h SD_h  (= sum_b w_b (T_sb + deltas))
+//   SA_s = ST_s + sum_{h on s} V_h  (= sum_b w_b (T_sb + deltas)), with
+//          V_h = alpha_h SD_h, or (smooth) c_u U_h + c_d L_h
 //   normfactor mu on s:  (F_s / mu) SA_s, F_s / mu formed as the product of
 //                        the sample's other factors
-//   normsys alpha on s:  F_s L SA_s, L = ln hi (alpha >= 0) or -ln lo
-//   histosys h:          F_{s_h} SD_h
-//   constrained p:       + theta_p
+//   normsys alpha on s:  F_s L SA_s, L = eta'(alpha) / eta(alpha) (ln hi or
+//                        -ln lo for the exponential code)
+//   histosys h:          F_{s_h} SD_h, or (smooth) F_{s_h} (g_u U_h + g_d L_h)
+//   constrained p:       + (theta_p - m_p) / s_p^2
 // Each modifier's term is formed by a thread of its own; a parameter's
 // thread then adds the terms of the modifiers it drives, in modifier order.
 template <bool GRAD>
@@ -239,18 +334,31 @@ __global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan plan, c
     double c = 0.0;
     if (p < pl.n_param) {
       if (!hf_par_ok(pl, s_theta, p)) s_ok = 0;
-      if (pl.par_constrained[p]) c = 0.5 * s_theta[p] * s_theta[p];
+      if (pl.par_constrained[p]) {
+        const double dv = s_theta[p] - pl.par_mean[p];
+        c = 0.5 * dv * dv * pl.par_ivar[p];
+      }
     }
     s_cons[p] = c;
   }
   rs.reduce(reinterpret_cast<const DD*>(a.partials), n_blocks, tot);  // ends with a barrier
   const auto val = [&](int j) { return tot[j].hi + tot[j].lo; };
+  const bool smooth = pl.smooth_histo != 0;
   if (t < kHfMaxSamples) {
     double sa = 0.0;
     if (t < pl.n_samples) {
       sa = val(1 + t);
-      for (int h = pl.hs_start[t]; h < pl.hs_start[t + 1]; ++h)
-        sa = fma(s_theta[pl.histo_param[h]], val(1 + kHfMaxSamples + h), sa);
+      for (int h = pl.hs_start[t]; h < pl.hs_start[t + 1]; ++h) {
+        const double al = s_theta[pl.histo_param[h]];
+        if (smooth) {
+          double cu, cd, gu, gd;
+          hf_histo_coef(al, pl.hs_code[h], cu, cd, gu, gd);
+          sa = fma(cu, val(1 + kHfMaxSamples + 2 * h), sa);
+          sa = fma(cd, val(2 + kHfMaxSamples + 2 * h), sa);
+        } else {
+          sa = fma(al, val(1 + kHfMaxSamples + h), sa);
+        }
+      }
     }
     s_SA[t] = sa;
   }
@@ -267,8 +375,9 @@ __global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan plan, c
         for (int i = pl.nf_start[s]; i < pl.nf_start[s + 1]; ++i)
           if (i != j) others *= s_theta[pl.nf_param[i]];
         for (int k = pl.ns_start[s]; k < pl.ns_start[s + 1]; ++k) {
-          const double al = s_theta[pl.ns_param[k]];
-          others *= exp(al >= 0.0 ? al * pl.ns_lnhi[k] : -al * pl.ns_lnlo[k]);
+          double eta, deta;
+          hf_eta(s_theta[pl.ns_param[k]], pl.ns_lnhi[k], pl.ns_lnlo[k], pl.ns_code[k], eta, deta);
+          others *= eta;
         }
         term = others * s_SA[s];
       }
@@ -276,12 +385,29 @@ __global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan plan, c
       const int k = j - kHfMaxNormfactor;
       if (k < pl.n_normsys) {
         const int s = pl.ns_sample[k];
-        const double L = s_theta[pl.ns_param[k]] >= 0.0 ? pl.ns_lnhi[k] : -pl.ns_lnlo[k];
+        const double al = s_theta[pl.ns_param[k]];
+        double L;
+        if (pl.ns_code[k] == 1 && fabs(al) < 1.0) {
+          double eta, deta;
+          hf_eta(al, pl.ns_lnhi[k], pl.ns_lnlo[k], 1, eta, deta);
+          L = deta / eta;
+        } else {
+          L = al >= 0.0 ? pl.ns_lnhi[k] : -pl.ns_lnlo[k];
+        }
         term = s_F[s] * L * s_SA[s];
       }
     } else {
       const int h = j - kHfMaxNormfactor - kHfMaxNormsys;
-      if (h < pl.n_histo) term = s_F[pl.histo_sample[h]] * val(1 + kHfMaxSamples + h);
+      if (h < pl.n_histo) {
+        if (smooth) {
+          double cu, cd, gu, gd;
+          hf_histo_coef(s_theta[pl.histo_param[h]], pl.hs_code[h], cu, cd, gu, gd);
+          term = s_F[pl.histo_sample[h]] *
+                 fma(gu, val(1 + kHfMaxSamples + 2 * h), gd * val(2 + kHfMaxSamples + 2 * h));
+        } else {
+          term = s_F[pl.histo_sample[h]] * val(1 + kHfMaxSamples + h);
+        }
+      }
     }
     s_term[j] = term;
   }
@@ -303,7 +429,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_hf_finish(const HFPlan plan, c
     double g = 0.0;
     if (status == 0) {
       for (int i = pl.par_start[q]; i < pl.par_start[q + 1]; ++i) g += s_term[pl.par_slot[i]];
-      if (pl.par_constrained[q]) g += s_theta[q];
+      if (pl.par_constrained[q]) g = fma(s_theta[q] - pl.par_mean[q], pl.par_ivar[q], g);
     }
     a.grad_out[q] = pl.par_free[q] ? g : 0.0;
   }
@@ -328,12 +454,21 @@ hipError_t launch_hf_tau(const double* sigma, int64_t n, double* tau, hipStream_
 
 hipError_t launch_hf_eval(const HFPlan& pl, const HFArgs& a, bool grad, int grid, hipStream_t st) {
   const bool stat = a.gamma != nullptr;
-  if (stat) {
-    if (grad) hipLaunchKernelGGL((k_hf_stream<true, true>), dim3(grid), dim3(kBlock), 0, st, pl, a);
-    else hipLaunchKernelGGL((k_hf_stream<false, true>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+  const dim3 g(grid), b(kBlock);
+  if (pl.smooth_histo) {
+    if (stat) {
+      if (grad) hipLaunchKernelGGL((k_hf_stream<true, true, true>), g, b, 0, st, pl, a);
+      else hipLaunchKernelGGL((k_hf_stream<false, true, true>), g, b, 0, st, pl, a);
+    } else {
+      if (grad) hipLaunchKernelGGL((k_hf_stream<true, false, true>), g, b, 0, st, pl, a);
+      else hipLaunchKernelGGL((k_hf_stream<false, false, true>), g, b, 0, st, pl, a);
+    }
+  } else if (stat) {
+    if (grad) hipLaunchKernelGGL((k_hf_stream<true, true, false>), g, b, 0, st, pl, a);
+    else hipLaunchKernelGGL((k_hf_stream<false, true, false>), g, b, 0, st, pl, a);
   } else {
-    if (grad) hipLaunchKernelGGL((k_hf_stream<true, false>), dim3(grid), dim3(kBlock), 0, st, pl, a);
-    else hipLaunchKernelGGL((k_hf_stream<false, false>), dim3(grid), dim3(kBlock), 0, st, pl, a);
+    if (grad) hipLaunchKernelGGL((k_hf_stream<true, false, false>), g, b, 0, st, pl, a);
+    else hipLaunchKernelGGL((k_hf_stream<false, false, false>), g, b, 0, st, pl, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -81,11 +81,18 @@ nll_status nll_hf_create(const nll_hf_desc* d, nll_hf_model** out) {
     pl.par_hi[p] = d->param_hi[p];
     pl.par_free[p] = d->param_free ? (d->param_free[p] != 0) : 1;
     pl.par_constrained[p] = d->param_constrained ? (d->param_constrained[p] != 0) : 0;
+    const double mean = d->param_mean ? d->param_mean[p] : 0.0;
+    const double sig = d->param_sigma ? d->param_sigma[p] : 1.0;
+    if (pl.par_constrained[p] && !(std::isfinite(mean) && sig > 0.0 && std::isfinite(sig))) return NLL_ERR_ARG;
+    pl.par_mean[p] = mean;
+    pl.par_ivar[p] = 1.0 / (sig * sig);
   }
-  int n_nf = 0, n_ns = 0, n_hs = 0;
+  int n_nf = 0, n_ns = 0, n_hs = 0, n_smooth_hs = 0;
   for (int i = 0; i < d->n_modifiers; ++i) {
     const nll_hf_modifier& md = d->modifiers[i];
     if (md.sample < 0 || md.sample >= d->n_samples || md.param < 0 || md.param >= d->n_param) return NLL_ERR_ARG;
+    if (md.interp != 0 && md.interp != 1) return NLL_ERR_ARG;
+    if (md.type == NLL_HF_HISTOSYS && md.interp == 1) ++n_smooth_hs;
     if (md.type == NLL_HF_NORMFACTOR) {
       ++n_nf;
     } else if (md.type == NLL_HF_NORMSYS) {
@@ -98,6 +105,10 @@ nll_status nll_hf_create(const nll_hf_desc* d, nll_hf_model** out) {
     }
   }
   if (n_nf > kHfMaxNormfactor || n_ns > kHfMaxNormsys || n_hs > kHfMaxHisto) return NLL_ERR_UNSUPPORTED;
+  // a smooth histosys: both delta templates of every histosys are summed
+  // apart, two record slots each
+  if (n_smooth_hs > 0 && n_hs > kHfPolyHisto) return NLL_ERR_UNSUPPORTED;
+  pl.smooth_histo = n_smooth_hs > 0 ? 1 : 0;
   // each kind sorted by sample (stable), with per-sample ranges; histo_caller
   // maps a sorted histosys to its position in the caller's template order
   int histo_caller[kHfMaxHisto] = {};
@@ -116,10 +127,12 @@ nll_status nll_hf_create(const nll_hf_desc* d, nll_hf_model** out) {
       } else if (md.type == NLL_HF_NORMSYS) {
         pl.ns_sample[pl.n_normsys] = s;
         pl.ns_param[pl.n_normsys] = md.param;
+        pl.ns_code[pl.n_normsys] = md.interp;
         pl.ns_lnhi[pl.n_normsys] = std::log(md.hi);
         pl.ns_lnlo[pl.n_normsys++] = std::log(md.lo);
       } else {
         histo_caller[pl.n_histo] = caller_h - 1;
+        pl.hs_code[pl.n_histo] = md.interp;
         pl.histo_sample[pl.n_histo] = s;
         pl.histo_param[pl.n_histo++] = md.param;
       }
@@ -215,7 +228,7 @@ nll_status nll_hf_set_data(nll_hf_model* m, const double* counts, const double* 
   return NLL_OK;
 }
 
-nll_status nll_hf_set_staterror(nll_hf_model* m, uint32_t sample_mask, const double* sigma) {
+static nll_status hf_set_bin_params(nll_hf_model* m, uint32_t sample_mask, const double* sigma, int kind) {
   if (!m) return NLL_ERR_ARG;
   const int S = m->plan.n_samples;
   if (sample_mask == 0 || (S < 32 && (sample_mask >> S) != 0)) return NLL_ERR_ARG;
@@ -227,8 +240,17 @@ nll_status nll_hf_set_staterror(nll_hf_model* m, uint32_t sample_mask, const dou
   }
   if (m->n_bins > 0 && launch_hf_tau(sigma, m->n_bins, m->stat_tau, m->stream) != hipSuccess) return NLL_ERR_DEVICE;
   m->plan.stat_mask = (int32_t)sample_mask;
+  m->plan.stat_kind = kind;
   m->have_stat = true;
   return NLL_OK;
+}
+
+nll_status nll_hf_set_staterror(nll_hf_model* m, uint32_t sample_mask, const double* sigma) {
+  return hf_set_bin_params(m, sample_mask, sigma, 0);
+}
+
+nll_status nll_hf_set_shapesys(nll_hf_model* m, uint32_t sample_mask, const double* sigma) {
+  return hf_set_bin_params(m, sample_mask, sigma, 1);
 }
 
 static nll_status hf_eval_impl(nll_hf_model* m, const double* theta, const double* gamma, double* nll_out,

@@ -259,3 +259,189 @@ def test_hf_staterror_errors(torch, nllmi):
     assert math.isinf(float(v.item())) and m.sync() == -5
     v, _, _ = m.eval_stat(th, gamma)
     assert math.isfinite(float(v.item())) and m.sync() == 0
+
+
+# ---------------------------------------------------------------------------
+# smooth interpolation codes, shifted constraints (luminosity), shapesys
+# ---------------------------------------------------------------------------
+
+def _smooth(spec, histo=True, normsys=True, every=1):
+    """A copy of spec with every `every`-th histosys / normsys on the smooth code."""
+    spec = copy.deepcopy(spec)
+    k = {"histosys": 0, "normsys": 0}
+    for m in spec["modifiers"]:
+        if m["type"] in k:
+            if k[m["type"]] % every == 0 and (histo if m["type"] == "histosys" else normsys):
+                m["interp"] = "poly6"
+            k[m["type"]] += 1
+    return spec
+
+
+def _edge_points(w, spec):
+    """The seeded points, then alphas at the codes' joins (+-1), at 0 and just
+    inside and outside the polynomial region."""
+    pts = [p for p in w["points"]]
+    alphas = [p for p, par in enumerate(spec["params"]) if par["name"].startswith("alpha")]
+    base = w["points"][0]
+    for vals in ((1.0, -1.0), (0.0, -0.0), (0.999, -0.999), (1.001, -1.001), (0.03, -0.4)):
+        th = base.copy()
+        for i, p in enumerate(alphas):
+            th[p] = vals[i % 2]
+        pts.append(th)
+    return np.array(pts)
+
+
+@pytest.mark.parametrize("n_bins", [1, 257, 100_003])
+def test_hf_smooth_codes(torch, nllmi, n_bins):
+    """Every normsys on the sixth-order polynomial and every histosys on the
+    polynomial interpolation with linear extrapolation: NLL and gradient at
+    seeded points (alphas inside and outside [-1, 1]) and at the joins."""
+    w = datagen.hf_workload(n_bins=n_bins, n_samples=3, n_histosys=6, n_normsys=4, n_points=3)
+    print(f"[hf smooth B={n_bins}]", flush=True)
+    spec = _smooth(w["spec"])
+    check(torch, make(nllmi, w, spec), spec, w, _edge_points(w, spec))
+
+
+def test_hf_smooth_mixed_and_limits(torch, nllmi):
+    """Smooth and default codes mixed within samples and on shared alphas;
+    12 histosys (the limit of a model with a smooth histosys) at 2e6 bins;
+    a 13th rejected as unsupported, while 24 histosys on the default code
+    and smooth normsys are accepted."""
+    w = datagen.hf_workload(n_bins=20_011, n_samples=4, n_histosys=10, n_normsys=6, n_points=3)
+    print("[hf smooth mixed]", flush=True)
+    spec = _smooth(w["spec"], every=2)
+    hs = [m for m in spec["modifiers"] if m["type"] == "histosys"]
+    ns = [m for m in spec["modifiers"] if m["type"] == "normsys"]
+    hs[1]["param"] = hs[0]["param"]  # one alpha: a smooth and a linear histosys
+    ns[1]["param"] = ns[0]["param"]  # one alpha: a smooth and an exponential normsys
+    check(torch, make(nllmi, w, spec), spec, w, _edge_points(w, spec))
+    w = datagen.hf_workload(n_bins=2_000_000, n_samples=4, n_histosys=12, n_normsys=4, n_points=2)
+    print("[hf smooth B=2e6 H=12]", flush=True)
+    spec = _smooth(w["spec"])
+    check(torch, make(nllmi, w, spec), spec, w, w["points"])
+    w13 = datagen.hf_workload(n_bins=100, n_samples=3, n_histosys=13, n_normsys=2, n_points=1)
+    with pytest.raises(nllmi.NLLError) as e:
+        nllmi.HFModel(_smooth(w13["spec"], normsys=False))
+    assert e.value.status == -2
+    w24 = datagen.hf_workload(n_bins=3000, n_samples=4, n_histosys=24, n_normsys=4, n_points=2)
+    spec = _smooth(w24["spec"], histo=False)
+    check(torch, make(nllmi, w24, spec), spec, w24, w24["points"])
+    bad = copy.deepcopy(spec)
+    bad["modifiers"][0]["interp"] = "cubic"
+    with pytest.raises(KeyError):
+        nllmi.HFModel(bad)
+
+
+def test_hf_luminosity_and_shifted_constraints(torch, nllmi):
+    """A luminosity parameter: one normfactor shared by three samples,
+    constrained with mean 1 and width 0.02; one alpha constrained with mean
+    0.3 and width 0.5; smooth codes.  A width <= 0 is an argument error."""
+    w = datagen.hf_workload(n_bins=50_021, n_samples=4, n_histosys=6, n_normsys=3, n_points=3)
+    print("[hf lumi]", flush=True)
+    spec = _smooth(w["spec"])
+    P = len(spec["params"])
+    spec["params"].append({"name": "lumi", "value": 1.0, "lo": 0.5, "hi": 1.5, "free": True, "constrained": True,
+                           "constraint_mean": 1.0, "constraint_sigma": 0.02})
+    for s in (0, 2, 3):
+        spec["modifiers"].append({"type": "normfactor", "sample": s, "param": P})
+    a = next(p for p, par in enumerate(spec["params"]) if par["name"].startswith("alpha"))
+    spec["params"][a]["constraint_mean"], spec["params"][a]["constraint_sigma"] = 0.3, 0.5
+    rng = np.random.default_rng(5)
+    pts = np.array([np.append(p, 1.0 + rng.uniform(-0.05, 0.05)) for p in w["points"]])
+    check(torch, make(nllmi, w, spec), spec, w, pts)
+    bad = copy.deepcopy(spec)
+    bad["params"][P]["constraint_sigma"] = 0.0
+    with pytest.raises(nllmi.NLLError) as e:
+        nllmi.HFModel(bad)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("n_bins", [1, 257, 100_003])
+def test_hf_shapesys(torch, nllmi, n_bins):
+    """Per-bin parameters with Poisson constraints (shapesys) on sample 0 and
+    sample 2, smooth codes: NLL, gradient and d NLL / d gamma_b against the
+    oracle; bins without a parameter included."""
+    w = datagen.hf_workload(n_bins=n_bins, n_samples=3, n_histosys=5, n_normsys=3, n_points=2)
+    print(f"[hf shapesys B={n_bins}]", flush=True)
+    spec = _smooth(w["spec"])
+    m = make(nllmi, w, spec)
+    sigma, gamma = _stat_inputs(n_bins, seed=41 + n_bins)
+    m.set_shapesys([0, 2], sigma)
+    check_stat_kind(torch, m, spec, w, 0b101, sigma, gamma, w["points"], "poisson")
+    # the same model switched to staterror: the Gaussian constraint again
+    m.set_staterror([0, 2], sigma)
+    check_stat_kind(torch, m, spec, w, 0b101, sigma, gamma, w["points"][:1], "gauss")
+
+
+def test_hf_shapesys_full_and_errors(torch, nllmi):
+    """The benchmarked template model (2e6 bins) with shapesys on the two
+    backgrounds; then gamma_b <= 0 in a bin with a parameter (an invalid
+    Poisson mean: +inf and status -5) and in a bin without one (ignored)."""
+    w = datagen.hf_workload(n_points=1)
+    print("[hf shapesys B=2e6]", flush=True)
+    m = make(nllmi, w)
+    sigma, gamma = _stat_inputs(w["spec"]["n_bins"], seed=43)
+    m.set_shapesys([1, 2], sigma)
+    check_stat_kind(torch, m, w["spec"], w, 0b110, sigma, gamma, w["points"], "poisson")
+    th = torch.from_numpy(np.ascontiguousarray(w["points"][0]))
+    g2 = torch.from_numpy(gamma.copy())
+    active = int(np.flatnonzero((sigma > 0) & np.isfinite(sigma))[5])
+    g2[active] = 0.0
+    v, _, _ = m.eval_stat(th, g2)
+    assert math.isinf(float(v.item())) and m.sync() == -5
+    g3 = torch.from_numpy(gamma.copy())
+    g3[0] = -1e-3  # sigma[0] = 0: no parameter in bin 0
+    assert sigma[0] == 0.0
+    st, ref, _, _ = hf.nll(w["spec"], w["counts"], w["nominal"], w["up"], w["down"], w["points"][0],
+                           stat=(0b110, sigma, g3.numpy(), "poisson"))
+    v, _, _ = m.eval_stat(th, g3)
+    assert st == hf.OK and abs(float(v.item()) - ref) <= NLL_TOL * abs(ref) and m.sync() == 0
+
+
+def check_stat_kind(torch, m, spec, w, mask, sigma, gamma, points, kind):
+    for th in points:
+        st, ref, gref, ggref = hf.nll(spec, w["counts"], w["nominal"], w["up"], w["down"], th,
+                                      stat=(mask, sigma, gamma, kind))
+        assert st == hf.OK
+        nu, _ = hf.expected(spec, w["nominal"], w["up"], w["down"], th, (mask, sigma, gamma))
+        n = w["counts"]
+        wgt = np.where(n > 0, 1.0 - n / np.where(nu > 0, nu, 1.0), 1.0)
+        v, g, gg = m.eval_stat(torch.from_numpy(np.ascontiguousarray(th)), torch.from_numpy(gamma))
+        v, g, gg = float(v.item()), g.cpu().numpy(), gg.cpu().numpy()
+        assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
+        act = (sigma > 0) & np.isfinite(sigma)
+        tau = np.where(act, 1.0 / np.where(act, sigma, 1.0) ** 2, 0.0)
+        scale = np.abs(wgt) * np.abs(nu) + np.abs(ggref) + tau + 1.0
+        assert np.all(np.abs(gg - ggref) <= 1e-12 * scale), np.max(np.abs(gg - ggref) / scale)
+    assert m.sync() == 0
+
+
+def test_hf_smooth_lbfgs_fit(torch, nllmi):
+    """With the smooth codes the likelihood has no kink at alpha = 0, so
+    torch's L-BFGS through NLL.apply fits every parameter (normfactors,
+    histosys and normsys alphas, luminosity) to the oracle's stationary
+    point."""
+    w = datagen.hf_workload(n_bins=20_000, n_samples=3, n_histosys=4, n_normsys=2, n_points=1)
+    print("[hf smooth lbfgs]", flush=True)
+    spec = _smooth(w["spec"])
+    m = make(nllmi, w, spec)
+    th = torch.tensor(w["points"][0], dtype=torch.float64, device="cuda", requires_grad=True)
+    opt = torch.optim.LBFGS([th], max_iter=500, history_size=20, tolerance_grad=1e-14, tolerance_change=1e-16,
+                            line_search_fn="strong_wolfe")
+
+    def closure():
+        opt.zero_grad()
+        v = nllmi.NLL.apply(th, m)
+        v.backward()
+        return v
+
+    v0 = float(nllmi.NLL.apply(th.detach(), m).item())
+    opt.step(closure)
+    res = th.detach().cpu().numpy()
+    st, v, g = hf.nll(spec, w["counts"], w["nominal"], w["up"], w["down"], res)
+    nu, dnu = hf.expected(spec, w["nominal"], w["up"], w["down"], res)
+    n = w["counts"]
+    G = max(float(np.sum(np.abs(np.where(n > 0, 1.0 - n / nu, 1.0) * d))) for d in dnu)
+    assert st == hf.OK and v < v0
+    assert np.max(np.abs(g)) <= 1e-7 * G, (g, G)
