@@ -128,26 +128,26 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
 }
 
 // Gradient-descent state of set s as read at the start of a finishing
-// kernel (thread 0: f_acc, eta; thread q < P: its parameter's entries), so
-// that these loads travel together with the kernel's other loads.
+// kernel (f_acc, eta and the last status; thread q < P: its parameter's
+// entries), so that these loads travel together with the kernel's other
+// loads.  Every lane loads, with neither a branch nor a select after the
+// load (threads q >= P read parameter 0's entries, which no caller uses),
+// so that the waits that follow count these loads exactly.
 struct GDPre {
-  double fa, eta;         // thread 0
-  int ls;                 // thread 0: last status
+  double fa, eta;         // every thread
+  int ls;                 // every thread: last status
   double acc, ga, prop;   // thread q < P
 };
 __device__ inline GDPre gd_preload(const GDState& gd, int s, int P) {
-  GDPre r{0.0, 0.0, 0, 0.0, 0.0, 0.0};
+  GDPre r;
   const int q = threadIdx.x;
-  if (q == 0) {
-    r.fa = gd.f_acc[s];
-    r.eta = gd.eta[s];
-    r.ls = gd.last_status[s];
-  }
-  if (q < P) {
-    r.acc = gd.th_acc[(size_t)s * P + q];
-    r.ga = gd.g_acc[(size_t)s * P + q];
-    r.prop = gd.th_prop[(size_t)s * P + q];
-  }
+  r.fa = gd.f_acc[s];
+  r.eta = gd.eta[s];
+  r.ls = gd.last_status[s];
+  const size_t i = (size_t)s * P + (q < P ? q : 0);
+  r.acc = gd.th_acc[i];
+  r.ga = gd.g_acc[i];
+  r.prop = gd.th_prop[i];
   return r;
 }
 
@@ -516,6 +516,24 @@ __device__ inline void preload_ring(const double* const* cols, int64_t base0, in
     if (j < count) load_tile<M, U, NT>(cols, base0 + j * stride, xb[j]);
 }
 
+// The same with every load issued: tiles past count read the word at dummy
+// (any valid address; the values are never used), so that the waits of a
+// kernel start that loads its inputs before these tiles and uses them
+// after count exactly the loads in flight.
+template <class M, int U, int R>
+__device__ inline void preload_ring_all(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
+                                        const double* dummy, double (&xb)[R][U][M::NOBS]) {
+#pragma unroll
+  for (int j = 0; j < R - 1; ++j) {
+    const bool in = j < count;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int o = 0; o < M::NOBS; ++o)
+        xb[j][u][o] = *(in ? cols[o] + base0 + j * stride + (int64_t)u * kBlock : dummy);
+  }
+}
+
 template <class M, bool GRAD, int U, int R, bool NT = false, class CT, class AT>
 __device__ inline void stream_tiles(const double* const* cols, int64_t base0, int64_t stride, int64_t count,
                                     double (&xb)[R][U][M::NOBS], const CT& C, AT& acc) {
@@ -592,9 +610,15 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   // Fit: the constants of the proposal were prepared by the previous step's
   // finishing kernel; the event pass reads the few it needs straight from
   // there (uniform loads), overlapping the first tiles' loads.
+  // Every load is issued before the first LDS copy is written: plan
+  // words and parameters, then the first event tiles.
+  PlanRegs<kBlock> plr;
+  double thv = 0.0;
   if constexpr (!FIT) {
-    stage_plan<kBlock>(pl, &spl);
-    stage_theta(a.theta, pl.n_param, s_theta);
+    plr.load(pl);
+    const int P = pl.n_param;
+    const double v = a.theta[(int)threadIdx.x < P ? threadIdx.x : 0];
+    thv = (int)threadIdx.x < P ? v : 0.0;
   }
   const double* cols[M::NOBS];
 #pragma unroll
@@ -604,7 +628,11 @@ __global__ __launch_bounds__(kBlock) void k_single(const Plan pl, const SingleAr
   const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const int64_t base0 = (int64_t)blockIdx.x * tile + threadIdx.x;
   double xb[ring_depth<M>()][U][M::NOBS];
-  preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
+  preload_ring_all<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, a.glx, xb);
+  if constexpr (!FIT) {
+    plr.store(&spl);
+    if ((int)threadIdx.x < pl.n_param) s_theta[threadIdx.x] = thv;
+  }
 
   using CT = typename Pass<M, GRAD>::C;
   __shared__ double s_etab[CT::kExpTab ? kExpTabSize : 1];
@@ -756,21 +784,22 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
   const int t = threadIdx.x;
   const bool first = a.partials_prev == nullptr;
 
-  // loads in the order they are needed (they complete in order): plan,
-  // state and the previous proposal's constants and records, then the
-  // first event tiles
-  GDPre pre{};
-  PtRegs<M, kBlock> ptv;
+  // Every load is issued, in the order the values are needed (loads
+  // complete in order), before the first LDS copy is written: plan, state
+  // and the previous proposal's constants and records, then the first event
+  // tiles; each copy then waits for its own loads only.  The first step (no
+  // records yet) issues the same loads from buffers that exist and ignores
+  // them, so that no branch stands between the loads.
+  PlanRegs<kBlock> plr;
+  plr.load(pl);
+  const GDPre pre = gd_preload(a.gd, 0, pl.n_param);  // .prop: the proposal evaluated last
   double neff = (double)a.n;
+  if constexpr (M::WEIGHTED) neff = *a.wsum;
+  PtRegs<M, kBlock> ptv;
+  ptv.load(a.consts, pl.n_param);
+  const DD* rec = reinterpret_cast<const DD*>(first ? a.partials : a.partials_prev);
   RecordSumT<NV, kBlock, 16> rs;
-  if (!first) {
-    stage_plan<kBlock>(pl, &spl);
-    stage_theta(a.gd.th_prop, pl.n_param, s_theta);
-    pre = gd_preload(a.gd, 0, pl.n_param);
-    if constexpr (M::WEIGHTED) neff = *a.wsum;
-    ptv.load(a.consts, pl.n_param);
-    rs.issue(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x);
-  }
+  rs.issue(rec, gridDim.x);
   const double* cols[M::NOBS];
 #pragma unroll
   for (int o = 0; o < M::NOBS; ++o) cols[o] = a.cols[o];
@@ -779,7 +808,9 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
   const int64_t mine = nfull > (int64_t)blockIdx.x ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const int64_t base0 = (int64_t)blockIdx.x * tile + t;
   double xb[ring_depth<M>()][U][M::NOBS];
-  preload_ring<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, xb);
+  preload_ring_all<M, U>(cols, base0, (int64_t)gridDim.x * tile, mine, a.glx, xb);
+  plr.store(&spl);
+  if (t < pl.n_param) s_theta[t] = pre.prop;
   if constexpr (CT::kExpTab) stage_exp_table(s_etab);
   if constexpr (M::EVENT_LOG) stage_log_table(g_log_tab);
 
@@ -794,7 +825,7 @@ __global__ __launch_bounds__(kBlock) void k_single_fit(const Plan pl, const Sing
     bad = uniform(a.consts->bad);
   } else {
     ptv.store(&pt, pl.n_param);
-    rs.reduce(reinterpret_cast<const DD*>(a.partials_prev), gridDim.x, tot);  // ends with a barrier
+    rs.reduce(rec, gridDim.x, tot);  // ends with a barrier
     finish_block<M, true>(spl, pt, tot, neff, s_theta, false, &s_nll, &s_st, s_grad);
     const double next = gd_update_to(spl, a.gd_out, s_st, s_nll, s_grad, neff, pre, blockIdx.x == 0);
     if (t < spl.n_param) s_theta[t] = next;  // compute_pertheta starts with a barrier

@@ -179,12 +179,15 @@ template <class M, int NT>
 struct PtRegs {
   static constexpr int N = (PtWords<M>::kMax + NT - 1) / NT;
   double v[N];
+  // every lane loads (lanes past the words read word 0, which store()
+  // drops), with neither a branch nor a select after the load, so that the
+  // waits that follow count these loads exactly
   __device__ void load(const PerTheta* src, int P) {
     const double* s = reinterpret_cast<const double*>(src);
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const int i = threadIdx.x + j * NT;
-      v[j] = i < PtWords<M>::count(P) ? s[PtWords<M>::word(i, P)] : 0.0;
+      v[j] = s[i < PtWords<M>::count(P) ? PtWords<M>::word(i, P) : 0];
     }
   }
   __device__ void store(PerTheta* dst, int P) const {
@@ -213,6 +216,34 @@ __device__ inline void stage_plan(const Plan& src, Plan* dst) {
 __device__ inline void stage_theta(const double* __restrict__ theta_g, int n_param, double* dst) {
   if ((int)threadIdx.x < n_param) dst[threadIdx.x] = theta_g[threadIdx.x];
 }
+
+// The plan's words in registers, NT threads each holding up to N of them:
+// a kernel start that issues all its loads (plan, parameters, constants,
+// records, the first event tiles) before it writes any of them to LDS
+// waits for each only when it stores it, instead of one round trip per
+// staged copy.  Every lane loads (lanes past the plan read word 0).
+template <int NT>
+struct PlanRegs {
+  static constexpr int W = (int)(sizeof(Plan) / 8);
+  static constexpr int N = (W + NT - 1) / NT;
+  uint2 w[N];
+  __device__ void load(const Plan& src) {
+    const uint2* s = reinterpret_cast<const uint2*>(&src);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int i = (int)threadIdx.x + j * NT;
+      w[j] = s[i < W ? i : 0];
+    }
+  }
+  __device__ void store(Plan* dst) const {
+    uint2* d = reinterpret_cast<uint2*>(dst);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int i = (int)threadIdx.x + j * NT;
+      if (i < W) d[i] = w[j];
+    }
+  }
+};
 
 // Fills *pt for the parameter vector theta.  pl and theta are the block's
 // LDS copies (stage_plan, stage_theta, or values written by the calling

@@ -152,6 +152,10 @@ struct RecordSum {
 // addresses), with each lane's batch of B records added as a pairwise tree
 // (a dependent chain of log2 B additions instead of B - 1).  The order
 // depends only on count and NV.
+// the record that lanes past the last one read (no branch, no select)
+static __device__ const DD g_zero_record = {0.0, 0.0};
+typedef const double __attribute__((address_space(1))) gdouble;  // global memory
+
 template <int NV, int BLOCK, int B_ = 8>
 struct RecordSumT {
   static constexpr int S0 = pow2_floor<(BLOCK / NV > 0 ? BLOCK / NV : 1)>();
@@ -163,10 +167,17 @@ struct RecordSumT {
   __device__ void load(const DD* src, int64_t count, int64_t r0) {
     const int t = threadIdx.x;
     const int j = t / S, k = t % S;
+    // every lane loads: lanes past the records read a zero record, so that
+    // neither a branch nor a select after the load keeps these loads from
+    // the waits that follow (a select would wait for its load at once)
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int64_t r = r0 + k + (int64_t)b * S;
-      buf[b] = (j < NV && r < count) ? src[(int64_t)j * count + r] : DD{0.0, 0.0};
+      const bool in = j < NV && r < count;
+      // (both pointers as global memory: a generic pointer would make
+      // these flat loads, which the LDS waits would then count too)
+      const gdouble* p = in ? (const gdouble*)(src + (int64_t)j * count + r) : (const gdouble*)&g_zero_record;
+      buf[b] = DD{p[0], p[1]};
     }
   }
   __device__ DD tree() {
