@@ -1072,24 +1072,33 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   __shared__ double s_theta[kMaxParams];
   __shared__ double s_nll;
   __shared__ int s_st;
-  const int s = blockIdx.x;
-  if (s >= a.n_sets) return;
+  const int s = blockIdx.x;  // the grid is exactly one block per set
   const int P = pl.n_param;
   const int t = threadIdx.x;
-  // every independent load at once: plan, constants, parameters, fit
-  // state, offsets and the first batch of partial records
-  stage_plan<kBlock>(pl, &spl);
+  // every independent load at once, before the first LDS copy is written:
+  // plan, constants, parameters, fit state, the set's item range and
+  // events, then its first batch of item records (each copy then waits for
+  // its own loads only)
+  PlanRegs<kBlock> plr;
+  plr.load(pl);
   PtRegs<M, kBlock> ptv;
   ptv.load(&a.consts[s], P);
-  stage_theta(FIT ? a.gd.th_prop + (size_t)s * P : a.theta + (size_t)s * P, P, s_theta);
   GDPre pre{};
-  if constexpr (FIT) pre = gd_preload(a.gd, s, P);
+  double thv;
+  if constexpr (FIT) {
+    pre = gd_preload(a.gd, s, P);
+    thv = pre.prop;
+  } else {
+    thv = a.theta[(size_t)s * P + (t < P ? t : 0)];  // read by every lane, kept by t < P
+  }
   const int64_t first = a.tile_off[s], n_items = a.tile_off[s + 1] - first;
   const int flag = a.set_flag[s];
   const int64_t o0 = a.offsets[s], o1 = a.offsets[s + 1];
   const DD* recs = reinterpret_cast<const DD*>(a.partials) + (size_t)first * NV;
   RecordSum<NV, kBlock> rs;
   rs.issue(recs, n_items);
+  plr.store(&spl);
+  if (t < P) s_theta[t] = thv;
   ptv.store(&spt, P);
   rs.reduce(recs, n_items, tot);  // ends with a barrier
   const int64_t n_s = flag ? 0 : o1 - o0;

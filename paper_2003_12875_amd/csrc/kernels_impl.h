@@ -154,11 +154,12 @@ struct Launch {
   }
   static hipError_t sets(const VariantOps&, const Plan& pl, const SetsArgs& a, bool grad, bool fit, int unroll, int grid, int lds_cap,
                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    if (a.n_sets <= 0) return hipSuccess;  // the finishing kernel's grid is one block per set
     if (grad || fit) sets_u<true>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
     else sets_u<false>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 fg(a.n_sets > 0 ? a.n_sets : 1);
+    const dim3 fg(a.n_sets);
     if (fit) hipLaunchKernelGGL((k_sets_finish<M, true, true>), fg, dim3(kBlock), 0, st, pl, a);
     else if (grad) hipLaunchKernelGGL((k_sets_finish<M, true, false>), fg, dim3(kBlock), 0, st, pl, a);
     else hipLaunchKernelGGL((k_sets_finish<M, false, false>), fg, dim3(kBlock), 0, st, pl, a);

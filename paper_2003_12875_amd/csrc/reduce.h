@@ -96,6 +96,19 @@ __device__ inline void block_sum_vals(const double (&v)[NV], double* buf, DD* ou
   __syncthreads();
 }
 
+// A record for a lane that may have none: lanes with `in` false read a
+// zero record instead, so that every lane issues the load with neither a
+// branch nor a select after it (a select would wait for the load at once,
+// and a branch hides it from the waits that follow).  Both pointers are
+// taken as global memory: a generic pointer would make this a flat load,
+// which the LDS waits would then count too.
+static __device__ const DD g_zero_record = {0.0, 0.0};
+typedef const double __attribute__((address_space(1))) gdouble;
+__device__ __forceinline__ DD load_record(const DD* src, int64_t i, bool in) {
+  const gdouble* p = in ? (const gdouble*)(src + i) : (const gdouble*)&g_zero_record;
+  return DD{p[0], p[1]};
+}
+
 // Fixed-order sum of `count` records of NV double-double values (record r
 // at src[r * NV], written by an earlier kernel) by one block of BLOCK
 // threads, in two phases so that callers can issue their other loads
@@ -122,7 +135,7 @@ struct RecordSum {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int64_t r = k + (int64_t)b * S;
-      buf[b] = (j < NV && r < count) ? src[r * NV + j] : DD{0.0, 0.0};
+      buf[b] = load_record(src, r * NV + j, j < NV && r < count);
     }
   }
 
@@ -136,7 +149,7 @@ struct RecordSum {
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int64_t r = r0 + (int64_t)b * S;
-        buf[b] = (j < NV && r < count) ? src[r * NV + j] : DD{0.0, 0.0};
+        buf[b] = load_record(src, r * NV + j, j < NV && r < count);
       }
 #pragma unroll
       for (int b = 0; b < B; ++b) acc = dd_add(acc, buf[b]);
@@ -152,10 +165,6 @@ struct RecordSum {
 // addresses), with each lane's batch of B records added as a pairwise tree
 // (a dependent chain of log2 B additions instead of B - 1).  The order
 // depends only on count and NV.
-// the record that lanes past the last one read (no branch, no select)
-static __device__ const DD g_zero_record = {0.0, 0.0};
-typedef const double __attribute__((address_space(1))) gdouble;  // global memory
-
 template <int NV, int BLOCK, int B_ = 8>
 struct RecordSumT {
   static constexpr int S0 = pow2_floor<(BLOCK / NV > 0 ? BLOCK / NV : 1)>();
@@ -167,17 +176,10 @@ struct RecordSumT {
   __device__ void load(const DD* src, int64_t count, int64_t r0) {
     const int t = threadIdx.x;
     const int j = t / S, k = t % S;
-    // every lane loads: lanes past the records read a zero record, so that
-    // neither a branch nor a select after the load keeps these loads from
-    // the waits that follow (a select would wait for its load at once)
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int64_t r = r0 + k + (int64_t)b * S;
-      const bool in = j < NV && r < count;
-      // (both pointers as global memory: a generic pointer would make
-      // these flat loads, which the LDS waits would then count too)
-      const gdouble* p = in ? (const gdouble*)(src + (int64_t)j * count + r) : (const gdouble*)&g_zero_record;
-      buf[b] = DD{p[0], p[1]};
+      buf[b] = load_record(src, (int64_t)j * count + r, j < NV && r < count);
     }
   }
   __device__ DD tree() {

@@ -132,6 +132,7 @@ hipError_t op_consts(const VariantOps& self, const Plan& pl, const double* theta
 
 hipError_t op_sets(const VariantOps& self, const Plan& pl, const SetsArgs& a, bool grad, bool fit, int unroll,
                    int grid, int lds_cap, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (a.n_sets <= 0) return hipSuccess;  // the finishing kernel's grid is one block per set
   const RtcModule& r = R(self);
   hipFunction_t f = r.f[kSets + 2 * ((grad || fit) ? 1 : 0) + u_index(unroll)];
   const WorkItem* items = a.items;
@@ -142,7 +143,7 @@ hipError_t op_sets(const VariantOps& self, const Plan& pl, const SetsArgs& a, bo
   void* args[] = {const_cast<Plan*>(&pl), const_cast<SetsArgs*>(&a)};
   if (e != hipSuccess) return e;
   hipFunction_t fin = r.f[kSetsFinish + (fit ? 0 : grad ? 1 : 2)];
-  return launch(fin, a.n_sets > 0 ? a.n_sets : 1, kBlock, 0, st, args);
+  return launch(fin, a.n_sets, kBlock, 0, st, args);
 }
 
 hipError_t op_fit_init(const VariantOps& self, const Plan& pl, const double* theta, int n_sets, double eta,
