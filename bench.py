@@ -771,6 +771,27 @@ def extras(torch, nllmi, datagen, args, parity):
                                                "status": mh.sync()}
     del mh
     torch.cuda.empty_cache()
+    # the smooth interpolation codes (every normsys and histosys), 12
+    # histosys at 2e6 bins: both delta templates of every histosys are read,
+    # 8 (1 + 4 + 2 x 12) bytes per bin
+    w = datagen.hf_workload(n_histosys=12, n_points=1)
+    spec = w["spec"]
+    for md in spec["modifiers"]:
+        if md["type"] in ("normsys", "histosys"):
+            md["interp"] = "poly6"
+    mh = nllmi.HFModel(spec)
+    mh.set_data(w["counts"], w["nominal"], w["up"], w["down"])
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    g = torch.empty(mh.n_param, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: mh.eval_grad(th, out=out, grad=g), 20)
+    nbytes = 8.0 * (1 + mh.n_samples + 2 * mh.n_histosys) * mh.n_bins
+    ex["histfactory_smooth_2e6_bins"] = {"n_bins": mh.n_bins, "samples": mh.n_samples, "histosys": mh.n_histosys,
+                                         "params": mh.n_param, "eval_grad_ms": tg, "bytes_per_eval": nbytes,
+                                         "achieved_GBs": nbytes / (tg * 1e-3) / 1e9,
+                                         "hbm_frac": nbytes / (tg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                         "status": mh.sync()}
+    del mh
+    torch.cuda.empty_cache()
     # just-in-time density: a Gaussian written as an expression string on the
     # 1-D Gaussian's range with 1e7 events, against the built-in Gaussian leaf
     # on the same events (compile time included once)
