@@ -433,6 +433,97 @@ def johnson_workload(n: int = 10_000_000, single: bool = False, n_points: int = 
             "points": parameter_points(spec, n_points, JOHNSON_SEED + 1), "seed": JOHNSON_SEED}
 
 
+JIT_COMPOSITE_SEED = MASTER_SEED + 11000
+
+# formula densities used as leaves of composite models (C syntax; x and p[k])
+BREIT_WIGNER = "1.0/((x-p[0])*(x-p[0]) + 0.25*p[1]*p[1])"
+GAUSS_FORMULA = "exp(-0.5*((x-p[0])/p[1])*((x-p[0])/p[1]))"
+QUADRATIC = "1.0 + p[0]*x + p[1]*x*x"
+POWER_EXP = "pow(x, p[0])*exp(p[1]*x)"
+
+
+def jit_composite_spec(kind: str) -> dict:
+    """Composite models with formula leaves ("jit" nodes), for one or two
+    observables; the events of each come from a built-in model of similar
+    shape (jit_composite_workload), which parity does not need to match.
+      "bw_exp":     f BW(x; m, G) + (1 - f) Exp(x; c) on [0, 10]
+      "three":      f1 formula-Gauss(x; mu1, s1) + f2 Gauss(x; mu2, s2)
+                    + (1 - f1 - f2) quadratic(x; a, b) on [0, 10]
+      "two_jit":    yields nu1 BW(x; m, G) + nu2 power-exp(x; k, c) on [0.5, 10]
+      "prod":       power-exp(x; k, c) x Gauss(y; mu, s), x in [0.5, 10], y in [-5, 5]
+      "narrow":     f formula-Gauss(x; mu, 0.02-wide) + (1 - f) Exp(x; c) on [0, 10]
+    """
+    x = {"name": "x", "lo": 0.0, "hi": 10.0}
+    if kind == "bw_exp":
+        return {"obs": [x],
+                "params": [param("f", 0.3, 0.0, 1.0, jitter=0.05), param("m", 5.0, 0.0, 10.0, jitter=0.1),
+                           param("G", 0.8, 0.01, 5.0, jitter=0.1), param("c", -0.7, -5.0, 5.0, jitter=0.1)],
+                "nodes": [{"kind": "jit", "obs": 0, "params": [1, 2], "density": BREIT_WIGNER},
+                          {"kind": "exp", "obs": 0, "params": [3], "norm": "analytic"},
+                          {"kind": "sum", "params": [0], "children": [0, 1]}],
+                "root": 2}
+    if kind == "three":
+        return {"obs": [x],
+                "params": [param("f1", 0.3, 0.0, 1.0, jitter=0.05), param("f2", 0.2, 0.0, 1.0, jitter=0.05),
+                           param("mu1", 3.0, 0.0, 10.0, jitter=0.1), param("s1", 0.6, 0.01, 5.0, jitter=0.05),
+                           param("mu2", 7.0, 0.0, 10.0, jitter=0.1), param("s2", 0.4, 0.01, 5.0, jitter=0.05),
+                           param("a", 0.05, -0.09, 1.0, jitter=0.02), param("b", 0.01, 0.0, 1.0, jitter=0.005)],
+                "nodes": [{"kind": "jit", "obs": 0, "params": [2, 3], "density": GAUSS_FORMULA},
+                          {"kind": "gauss", "obs": 0, "params": [4, 5], "norm": "analytic"},
+                          {"kind": "jit", "obs": 0, "params": [6, 7], "density": QUADRATIC},
+                          {"kind": "sum", "params": [0, 1], "children": [0, 1, 2]}],
+                "root": 3}
+    if kind == "two_jit":
+        return {"obs": [{"name": "x", "lo": 0.5, "hi": 10.0}],
+                "params": [param("nu1", 3000.0, 0.0, 1e6, jitter=300.0), param("nu2", 7000.0, 0.0, 1e6, jitter=500.0),
+                           param("m", 5.0, 0.5, 10.0, jitter=0.1), param("G", 0.8, 0.01, 5.0, jitter=0.1),
+                           param("k", 1.5, 0.0, 5.0, jitter=0.1), param("c", -0.7, -5.0, 5.0, jitter=0.1)],
+                "nodes": [{"kind": "jit", "obs": 0, "params": [2, 3], "density": BREIT_WIGNER},
+                          {"kind": "jit", "obs": 0, "params": [4, 5], "density": POWER_EXP},
+                          {"kind": "sum", "params": [0, 1], "children": [0, 1]}],
+                "root": 2}
+    if kind == "prod":
+        return {"obs": [{"name": "x", "lo": 0.5, "hi": 10.0}, {"name": "y", "lo": -5.0, "hi": 5.0}],
+                "params": [param("k", 1.5, 0.0, 5.0, jitter=0.1), param("c", -0.7, -5.0, 5.0, jitter=0.1),
+                           param("mu", 0.2, -5.0, 5.0, jitter=0.1), param("s", 1.2, 0.05, 5.0, jitter=0.1)],
+                "nodes": [{"kind": "jit", "obs": 0, "params": [0, 1], "density": POWER_EXP},
+                          {"kind": "gauss", "obs": 1, "params": [2, 3], "norm": "analytic"},
+                          {"kind": "prod", "children": [0, 1]}],
+                "root": 2}
+    if kind == "narrow":
+        return {"obs": [x],
+                "params": [param("f", 0.2, 0.0, 1.0, jitter=0.03), param("mu", 5.0, 0.0, 10.0, jitter=0.005),
+                           param("s", 0.02, 0.001, 5.0, jitter=0.002), param("c", -0.7, -5.0, 5.0, jitter=0.1)],
+                "nodes": [{"kind": "jit", "obs": 0, "params": [1, 2], "density": GAUSS_FORMULA},
+                          {"kind": "exp", "obs": 0, "params": [3], "norm": "analytic"},
+                          {"kind": "sum", "params": [0], "children": [0, 1]}],
+                "root": 2}
+    raise ValueError(kind)
+
+
+def jit_composite_workload(kind: str, n: int = 100_000, n_points: int = 3, threads: int | None = None) -> dict:
+    """The model jit_composite_spec(kind), n events from a built-in model of
+    similar shape (a Gaussian peak over an exponential, or a product of two
+    Gaussians), and seeded parameter points around the spec values."""
+    spec = jit_composite_spec(kind)
+    seed = JIT_COMPOSITE_SEED + {"bw_exp": 0, "three": 1, "two_jit": 2, "prod": 3, "narrow": 4}[kind]
+    if kind == "prod":
+        src = {"obs": spec["obs"],
+               "params": [param("a", 4.0, 0.5, 10.0), param("b", 2.0, 0.1, 10.0), param("mu", 0.2, -5, 5),
+                          param("s", 1.2, 0.05, 5.0)],
+               "nodes": [{"kind": "gauss", "obs": 0, "params": [0, 1], "norm": "analytic"},
+                         {"kind": "gauss", "obs": 1, "params": [2, 3], "norm": "analytic"},
+                         {"kind": "prod", "children": [0, 1]}],
+               "root": 2}
+    else:
+        lo, hi = spec["obs"][0]["lo"], spec["obs"][0]["hi"]
+        mu, sig = (5.0, 0.02) if kind == "narrow" else (5.0, 0.6)
+        src = mixture_spec(f=0.3, mu=mu, sigma=sig, c=-0.3, lo=lo, hi=hi)
+    cols = generate(src, n, seed, threads=threads)
+    return {"spec": spec, "cols": cols, "n": n, "theta": theta_of(spec),
+            "points": parameter_points(spec, n_points, seed + 1), "seed": seed}
+
+
 def hypatia_spec(f=0.4, lo=5.20, hi=5.35):
     """f * Hypatia2(m; 5.28, 0.003, -2, 0.5, 0, 2, 3, 2.5, 4) + (1 - f) *
     Exp(m; -1.5) on m in [5.20, 5.35]: a B-mass-like peak with power-law

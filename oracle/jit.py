@@ -53,7 +53,10 @@ def g_and_grad(expr: str, x, p):
 
 def norm(expr: str, lo: float, hi: float, p):
     """Z and dZ/dp_k by adaptive quadrature (asked for 2e-14 relative: quad
-    reports that rounding limits it there, which is the intent)."""
+    reports that rounding limits it there, which is the intent), started
+    from 64 equal subintervals: one rule over the whole range can miss a
+    peak narrow against it (the derivative integrands vanish at a symmetric
+    peak's centre, where that rule's middle node falls)."""
     with warnings.catch_warnings():
         warnings.simplefilter("ignore", integrate.IntegrationWarning)
         return _norm(expr, lo, hi, p)
@@ -62,14 +65,15 @@ def norm(expr: str, lo: float, hi: float, p):
 def _norm(expr: str, lo: float, hi: float, p):
     p = np.asarray(p, dtype=np.float64)
     f = lambda t: float(np.real(g(expr, np.array([t]), p.astype(np.complex128)))[0])
-    Z = integrate.quad(f, lo, hi, epsabs=0, epsrel=2e-14, limit=400)[0]
+    pts = np.linspace(lo, hi, 65)[1:-1]
+    Z = integrate.quad(f, lo, hi, epsabs=0, epsrel=2e-14, limit=4000, points=pts)[0]
     dZ = []
     for k in range(len(p)):
         def fk(t, k=k):
             pc = p.astype(np.complex128)
             pc[k] += 1j * H
             return float(np.imag(g(expr, np.array([t]), pc))[0]) / H
-        dZ.append(integrate.quad(fk, lo, hi, epsabs=0, epsrel=2e-14, limit=400)[0])
+        dZ.append(integrate.quad(fk, lo, hi, epsabs=0, epsrel=2e-14, limit=4000, points=pts)[0])
     return Z, np.array(dZ)
 
 

@@ -62,3 +62,19 @@ def test_status_conventions():
     x = np.array([0.5, 1.0])
     assert jit.nll(GAUSS, -10, 10, [-5, 0.1], [5, 5], x, [0.0, 6.0])[0] == jit.E_PARAM
     assert jit.nll("x - p[0]", 0, 2, [-5], [5], x, [0.7])[0] == jit.E_PDF  # negative at x = 0.5
+
+
+@pytest.mark.parametrize("sigma", [0.02, 0.005])
+def test_narrow_peak_matches_builtin(sigma):
+    """A Gaussian 1/500 to 1/2000 of the range wide: the normalisation and
+    its derivatives (which vanish at the peak's centre) against the C++
+    oracle's closed form."""
+    spec = datagen.gauss_spec(5.0, sigma, 0.0, 10.0)
+    spec["params"][1]["lo"] = 1e-4
+    x = datagen.generate(spec, 3000, seed=5)[0]
+    for th in ([5.0, sigma], [5.0 + 0.3 * sigma, 1.1 * sigma]):
+        st, v, g = jit.nll(GAUSS, 0.0, 10.0, [0.0, 1e-4], [10.0, 5.0], x, th)
+        st2, v2, g2 = oracle.Oracle(spec).nll([x], np.array(th))
+        assert st == 0 and st2 == 0
+        assert abs(v - v2) <= 1e-12 * abs(v2), (v, v2)
+        assert np.max(np.abs(g - g2)) <= 1e-8 * np.max(np.abs(g2)), (g, g2)
