@@ -99,6 +99,25 @@ typedef enum nll_status {
  *              only (else NLL_ERR_UNSUPPORTED); K_nu is tabulated per
  *              parameter point on the core's range, which takes
  *              |lambda| <= 6 and 1e-3 <= alpha r <= 700 over it
+ *   NLL_JIT    (p[0] .. p[n-1]), 1 <= n <= 8: a density given as a formula
+ *              string (Sec. 4: PDFs written as expressions and compiled at
+ *              run time), `density` below, a C expression in x and p[k]
+ *              (double arithmetic; + - * /, exp log sqrt pow sin cos tan
+ *              atan tanh sinh cosh asinh erf fabs), p[k] the node's k-th
+ *              parameter, k a literal index < n.  Normalised numerically
+ *              whatever `norm` says: composite 256-point Gauss-Legendre on
+ *              1, 2, 4, ... 256 equal panels of the range until two levels
+ *              agree (to 1e-13 of the integral of |g|, 1e-11 of those of
+ *              |dg/dp_k|); no agreement, or Z <= 0 or not finite, is an
+ *              invalid density (NLL_ERR_INVALID_PDF through nll_sync), as
+ *              is an event where g < 0 or is not finite (g = 0 is a term
+ *              that contributes nothing).  Gradient by forward-mode dual
+ *              numbers in the same pass.  Any graph position, any number
+ *              of such leaves; FP64 only (else NLL_ERR_UNSUPPORTED).  A
+ *              model with one is compiled at creation (run-time
+ *              compilation, as any shape outside the compiled set); the
+ *              expression is compiled as given: it must come from a
+ *              trusted source, as any code the process runs
  * Composite nodes:
  *   NLL_SUM    over k >= 2 children on the same observables, either
  *              fractions (f_1 .. f_{k-1}): p = sum_{j<k} f_j p_j +
@@ -109,7 +128,7 @@ typedef enum nll_status {
  *   NLL_PROD   no params; children on disjoint observables: p = prod p_d   */
 enum nll_node_kind {
   NLL_GAUSS = 1, NLL_EXP = 2, NLL_CHEB = 3, NLL_CB = 4, NLL_ARGUS = 5, NLL_SUM = 6, NLL_PROD = 7, NLL_JOHNSON = 8,
-  NLL_CHI2 = 9, NLL_HYPATIA = 10
+  NLL_CHI2 = 9, NLL_HYPATIA = 10, NLL_JIT = 11
 };
 
 /* Normalisation of a leaf over its observable range [lo, hi]:
@@ -142,6 +161,9 @@ typedef struct nll_node_desc {
   int32_t n_child;
   int32_t child[NLL_NODE_MAX_CHILDREN]; /* indices of EARLIER nodes          */
   int32_t norm;                         /* nll_norm_method (leaves)          */
+  const char* density;                  /* NLL_JIT: the formula (host string,
+                                           <= 4096 characters, read during
+                                           nll_create_model only); else NULL */
 } nll_node_desc;
 
 typedef struct nll_model_desc {
@@ -548,8 +570,10 @@ nll_status nll_hf_sync(nll_hf_model* model, int32_t* status_out);
  * at run time).  One observable x on [obs_lo, obs_hi] and a density
  * expression g(x; p[0] .. p[n_param-1]) in C syntax (double arithmetic;
  * + - * /, exp log sqrt pow sin cos tan atan tanh sinh cosh asinh erf fabs),
- * normalised over the range by 256-point Gauss-Legendre on one panel (the
- * expression should be smooth there):
+ * normalised over the range by composite 256-point Gauss-Legendre on 1, 2,
+ * 4, ... 256 equal panels until two levels agree (no agreement is an
+ * invalid density); the same expressions serve as NLL_JIT leaves of
+ * composite models (nll_node_desc):
  *   NLL = -sum_i log g(x_i) + N log Z,   Z = int g dx,
  * with the gradient from forward-mode dual numbers in the same pass.  An
  * event with g <= 0 or non-finite, or Z <= 0, gives +inf and

@@ -23,7 +23,7 @@ from ._native import (HF_MODIFIER, HFDesc, HFModifier, JitDesc, MAX_NODE_CHILDRE
                       STATUS, check, lib, LIB_PATH)
 
 KIND = {"gauss": 1, "exp": 2, "cheb": 3, "cb": 4, "argus": 5, "sum": 6, "prod": 7, "johnson": 8, "chi2": 9,
-        "hypatia": 10}
+        "hypatia": 10, "jit": 11}
 NORM = {"analytic": 0, "gl256": 1, "gl256_single": 2}
 PRECISION = {"fp64": 0, "fp32c": 1}
 
@@ -86,9 +86,11 @@ class Model:
 
             {"obs": [{"name", "lo", "hi"}...],
              "params": [{"name", "value", "lo", "hi", "free"}...],
-             "nodes": [{"kind": "gauss"|"exp"|"cheb"|"cb"|"argus"|"sum"|"prod",
+             "nodes": [{"kind": "gauss"|"exp"|"cheb"|"cb"|"argus"|"johnson"|"chi2"|
+                                "hypatia"|"jit"|"sum"|"prod",
                         "obs": int, "params": [...], "children": [...],
-                        "norm": "analytic"|"gl256"|"gl256_single"}...],
+                        "norm": "analytic"|"gl256"|"gl256_single",
+                        "density": str (jit: a formula in x and p[k])}...],
              "root": int, "extended": bool, "yield_param": int}
         """
         obs, params, nodes = spec["obs"], spec["params"], spec["nodes"]
@@ -99,6 +101,7 @@ class Model:
         phi = (ctypes.c_double * n_param)(*[float(p["hi"]) for p in params])
         pfree = (ctypes.c_uint8 * n_param)(*[1 if p.get("free", True) else 0 for p in params])
         nd = (NodeDesc * n_node)()
+        dens = []  # the formulas' bytes, alive until the model is created
         for i, n in enumerate(nodes):
             ps, cs = list(n.get("params", [])), list(n.get("children", []))
             if len(ps) > MAX_NODE_PARAMS or len(cs) > MAX_NODE_CHILDREN:
@@ -112,6 +115,9 @@ class Model:
             for j, v in enumerate(cs):
                 nd[i].child[j] = int(v)
             nd[i].norm = NORM[n.get("norm", "analytic")]
+            if n["kind"] == "jit":
+                dens.append(str(n["density"]).encode())
+                nd[i].density = dens[-1]
         d = ModelDesc()
         d.n_obs, d.obs_lo, d.obs_hi = n_obs, lo, hi
         d.n_param, d.param_lo, d.param_hi, d.param_free = n_param, plo, phi, pfree
@@ -119,7 +125,7 @@ class Model:
         d.precision = PRECISION[precision]
         d.extended = 1 if spec.get("extended", False) else 0
         d.yield_param = int(spec.get("yield_param", -1)) if spec.get("extended", False) else 0
-        return cls({"desc": d, "n_param": n_param, "n_obs": n_obs, "keep": (lo, hi, plo, phi, pfree, nd)},
+        return cls({"desc": d, "n_param": n_param, "n_obs": n_obs, "keep": (lo, hi, plo, phi, pfree, nd, dens)},
                    device)
 
     def close(self):

@@ -35,7 +35,8 @@ class NLLError(RuntimeError):
 class NodeDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("obs", ctypes.c_int32), ("n_param", ctypes.c_int32),
                 ("param", ctypes.c_int32 * MAX_NODE_PARAMS), ("n_child", ctypes.c_int32),
-                ("child", ctypes.c_int32 * MAX_NODE_CHILDREN), ("norm", ctypes.c_int32)]
+                ("child", ctypes.c_int32 * MAX_NODE_CHILDREN), ("norm", ctypes.c_int32),
+                ("density", ctypes.c_char_p)]
 
 
 class ModelDesc(ctypes.Structure):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -95,12 +96,40 @@ int expected_params(int kind, int np) {
     case NLL_JOHNSON: return 4;
     case NLL_CHI2: return 1;
     case NLL_HYPATIA: return 9;
+    case NLL_JIT: return (np >= 1 && np <= kJitMaxLeafParams) ? np : -1;
     default: return -1;
   }
 }
 
 bool is_leaf(int kind) {
-  return (kind >= NLL_GAUSS && kind <= NLL_ARGUS) || kind == NLL_JOHNSON || kind == NLL_CHI2 || kind == NLL_HYPATIA;
+  return (kind >= NLL_GAUSS && kind <= NLL_ARGUS) || kind == NLL_JOHNSON || kind == NLL_CHI2 || kind == NLL_HYPATIA ||
+         kind == NLL_JIT;
+}
+
+// A formula leaf's expression: present, at most 4096 characters, and every
+// parameter reference p[k] a literal index below the leaf's parameter count
+// (the expression is compiled as given; an index past the leaf's
+// parameters would read past them).
+nll_status check_density(const char* e, int np) {
+  if (!e) return NLL_ERR_ARG;
+  const size_t n = std::strlen(e);
+  if (n == 0) return NLL_ERR_ARG;
+  if (n > 4096) return NLL_ERR_UNSUPPORTED;
+  auto ident = [](char c) { return std::isalnum((unsigned char)c) || c == '_'; };
+  for (size_t i = 0; i + 1 < n; ++i) {
+    if (e[i] != 'p' || (i > 0 && ident(e[i - 1]))) continue;
+    size_t j = i + 1;
+    while (j < n && e[j] == ' ') ++j;
+    if (j >= n || e[j] != '[') continue;
+    ++j;
+    while (j < n && e[j] == ' ') ++j;
+    if (j >= n || !std::isdigit((unsigned char)e[j])) return NLL_ERR_ARG;
+    long k = 0;
+    while (j < n && std::isdigit((unsigned char)e[j]) && k < 1000) k = 10 * k + (e[j++] - '0');
+    while (j < n && e[j] == ' ') ++j;
+    if (j >= n || e[j] != ']' || k >= np) return NLL_ERR_ARG;
+  }
+  return NLL_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -146,6 +175,12 @@ struct Lowering {
         // Hypatia2: its per-point tables sit beside the constants, one set
         // per model, and the FP32-compensated pass has no form of it
         if (nd.kind == NLL_HYPATIA && (++n_hypatia > 1 || D.precision != NLL_FP64)) return NLL_ERR_UNSUPPORTED;
+        // a formula leaf: FP64 only (its expression has no FP32 form)
+        if (nd.kind == NLL_JIT) {
+          const nll_status ds = check_density(nd.density, nd.n_param);
+          if (ds != NLL_OK) return ds;
+          if (D.precision != NLL_FP64) return NLL_ERR_UNSUPPORTED;
+        }
         obs_mask[i] = 1u << nd.obs;
       } else if (nd.kind == NLL_SUM || nd.kind == NLL_PROD) {
         // a sum takes fractions f_1..f_{k-1} or yields nu_1..nu_k
@@ -258,9 +293,11 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
     if ((int)t.refs.size() > kMaxPathRefs) return NLL_ERR_UNSUPPORTED;
 
   std::vector<int> kind(L), obs(L), root(L), np(L);
+  std::vector<std::string> density(L);
   for (int l = 0; l < L; ++l) {
     const nll_node_desc& nd = D.nodes[lw.leaves[l]];
     kind[l] = nd.kind;
+    if (nd.kind == NLL_JIT) density[l] = nd.density;
     obs[l] = nd.obs;
     np[l] = nd.n_param;
     bool all = true;
@@ -305,6 +342,7 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
     shape.obs = obs;
     shape.root = root;
     shape.np = np;
+    shape.density = density;
     shape.K = K;
     shape.n_obs = D.n_obs;
     shape.precision = D.precision;
@@ -342,7 +380,7 @@ nll_status build_plan(const nll_model_desc& D, Plan& pl, const VariantOps** ops_
     pl.leaf_obs[s] = nd.obs;
     pl.leaf_np[s] = nd.n_param;
     for (int p = 0; p < nd.n_param; ++p) pl.leaf_param[s][p] = nd.param[p];
-    pl.leaf_norm[s] = nd.kind == NLL_HYPATIA ? kNormGL : nd.norm;  // no closed form
+    pl.leaf_norm[s] = (nd.kind == NLL_HYPATIA || nd.kind == NLL_JIT) ? kNormGL : nd.norm;  // no closed form
     pl.leaf_root[s] = root[l];
   }
   // Flat shapes: term k is the one whose only non-root leaf sits in the

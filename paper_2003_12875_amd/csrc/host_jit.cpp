@@ -126,6 +126,8 @@ nll_status nll_jit_create(const nll_jit_desc* d, nll_jit_model** out, char* log,
   for (int k = 0; k < d->n_param; ++k)
     if (!(d->param_lo[k] <= d->param_hi[k])) return NLL_ERR_ARG;
   std::string src = jit_source_template();
+  const size_t dual_at = src.find("@DUAL@");
+  if (dual_at != std::string::npos) src.replace(dual_at, 6, jit_dual_source());
   const std::string expr = d->density;
   for (size_t at = src.find("@EXPR@"); at != std::string::npos; at = src.find("@EXPR@", at + expr.size()))
     src.replace(at, 6, expr);

@@ -109,6 +109,7 @@ struct HypatiaLeaf {
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = true;       // per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised through gl_norm on its tables
   static constexpr int kSetupLanes = 1;
 
   __device__ static bool valid(const double* p) {

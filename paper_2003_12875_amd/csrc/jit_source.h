@@ -16,6 +16,56 @@
 
 namespace nllmi {
 
+// Forward-mode dual numbers over N parameters (value and d/dp_k through
+// every operation and elementary function), in the global namespace so
+// that the device library's functions of double stay visible beside
+// them.  Pasted into both the stand-alone density program and the
+// density leaves of composite models (leaves.h, JitLeaf).
+inline const char* jit_dual_source() {
+  return R"JIT(
+// forward-mode dual numbers
+template <int N> struct Dual { double v; double d[N]; };
+template <int N> __device__ inline Dual<N> dconst(double c) { Dual<N> r; r.v = c; for (int k = 0; k < N; ++k) r.d[k] = 0.0; return r; }
+template <int N> __device__ inline Dual<N> dscale(const Dual<N>& a, double v, double s) {
+  Dual<N> r; r.v = v; for (int k = 0; k < N; ++k) r.d[k] = s * a.d[k]; return r;
+}
+template <int N> __device__ inline Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v + b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+template <int N> __device__ inline Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v - b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+template <int N> __device__ inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v * b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+template <int N> __device__ inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v / b.v; const double ib = 1.0 / b.v; for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib; return r; }
+template <int N> __device__ inline Dual<N> operator-(const Dual<N>& a) { return dscale(a, -a.v, -1.0); }
+template <int N> __device__ inline Dual<N> operator+(const Dual<N>& a) { return a; }
+template <int N> __device__ inline Dual<N> operator+(const Dual<N>& a, double b) { Dual<N> r = a; r.v += b; return r; }
+template <int N> __device__ inline Dual<N> operator+(double a, const Dual<N>& b) { Dual<N> r = b; r.v += a; return r; }
+template <int N> __device__ inline Dual<N> operator-(const Dual<N>& a, double b) { Dual<N> r = a; r.v -= b; return r; }
+template <int N> __device__ inline Dual<N> operator-(double a, const Dual<N>& b) { return dscale(b, a - b.v, -1.0); }
+template <int N> __device__ inline Dual<N> operator*(const Dual<N>& a, double b) { return dscale(a, a.v * b, b); }
+template <int N> __device__ inline Dual<N> operator*(double a, const Dual<N>& b) { return dscale(b, a * b.v, a); }
+template <int N> __device__ inline Dual<N> operator/(const Dual<N>& a, double b) { return dscale(a, a.v / b, 1.0 / b); }
+template <int N> __device__ inline Dual<N> operator/(double a, const Dual<N>& b) { const double v = a / b.v; return dscale(b, v, -v / b.v); }
+template <int N> __device__ inline Dual<N> exp(const Dual<N>& a) { const double v = exp(a.v); return dscale(a, v, v); }
+template <int N> __device__ inline Dual<N> log(const Dual<N>& a) { return dscale(a, log(a.v), 1.0 / a.v); }
+template <int N> __device__ inline Dual<N> sqrt(const Dual<N>& a) { const double v = sqrt(a.v); return dscale(a, v, 0.5 / v); }
+template <int N> __device__ inline Dual<N> sin(const Dual<N>& a) { return dscale(a, sin(a.v), cos(a.v)); }
+template <int N> __device__ inline Dual<N> cos(const Dual<N>& a) { return dscale(a, cos(a.v), -sin(a.v)); }
+template <int N> __device__ inline Dual<N> tan(const Dual<N>& a) { const double v = tan(a.v); return dscale(a, v, 1.0 + v * v); }
+template <int N> __device__ inline Dual<N> atan(const Dual<N>& a) { return dscale(a, atan(a.v), 1.0 / (1.0 + a.v * a.v)); }
+template <int N> __device__ inline Dual<N> tanh(const Dual<N>& a) { const double v = tanh(a.v); return dscale(a, v, 1.0 - v * v); }
+template <int N> __device__ inline Dual<N> sinh(const Dual<N>& a) { return dscale(a, sinh(a.v), cosh(a.v)); }
+template <int N> __device__ inline Dual<N> cosh(const Dual<N>& a) { return dscale(a, cosh(a.v), sinh(a.v)); }
+template <int N> __device__ inline Dual<N> asinh(const Dual<N>& a) { return dscale(a, asinh(a.v), 1.0 / sqrt(1.0 + a.v * a.v)); }
+template <int N> __device__ inline Dual<N> erf(const Dual<N>& a) { return dscale(a, erf(a.v), 1.1283791670955126 * exp(-a.v * a.v)); }
+template <int N> __device__ inline Dual<N> fabs(const Dual<N>& a) { return dscale(a, fabs(a.v), a.v < 0.0 ? -1.0 : 1.0); }
+template <int N> __device__ inline Dual<N> pow(const Dual<N>& a, double b) { const double v = pow(a.v, b); return dscale(a, v, b * pow(a.v, b - 1.0)); }
+template <int N> __device__ inline Dual<N> pow(double a, const Dual<N>& b) { const double v = pow(a, b.v); return dscale(b, v, v * log(a)); }
+template <int N> __device__ inline Dual<N> pow(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = pow(a.v, b.v); const double la = log(a.v), ia = 1.0 / a.v;
+  for (int k = 0; k < N; ++k) r.d[k] = r.v * (b.d[k] * la + b.v * a.d[k] * ia);
+  return r;
+}
+)JIT";
+}
+
 inline const char* jit_source_template() {
   return R"JIT(
 typedef long long i64;
@@ -66,46 +116,7 @@ __device__ inline DD block_sum(DD v, DD* lds) {
   return r;
 }
 
-// forward-mode dual numbers
-template <int N> struct Dual { double v; double d[N]; };
-template <int N> __device__ inline Dual<N> dconst(double c) { Dual<N> r; r.v = c; for (int k = 0; k < N; ++k) r.d[k] = 0.0; return r; }
-template <int N> __device__ inline Dual<N> dscale(const Dual<N>& a, double v, double s) {
-  Dual<N> r; r.v = v; for (int k = 0; k < N; ++k) r.d[k] = s * a.d[k]; return r;
-}
-template <int N> __device__ inline Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v + b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
-template <int N> __device__ inline Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v - b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
-template <int N> __device__ inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v * b.v; for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
-template <int N> __device__ inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v / b.v; const double ib = 1.0 / b.v; for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib; return r; }
-template <int N> __device__ inline Dual<N> operator-(const Dual<N>& a) { return dscale(a, -a.v, -1.0); }
-template <int N> __device__ inline Dual<N> operator+(const Dual<N>& a) { return a; }
-template <int N> __device__ inline Dual<N> operator+(const Dual<N>& a, double b) { Dual<N> r = a; r.v += b; return r; }
-template <int N> __device__ inline Dual<N> operator+(double a, const Dual<N>& b) { Dual<N> r = b; r.v += a; return r; }
-template <int N> __device__ inline Dual<N> operator-(const Dual<N>& a, double b) { Dual<N> r = a; r.v -= b; return r; }
-template <int N> __device__ inline Dual<N> operator-(double a, const Dual<N>& b) { return dscale(b, a - b.v, -1.0); }
-template <int N> __device__ inline Dual<N> operator*(const Dual<N>& a, double b) { return dscale(a, a.v * b, b); }
-template <int N> __device__ inline Dual<N> operator*(double a, const Dual<N>& b) { return dscale(b, a * b.v, a); }
-template <int N> __device__ inline Dual<N> operator/(const Dual<N>& a, double b) { return dscale(a, a.v / b, 1.0 / b); }
-template <int N> __device__ inline Dual<N> operator/(double a, const Dual<N>& b) { const double v = a / b.v; return dscale(b, v, -v / b.v); }
-template <int N> __device__ inline Dual<N> exp(const Dual<N>& a) { const double v = exp(a.v); return dscale(a, v, v); }
-template <int N> __device__ inline Dual<N> log(const Dual<N>& a) { return dscale(a, log(a.v), 1.0 / a.v); }
-template <int N> __device__ inline Dual<N> sqrt(const Dual<N>& a) { const double v = sqrt(a.v); return dscale(a, v, 0.5 / v); }
-template <int N> __device__ inline Dual<N> sin(const Dual<N>& a) { return dscale(a, sin(a.v), cos(a.v)); }
-template <int N> __device__ inline Dual<N> cos(const Dual<N>& a) { return dscale(a, cos(a.v), -sin(a.v)); }
-template <int N> __device__ inline Dual<N> tan(const Dual<N>& a) { const double v = tan(a.v); return dscale(a, v, 1.0 + v * v); }
-template <int N> __device__ inline Dual<N> atan(const Dual<N>& a) { return dscale(a, atan(a.v), 1.0 / (1.0 + a.v * a.v)); }
-template <int N> __device__ inline Dual<N> tanh(const Dual<N>& a) { const double v = tanh(a.v); return dscale(a, v, 1.0 - v * v); }
-template <int N> __device__ inline Dual<N> sinh(const Dual<N>& a) { return dscale(a, sinh(a.v), cosh(a.v)); }
-template <int N> __device__ inline Dual<N> cosh(const Dual<N>& a) { return dscale(a, cosh(a.v), sinh(a.v)); }
-template <int N> __device__ inline Dual<N> asinh(const Dual<N>& a) { return dscale(a, asinh(a.v), 1.0 / sqrt(1.0 + a.v * a.v)); }
-template <int N> __device__ inline Dual<N> erf(const Dual<N>& a) { return dscale(a, erf(a.v), 1.1283791670955126 * exp(-a.v * a.v)); }
-template <int N> __device__ inline Dual<N> fabs(const Dual<N>& a) { return dscale(a, fabs(a.v), a.v < 0.0 ? -1.0 : 1.0); }
-template <int N> __device__ inline Dual<N> pow(const Dual<N>& a, double b) { const double v = pow(a.v, b); return dscale(a, v, b * pow(a.v, b - 1.0)); }
-template <int N> __device__ inline Dual<N> pow(double a, const Dual<N>& b) { const double v = pow(a, b.v); return dscale(b, v, v * log(a)); }
-template <int N> __device__ inline Dual<N> pow(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r; r.v = pow(a.v, b.v); const double la = log(a.v), ia = 1.0 / a.v;
-  for (int k = 0; k < N; ++k) r.d[k] = r.v * (b.d[k] * la + b.v * a.d[k] * ia);
-  return r;
-}
+@DUAL@
 
 // Sum of log g over a thread's events as one logarithm: the running
 // product of the g, renormalised to a mantissa in [1/2, 1) and an exponent

@@ -74,8 +74,8 @@ __device__ __forceinline__ void finish_block(const Plan& pl, const PerTheta& pt,
   }
   int status = 0;
   if (flagged) status = -1;                                                 // malformed offsets
-  else if (pt.bad) status = -3;                                             // parameter range
-  else if (bad_events > 0 || !__builtin_isfinite(nll)) status = -5;         // invalid density
+  else if (pt.bad & 1) status = -3;                                         // parameter range
+  else if (pt.bad || bad_events > 0 || !__builtin_isfinite(nll)) status = -5;  // invalid density
   if (status != 0) nll = __builtin_inf();
   if (threadIdx.x == 0) {
     *s_nll = nll;

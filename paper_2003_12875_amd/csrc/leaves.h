@@ -74,6 +74,7 @@ struct GaussLeaf {
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = false;       // no per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised by the shared rules (closed form or one GL rule)
   struct C {
     double is, b;
   };
@@ -171,6 +172,7 @@ struct ExpLeaf {
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = false;       // no per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised by the shared rules (closed form or one GL rule)
   struct C {
     double c;
   };
@@ -268,6 +270,7 @@ struct ChebLeaf {
   static constexpr bool kLinear = true;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = false;       // no per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised by the shared rules (closed form or one GL rule)
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double sx, ox, a[K];
@@ -397,6 +400,7 @@ struct CBLeaf {
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = false;       // no per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised by the shared rules (closed form or one GL rule)
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double is, b, na, logA, B, n, Ka, Kb, Kc, nOverA;
@@ -616,6 +620,7 @@ struct ArgusLeaf {
   static constexpr bool kLinear = true;
   static constexpr bool kEventLog = false;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = false;       // no per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised by the shared rules (closed form or one GL rule)
   static constexpr int kSetupLanes = 1;  // setup() on one lane
   struct C {
     double m0, im02, c, dm0;  // dm0: 2/m0^3, or 0 when m0 is not differentiated
@@ -729,6 +734,7 @@ struct JohnsonLeaf {
   static constexpr bool kLinear = true;
   static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = false;       // no per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised by the shared rules (closed form or one GL rule)
   struct C {
     double mu, il, ga, de;
   };
@@ -916,6 +922,7 @@ struct Chi2Leaf {
   static constexpr bool kLinear = false;
   static constexpr bool kEventLog = true;  // a logarithm per event (FP64 pass)
   static constexpr bool kAux = false;       // no per-point tables beside PerTheta
+  static constexpr bool kOwnNorm = false;   // normalised by the shared rules (closed form or one GL rule)
   struct C {
     double km1;  // nu/2 - 1
   };
@@ -996,3 +1003,4 @@ static_assert(11 <= kLeafConsts && 2 + 8 <= kLeafConsts, "leaf constants");
 }  // namespace nllmi
 
 #include "hypatia.h"
+#include "jit_leaf.h"

@@ -33,7 +33,11 @@ constexpr int kBlock = 256;         // threads per block (4 wave64)
 constexpr int kFinishBlock = 1024;  // threads of the single-dataset finishing kernel
 constexpr int kMaxAcc = 1 + kMaxTerms + kMaxLeaves * kMaxLeafParams;
 
-enum LeafKind : int32_t { kGauss = 1, kExp = 2, kCheb = 3, kCB = 4, kArgus = 5, kJohnson = 8, kChi2 = 9, kHypatia = 10 };
+enum LeafKind : int32_t {
+  kGauss = 1, kExp = 2, kCheb = 3, kCB = 4, kArgus = 5, kJohnson = 8, kChi2 = 9, kHypatia = 10, kJit = 11
+};
+constexpr int kJitMaxLeafParams = 8;  // parameters of a formula leaf (forward-mode duals)
+constexpr int kJitMaxPanels = 256;    // panels of its composite Gauss-Legendre normalisation
 
 // Hypatia2 per-point tables (at most one such leaf per model; kept beside
 // PerTheta, in LDS or in a per-set device array): Chebyshev interpolants of
@@ -95,7 +99,7 @@ struct PerTheta {
   double croot;                           // - sum log Z over root leaves
   double dlogw[kMaxTerms][kMaxParams];    // d log w_k / d theta (fraction params)
   double phioff[kMaxLeaves][kMaxLeafParams];  // FP32 pass: feature offsets (else 0)
-  int32_t bad;                            // parameter outside its allowed range
+  int32_t bad;  // bit 0: a parameter outside its range or a leaf's domain; bit 1: a formula leaf's normalisation not positive and finite
   int32_t pad;
 };
 

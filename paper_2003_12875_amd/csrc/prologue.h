@@ -303,23 +303,58 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
 #pragma unroll
         for (int j = 0; j < Leaf::NP; ++j) p[j] = theta[pl.leaf_param[l][j]];
         const double lo = pl.lo[pl.leaf_obs[l]], hi = pl.hi[pl.leaf_obs[l]];
-        const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
-        double v[Leaf::NP + 1];
-        if (ok && tid < kGLNodes) {
-          if constexpr (Leaf::kAux) {
-            Leaf::gl_norm(aux, lo, hi, glx, glw, v);
-          } else {
-            gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
+        if constexpr (Leaf::kOwnNorm) {
+          // composite rule on 1, 2, 4, ... panels until two successive
+          // levels agree to 1e-13 of the integral of |g| and 1e-11 of those
+          // of |dg/dp_k| (a level that resolves the density is exact to
+          // rounding, so agreement means the finer one is); no agreement
+          // within kJitMaxPanels panels leaves Z = NaN, an invalid density
+          constexpr int NV = Leaf::NP + 1;
+          double zp[NV], zc[NV], ab[NV];
+          auto level = [&](int n_pan, double (&z)[NV]) {
+            if (tid < kGLNodes) {
+              Leaf::norm_level(p, lo, hi, n_pan, glx, glw, tid, z, ab);
+            } else {
+#pragma unroll
+              for (int j = 0; j < NV; ++j) z[j] = ab[j] = 0.0;
+            }
+            block_sum_small<NV>(z, lds);
+            block_sum_small<NV>(ab, lds);
+          };
+          level(1, zp);
+          bool conv = false;
+          for (int n_pan = 2; n_pan <= kJitMaxPanels && !conv; n_pan *= 2) {
+            level(n_pan, zc);
+            conv = __builtin_isfinite(zc[0]) && fabs(zc[0] - zp[0]) <= 1e-13 * ab[0];
+#pragma unroll
+            for (int j = 1; j < NV; ++j) conv = conv && fabs(zc[j] - zp[j]) <= 1e-11 * ab[j];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) zp[j] = zc[j];
+          }
+          if (tid == 0) {
+            pt->logz[l] = conv ? zp[0] : __builtin_nan("");  // Z for now
+#pragma unroll
+            for (int j = 0; j < Leaf::NP; ++j) pt->dlogz[l][j] = zp[j + 1];  // dZ for now
           }
         } else {
+          const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
+          double v[Leaf::NP + 1];
+          if (ok && tid < kGLNodes) {
+            if constexpr (Leaf::kAux) {
+              Leaf::gl_norm(aux, lo, hi, glx, glw, v);
+            } else {
+              gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
+            }
+          } else {
 #pragma unroll
-          for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
-        }
-        block_sum_small<Leaf::NP + 1>(v, lds);
-        if (tid == 0) {
-          pt->logz[l] = v[0];  // Z for now
+            for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
+          }
+          block_sum_small<Leaf::NP + 1>(v, lds);
+          if (tid == 0) {
+            pt->logz[l] = v[0];  // Z for now
 #pragma unroll
-          for (int j = 0; j < Leaf::NP; ++j) pt->dlogz[l][j] = v[j + 1];  // dZ for now
+            for (int j = 0; j < Leaf::NP; ++j) pt->dlogz[l][j] = v[j + 1];  // dZ for now
+          }
         }
       }
     });
@@ -368,7 +403,10 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
         if constexpr (Leaf::kKind == kArgus) {
           if (!pl.par_free[pl.leaf_param[l][0]]) s.ec[3] = 0.0;  // m0 not differentiated
         }
-        if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) atomicOr(&s_bad, 1);
+        // a parameter outside a leaf's domain: bit 0; a formula leaf whose
+        // normalisation is not positive and finite (or did not converge):
+        // bit 1, an invalid density rather than an invalid parameter
+        if (!ok || !(s.Z > 0.0) || !__builtin_isfinite(s.Z)) atomicOr(&s_bad, Leaf::kOwnNorm ? 2 : 1);
         for (int j = 0; j < kLeafConsts; ++j) pt->ec[l][j] = s.ec[j];
         const double iz = 1.0 / s.Z;
         // the FP32 pass evaluates the leaf on x - x0: its log-density is off

@@ -26,6 +26,7 @@
 #include <string>
 #include <vector>
 
+#include "jit_source.h"
 #include "rtc.h"
 #include "runtime.h"
 
@@ -198,7 +199,18 @@ hipError_t op_w_fit_finish(const VariantOps& self, const Plan& pl, const SingleA
 }
 
 // --- source, names, compilation ---------------------------------------------
-std::string leaf_type(int kind, int np) {
+uint64_t fnv1a(uint64_t h, const void* p, size_t n);
+
+// the generated type that holds a formula leaf's expression
+std::string jit_functor_name(const std::string& density, int np) {
+  uint64_t h = fnv1a(1469598103934665603ull, density.c_str(), density.size() + 1);
+  h = fnv1a(h, &np, sizeof(np));
+  char hex[17];
+  std::snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)h);
+  return std::string("nllmi_jit_") + hex;
+}
+
+std::string leaf_type(int kind, int np, const std::string& density) {
   switch (kind) {
     case kGauss: return "nllmi::GaussLeaf";
     case kExp: return "nllmi::ExpLeaf";
@@ -208,6 +220,7 @@ std::string leaf_type(int kind, int np) {
     case kJohnson: return "nllmi::JohnsonLeaf";
     case kChi2: return "nllmi::Chi2Leaf";
     case kHypatia: return "nllmi::HypatiaLeaf";
+    case kJit: return "nllmi::JitLeaf<" + std::to_string(np) + ",::" + jit_functor_name(density, np) + ">";
     default: return "";
   }
 }
@@ -318,10 +331,31 @@ void write_file_atomic(const std::string& path, const std::vector<char>& data) {
 
 const char* kOptions[] = {"-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
 
+// The formula leaves' expressions (kJit), after the kernel templates: the
+// forward-mode dual numbers, then per formula a type with its value and its
+// dual evaluation, as JitLeaf (jit_leaf.h) expects.  Empty without them.
+std::string jit_functors(const RtcShape& s) {
+  std::string out;
+  std::vector<std::string> done;
+  for (size_t l = 0; l < s.kind.size(); ++l) {
+    if (s.kind[l] != kJit || l >= s.density.size()) continue;
+    const std::string name = jit_functor_name(s.density[l], s.np[l]);
+    if (std::find(done.begin(), done.end(), name) != done.end()) continue;
+    done.push_back(name);
+    if (out.empty()) out = jit_dual_source();
+    const std::string& e = s.density[l];
+    out += "\nstruct " + name + " {\n  template <int N> using D = Dual<N>;\n" +
+           "  __device__ static double val(double x, const double* p) { return (double)(" + e + "); }\n" +
+           "  template <int N> __device__ static Dual<N> dual(double x, const Dual<N>* p) { return dconst<N>(0.0) + (" +
+           e + "); }\n};\n";
+  }
+  return out;
+}
+
 // compile the explicit instantiations of `names` (and their lowered names)
-nll_status compile(const std::string& arch, const Names& names, std::vector<char>& code,
+nll_status compile(const std::string& arch, const Names& names, const std::string& extra, std::vector<char>& code,
                    std::vector<std::string>& lowered, std::string& log) {
-  std::string src = "#include \"kernels_dev.h\"\n";
+  std::string src = "#include \"kernels_dev.h\"\n" + extra;
   hiprtcProgram prog;
   if (hiprtcCreateProgram(&prog, src.c_str(), "nllmi_rtc.hip", kRtcHeaderCount, kRtcHeaderTexts, kRtcHeaderNames) !=
       HIPRTC_SUCCESS)
@@ -367,8 +401,8 @@ std::map<std::string, std::unique_ptr<RtcModule>> g_modules;  // "device|model t
 std::string rtc_model_type(const RtcShape& s) {
   std::string m = "nllmi::Model<" + std::to_string(s.K) + "," + std::to_string(s.n_obs);
   for (size_t l = 0; l < s.kind.size(); ++l)
-    m += ",nllmi::Slot<" + leaf_type(s.kind[l], s.np[l]) + "," + std::to_string(s.obs[l]) + "," +
-         tf(s.root[l] != 0) + ">";
+    m += ",nllmi::Slot<" + leaf_type(s.kind[l], s.np[l], l < s.density.size() ? s.density[l] : std::string()) +
+         "," + std::to_string(s.obs[l]) + "," + tf(s.root[l] != 0) + ">";
   m += ">";
   if (s.nonflat) m = "nllmi::NonFlat<" + m + ">";
   if (s.precision == 1) m = "nllmi::FP32C<" + m + ">";
@@ -384,7 +418,7 @@ nll_status rtc_compile_check(const RtcShape& s, const std::string& arch, std::st
   std::vector<char> code;
   std::vector<std::string> lowered;
   std::string clog;
-  const nll_status st = compile(arch, names, code, lowered, clog);
+  const nll_status st = compile(arch, names, jit_functors(s), code, lowered, clog);
   if (log) *log = clog;
   return st;
 }
@@ -397,8 +431,12 @@ const VariantOps* rtc_variant(const RtcShape& s, int device, nll_status* status,
     return nullptr;
   }
   int npt = 0;
+  if (s.density.size() != (size_t)L) {
+    *status = NLL_ERR_ARG;
+    return nullptr;
+  }
   for (int l = 0; l < L; ++l) {
-    if (leaf_type(s.kind[l], s.np[l]).empty()) {
+    if (leaf_type(s.kind[l], s.np[l], s.density[l]).empty()) {
       *status = NLL_ERR_UNSUPPORTED;
       return nullptr;
     }
@@ -438,6 +476,8 @@ const VariantOps* rtc_variant(const RtcShape& s, int device, nll_status* status,
     h = fnv1a(h, kRtcHeaderTexts[i], std::strlen(kRtcHeaderTexts[i]) + 1);
   }
   for (int i = 0; i < kNumKernels; ++i) h = fnv1a(h, names.expr[i].c_str(), names.expr[i].size() + 1);
+  const std::string extra = jit_functors(s);
+  h = fnv1a(h, extra.c_str(), extra.size() + 1);
   for (const char* o : kOptions) h = fnv1a(h, o, std::strlen(o) + 1);
   h = fnv1a(h, arch.c_str(), arch.size() + 1);
   int rtc_ver[2] = {0, 0};
@@ -467,7 +507,7 @@ const VariantOps* rtc_variant(const RtcShape& s, int device, nll_status* status,
   }
   if (!cached) {
     std::string clog;
-    const nll_status st = compile(arch, names, code, lowered, clog);
+    const nll_status st = compile(arch, names, extra, code, lowered, clog);
     if (log) *log = clog;
     if (st != NLL_OK) {
       *status = st;

@@ -17,6 +17,7 @@ namespace nllmi {
 // terms are not one non-root leaf each, e.g. a product of two sums).
 struct RtcShape {
   std::vector<int> kind, obs, root, np;
+  std::vector<std::string> density;  // per leaf: the formula of a formula leaf (kJit), else empty
   int K = 1, n_obs = 1, precision = 0;
   bool nonflat = false;
 };

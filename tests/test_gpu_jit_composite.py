@@ -1,0 +1,128 @@
+"""GPU tests of formula densities (Sec. 4's expression strings) as leaves of
+composite models: a Breit-Wigner formula beside a built-in exponential, a
+formula Gaussian and a quadratic beside a built-in Gaussian (three terms),
+two formulas in a sum of yields, a formula on x times a built-in Gaussian on
+y, and a formula peak 1/500 of the range wide, against the composite oracle
+(oracle.composite: adaptive quadrature, complex-step gradient).  NLL within
+1e-12 relative, gradient within 1e-8 of the oracle's max-norm.  Then the
+batched pass, gradient-descent fit steps, and the status and error rules."""
+import copy
+import math
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import composite
+
+pytestmark = pytest.mark.gpu
+
+NLL_TOL = 1e-12
+GRAD_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def nllmi():
+    import paper_2003_12875_amd as m
+    m.lib()
+    return m
+
+
+def build(torch, nllmi, spec, cols):
+    m = nllmi.Model.from_spec(spec)
+    m.set_data([torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in cols])
+    return m
+
+
+def check(torch, m, spec, cols, points):
+    for th in points:
+        st, ref, gref = composite.nll(spec, cols, th)
+        assert st == 0
+        t = torch.from_numpy(np.ascontiguousarray(th))
+        v, g = m.eval_grad(t)
+        v, g = float(v.item()), g.cpu().numpy()
+        assert abs(v - ref) <= NLL_TOL * abs(ref), (th, v, ref)
+        assert np.max(np.abs(g - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
+        v0 = float(m.eval(t).item())
+        assert abs(v0 - ref) <= NLL_TOL * abs(ref), (th, v0, ref)
+    assert m.sync() == 0
+
+
+@pytest.mark.parametrize("kind", ["bw_exp", "three", "two_jit", "prod", "narrow"])
+def test_formula_leaves_in_composites(torch, nllmi, kind):
+    w = datagen.jit_composite_workload(kind, n=200_003, n_points=3)
+    print(f"[jit composite {kind}]", flush=True)
+    m = build(torch, nllmi, w["spec"], w["cols"])
+    assert m.info["variant"].startswith("rtc:")
+    check(torch, m, w["spec"], w["cols"], w["points"])
+
+
+def test_batched_and_fit(torch, nllmi):
+    """The batched pass over sets of uneven sizes (one empty) at different
+    points; then gradient-descent fit steps: the final state is the oracle's
+    NLL and gradient at the final point, below the start's NLL."""
+    w = datagen.jit_composite_workload("bw_exp", n=120_000, n_points=5)
+    spec, cols = w["spec"], w["cols"]
+    print("[jit composite batched]", flush=True)
+    m = build(torch, nllmi, spec, cols)
+    offsets = np.array([0, 1, 777, 777, 40_000, 120_000], dtype=np.int64)
+    pts = w["points"]
+    nll, g, st = m.eval_batched(torch.from_numpy(offsets).cuda(), torch.from_numpy(pts).cuda())
+    nll, g, st = nll.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+    for s in range(5):
+        a, b = offsets[s], offsets[s + 1]
+        assert st[s] == 0
+        if b == a:
+            assert nll[s] == 0.0 and np.all(g[s] == 0.0)
+            continue
+        sto, ref, gref = composite.nll(spec, [c[a:b] for c in cols], pts[s])
+        assert sto == 0
+        assert abs(nll[s] / ref - 1.0) <= NLL_TOL, (s, nll[s], ref)
+        assert np.max(np.abs(g[s] - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (s, g[s], gref)
+    start = composite.nll(spec, cols, pts[0], grad=False)[1]
+    for steps in (1, 6):
+        th, f, gg, stt = m.fit(torch.from_numpy(pts[0]), steps)
+        th, f, gg = th.cpu().numpy(), float(f.item()), gg.cpu().numpy()
+        assert int(stt.item()) == 0
+        sto, ref, gref = composite.nll(spec, cols, th)
+        assert sto == 0 and f <= start
+        assert abs(f - ref) <= NLL_TOL * abs(ref), (steps, f, ref)
+        assert np.max(np.abs(gg - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (steps, gg, gref)
+
+
+def test_status_and_errors(torch, nllmi):
+    """A formula negative at some events: +inf and the invalid-density
+    status; a parameter outside its range: the range status; a formula
+    whose composite rule does not settle within 256 panels (a step): the
+    invalid-density status; a parameter index past the leaf's parameters,
+    no expression, or the FP32-compensated pass: errors at creation."""
+    w = datagen.jit_composite_workload("three", n=20_000, n_points=1)
+    spec, cols, th = copy.deepcopy(w["spec"]), w["cols"], w["points"][0].copy()
+    spec["params"][6]["lo"] = -1.0
+    m = build(torch, nllmi, spec, cols)
+    bad = th.copy()
+    bad[6], bad[7] = -0.5, 0.0  # 1 - x/2 < 0 above x = 2
+    assert math.isinf(float(m.eval(torch.from_numpy(bad)).item())) and m.sync() == -5
+    bad = th.copy()
+    bad[3] = 9.0  # s1 above its range
+    assert math.isinf(float(m.eval(torch.from_numpy(bad)).item())) and m.sync() == -3
+    v = float(m.eval(torch.from_numpy(th)).item())
+    assert math.isfinite(v) and m.sync() == 0
+    step = copy.deepcopy(w["spec"])
+    step["nodes"][2]["density"] = "1.0 + p[0]*x + p[1]*x*x + (x > 3.1)"
+    ms = build(torch, nllmi, step, cols)
+    assert math.isinf(float(ms.eval(torch.from_numpy(th)).item())) and ms.sync() == -5
+    for node, precision in (({"density": "p[0] + p[2]*x"}, "fp64"), ({"density": ""}, "fp64"), ({}, "fp32c")):
+        s = copy.deepcopy(w["spec"])
+        s["nodes"][2].update(node)
+        with pytest.raises(nllmi.NLLError) as e:
+            nllmi.Model.from_spec(s, precision=precision)
+        assert e.value.status == (-2 if precision == "fp32c" else -1)
