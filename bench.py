@@ -812,6 +812,23 @@ def extras(torch, nllmi, datagen, args, parity):
                            "builtin_gauss_eval_grad_ms": tb, "status": mj.sync()}
     del mj, mb, x
     torch.cuda.empty_cache()
+    # a formula leaf inside a composite model: f Breit-Wigner(x) formula +
+    # (1 - f) built-in Exp(x) with 1e7 events, compiled at model creation
+    # (the code-object cache may hold it from an earlier run)
+    w = datagen.jit_composite_workload("bw_exp", n=10_000_000, n_points=1)
+    t0 = time.perf_counter()
+    mc = nllmi.Model.from_spec(w["spec"])
+    t_compile = time.perf_counter() - t0
+    mc.set_data([torch.from_numpy(c).cuda() for c in w["cols"]])
+    th = torch.as_tensor(w["points"][0], dtype=torch.float64, device="cuda")
+    g = torch.empty(mc.n_param, dtype=torch.float64, device="cuda")
+    tg = time_launches(torch, lambda: mc.eval_grad(th, out=out, grad=g), 20)
+    tf = time_launches(torch, lambda: mc.eval(th, out=out), 20)
+    ex["jit_composite_bw_exp_1e7"] = {"create_s": t_compile, "eval_grad_ms": tg, "eval_ms": tf,
+                                      "events_per_s": 1e7 / (tg * 1e-3), "variant": mc.info["variant"],
+                                      "status": mc.sync()}
+    del mc
+    torch.cuda.empty_cache()
     return ex
 
 
