@@ -58,14 +58,22 @@ __device__ inline double uniform_d(double v) {
 }
 
 // K_nu(z) e^z, K_{nu+1}(z) e^z and their derivatives in the order, as four
-// trapezoidal sums over t (see the header); z > 0.
-__device__ inline void bessel_k4(double nu, double z, double out[4]) {
+// trapezoidal sums over t (see the header); z > 0.  A group of G
+// consecutive lanes of one wave (G a power of 2, the group aligned to G)
+// computes one set of sums: lane r takes the terms j = r, r + G, ... in
+// rounds of G terms; each round's terms are added across the group (xor
+// butterfly) to sums that every lane of the group holds, and the sums stop
+// after the first round whose every term is negligible against them (past
+// the integrand's peak, t > 1 and z sinh t above the orders).  The order
+// of the additions depends on G only.
+__device__ inline void bessel_k4(double nu, double z, double out[4], int G, int r) {
   const double a0 = fabs(nu), a1 = fabs(nu + 1.0);
   const double g0 = nu < 0.0 ? -1.0 : 1.0, g1 = nu + 1.0 < 0.0 ? -1.0 : 1.0;
   const double h = fmin(0.25, 0.45 / sqrt(sqrt(z * z + (a0 + 1.0) * (a0 + 1.0))));
   const double mono = fmax(a0, a1) + 1.0;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int j = 0; j < 8192; ++j) {
+  for (int base = 0; base < 8192; base += G) {
+    const int j = base + r;
     const double t = j * h;
     const double et = exp(t);
     const double ch = 0.5 * (et + 1.0 / et), sh = 0.5 * (et - 1.0 / et);
@@ -76,13 +84,21 @@ __device__ inline void bessel_k4(double nu, double z, double out[4]) {
     double c1 = 0.5 * (p1 + 1.0 / p1), d1 = g1 * 0.5 * m1 * (1.0 + 1.0 / p1);
     const double w = j == 0 ? 0.5 * E : E;
     const double u0 = w * c0, u1 = w * c1, u2 = w * t * d0, u3 = w * t * d1;
-    s0 += u0;
-    s1 += u1;
-    s2 += u2;
-    s3 += u3;
-    if (t > 1.0 && z * sh > mono && u0 <= 1e-18 * s0 && u1 <= 1e-18 * s1 && fabs(u2) <= 1e-18 * fabs(s2) + 1e-300 &&
-        fabs(u3) <= 1e-18 * fabs(s3) + 1e-300)
-      break;
+    double v0 = u0, v1 = u1, v2 = u2, v3 = u3;
+    for (int off = 1; off < G; off <<= 1) {
+      v0 += __shfl_xor(v0, off, 64);
+      v1 += __shfl_xor(v1, off, 64);
+      v2 += __shfl_xor(v2, off, 64);
+      v3 += __shfl_xor(v3, off, 64);
+    }
+    s0 += v0;
+    s1 += v1;
+    s2 += v2;
+    s3 += v3;
+    int done = t > 1.0 && z * sh > mono && u0 <= 1e-18 * s0 && u1 <= 1e-18 * s1 &&
+               fabs(u2) <= 1e-18 * fabs(s2) + 1e-300 && fabs(u3) <= 1e-18 * fabs(s3) + 1e-300;
+    for (int off = 1; off < G; off <<= 1) done &= __shfl_xor(done, off, 64);
+    if (done) break;
   }
   out[0] = h * s0;
   out[1] = h * s1;
@@ -191,18 +207,21 @@ struct HypatiaLeaf {
   // -------- per parameter point (all threads of the block) --------------
   template <int NT>
   __device__ static void setup_aux(const double* p, double lo, double hi, double* aux) {
-    static_assert(NT >= 256 && kHypPanels * kHypDeg <= 192, "node threads below the junction threads 192, 193");
+    static_assert(NT >= 256 && kHypPanels * kHypDeg <= 192, "node lanes below the junction lanes 192..255");
     double* sc = aux + kHypScal;
     double* tl = aux + kHypTails;  // [2][9][3]
     const int t = threadIdx.x;
     const bool ok0 = valid(p);
+    // A^2 from K_lambda(zeta), K_{lambda+1}(zeta): the sums over wave 0's
+    // 64 lanes, the rest on lane 0
+    double S0[4];
+    if (t < 64 && ok0) bessel_k4(p[2], p[3], S0, 64, t);
     if (t == 0) {
       sc[hOk] = ok0 ? 1.0 : 0.0;
-      sc[hBadJ] = 0.0;  // set by the junction threads (hOk is read before they run)
+      sc[hBadJ] = 0.0;  // set by the junction lanes (hOk is read before they run)
       if (ok0) {
         const double sg = p[1], la = p[2], ze = p[3];
-        double S[4];
-        bessel_k4(la, ze, S);
+        const double* S = S0;
         const double A2 = ze * S[0] / S[1];
         const double Ql = S[1] / S[0];
         const double dl2 = S[2] / S[0] - S[3] / S[1];                 // d ln A^2 / d lambda
@@ -243,74 +262,83 @@ struct HypatiaLeaf {
     if (sc[hOk] == 0.0) return;  // uniform
     const double nu = sc[hNu], delta2 = sc[hDelta2], alpha = sc[hAlpha], beta = sc[hBeta];
     const int npan = (int)sc[hNPan];
-    // interpolation nodes: thread j < npan * kHypDeg, panel j / kHypDeg
+    // interpolation nodes on lanes 0..191: node n = npan * kHypDeg at most
+    // (panel n / kHypDeg) on the G lanes [n G, n G + G), G the largest power
+    // of 2 (at most 64) with npan * kHypDeg * G <= 192; its lane 0 keeps it
+    const int n_nodes = npan * kHypDeg;
+    int G = 64;
+    while (G > 1 && n_nodes * G > 192) G >>= 1;
     double nv[3] = {0.0, 0.0, 0.0};
-    const bool node = t < npan * kHypDeg;
+    const int nd = t / G, nr = t % G;
+    const bool node = t < 192 && nd < n_nodes;
     if (node) {
-      const int pn = t / kHypDeg, jj = t % kHypDeg;
+      const int pn = nd / kHypDeg, jj = nd % kHypDeg;
       const double y = cospi(((double)jj + 0.5) / kHypDeg);
       const double s = sc[hS0] + ((double)pn + 0.5 * (y + 1.0)) / sc[hInvW];
       const double z = exp(s);
       double S[4];
-      bessel_k4(nu, z, S);
+      bessel_k4(nu, z, S, G, nr);
       nv[0] = log(S[0]);
       nv[1] = (S[1] / S[0] - 1.0) * z;
       nv[2] = S[2] / S[0];
     }
-    // junctions: thread 192 the low one, 193 the high one
-    if (t == 192 || t == 193) {
-      const bool low = t == 192;
+    // junctions, beside the nodes: lanes 192..223 the low one, 224..255 the
+    // high one (32 lanes each for the sums, the rest on the first)
+    if (t >= 192 && t < 256) {
+      const bool low = t < 224;
       const double d = low ? sc[hDl] : sc[hDh];
       const double r2 = fma(d, d, delta2), r = sqrt(r2), z = alpha * r;
       double S[4];
-      bessel_k4(nu, z, S);
-      const double lr2 = log(r2);
-      const double lk = log(S[0]) - z;
-      const double Q = S[1] / S[0], f3 = S[2] / S[0], f4 = S[3] / S[1];
-      const double L = fma(0.5 * nu, lr2, fma(beta, d, lk));
-      const double Fd = 2.0 * nu * d / r2 + beta - alpha * d / r * Q;
-      const double Fdl = nu / r2 - 0.5 * alpha * Q / r;
-      const double Fal = nu / alpha - r * Q;
-      const double Fnu = 0.5 * lr2 + f3;
-      const double Qp = Q * Q - (2.0 * nu + 1.0) * Q / z - 1.0;
-      const double dQnu = Q * (f4 - f3);
-      const double r3 = r2 * r;
-      const double Gdd = 2.0 * nu * (r2 - 2.0 * d * d) / (r2 * r2) - alpha * delta2 * Q / r3 -
-                         alpha * alpha * d * d * Qp / r2;
-      const double Gdl = -2.0 * nu * d / (r2 * r2) + alpha * d * Q / (2.0 * r3) - alpha * alpha * d * Qp / (2.0 * r2);
-      const double Gal = -(d / r) * (Q + z * Qp);
-      const double Gnu = 2.0 * d / r2 - alpha * d / r * dQnu;
-      const double n = low ? sc[hNl] : sc[hNr];
-      const double sl = Fd;  // the log-slope at the junction
-      const double k = low ? sl / n : -sl / n;
-      const int nidx = low ? 6 : 8;
-      if (low) {
-        sc[hLGl] = L;
-        sc[hKl] = k;
-        sc[hRef] = L;
-      } else {
-        sc[hLGh] = L;
-        sc[hKh] = k;
-      }
-      if (!(k > 0.0) || !__builtin_isfinite(L)) sc[hBadJ] = 1.0;
-      double* tab = tl + (low ? 0 : 27);
-      for (int q = 0; q < NP; ++q) {
-        const double dd = q == 1 ? (low ? -p[5] : p[7]) : (q == 5 && low ? -p[1] : (q == 7 && !low ? p[1] : 0.0));
-        const double ddl = q == 1 ? sc[hCsd] : (q == 2 ? sc[hCld] : (q == 3 ? sc[hCzd] : 0.0));
-        const double dal = q == 1 ? sc[hCsa] : (q == 2 ? sc[hCla] : (q == 3 ? sc[hCza] : 0.0));
-        const double dnu = q == 2 ? 1.0 : 0.0, dbe = q == 4 ? 1.0 : 0.0;
-        const double dL = Fd * dd + Fdl * ddl + Fal * dal + Fnu * dnu + d * dbe;
-        const double ds = Gdd * dd + Gdl * ddl + Gal * dal + Gnu * dnu + dbe;
-        const double dk = (low ? ds : -ds) / n - (q == nidx ? k / n : 0.0);
-        const double dw = low ? dd + (q == 0 ? 1.0 : 0.0) : -dd - (q == 0 ? 1.0 : 0.0);
-        tab[3 * q] = dL;
-        tab[3 * q + 1] = n * dk;
-        tab[3 * q + 2] = n * k * dw;
+      bessel_k4(nu, z, S, 32, t & 31);
+      if ((t & 31) == 0) {
+        const double lr2 = log(r2);
+        const double lk = log(S[0]) - z;
+        const double Q = S[1] / S[0], f3 = S[2] / S[0], f4 = S[3] / S[1];
+        const double L = fma(0.5 * nu, lr2, fma(beta, d, lk));
+        const double Fd = 2.0 * nu * d / r2 + beta - alpha * d / r * Q;
+        const double Fdl = nu / r2 - 0.5 * alpha * Q / r;
+        const double Fal = nu / alpha - r * Q;
+        const double Fnu = 0.5 * lr2 + f3;
+        const double Qp = Q * Q - (2.0 * nu + 1.0) * Q / z - 1.0;
+        const double dQnu = Q * (f4 - f3);
+        const double r3 = r2 * r;
+        const double Gdd = 2.0 * nu * (r2 - 2.0 * d * d) / (r2 * r2) - alpha * delta2 * Q / r3 -
+                           alpha * alpha * d * d * Qp / r2;
+        const double Gdl = -2.0 * nu * d / (r2 * r2) + alpha * d * Q / (2.0 * r3) - alpha * alpha * d * Qp / (2.0 * r2);
+        const double Gal = -(d / r) * (Q + z * Qp);
+        const double Gnu = 2.0 * d / r2 - alpha * d / r * dQnu;
+        const double n = low ? sc[hNl] : sc[hNr];
+        const double sl = Fd;  // the log-slope at the junction
+        const double k = low ? sl / n : -sl / n;
+        const int nidx = low ? 6 : 8;
+        if (low) {
+          sc[hLGl] = L;
+          sc[hKl] = k;
+          sc[hRef] = L;
+        } else {
+          sc[hLGh] = L;
+          sc[hKh] = k;
+        }
+        if (!(k > 0.0) || !__builtin_isfinite(L)) sc[hBadJ] = 1.0;
+        double* tab = tl + (low ? 0 : 27);
+        for (int q = 0; q < NP; ++q) {
+          const double dd = q == 1 ? (low ? -p[5] : p[7]) : (q == 5 && low ? -p[1] : (q == 7 && !low ? p[1] : 0.0));
+          const double ddl = q == 1 ? sc[hCsd] : (q == 2 ? sc[hCld] : (q == 3 ? sc[hCzd] : 0.0));
+          const double dal = q == 1 ? sc[hCsa] : (q == 2 ? sc[hCla] : (q == 3 ? sc[hCza] : 0.0));
+          const double dnu = q == 2 ? 1.0 : 0.0, dbe = q == 4 ? 1.0 : 0.0;
+          const double dL = Fd * dd + Fdl * ddl + Fal * dal + Fnu * dnu + d * dbe;
+          const double ds = Gdd * dd + Gdl * ddl + Gal * dal + Gnu * dnu + dbe;
+          const double dk = (low ? ds : -ds) / n - (q == nidx ? k / n : 0.0);
+          const double dw = low ? dd + (q == 0 ? 1.0 : 0.0) : -dd - (q == 0 ? 1.0 : 0.0);
+          tab[3 * q] = dL;
+          tab[3 * q + 1] = n * dk;
+          tab[3 * q + 2] = n * k * dw;
+        }
       }
     }
     // node values into the coefficient area, then the coefficients
-    if (node) {
-      const int pn = t / kHypDeg, jj = t % kHypDeg;
+    if (node && nr == 0) {
+      const int pn = nd / kHypDeg, jj = nd % kHypDeg;
       for (int f = 0; f < 3; ++f) aux[f * kHypFn + pn * kHypDeg + jj] = nv[f];
     }
     __syncthreads();
