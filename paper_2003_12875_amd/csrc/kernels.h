@@ -23,6 +23,8 @@ struct VariantOps {
   // 1: a leaf keeps per-point tables (kAuxWords) beside PerTheta, passed
   // as SingleArgs::aux / SetsArgs::aux and to consts / fit_init
   int aux;
+  // threads per block of the per-set finishing kernel (finish_threads<M>)
+  int fin_threads;
   // run-time compiled shapes: their module and kernels (null: compiled
   // ahead of time); the launchers receive the variant itself
   const void* rtc;

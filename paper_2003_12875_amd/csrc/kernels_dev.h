@@ -1060,8 +1060,24 @@ __global__ __launch_bounds__(kBlock) void k_sets(const Plan pl, const SetsArgs a
 // One block per set: reduce the set's work-item partials in item order,
 // write NLL / gradient / status, or (fitting) take the gradient-descent step
 // and prepare the constants of the next proposal.
+// Threads per block of the per-set finishing kernel: 128 for models of at
+// most 4 leaves without per-point tables (then the 4096 blocks of a large
+// batch are all resident at once: two waves each), else 256.  The
+// launchers use the same rule (kernels_impl.h, rtc.cpp).
+template <class M>
+constexpr int finish_threads() {
+  return (M::AUX || M::L > 4) ? kBlock : kBlock / 2;
+}
+// Waves per SIMD the finishing kernel is compiled for: 8 (at most 64
+// registers, so that 16 blocks of 128 threads share a CU) for one-leaf
+// models, whose kernels fit that without spilling; else no requirement.
+template <class M>
+constexpr int finish_waves() {
+  return (finish_threads<M>() == kBlock / 2 && M::L == 1) ? 8 : 1;
+}
+
 template <class M, bool GRAD, bool FIT>
-__global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const SetsArgs a) {
+__global__ __launch_bounds__(kBlock, finish_waves<M>()) void k_sets_finish(const Plan pl, const SetsArgs a) {
   constexpr int NA = M::template NA<GRAD>;
   constexpr int NV = NA + 1;
   __shared__ Plan spl;
@@ -1072,6 +1088,7 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   __shared__ double s_theta[kMaxParams];
   __shared__ double s_nll;
   __shared__ int s_st;
+  constexpr int NT = finish_threads<M>();  // the launch's threads per block
   const int s = blockIdx.x;  // the grid is exactly one block per set
   const int P = pl.n_param;
   const int t = threadIdx.x;
@@ -1079,9 +1096,9 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   // plan, constants, parameters, fit state, the set's item range and
   // events, then its first batch of item records (each copy then waits for
   // its own loads only)
-  PlanRegs<kBlock> plr;
+  PlanRegs<NT> plr;
   plr.load(pl);
-  PtRegs<M, kBlock> ptv;
+  PtRegs<M, NT> ptv;
   ptv.load(&a.consts[s], P);
   GDPre pre{};
   double thv;
@@ -1095,7 +1112,7 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
   const int flag = a.set_flag[s];
   const int64_t o0 = a.offsets[s], o1 = a.offsets[s + 1];
   const DD* recs = reinterpret_cast<const DD*>(a.partials) + (size_t)first * NV;
-  RecordSum<NV, kBlock> rs;
+  RecordSum<NV, NT> rs;
   rs.issue(recs, n_items);
   plr.store(&spl);
   if (t < P) s_theta[t] = thv;
@@ -1113,9 +1130,9 @@ __global__ __launch_bounds__(kBlock) void k_sets_finish(const Plan pl, const Set
     const double next = gd_update(spl, a.gd, s, s_st, s_nll, s_grad, n_s, pre);
     if (t < P) s_theta[t] = next;  // compute_pertheta starts with a barrier
     __shared__ double s_aux[M::AUX ? kAuxWords : 1];
-    compute_pertheta<M>(spl, s_theta, a.glx, a.glw, &spt, small, s_aux);
-    copy_pertheta<M, kBlock>(&a.consts[s], &spt, P);
-    if constexpr (M::AUX) copy_aux<kBlock>(a.aux + (size_t)s * kAuxWords, s_aux);
+    compute_pertheta<M, NT>(spl, s_theta, a.glx, a.glw, &spt, small, s_aux);
+    copy_pertheta<M, NT>(&a.consts[s], &spt, P);
+    if constexpr (M::AUX) copy_aux<NT>(a.aux + (size_t)s * kAuxWords, s_aux);
   }
 }
 

@@ -159,10 +159,10 @@ struct Launch {
     else sets_u<false>(pl, a, unroll, grid, lds_cap, st, ev0, ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 fg(a.n_sets);
-    if (fit) hipLaunchKernelGGL((k_sets_finish<M, true, true>), fg, dim3(kBlock), 0, st, pl, a);
-    else if (grad) hipLaunchKernelGGL((k_sets_finish<M, true, false>), fg, dim3(kBlock), 0, st, pl, a);
-    else hipLaunchKernelGGL((k_sets_finish<M, false, false>), fg, dim3(kBlock), 0, st, pl, a);
+    const dim3 fg(a.n_sets), fb(finish_threads<M>());
+    if (fit) hipLaunchKernelGGL((k_sets_finish<M, true, true>), fg, fb, 0, st, pl, a);
+    else if (grad) hipLaunchKernelGGL((k_sets_finish<M, true, false>), fg, fb, 0, st, pl, a);
+    else hipLaunchKernelGGL((k_sets_finish<M, false, false>), fg, fb, 0, st, pl, a);
     return hipGetLastError();
   }
   static hipError_t fit_init(const VariantOps&, const Plan& pl, const double* theta, int n_sets, double eta, const GDState& gd,
@@ -197,6 +197,7 @@ VariantOps make_ops(const char* name) {
   v.precision = M::PREC;
   v.flat = M::FLAT ? 1 : 0;
   v.aux = M::AUX ? 1 : 0;
+  v.fin_threads = finish_threads<M>();
   v.rtc = nullptr;
   v.single = &Launch<M>::single;
   v.single_fit = &Launch<M>::single_fit;

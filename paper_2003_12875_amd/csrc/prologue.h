@@ -24,11 +24,12 @@ namespace nllmi {
 
 constexpr int kGLNodes = 256;  // Gauss-Legendre nodes per panel, one per thread
 
-// sum over the first kGLNodes threads (4 waves) of NV values per thread, in
-// a fixed order (deterministic); the other threads of a larger block only
-// take part in the barriers.
-template <int NV>
+// sum over the first W waves of NV values per thread (W = 4: the first
+// kGLNodes threads), in a fixed order (deterministic); the other threads of
+// a larger block only take part in the barriers.
+template <int NV, int W = kGLNodes / 64>
 __device__ inline void block_sum_small(double (&v)[NV], double* lds /* >= 4*NV */) {
+  static_assert(W == 2 || W == 4, "waves in the sum");
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -36,24 +37,44 @@ __device__ inline void block_sum_small(double (&v)[NV], double* lds /* >= 4*NV *
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane == 0 && wave < kGLNodes / 64) {
+  if (lane == 0 && wave < W) {
 #pragma unroll
     for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < NV; ++j) v[j] = ((lds[j] + lds[NV + j]) + lds[2 * NV + j]) + lds[3 * NV + j];
+  for (int j = 0; j < NV; ++j) {
+    if constexpr (W == 4) {
+      v[j] = ((lds[j] + lds[NV + j]) + lds[2 * NV + j]) + lds[3 * NV + j];
+    } else {
+      v[j] = lds[j] + lds[NV + j];
+    }
+  }
   __syncthreads();
 }
 
-// Gauss-Legendre contribution of this thread's node to Z and dZ of a leaf.
+// Lanes of the per-point set-up (compute_pertheta, phase 2): leaf l's
+// group, the parameter range checks (two runs of 16 lanes), the sum checks
+// and the term weights, disjoint for up to kMaxLeaves leaves.  256 threads
+// or more: leaf l at 64 (l % 4) + 32 (l / 4), checks at 144 and 176, sums at
+// 80, weights at 208; 128 threads (models with at most 4 leaves): leaf l at
+// 32 l, checks at 16 and 48, sums at 80, weights at 112.
+template <int NT>
+struct PtLanes {
+  static constexpr int kMaxLeaves = NT >= 256 ? 8 : 4;
+  static constexpr int leaf(int l) { return NT >= 256 ? 64 * (l % 4) + 32 * (l / 4) : 32 * l; }
+  static constexpr int kParA = NT >= 256 ? 144 : 16;
+  static constexpr int kParB = NT >= 256 ? 176 : 48;
+  static constexpr int kSum = 80;
+  static constexpr int kTerm = NT >= 256 ? 208 : 112;
+};
+
+// Gauss-Legendre contribution of node i (of every panel) to Z and dZ of a
+// leaf, added to v.
 template <class Leaf>
 __device__ inline void gl_node(const double* p, int norm, double lo, double hi, const double* glx,
-                               const double* glw, double (&v)[Leaf::NP + 1]) {
-  const int i = threadIdx.x;
+                               const double* glw, int i, double (&v)[Leaf::NP + 1]) {
   double dg[kMaxLeafParams];
-#pragma unroll
-  for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
   auto panel = [&](double a, double b) {
     const double h = 0.5 * (b - a), c = 0.5 * (a + b);
     const double w = h * glw[i];
@@ -252,22 +273,24 @@ struct PlanRegs {
 // complete and visible to the block.  Phases:
 //   (0) the per-point tables of a leaf that has them (into aux, LDS: all
 //       threads, with barriers);
-//   (1) leaves normalised numerically: one Gauss-Legendre node per thread
-//       (skipped, with its barrier, when every leaf has a closed form);
-//   (2) in parallel: leaf l's constants and closed-form integrals on wave
-//       l % 4 (lanes cooperating where the leaf provides it), the parameter
-//       range checks (Sec. 3) and the term weights log w_k, d log w_k on
-//       lanes that hold no leaf;
+//   (1) leaves normalised numerically: one Gauss-Legendre node per thread,
+//       two with 128 threads (skipped, with its barrier, when every leaf has
+//       a closed form);
+//   (2) in parallel: leaf l's constants and closed-form integrals on its
+//       lane group (lanes cooperating where the leaf provides it), the
+//       parameter range checks (Sec. 3) and the term weights log w_k,
+//       d log w_k on lanes that hold no leaf (PtLanes);
 //   (3) term constants log w_k - sum log Z over the term's non-root leaves.
 template <class M, int NT = kBlock>
 __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* theta, const double* __restrict__ glx,
                                  const double* __restrict__ glw, PerTheta* pt, double* lds,
                                  double* aux = nullptr) {
-  static_assert(NT >= kGLNodes && NT % 64 == 0, "at least one thread per quadrature node");
-  // lanes: leaf l at 64 (l % 4) + 32 (l / 4) (up to 16 each), parameter
-  // checks at 144..159 and 176..191, sum checks at 80..84, term weights at
-  // 208..215 -- disjoint for up to 8 leaves
-  static_assert(M::L <= 8 && NT >= 256, "leaf lane groups at lanes 0 and 32 of waves 0..3");
+  // quadrature nodes: one per thread (256 threads or more) or two (128)
+  static_assert(NT % 64 == 0 && (NT >= kGLNodes || 2 * NT == kGLNodes), "one or two quadrature nodes per thread");
+  constexpr int W = (NT < kGLNodes ? NT : kGLNodes) / 64;  // waves in the node sums
+  using LN = PtLanes<NT>;
+  static_assert(M::L <= LN::kMaxLeaves, "leaf lane groups");
+  static_assert(!M::AUX || NT >= kGLNodes, "per-point tables: 256 threads or more");
   static_assert(kMaxParams <= 32 && kMaxSums + 1 <= 16 && kMaxTerms <= 16, "check and weight lanes");
   const int tid = threadIdx.x;
   __shared__ int s_bad;
@@ -312,14 +335,19 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
           constexpr int NV = Leaf::NP + 1;
           double zp[NV], zc[NV], ab[NV];
           auto level = [&](int n_pan, double (&z)[NV]) {
-            if (tid < kGLNodes) {
-              Leaf::norm_level(p, lo, hi, n_pan, glx, glw, tid, z, ab);
-            } else {
 #pragma unroll
-              for (int j = 0; j < NV; ++j) z[j] = ab[j] = 0.0;
+            for (int j = 0; j < NV; ++j) z[j] = ab[j] = 0.0;
+            for (int i = tid; i < kGLNodes; i += NT) {
+              double zi[NV], ai[NV];
+              Leaf::norm_level(p, lo, hi, n_pan, glx, glw, i, zi, ai);
+#pragma unroll
+              for (int j = 0; j < NV; ++j) {
+                z[j] += zi[j];
+                ab[j] += ai[j];
+              }
             }
-            block_sum_small<NV>(z, lds);
-            block_sum_small<NV>(ab, lds);
+            block_sum_small<NV, W>(z, lds);
+            block_sum_small<NV, W>(ab, lds);
           };
           level(1, zp);
           bool conv = false;
@@ -339,17 +367,16 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
         } else {
           const bool ok = Leaf::valid(p) && !(Leaf::kKind == kArgus && !(p[0] > lo));
           double v[Leaf::NP + 1];
-          if (ok && tid < kGLNodes) {
-            if constexpr (Leaf::kAux) {
-              Leaf::gl_norm(aux, lo, hi, glx, glw, v);
-            } else {
-              gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, v);
-            }
-          } else {
 #pragma unroll
-            for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
+          for (int j = 0; j <= Leaf::NP; ++j) v[j] = 0.0;
+          if (ok) {
+            if constexpr (Leaf::kAux) {
+              if (tid < kGLNodes) Leaf::gl_norm(aux, lo, hi, glx, glw, v);
+            } else {
+              for (int i = tid; i < kGLNodes; i += NT) gl_node<Leaf>(p, pl.leaf_norm[l], lo, hi, glx, glw, i, v);
+            }
           }
-          block_sum_small<Leaf::NP + 1>(v, lds);
+          block_sum_small<Leaf::NP + 1, W>(v, lds);
           if (tid == 0) {
             pt->logz[l] = v[0];  // Z for now
 #pragma unroll
@@ -361,11 +388,11 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
     __syncthreads();
   }
 
-  // (2a) leaf l: lanes [32 (l / 4), 32 (l / 4) + Leaf::kSetupLanes) of wave l % 4
+  // (2a) leaf l: lanes [LN::leaf(l), LN::leaf(l) + Leaf::kSetupLanes)
   static_for<M::L>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     using Leaf = typename M::template S<l>::Leaf;
-    constexpr int owner = 64 * (l % 4) + 32 * (l / 4);
+    constexpr int owner = LN::leaf(l);
     static_assert(Leaf::kSetupLanes >= 1 && Leaf::kSetupLanes <= 16, "setup lanes");
     if (tid >= owner && tid < owner + Leaf::kSetupLanes) {
       const int lane = tid - owner;
@@ -422,19 +449,18 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
     }
   });
 
-  // (2b) checks (Sec. 3) on lanes no leaf uses (leaf groups start at lanes 0
-  // and 32 of each wave): parameter ranges, one lane per parameter, on
-  // lanes 16..31 and 48..63 of wave 2; sum fractions in [0, 1] with a sum
-  // <= 1 (or yields >= 0 with a positive finite total), one lane per sum
-  // node, and a positive expected count, on lanes 16..20 of wave 1
-  if ((tid >= 144 && tid < 160) || (tid >= 176 && tid < 192)) {
-    const int q = tid < 160 ? tid - 144 : tid - 176 + 16;
+  // (2b) checks (Sec. 3) on lanes no leaf uses (PtLanes): parameter ranges,
+  // one lane per parameter; sum fractions in [0, 1] with a sum <= 1 (or
+  // yields >= 0 with a positive finite total), one lane per sum node, and a
+  // positive expected count
+  if ((tid >= LN::kParA && tid < LN::kParA + 16) || (tid >= LN::kParB && tid < LN::kParB + 16)) {
+    const int q = tid < LN::kParA + 16 ? tid - LN::kParA : tid - LN::kParB + 16;
     if (q < pl.n_param) {
       const double v = theta[q];
       if (!(v >= pl.par_lo[q] && v <= pl.par_hi[q])) atomicOr(&s_bad, 1);  // NaN fails too
     }
-  } else if (tid >= 80 && tid < 80 + kMaxSums) {
-    const int qs = tid - 80;
+  } else if (tid >= LN::kSum && tid < LN::kSum + kMaxSums) {
+    const int qs = tid - LN::kSum;
     if (qs < pl.n_sum) {
       double f = 0.0;
       bool ok = true;
@@ -455,11 +481,11 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
       }
       if (!ok) atomicOr(&s_bad, 1);
     }
-  } else if (tid == 80 + kMaxSums) {
+  } else if (tid == LN::kSum + kMaxSums) {
     if (pl.extended && !(expected_count(pl, theta) > 0.0)) atomicOr(&s_bad, 1);
   }
 
-  // (2c) term weights, one lane per term on wave 3 lanes 16..23: log w_k and
+  // (2c) term weights, one lane per term (PtLanes): log w_k and
   // d log w_k / d theta over the coefficient parameters of every sum on the
   // path: a fraction f_j (the last child 1 - sum f), or a yield's share
   // nu_j / S with S = sum nu (d log / d nu_i = [i = j] / nu_j - 1 / S).
@@ -467,8 +493,8 @@ __device__ __forceinline__ void compute_pertheta(const Plan& pl, const double* t
   // (or a last fraction at 0) keeps a finite log and derivative (the
   // floored term then carries a weight of 1e-200, i.e. nothing, in the
   // likelihood).
-  if (tid >= 208 && tid < 208 + M::K) {
-    const int k = tid - 208;
+  if (tid >= LN::kTerm && tid < LN::kTerm + M::K) {
+    const int k = tid - LN::kTerm;
     double lw = 0.0;
     for (int r = 0; r < pl.term_nref[k]; ++r) {
       const int q = pl.term_ref_sum[k][r], j = pl.term_ref_child[k][r];

@@ -144,7 +144,7 @@ hipError_t op_sets(const VariantOps& self, const Plan& pl, const SetsArgs& a, bo
   void* args[] = {const_cast<Plan*>(&pl), const_cast<SetsArgs*>(&a)};
   if (e != hipSuccess) return e;
   hipFunction_t fin = r.f[kSetsFinish + (fit ? 0 : grad ? 1 : 2)];
-  return launch(fin, a.n_sets, kBlock, 0, st, args);
+  return launch(fin, a.n_sets, self.fin_threads, 0, st, args);
 }
 
 hipError_t op_fit_init(const VariantOps& self, const Plan& pl, const double* theta, int n_sets, double eta,
@@ -559,6 +559,7 @@ const VariantOps* rtc_variant(const RtcShape& s, int device, nll_status* status,
   v.aux = 0;
   for (int l = 0; l < L; ++l)
     if (s.kind[l] == kHypatia) v.aux = 1;
+  v.fin_threads = (v.aux || L > 4) ? kBlock : kBlock / 2;  // as finish_threads<M> (kernels_dev.h)
   v.single = &op_single;
   v.single_fit = &op_single_fit;
   v.fit_finish = &op_fit_finish;
