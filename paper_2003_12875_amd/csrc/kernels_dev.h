@@ -1070,10 +1070,16 @@ constexpr int finish_threads() {
 }
 // Waves per SIMD the finishing kernel is compiled for: 8 (at most 64
 // registers, so that 16 blocks of 128 threads share a CU) for one-leaf
-// models, whose kernels fit that without spilling; else no requirement.
+// Gaussian, exponential and Chebyshev models, measured to fit that without
+// spilling to scratch memory; else no requirement.
 template <class M>
 constexpr int finish_waves() {
-  return (finish_threads<M>() == kBlock / 2 && M::L == 1) ? 8 : 1;
+  if constexpr (M::L == 1 && !M::AUX) {
+    constexpr int k = M::template S<0>::Leaf::kKind;
+    return (k == kGauss || k == kExp || k == kCheb) ? 8 : 1;
+  } else {
+    return 1;
+  }
 }
 
 template <class M, bool GRAD, bool FIT>
