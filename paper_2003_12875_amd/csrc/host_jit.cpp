@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kJitMaxParams = 8;  // MAXP of the device source
 constexpr int kJitThreads = 256;  // NTH of the device source
-constexpr int kJitBlocksPerCu = 2;
+constexpr int kJitBlocksPerCu = 4;  // stream blocks per CU at most (fewer where fewer fit)
 
 // mirrors JitArgs of the device source (same member types and order)
 struct JitArgsHost {
@@ -53,6 +53,7 @@ struct nll_jit_model {
   int par_free[kJitMaxParams] = {};
   hipModule_t module = nullptr;
   hipFunction_t f_stream[2] = {}, f_finish[2] = {};  // [0] NLL alone, [1] with gradient
+  int stream_blocks_per_cu[2] = {1, 1};               // resident at once, so the grid is one wave of blocks
   const double* x = nullptr;
   int64_t n = -1;
   double* partials = nullptr;
@@ -162,6 +163,12 @@ nll_status nll_jit_create(const nll_jit_desc* d, nll_jit_model** out, char* log,
   hipFunction_t* slots[4] = {&m->f_stream[0], &m->f_stream[1], &m->f_finish[0], &m->f_finish[1]};
   for (int i = 0; i < 4; ++i)
     if (hipModuleGetFunction(slots[i], m->module, names[i]) != hipSuccess) return fail(NLL_ERR_DEVICE);
+  for (int g = 0; g < 2; ++g) {
+    int nb = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, m->f_stream[g], kJitThreads, 0) != hipSuccess)
+      return fail(NLL_ERR_DEVICE);
+    m->stream_blocks_per_cu[g] = std::max(1, std::min(nb, kJitBlocksPerCu));
+  }
   const size_t nv = (size_t)d->n_param + 2;
   if ((st = jit_alloc(&m->partials, (size_t)m->n_cu * kJitBlocksPerCu * nv * 2)) != NLL_OK) return fail(st);
   if ((st = jit_alloc(&m->status, 1)) != NLL_OK || (st = jit_alloc(&m->dbad, 1)) != NLL_OK) return fail(st);
@@ -229,10 +236,10 @@ nll_status nll_jit_eval(nll_jit_model* m, const double* theta, double* nll_out, 
     a.par_free[k] = m->par_free[k];
   }
   const int64_t want = (m->n + kJitThreads - 1) / kJitThreads;
-  const int64_t cap = (int64_t)m->n_cu * kJitBlocksPerCu;
+  const int g = grad_out ? 1 : 0;
+  const int64_t cap = (int64_t)m->n_cu * m->stream_blocks_per_cu[g];
   const int grid = (int)std::max<int64_t>(1, std::min(want, cap));
   a.n_blocks = grid;
-  const int g = grad_out ? 1 : 0;
   void* args[] = {&a};
   if (hipModuleLaunchKernel(m->f_stream[g], grid, 1, 1, kJitThreads, 1, 1, 0, m->stream, args, nullptr) !=
           hipSuccess ||
