@@ -728,8 +728,16 @@ __device__ inline void model_event(const double (&x)[M::NOBS], const Consts<type
   const double w = x[B::NOBS];
   double lp = e.a[0];
   // one event's product is s times the root linear factors: a normal
-  // double when the density is valid; otherwise log gives -inf or NaN
-  if constexpr (B::NEED_PROD) lp += e.P > 0.0 ? log_pos_tab(e.P, g_log_tab) : log(e.P);
+  // double when the density is valid.  Otherwise the logarithm's own values
+  // (-inf at 0, +inf at +inf, NaN below 0 or at NaN) are selected as
+  // constants: a select between two logarithms would evaluate both.
+  if constexpr (B::NEED_PROD) {
+    const double P = e.P;
+    const bool fin = P > 0.0 && P <= 1.7976931348623157e308;
+    const double lt = log_pos_tab(fin ? P : 1.0, g_log_tab);
+    const double inv = P == 0.0 ? -__builtin_inf() : (P > 0.0 ? __builtin_inf() : __builtin_nan(""));
+    lp += fin ? lt : inv;
+  }
   acc.a[0] = fma(w, lp, acc.a[0]);
 #pragma unroll
   for (int j = 1; j < NA; ++j) acc.a[j] = fma(w, e.a[j], acc.a[j]);
