@@ -13,13 +13,13 @@
 // The dual type carries the value .v and the derivatives .d[k] through
 // every operation, so that one evaluation gives g and dg/dp_k.
 //
-// Per event: lambda = log g (the device library's log: g = 0 gives -inf, a
-// term that contributes nothing; g < 0 or non-finite makes the likelihood
-// non-finite, reported as an invalid density) and the features
+// Per event: lambda = log g (the staged logarithm table; g = 0 gives -inf,
+// a term that contributes nothing; g < 0 or non-finite makes the
+// likelihood non-finite, reported as an invalid density) and the features
 // phi_k = (dg/dp_k) / g, which the model multiplies by the term's
 // responsibility (0 where g = 0, and so are the features; a subnormal g is
-// divided into, as its reciprocal would overflow and meet a responsibility
-// of 0 as inf x 0).
+// scaled by 2^64 before its reciprocal, which would otherwise overflow and
+// meet a responsibility of 0 as inf x 0).
 // Normalisation: composite 256-point Gauss-Legendre over [lo, hi] on 1, 2,
 // 4, ... kJitMaxPanels equal panels, until two successive levels agree
 // (compute_pertheta, phase 1, with norm_level below for one thread's nodes).
@@ -76,21 +76,26 @@ struct JitLeaf {
       DT pd[NP_];
       seed(c.p, pd);
       const DT g = F::template dual<NP_>(x, pd);
-      lam = log(g.v);
-      if (g.v >= 2.2250738585072014e-308) {
-        const double ig = 1.0 / g.v;
+      lam = log_g(g.v);
+      // without a branch: g'_k s times the refined reciprocal of g s, s = 2^64
+      // for subnormal g (g s is then exact and normal), else 1
+      const double s = g.v < 2.2250738585072014e-308 ? 18446744073709551616.0 : 1.0;
+      const double r = rcp_grad(g.v * s);
+      const bool pos = g.v > 0.0;
 #pragma unroll
-        for (int k = 0; k < NP_; ++k) phi[k] = g.d[k] * ig;
-      } else if (g.v > 0.0) {  // subnormal g: its reciprocal overflows, so divide
-#pragma unroll
-        for (int k = 0; k < NP_; ++k) phi[k] = g.d[k] / g.v;
-      } else {  // g = 0 (a term that contributes nothing), or an invalid g
-#pragma unroll
-        for (int k = 0; k < NP_; ++k) phi[k] = 0.0;
-      }
+      for (int k = 0; k < NP_; ++k) phi[k] = pos ? (g.d[k] * s) * r : 0.0;
     } else {
-      lam = log(F::val(x, c.p));
+      lam = log_g(F::val(x, c.p));
     }
+  }
+  // log g by the staged table for positive finite g; the logarithm's own
+  // values otherwise (-inf at 0, +inf at +inf, NaN below 0 or at NaN),
+  // selected as constants so that no second logarithm is evaluated
+  __device__ static inline double log_g(double g) {
+    const bool fin = g > 0.0 && g <= 1.7976931348623157e308;
+    const double lt = log_pos_tab(fin ? g : 1.0, g_log_tab);
+    const double inv = g == 0.0 ? -__builtin_inf() : (g > 0.0 ? __builtin_inf() : __builtin_nan(""));
+    return fin ? lt : inv;
   }
   // This thread's share of the composite rule on n_pan equal panels of
   // [lo, hi]: node t of every panel (t < 256), with w g and w dg/dp_k
