@@ -167,3 +167,27 @@ def test_subnormal_density_values(torch, nllmi):
         assert np.max(np.abs(g.cpu().numpy() - gref)) <= GRAD_TOL * np.max(np.abs(gref)), (th, g, gref)
         assert abs(m.eval(torch.from_numpy(np.asarray(th))).item() - ref) <= NLL_TOL * abs(ref)
     assert m.sync() == 0
+
+
+MANY = {
+    1: ("exp(-p[0]*x)", 0.0, 8.0, [0.6], [0.01], [5.0]),
+    5: ("p[0] + p[1]*x + p[2]*x*x + p[3]*exp(-p[4]*x)", 0.0, 2.0,
+        [1.0, 0.3, 0.2, 0.5, 1.0], [0.1, -1, -1, 0, 0], [5, 5, 5, 5, 5]),
+    8: ("p[0] + p[1]*x + p[2]*x*x + p[3]*exp(-p[4]*x) + p[5]/(1.0 + p[6]*x*x) + p[7]*sin(x)", 0.0, 2.0,
+        [1.0, 0.3, 0.2, 0.5, 1.0, 0.4, 0.7, 0.1], [0.1, -1, -1, 0, 0, 0, 0, -1], [5] * 8),
+}
+
+
+@pytest.mark.parametrize("np_", [1, 5, 8])
+def test_parameter_counts_and_full_trips(torch, nllmi, np_):
+    """One, five and eight parameters (five and more take the finishing
+    block's three separate reductions; every count a different width of the
+    halving block reduction), on 2.2-3e6 events, so that every thread of the
+    streaming pass runs full trips of 8 events with the next trip's loads in
+    flight and then a ragged last trip."""
+    expr, lo, hi, p0, plo, phi = MANY[np_]
+    n = 3_000_017 if np_ < 8 else 2_200_001
+    x = exp_events(n, lo, hi, -0.3, seed=40 + np_)
+    pts = [p0, [v * (1.0 + 0.05 * ((k % 3) - 1)) for k, v in enumerate(p0)]]
+    print(f"[jit {np_} parameters, {n} events]", flush=True)
+    check(torch, nllmi, expr, lo, hi, params(p0, plo, phi), x, pts)
