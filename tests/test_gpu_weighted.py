@@ -177,3 +177,32 @@ def test_weights_lifecycle_and_refusals(torch, nllmi):
         mf.set_weights(torch.from_numpy(wt).cuda())
     assert e.value.status == -2
     assert m.sync() == 0
+
+
+def test_weighted_invalid_densities(torch, nllmi):
+    """Weighted events where the density is zero (an ARGUS endpoint below
+    the events' largest values) or negative (a Chebyshev series below zero
+    over part of the range): the NLL is +inf and the status the invalid
+    density's (-5), as for unweighted events; the same models at valid
+    points are finite and equal the oracle's weighted NLL."""
+    P = datagen.param
+    argus = {"obs": [{"name": "m", "lo": 0.2, "hi": 1.0}],
+             "params": [P("m0", 1.0, 0.5, 1.0), P("c", -6.0, -50, 0)],
+             "nodes": [{"kind": "argus", "obs": 0, "params": [0, 1], "norm": "gl256"}], "root": 0}
+    cheb = {"obs": [{"name": "y", "lo": -1.0, "hi": 1.0}],
+            "params": [P("a1", 0.1, -2, 2), P("a2", -0.2, -2, 2), P("a3", 0.05, -2, 2), P("a4", 0.1, -2, 2)],
+            "nodes": [{"kind": "cheb", "obs": 0, "params": [0, 1, 2, 3], "norm": "analytic"}], "root": 0}
+    for spec, bad in ((argus, [0.95, -6.0]), (cheb, [1.5, 0.0, 0.0, 0.0])):
+        n = 50_000
+        cols = datagen.generate(spec, n, seed=77)
+        wt = 0.5 + datagen.uniforms(5, 13, n)
+        print(f"[weighted invalid {spec['nodes'][0]['kind']}]", flush=True)
+        m = nllmi.Model.from_spec(spec)
+        m.set_data(to_dev(torch, cols))
+        m.set_weights(torch.from_numpy(wt).cuda())
+        assert np.isinf(float(m.eval(torch.from_numpy(np.asarray(bad))).item())) and m.sync() == -5
+        th = datagen.theta_of(spec)
+        st, ref, gref = oracle.Oracle(spec).nll(cols, th, threads=4, weights=wt)
+        assert st == 0
+        v = float(m.eval(torch.from_numpy(th)).item())
+        assert abs(v - ref) <= NLL_TOL * abs(ref) and m.sync() == 0, (v, ref)
