@@ -126,3 +126,21 @@ def test_status_and_errors(torch, nllmi):
         with pytest.raises(nllmi.NLLError) as e:
             nllmi.Model.from_spec(s, precision=precision)
         assert e.value.status == (-2 if precision == "fp32c" else -1)
+
+
+def test_formula_zero_at_some_events(torch, nllmi):
+    """A formula that vanishes at x = 5 beside an exponential that does
+    not, with some events exactly there: its term contributes nothing at
+    those events (log g = -inf, features 0), the density stays valid, and
+    NLL and gradient equal the composite oracle's."""
+    w = datagen.jit_composite_workload("three", n=30_000, n_points=1)
+    spec = {"obs": w["spec"]["obs"],
+            "params": [datagen.param("f", 0.4, 0.0, 1.0), datagen.param("c", -0.5, -5.0, 5.0),
+                       datagen.param("d", -0.3, -5.0, 5.0)],
+            "nodes": [{"kind": "jit", "obs": 0, "params": [1], "density": "(x - 5.0)*(x - 5.0)*exp(p[0]*x)"},
+                      {"kind": "exp", "obs": 0, "params": [2], "norm": "analytic"},
+                      {"kind": "sum", "params": [0], "children": [0, 1]}], "root": 2}
+    cols = [np.concatenate([w["cols"][0][:20_000], np.full(7, 5.0), w["cols"][0][20_000:]])]
+    print("[jit composite zero]", flush=True)
+    m = build(torch, nllmi, spec, cols)
+    check(torch, m, spec, cols, [np.array([0.4, -0.5, -0.3]), np.array([0.25, -0.2, -0.6])])
