@@ -141,8 +141,8 @@ def test_narrow_peak_expression(torch, nllmi, threads, sigma):
 def test_subnormal_density_values(torch, nllmi):
     """Events where g is subnormal (down to 1e-320): the running product
     takes each g's own mantissa and exponent, so log g keeps full
-    precision, and the features g'_k / g are divided directly where 1/g
-    would overflow.  g = (p0 x) e^(-p1 x) and its derivatives x e^(-p1 x)
+    precision, and the features g'_k / g take the reciprocal of g 2^64
+    where that of g would overflow.  g = (p0 x) e^(-p1 x) and its derivatives x e^(-p1 x)
     and -x g are formed by the same correctly rounded operations on both
     sides (e^(-p1 x) is exactly 1 at the subnormal events), so the
     reference takes them written out in numpy (the complex step of the
