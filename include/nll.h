@@ -298,8 +298,10 @@ nll_status nll_eval_batched_noalloc(nll_model* model, int32_t n_sets, const int6
  * theta[p * n_param ...] (device); nll_out[p] (device), grad_out (device
  * [n_points * n_param], NULL for NLL only) and status_out[p] (device, NULL
  * allowed) as in nll_eval_batched, each point normalised and checked on
- * its own.  The events are read once per point (work items of
- * tile_events events over all points share the persistent grid). */
+ * its own.  The events are read once per point (work items of up to
+ * tile_events events over all points share a persistent grid of at most
+ * 4 blocks per CU; the tile is halved, down to 4096 events, while there
+ * are fewer than two items per block). */
 nll_status nll_eval_points(nll_model* model, int32_t n_points, const double* theta, double* nll_out,
                            double* grad_out, int32_t* status_out);
 
@@ -369,7 +371,8 @@ typedef struct nll_schedule {
                                  block b streams the b-th chunk of every
                                  round (the last round's G chunks split
                                  what remains equally); nll_eval_points:
-                                 events per (point, tile) work item        */
+                                 at most this many events per (point,
+                                 tile) work item                            */
   int32_t sets_blocks_per_cu; /* batched: grid G = CUs * sets_blocks_per_cu */
   int32_t sets_unroll;        /* batched: events per thread per tile, as
                                  unroll                                     */
